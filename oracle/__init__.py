@@ -1,0 +1,276 @@
+"""FP64 CPU oracle of the MFV/MFM neighbour loops (arXiv 2211.12243, sec. 2.3).
+
+TEST INFRASTRUCTURE ONLY.  This package is the independent checker that the GPU
+library is compared against.  Only the tests, the smoke check and the CPU
+baseline of the benchmark may import it; the product package never does.  It
+shares no code with the HIP library: the arithmetic lives in ``mfm_oracle.c``
+(plain C, FP64, compiled with gcc) and this module only marshals numpy arrays.
+
+Pins (what fixes each function independently of itself) are in
+``tests/test_oracle_*.py``.  Functions without such a pin are marked
+"parity unpinned" in their docstring.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+from dataclasses import dataclass, field
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "mfm_oracle.c")
+_LIB = os.path.join(_HERE, "liborc.so")
+
+
+def build(force: bool = True) -> str:
+    """Compile the oracle with gcc (FP64, no fast-math, OpenMP)."""
+    if force or not os.path.exists(_LIB):
+        tmp = _LIB + ".tmp"
+        subprocess.check_call(
+            ["gcc", "-O2", "-std=c11", "-fopenmp", "-fPIC", "-shared", "-fno-fast-math",
+             "-ffp-contract=off", "-Wall", "-o", tmp, _SRC, "-lm"])
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+class Params(ctypes.Structure):
+    _fields_ = [
+        ("scheme", ctypes.c_int32), ("limiter", ctypes.c_int32),
+        ("max_boosts", ctypes.c_int32), ("h_maxit", ctypes.c_int32),
+        ("riemann_maxit", ctypes.c_int32), ("pad0", ctypes.c_int32),
+        ("gamma", ctypes.c_double), ("n_ngb", ctypes.c_double),
+        ("ncond_max", ctypes.c_double), ("ngb_boost", ctypes.c_double),
+        ("h_tol", ctypes.c_double), ("c_cfl", ctypes.c_double),
+        ("psi1", ctypes.c_double), ("psi2", ctypes.c_double),
+        ("riemann_tol", ctypes.c_double), ("alpha1", ctypes.c_double),
+        ("box", ctypes.c_double * 3),
+    ]
+
+
+class Counters(ctypes.Structure):
+    _fields_ = [(k, ctypes.c_int64) for k in (
+        "h_noconv", "ncond_boosts", "ncond_fail", "h_fallback", "grad_pairs", "faces",
+        "riemann_iters", "riemann_maxit", "vacuum", "positivity", "neg_mass", "singular_e")]
+
+    def as_dict(self):
+        return {k: int(getattr(self, k)) for k, _ in self._fields_}
+
+
+def make_params(cfg: dict) -> Params:
+    """Build the oracle's parameter struct from a plain dict of values."""
+    p = Params()
+    p.scheme = 1 if cfg.get("scheme", "mfv") == "mfm" else 0
+    p.limiter = int(cfg.get("limiter", 3))
+    p.max_boosts = int(cfg.get("max_boosts", 5))
+    p.h_maxit = int(cfg.get("h_maxit", 64))
+    p.riemann_maxit = int(cfg.get("riemann_maxit", 100))
+    p.gamma = float(cfg.get("gamma", 5.0 / 3.0))
+    p.n_ngb = float(cfg.get("n_ngb", 32.0))
+    p.ncond_max = float(cfg.get("ncond_max", 100.0))
+    p.ngb_boost = float(cfg.get("ngb_boost", 1.2))
+    p.h_tol = float(cfg.get("h_tol", 1e-13))
+    p.c_cfl = float(cfg.get("c_cfl", 0.2))
+    p.psi1 = float(cfg.get("psi1", 0.5))
+    p.psi2 = float(cfg.get("psi2", 0.25))
+    p.riemann_tol = float(cfg.get("riemann_tol", 1e-10))
+    p.alpha1 = float(cfg.get("alpha1", 0.01))
+    box = cfg.get("box", (1.0, 1.0, 1.0))
+    for k in range(3):
+        p.box[k] = float(box[k])
+    return p
+
+
+_lib = None
+_D = ctypes.POINTER(ctypes.c_double)
+_I64 = ctypes.POINTER(ctypes.c_int64)
+_I32 = ctypes.POINTER(ctypes.c_int32)
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB):
+            build(force=False)
+        L = ctypes.CDLL(_LIB)
+        P = ctypes.POINTER(Params)
+        C = ctypes.POINTER(Counters)
+        i64 = ctypes.c_int64
+        L.orc_kernel_W.restype = ctypes.c_double
+        L.orc_kernel_W.argtypes = [ctypes.c_double, ctypes.c_double]
+        L.orc_neighbours.argtypes = [P, i64, _D, _D, _D, _D, ctypes.c_int, _I64, _I32]
+        L.orc_density.argtypes = [P, i64, _D, _D, _D, _D, _D, _D, _D, C]
+        L.orc_gradients.argtypes = [P, i64] + [_D] * 10 + [_D] * 8 + [C]
+        L.orc_riemann.argtypes = [ctypes.c_double] * 8 + [ctypes.c_int, _D, _D,
+                                                            ctypes.POINTER(ctypes.c_int)]
+        L.orc_riemann_sample.argtypes = [ctypes.c_double] * 10 + [_D, _D, _D]
+        L.orc_face.argtypes = [P, i64, i64, i64] + [_D] * 12 + [ctypes.c_double, _D, C]
+        L.orc_fluxes.argtypes = [P, i64] + [_D] * 12 + [ctypes.c_double, _D, _D, C]
+        L.orc_update.argtypes = [P, i64] + [_D] * 9 + [_D, ctypes.c_double, C]
+        L.orc_step.argtypes = [P, i64] + [_D] * 10 + [ctypes.c_double, _D, C]
+        for f in ("orc_neighbours", "orc_density", "orc_gradients", "orc_riemann",
+                  "orc_riemann_sample", "orc_face", "orc_fluxes", "orc_update", "orc_step"):
+            getattr(L, f).restype = ctypes.c_int
+        _lib = L
+    return _lib
+
+
+def _p(a):
+    return a.ctypes.data_as(_D)
+
+
+def _f64(a):
+    return np.ascontiguousarray(a, dtype=np.float64)
+
+
+def kernel_W(r: float, H: float) -> float:
+    """Cubic-spline kernel with compact support H (sec. 2.3.2)."""
+    return lib().orc_kernel_W(float(r), float(H))
+
+
+def neighbours(cfg: dict, x, y, z, R, use_grid: bool = True):
+    """Neighbour sets N_i = {j : |x_j - x_i| < R_i} as CSR (start, idx), self included."""
+    p = make_params(cfg)
+    x, y, z, R = (_f64(a) for a in (x, y, z, R))
+    n = x.size
+    start = np.zeros(n + 1, dtype=np.int64)
+    L = lib()
+    rc = L.orc_neighbours(ctypes.byref(p), n, _p(x), _p(y), _p(z), _p(R), int(use_grid),
+                          start.ctypes.data_as(_I64), None)
+    assert rc == 0
+    idx = np.zeros(max(int(start[-1]), 1), dtype=np.int32)
+    rc = L.orc_neighbours(ctypes.byref(p), n, _p(x), _p(y), _p(z), _p(R), int(use_grid),
+                          start.ctypes.data_as(_I64), idx.ctypes.data_as(_I32))
+    assert rc == 0
+    return start, idx[: int(start[-1])]
+
+
+def density(cfg: dict, x, y, z, H):
+    """Loop (1): smoothing length, volume and unweighted condition number."""
+    p = make_params(cfg)
+    x, y, z = (_f64(a) for a in (x, y, z))
+    H = _f64(H).copy()
+    n = x.size
+    V, nc, nngb = (np.empty(n) for _ in range(3))
+    cnt = Counters()
+    rc = lib().orc_density(ctypes.byref(p), n, _p(x), _p(y), _p(z), _p(H), _p(V), _p(nc),
+                           _p(nngb), ctypes.byref(cnt))
+    if rc:
+        raise RuntimeError(f"orc_density failed: {rc}")
+    return {"H": H, "V": V, "ncond_tilde": nc, "nngb": nngb}, cnt.as_dict()
+
+
+def gradients(cfg: dict, x, y, z, H, V, m, vx, vy, vz, U):
+    """Loops (2) and (4): primitives, B = E^-1, limited gradients, dt_i."""
+    p = make_params(cfg)
+    arrs = [_f64(a) for a in (x, y, z, H, V, m, vx, vy, vz, U)]
+    n = arrs[0].size
+    rho, P, c, nc, dti = (np.empty(n) for _ in range(5))
+    B = np.empty((6, n))
+    grad = np.empty((15, n))
+    alpha = np.empty((5, n))
+    cnt = Counters()
+    rc = lib().orc_gradients(ctypes.byref(p), n, *[_p(a) for a in arrs], _p(rho), _p(P), _p(c),
+                             _p(B), _p(grad), _p(alpha), _p(nc), _p(dti), ctypes.byref(cnt))
+    if rc:
+        raise RuntimeError(f"orc_gradients failed: {rc}")
+    return {"rho": rho, "P": P, "c": c, "B": B, "grad": grad, "alpha": alpha, "ncond": nc,
+            "dt_i": dti}, cnt.as_dict()
+
+
+def riemann(gamma, rhoL, uL, PL, rhoR, uR, PR, tol=1e-10, maxit=100):
+    """Exact Riemann solve: returns (status, p*, u*, iterations)."""
+    ps, us = ctypes.c_double(), ctypes.c_double()
+    it = ctypes.c_int()
+    st = lib().orc_riemann(float(gamma), float(rhoL), float(uL), float(PL), float(rhoR),
+                           float(uR), float(PR), float(tol), int(maxit), ctypes.byref(ps),
+                           ctypes.byref(us), ctypes.byref(it))
+    return st, ps.value, us.value, it.value
+
+
+def riemann_sample(gamma, rhoL, uL, PL, rhoR, uR, PR, ps, us, xi):
+    """Exact solution at speed xi: returns (rho, u, P)."""
+    r, u, P = ctypes.c_double(), ctypes.c_double(), ctypes.c_double()
+    lib().orc_riemann_sample(*(float(v) for v in (gamma, rhoL, uL, PL, rhoR, uR, PR, ps, us, xi)),
+                             ctypes.byref(r), ctypes.byref(u), ctypes.byref(P))
+    return r.value, u.value, P.value
+
+
+def face(cfg: dict, i, j, x, y, z, H, V, rho, vx, vy, vz, P, B, grad, dt):
+    """Contribution c = |A_ij| F_ij of one face, oriented from i to j."""
+    p = make_params(cfg)
+    arrs = [_f64(a) for a in (x, y, z, H, V, rho, vx, vy, vz, P)]
+    B = _f64(B)
+    grad = _f64(grad)
+    n = arrs[0].size
+    c = np.zeros(5)
+    cnt = Counters()
+    lib().orc_face(ctypes.byref(p), n, int(i), int(j), *[_p(a) for a in arrs], _p(B), _p(grad),
+                   float(dt), _p(c), ctypes.byref(cnt))
+    return c, cnt.as_dict()
+
+
+def fluxes(cfg: dict, x, y, z, H, V, rho, vx, vy, vz, P, B, grad, dt):
+    """Loop (3): dQ (5, n) and its per-component scale dt * sum_j |c_ij|."""
+    p = make_params(cfg)
+    arrs = [_f64(a) for a in (x, y, z, H, V, rho, vx, vy, vz, P)]
+    B = _f64(B)
+    grad = _f64(grad)
+    n = arrs[0].size
+    dQ = np.empty((5, n))
+    scale = np.empty((5, n))
+    cnt = Counters()
+    rc = lib().orc_fluxes(ctypes.byref(p), n, *[_p(a) for a in arrs], _p(B), _p(grad), float(dt),
+                          _p(dQ), _p(scale), ctypes.byref(cnt))
+    if rc:
+        raise RuntimeError(f"orc_fluxes failed: {rc}")
+    return {"dQ": dQ, "scale": scale}, cnt.as_dict()
+
+
+def update(cfg: dict, state: dict, dQ, dt):
+    """Close of the step on a copy of ``state`` (keys x,y,z,m,vx,vy,vz,E,U)."""
+    p = make_params(cfg)
+    s = {k: _f64(state[k]).copy() for k in ("x", "y", "z", "m", "vx", "vy", "vz", "E", "U")}
+    n = s["x"].size
+    dQ = _f64(dQ)
+    cnt = Counters()
+    rc = lib().orc_update(ctypes.byref(p), n, *[_p(s[k]) for k in
+                                                ("x", "y", "z", "m", "vx", "vy", "vz", "E", "U")],
+                          _p(dQ), float(dt), ctypes.byref(cnt))
+    if rc:
+        raise RuntimeError(f"orc_update failed: {rc}")
+    return s, cnt.as_dict()
+
+
+STATE_KEYS = ("x", "y", "z", "m", "vx", "vy", "vz", "E", "U", "H")
+
+
+def step(cfg: dict, state: dict, dt_max: float):
+    """One full step on a copy of ``state``; returns (new_state, dt, counters)."""
+    p = make_params(cfg)
+    s = {k: _f64(state[k]).copy() for k in STATE_KEYS}
+    n = s["x"].size
+    dt = ctypes.c_double()
+    cnt = Counters()
+    rc = lib().orc_step(ctypes.byref(p), n, *[_p(s[k]) for k in STATE_KEYS], float(dt_max),
+                        ctypes.byref(dt), ctypes.byref(cnt))
+    if rc:
+        raise RuntimeError(f"orc_step failed: {rc}")
+    return s, dt.value, cnt.as_dict()
+
+
+def pipeline(cfg: dict, state: dict, dt_max: float):
+    """Every stage of one step, keeping the intermediate fields (for parity tests)."""
+    d, c1 = density(cfg, state["x"], state["y"], state["z"], state["H"])
+    g, c2 = gradients(cfg, state["x"], state["y"], state["z"], d["H"], d["V"], state["m"],
+                      state["vx"], state["vy"], state["vz"], state["U"])
+    dt = min(float(dt_max), float(np.min(g["dt_i"])))
+    f, c3 = fluxes(cfg, state["x"], state["y"], state["z"], d["H"], d["V"], g["rho"],
+                   state["vx"], state["vy"], state["vz"], g["P"], g["B"], g["grad"], dt)
+    new, c4 = update(cfg, state, f["dQ"], dt)
+    new["H"] = d["H"].copy()
+    counters = {k: c1[k] + c2[k] + c3[k] + c4[k] for k in c1}
+    out = {"density": d, "gradients": g, "fluxes": f, "dt": dt, "state": new,
+           "counters": counters}
+    return out

@@ -1,0 +1,999 @@
+/*
+ * mfm_oracle.c -- plain FP64 CPU oracle of the MFV/MFM neighbour loops of
+ * arXiv 2211.12243 (Alonso Asensio et al., "Mesh-free hydrodynamics in
+ * pkdgrav3").
+ *
+ * TEST INFRASTRUCTURE ONLY: the checker that the GPU library is compared with.
+ * Nothing in the product path links, loads or calls this file.  It shares no
+ * code with the HIP library.
+ *
+ * Every loop is written for clarity, not speed: no blocking, no fusion, no
+ * reordering beyond what the definitions state.  OpenMP only splits the
+ * independent per-particle (or per-face) work across host threads; every
+ * accumulation into a particle happens serially, in a fixed order.
+ *
+ * Readings of the paper where it is silent are marked "reading:".
+ */
+#include "mfm_oracle.h"
+
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+
+#ifndef M_PI
+#define M_PI 3.14159265358979323846
+#endif
+
+/* ------------------------------------------------------------------------ */
+/* Kernel (sec. 2.3.2).  reading: the cubic spline in compact-support form,  */
+/* W(r,H) = 8/(pi H^3) w(r/H), w = 1-6q^2+6q^3 (q<1/2), 2(1-q)^3 (q<1), 0     */
+/* beyond; it vanishes for r >= H and integrates to one over 3D space.       */
+/* ------------------------------------------------------------------------ */
+static double w_shape(double q) {
+  if (q < 0.5) return 1.0 - 6.0 * q * q + 6.0 * q * q * q;
+  if (q < 1.0) {
+    double t = 1.0 - q;
+    return 2.0 * t * t * t;
+  }
+  return 0.0;
+}
+
+/* dw/dq of the shape above. */
+static double w_shape_dq(double q) {
+  if (q < 0.5) return -12.0 * q + 18.0 * q * q;
+  if (q < 1.0) {
+    double t = 1.0 - q;
+    return -6.0 * t * t;
+  }
+  return 0.0;
+}
+
+double orc_kernel_W(double r, double H) {
+  return 8.0 / (M_PI * H * H * H) * w_shape(r / H);
+}
+
+/* ------------------------------------------------------------------------ */
+/* Geometry                                                                  */
+/* ------------------------------------------------------------------------ */
+static int is_periodic(const orc_params *p) {
+  return p->box[0] > 0.0 && p->box[1] > 0.0 && p->box[2] > 0.0;
+}
+
+/* Minimum-image separation along one axis of side L (L == 0: open axis). */
+static double min_image(double d, double L) {
+  if (L > 0.0) {
+    if (d > 0.5 * L)
+      d -= L;
+    else if (d < -0.5 * L)
+      d += L;
+  }
+  return d;
+}
+
+/* d = x_j - x_i (minimum image). */
+static void separation(const orc_params *p, const double *x, const double *y, const double *z,
+                       int64_t i, int64_t j, double d[3]) {
+  d[0] = min_image(x[j] - x[i], p->box[0]);
+  d[1] = min_image(y[j] - y[i], p->box[1]);
+  d[2] = min_image(z[j] - z[i], p->box[2]);
+}
+
+/* ------------------------------------------------------------------------ */
+/* Neighbour sets: N_i = { j : |x_j - x_i| < R_i }, self included.           */
+/* The grid only prunes candidates; membership is always the exact distance  */
+/* test, so grid and brute force must produce the same sets.                 */
+/* ------------------------------------------------------------------------ */
+typedef struct {
+  int nc[3];
+  int64_t *cell_start; /* ncells + 1 */
+  int64_t *cell_idx;   /* n */
+} orc_grid;
+
+static int grid_build(const orc_params *p, int64_t n, const double *x, const double *y,
+                      const double *z, double rmax, orc_grid *g) {
+  if (!is_periodic(p) || !(rmax > 0.0)) return 0;
+  const double *pos[3] = {x, y, z};
+  for (int k = 0; k < 3; ++k) {
+    double c = floor(p->box[k] / rmax);
+    if (c < 3.0) return 0;
+    if (c > 1024.0) c = 1024.0;
+    g->nc[k] = (int)c;
+  }
+  int64_t ncell = (int64_t)g->nc[0] * g->nc[1] * g->nc[2];
+  g->cell_start = (int64_t *)calloc((size_t)ncell + 1, sizeof(int64_t));
+  g->cell_idx = (int64_t *)malloc((size_t)(n > 0 ? n : 1) * sizeof(int64_t));
+  int64_t *cell_of = (int64_t *)malloc((size_t)(n > 0 ? n : 1) * sizeof(int64_t));
+  for (int64_t i = 0; i < n; ++i) {
+    int c[3];
+    for (int k = 0; k < 3; ++k) {
+      c[k] = (int)(pos[k][i] / p->box[k] * g->nc[k]);
+      if (c[k] < 0) c[k] = 0;
+      if (c[k] >= g->nc[k]) c[k] = g->nc[k] - 1;
+    }
+    cell_of[i] = ((int64_t)c[2] * g->nc[1] + c[1]) * g->nc[0] + c[0];
+    g->cell_start[cell_of[i] + 1]++;
+  }
+  for (int64_t c = 0; c < ncell; ++c) g->cell_start[c + 1] += g->cell_start[c];
+  int64_t *fill = (int64_t *)malloc((size_t)ncell * sizeof(int64_t));
+  memcpy(fill, g->cell_start, (size_t)ncell * sizeof(int64_t));
+  for (int64_t i = 0; i < n; ++i) g->cell_idx[fill[cell_of[i]]++] = i;
+  free(fill);
+  free(cell_of);
+  return 1;
+}
+
+static void grid_free(orc_grid *g) {
+  free(g->cell_start);
+  free(g->cell_idx);
+}
+
+/* Visit the candidates of particle i.  The visitor returns nothing; it sees j
+ * and the exact minimum-image separation. */
+typedef void (*visit_fn)(void *ctx, int64_t j, const double d[3], double r2);
+
+static void for_candidates(const orc_params *p, int64_t n, const double *x, const double *y,
+                           const double *z, const orc_grid *g, int use_grid, int64_t i,
+                           visit_fn f, void *ctx) {
+  double d[3];
+  if (!use_grid) {
+    for (int64_t j = 0; j < n; ++j) {
+      separation(p, x, y, z, i, j, d);
+      f(ctx, j, d, d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
+    }
+    return;
+  }
+  const double *pos[3] = {x, y, z};
+  int c[3];
+  for (int k = 0; k < 3; ++k) {
+    c[k] = (int)(pos[k][i] / p->box[k] * g->nc[k]);
+    if (c[k] < 0) c[k] = 0;
+    if (c[k] >= g->nc[k]) c[k] = g->nc[k] - 1;
+  }
+  for (int dz = -1; dz <= 1; ++dz)
+    for (int dy = -1; dy <= 1; ++dy)
+      for (int dx = -1; dx <= 1; ++dx) {
+        int cx = (c[0] + dx + g->nc[0]) % g->nc[0];
+        int cy = (c[1] + dy + g->nc[1]) % g->nc[1];
+        int cz = (c[2] + dz + g->nc[2]) % g->nc[2];
+        int64_t cell = ((int64_t)cz * g->nc[1] + cy) * g->nc[0] + cx;
+        for (int64_t k = g->cell_start[cell]; k < g->cell_start[cell + 1]; ++k) {
+          int64_t j = g->cell_idx[k];
+          separation(p, x, y, z, i, j, d);
+          f(ctx, j, d, d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
+        }
+      }
+}
+
+typedef struct {
+  double R2;
+  int64_t count;
+  int32_t *out; /* may be NULL (count only) */
+} collect_ctx;
+
+static void collect_visit(void *vctx, int64_t j, const double d[3], double r2) {
+  (void)d;
+  collect_ctx *c = (collect_ctx *)vctx;
+  if (r2 < c->R2) {
+    if (c->out) c->out[c->count] = (int32_t)j;
+    c->count++;
+  }
+}
+
+int orc_neighbours(const orc_params *p, int64_t n, const double *x, const double *y,
+                   const double *z, const double *R, int use_grid, int64_t *start,
+                   int32_t *idx) {
+  if (!p || n < 0 || !x || !y || !z || !R || !start) return -1;
+  double rmax = 0.0;
+  for (int64_t i = 0; i < n; ++i)
+    if (R[i] > rmax) rmax = R[i];
+  orc_grid g;
+  memset(&g, 0, sizeof(g));
+  int have_grid = use_grid ? grid_build(p, n, x, y, z, rmax, &g) : 0;
+  if (idx == NULL) {
+#pragma omp parallel for schedule(dynamic, 256)
+    for (int64_t i = 0; i < n; ++i) {
+      collect_ctx c = {R[i] * R[i], 0, NULL};
+      for_candidates(p, n, x, y, z, &g, have_grid, i, collect_visit, &c);
+      start[i + 1] = c.count;
+    }
+    start[0] = 0;
+    for (int64_t i = 0; i < n; ++i) start[i + 1] += start[i];
+  } else {
+#pragma omp parallel for schedule(dynamic, 256)
+    for (int64_t i = 0; i < n; ++i) {
+      collect_ctx c = {R[i] * R[i], 0, idx + start[i]};
+      for_candidates(p, n, x, y, z, &g, have_grid, i, collect_visit, &c);
+    }
+  }
+  if (have_grid) grid_free(&g);
+  return 0;
+}
+
+/* Build CSR lists for radius R_i (helper used by the loops below). */
+static int build_lists(const orc_params *p, int64_t n, const double *x, const double *y,
+                       const double *z, const double *R, int64_t **start, int32_t **idx) {
+  *start = (int64_t *)calloc((size_t)n + 1, sizeof(int64_t));
+  if (!*start) return -2;
+  orc_neighbours(p, n, x, y, z, R, 1, *start, NULL);
+  *idx = (int32_t *)malloc((size_t)((*start)[n] > 0 ? (*start)[n] : 1) * sizeof(int32_t));
+  if (!*idx) return -2;
+  orc_neighbours(p, n, x, y, z, R, 1, *start, *idx);
+  return 0;
+}
+
+/* ------------------------------------------------------------------------ */
+/* 3x3 symmetric matrices stored as (xx, xy, xz, yy, yz, zz).               */
+/* ------------------------------------------------------------------------ */
+static double sym_inverse(const double e[6], double b[6]) {
+  double c00 = e[3] * e[5] - e[4] * e[4];
+  double c01 = e[2] * e[4] - e[1] * e[5];
+  double c02 = e[1] * e[4] - e[2] * e[3];
+  double c11 = e[0] * e[5] - e[2] * e[2];
+  double c12 = e[1] * e[2] - e[0] * e[4];
+  double c22 = e[0] * e[3] - e[1] * e[1];
+  double det = e[0] * c00 + e[1] * c01 + e[2] * c02;
+  b[0] = c00 / det;
+  b[1] = c01 / det;
+  b[2] = c02 / det;
+  b[3] = c11 / det;
+  b[4] = c12 / det;
+  b[5] = c22 / det;
+  return det;
+}
+
+static double sym_frob(const double a[6]) {
+  return sqrt(a[0] * a[0] + a[3] * a[3] + a[5] * a[5] +
+              2.0 * (a[1] * a[1] + a[2] * a[2] + a[4] * a[4]));
+}
+
+static void sym_mul(const double a[6], const double v[3], double out[3]) {
+  out[0] = a[0] * v[0] + a[1] * v[1] + a[2] * v[2];
+  out[1] = a[1] * v[0] + a[3] * v[1] + a[4] * v[2];
+  out[2] = a[2] * v[0] + a[4] * v[1] + a[5] * v[2];
+}
+
+/* Condition number of eq. Ncond with nu = 3: the paper's norm is the sum of
+ * squared entries, so (||B|| ||E||)^(1/2) is the product of Frobenius norms. */
+static double cond_number(const double e[6]) {
+  double b[6];
+  double det = sym_inverse(e, b);
+  if (!(det != 0.0) || !isfinite(det)) return INFINITY;
+  return sym_frob(b) * sym_frob(e) / 3.0;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Density loop (loop 1 of sec. 2.2.3; sec. 2.3.2 and 2.3.5)                */
+/* ------------------------------------------------------------------------ */
+
+/* g(H) = (4 pi/3) H^3 omega^-1(H) - N_NGB = (32/3) sum_j w(r_j/H) - N_NGB and
+ * its derivative in H.  g never decreases with H. */
+static void g_eval(const double *r, int64_t nr, double H, double nngb, double *g,
+                   double *dg) {
+  double s = 0.0, ds = 0.0;
+  for (int64_t k = 0; k < nr; ++k) {
+    double q = r[k] / H;
+    if (q < 1.0) {
+      s += w_shape(q);
+      ds += q * w_shape_dq(q);
+    }
+  }
+  *g = 32.0 / 3.0 * s - nngb;
+  *dg = -32.0 / 3.0 * ds / H;
+}
+
+/* reading: Newton's method on g(H) = 0 kept inside a bisection bracket
+ * (lo, hi); stop when the step is below h_tol * H.  Returns iterations, or
+ * -1 when the cap was reached. */
+static int solve_h(const double *r, int64_t nr, double nngb, double hi, double tol, int maxit,
+                   double *H) {
+  double lo = 0.0;
+  double h = *H;
+  if (!(h > lo && h < hi)) h = 0.5 * (lo + hi);
+  for (int it = 1; it <= maxit; ++it) {
+    double g, dg;
+    g_eval(r, nr, h, nngb, &g, &dg);
+    if (g == 0.0) {
+      *H = h;
+      return it;
+    }
+    if (g < 0.0)
+      lo = h;
+    else
+      hi = h;
+    double hn = (dg > 0.0) ? h - g / dg : NAN;
+    if (!(hn > lo && hn < hi)) hn = 0.5 * (lo + hi);
+    int done = fabs(hn - h) <= tol * hn;
+    h = hn;
+    if (done) {
+      *H = h;
+      return it;
+    }
+  }
+  *H = h;
+  return -1;
+}
+
+/* Unweighted E~ = sum_{j != i, r < H} W(r, H) d d^T, used for the anisotropy
+ * check while the neighbour volumes are not yet known (reading). */
+static double ncond_unweighted(const double *dd, const double *r, int64_t nr, double H) {
+  double e[6] = {0, 0, 0, 0, 0, 0};
+  for (int64_t k = 0; k < nr; ++k) {
+    if (!(r[k] < H) || r[k] == 0.0) continue;
+    double w = orc_kernel_W(r[k], H);
+    const double *d = dd + 3 * k;
+    e[0] += w * d[0] * d[0];
+    e[1] += w * d[0] * d[1];
+    e[2] += w * d[0] * d[2];
+    e[3] += w * d[1] * d[1];
+    e[4] += w * d[1] * d[2];
+    e[5] += w * d[2] * d[2];
+  }
+  return cond_number(e);
+}
+
+typedef struct {
+  double *r;
+  double *d;
+  int64_t count, cap;
+  double R2;
+} cand_ctx;
+
+static void cand_visit(void *vctx, int64_t j, const double d[3], double r2) {
+  (void)j;
+  cand_ctx *c = (cand_ctx *)vctx;
+  if (!(r2 < c->R2)) return;
+  if (c->count == c->cap) {
+    c->cap = c->cap ? 2 * c->cap : 256;
+    c->r = (double *)realloc(c->r, (size_t)c->cap * sizeof(double));
+    c->d = (double *)realloc(c->d, (size_t)c->cap * 3 * sizeof(double));
+  }
+  c->r[c->count] = sqrt(r2);
+  c->d[3 * c->count + 0] = d[0];
+  c->d[3 * c->count + 1] = d[1];
+  c->d[3 * c->count + 2] = d[2];
+  c->count++;
+}
+
+int orc_density(const orc_params *p, int64_t n, const double *x, const double *y,
+                const double *z, double *H, double *V, double *ncond, double *nngb,
+                orc_counters *cnt) {
+  if (!p || n <= 0 || !x || !y || !z || !H || !V || !ncond || !nngb || !cnt) return -1;
+  if (!(p->n_ngb > 32.0 / 3.0)) return -1; /* the self term alone would exceed N_NGB */
+  int periodic = is_periodic(p);
+  double half = INFINITY;
+  if (periodic)
+    for (int k = 0; k < 3; ++k) half = fmin(half, 0.5 * p->box[k]);
+  /* Candidate radius: twice the start value (covers the N_NGB boosts), at
+   * most half the box.  A particle whose root is not bracketed falls back to
+   * a brute-force search with the widest radius. */
+  double *R = (double *)malloc((size_t)n * sizeof(double));
+  double rmax = 0.0;
+  for (int64_t i = 0; i < n; ++i) {
+    R[i] = fmin(2.0 * H[i], half);
+    if (R[i] > rmax) rmax = R[i];
+  }
+  orc_grid g;
+  memset(&g, 0, sizeof(g));
+  int have_grid = grid_build(p, n, x, y, z, rmax, &g);
+  int64_t noconv = 0, boosts = 0, fails = 0, fallback = 0;
+#pragma omp parallel for schedule(dynamic, 64) reduction(+ : noconv, boosts, fails, fallback)
+  for (int64_t i = 0; i < n; ++i) {
+    cand_ctx c = {NULL, NULL, 0, 0, R[i] * R[i]};
+    for_candidates(p, n, x, y, z, &g, have_grid, i, cand_visit, &c);
+    double hi = R[i];
+    double gv, dg;
+    g_eval(c.r, c.count, hi, p->n_ngb, &gv, &dg);
+    if (!periodic || gv < 0.0) {
+      /* widen: every particle is a candidate */
+      fallback += periodic ? 1 : 0;
+      c.count = 0;
+      c.R2 = INFINITY;
+      for_candidates(p, n, x, y, z, &g, 0, i, cand_visit, &c);
+      if (periodic) {
+        hi = half;
+      } else {
+        double rm = 0.0;
+        for (int64_t k = 0; k < c.count; ++k) rm = fmax(rm, c.r[k]);
+        hi = 2.0 * rm + 1e-300;
+      }
+    }
+    double target = p->n_ngb;
+    double h = H[i];
+    int b = 0;
+    double nc;
+    for (;;) {
+      int it = solve_h(c.r, c.count, target, hi, p->h_tol, p->h_maxit, &h);
+      if (it < 0) noconv++;
+      nc = ncond_unweighted(c.d, c.r, c.count, h);
+      if (!(nc > p->ncond_max)) break;
+      if (b == p->max_boosts) {
+        fails++;
+        break;
+      }
+      target *= p->ngb_boost;
+      b++;
+      boosts++;
+    }
+    double winv = 0.0;
+    for (int64_t k = 0; k < c.count; ++k)
+      if (c.r[k] < h) winv += orc_kernel_W(c.r[k], h);
+    H[i] = h;
+    V[i] = 1.0 / winv;
+    ncond[i] = nc;
+    nngb[i] = target;
+    free(c.r);
+    free(c.d);
+  }
+  if (have_grid) grid_free(&g);
+  free(R);
+  cnt->h_noconv += noconv;
+  cnt->ncond_boosts += boosts;
+  cnt->ncond_fail += fails;
+  cnt->h_fallback += fallback;
+  return 0;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Gradient loop (loop 2) and time step (loop 4)                             */
+/* ------------------------------------------------------------------------ */
+enum { Q_RHO = 0, Q_VX = 1, Q_VY = 2, Q_VZ = 3, Q_P = 4, NQ = 5 };
+
+int orc_gradients(const orc_params *p, int64_t n, const double *x, const double *y,
+                  const double *z, const double *H, const double *V, const double *m,
+                  const double *vx, const double *vy, const double *vz, const double *U,
+                  double *rho, double *P, double *c, double *B, double *grad, double *alpha,
+                  double *ncond, double *dt_i, orc_counters *cnt) {
+  if (!p || n <= 0) return -1;
+  const double gam = p->gamma;
+  /* Primitives: rho = m omega^-1, P = (gamma-1) U omega^-1 (sec. 2.3.7),
+   * c = sqrt(gamma P / rho). */
+  for (int64_t i = 0; i < n; ++i) {
+    rho[i] = m[i] / V[i];
+    P[i] = (gam - 1.0) * U[i] / V[i];
+    c[i] = sqrt(gam * P[i] / rho[i]);
+  }
+  int64_t *start;
+  int32_t *idx;
+  if (build_lists(p, n, x, y, z, H, &start, &idx)) return -2;
+  const double *qs[NQ] = {rho, vx, vy, vz, P};
+  int64_t pairs = 0, singular = 0;
+#pragma omp parallel for schedule(dynamic, 64) reduction(+ : pairs, singular)
+  for (int64_t i = 0; i < n; ++i) {
+    double e[6] = {0, 0, 0, 0, 0, 0};
+    double s[NQ][3];
+    double qmax[NQ], qmin[NQ];
+    for (int q = 0; q < NQ; ++q) {
+      s[q][0] = s[q][1] = s[q][2] = 0.0;
+      qmax[q] = qmin[q] = qs[q][i];
+    }
+    double vsig = 0.0;
+    for (int64_t k = start[i]; k < start[i + 1]; ++k) {
+      int64_t j = idx[k];
+      if (j == i) continue;
+      double d[3];
+      separation(p, x, y, z, i, j, d);
+      double r = sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
+      pairs++;
+      if (r == 0.0) continue; /* coincident particles add nothing (reading) */
+      /* eq. E_matrix with omega_j = V_j and mu(x_i, x_j) = (x_j - x_i) W(r, H_i) */
+      double wv = V[j] * orc_kernel_W(r, H[i]);
+      e[0] += wv * d[0] * d[0];
+      e[1] += wv * d[0] * d[1];
+      e[2] += wv * d[0] * d[2];
+      e[3] += wv * d[1] * d[1];
+      e[4] += wv * d[1] * d[2];
+      e[5] += wv * d[2] * d[2];
+      /* eq. LV_gradient: sum_j omega_j (f_j - f_i) mu(x_i, x_j), B applied after */
+      for (int q = 0; q < NQ; ++q) {
+        double df = qs[q][j] - qs[q][i];
+        s[q][0] += wv * df * d[0];
+        s[q][1] += wv * df * d[1];
+        s[q][2] += wv * df * d[2];
+        if (qs[q][j] > qmax[q]) qmax[q] = qs[q][j];
+        if (qs[q][j] < qmin[q]) qmin[q] = qs[q][j];
+      }
+      /* signal velocity (sec. 2.3.10); x_i - x_j = -d */
+      double proj = -(d[0] * (vx[i] - vx[j]) + d[1] * (vy[i] - vy[j]) + d[2] * (vz[i] - vz[j])) / r;
+      double vs = c[i] + c[j] - fmin(0.0, proj);
+      if (vs > vsig) vsig = vs;
+    }
+    double b[6];
+    double det = sym_inverse(e, b);
+    if (!(det != 0.0) || !isfinite(det)) singular++;
+    double g[NQ][3];
+    for (int q = 0; q < NQ; ++q) sym_mul(b, s[q], g[q]);
+    double nc = sym_frob(b) * sym_frob(e) / 3.0;
+    /* Conditioned Barth-Jespersen limiter (sec. 2.3.6).  reading: the face
+     * extrapolations d_j = grad q . (x_j - x_i)/2 are bounded by the
+     * neighbour extrema; the bound is relaxed by beta in [1, 2], beta = 2 for
+     * a perfectly isotropic neighbourhood and 1 at the N_cond threshold. */
+    double a[NQ] = {1, 1, 1, 1, 1};
+    if (p->limiter & 1) {
+      double dmax[NQ], dmin[NQ];
+      for (int q = 0; q < NQ; ++q) dmax[q] = dmin[q] = 0.0;
+      for (int64_t k = start[i]; k < start[i + 1]; ++k) {
+        int64_t j = idx[k];
+        if (j == i) continue;
+        double d[3];
+        separation(p, x, y, z, i, j, d);
+        for (int q = 0; q < NQ; ++q) {
+          double ex = 0.5 * (g[q][0] * d[0] + g[q][1] * d[1] + g[q][2] * d[2]);
+          if (ex > dmax[q]) dmax[q] = ex;
+          if (ex < dmin[q]) dmin[q] = ex;
+        }
+      }
+      double t = (p->ncond_max - nc) / (p->ncond_max - 1.0);
+      if (!(t > 0.0)) t = 0.0;
+      if (t > 1.0) t = 1.0;
+      double beta = 1.0 + t;
+      for (int q = 0; q < NQ; ++q) {
+        double rp = INFINITY, rm = INFINITY;
+        if (dmax[q] > 0.0) rp = (qmax[q] - qs[q][i]) / dmax[q];
+        if (dmin[q] < 0.0) rm = (qs[q][i] - qmin[q]) / (-dmin[q]);
+        double lim = beta * fmin(rp, rm);
+        a[q] = lim < 1.0 ? lim : 1.0;
+      }
+    }
+    for (int k = 0; k < 6; ++k) B[(int64_t)k * n + i] = b[k];
+    for (int q = 0; q < NQ; ++q) {
+      alpha[(int64_t)q * n + i] = a[q];
+      for (int k = 0; k < 3; ++k) grad[(int64_t)(3 * q + k) * n + i] = a[q] * g[q][k];
+    }
+    ncond[i] = nc;
+    dt_i[i] = vsig > 0.0 ? p->c_cfl * H[i] / vsig : INFINITY;
+  }
+  free(start);
+  free(idx);
+  cnt->grad_pairs += pairs;
+  cnt->singular_e += singular;
+  return 0;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Exact Riemann solver (Toro 2009), the solver the paper names in 2.3.3     */
+/* ------------------------------------------------------------------------ */
+
+/* Pressure function f_K(p) of one side and its derivative: a shock branch for
+ * p > p_K, a rarefaction branch otherwise. */
+static void pressure_fn(double gam, double p, double rhoK, double pK, double cK, double *f,
+                        double *df) {
+  if (p <= pK) {
+    double pr = p / pK;
+    *f = 2.0 * cK / (gam - 1.0) * (pow(pr, (gam - 1.0) / (2.0 * gam)) - 1.0);
+    *df = pow(pr, -(gam + 1.0) / (2.0 * gam)) / (rhoK * cK);
+  } else {
+    double A = 2.0 / ((gam + 1.0) * rhoK);
+    double Bk = (gam - 1.0) / (gam + 1.0) * pK;
+    double q = sqrt(A / (Bk + p));
+    *f = (p - pK) * q;
+    *df = q * (1.0 - 0.5 * (p - pK) / (Bk + p));
+  }
+}
+
+int orc_riemann(double gam, double rhoL, double uL, double PL, double rhoR, double uR,
+                double PR, double tol, int maxit, double *pstar, double *ustar, int *iters) {
+  double cL = sqrt(gam * PL / rhoL), cR = sqrt(gam * PR / rhoR);
+  double du = uR - uL;
+  *iters = 0;
+  /* vacuum is generated when the two rarefactions cannot meet */
+  if (2.0 / (gam - 1.0) * (cL + cR) <= du) {
+    *pstar = 0.0;
+    *ustar = 0.5 * (uL + uR);
+    return 1;
+  }
+  /* reading: Toro's adaptive starting value (primitive-variable guess when
+   * the states are close, two-rarefaction or two-shock otherwise) */
+  double pmin = fmin(PL, PR), pmax = fmax(PL, PR);
+  double ppv = 0.5 * (PL + PR) - 0.125 * du * (rhoL + rhoR) * (cL + cR);
+  if (ppv < 0.0) ppv = 0.0;
+  double p0;
+  if (pmax / pmin <= 2.0 && pmin <= ppv && ppv <= pmax) {
+    p0 = ppv;
+  } else if (ppv < pmin) {
+    double zz = (gam - 1.0) / (2.0 * gam);
+    double num = cL + cR - 0.5 * (gam - 1.0) * du;
+    double den = cL / pow(PL, zz) + cR / pow(PR, zz);
+    p0 = pow(num / den, 1.0 / zz);
+  } else {
+    double gL = sqrt(2.0 / ((gam + 1.0) * rhoL) / ((gam - 1.0) / (gam + 1.0) * PL + ppv));
+    double gR = sqrt(2.0 / ((gam + 1.0) * rhoR) / ((gam - 1.0) / (gam + 1.0) * PR + ppv));
+    p0 = (gL * PL + gR * PR - du) / (gL + gR);
+  }
+  double floor_p = 1e-10 * 0.5 * (PL + PR);
+  if (!(p0 > floor_p)) p0 = floor_p;
+  double p = p0, fL, dfL, fR, dfR;
+  int status = 2;
+  for (int it = 1; it <= maxit; ++it) {
+    pressure_fn(gam, p, rhoL, PL, cL, &fL, &dfL);
+    pressure_fn(gam, p, rhoR, PR, cR, &fR, &dfR);
+    double pn = p - (fL + fR + du) / (dfL + dfR);
+    if (pn < 0.0) pn = floor_p;
+    double change = 2.0 * fabs(pn - p) / (pn + p);
+    p = pn;
+    *iters = it;
+    if (change < tol) {
+      status = 0;
+      break;
+    }
+  }
+  pressure_fn(gam, p, rhoL, PL, cL, &fL, &dfL);
+  pressure_fn(gam, p, rhoR, PR, cR, &fR, &dfR);
+  *pstar = p;
+  *ustar = 0.5 * (uL + uR) + 0.5 * (fR - fL);
+  return status;
+}
+
+int orc_riemann_sample(double gam, double rhoL, double uL, double PL, double rhoR, double uR,
+                       double PR, double ps, double us, double xi, double *rho, double *u,
+                       double *P) {
+  double cL = sqrt(gam * PL / rhoL), cR = sqrt(gam * PR / rhoR);
+  double g1 = (gam - 1.0) / (2.0 * gam), g2 = (gam + 1.0) / (2.0 * gam);
+  double g4 = 2.0 / (gam - 1.0), g5 = 2.0 / (gam + 1.0), g6 = (gam - 1.0) / (gam + 1.0);
+  double g7 = 0.5 * (gam - 1.0), g3 = 2.0 * gam / (gam - 1.0);
+  if (xi <= us) { /* left of the contact */
+    if (ps <= PL) { /* left rarefaction */
+      if (xi <= uL - cL) {
+        *rho = rhoL; *u = uL; *P = PL;
+      } else {
+        double cml = cL * pow(ps / PL, g1);
+        if (xi > us - cml) {
+          *rho = rhoL * pow(ps / PL, 1.0 / gam); *u = us; *P = ps;
+        } else { /* inside the fan */
+          double cc = g5 * (cL + g7 * (uL - xi));
+          *u = g5 * (cL + g7 * uL + xi);
+          *rho = rhoL * pow(cc / cL, g4);
+          *P = PL * pow(cc / cL, g3);
+        }
+      }
+    } else { /* left shock */
+      double pml = ps / PL;
+      double sl = uL - cL * sqrt(g2 * pml + g1);
+      if (xi <= sl) {
+        *rho = rhoL; *u = uL; *P = PL;
+      } else {
+        *rho = rhoL * (pml + g6) / (pml * g6 + 1.0); *u = us; *P = ps;
+      }
+    }
+  } else { /* right of the contact */
+    if (ps > PR) { /* right shock */
+      double pmr = ps / PR;
+      double sr = uR + cR * sqrt(g2 * pmr + g1);
+      if (xi >= sr) {
+        *rho = rhoR; *u = uR; *P = PR;
+      } else {
+        *rho = rhoR * (pmr + g6) / (pmr * g6 + 1.0); *u = us; *P = ps;
+      }
+    } else { /* right rarefaction */
+      if (xi >= uR + cR) {
+        *rho = rhoR; *u = uR; *P = PR;
+      } else {
+        double cmr = cR * pow(ps / PR, g1);
+        if (xi <= us + cmr) {
+          *rho = rhoR * pow(ps / PR, 1.0 / gam); *u = us; *P = ps;
+        } else {
+          double cc = g5 * (cR - g7 * (uR - xi));
+          *u = g5 * (-cR + g7 * uR + xi);
+          *rho = rhoR * pow(cc / cR, g4);
+          *P = PR * pow(cc / cR, g3);
+        }
+      }
+    }
+  }
+  return 0;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Flux loop (loop 3)                                                        */
+/* ------------------------------------------------------------------------ */
+
+/* reading of the pairwise limiter (sec. 2.3.6, psi_1 and psi_2): the face
+ * value qf extrapolated from the own side (value qo) towards the other side
+ * (value qn) may overshoot the midpoint by at most psi_2 |qo - qn| and the
+ * pair minimum / maximum by psi_1 |qo - qn| (a sign-preserving ratio when that
+ * would cross zero). */
+static double pair_limit(double qf, double qo, double qn, double psi1, double psi2) {
+  if (qo == qn) return qo;
+  double dq = fabs(qo - qn);
+  double d1 = psi1 * dq, d2 = psi2 * dq;
+  double qbar = 0.5 * (qo + qn);
+  if (qo < qn) {
+    double lo = qo;
+    double lower = ((lo - d1) * lo > 0.0) ? lo - d1 : lo / (1.0 + d1 / fabs(lo));
+    return fmax(lower, fmin(qbar + d2, qf));
+  } else {
+    double hi = qo;
+    double upper = ((hi + d1) * hi > 0.0) ? hi + d1 : hi / (1.0 + d1 / fabs(hi));
+    return fmin(upper, fmax(qbar - d2, qf));
+  }
+}
+
+int orc_face(const orc_params *p, int64_t n, int64_t i, int64_t j, const double *x,
+             const double *y, const double *z, const double *H, const double *V,
+             const double *rho, const double *vx, const double *vy, const double *vz,
+             const double *P, const double *B, const double *grad, double dt, double *c,
+             orc_counters *cnt) {
+  const double gam = p->gamma;
+  for (int k = 0; k < 5; ++k) c[k] = 0.0;
+  double d[3];
+  separation(p, x, y, z, i, j, d);
+  double r2 = d[0] * d[0] + d[1] * d[1] + d[2] * d[2];
+  if (r2 == 0.0) return 0; /* coincident particles exchange nothing (reading) */
+  double r = sqrt(r2);
+  /* Face vector A_ij = V_i omega_j B_i mu(x_i,x_j) - V_j omega_i B_j mu(x_j,x_i)
+   * with omega = V and mu(a, b) = (b - a) W(|b - a|, H_a): it points from i to j. */
+  double bi[6], bj[6];
+  for (int k = 0; k < 6; ++k) {
+    bi[k] = B[(int64_t)k * n + i];
+    bj[k] = B[(int64_t)k * n + j];
+  }
+  double Bd_i[3], Bd_j[3];
+  sym_mul(bi, d, Bd_i);
+  sym_mul(bj, d, Bd_j);
+  double Wi = orc_kernel_W(r, H[i]), Wj = orc_kernel_W(r, H[j]);
+  double A[3];
+  for (int k = 0; k < 3; ++k) A[k] = V[i] * V[j] * (Wi * Bd_i[k] + Wj * Bd_j[k]);
+  double Amag = sqrt(A[0] * A[0] + A[1] * A[1] + A[2] * A[2]);
+  if (Amag == 0.0) return 0;
+  double nv[3] = {A[0] / Amag, A[1] / Amag, A[2] / Amag};
+
+  double qi[NQ] = {rho[i], vx[i], vy[i], vz[i], P[i]};
+  double qj[NQ] = {rho[j], vx[j], vy[j], vz[j], P[j]};
+  double gi[NQ][3], gj[NQ][3];
+  for (int q = 0; q < NQ; ++q)
+    for (int k = 0; k < 3; ++k) {
+      gi[q][k] = grad[(int64_t)(3 * q + k) * n + i];
+      gj[q][k] = grad[(int64_t)(3 * q + k) * n + j];
+    }
+  /* Half-step time extrapolation (sec. 2.3.4).  reading: the Lagrangian
+   * primitive equations, drho/dt = -rho div v, dv/dt = -grad P / rho,
+   * dP/dt = -gamma P div v, with the limited gradients. */
+  double qpi[NQ], qpj[NQ];
+  {
+    double dvi = gi[Q_VX][0] + gi[Q_VY][1] + gi[Q_VZ][2];
+    double dvj = gj[Q_VX][0] + gj[Q_VY][1] + gj[Q_VZ][2];
+    qpi[Q_RHO] = qi[Q_RHO] - 0.5 * dt * qi[Q_RHO] * dvi;
+    qpj[Q_RHO] = qj[Q_RHO] - 0.5 * dt * qj[Q_RHO] * dvj;
+    for (int k = 0; k < 3; ++k) {
+      qpi[Q_VX + k] = qi[Q_VX + k] - 0.5 * dt * gi[Q_P][k] / qi[Q_RHO];
+      qpj[Q_VX + k] = qj[Q_VX + k] - 0.5 * dt * gj[Q_P][k] / qj[Q_RHO];
+    }
+    qpi[Q_P] = qi[Q_P] - 0.5 * dt * gam * qi[Q_P] * dvi;
+    qpj[Q_P] = qj[Q_P] - 0.5 * dt * gam * qj[Q_P] * dvj;
+  }
+  /* Spatial extrapolation to the mid-point face (sec. 2.3.6), primitives. */
+  double qL[NQ], qR[NQ];
+  for (int q = 0; q < NQ; ++q) {
+    qL[q] = qpi[q] + 0.5 * (gi[q][0] * d[0] + gi[q][1] * d[1] + gi[q][2] * d[2]);
+    qR[q] = qpj[q] - 0.5 * (gj[q][0] * d[0] + gj[q][1] * d[1] + gj[q][2] * d[2]);
+  }
+  if (p->limiter & 2) {
+    for (int q = 0; q < NQ; ++q) {
+      qL[q] = pair_limit(qL[q], qi[q], qj[q], p->psi1, p->psi2);
+      qR[q] = pair_limit(qR[q], qj[q], qi[q], p->psi1, p->psi2);
+    }
+  }
+  /* reading: a non-positive reconstructed density or pressure falls back to
+   * the first-order (particle) states for this face */
+  if (!(qL[Q_RHO] > 0.0 && qR[Q_RHO] > 0.0 && qL[Q_P] > 0.0 && qR[Q_P] > 0.0)) {
+    for (int q = 0; q < NQ; ++q) {
+      qL[q] = qi[q];
+      qR[q] = qj[q];
+    }
+    if (cnt) cnt->positivity++;
+  }
+  /* Boost into the frame of the face, v_frame = (v_i + v_j)/2, and project on
+   * the face normal (sec. 2.3.3). */
+  double vf[3] = {0.5 * (vx[i] + vx[j]), 0.5 * (vy[i] + vy[j]), 0.5 * (vz[i] + vz[j])};
+  double wL[3], wR[3];
+  for (int k = 0; k < 3; ++k) {
+    wL[k] = qL[Q_VX + k] - vf[k];
+    wR[k] = qR[Q_VX + k] - vf[k];
+  }
+  double uL = wL[0] * nv[0] + wL[1] * nv[1] + wL[2] * nv[2];
+  double uR = wR[0] * nv[0] + wR[1] * nv[1] + wR[2] * nv[2];
+  double ps, us;
+  int iters;
+  int st = orc_riemann(gam, qL[Q_RHO], uL, qL[Q_P], qR[Q_RHO], uR, qR[Q_P], p->riemann_tol,
+                       p->riemann_maxit, &ps, &us, &iters);
+  if (cnt) cnt->riemann_iters += iters;
+  if (st == 1) {
+    if (cnt) cnt->vacuum++;
+    return 0;
+  }
+  if (st == 2 && cnt) cnt->riemann_maxit++;
+  double vfn = vf[0] * nv[0] + vf[1] * nv[1] + vf[2] * nv[2];
+  double F[5];
+  if (p->scheme == 1) {
+    /* MFM: the face moves with the contact, so no mass crosses it */
+    F[0] = 0.0;
+    for (int k = 0; k < 3; ++k) F[1 + k] = ps * nv[k];
+    F[4] = ps * (us + vfn);
+  } else {
+    /* MFV: the face moves with v_frame; the Riemann solution is sampled on the
+     * face (xi = 0).  reading: the transverse velocity is taken from the side
+     * the contact leaves behind (left when u* >= 0). */
+    double rf, uf, pf;
+    orc_riemann_sample(gam, qL[Q_RHO], uL, qL[Q_P], qR[Q_RHO], uR, qR[Q_P], ps, us, 0.0, &rf,
+                       &uf, &pf);
+    const double *wu = (us >= 0.0) ? wL : wR;
+    double wun = wu[0] * nv[0] + wu[1] * nv[1] + wu[2] * nv[2];
+    double vfa[3];
+    for (int k = 0; k < 3; ++k) vfa[k] = uf * nv[k] + (wu[k] - wun * nv[k]);
+    double v2 = vfa[0] * vfa[0] + vfa[1] * vfa[1] + vfa[2] * vfa[2];
+    double Fm = rf * uf;
+    double Fp[3];
+    for (int k = 0; k < 3; ++k) Fp[k] = Fm * vfa[k] + pf * nv[k];
+    double FE = uf * (pf / (gam - 1.0) + 0.5 * rf * v2 + pf);
+    /* back to the lab frame */
+    double vf2 = vf[0] * vf[0] + vf[1] * vf[1] + vf[2] * vf[2];
+    F[0] = Fm;
+    for (int k = 0; k < 3; ++k) F[1 + k] = Fp[k] + vf[k] * Fm;
+    F[4] = FE + (vf[0] * Fp[0] + vf[1] * Fp[1] + vf[2] * Fp[2]) + 0.5 * vf2 * Fm;
+  }
+  for (int k = 0; k < 5; ++k) c[k] = Amag * F[k];
+  return 0;
+}
+
+int orc_fluxes(const orc_params *p, int64_t n, const double *x, const double *y,
+               const double *z, const double *H, const double *V, const double *rho,
+               const double *vx, const double *vy, const double *vz, const double *P,
+               const double *B, const double *grad, double dt, double *dQ, double *scale,
+               orc_counters *cnt) {
+  if (!p || n <= 0) return -1;
+  int64_t *start;
+  int32_t *idx;
+  if (build_lists(p, n, x, y, z, H, &start, &idx)) return -2;
+  /* Unordered pairs with r_ij < max(H_i, H_j): take {i, j} from i's list when
+   * j > i, or when i is not in j's list (r_ij >= H_j). */
+  int64_t *fcount = (int64_t *)calloc((size_t)n + 1, sizeof(int64_t));
+#pragma omp parallel for schedule(dynamic, 256)
+  for (int64_t i = 0; i < n; ++i) {
+    int64_t cc = 0;
+    for (int64_t k = start[i]; k < start[i + 1]; ++k) {
+      int64_t j = idx[k];
+      if (j == i) continue;
+      double d[3];
+      separation(p, x, y, z, i, j, d);
+      double r2 = d[0] * d[0] + d[1] * d[1] + d[2] * d[2];
+      if (j > i || !(r2 < H[j] * H[j])) cc++;
+    }
+    fcount[i + 1] = cc;
+  }
+  for (int64_t i = 0; i < n; ++i) fcount[i + 1] += fcount[i];
+  int64_t nf = fcount[n];
+  int64_t *fa = (int64_t *)malloc((size_t)(nf > 0 ? nf : 1) * sizeof(int64_t));
+  int64_t *fb = (int64_t *)malloc((size_t)(nf > 0 ? nf : 1) * sizeof(int64_t));
+  double *fc = (double *)malloc((size_t)(nf > 0 ? nf : 1) * 5 * sizeof(double));
+#pragma omp parallel for schedule(dynamic, 256)
+  for (int64_t i = 0; i < n; ++i) {
+    int64_t f = fcount[i];
+    for (int64_t k = start[i]; k < start[i + 1]; ++k) {
+      int64_t j = idx[k];
+      if (j == i) continue;
+      double d[3];
+      separation(p, x, y, z, i, j, d);
+      double r2 = d[0] * d[0] + d[1] * d[1] + d[2] * d[2];
+      if (j > i || !(r2 < H[j] * H[j])) {
+        fa[f] = i < j ? i : j; /* left state: the lower index */
+        fb[f] = i < j ? j : i;
+        f++;
+      }
+    }
+  }
+  free(start);
+  free(idx);
+  /* Each face once; counters are per-thread then summed. */
+  int64_t iters = 0, vac = 0, pos = 0, mx = 0;
+#pragma omp parallel for schedule(dynamic, 1024) reduction(+ : iters, vac, pos, mx)
+  for (int64_t f = 0; f < nf; ++f) {
+    orc_counters local;
+    memset(&local, 0, sizeof(local));
+    orc_face(p, n, fa[f], fb[f], x, y, z, H, V, rho, vx, vy, vz, P, B, grad, dt, fc + 5 * f,
+             &local);
+    iters += local.riemann_iters;
+    vac += local.vacuum;
+    pos += local.positivity;
+    mx += local.riemann_maxit;
+  }
+  /* eq. hydro_discr: U_i <- U_i - dt sum_j F_ij A_ij, applied as -c to i and
+   * +c to j so that the pair is exactly antisymmetric. */
+  for (int64_t k = 0; k < 5 * n; ++k) {
+    dQ[k] = 0.0;
+    scale[k] = 0.0;
+  }
+  for (int64_t f = 0; f < nf; ++f) {
+    int64_t a = fa[f], b = fb[f];
+    for (int k = 0; k < 5; ++k) {
+      double v = dt * fc[5 * f + k];
+      dQ[(int64_t)k * n + a] -= v;
+      dQ[(int64_t)k * n + b] += v;
+      scale[(int64_t)k * n + a] += fabs(v);
+      scale[(int64_t)k * n + b] += fabs(v);
+    }
+  }
+  free(fa);
+  free(fb);
+  free(fc);
+  free(fcount);
+  cnt->faces += nf;
+  cnt->riemann_iters += iters;
+  cnt->vacuum += vac;
+  cnt->positivity += pos;
+  cnt->riemann_maxit += mx;
+  return 0;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Close of the step                                                         */
+/* ------------------------------------------------------------------------ */
+int orc_update(const orc_params *p, int64_t n, double *x, double *y, double *z, double *m,
+               double *vx, double *vy, double *vz, double *E, double *U, const double *dQ,
+               double dt, orc_counters *cnt) {
+  if (!p || n <= 0) return -1;
+  double *pos[3] = {x, y, z};
+  int64_t neg = 0;
+  for (int64_t i = 0; i < n; ++i) {
+    double dm = dQ[i], dp[3] = {dQ[n + i], dQ[2 * n + i], dQ[3 * n + i]}, dE = dQ[4 * n + i];
+    double v0[3] = {vx[i], vy[i], vz[i]};
+    /* eq. internal_energy_integration with the start-of-step velocity (reading) */
+    double v0sq = v0[0] * v0[0] + v0[1] * v0[1] + v0[2] * v0[2];
+    double dU = dE - (v0[0] * dp[0] + v0[1] * dp[1] + v0[2] * dp[2]) + 0.5 * v0sq * dm;
+    double m1 = m[i] + dm;
+    if (!(m1 > 0.0)) neg++; /* MFV mass depletion is counted, not clamped */
+    double p1[3] = {m[i] * v0[0] + dp[0], m[i] * v0[1] + dp[1], m[i] * v0[2] + dp[2]};
+    double v1[3] = {p1[0] / m1, p1[1] / m1, p1[2] / m1};
+    double E1 = E[i] + dE;
+    double U1 = U[i] + dU;
+    /* Pressure switch (sec. 2.3.7) without gravity and with the entropy branch
+     * off: when U exceeds alpha_1 E_kin the internal energy is recovered from
+     * the total energy, otherwise the integrated U is kept. */
+    double ekin = (p1[0] * p1[0] + p1[1] * p1[1] + p1[2] * p1[2]) / (2.0 * m1);
+    if (U1 > p->alpha1 * ekin) U1 = E1 - ekin;
+    /* reading: drift with the mean of the old and new velocities, periodic wrap */
+    for (int k = 0; k < 3; ++k) {
+      double xn = pos[k][i] + dt * 0.5 * (v0[k] + v1[k]);
+      double L = p->box[k];
+      if (L > 0.0) {
+        if (xn < 0.0) xn += L;
+        if (xn >= L) xn -= L;
+      }
+      pos[k][i] = xn;
+    }
+    m[i] = m1;
+    vx[i] = v1[0];
+    vy[i] = v1[1];
+    vz[i] = v1[2];
+    E[i] = E1;
+    U[i] = U1;
+  }
+  cnt->neg_mass += neg;
+  return 0;
+}
+
+int orc_step(const orc_params *p, int64_t n, double *x, double *y, double *z, double *m,
+             double *vx, double *vy, double *vz, double *E, double *U, double *H,
+             double dt_max, double *dt_out, orc_counters *cnt) {
+  if (!p || n <= 0 || !dt_out || !cnt) return -1;
+  size_t sz = (size_t)n * sizeof(double);
+  double *V = (double *)malloc(sz), *nc0 = (double *)malloc(sz), *nng = (double *)malloc(sz);
+  double *rho = (double *)malloc(sz), *P = (double *)malloc(sz), *c = (double *)malloc(sz);
+  double *B = (double *)malloc(6 * sz), *grad = (double *)malloc(15 * sz);
+  double *alpha = (double *)malloc(5 * sz), *nc = (double *)malloc(sz);
+  double *dti = (double *)malloc(sz), *dQ = (double *)malloc(5 * sz);
+  double *scale = (double *)malloc(5 * sz);
+  int rc = orc_density(p, n, x, y, z, H, V, nc0, nng, cnt);
+  if (!rc)
+    rc = orc_gradients(p, n, x, y, z, H, V, m, vx, vy, vz, U, rho, P, c, B, grad, alpha, nc, dti,
+                       cnt);
+  double dt = dt_max;
+  if (!rc) {
+    for (int64_t i = 0; i < n; ++i)
+      if (dti[i] < dt) dt = dti[i];
+    rc = orc_fluxes(p, n, x, y, z, H, V, rho, vx, vy, vz, P, B, grad, dt, dQ, scale, cnt);
+  }
+  if (!rc) rc = orc_update(p, n, x, y, z, m, vx, vy, vz, E, U, dQ, dt, cnt);
+  *dt_out = dt;
+  free(V); free(nc0); free(nng); free(rho); free(P); free(c); free(B); free(grad);
+  free(alpha); free(nc); free(dti); free(dQ); free(scale);
+  return rc;
+}

@@ -1,0 +1,135 @@
+/*
+ * mfm_oracle.h -- FP64 CPU oracle for the neighbour loops of the mesh-less
+ * finite-volume (MFV) and finite-mass (MFM) hydro scheme of Alonso Asensio,
+ * Dalla Vecchia, Potter & Stadel (arXiv 2211.12243).
+ *
+ * TEST INFRASTRUCTURE ONLY.  This library is the checker that the GPU path is
+ * compared against.  Only the test suite, the smoke check and the CPU-baseline
+ * leg of the benchmark load it; the product path never links or calls it.  It
+ * shares no code, header or table with the HIP library.
+ *
+ * Conventions (all arrays are plain host memory owned by the caller):
+ *   - n particles, structure of arrays, FP64.
+ *   - B (inverse of the E matrix) is stored as 6 arrays of n: xx,xy,xz,yy,yz,zz.
+ *   - grad is stored as 15 arrays of n: for q in (rho, vx, vy, vz, P) the
+ *     three components d/dx, d/dy, d/dz, i.e. grad[(3*q + k)*n + i].
+ *   - dQ and its scale are 5 arrays of n: (mass, px, py, pz, energy).
+ *   - box[k] > 0 makes axis k periodic with that side; box[k] == 0 on all axes
+ *     makes the domain open (used by the linear-field test).
+ * Every function returns 0 on success and a negative code on bad arguments.
+ */
+#ifndef MFM_ORACLE_H
+#define MFM_ORACLE_H
+#include <stdint.h>
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct {
+  int32_t scheme;        /* 0 = MFV, 1 = MFM (sec. 2.3.3, face velocity) */
+  int32_t limiter;       /* bit0: conditioned BJ slope limiter; bit1: pairwise face limiter (sec. 2.3.6) */
+  int32_t max_boosts;    /* times N_NGB may be multiplied by ngb_boost per particle (sec. 2.3.5) */
+  int32_t h_maxit;       /* iteration cap of the smoothing-length solve */
+  int32_t riemann_maxit; /* Newton cap of the exact Riemann solver */
+  int32_t pad0;
+  double gamma;          /* adiabatic index */
+  double n_ngb;          /* target neighbour number N_NGB (sec. 2.3.5) */
+  double ncond_max;      /* condition-number threshold, 100 in the paper */
+  double ngb_boost;      /* N_NGB growth factor on failure, 1.2 in the paper */
+  double h_tol;          /* relative tolerance of the H solve */
+  double c_cfl;          /* CFL factor (sec. 2.3.10) */
+  double psi1, psi2;     /* pairwise limiter constants, 0.5 and 0.25 in the paper */
+  double riemann_tol;    /* relative Newton step tolerance of the Riemann solve */
+  double alpha1;         /* dual-energy switch constant alpha_1 = 1/100 (sec. 2.3.7) */
+  double box[3];         /* periodic box sides (0 = open) */
+} orc_params;
+
+typedef struct {
+  int64_t h_noconv;      /* smoothing-length solves that hit the iteration cap */
+  int64_t ncond_boosts;  /* N_NGB boosts applied */
+  int64_t ncond_fail;    /* particles still above ncond_max after all boosts */
+  int64_t h_fallback;    /* particles whose candidate radius had to be widened */
+  int64_t grad_pairs;    /* ordered gradient interactions: sum_i #{j != i : r_ij < H_i} */
+  int64_t faces;         /* unordered flux pairs: #{i<j : r_ij < max(H_i, H_j)} */
+  int64_t riemann_iters; /* total Newton iterations of the Riemann solves */
+  int64_t riemann_maxit; /* Riemann solves that hit the iteration cap */
+  int64_t vacuum;        /* faces with vacuum generation (zero flux) */
+  int64_t positivity;    /* faces that fell back to first-order states */
+  int64_t neg_mass;      /* MFV particles whose mass became non-positive */
+  int64_t singular_e;    /* particles with a singular E matrix */
+} orc_counters;
+
+/* The cubic-spline kernel W(r, H) with compact support H (sec. 2.3.2). */
+double orc_kernel_W(double r, double H);
+
+/* All j with |x_j - x_i| < R_i (minimum image), including j == i.
+ * Two-pass CSR: call with idx == NULL to get counts into start[0..n] (start[n]
+ * = total), then again with idx of that length.  use_grid = 0 forces brute
+ * force O(N^2), 1 lets the oracle use its own uniform grid (periodic boxes). */
+int orc_neighbours(const orc_params *p, int64_t n, const double *x, const double *y,
+                   const double *z, const double *R, int use_grid, int64_t *start,
+                   int32_t *idx);
+
+/* Density loop (sec. 2.3.2, 2.3.5): solve the smoothing-length equation per
+ * particle starting from H, apply the condition-number check with N_NGB boosts,
+ * then V_i = 1/sum_j W(r_ij, H_i) (self included).
+ * In: x,y,z,H (start value).  Out: H (converged), V, ncond (unweighted, from
+ * the final neighbour set), nngb (effective N_NGB after boosts). */
+int orc_density(const orc_params *p, int64_t n, const double *x, const double *y,
+                const double *z, double *H, double *V, double *ncond, double *nngb,
+                orc_counters *cnt);
+
+/* Gradient loop (sec. 2.3.3, 2.3.6) and time-step loop (sec. 2.3.10).
+ * In: x,y,z,H,V,m,vx,vy,vz,U.  Out: rho, P, c, B[6n], grad[15n] (already
+ * multiplied by the limiter), alpha[5n] (limiter factors), ncond (weighted E),
+ * dt_i. */
+int orc_gradients(const orc_params *p, int64_t n, const double *x, const double *y,
+                  const double *z, const double *H, const double *V, const double *m,
+                  const double *vx, const double *vy, const double *vz, const double *U,
+                  double *rho, double *P, double *c, double *B, double *grad, double *alpha,
+                  double *ncond, double *dt_i, orc_counters *cnt);
+
+/* Exact Riemann solver (Toro's pressure function, Newton iteration).
+ * Returns 0 on convergence, 1 for vacuum generation, 2 when the cap was hit. */
+int orc_riemann(double gamma, double rhoL, double uL, double PL, double rhoR, double uR,
+                double PR, double tol, int maxit, double *pstar, double *ustar, int *iters);
+
+/* Sample the exact solution at speed xi = x/t (Toro's sampling). */
+int orc_riemann_sample(double gamma, double rhoL, double uL, double PL, double rhoR, double uR,
+                       double PR, double pstar, double ustar, double xi, double *rho, double *u,
+                       double *P);
+
+/* The flux of one face (i, j) as the oracle computes it: contribution vector
+ * c = |A_ij| F_ij (5 components) oriented from i (left) to j (right). */
+int orc_face(const orc_params *p, int64_t n, int64_t i, int64_t j, const double *x,
+             const double *y, const double *z, const double *H, const double *V,
+             const double *rho, const double *vx, const double *vy, const double *vz,
+             const double *P, const double *B, const double *grad, double dt, double *c,
+             orc_counters *cnt);
+
+/* Flux loop (sec. 2.3.3, 2.3.4, 2.3.6): for every unordered pair with
+ * r_ij < max(H_i, H_j), dQ_i -= dt c_ij and dQ_j += dt c_ij.
+ * Out: dQ[5n]; scale[5n] = dt * sum_j |c_ij| per component (the size against
+ * which accumulated sums are judged). */
+int orc_fluxes(const orc_params *p, int64_t n, const double *x, const double *y,
+               const double *z, const double *H, const double *V, const double *rho,
+               const double *vx, const double *vy, const double *vz, const double *P,
+               const double *B, const double *grad, double dt, double *dQ, double *scale,
+               orc_counters *cnt);
+
+/* Close of the step (eq. hydro_discr, internal-energy integration and the
+ * pressure switch of sec. 2.3.7, drift).  Updates x,y,z,m,vx,vy,vz,E,U in place. */
+int orc_update(const orc_params *p, int64_t n, double *x, double *y, double *z, double *m,
+               double *vx, double *vy, double *vz, double *E, double *U, const double *dQ,
+               double dt, orc_counters *cnt);
+
+/* One full step: density, gradients, dt = min(dt_max, min_i dt_i), fluxes,
+ * update.  State arrays are updated in place; dt_out receives the step. */
+int orc_step(const orc_params *p, int64_t n, double *x, double *y, double *z, double *m,
+             double *vx, double *vy, double *vz, double *E, double *U, double *H,
+             double dt_max, double *dt_out, orc_counters *cnt);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

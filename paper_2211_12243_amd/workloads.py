@@ -1,0 +1,209 @@
+"""Seeded synthetic particle sets shaped like the paper's hydro tests.
+
+This module only draws inputs: positions, masses, velocities and energies.  It
+holds none of the hydro method's arithmetic, and both the GPU library's tests
+and the CPU oracle's tests take their inputs from here.
+
+Recipes (all in a periodic unit box, lattice spacing D = 1/n, each particle at
+((i, j, k) + 1/2) D plus a seeded uniform jitter of up to 0.1 D per axis):
+
+* ``sod``    -- planar jump at x = 0.5 of the unjittered lattice: density 1 |
+  0.125 set through the particle mass, pressure 1 | 0.1, at rest (a Sod-like
+  shock tube, cf. sec. 3.1.2).
+* ``kh``     -- shear layers: density 2 for |y - 0.5| < 0.25 (through the mass),
+  1 outside; vx = +0.5 inside, -0.5 outside; vy = 0.01 sin(4 pi x); P = 2.5.
+* ``sedov``  -- uniform density 1 and pressure 1e-6; a unit energy added to the
+  internal energy of the 33 particles nearest the box centre with cubic-spline
+  weights of support equal to the distance of the 34th nearest (cf. sec. 3.1.5).
+* ``uniform`` -- uniform gas (density 1, pressure 1), optional bulk velocity;
+  with ``jitter = 0`` a perfect lattice.
+* ``clustered`` -- log-normal density field with a k^-2 spectrum, particles
+  Poisson-sampled per grid cell, Zel'dovich-like velocities (a stand-in for the
+  clustered cosmological gas the paper's scaling runs use, which are not
+  available here).
+
+A state is a dict of float64 numpy arrays: x, y, z, vx, vy, vz, m, E, U, H with
+E and U extensive (total and internal energy of the particle).  H is a start
+value for the smoothing-length solve: the support radius that encloses n_ngb
+particles at the mean number density.
+"""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+
+
+def _lattice(n: int, jitter: float, rng: np.random.Generator):
+    D = 1.0 / n
+    g = (np.arange(n, dtype=np.float64) + 0.5) * D
+    X, Y, Z = np.meshgrid(g, g, g, indexing="ij")
+    lat = np.stack([X.ravel(), Y.ravel(), Z.ravel()])
+    pos = lat.copy()
+    if jitter > 0:
+        pos += rng.uniform(-jitter * D, jitter * D, size=pos.shape)
+    pos = np.mod(pos, 1.0)
+    pos[pos >= 1.0] -= 1.0
+    return lat, pos, D
+
+
+def _finish(pos, m, v, P, gamma, rho_nominal, n_ngb, N):
+    U = m * P / ((gamma - 1.0) * rho_nominal)
+    E = U + 0.5 * m * (v[0] ** 2 + v[1] ** 2 + v[2] ** 2)
+    H0 = (3.0 * n_ngb / (4.0 * math.pi * N)) ** (1.0 / 3.0)
+    return {
+        "x": pos[0].copy(), "y": pos[1].copy(), "z": pos[2].copy(),
+        "vx": v[0].copy(), "vy": v[1].copy(), "vz": v[2].copy(),
+        "m": m, "E": E, "U": U, "H": np.full(N, H0),
+    }
+
+
+def sod(n: int = 16, seed: int = 1, gamma: float = 5.0 / 3.0, n_ngb: float = 32.0,
+        jitter: float = 0.1, rho=(1.0, 0.125), P=(1.0, 0.1)):
+    rng = np.random.default_rng(seed)
+    lat, pos, D = _lattice(n, jitter, rng)
+    N = pos.shape[1]
+    left = lat[0] < 0.5
+    rho_n = np.where(left, rho[0], rho[1])
+    Pn = np.where(left, P[0], P[1])
+    m = rho_n * D ** 3
+    v = np.zeros((3, N))
+    return _finish(pos, m, v, Pn, gamma, rho_n, n_ngb, N)
+
+
+def kh(n: int = 64, seed: int = 2, gamma: float = 5.0 / 3.0, n_ngb: float = 32.0,
+       jitter: float = 0.1):
+    rng = np.random.default_rng(seed)
+    lat, pos, D = _lattice(n, jitter, rng)
+    N = pos.shape[1]
+    inside = np.abs(lat[1] - 0.5) < 0.25
+    rho_n = np.where(inside, 2.0, 1.0)
+    m = rho_n * D ** 3
+    v = np.zeros((3, N))
+    v[0] = np.where(inside, 0.5, -0.5)
+    v[1] = 0.01 * np.sin(4.0 * math.pi * pos[0])
+    Pn = np.full(N, 2.5)
+    return _finish(pos, m, v, Pn, gamma, rho_n, n_ngb, N)
+
+
+def _spline_shape(q):
+    """Cubic B-spline shape used only to spread the deposited blast energy."""
+    q = np.asarray(q, dtype=np.float64)
+    out = np.where(q < 0.5, 1.0 - 6.0 * q ** 2 + 6.0 * q ** 3, 2.0 * (1.0 - q) ** 3)
+    return np.where(q < 1.0, out, 0.0)
+
+
+def sedov(n: int = 128, seed: int = 3, gamma: float = 5.0 / 3.0, n_ngb: float = 32.0,
+          jitter: float = 0.1, P0: float = 1e-6, E_blast: float = 1.0, n_dep: int = 33):
+    rng = np.random.default_rng(seed)
+    lat, pos, D = _lattice(n, jitter, rng)
+    N = pos.shape[1]
+    rho_n = np.ones(N)
+    m = rho_n * D ** 3
+    v = np.zeros((3, N))
+    st = _finish(pos, m, v, np.full(N, P0), gamma, rho_n, n_ngb, N)
+    d = pos - 0.5
+    r = np.sqrt((d ** 2).sum(axis=0))
+    order = np.lexsort((np.arange(N), r))  # by distance, ties by index
+    near = order[:n_dep]
+    h_dep = r[order[n_dep]]
+    w = _spline_shape(r[near] / h_dep)
+    w = w / w.sum()
+    st["U"][near] += E_blast * w
+    st["E"][near] += E_blast * w
+    return st
+
+
+def uniform(n: int = 16, seed: int = 0, gamma: float = 5.0 / 3.0, n_ngb: float = 32.0,
+            jitter: float = 0.1, rho: float = 1.0, P: float = 1.0, v0=(0.0, 0.0, 0.0)):
+    rng = np.random.default_rng(seed)
+    lat, pos, D = _lattice(n, jitter, rng)
+    N = pos.shape[1]
+    m = np.full(N, rho * D ** 3)
+    v = np.zeros((3, N))
+    for k in range(3):
+        v[k] += v0[k]
+    return _finish(pos, m, v, np.full(N, P), gamma, np.full(N, rho), n_ngb, N)
+
+
+def random_gas(N: int = 2000, seed: int = 0, gamma: float = 5.0 / 3.0, n_ngb: float = 32.0,
+               box: float = 1.0):
+    """Uniform random positions, random smooth-ish states (for parity tests)."""
+    rng = np.random.default_rng(seed)
+    pos = rng.uniform(0.0, box, size=(3, N))
+    rho_n = rng.uniform(0.5, 2.0, size=N)
+    m = rho_n * box ** 3 / N
+    v = rng.normal(0.0, 0.3, size=(3, N))
+    P = rng.uniform(0.5, 2.0, size=N)
+    st = _finish(pos, m, v, P, gamma, rho_n, n_ngb, N)
+    st["H"] *= box
+    return st
+
+
+def clustered(n: int = 256, seed: int = 4, gamma: float = 5.0 / 3.0, n_ngb: float = 32.0,
+              sigma_ln: float = 1.5, vrms_over_cs: float = 10.0):
+    """Log-normal clustered gas on an n^3 grid with N = n^3 particles in total."""
+    rng = np.random.default_rng(seed)
+    N = n ** 3
+    k = np.fft.fftfreq(n, d=1.0 / n)
+    KX, KY, KZ = np.meshgrid(k, k, k, indexing="ij")
+    K2 = KX ** 2 + KY ** 2 + KZ ** 2
+    K2[0, 0, 0] = 1.0
+    white = rng.standard_normal((n, n, n))
+    wk = np.fft.fftn(white)
+    amp = 1.0 / np.sqrt(K2)  # sqrt of P(k) ~ k^-2
+    amp[0, 0, 0] = 0.0
+    dk = wk * amp
+    delta = np.real(np.fft.ifftn(dk))
+    delta /= delta.std()
+    lnrho = sigma_ln * delta - 0.5 * sigma_ln ** 2
+    rho = np.exp(lnrho)
+    prob = (rho / rho.sum()).ravel()
+    counts = rng.multinomial(N, prob)
+    cells = np.repeat(np.arange(n ** 3), counts)
+    ci = np.stack(np.unravel_index(cells, (n, n, n))).astype(np.float64)
+    pos = (ci + rng.uniform(0.0, 1.0, size=ci.shape)) / n
+    pos = np.mod(pos, 1.0)
+    # Zel'dovich-like displacement field psi(k) = i k delta(k) / k^2
+    vel = []
+    for K in (KX, KY, KZ):
+        psik = 1j * K * dk / K2
+        psik[0, 0, 0] = 0.0
+        vel.append(np.real(np.fft.ifftn(psik)).ravel()[cells])
+    vel = np.stack(vel)
+    u0 = 1.0 / (gamma * (gamma - 1.0))  # sound speed 1 in code units
+    vrms = np.sqrt((vel ** 2).sum(axis=0).mean())
+    vel *= vrms_over_cs / vrms
+    m = np.full(N, 1.0 / N)
+    U = m * u0
+    E = U + 0.5 * m * (vel ** 2).sum(axis=0)
+    rho_p = rho.ravel()[cells] * 1.0
+    H = (3.0 * n_ngb * m / (4.0 * math.pi * rho_p)) ** (1.0 / 3.0)
+    return {"x": pos[0].copy(), "y": pos[1].copy(), "z": pos[2].copy(),
+            "vx": vel[0].copy(), "vy": vel[1].copy(), "vz": vel[2].copy(),
+            "m": m, "E": E, "U": U, "H": H}
+
+
+# The five configurations of the benchmark set, by name.
+CONFIGS = {
+    "sod16": dict(maker="sod", n=16, seed=1, scheme="mfv"),
+    "kh64": dict(maker="kh", n=64, seed=2, scheme="mfv"),
+    "sedov128": dict(maker="sedov", n=128, seed=3, scheme="mfm"),
+    "clustered256": dict(maker="clustered", n=256, seed=4, scheme="mfm"),
+}
+
+
+def make(name: str, **over):
+    spec = dict(CONFIGS[name])
+    spec.update(over)
+    maker = spec.pop("maker")
+    spec.pop("scheme", None)
+    return globals()[maker](**spec)
+
+
+def params_for(name: str, **over) -> dict:
+    """Plain-dict hydro parameters of a named configuration (gamma 5/3, N_NGB 32)."""
+    cfg = {"scheme": CONFIGS[name]["scheme"], "gamma": 5.0 / 3.0, "n_ngb": 32.0,
+           "box": (1.0, 1.0, 1.0)}
+    cfg.update(over)
+    return cfg

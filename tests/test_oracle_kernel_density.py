@@ -1,0 +1,151 @@
+"""Pins of the oracle's kernel, neighbour search and density loop (sec. 2.3.2, 2.3.5).
+
+Each check is fixed by something other than the oracle itself: quadrature of the
+kernel, brute-force neighbour sets computed with numpy, lattice symmetry, and
+the partition-of-unity property.
+"""
+import math
+
+import numpy as np
+import pytest
+from scipy import integrate
+
+import oracle
+from paper_2211_12243_amd import workloads as W
+
+BOX = {"box": (1.0, 1.0, 1.0)}
+
+
+def test_kernel_normalised_and_compact():
+    for H in (0.3, 1.0, 2.5):
+        val, err = integrate.quad(lambda r: 4 * math.pi * r * r * oracle.kernel_W(r, H), 0, H,
+                                  points=[0.5 * H], epsabs=1e-14, epsrel=1e-13)
+        assert abs(val - 1.0) < 1e-12
+        assert oracle.kernel_W(H, H) == 0.0
+        assert oracle.kernel_W(1.5 * H, H) == 0.0
+        assert oracle.kernel_W(0.0, H) == pytest.approx(8.0 / (math.pi * H ** 3), rel=1e-15)
+
+
+def test_kernel_smoothing_length_ratio():
+    # sec. 2.3.2: the smoothing length is about 0.55 of the support radius for
+    # the cubic spline (Dehnen & Aly: h = 2 sigma, sigma^2 = <r^2>/3).
+    H = 1.0
+    m2, _ = integrate.quad(lambda r: 4 * math.pi * r ** 4 * oracle.kernel_W(r, H), 0, H,
+                           points=[0.5], epsabs=1e-14)
+    ratio = 2.0 * math.sqrt(m2 / 3.0) / H
+    assert round(ratio, 2) == 0.55
+    assert abs(ratio - math.sqrt(0.3)) < 1e-12  # exact value of this kernel's second moment
+
+
+def test_kernel_continuous_first_derivative():
+    H = 1.0
+    for q0 in (0.5, 1.0):
+        eps = 1e-7
+        left = (oracle.kernel_W(q0 - eps, H) - oracle.kernel_W(q0 - 2 * eps, H)) / eps
+        right = (oracle.kernel_W(q0 + 2 * eps, H) - oracle.kernel_W(q0 + eps, H)) / eps
+        assert abs(left - right) < 1e-5
+
+
+def _np_neighbours(x, y, z, R, box):
+    pos = np.stack([x, y, z], axis=1)
+    d = pos[None, :, :] - pos[:, None, :]
+    for k in range(3):
+        if box[k] > 0:
+            d[..., k] -= box[k] * np.round(d[..., k] / box[k])
+    r2 = (d ** 2).sum(-1)
+    return [set(np.nonzero(r2[i] < R[i] ** 2)[0].tolist()) for i in range(len(x))]
+
+
+@pytest.mark.parametrize("seed", [0, 1])
+def test_neighbour_sets_grid_equals_brute_force(seed):
+    rng = np.random.default_rng(seed)
+    n = 600
+    x, y, z = rng.uniform(0, 1, (3, n))
+    # cluster some particles at the box faces and corners to exercise the wrap
+    x[:50] = rng.uniform(0, 0.02, 50)
+    y[50:100] = rng.uniform(0.98, 1.0, 50)
+    R = rng.uniform(0.05, 0.2, n)
+    ref = _np_neighbours(x, y, z, R, (1.0, 1.0, 1.0))
+    for use_grid in (False, True):
+        start, idx = oracle.neighbours(BOX, x, y, z, R, use_grid=use_grid)
+        got = [set(idx[start[i]:start[i + 1]].tolist()) for i in range(n)]
+        assert got == ref
+
+
+@pytest.fixture(scope="module")
+def lattice_density():
+    st = W.uniform(n=10, jitter=0.0)
+    d, cnt = oracle.density({}, st["x"], st["y"], st["z"], st["H"])
+    return st, d, cnt
+
+
+def test_density_perfect_lattice_is_uniform(lattice_density):
+    st, d, cnt = lattice_density
+    H, V = d["H"], d["V"]
+    assert np.ptp(H) / H.mean() < 1e-12
+    assert np.ptp(V) / V.mean() < 1e-12
+    # cubic symmetry makes E proportional to the identity: N_cond = 1 (sec. 2.3.5)
+    assert np.max(np.abs(d["ncond_tilde"] - 1.0)) < 1e-12
+    assert cnt["ncond_boosts"] == 0 and cnt["h_noconv"] == 0
+
+
+def test_density_root_solves_the_neighbour_equation(lattice_density):
+    # (4 pi / 3) n_i H_i^3 = N_NGB with n_i = 1/V_i (sec. 2.3.5)
+    st, d, _ = lattice_density
+    lhs = 4.0 * math.pi / 3.0 * d["H"] ** 3 / d["V"]
+    assert np.max(np.abs(lhs - 32.0)) < 1e-11
+
+
+def test_density_estimate_converges_to_number_density():
+    # omega^-1 is a kernel estimate of the number density (sec. 2.3.2); on a
+    # lattice it is off only by the kernel's aliasing error, below one percent.
+    errs = []
+    for nngb in (32.0, 64.0, 128.0):
+        st = W.uniform(n=12, jitter=0.0, n_ngb=nngb)
+        d, _ = oracle.density({"n_ngb": nngb}, st["x"], st["y"], st["z"], st["H"])
+        errs.append(abs(d["V"].mean() * 12 ** 3 - 1.0))
+    assert max(errs) < 1e-2, errs
+
+
+def test_density_partition_of_unity_volume():
+    # sum_i psi_i(x) = 1, so the volumes V_i = int psi_i tile the box (to O(h^2))
+    st = W.uniform(n=14, jitter=0.1, seed=5)
+    d, _ = oracle.density({}, st["x"], st["y"], st["z"], st["H"])
+    assert abs(d["V"].sum() - 1.0) < 1e-2
+
+
+def test_density_root_independent_of_start():
+    st = W.random_gas(N=1500, seed=3)
+    d1, _ = oracle.density({}, st["x"], st["y"], st["z"], st["H"])
+    d2, _ = oracle.density({}, st["x"], st["y"], st["z"], 0.6 * st["H"])
+    d3, _ = oracle.density({}, st["x"], st["y"], st["z"], 1.7 * st["H"])
+    assert np.max(np.abs(d1["H"] / d2["H"] - 1)) < 1e-12
+    assert np.max(np.abs(d1["H"] / d3["H"] - 1)) < 1e-12
+
+
+def test_density_brute_force_h_matches():
+    # recompute omega^-1 at the oracle's H with numpy neighbour sets
+    st = W.random_gas(N=800, seed=7)
+    d, _ = oracle.density({}, st["x"], st["y"], st["z"], st["H"])
+    sets = _np_neighbours(st["x"], st["y"], st["z"], d["H"], (1, 1, 1))
+    pos = np.stack([st["x"], st["y"], st["z"]], 1)
+    for i in range(0, 800, 37):
+        dd = pos[list(sets[i])] - pos[i]
+        dd -= np.round(dd)
+        r = np.sqrt((dd ** 2).sum(1))
+        winv = sum(oracle.kernel_W(rr, d["H"][i]) for rr in r)
+        assert winv * d["V"][i] == pytest.approx(1.0, rel=1e-13)
+
+
+def test_condition_number_boost_on_planar_particles():
+    # particles on two close planes: E is nearly singular in z, N_cond > 100,
+    # so N_NGB is boosted (sec. 2.3.5)
+    rng = np.random.default_rng(0)
+    n = 2000
+    x, y = rng.uniform(0, 1, (2, n))
+    z = np.where(np.arange(n) % 2 == 0, 0.5, 0.5 + 1e-4)
+    H = np.full(n, 0.15)
+    d, cnt = oracle.density({"max_boosts": 2}, x, y, z, H)
+    assert cnt["ncond_boosts"] > 0
+    assert np.all(d["nngb"] >= 32.0)
+    assert np.any(d["nngb"] > 32.0 * 1.19)
