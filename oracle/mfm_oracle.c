@@ -282,8 +282,9 @@ static void g_eval(const double *r, int64_t nr, double H, double nngb, double *g
 }
 
 /* reading: Newton's method on g(H) = 0 kept inside a bisection bracket
- * (lo, hi); stop when the step is below h_tol * H.  Returns iterations, or
- * -1 when the cap was reached. */
+ * (lo, hi); stop when a Newton step (not a bisection step) is below
+ * h_tol * H, so the last step converges quadratically and H is the root to
+ * roundoff.  Returns iterations, or -1 when the cap was reached. */
 static int solve_h(const double *r, int64_t nr, double nngb, double hi, double tol, int maxit,
                    double *H) {
   double lo = 0.0;
@@ -301,8 +302,12 @@ static int solve_h(const double *r, int64_t nr, double nngb, double hi, double t
     else
       hi = h;
     double hn = (dg > 0.0) ? h - g / dg : NAN;
-    if (!(hn > lo && hn < hi)) hn = 0.5 * (lo + hi);
-    int done = fabs(hn - h) <= tol * hn;
+    int newton = 1;
+    if (!(hn > lo && hn < hi)) {
+      hn = 0.5 * (lo + hi);
+      newton = 0;
+    }
+    int done = newton && fabs(hn - h) <= tol * hn;
     h = hn;
     if (done) {
       *H = h;
