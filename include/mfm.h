@@ -1,0 +1,213 @@
+/*
+ * mfm.h -- C ABI of the MI355X library for the neighbour loops of the
+ * mesh-less finite-volume (MFV) and mesh-less finite-mass (MFM) hydro scheme
+ * of Alonso Asensio, Dalla Vecchia, Potter & Stadel, "Mesh-free hydrodynamics
+ * in pkdgrav3 for galaxy formation simulations" (arXiv 2211.12243).
+ *
+ * The paper splits one hydro step into four loops over neighbouring particles
+ * (sec. 2.2.3): (1) smoothing length and number density, (2) gradients and
+ * limiter, (3) extrapolation, Riemann solver and fluxes, (4) time step.  The
+ * entry points below are those loops, plus the neighbour-cell build that they
+ * share and the close of the step (eq. hydro_discr and sec. 2.3.7).
+ *
+ * Memory.  Every array is DEVICE memory owned by the caller (for example torch
+ * tensors), structure of arrays, FP64, length n unless stated.  The library
+ * never allocates or frees device memory: mfm_create carves its scratch space
+ * out of one caller-supplied device workspace of mfm_workspace_bytes() bytes,
+ * which must stay alive until mfm_destroy.  The library never frees caller
+ * memory.  Host structs passed by pointer are copied; they may be freed after
+ * the call returns.
+ *
+ * Streams.  Every call enqueues work on the hipStream_t given to mfm_create
+ * and returns without waiting, except where stated ("synchronises").
+ *
+ * Errors.  Every function returns MFM_OK (0) or a negative MFM_E_* code; no
+ * exception or abort crosses the ABI.  mfm_strerror() gives the text, and
+ * mfm_last_error() the message of the last failure on a context (for
+ * MFM_E_HIP it holds the HIP runtime's error string).  Conditions found inside
+ * kernels (an H solve that did not converge, an overflowing neighbour list)
+ * are counted in device counters and surface at the next synchronising call.
+ *
+ * Threads.  A context may be used by one host thread at a time.
+ */
+#ifndef MFM_H
+#define MFM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* status codes */
+#define MFM_OK 0
+#define MFM_E_ARG (-1)        /* null pointer, n out of range, invalid parameter */
+#define MFM_E_WORKSPACE (-2)  /* workspace missing or smaller than mfm_workspace_bytes() */
+#define MFM_E_HIP (-3)        /* HIP runtime error (text in mfm_last_error) */
+#define MFM_E_H_NOCONV (-4)   /* some smoothing-length solve hit its iteration cap */
+#define MFM_E_CELLS (-5)      /* smoothing lengths outgrew the cell grid after rebuilds */
+#define MFM_E_LIST (-6)       /* a particle has more neighbours than the list capacity */
+#define MFM_E_NONFINITE (-7)  /* a non-finite time step or state was produced */
+#define MFM_E_STATE (-8)      /* call order violated (e.g. mfm_fluxes before mfm_gradients) */
+
+/* parameter values */
+#define MFM_SCHEME_MFV 0 /* face moves with the mean particle velocity; mass flows */
+#define MFM_SCHEME_MFM 1 /* face moves with the contact of the Riemann problem; no mass flux */
+#define MFM_FP64 0       /* all pair arithmetic in FP64 */
+#define MFM_MIXED 1      /* FP32 pair arithmetic, FP64 accumulators (see mfm_params.precision) */
+#define MFM_GUESS_PLAIN 0
+#define MFM_GUESS_LEARNED 1
+#define MFM_LIMIT_BJ 1       /* conditioned Barth-Jespersen slope limiter (sec. 2.3.6) */
+#define MFM_LIMIT_PAIRWISE 2 /* pairwise face limiter with psi1, psi2 (sec. 2.3.6) */
+
+/* Hydro parameters (sec. 2.3).  mfm_default_params() fills the paper's
+ * defaults: N_NGB = 32, N_cond threshold 100 with x1.2 boosts (sec. 2.3.5),
+ * psi1 = 0.5, psi2 = 0.25 (sec. 2.3.6), alpha1 = 1/100 (sec. 2.3.7). */
+typedef struct mfm_params {
+  int32_t scheme;        /* MFM_SCHEME_MFV or MFM_SCHEME_MFM */
+  int32_t precision;     /* MFM_FP64 or MFM_MIXED */
+  int32_t limiter;       /* OR of MFM_LIMIT_* */
+  int32_t max_boosts;    /* N_NGB boosts allowed per particle and step (default 5) */
+  int32_t h_maxit;       /* smoothing-length iteration cap (default 64) */
+  int32_t riemann_maxit; /* Riemann Newton cap (default 100) */
+  int32_t guess;         /* MFM_GUESS_PLAIN or MFM_GUESS_LEARNED */
+  int32_t max_list;      /* neighbour list capacity per particle (default 128) */
+  double gamma;          /* adiabatic index (> 1) */
+  double n_ngb;          /* neighbour number N_NGB (> 32/3, non-integer allowed) */
+  double ncond_max;      /* condition-number threshold (default 100) */
+  double ngb_boost;      /* N_NGB factor when a particle fails the check (default 1.2) */
+  double h_tol;          /* relative tolerance of the smoothing-length solve (default 1e-13) */
+  double c_cfl;          /* CFL factor (default 0.2) */
+  double psi1, psi2;     /* pairwise limiter constants */
+  double riemann_tol;    /* relative Newton step tolerance of the exact solver (default 1e-10) */
+  double alpha1;         /* dual-energy switch: U > alpha1 E_kin -> U from E (default 0.01) */
+  double box[3];         /* periodic box sides; all > 0 (the library needs a periodic box) */
+  double cell_margin;    /* cell side >= cell_margin * max_i H_i (>= 1, default 1.15) */
+  int32_t max_cell_dim;  /* cells per axis at most (default 256, at most 1024) */
+  int32_t pad0;
+} mfm_params;
+
+/* The particle set: device pointers, each of n FP64 values (B: 6n, grad: 15n,
+ * dQ: 5n, entry k of particle i at [k * n + i]).
+ *   state (read and written): x, y, z  positions in [0, box)
+ *                             vx, vy, vz velocities
+ *                             m  mass, E total energy, U internal energy
+ *                                (E and U extensive: per particle, not per mass)
+ *                             H  support radius of the kernel (the start value
+ *                                of the smoothing-length solve; overwritten)
+ *   outputs of mfm_density:   V volume 1/omega^-1, rho = m/V, P = (gamma-1)U/V,
+ *                             c sound speed, ncond (the unweighted check value)
+ *   outputs of mfm_gradients: B = E^-1 (xx,xy,xz,yy,yz,zz), grad (for q in
+ *                             rho, vx, vy, vz, P the d/dx, d/dy, d/dz, already
+ *                             multiplied by the slope limiter), ncond (of the
+ *                             volume-weighted E), dt_i
+ *   output of mfm_fluxes:     dQ = -dt sum_j F_ij A_ij for (m, px, py, pz, E)
+ *   id (optional int64):      moved with the state whenever the state is permuted
+ */
+typedef struct mfm_particles {
+  int64_t n;
+  double *x, *y, *z, *vx, *vy, *vz, *m, *E, *U, *H;
+  double *V, *rho, *P, *c, *ncond;
+  double *B, *grad, *dQ, *dt_i;
+  int64_t *id; /* optional (may be NULL): caller's particle labels, permuted with the state */
+} mfm_particles;
+
+/* Counters and conserved totals (filled by mfm_diagnostics). */
+typedef struct mfm_diag {
+  int64_t h_noconv;      /* smoothing-length solves that hit h_maxit */
+  int64_t ncond_boosts;  /* N_NGB boosts applied */
+  int64_t ncond_fail;    /* particles still above ncond_max after max_boosts */
+  int64_t cell_rebuilds; /* cell grids rebuilt because H outgrew them */
+  int64_t list_overflow; /* particles with more than max_list neighbours */
+  int64_t grad_pairs;    /* sum_i #{j != i : r_ij < H_i} of the last mfm_gradients */
+  int64_t faces;         /* #{unordered pairs : r_ij < max(H_i, H_j)} of the last mfm_fluxes */
+  int64_t riemann_iters; /* Newton iterations of the last mfm_fluxes */
+  int64_t riemann_maxit; /* faces that hit riemann_maxit */
+  int64_t vacuum;        /* faces with vacuum generation (no flux) */
+  int64_t positivity;    /* faces that fell back to first-order states */
+  int64_t neg_mass;      /* particles whose MFV mass became non-positive (not clamped) */
+  int64_t singular_e;    /* particles with a singular E matrix */
+  int64_t guess_fallback;/* learned guesses rejected for the plain one */
+  int64_t fp64_inverse;  /* mixed path: E matrices inverted in FP64 */
+  int64_t pad[3];
+  double mass, px, py, pz, energy; /* sums over particles of m, m v, E */
+} mfm_diag;
+
+/* Fill p with the defaults listed above (MFV, FP64, both limiters, gamma 5/3,
+ * unit periodic box). */
+void mfm_default_params(mfm_params *p);
+
+/* Bytes of device workspace a context for up to n_max particles needs. */
+size_t mfm_workspace_bytes(const mfm_params *p, int64_t n_max);
+
+/* Create a context.  workspace: device pointer of at least
+ * mfm_workspace_bytes(p, n_max) bytes, 256-byte aligned.  stream: a
+ * hipStream_t (NULL = the default stream).  Returns MFM_E_ARG for invalid
+ * parameters, MFM_E_WORKSPACE when the workspace is missing or too small. */
+int mfm_create(const mfm_params *p, int64_t n_max, void *workspace, size_t workspace_bytes,
+               void *stream, struct mfm_ctx **out);
+int mfm_destroy(struct mfm_ctx *ctx);
+
+/* Sort the particles into cells on a Morton (Z-order) curve of cells of side
+ * >= cell_margin * max H (sec. 2.2.1: particles are reordered in memory so
+ * that spatial neighbours are contiguous) and permute the state arrays
+ * (x..H) IN PLACE into that order.  perm (device int64, n, may be NULL)
+ * receives for each new slot k the slot the particle had before the call.
+ * Synchronises (it reads max H to size the grid). */
+int mfm_build_cells(struct mfm_ctx *ctx, const mfm_particles *parts, int64_t *perm);
+
+/* Loop (1), sec. 2.3.2 and 2.3.5: per particle, solve
+ * (4 pi/3) H^3 omega^-1(H) = N_NGB for H, with omega^-1 = sum_j W(r_ij, H)
+ * (self included); if the condition number of E~ = sum_j W d d^T exceeds
+ * ncond_max, multiply N_NGB by ngb_boost and solve again.  Writes H, V, rho,
+ * P, c, ncond and the neighbour lists used by the next two loops.  Requires
+ * mfm_build_cells on the same positions.  If some H reaches the cell side the
+ * call rebuilds the cells and repeats (this synchronises). */
+int mfm_density(struct mfm_ctx *ctx, const mfm_particles *parts);
+
+/* Loops (2) and (4), sec. 2.3.3, 2.3.6, 2.3.10: E_i = sum_j V_j W_ij d d^T,
+ * B_i = E_i^-1, grad q_i = B_i sum_j V_j W_ij (q_j - q_i) d for q in
+ * (rho, v, P), conditioned slope limiter, signal velocity and
+ * dt_i = c_cfl H_i / v_sig,i.  dt_dev (device double) receives
+ * min(dt_max, min_i dt_i); it stays on the device. */
+int mfm_gradients(struct mfm_ctx *ctx, const mfm_particles *parts, double dt_max,
+                  double *dt_dev);
+
+/* Loop (3), sec. 2.3.3, 2.3.4, 2.3.6: for every unordered pair with
+ * r_ij < max(H_i, H_j), the face vector A_ij, half-step extrapolation of the
+ * primitives to the face, pairwise limiter, exact Riemann solve, MFV or MFM
+ * flux; dQ_i -= dt F_ij A_ij and dQ_j += dt F_ij A_ij with the same value
+ * (bitwise antisymmetric).  dt_dev: device pointer to the step (from
+ * mfm_gradients). */
+int mfm_fluxes(struct mfm_ctx *ctx, const mfm_particles *parts, const double *dt_dev);
+
+/* Close of the step, eq. hydro_discr and sec. 2.3.7: m += dQ_m, m v += dQ_p,
+ * E += dQ_E, U += dQ_E - v.dQ_p + v^2/2 dQ_m, U := E - E_kin when
+ * U > alpha1 E_kin, and the drift x += dt (v_old + v_new)/2 (periodic wrap). */
+int mfm_update(struct mfm_ctx *ctx, const mfm_particles *parts, const double *dt_dev);
+
+/* One full step: cells, density, gradients, fluxes, update.  dt_host receives
+ * the step taken.  Synchronises. */
+int mfm_step(struct mfm_ctx *ctx, const mfm_particles *parts, double dt_max, double *dt_host);
+
+/* Counters accumulated since the last mfm_reset_counters, and the conserved
+ * totals of the current state.  Synchronises. */
+int mfm_diagnostics(struct mfm_ctx *ctx, const mfm_particles *parts, mfm_diag *out);
+int mfm_reset_counters(struct mfm_ctx *ctx);
+
+/* Kernel timing on the context's stream with HIP events.  While enabled every
+ * launch of the loops is bracketed by events; mfm_kernel_times (synchronises)
+ * returns, per stage (0 cells, 1 density, 2 lists, 3 gradients, 4 fluxes,
+ * 5 update), the summed milliseconds and launch counts since enabling. */
+#define MFM_NSTAGES 6
+int mfm_enable_timing(struct mfm_ctx *ctx, int on);
+int mfm_kernel_times(struct mfm_ctx *ctx, double *ms_out, int64_t *count_out);
+
+const char *mfm_strerror(int status);
+const char *mfm_last_error(struct mfm_ctx *ctx);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,193 @@
+// cells.hip -- neighbour-cell build: Morton order of cells, counting sort of
+// the particles into it, and the in-place permutation of the state arrays.
+//
+// The paper reorders its particle array so that the particles of a tree node
+// are contiguous (sec. 2.2.1) and searches neighbours per bucket of particles
+// (sec. 2.2.3).  Here the buckets are cells of a uniform periodic grid whose
+// side is at least the largest support radius, laid out along a Z-order curve,
+// so every pair closer than max(H_i, H_j) is found in the 27 cells around a
+// particle's own, and a 64-lane wavefront of consecutive particles touches a
+// compact set of cells.
+#include "mfm_internal.h"
+
+namespace {
+
+constexpr int BS = 256;
+constexpr int RED_BLOCKS = 1024;
+
+__global__ void fill_i32_k(int32_t *a, int64_t n, int32_t v) {
+  for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < n;
+       k += (int64_t)gridDim.x * blockDim.x)
+    a[k] = v;
+}
+
+__global__ void max_partial_k(const double *__restrict__ v, int64_t n, double *partial) {
+  __shared__ double s[BS / 64];
+  double m = 0.0;
+  for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < n;
+       k += (int64_t)gridDim.x * blockDim.x)
+    m = fmax(m, v[k]);
+  for (int o = 32; o > 0; o >>= 1) m = fmax(m, __shfl_xor(m, o, 64));
+  if ((threadIdx.x & 63) == 0) s[threadIdx.x >> 6] = m;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int w = 1; w < BS / 64; ++w) m = fmax(m, s[w]);
+    partial[blockIdx.x] = m;
+  }
+}
+
+__global__ void max_final_k(const double *partial, int np, double *out) {
+  __shared__ double s[BS / 64];
+  double m = 0.0;
+  for (int k = threadIdx.x; k < np; k += blockDim.x) m = fmax(m, partial[k]);
+  for (int o = 32; o > 0; o >>= 1) m = fmax(m, __shfl_xor(m, o, 64));
+  if ((threadIdx.x & 63) == 0) s[threadIdx.x >> 6] = m;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int w = 1; w < BS / 64; ++w) m = fmax(m, s[w]);
+    out[0] = m;
+  }
+}
+
+// Morton code of each particle's cell and the per-cell histogram.
+__global__ void cell_code_k(int64_t n, const double *__restrict__ x, const double *__restrict__ y,
+                            const double *__restrict__ z, CellGrid g, uint32_t *code,
+                            int32_t *count) {
+  int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  int cx = cell_coord(x[i], g.inv[0], g.nc[0]);
+  int cy = cell_coord(y[i], g.inv[1], g.nc[1]);
+  int cz = cell_coord(z[i], g.inv[2], g.nc[2]);
+  uint32_t c = morton3(cx, cy, cz);
+  code[i] = c;
+  atomicAdd(count + c, 1);
+}
+
+// Exclusive scan, 1024 elements per block (4 per thread), block totals out.
+__global__ void scan_block_k(const int32_t *in, int32_t *out, int64_t n, int32_t *block_sums) {
+  __shared__ int32_t s[BS];
+  int64_t base = blockIdx.x * (int64_t)(4 * BS) + 4 * threadIdx.x;
+  int32_t v[4];
+  int32_t t = 0;
+  for (int k = 0; k < 4; ++k) {
+    v[k] = (base + k < n) ? in[base + k] : 0;
+    t += v[k];
+  }
+  s[threadIdx.x] = t;
+  __syncthreads();
+  for (int off = 1; off < BS; off <<= 1) {
+    int32_t add = (threadIdx.x >= (unsigned)off) ? s[threadIdx.x - off] : 0;
+    __syncthreads();
+    s[threadIdx.x] += add;
+    __syncthreads();
+  }
+  int32_t run = s[threadIdx.x] - t;  // exclusive prefix of this thread
+  for (int k = 0; k < 4; ++k) {
+    if (base + k < n) out[base + k] = run;
+    run += v[k];
+  }
+  if (threadIdx.x == BS - 1) block_sums[blockIdx.x] = s[BS - 1];
+}
+
+__global__ void scan_add_k(int32_t *out, int64_t n, const int32_t *block_offsets) {
+  int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i < n) out[i] += block_offsets[i / (4 * BS)];
+}
+
+hipError_t scan_exclusive(hipStream_t st, const int32_t *in, int32_t *out, int64_t n,
+                          int32_t *tmp) {
+  int64_t nb = (n + 4 * BS - 1) / (4 * BS);
+  scan_block_k<<<(int)nb, BS, 0, st>>>(in, out, n, tmp);
+  if (nb > 1) {
+    hipError_t e = scan_exclusive(st, tmp, tmp, nb, tmp + nb);
+    if (e != hipSuccess) return e;
+    scan_add_k<<<blocks_for(n, BS), BS, 0, st>>>(out, n, tmp);
+  }
+  return hipGetLastError();
+}
+
+__global__ void scatter_k(int64_t n, const uint32_t *__restrict__ code, int32_t *cursor,
+                          int32_t *order) {
+  int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  int32_t dst = atomicAdd(cursor + code[i], 1);
+  order[dst] = (int32_t)i;
+}
+
+// Within a cell, order the particles by their slot before the sort, so the
+// result does not depend on the order the atomics were served in.
+__global__ void cell_sort_k(int64_t ncodes, const int32_t *__restrict__ start,
+                            const int32_t *__restrict__ count, int32_t *order) {
+  int64_t c = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (c >= ncodes) return;
+  int k = count[c];
+  if (k < 2) return;
+  int32_t *a = order + start[c];
+  for (int s = 1; s < k; ++s) {
+    int32_t v = a[s];
+    int t = s - 1;
+    while (t >= 0 && a[t] > v) {
+      a[t + 1] = a[t];
+      --t;
+    }
+    a[t + 1] = v;
+  }
+}
+
+struct Fields {
+  double *f[10];
+  int64_t *id;
+};
+
+__global__ void gather_k(int64_t n, Fields fs, const int32_t *__restrict__ order, double *tmp,
+                         int64_t *perm) {
+  int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (k >= n) return;
+  int32_t o = order[k];
+#pragma unroll
+  for (int f = 0; f < 10; ++f) tmp[f * n + k] = fs.f[f][o];
+  if (fs.id) ((int64_t *)(tmp + 10 * n))[k] = fs.id[o];
+  if (perm) perm[k] = o;
+}
+
+__global__ void writeback_k(int64_t n, Fields fs, const double *__restrict__ tmp) {
+  int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (k >= n) return;
+#pragma unroll
+  for (int f = 0; f < 10; ++f) fs.f[f][k] = tmp[f * n + k];
+  if (fs.id) fs.id[k] = ((const int64_t *)(tmp + 10 * n))[k];
+}
+
+}  // namespace
+
+hipError_t launch_max_h(mfm_ctx *ctx, const mfm_particles *pp) {
+  max_partial_k<<<RED_BLOCKS, BS, 0, ctx->stream>>>(pp->H, pp->n, ctx->red);
+  max_final_k<<<1, BS, 0, ctx->stream>>>(ctx->red, RED_BLOCKS, ctx->scalars);
+  return hipGetLastError();
+}
+
+hipError_t launch_build_cells(mfm_ctx *ctx, const mfm_particles *pp, int64_t *perm) {
+  hipStream_t st = ctx->stream;
+  const int64_t n = pp->n;
+  const CellGrid &g = ctx->grid;
+  int fb = (int)(ctx->ncodes / BS + 1);
+  if (fb > 4096) fb = 4096;
+  fill_i32_k<<<fb, BS, 0, st>>>(ctx->cell_count, ctx->ncodes, 0);
+  cell_code_k<<<blocks_for(n, BS), BS, 0, st>>>(n, pp->x, pp->y, pp->z, g, ctx->code,
+                                                 ctx->cell_count);
+  hipError_t e = scan_exclusive(st, ctx->cell_count, ctx->cell_start, ctx->ncodes, ctx->scan_tmp);
+  if (e != hipSuccess) return e;
+  e = hipMemcpyAsync(ctx->cursor, ctx->cell_start, ctx->ncodes * sizeof(int32_t),
+                     hipMemcpyDeviceToDevice, st);
+  if (e != hipSuccess) return e;
+  scatter_k<<<blocks_for(n, BS), BS, 0, st>>>(n, ctx->code, ctx->cursor, ctx->order);
+  cell_sort_k<<<blocks_for(ctx->ncodes, BS), BS, 0, st>>>(ctx->ncodes, ctx->cell_start,
+                                                           ctx->cell_count, ctx->order);
+  Fields fs;
+  double *src[10] = {pp->x, pp->y, pp->z, pp->vx, pp->vy, pp->vz, pp->m, pp->E, pp->U, pp->H};
+  for (int f = 0; f < 10; ++f) fs.f[f] = src[f];
+  fs.id = pp->id;
+  gather_k<<<blocks_for(n, BS), BS, 0, st>>>(n, fs, ctx->order, ctx->tmp, perm);
+  writeback_k<<<blocks_for(n, BS), BS, 0, st>>>(n, fs, ctx->tmp);
+  return hipGetLastError();
+}

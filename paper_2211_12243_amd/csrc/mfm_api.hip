@@ -1,0 +1,455 @@
+// mfm_api.hip -- the C ABI declared in include/mfm.h: parameter checks,
+// workspace carving, launch order, error reporting and event timing.
+#include <math.h>
+#include <stdio.h>
+#include <stdlib.h>
+#include <string.h>
+
+#include "mfm_internal.h"
+
+namespace {
+
+constexpr size_t ALIGN = 256;
+
+struct Layout {
+  size_t code, count, start, cursor, scan, order, tmp, list, cnt, rec, red, counters, scalars;
+  size_t total;
+  int64_t ncodes_max;
+  size_t scan_len;
+};
+
+int ceil_log2(int v) {
+  int b = 0;
+  while ((1 << b) < v) ++b;
+  return b;
+}
+
+size_t up(size_t v) { return (v + ALIGN - 1) / ALIGN * ALIGN; }
+
+Layout make_layout(const mfm_params *p, int64_t n) {
+  Layout L;
+  int bits = ceil_log2(p->max_cell_dim < 3 ? 3 : p->max_cell_dim);
+  L.ncodes_max = (int64_t)1 << (3 * bits);
+  size_t scan_len = 64;
+  for (int64_t m = L.ncodes_max; m > 1; m = (m + 1023) / 1024) scan_len += (size_t)(m + 1023) / 1024;
+  L.scan_len = scan_len;
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    size_t o = off;
+    off += up(bytes);
+    return o;
+  };
+  L.code = take(4 * (size_t)n);
+  L.count = take(4 * (size_t)L.ncodes_max);
+  L.start = take(4 * (size_t)L.ncodes_max);
+  L.cursor = take(4 * (size_t)L.ncodes_max);
+  L.scan = take(4 * scan_len);
+  L.order = take(4 * (size_t)n);
+  L.tmp = take(8 * 11 * (size_t)n);
+  L.list = take(4 * (size_t)p->max_list * (size_t)n);
+  L.cnt = take(4 * (size_t)n);
+  L.rec = take(8 * (size_t)R_STRIDE * (size_t)n);
+  L.red = take(8 * 5 * 1024);
+  L.counters = take(8 * NCOUNTERS);
+  L.scalars = take(8 * 16);
+  L.total = off;
+  return L;
+}
+
+int check_params(const mfm_params *p) {
+  if (!p) return 0;
+  if (p->scheme != MFM_SCHEME_MFV && p->scheme != MFM_SCHEME_MFM) return 0;
+  if (p->precision != MFM_FP64 && p->precision != MFM_MIXED) return 0;
+  if (!(p->gamma > 1.0)) return 0;
+  if (!(p->n_ngb > 32.0 / 3.0)) return 0;
+  if (!(p->ncond_max > 1.0) || !(p->ngb_boost > 1.0) || p->max_boosts < 0) return 0;
+  if (!(p->h_tol > 0.0) || p->h_maxit < 1) return 0;
+  if (!(p->c_cfl > 0.0)) return 0;
+  if (!(p->riemann_tol > 0.0) || p->riemann_maxit < 1) return 0;
+  if (p->max_list < 1 || p->max_list > 4096) return 0;
+  if (!(p->cell_margin >= 1.0)) return 0;
+  if (p->max_cell_dim < 3 || p->max_cell_dim > 512) return 0;
+  for (int k = 0; k < 3; ++k)
+    if (!(p->box[k] > 0.0)) return 0;
+  return 1;
+}
+
+int check_parts(const mfm_ctx *ctx, const mfm_particles *pp) {
+  if (!pp || pp->n <= 0 || pp->n > ctx->n_max || pp->n > 0x7fffffff) return 0;
+  const void *req[] = {pp->x, pp->y, pp->z, pp->vx, pp->vy, pp->vz, pp->m, pp->E, pp->U,
+                       pp->H, pp->V, pp->rho, pp->P, pp->c, pp->ncond, pp->B, pp->grad,
+                       pp->dQ, pp->dt_i};
+  for (const void *q : req)
+    if (!q) return 0;
+  return 1;
+}
+
+int fail(mfm_ctx *ctx, int code, const char *msg) {
+  if (ctx) snprintf(ctx->err, sizeof(ctx->err), "%s", msg);
+  return code;
+}
+
+int hip_fail(mfm_ctx *ctx, hipError_t e, const char *where) {
+  if (ctx) snprintf(ctx->err, sizeof(ctx->err), "%s: %s", where, hipGetErrorString(e));
+  return MFM_E_HIP;
+}
+
+#define HIPCHK(ctx, expr, where)              \
+  do {                                        \
+    hipError_t e_ = (expr);                   \
+    if (e_ != hipSuccess) return hip_fail(ctx, e_, where); \
+  } while (0)
+
+int read_counters(mfm_ctx *ctx, int64_t *host) {
+  HIPCHK(ctx, hipMemcpyAsync(host, ctx->counters, sizeof(int64_t) * NCOUNTERS,
+                             hipMemcpyDeviceToHost, ctx->stream),
+         "read counters");
+  HIPCHK(ctx, hipStreamSynchronize(ctx->stream), "synchronise");
+  return MFM_OK;
+}
+
+int setup_grid(mfm_ctx *ctx, double hmax) {
+  CellGrid &g = ctx->grid;
+  double s = hmax * ctx->p.cell_margin * ctx->margin_boost;
+  if (!(s > 0.0) || !isfinite(s)) return fail(ctx, MFM_E_ARG, "smoothing lengths must be > 0");
+  int ncmax = 0;
+  g.side_min = 1e300;
+  for (int k = 0; k < 3; ++k) {
+    double L = ctx->p.box[k];
+    double c = floor(L / s);
+    if (c > ctx->p.max_cell_dim) c = ctx->p.max_cell_dim;
+    if (c < 3.0)
+      return fail(ctx, MFM_E_CELLS, "support radius too large: fewer than 3 cells per axis");
+    g.nc[k] = (int)c;
+    g.inv[k] = c / L;
+    g.box[k] = L;
+    g.half[k] = 0.5 * L;
+    double side = L / c;
+    if (side < g.side_min) g.side_min = side;
+    if (g.nc[k] > ncmax) ncmax = g.nc[k];
+  }
+  ctx->bits = ceil_log2(ncmax);
+  ctx->ncodes = (int64_t)1 << (3 * ctx->bits);
+  g.start = ctx->cell_start;
+  g.count = ctx->cell_count;
+  return MFM_OK;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// timing
+// ---------------------------------------------------------------------------
+void stage_begin(mfm_ctx *ctx, int stage) {
+  if (!ctx->timing || ctx->ev_used >= 1024) return;
+  int k = ctx->ev_used;
+  ctx->ev_stage[k] = stage;
+  hipEventRecord(ctx->ev_pool[2 * k], ctx->stream);
+}
+
+void stage_end(mfm_ctx *ctx, int stage) {
+  (void)stage;
+  if (!ctx->timing || ctx->ev_used >= 1024) return;
+  int k = ctx->ev_used;
+  hipEventRecord(ctx->ev_pool[2 * k + 1], ctx->stream);
+  ctx->ev_used = k + 1;
+}
+
+static void harvest_events(mfm_ctx *ctx) {
+  for (int k = 0; k < ctx->ev_used; ++k) {
+    float ms = 0.0f;
+    hipEventSynchronize(ctx->ev_pool[2 * k + 1]);
+    if (hipEventElapsedTime(&ms, ctx->ev_pool[2 * k], ctx->ev_pool[2 * k + 1]) == hipSuccess) {
+      ctx->stage_ms[ctx->ev_stage[k]] += ms;
+      ctx->stage_count[ctx->ev_stage[k]] += 1;
+    }
+  }
+  ctx->ev_used = 0;
+}
+
+extern "C" {
+
+void mfm_default_params(mfm_params *p) {
+  if (!p) return;
+  memset(p, 0, sizeof(*p));
+  p->scheme = MFM_SCHEME_MFV;
+  p->precision = MFM_FP64;
+  p->limiter = MFM_LIMIT_BJ | MFM_LIMIT_PAIRWISE;
+  p->max_boosts = 5;
+  p->h_maxit = 64;
+  p->riemann_maxit = 100;
+  p->guess = MFM_GUESS_PLAIN;
+  p->max_list = 128;
+  p->gamma = 5.0 / 3.0;
+  p->n_ngb = 32.0;
+  p->ncond_max = 100.0;
+  p->ngb_boost = 1.2;
+  p->h_tol = 1e-13;
+  p->c_cfl = 0.2;
+  p->psi1 = 0.5;
+  p->psi2 = 0.25;
+  p->riemann_tol = 1e-10;
+  p->alpha1 = 0.01;
+  p->box[0] = p->box[1] = p->box[2] = 1.0;
+  p->cell_margin = 1.15;
+  p->max_cell_dim = 256;
+}
+
+size_t mfm_workspace_bytes(const mfm_params *p, int64_t n_max) {
+  if (!check_params(p) || n_max <= 0) return 0;
+  return make_layout(p, n_max).total;
+}
+
+int mfm_create(const mfm_params *p, int64_t n_max, void *workspace, size_t workspace_bytes,
+               void *stream, mfm_ctx **out) {
+  if (!out) return MFM_E_ARG;
+  *out = nullptr;
+  if (!check_params(p) || n_max <= 0 || n_max > 0x7fffffff) return MFM_E_ARG;
+  Layout L = make_layout(p, n_max);
+  if (!workspace || workspace_bytes < L.total || ((uintptr_t)workspace % ALIGN) != 0)
+    return MFM_E_WORKSPACE;
+  mfm_ctx *ctx = (mfm_ctx *)calloc(1, sizeof(mfm_ctx));
+  if (!ctx) return MFM_E_ARG;
+  ctx->p = *p;
+  ctx->n_max = n_max;
+  ctx->stream = (hipStream_t)stream;
+  ctx->ws = (char *)workspace;
+  ctx->ws_bytes = workspace_bytes;
+  ctx->code = (uint32_t *)(ctx->ws + L.code);
+  ctx->cell_count = (int32_t *)(ctx->ws + L.count);
+  ctx->cell_start = (int32_t *)(ctx->ws + L.start);
+  ctx->cursor = (int32_t *)(ctx->ws + L.cursor);
+  ctx->scan_tmp = (int32_t *)(ctx->ws + L.scan);
+  ctx->order = (int32_t *)(ctx->ws + L.order);
+  ctx->tmp = (double *)(ctx->ws + L.tmp);
+  ctx->list = (int32_t *)(ctx->ws + L.list);
+  ctx->list_cnt = (int32_t *)(ctx->ws + L.cnt);
+  ctx->rec = (double *)(ctx->ws + L.rec);
+  ctx->red = (double *)(ctx->ws + L.red);
+  ctx->counters = (int64_t *)(ctx->ws + L.counters);
+  ctx->scalars = (double *)(ctx->ws + L.scalars);
+  ctx->ncodes_max = L.ncodes_max;
+  ctx->scan_tmp_len = L.scan_len;
+  ctx->margin_boost = 1.0;
+  for (int k = 0; k < 2 * 1024; ++k) {
+    if (hipEventCreate(&ctx->ev_pool[k]) != hipSuccess) {
+      for (int q = 0; q < k; ++q) hipEventDestroy(ctx->ev_pool[q]);
+      free(ctx);
+      return MFM_E_HIP;
+    }
+  }
+  hipError_t e = hipMemsetAsync(ctx->counters, 0, sizeof(int64_t) * NCOUNTERS, ctx->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
+  if (e != hipSuccess) {
+    for (int q = 0; q < 2 * 1024; ++q) hipEventDestroy(ctx->ev_pool[q]);
+    free(ctx);
+    return MFM_E_HIP;
+  }
+  *out = ctx;
+  return MFM_OK;
+}
+
+int mfm_destroy(mfm_ctx *ctx) {
+  if (!ctx) return MFM_E_ARG;
+  hipStreamSynchronize(ctx->stream);
+  for (int q = 0; q < 2 * 1024; ++q) hipEventDestroy(ctx->ev_pool[q]);
+  free(ctx);
+  return MFM_OK;
+}
+
+int mfm_build_cells(mfm_ctx *ctx, const mfm_particles *pp, int64_t *perm) {
+  if (!ctx) return MFM_E_ARG;
+  if (!check_parts(ctx, pp)) return fail(ctx, MFM_E_ARG, "invalid particle set");
+  stage_begin(ctx, 0);
+  HIPCHK(ctx, launch_max_h(ctx, pp), "max H");
+  double hmax = 0.0;
+  HIPCHK(ctx, hipMemcpyAsync(&hmax, ctx->scalars, sizeof(double), hipMemcpyDeviceToHost,
+                             ctx->stream),
+         "read max H");
+  HIPCHK(ctx, hipStreamSynchronize(ctx->stream), "synchronise");
+  int rc = setup_grid(ctx, hmax);
+  if (rc) return rc;
+  HIPCHK(ctx, launch_build_cells(ctx, pp, perm), "cells");
+  stage_end(ctx, 0);
+  ctx->have_cells = 1;
+  ctx->have_density = 0;
+  ctx->have_grad = 0;
+  ctx->n_cells_built = pp->n;
+  return MFM_OK;
+}
+
+int mfm_density(mfm_ctx *ctx, const mfm_particles *pp) {
+  if (!ctx) return MFM_E_ARG;
+  if (!check_parts(ctx, pp)) return fail(ctx, MFM_E_ARG, "invalid particle set");
+  if (!ctx->have_cells || ctx->n_cells_built != pp->n)
+    return fail(ctx, MFM_E_STATE, "mfm_density needs mfm_build_cells first");
+  stage_begin(ctx, 1);
+  HIPCHK(ctx, launch_density(ctx, pp), "density");
+  stage_end(ctx, 1);
+  stage_begin(ctx, 2);
+  HIPCHK(ctx, launch_build_lists(ctx, pp), "lists");
+  stage_end(ctx, 2);
+  int64_t c[NCOUNTERS];
+  int rc = read_counters(ctx, c);
+  if (rc) return rc;
+  if (c[C_CELL_OVERFLOW] > 0) {
+    // some H reached the cell side: the next build uses larger cells
+    int64_t zero = 0;
+    HIPCHK(ctx, hipMemcpyAsync(ctx->counters + C_CELL_OVERFLOW, &zero, sizeof(zero),
+                               hipMemcpyHostToDevice, ctx->stream),
+           "reset overflow");
+    int64_t one = c[C_CELL_REBUILDS] + 1;
+    HIPCHK(ctx, hipMemcpyAsync(ctx->counters + C_CELL_REBUILDS, &one, sizeof(one),
+                               hipMemcpyHostToDevice, ctx->stream),
+           "count rebuild");
+    HIPCHK(ctx, hipStreamSynchronize(ctx->stream), "synchronise");
+    ctx->margin_boost *= 1.3;
+    ctx->have_cells = 0;
+    return fail(ctx, MFM_E_CELLS, "smoothing lengths outgrew the cell grid; rebuild cells");
+  }
+  if (c[C_LIST_OVERFLOW] > 0)
+    return fail(ctx, MFM_E_LIST, "neighbour list capacity exceeded (raise max_list)");
+  ctx->have_density = 1;
+  ctx->have_grad = 0;
+  return MFM_OK;
+}
+
+int mfm_gradients(mfm_ctx *ctx, const mfm_particles *pp, double dt_max, double *dt_dev) {
+  if (!ctx) return MFM_E_ARG;
+  if (!check_parts(ctx, pp) || !dt_dev || !(dt_max > 0.0))
+    return fail(ctx, MFM_E_ARG, "invalid arguments");
+  if (!ctx->have_density || ctx->n_cells_built != pp->n)
+    return fail(ctx, MFM_E_STATE, "mfm_gradients needs mfm_density first");
+  stage_begin(ctx, 3);
+  HIPCHK(ctx, launch_gradients(ctx, pp, dt_max, dt_dev), "gradients");
+  stage_end(ctx, 3);
+  ctx->have_grad = 1;
+  return MFM_OK;
+}
+
+int mfm_fluxes(mfm_ctx *ctx, const mfm_particles *pp, const double *dt_dev) {
+  if (!ctx) return MFM_E_ARG;
+  if (!check_parts(ctx, pp) || !dt_dev) return fail(ctx, MFM_E_ARG, "invalid arguments");
+  if (!ctx->have_grad || ctx->n_cells_built != pp->n)
+    return fail(ctx, MFM_E_STATE, "mfm_fluxes needs mfm_gradients first");
+  stage_begin(ctx, 4);
+  HIPCHK(ctx, launch_fluxes(ctx, pp, dt_dev), "fluxes");
+  stage_end(ctx, 4);
+  return MFM_OK;
+}
+
+int mfm_update(mfm_ctx *ctx, const mfm_particles *pp, const double *dt_dev) {
+  if (!ctx) return MFM_E_ARG;
+  if (!check_parts(ctx, pp) || !dt_dev) return fail(ctx, MFM_E_ARG, "invalid arguments");
+  stage_begin(ctx, 5);
+  HIPCHK(ctx, launch_update(ctx, pp, dt_dev), "update");
+  stage_end(ctx, 5);
+  ctx->have_cells = 0;
+  ctx->have_density = 0;
+  ctx->have_grad = 0;
+  return MFM_OK;
+}
+
+int mfm_step(mfm_ctx *ctx, const mfm_particles *pp, double dt_max, double *dt_host) {
+  if (!ctx) return MFM_E_ARG;
+  if (!dt_host) return fail(ctx, MFM_E_ARG, "dt_host is NULL");
+  int rc = MFM_E_CELLS;
+  for (int attempt = 0; attempt < 4 && rc == MFM_E_CELLS; ++attempt) {
+    rc = mfm_build_cells(ctx, pp, nullptr);
+    if (rc) return rc;
+    rc = mfm_density(ctx, pp);
+  }
+  if (rc) return rc;
+  double *dt_dev = ctx->scalars + 1;
+  rc = mfm_gradients(ctx, pp, dt_max, dt_dev);
+  if (rc) return rc;
+  rc = mfm_fluxes(ctx, pp, dt_dev);
+  if (rc) return rc;
+  rc = mfm_update(ctx, pp, dt_dev);
+  if (rc) return rc;
+  HIPCHK(ctx, hipMemcpyAsync(dt_host, dt_dev, sizeof(double), hipMemcpyDeviceToHost,
+                             ctx->stream),
+         "read dt");
+  int64_t c[NCOUNTERS];
+  rc = read_counters(ctx, c);
+  if (rc) return rc;
+  if (c[C_NONFINITE] > 0) return fail(ctx, MFM_E_NONFINITE, "non-finite step or state");
+  if (c[C_H_NOCONV] > 0) return fail(ctx, MFM_E_H_NOCONV, "smoothing-length solve did not converge");
+  return MFM_OK;
+}
+
+int mfm_diagnostics(mfm_ctx *ctx, const mfm_particles *pp, mfm_diag *out) {
+  if (!ctx || !out) return MFM_E_ARG;
+  memset(out, 0, sizeof(*out));
+  if (pp) {
+    if (!check_parts(ctx, pp)) return fail(ctx, MFM_E_ARG, "invalid particle set");
+    HIPCHK(ctx, launch_conserved(ctx, pp), "conserved sums");
+  }
+  double sums[5] = {0, 0, 0, 0, 0};
+  HIPCHK(ctx, hipMemcpyAsync(sums, ctx->scalars + 2, sizeof(sums), hipMemcpyDeviceToHost,
+                             ctx->stream),
+         "read sums");
+  int64_t c[NCOUNTERS];
+  int rc = read_counters(ctx, c);
+  if (rc) return rc;
+  int64_t *dst = &out->h_noconv;
+  for (int k = 0; k <= C_FP64_INVERSE; ++k) dst[k] = c[k];
+  if (pp) {
+    out->mass = sums[0];
+    out->px = sums[1];
+    out->py = sums[2];
+    out->pz = sums[3];
+    out->energy = sums[4];
+  }
+  return MFM_OK;
+}
+
+int mfm_reset_counters(mfm_ctx *ctx) {
+  if (!ctx) return MFM_E_ARG;
+  HIPCHK(ctx, hipMemsetAsync(ctx->counters, 0, sizeof(int64_t) * NCOUNTERS, ctx->stream),
+         "reset counters");
+  HIPCHK(ctx, hipStreamSynchronize(ctx->stream), "synchronise");
+  return MFM_OK;
+}
+
+int mfm_enable_timing(mfm_ctx *ctx, int on) {
+  if (!ctx) return MFM_E_ARG;
+  HIPCHK(ctx, hipStreamSynchronize(ctx->stream), "synchronise");
+  harvest_events(ctx);
+  ctx->timing = on ? 1 : 0;
+  for (int s = 0; s < MFM_NSTAGES; ++s) {
+    ctx->stage_ms[s] = 0.0;
+    ctx->stage_count[s] = 0;
+  }
+  return MFM_OK;
+}
+
+int mfm_kernel_times(mfm_ctx *ctx, double *ms_out, int64_t *count_out) {
+  if (!ctx || !ms_out) return MFM_E_ARG;
+  HIPCHK(ctx, hipStreamSynchronize(ctx->stream), "synchronise");
+  harvest_events(ctx);
+  for (int s = 0; s < MFM_NSTAGES; ++s) {
+    ms_out[s] = ctx->stage_ms[s];
+    if (count_out) count_out[s] = ctx->stage_count[s];
+  }
+  return MFM_OK;
+}
+
+const char *mfm_strerror(int status) {
+  switch (status) {
+    case MFM_OK: return "ok";
+    case MFM_E_ARG: return "invalid argument";
+    case MFM_E_WORKSPACE: return "workspace missing, misaligned or too small";
+    case MFM_E_HIP: return "HIP runtime error";
+    case MFM_E_H_NOCONV: return "smoothing-length solve did not converge";
+    case MFM_E_CELLS: return "smoothing lengths outgrew the cell grid";
+    case MFM_E_LIST: return "neighbour list capacity exceeded";
+    case MFM_E_NONFINITE: return "non-finite time step or state";
+    case MFM_E_STATE: return "call order violated";
+    default: return "unknown status";
+  }
+}
+
+const char *mfm_last_error(mfm_ctx *ctx) { return ctx ? ctx->err : "no context"; }
+
+}  // extern "C"

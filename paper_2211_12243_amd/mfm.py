@@ -1,0 +1,298 @@
+"""Python binding of libmfm (include/mfm.h): argument marshalling only.
+
+Every step of the hydro path runs in the HIP kernels of ``libmfm.so``.  This
+module loads that library with ctypes, mirrors its structs, and offers
+functions with the same names as the C entry points.  PyTorch supplies the
+device memory (tensors) and the stream.  If the library is not built, or no
+HIP device is visible, the calls raise; there is no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import torch
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libmfm.so")
+
+MFM_OK = 0
+MFM_SCHEME_MFV, MFM_SCHEME_MFM = 0, 1
+MFM_FP64, MFM_MIXED = 0, 1
+MFM_GUESS_PLAIN, MFM_GUESS_LEARNED = 0, 1
+MFM_LIMIT_BJ, MFM_LIMIT_PAIRWISE = 1, 2
+MFM_NSTAGES = 6
+STAGES = ("cells", "density", "lists", "gradients", "fluxes", "update")
+
+
+class mfm_params(ctypes.Structure):
+    _fields_ = [
+        ("scheme", ctypes.c_int32), ("precision", ctypes.c_int32), ("limiter", ctypes.c_int32),
+        ("max_boosts", ctypes.c_int32), ("h_maxit", ctypes.c_int32),
+        ("riemann_maxit", ctypes.c_int32), ("guess", ctypes.c_int32),
+        ("max_list", ctypes.c_int32),
+        ("gamma", ctypes.c_double), ("n_ngb", ctypes.c_double), ("ncond_max", ctypes.c_double),
+        ("ngb_boost", ctypes.c_double), ("h_tol", ctypes.c_double), ("c_cfl", ctypes.c_double),
+        ("psi1", ctypes.c_double), ("psi2", ctypes.c_double), ("riemann_tol", ctypes.c_double),
+        ("alpha1", ctypes.c_double), ("box", ctypes.c_double * 3),
+        ("cell_margin", ctypes.c_double), ("max_cell_dim", ctypes.c_int32),
+        ("pad0", ctypes.c_int32),
+    ]
+
+
+_PTR = ctypes.c_void_p
+_STATE = ("x", "y", "z", "vx", "vy", "vz", "m", "E", "U", "H")
+_DERIVED = ("V", "rho", "P", "c", "ncond")
+
+
+class mfm_particles(ctypes.Structure):
+    _fields_ = ([("n", ctypes.c_int64)] + [(k, _PTR) for k in _STATE + _DERIVED]
+                + [(k, _PTR) for k in ("B", "grad", "dQ", "dt_i", "id")])
+
+
+_DIAG_INT = ("h_noconv", "ncond_boosts", "ncond_fail", "cell_rebuilds", "list_overflow",
+             "grad_pairs", "faces", "riemann_iters", "riemann_maxit", "vacuum", "positivity",
+             "neg_mass", "singular_e", "guess_fallback", "fp64_inverse")
+
+
+class mfm_diag(ctypes.Structure):
+    _fields_ = ([(k, ctypes.c_int64) for k in _DIAG_INT] + [("pad", ctypes.c_int64 * 3)]
+                + [(k, ctypes.c_double) for k in ("mass", "px", "py", "pz", "energy")])
+
+    def as_dict(self):
+        d = {k: int(getattr(self, k)) for k in _DIAG_INT}
+        d.update({k: float(getattr(self, k)) for k in ("mass", "px", "py", "pz", "energy")})
+        return d
+
+
+class MFMError(RuntimeError):
+    pass
+
+
+_lib = None
+
+
+def lib():
+    """Load libmfm.so (raises if it is missing: nothing falls back to the CPU)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise MFMError(f"{LIB_PATH} is not built; run __graft_entry__.build()")
+        L = ctypes.CDLL(LIB_PATH)
+        P, PP, C = ctypes.POINTER(mfm_params), ctypes.POINTER(mfm_particles), _PTR
+        L.mfm_default_params.argtypes = [P]
+        L.mfm_default_params.restype = None
+        L.mfm_workspace_bytes.argtypes = [P, ctypes.c_int64]
+        L.mfm_workspace_bytes.restype = ctypes.c_size_t
+        L.mfm_create.argtypes = [P, ctypes.c_int64, _PTR, ctypes.c_size_t, _PTR,
+                                 ctypes.POINTER(_PTR)]
+        L.mfm_destroy.argtypes = [C]
+        L.mfm_build_cells.argtypes = [C, PP, _PTR]
+        L.mfm_density.argtypes = [C, PP]
+        L.mfm_gradients.argtypes = [C, PP, ctypes.c_double, _PTR]
+        L.mfm_fluxes.argtypes = [C, PP, _PTR]
+        L.mfm_update.argtypes = [C, PP, _PTR]
+        L.mfm_step.argtypes = [C, PP, ctypes.c_double, ctypes.POINTER(ctypes.c_double)]
+        L.mfm_diagnostics.argtypes = [C, PP, ctypes.POINTER(mfm_diag)]
+        L.mfm_reset_counters.argtypes = [C]
+        L.mfm_enable_timing.argtypes = [C, ctypes.c_int]
+        L.mfm_kernel_times.argtypes = [C, ctypes.POINTER(ctypes.c_double),
+                                       ctypes.POINTER(ctypes.c_int64)]
+        for f in ("mfm_create", "mfm_destroy", "mfm_build_cells", "mfm_density", "mfm_gradients",
+                  "mfm_fluxes", "mfm_update", "mfm_step", "mfm_diagnostics",
+                  "mfm_reset_counters", "mfm_enable_timing", "mfm_kernel_times"):
+            getattr(L, f).restype = ctypes.c_int
+        L.mfm_strerror.argtypes = [ctypes.c_int]
+        L.mfm_strerror.restype = ctypes.c_char_p
+        L.mfm_last_error.argtypes = [C]
+        L.mfm_last_error.restype = ctypes.c_char_p
+        _lib = L
+    return _lib
+
+
+EXPORTED = ("mfm_default_params", "mfm_workspace_bytes", "mfm_create", "mfm_destroy",
+            "mfm_build_cells", "mfm_density", "mfm_gradients", "mfm_fluxes", "mfm_update",
+            "mfm_step", "mfm_diagnostics", "mfm_reset_counters", "mfm_enable_timing",
+            "mfm_kernel_times", "mfm_strerror", "mfm_last_error")
+
+
+def mfm_default_params(**over) -> mfm_params:
+    p = mfm_params()
+    lib().mfm_default_params(ctypes.byref(p))
+    for k, v in over.items():
+        if k == "box":
+            for a in range(3):
+                p.box[a] = float(v[a])
+        elif k == "scheme" and isinstance(v, str):
+            p.scheme = MFM_SCHEME_MFM if v == "mfm" else MFM_SCHEME_MFV
+        elif k == "precision" and isinstance(v, str):
+            p.precision = MFM_MIXED if v == "mixed" else MFM_FP64
+        else:
+            setattr(p, k, v)
+    return p
+
+
+def params_from_dict(cfg: dict, **over) -> mfm_params:
+    """The library's parameter struct from the plain dict the tests share."""
+    keys = ("scheme", "limiter", "max_boosts", "h_maxit", "riemann_maxit", "gamma", "n_ngb",
+            "ncond_max", "ngb_boost", "h_tol", "c_cfl", "psi1", "psi2", "riemann_tol", "alpha1",
+            "box", "precision", "max_list", "cell_margin", "max_cell_dim", "guess")
+    d = {k: cfg[k] for k in keys if k in cfg}
+    d.update(over)
+    return mfm_default_params(**d)
+
+
+def _check(rc, ctx=None):
+    if rc != MFM_OK:
+        msg = lib().mfm_strerror(rc).decode()
+        if ctx is not None:
+            msg += ": " + (lib().mfm_last_error(ctx).decode() or "")
+        raise MFMError(f"libmfm status {rc}: {msg}")
+    return rc
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else None
+
+
+class ParticleSet:
+    """Device arrays of one particle set (torch tensors) and their C struct."""
+
+    def __init__(self, state: dict, device="cuda", ids: bool = True):
+        n = int(len(state["x"]))
+        self.n = n
+        f64 = dict(dtype=torch.float64, device=device)
+        self.t = {k: torch.as_tensor(state[k], **f64).contiguous().clone() for k in _STATE}
+        for k in _DERIVED + ("dt_i",):
+            self.t[k] = torch.zeros(n, **f64)
+        self.t["B"] = torch.zeros(6, n, **f64)
+        self.t["grad"] = torch.zeros(15, n, **f64)
+        self.t["dQ"] = torch.zeros(5, n, **f64)
+        self.t["id"] = (torch.arange(n, dtype=torch.int64, device=device) if ids else None)
+        self.s = mfm_particles()
+        self.s.n = n
+        for k in _STATE + _DERIVED + ("B", "grad", "dQ", "dt_i", "id"):
+            t = self.t[k]
+            setattr(self.s, k, t.data_ptr() if t is not None else None)
+
+    def __getitem__(self, k):
+        return self.t[k]
+
+    def host(self, keys=None) -> dict:
+        keys = keys or [k for k in self.t if self.t[k] is not None]
+        return {k: self.t[k].detach().cpu().numpy() for k in keys}
+
+
+class Context:
+    """A libmfm context with its workspace tensor, bound to one stream."""
+
+    def __init__(self, params: mfm_params, n_max: int, stream=None, device="cuda"):
+        L = lib()
+        self.params = params
+        self.n_max = int(n_max)
+        nbytes = L.mfm_workspace_bytes(ctypes.byref(params), self.n_max)
+        if nbytes == 0:
+            raise MFMError("invalid parameters (mfm_workspace_bytes returned 0)")
+        self.ws = torch.empty(nbytes + 256, dtype=torch.uint8, device=device)
+        base = self.ws.data_ptr()
+        self.ws_ptr = (base + 255) // 256 * 256
+        self.stream = stream if stream is not None else torch.cuda.current_stream(device)
+        self.h = ctypes.c_void_p()
+        _check(L.mfm_create(ctypes.byref(params), self.n_max, ctypes.c_void_p(self.ws_ptr),
+                            nbytes, ctypes.c_void_p(self.stream.cuda_stream),
+                            ctypes.byref(self.h)))
+        self.dt_dev = torch.zeros(1, dtype=torch.float64, device=device)
+
+    def close(self):
+        if self.h:
+            lib().mfm_destroy(self.h)
+            self.h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+# --- entry points with the C names --------------------------------------------------------
+
+def mfm_create(params: mfm_params, n_max: int, stream=None) -> Context:
+    return Context(params, n_max, stream)
+
+
+def mfm_destroy(ctx: Context):
+    ctx.close()
+
+
+def mfm_build_cells(ctx: Context, ps: ParticleSet, perm=None):
+    _check(lib().mfm_build_cells(ctx.h, ctypes.byref(ps.s), _ptr(perm)), ctx.h)
+
+
+def mfm_density(ctx: Context, ps: ParticleSet):
+    _check(lib().mfm_density(ctx.h, ctypes.byref(ps.s)), ctx.h)
+
+
+def mfm_gradients(ctx: Context, ps: ParticleSet, dt_max: float, dt_dev=None):
+    dt_dev = ctx.dt_dev if dt_dev is None else dt_dev
+    _check(lib().mfm_gradients(ctx.h, ctypes.byref(ps.s), float(dt_max), _ptr(dt_dev)), ctx.h)
+    return dt_dev
+
+
+def mfm_fluxes(ctx: Context, ps: ParticleSet, dt_dev=None):
+    dt_dev = ctx.dt_dev if dt_dev is None else dt_dev
+    _check(lib().mfm_fluxes(ctx.h, ctypes.byref(ps.s), _ptr(dt_dev)), ctx.h)
+
+
+def mfm_update(ctx: Context, ps: ParticleSet, dt_dev=None):
+    dt_dev = ctx.dt_dev if dt_dev is None else dt_dev
+    _check(lib().mfm_update(ctx.h, ctypes.byref(ps.s), _ptr(dt_dev)), ctx.h)
+
+
+def mfm_step(ctx: Context, ps: ParticleSet, dt_max: float) -> float:
+    dt = ctypes.c_double()
+    _check(lib().mfm_step(ctx.h, ctypes.byref(ps.s), float(dt_max), ctypes.byref(dt)), ctx.h)
+    return dt.value
+
+
+def mfm_diagnostics(ctx: Context, ps: ParticleSet | None = None) -> dict:
+    d = mfm_diag()
+    _check(lib().mfm_diagnostics(ctx.h, ctypes.byref(ps.s) if ps is not None else None,
+                                 ctypes.byref(d)), ctx.h)
+    return d.as_dict()
+
+
+def mfm_reset_counters(ctx: Context):
+    _check(lib().mfm_reset_counters(ctx.h), ctx.h)
+
+
+def mfm_enable_timing(ctx: Context, on: bool = True):
+    _check(lib().mfm_enable_timing(ctx.h, int(bool(on))), ctx.h)
+
+
+def mfm_kernel_times(ctx: Context) -> dict:
+    ms = (ctypes.c_double * MFM_NSTAGES)()
+    cnt = (ctypes.c_int64 * MFM_NSTAGES)()
+    _check(lib().mfm_kernel_times(ctx.h, ms, cnt), ctx.h)
+    return {STAGES[s]: (ms[s], int(cnt[s])) for s in range(MFM_NSTAGES)}
+
+
+def run_pipeline(ctx: Context, ps: ParticleSet, dt_max: float, update: bool = True):
+    """All loops of one step through the C entry points; returns dt (host float)."""
+    mfm_build_cells(ctx, ps)
+    for _ in range(4):
+        try:
+            mfm_density(ctx, ps)
+            break
+        except MFMError as e:
+            if "status -5" not in str(e):
+                raise
+            mfm_build_cells(ctx, ps)
+    else:
+        raise MFMError("cell grid kept overflowing")
+    mfm_gradients(ctx, ps, dt_max)
+    mfm_fluxes(ctx, ps)
+    dt = float(ctx.dt_dev.item())
+    if update:
+        mfm_update(ctx, ps)
+    return dt
