@@ -302,17 +302,12 @@ static int solve_h(const double *r, int64_t nr, double nngb, double hi, double t
     else
       hi = h;
     double hn = (dg > 0.0) ? h - g / dg : NAN;
-    int newton = 1;
-    if (!(hn > lo && hn < hi)) {
-      hn = 0.5 * (lo + hi);
-      newton = 0;
-    }
-    int done = newton && fabs(hn - h) <= tol * hn;
-    h = hn;
-    if (done) {
-      *H = h;
+    if (fabs(hn - h) <= tol * hn) { /* a small Newton step: converged */
+      *H = hn;
       return it;
     }
+    if (!(hn > lo && hn < hi)) hn = 0.5 * (lo + hi);
+    h = hn;
   }
   *H = h;
   return -1;

@@ -107,19 +107,15 @@ __global__ void __launch_bounds__(BS) density_k(DensityArgs a, CellGrid g) {
         else
           hi = h;
         double hn = (dg > 0.0) ? h - gv / dg : -1.0;
-        bool newton = true;
-        if (!(hn > lo && hn < hi)) {
-          hn = 0.5 * (lo + hi);
-          newton = false;
-        }
-        // stop on a small Newton step only: its quadratic convergence leaves H
-        // at the root to roundoff
-        bool done = newton && fabs(hn - h) <= a.h_tol * hn;
-        h = hn;
-        if (done) {
+        // stop on a small Newton step only (never on a bisection step): its
+        // quadratic convergence leaves H at the root to roundoff
+        if (fabs(hn - h) <= a.h_tol * hn) {
+          h = hn;
           conv = true;
           break;
         }
+        if (!(hn > lo && hn < hi)) hn = 0.5 * (lo + hi);
+        h = hn;
       }
       if (!conv) ++noconv;
       // number density at the solution and the unweighted E~ of the check

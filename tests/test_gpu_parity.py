@@ -109,6 +109,7 @@ def check_fields(gpu, new, dt, diag, ref, tol, st):
     bad = {k: v for k, v in errs.items() if not (v <= tol)}
     assert not bad, bad
     # exact integer results
+    assert diag["h_noconv"] == 0 and ref["counters"]["h_noconv"] == 0
     assert diag["grad_pairs"] == ref["counters"]["grad_pairs"]
     assert diag["faces"] == ref["counters"]["faces"]
     return errs

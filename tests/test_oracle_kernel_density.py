@@ -115,10 +115,12 @@ def test_density_partition_of_unity_volume():
 
 
 def test_density_root_independent_of_start():
+    # the root of the monotone g(H) is unique, so every start value converges to it
     st = W.random_gas(N=1500, seed=3)
-    d1, _ = oracle.density({}, st["x"], st["y"], st["z"], st["H"])
-    d2, _ = oracle.density({}, st["x"], st["y"], st["z"], 0.6 * st["H"])
-    d3, _ = oracle.density({}, st["x"], st["y"], st["z"], 1.7 * st["H"])
+    d1, c1 = oracle.density({}, st["x"], st["y"], st["z"], st["H"])
+    d2, c2 = oracle.density({}, st["x"], st["y"], st["z"], 0.6 * st["H"])
+    d3, c3 = oracle.density({}, st["x"], st["y"], st["z"], 1.7 * st["H"])
+    assert c1["h_noconv"] == c2["h_noconv"] == c3["h_noconv"] == 0
     assert np.max(np.abs(d1["H"] / d2["H"] - 1)) < 1e-12
     assert np.max(np.abs(d1["H"] / d3["H"] - 1)) < 1e-12
 
@@ -149,3 +151,12 @@ def test_condition_number_boost_on_planar_particles():
     assert cnt["ncond_boosts"] > 0
     assert np.all(d["nngb"] >= 32.0)
     assert np.any(d["nngb"] > 32.0 * 1.19)
+
+
+def test_density_solve_converges_on_blast_set():
+    # a strongly varying energy field does not affect the H solve (positions only)
+    st = W.sedov(n=20, seed=7)
+    d, cnt = oracle.density({}, st["x"], st["y"], st["z"], st["H"])
+    assert cnt["h_noconv"] == 0
+    lhs = 4.0 * math.pi / 3.0 * d["H"] ** 3 / d["V"]
+    assert np.max(np.abs(lhs - 32.0)) < 1e-11
