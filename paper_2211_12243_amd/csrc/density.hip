@@ -161,9 +161,9 @@ __global__ void __launch_bounds__(BS) density_k(DensityArgs a, CellGrid g) {
     a.c[i] = sqrt(a.gamma * P / rho);
     a.ncond[i] = nc;
   }
-  count_add(a.counters + C_H_NOCONV, noconv);
-  count_add(a.counters + C_NCOND_BOOSTS, boosts);
-  count_add(a.counters + C_NCOND_FAIL, fails);
+  count_add(a.counters + C_PASS_NOCONV, noconv);
+  count_add(a.counters + C_PASS_BOOSTS, boosts);
+  count_add(a.counters + C_PASS_FAIL, fails);
   count_add(a.counters + C_CELL_OVERFLOW, overflow);
 }
 

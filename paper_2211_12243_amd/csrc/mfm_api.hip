@@ -283,6 +283,10 @@ int mfm_density(mfm_ctx *ctx, const mfm_particles *pp) {
   if (!check_parts(ctx, pp)) return fail(ctx, MFM_E_ARG, "invalid particle set");
   if (!ctx->have_cells || ctx->n_cells_built != pp->n)
     return fail(ctx, MFM_E_STATE, "mfm_density needs mfm_build_cells first");
+  HIPCHK(ctx, hipMemsetAsync(ctx->counters + C_CELL_OVERFLOW, 0, sizeof(int64_t),
+                             ctx->stream), "clear pass counters");
+  HIPCHK(ctx, hipMemsetAsync(ctx->counters + C_PASS_NOCONV, 0, 3 * sizeof(int64_t),
+                             ctx->stream), "clear pass counters");
   stage_begin(ctx, 1);
   HIPCHK(ctx, launch_density(ctx, pp), "density");
   stage_end(ctx, 1);
@@ -293,20 +297,25 @@ int mfm_density(mfm_ctx *ctx, const mfm_particles *pp) {
   int rc = read_counters(ctx, c);
   if (rc) return rc;
   if (c[C_CELL_OVERFLOW] > 0) {
-    // some H reached the cell side: the next build uses larger cells
-    int64_t zero = 0;
-    HIPCHK(ctx, hipMemcpyAsync(ctx->counters + C_CELL_OVERFLOW, &zero, sizeof(zero),
-                               hipMemcpyHostToDevice, ctx->stream),
-           "reset overflow");
-    int64_t one = c[C_CELL_REBUILDS] + 1;
-    HIPCHK(ctx, hipMemcpyAsync(ctx->counters + C_CELL_REBUILDS, &one, sizeof(one),
-                               hipMemcpyHostToDevice, ctx->stream),
+    // some H reached the cell side: this pass is discarded (its counts too)
+    // and the next build uses larger cells
+    c[C_CELL_REBUILDS] += 1;
+    HIPCHK(ctx, hipMemcpyAsync(ctx->counters + C_CELL_REBUILDS, c + C_CELL_REBUILDS,
+                               sizeof(int64_t), hipMemcpyHostToDevice, ctx->stream),
            "count rebuild");
     HIPCHK(ctx, hipStreamSynchronize(ctx->stream), "synchronise");
     ctx->margin_boost *= 1.3;
     ctx->have_cells = 0;
     return fail(ctx, MFM_E_CELLS, "smoothing lengths outgrew the cell grid; rebuild cells");
   }
+  // accept the pass: fold its counts into the running counters
+  c[C_H_NOCONV] += c[C_PASS_NOCONV];
+  c[C_NCOND_BOOSTS] += c[C_PASS_BOOSTS];
+  c[C_NCOND_FAIL] += c[C_PASS_FAIL];
+  HIPCHK(ctx, hipMemcpyAsync(ctx->counters, c, 3 * sizeof(int64_t), hipMemcpyHostToDevice,
+                             ctx->stream),
+         "fold pass counters");
+  HIPCHK(ctx, hipStreamSynchronize(ctx->stream), "synchronise");
   if (c[C_LIST_OVERFLOW] > 0)
     return fail(ctx, MFM_E_LIST, "neighbour list capacity exceeded (raise max_list)");
   ctx->have_density = 1;

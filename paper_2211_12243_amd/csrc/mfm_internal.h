@@ -29,6 +29,11 @@ enum {
   C_FP64_INVERSE,
   C_CELL_OVERFLOW,  // internal: some H reached the cell side in the last density pass
   C_NONFINITE,      // internal: non-finite dt or state
+  // counts of the density pass in flight; folded into the slots above only
+  // when the pass is accepted (a pass whose H outgrew the cells is redone)
+  C_PASS_NOCONV,
+  C_PASS_BOOSTS,
+  C_PASS_FAIL,
   NCOUNTERS = 24
 };
 
