@@ -72,7 +72,7 @@ typedef struct mfm_params {
   int32_t h_maxit;       /* smoothing-length iteration cap (default 64) */
   int32_t riemann_maxit; /* Riemann Newton cap (default 100) */
   int32_t guess;         /* MFM_GUESS_PLAIN or MFM_GUESS_LEARNED */
-  int32_t max_list;      /* neighbour list capacity per particle (default 128) */
+  int32_t max_list;      /* candidate list capacity per particle (default 128) */
   double gamma;          /* adiabatic index (> 1) */
   double n_ngb;          /* neighbour number N_NGB (> 32/3, non-integer allowed) */
   double ncond_max;      /* condition-number threshold (default 100) */
@@ -198,8 +198,9 @@ int mfm_reset_counters(struct mfm_ctx *ctx);
 
 /* Kernel timing on the context's stream with HIP events.  While enabled every
  * launch of the loops is bracketed by events; mfm_kernel_times (synchronises)
- * returns, per stage (0 cells, 1 density, 2 lists, 3 gradients, 4 fluxes,
- * 5 update), the summed milliseconds and launch counts since enabling. */
+ * returns, per stage (0 cells, 1 neighbour search, 2 density, 3 gradients,
+ * 4 fluxes, 5 update), the summed milliseconds and launch counts since
+ * enabling. */
 #define MFM_NSTAGES 6
 int mfm_enable_timing(struct mfm_ctx *ctx, int on);
 int mfm_kernel_times(struct mfm_ctx *ctx, double *ms_out, int64_t *count_out);

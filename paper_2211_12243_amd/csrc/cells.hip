@@ -134,6 +134,12 @@ __global__ void cell_sort_k(int64_t ncodes, const int32_t *__restrict__ start,
   }
 }
 
+__global__ void range_k(int64_t ncodes, const int32_t *__restrict__ start,
+                        const int32_t *__restrict__ count, int2 *range) {
+  int64_t c = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (c < ncodes) range[c] = make_int2(start[c], count[c]);
+}
+
 struct Fields {
   double *f[10];
   int64_t *id;
@@ -150,12 +156,14 @@ __global__ void gather_k(int64_t n, Fields fs, const int32_t *__restrict__ order
   if (perm) perm[k] = o;
 }
 
-__global__ void writeback_k(int64_t n, Fields fs, const double *__restrict__ tmp) {
+__global__ void writeback_k(int64_t n, Fields fs, const double *__restrict__ tmp,
+                            double4 *pos4) {
   int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (k >= n) return;
 #pragma unroll
   for (int f = 0; f < 10; ++f) fs.f[f][k] = tmp[f * n + k];
   if (fs.id) fs.id[k] = ((const int64_t *)(tmp + 10 * n))[k];
+  pos4[k] = make_double4(tmp[k], tmp[n + k], tmp[2 * n + k], 0.0);
 }
 
 }  // namespace
@@ -183,11 +191,14 @@ hipError_t launch_build_cells(mfm_ctx *ctx, const mfm_particles *pp, int64_t *pe
   scatter_k<<<blocks_for(n, BS), BS, 0, st>>>(n, ctx->code, ctx->cursor, ctx->order);
   cell_sort_k<<<blocks_for(ctx->ncodes, BS), BS, 0, st>>>(ctx->ncodes, ctx->cell_start,
                                                            ctx->cell_count, ctx->order);
+  range_k<<<blocks_for(ctx->ncodes, BS), BS, 0, st>>>(ctx->ncodes, ctx->cell_start,
+                                                       ctx->cell_count, ctx->crange);
   Fields fs;
   double *src[10] = {pp->x, pp->y, pp->z, pp->vx, pp->vy, pp->vz, pp->m, pp->E, pp->U, pp->H};
   for (int f = 0; f < 10; ++f) fs.f[f] = src[f];
   fs.id = pp->id;
   gather_k<<<blocks_for(n, BS), BS, 0, st>>>(n, fs, ctx->order, ctx->tmp, perm);
-  writeback_k<<<blocks_for(n, BS), BS, 0, st>>>(n, fs, ctx->tmp);
+  writeback_k<<<blocks_for(n, BS), BS, 0, st>>>(n, fs, ctx->tmp,
+                                                reinterpret_cast<double4 *>(ctx->pos4));
   return hipGetLastError();
 }

@@ -1,14 +1,21 @@
 // density.hip -- loop (1) of the scheme: smoothing length and number density
-// (sec. 2.3.2 and 2.3.5), and the neighbour lists the next two loops read.
+// (sec. 2.3.2 and 2.3.5), plus the one neighbour search of the step.
 //
-// One lane per particle.  The lanes of a wavefront are 64 consecutive
-// particles of the Z-ordered cell list, so their 27-cell stencils overlap and
-// the candidate reads are served from L1/L2.  Each lane solves
+// cand_k: one lane per particle scans the 27 cells around its own (cell side
+// >= cell_margin * max H, so every pair closer than the side is found) and
+// keeps the candidates with r < side as (index, r^2) in a tiled list (see
+// list_at: each lane fills whole cache lines of its own entries).  The list is a superset of every neighbour set the step uses:
+// the gradient loop filters r < H_i and the flux loop r < max(H_i, H_j).
+//
+// density_k: each lane solves
 //   g(H) = (32/3) sum_j w(r_ij / H) - N_NGB = 0
 // ((4 pi / 3) H^3 omega^-1 = N_NGB with omega^-1 = sum_j W(r_ij, H)) by Newton
-// steps kept inside a bisection bracket whose upper end is the smallest cell
-// side (beyond it the stencil would miss neighbours; reaching it is flagged
-// and the host rebuilds the grid).  The solve ends on a small Newton step.
+// steps kept inside a bisection bracket (0, side); each evaluation streams only
+// the lane's own r^2 list.  The solve ends on a small Newton step, so H is the
+// root to roundoff.  Reaching the side is flagged and the host rebuilds the
+// grid with larger cells.  Then the number density, the unweighted E~ of the
+// condition-number check (with N_NGB boosts), the primitives and the packed
+// 128-byte record the gradient loop gathers.
 #include "mfm_internal.h"
 
 namespace {
@@ -16,31 +23,84 @@ namespace {
 constexpr int BS = 256;
 constexpr double PI = 3.14159265358979323846;
 
-// Visit every particle in the 27 cells around (cx, cy, cz).
-template <typename F>
-__device__ __forceinline__ void for_stencil(const CellGrid &g, int cx, int cy, int cz, F &&f) {
-  for (int dz = -1; dz <= 1; ++dz) {
-    int zz = cz + dz;
-    zz = zz < 0 ? zz + g.nc[2] : (zz >= g.nc[2] ? zz - g.nc[2] : zz);
-    for (int dy = -1; dy <= 1; ++dy) {
-      int yy = cy + dy;
-      yy = yy < 0 ? yy + g.nc[1] : (yy >= g.nc[1] ? yy - g.nc[1] : yy);
-      for (int dx = -1; dx <= 1; ++dx) {
-        int xx = cx + dx;
-        xx = xx < 0 ? xx + g.nc[0] : (xx >= g.nc[0] ? xx - g.nc[0] : xx);
-        uint32_t code = morton3(xx, yy, zz);
-        int s = g.start[code];
-        int e = s + g.count[code];
-        for (int j = s; j < e; ++j) f(j);
+struct CandArgs {
+  int64_t n;
+  const double4 *pos;
+  int max_list;
+  int32_t *cand;
+  double *cand_r2;
+  int32_t *cand_cnt;
+  int64_t *counters;
+};
+
+__global__ void __launch_bounds__(BS) cand_k(CandArgs a, CellGrid g) {
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  const int64_t n = a.n;
+  int64_t overflow = 0;
+  if (i < n) {
+    const double4 pi = a.pos[i];
+    const int cx = cell_coord(pi.x, g.inv[0], g.nc[0]);
+    const int cy = cell_coord(pi.y, g.inv[1], g.nc[1]);
+    const int cz = cell_coord(pi.z, g.inv[2], g.nc[2]);
+    const double R2 = g.side_min * g.side_min;
+    // position inside the own cell in cell units; a neighbour cell whose
+    // nearest point is farther than the search radius is skipped (the test is
+    // in FP32 with a margin, so it only ever skips cells that hold no candidate)
+    const float fx = (float)(pi.x * g.inv[0] - cx), fy = (float)(pi.y * g.inv[1] - cy),
+                fz = (float)(pi.z * g.inv[2] - cz);
+    const float sx = (float)(1.0 / g.inv[0]), sy = (float)(1.0 / g.inv[1]),
+                sz = (float)(1.0 / g.inv[2]);
+    const float lim = (float)R2 * 1.0001f;
+    int k = 0;
+    for (int dz = -1; dz <= 1; ++dz) {
+      const float gz = sz * fmaxf(dz > 0 ? 1.0f - fz : (dz < 0 ? fz : 0.0f), 0.0f);
+      int zz = cz + dz;
+      zz = zz < 0 ? zz + g.nc[2] : (zz >= g.nc[2] ? zz - g.nc[2] : zz);
+      for (int dy = -1; dy <= 1; ++dy) {
+        const float gy = sy * fmaxf(dy > 0 ? 1.0f - fy : (dy < 0 ? fy : 0.0f), 0.0f);
+        int yy = cy + dy;
+        yy = yy < 0 ? yy + g.nc[1] : (yy >= g.nc[1] ? yy - g.nc[1] : yy);
+        for (int dx = -1; dx <= 1; ++dx) {
+          const float gx = sx * fmaxf(dx > 0 ? 1.0f - fx : (dx < 0 ? fx : 0.0f), 0.0f);
+          if (gx * gx + gy * gy + gz * gz > lim) continue;
+          int xx = cx + dx;
+          xx = xx < 0 ? xx + g.nc[0] : (xx >= g.nc[0] ? xx - g.nc[0] : xx);
+          const int2 rg = g.range[morton3(xx, yy, zz)];
+          for (int j = rg.x; j < rg.x + rg.y; ++j) {
+            const double4 pj = a.pos[j];
+            double ex = min_image(pj.x - pi.x, g.box[0], g.half[0]);
+            double ey = min_image(pj.y - pi.y, g.box[1], g.half[1]);
+            double ez = min_image(pj.z - pi.z, g.box[2], g.half[2]);
+            double r2 = ex * ex + ey * ey + ez * ez;
+            if (r2 < R2 && j != i) {
+              if (k < a.max_list) {
+                const int64_t at = list_at(i, k, n);
+                a.cand[at] = j;
+                a.cand_r2[at] = r2;
+              }
+              ++k;
+            }
+          }
+        }
       }
     }
+    if (k > a.max_list) {
+      overflow = 1;
+      k = a.max_list;
+    }
+    a.cand_cnt[i] = k;
   }
+  count_add(a.counters + C_LIST_OVERFLOW, overflow);
 }
 
 struct DensityArgs {
   int64_t n;
-  const double *x, *y, *z, *m, *U;
+  const double4 *pos;
+  const double *m, *U, *vx, *vy, *vz;
   double *H, *V, *rho, *P, *c, *ncond;
+  double *gin;  // GIN_STRIDE doubles per particle
+  const int32_t *cand, *cand_cnt;
+  const double *cand_r2;
   double gamma, n_ngb, ncond_max, ngb_boost, h_tol;
   int h_maxit, max_boosts;
   int64_t *counters;
@@ -67,13 +127,10 @@ __device__ double cond3(const double e[6]) {
 
 __global__ void __launch_bounds__(BS) density_k(DensityArgs a, CellGrid g) {
   const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  const bool active = i < a.n;
+  const int64_t n = a.n;
   int64_t noconv = 0, boosts = 0, fails = 0, overflow = 0;
-  if (active) {
-    const double xi = a.x[i], yi = a.y[i], zi = a.z[i];
-    const int cx = cell_coord(xi, g.inv[0], g.nc[0]);
-    const int cy = cell_coord(yi, g.inv[1], g.nc[1]);
-    const int cz = cell_coord(zi, g.inv[2], g.nc[2]);
+  if (i < n) {
+    const int cnt = a.cand_cnt[i];
     const double cover = g.side_min;
     double h = a.H[i];
     double target = a.n_ngb;
@@ -84,20 +141,17 @@ __global__ void __launch_bounds__(BS) density_k(DensityArgs a, CellGrid g) {
       bool conv = false;
       for (int it = 0; it < a.h_maxit; ++it) {
         const double h2 = h * h, ih = 1.0 / h;
-        double s = 0.0, ds = 0.0;
-        for_stencil(g, cx, cy, cz, [&](int j) {
-          double dx = min_image(a.x[j] - xi, g.box[0], g.half[0]);
-          double dy = min_image(a.y[j] - yi, g.box[1], g.half[1]);
-          double dz = min_image(a.z[j] - zi, g.box[2], g.half[2]);
-          double r2 = dx * dx + dy * dy + dz * dz;
+        double s = 1.0, ds = 0.0;  // the particle itself: w(0) = 1
+        for (int k = 0; k < cnt; ++k) {
+          const double r2 = a.cand_r2[list_at(i, k, n)];
           if (r2 < h2) {
-            double q = sqrt(r2) * ih;
+            const double q = sqrt(r2) * ih;
             s += spline_w(q);
             ds += spline_qdw(q);
           }
-        });
-        double gv = (32.0 / 3.0) * s - target;
-        double dg = -(32.0 / 3.0) * ds * ih;
+        }
+        const double gv = (32.0 / 3.0) * s - target;
+        const double dg = -(32.0 / 3.0) * ds * ih;
         if (gv == 0.0) {
           conv = true;
           break;
@@ -120,17 +174,19 @@ __global__ void __launch_bounds__(BS) density_k(DensityArgs a, CellGrid g) {
       if (!conv) ++noconv;
       // number density at the solution and the unweighted E~ of the check
       const double h2 = h * h, ih = 1.0 / h;
-      double ws = 0.0;
+      const double4 pi = a.pos[i];
+      double ws = 1.0;
       double e[6] = {0, 0, 0, 0, 0, 0};
-      for_stencil(g, cx, cy, cz, [&](int j) {
-        double dx = min_image(a.x[j] - xi, g.box[0], g.half[0]);
-        double dy = min_image(a.y[j] - yi, g.box[1], g.half[1]);
-        double dz = min_image(a.z[j] - zi, g.box[2], g.half[2]);
-        double r2 = dx * dx + dy * dy + dz * dz;
+      for (int k = 0; k < cnt; ++k) {
+        const double r2 = a.cand_r2[list_at(i, k, n)];
         if (r2 < h2) {
-          double w = spline_w(sqrt(r2) * ih);
+          const double w = spline_w(sqrt(r2) * ih);
           ws += w;
           if (r2 > 0.0) {
+            const double4 pj = a.pos[a.cand[list_at(i, k, n)]];
+            const double dx = min_image(pj.x - pi.x, g.box[0], g.half[0]);
+            const double dy = min_image(pj.y - pi.y, g.box[1], g.half[1]);
+            const double dz = min_image(pj.z - pi.z, g.box[2], g.half[2]);
             e[0] += w * dx * dx;
             e[1] += w * dx * dy;
             e[2] += w * dx * dz;
@@ -139,7 +195,7 @@ __global__ void __launch_bounds__(BS) density_k(DensityArgs a, CellGrid g) {
             e[5] += w * dz * dz;
           }
         }
-      });
+      }
       winv = 8.0 / (PI * h * h2) * ws;
       nc = cond3(e);  // the kernel's normalisation drops out of the condition number
       if (!(nc > a.ncond_max)) break;
@@ -154,12 +210,19 @@ __global__ void __launch_bounds__(BS) density_k(DensityArgs a, CellGrid g) {
     const double V = 1.0 / winv;
     const double rho = a.m[i] / V;
     const double P = (a.gamma - 1.0) * a.U[i] / V;
+    const double cs = sqrt(a.gamma * P / rho);
     a.H[i] = h;
     a.V[i] = V;
     a.rho[i] = rho;
     a.P[i] = P;
-    a.c[i] = sqrt(a.gamma * P / rho);
+    a.c[i] = cs;
     a.ncond[i] = nc;
+    const double4 pi = a.pos[i];
+    double4 *gr = reinterpret_cast<double4 *>(a.gin + i * GIN_STRIDE);
+    gr[0] = make_double4(pi.x, pi.y, pi.z, h);
+    gr[1] = make_double4(V, rho, a.vx[i], a.vy[i]);
+    gr[2] = make_double4(a.vz[i], P, cs, 0.0);
+    gr[3] = make_double4(0.0, 0.0, 0.0, 0.0);
   }
   count_add(a.counters + C_PASS_NOCONV, noconv);
   count_add(a.counters + C_PASS_BOOSTS, boosts);
@@ -167,49 +230,31 @@ __global__ void __launch_bounds__(BS) density_k(DensityArgs a, CellGrid g) {
   count_add(a.counters + C_CELL_OVERFLOW, overflow);
 }
 
-// Symmetric neighbour lists: j != i with r_ij < max(H_i, H_j).  The gradient
-// loop keeps the entries with r_ij < H_i, the flux loop uses them all.
-__global__ void __launch_bounds__(BS)
-    lists_k(int64_t n, const double *__restrict__ x, const double *__restrict__ y,
-            const double *__restrict__ z, const double *__restrict__ H, CellGrid g,
-            int max_list, int32_t *__restrict__ list, int32_t *__restrict__ cnt,
-            int64_t *counters) {
-  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  int64_t overflow = 0;
-  if (i < n) {
-    const double xi = x[i], yi = y[i], zi = z[i], hi = H[i];
-    const int cx = cell_coord(xi, g.inv[0], g.nc[0]);
-    const int cy = cell_coord(yi, g.inv[1], g.nc[1]);
-    const int cz = cell_coord(zi, g.inv[2], g.nc[2]);
-    int k = 0;
-    for_stencil(g, cx, cy, cz, [&](int j) {
-      if (j == i) return;
-      double dx = min_image(x[j] - xi, g.box[0], g.half[0]);
-      double dy = min_image(y[j] - yi, g.box[1], g.half[1]);
-      double dz = min_image(z[j] - zi, g.box[2], g.half[2]);
-      double r2 = dx * dx + dy * dy + dz * dz;
-      double hm = fmax(hi, H[j]);
-      if (r2 < hm * hm) {
-        if (k < max_list) list[(int64_t)k * n + i] = j;
-        ++k;
-      }
-    });
-    if (k > max_list) {
-      overflow = 1;
-      k = max_list;
-    }
-    cnt[i] = k;
-  }
-  count_add(counters + C_LIST_OVERFLOW, overflow);
-}
-
 }  // namespace
+
+hipError_t launch_candidates(mfm_ctx *ctx, const mfm_particles *pp) {
+  CandArgs a;
+  a.n = pp->n;
+  a.pos = reinterpret_cast<const double4 *>(ctx->pos4);
+  a.max_list = ctx->p.max_list;
+  a.cand = ctx->cand;
+  a.cand_r2 = ctx->cand_r2;
+  a.cand_cnt = ctx->cand_cnt;
+  a.counters = ctx->counters;
+  cand_k<<<blocks_for(pp->n, BS), BS, 0, ctx->stream>>>(a, ctx->grid);
+  return hipGetLastError();
+}
 
 hipError_t launch_density(mfm_ctx *ctx, const mfm_particles *pp) {
   DensityArgs a;
   a.n = pp->n;
-  a.x = pp->x; a.y = pp->y; a.z = pp->z; a.m = pp->m; a.U = pp->U;
+  a.pos = reinterpret_cast<const double4 *>(ctx->pos4);
+  a.m = pp->m; a.U = pp->U; a.vx = pp->vx; a.vy = pp->vy; a.vz = pp->vz;
   a.H = pp->H; a.V = pp->V; a.rho = pp->rho; a.P = pp->P; a.c = pp->c; a.ncond = pp->ncond;
+  a.gin = ctx->gin;
+  a.cand = ctx->cand;
+  a.cand_cnt = ctx->cand_cnt;
+  a.cand_r2 = ctx->cand_r2;
   a.gamma = ctx->p.gamma;
   a.n_ngb = ctx->p.n_ngb;
   a.ncond_max = ctx->p.ncond_max;
@@ -219,12 +264,5 @@ hipError_t launch_density(mfm_ctx *ctx, const mfm_particles *pp) {
   a.max_boosts = ctx->p.max_boosts;
   a.counters = ctx->counters;
   density_k<<<blocks_for(pp->n, BS), BS, 0, ctx->stream>>>(a, ctx->grid);
-  return hipGetLastError();
-}
-
-hipError_t launch_build_lists(mfm_ctx *ctx, const mfm_particles *pp) {
-  lists_k<<<blocks_for(pp->n, BS), BS, 0, ctx->stream>>>(pp->n, pp->x, pp->y, pp->z, pp->H,
-                                                          ctx->grid, ctx->p.max_list, ctx->list,
-                                                          ctx->list_cnt, ctx->counters);
   return hipGetLastError();
 }

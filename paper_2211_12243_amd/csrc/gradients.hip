@@ -2,13 +2,14 @@
 // (Lanson-Vila) gradients with the conditioned slope limiter (sec. 2.3.3 and
 // 2.3.6) and the CFL time step (sec. 2.3.10), then the global minimum step.
 //
-// One lane per particle over its neighbour list (k-major layout, so the list
-// reads of a wavefront are coalesced).  Pass one accumulates E_i, the five
-// gradient sums, the neighbour extrema and the signal velocity; B_i = E_i^-1 is
-// the cofactor inverse in FP64; pass two finds the extreme face extrapolations
-// for the limiter.  The particle's flux-pass record (positions, primitives, B,
-// limited gradients: 256 bytes) is written packed, so the flux loop gathers
-// each neighbour with two cache lines instead of thirty scattered ones.
+// One lane per particle over its candidate list.  Each
+// neighbour (r < H_i) is gathered as one 128-byte record written by the
+// density loop.  Pass one accumulates E_i, the five gradient sums, the
+// neighbour extrema and the signal velocity, and records the faces this
+// particle will evaluate in the flux loop; B_i = E_i^-1 is the FP64 cofactor
+// inverse; pass two finds the extreme face extrapolations for the limiter.
+// The particle's flux record (positions, 1/H, V, primitives, 1/rho, B,
+// limited gradients: 256 bytes) is written packed.
 #include "mfm_internal.h"
 
 namespace {
@@ -19,9 +20,13 @@ constexpr double PI = 3.14159265358979323846;
 
 struct GradArgs {
   int64_t n;
-  const double *x, *y, *z, *H, *V, *rho, *vx, *vy, *vz, *P, *c;
+  const double *gin;
+  const double *H;      // converged support radii (SoA: 16 particles per cache line)
+  const double4 *pos;   // (x, y, z, 0) per particle
+  const int32_t *cand, *cand_cnt;
+  const double *cand_r2;
   double *B, *grad, *ncond, *dt_i, *rec;
-  const int32_t *list, *cnt;
+  int32_t *fslot, *fcnt;
   double box[3], half[3];
   double ncond_max, c_cfl;
   int limiter;
@@ -33,10 +38,12 @@ __global__ void __launch_bounds__(BS) gradients_k(GradArgs a) {
   const int64_t n = a.n;
   int64_t pairs = 0, singular = 0;
   if (i < n) {
-    const double xi = a.x[i], yi = a.y[i], zi = a.z[i], hi = a.H[i];
+    const double *gi = a.gin + i * GIN_STRIDE;
+    const double xi = gi[GIN_X], yi = gi[GIN_Y], zi = gi[GIN_Z], hi = gi[GIN_H];
     const double h2 = hi * hi, ih = 1.0 / hi, wnorm = 8.0 / (PI * hi * h2);
-    double qi[5] = {a.rho[i], a.vx[i], a.vy[i], a.vz[i], a.P[i]};
-    const double ci = a.c[i];
+    const double qi[5] = {gi[GIN_RHO], gi[GIN_VX], gi[GIN_VY], gi[GIN_VZ], gi[GIN_P]};
+    const double ci = gi[GIN_C];
+    const int b0 = (int)(i / FLUX_BLOCK) * FLUX_BLOCK;
     double e[6] = {0, 0, 0, 0, 0, 0};
     double s[5][3];
     double qmax[5], qmin[5];
@@ -46,28 +53,39 @@ __global__ void __launch_bounds__(BS) gradients_k(GradArgs a) {
       qmax[q] = qmin[q] = qi[q];
     }
     double vsig = 0.0;
-    const int cnt = a.cnt[i];
+    int nf = 0;
+    const int cnt = a.cand_cnt[i];
     for (int k = 0; k < cnt; ++k) {
-      const int j = a.list[(int64_t)k * n + i];
-      double d0 = min_image(a.x[j] - xi, a.box[0], a.half[0]);
-      double d1 = min_image(a.y[j] - yi, a.box[1], a.half[1]);
-      double d2 = min_image(a.z[j] - zi, a.box[2], a.half[2]);
-      double r2 = d0 * d0 + d1 * d1 + d2 * d2;
-      if (!(r2 < h2)) continue;
+      const int64_t at = list_at(i, k, n);
+      const int j = a.cand[at];
+      const double r2 = a.cand_r2[at];
+      // faces of the flux loop: r < max(H_i, H_j); one evaluation per face
+      // inside a block, one per side across blocks
+      const bool gather = r2 < h2;  // j is in the gather set of i (then also a face)
+      if ((gather || r2 < a.H[j] * a.H[j]) &&
+          ((j < b0 || j >= b0 + FLUX_BLOCK) || emit_face((int)i, j))) {
+        a.fslot[list_at(i, nf, n)] = j;
+        ++nf;
+      }
+      if (!gather) continue;
+      const double *gj = a.gin + (int64_t)j * GIN_STRIDE;
       ++pairs;
       if (r2 == 0.0) continue;
-      double r = sqrt(r2);
-      double wv = a.V[j] * wnorm * spline_w(r * ih);
+      const double d0 = min_image(gj[GIN_X] - xi, a.box[0], a.half[0]);
+      const double d1 = min_image(gj[GIN_Y] - yi, a.box[1], a.half[1]);
+      const double d2 = min_image(gj[GIN_Z] - zi, a.box[2], a.half[2]);
+      const double r = sqrt(r2);
+      const double wv = gj[GIN_V] * wnorm * spline_w(r * ih);
       e[0] += wv * d0 * d0;
       e[1] += wv * d0 * d1;
       e[2] += wv * d0 * d2;
       e[3] += wv * d1 * d1;
       e[4] += wv * d1 * d2;
       e[5] += wv * d2 * d2;
-      double qj[5] = {a.rho[j], a.vx[j], a.vy[j], a.vz[j], a.P[j]};
+      const double qj[5] = {gj[GIN_RHO], gj[GIN_VX], gj[GIN_VY], gj[GIN_VZ], gj[GIN_P]};
 #pragma unroll
       for (int q = 0; q < 5; ++q) {
-        double df = wv * (qj[q] - qi[q]);
+        const double df = wv * (qj[q] - qi[q]);
         s[q][0] += df * d0;
         s[q][1] += df * d1;
         s[q][2] += df * d2;
@@ -75,8 +93,9 @@ __global__ void __launch_bounds__(BS) gradients_k(GradArgs a) {
         qmin[q] = fmin(qmin[q], qj[q]);
       }
       // signal velocity: x_i - x_j = -d
-      double proj = -(d0 * (qi[1] - qj[1]) + d1 * (qi[2] - qj[2]) + d2 * (qi[3] - qj[3])) / r;
-      vsig = fmax(vsig, ci + a.c[j] - fmin(0.0, proj));
+      const double proj =
+          -(d0 * (qi[1] - qj[1]) + d1 * (qi[2] - qj[2]) + d2 * (qi[3] - qj[3])) / r;
+      vsig = fmax(vsig, ci + gj[GIN_C] - fmin(0.0, proj));
     }
     // B = E^-1 by cofactors
     double cf[6];
@@ -86,7 +105,7 @@ __global__ void __launch_bounds__(BS) gradients_k(GradArgs a) {
     cf[3] = e[0] * e[5] - e[2] * e[2];
     cf[4] = e[1] * e[2] - e[0] * e[4];
     cf[5] = e[0] * e[3] - e[1] * e[1];
-    double det = e[0] * cf[0] + e[1] * cf[1] + e[2] * cf[2];
+    const double det = e[0] * cf[0] + e[1] * cf[1] + e[2] * cf[2];
     if (!(det != 0.0) || !isfinite(det)) ++singular;
     double b[6];
 #pragma unroll
@@ -107,15 +126,16 @@ __global__ void __launch_bounds__(BS) gradients_k(GradArgs a) {
     if (a.limiter & MFM_LIMIT_BJ) {
       double dmax[5] = {0, 0, 0, 0, 0}, dmin[5] = {0, 0, 0, 0, 0};
       for (int k = 0; k < cnt; ++k) {
-        const int j = a.list[(int64_t)k * n + i];
-        double d0 = min_image(a.x[j] - xi, a.box[0], a.half[0]);
-        double d1 = min_image(a.y[j] - yi, a.box[1], a.half[1]);
-        double d2 = min_image(a.z[j] - zi, a.box[2], a.half[2]);
-        double r2 = d0 * d0 + d1 * d1 + d2 * d2;
+        const int64_t at = list_at(i, k, n);
+        const double r2 = a.cand_r2[at];
         if (!(r2 < h2)) continue;
+        const double4 pj = a.pos[a.cand[at]];
+        const double d0 = min_image(pj.x - xi, a.box[0], a.half[0]);
+        const double d1 = min_image(pj.y - yi, a.box[1], a.half[1]);
+        const double d2 = min_image(pj.z - zi, a.box[2], a.half[2]);
 #pragma unroll
         for (int q = 0; q < 5; ++q) {
-          double ex = 0.5 * (g[q][0] * d0 + g[q][1] * d1 + g[q][2] * d2);
+          const double ex = 0.5 * (g[q][0] * d0 + g[q][1] * d1 + g[q][2] * d2);
           dmax[q] = fmax(dmax[q], ex);
           dmin[q] = fmin(dmin[q], ex);
         }
@@ -135,10 +155,14 @@ __global__ void __launch_bounds__(BS) gradients_k(GradArgs a) {
     rec[R_X] = xi;
     rec[R_Y] = yi;
     rec[R_Z] = zi;
-    rec[R_H] = hi;
-    rec[R_V] = a.V[i];
-#pragma unroll
-    for (int q = 0; q < 5; ++q) rec[R_RHO + q] = qi[q];
+    rec[R_IH] = ih;
+    rec[R_V] = gi[GIN_V];
+    rec[R_RHO] = qi[0];
+    rec[R_IRHO] = 1.0 / qi[0];
+    rec[R_VX] = qi[1];
+    rec[R_VY] = qi[2];
+    rec[R_VZ] = qi[3];
+    rec[R_P] = qi[4];
 #pragma unroll
     for (int k = 0; k < 6; ++k) {
       a.B[k * n + i] = b[k];
@@ -148,13 +172,13 @@ __global__ void __launch_bounds__(BS) gradients_k(GradArgs a) {
     for (int q = 0; q < 5; ++q)
 #pragma unroll
       for (int k = 0; k < 3; ++k) {
-        double v = alpha[q] * g[q][k];
+        const double v = alpha[q] * g[q][k];
         a.grad[(3 * q + k) * n + i] = v;
         rec[R_G + 3 * q + k] = v;
       }
-    rec[R_STRIDE - 1] = 0.0;
     a.ncond[i] = nc;
     a.dt_i[i] = vsig > 0.0 ? a.c_cfl * hi / vsig : __builtin_huge_val();
+    a.fcnt[i] = nf;
   }
   count_add(a.counters + C_GRAD_PAIRS, pairs);
   count_add(a.counters + C_SINGULAR_E, singular);
@@ -185,8 +209,9 @@ __global__ void dt_final_k(const double *partial, int np, double dt_max, double 
   __syncthreads();
   if (threadIdx.x == 0) {
     for (int w = 1; w < BS / 64; ++w) m = fmin(m, s[w]);
-    double v = fmin(dt_max, m);
-    if (!(v > 0.0) || !isfinite(v)) atomicAdd((unsigned long long *)(counters + C_NONFINITE), 1ull);
+    const double v = fmin(dt_max, m);
+    if (!(v > 0.0) || !isfinite(v))
+      atomicAdd((unsigned long long *)(counters + C_NONFINITE), 1ull);
     dt[0] = v;
   }
 }
@@ -197,10 +222,15 @@ hipError_t launch_gradients(mfm_ctx *ctx, const mfm_particles *pp, double dt_max
                             double *dt_dev) {
   GradArgs a;
   a.n = pp->n;
-  a.x = pp->x; a.y = pp->y; a.z = pp->z; a.H = pp->H; a.V = pp->V; a.rho = pp->rho;
-  a.vx = pp->vx; a.vy = pp->vy; a.vz = pp->vz; a.P = pp->P; a.c = pp->c;
+  a.gin = ctx->gin;
+  a.H = pp->H;
+  a.pos = reinterpret_cast<const double4 *>(ctx->pos4);
+  a.cand = ctx->cand;
+  a.cand_cnt = ctx->cand_cnt;
+  a.cand_r2 = ctx->cand_r2;
   a.B = pp->B; a.grad = pp->grad; a.ncond = pp->ncond; a.dt_i = pp->dt_i; a.rec = ctx->rec;
-  a.list = ctx->list; a.cnt = ctx->list_cnt;
+  a.fslot = ctx->fslot;
+  a.fcnt = ctx->fcnt;
   for (int k = 0; k < 3; ++k) {
     a.box[k] = ctx->p.box[k];
     a.half[k] = 0.5 * ctx->p.box[k];

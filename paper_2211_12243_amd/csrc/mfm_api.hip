@@ -12,7 +12,8 @@ namespace {
 constexpr size_t ALIGN = 256;
 
 struct Layout {
-  size_t code, count, start, cursor, scan, order, tmp, list, cnt, rec, red, counters, scalars;
+  size_t code, count, start, cursor, crange, scan, order, tmp, pos4, cand, cand_r2, cand_cnt, gin, fslot,
+      fcnt, rec, red, counters, scalars;
   size_t total;
   int64_t ncodes_max;
   size_t scan_len;
@@ -43,11 +44,17 @@ Layout make_layout(const mfm_params *p, int64_t n) {
   L.count = take(4 * (size_t)L.ncodes_max);
   L.start = take(4 * (size_t)L.ncodes_max);
   L.cursor = take(4 * (size_t)L.ncodes_max);
+  L.crange = take(8 * (size_t)L.ncodes_max);
   L.scan = take(4 * scan_len);
   L.order = take(4 * (size_t)n);
   L.tmp = take(8 * 11 * (size_t)n);
-  L.list = take(4 * (size_t)p->max_list * (size_t)n);
-  L.cnt = take(4 * (size_t)n);
+  L.pos4 = take(32 * (size_t)n);
+  L.cand = take(4 * list_len(p->max_list, n));
+  L.cand_r2 = take(8 * list_len(p->max_list, n));
+  L.cand_cnt = take(4 * (size_t)n);
+  L.gin = take(8 * (size_t)GIN_STRIDE * (size_t)n);
+  L.fslot = take(4 * list_len(p->max_list, n));
+  L.fcnt = take(4 * (size_t)n);
   L.rec = take(8 * (size_t)R_STRIDE * (size_t)n);
   L.red = take(8 * 5 * 1024);
   L.counters = take(8 * NCOUNTERS);
@@ -132,6 +139,7 @@ int setup_grid(mfm_ctx *ctx, double hmax) {
   ctx->ncodes = (int64_t)1 << (3 * ctx->bits);
   g.start = ctx->cell_start;
   g.count = ctx->cell_count;
+  g.range = ctx->crange;
   return MFM_OK;
 }
 
@@ -219,11 +227,17 @@ int mfm_create(const mfm_params *p, int64_t n_max, void *workspace, size_t works
   ctx->cell_count = (int32_t *)(ctx->ws + L.count);
   ctx->cell_start = (int32_t *)(ctx->ws + L.start);
   ctx->cursor = (int32_t *)(ctx->ws + L.cursor);
+  ctx->crange = (int2 *)(ctx->ws + L.crange);
   ctx->scan_tmp = (int32_t *)(ctx->ws + L.scan);
   ctx->order = (int32_t *)(ctx->ws + L.order);
   ctx->tmp = (double *)(ctx->ws + L.tmp);
-  ctx->list = (int32_t *)(ctx->ws + L.list);
-  ctx->list_cnt = (int32_t *)(ctx->ws + L.cnt);
+  ctx->pos4 = (double *)(ctx->ws + L.pos4);
+  ctx->cand = (int32_t *)(ctx->ws + L.cand);
+  ctx->cand_r2 = (double *)(ctx->ws + L.cand_r2);
+  ctx->cand_cnt = (int32_t *)(ctx->ws + L.cand_cnt);
+  ctx->gin = (double *)(ctx->ws + L.gin);
+  ctx->fslot = (int32_t *)(ctx->ws + L.fslot);
+  ctx->fcnt = (int32_t *)(ctx->ws + L.fcnt);
   ctx->rec = (double *)(ctx->ws + L.rec);
   ctx->red = (double *)(ctx->ws + L.red);
   ctx->counters = (int64_t *)(ctx->ws + L.counters);
@@ -288,10 +302,10 @@ int mfm_density(mfm_ctx *ctx, const mfm_particles *pp) {
   HIPCHK(ctx, hipMemsetAsync(ctx->counters + C_PASS_NOCONV, 0, 3 * sizeof(int64_t),
                              ctx->stream), "clear pass counters");
   stage_begin(ctx, 1);
-  HIPCHK(ctx, launch_density(ctx, pp), "density");
+  HIPCHK(ctx, launch_candidates(ctx, pp), "neighbour search");
   stage_end(ctx, 1);
   stage_begin(ctx, 2);
-  HIPCHK(ctx, launch_build_lists(ctx, pp), "lists");
+  HIPCHK(ctx, launch_density(ctx, pp), "density");
   stage_end(ctx, 2);
   int64_t c[NCOUNTERS];
   int rc = read_counters(ctx, c);
@@ -317,7 +331,7 @@ int mfm_density(mfm_ctx *ctx, const mfm_particles *pp) {
          "fold pass counters");
   HIPCHK(ctx, hipStreamSynchronize(ctx->stream), "synchronise");
   if (c[C_LIST_OVERFLOW] > 0)
-    return fail(ctx, MFM_E_LIST, "neighbour list capacity exceeded (raise max_list)");
+    return fail(ctx, MFM_E_LIST, "candidate list capacity exceeded (raise max_list)");
   ctx->have_density = 1;
   ctx->have_grad = 0;
   return MFM_OK;

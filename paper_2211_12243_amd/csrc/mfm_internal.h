@@ -37,11 +37,22 @@ enum {
   NCOUNTERS = 24
 };
 
-// Packed per-particle record read by the flux pass (one 256-byte line pair).
+// Packed per-particle record the gradient loop gathers for each neighbour
+// (written by the density loop; one 128-byte line).
+enum { GIN_X = 0, GIN_Y, GIN_Z, GIN_H, GIN_V, GIN_RHO, GIN_VX, GIN_VY, GIN_VZ, GIN_P, GIN_C,
+       GIN_STRIDE = 16 };
+
+// Packed per-particle record the flux loop gathers for each face side
+// (written by the gradient loop; two 128-byte lines).
 enum {
-  R_X = 0, R_Y, R_Z, R_H, R_V, R_RHO, R_VX, R_VY, R_VZ, R_P,
-  R_B = 10,     // 6 entries of B = E^-1
-  R_G = 16,     // 15 entries of the limited gradients (rho, vx, vy, vz, P) x (x, y, z)
+  R_X = 0, R_Y, R_Z,
+  R_IH = 3,     // 1 / H
+  R_V = 4,      // volume
+  R_RHO = 5,    // primitives rho, vx, vy, vz, P at 5..10 (with 1/rho at 6)
+  R_IRHO = 6,
+  R_VX = 7, R_VY = 8, R_VZ = 9, R_P = 10,
+  R_B = 11,     // 6 entries of B = E^-1
+  R_G = 17,     // 15 entries of the limited gradients (rho, vx, vy, vz, P) x (x, y, z)
   R_STRIDE = 32
 };
 
@@ -54,6 +65,7 @@ struct CellGrid {
   double side_min;    // smallest cell side: every pair closer than this is in the 27-cell stencil
   const int32_t *start;  // indexed by Morton code
   const int32_t *count;  // indexed by Morton code
+  const int2 *range;     // (start, count) by Morton code, one load per cell
 };
 
 struct mfm_ctx {
@@ -67,11 +79,17 @@ struct mfm_ctx {
   int32_t *cell_count; // ncodes_max
   int32_t *cell_start; // ncodes_max
   int32_t *cursor;     // ncodes_max
+  int2 *crange;        // ncodes_max: (start, count) per cell
   int32_t *scan_tmp;   // block sums of the scans
   int32_t *order;      // n: input slot of each sorted slot
   double *tmp;         // 11 n doubles: gather buffer of the permutation
-  int32_t *list;       // max_list * n, entry k of particle i at [k * n + i]
-  int32_t *list_cnt;   // n
+  double *pos4;        // 4 n: (x, y, z, 0) per particle, for the neighbour search
+  int32_t *cand;       // max_list * n candidates (r < cell side), entry k of i at [k * n + i]
+  double *cand_r2;     // max_list * n: their squared distances
+  int32_t *cand_cnt;   // n
+  double *gin;         // GIN_STRIDE * n packed gradient-loop records
+  int32_t *fslot;      // max_list * n: faces each particle evaluates (k-major)
+  int32_t *fcnt;       // n
   double *rec;         // R_STRIDE * n packed flux records
   double *red;         // reduction partials
   int64_t *counters;   // NCOUNTERS
@@ -170,8 +188,8 @@ __device__ __forceinline__ void count_add(int64_t *ctr, int64_t v) {
 // ---------------------------------------------------------------------------
 hipError_t launch_max_h(mfm_ctx *ctx, const mfm_particles *pp);
 hipError_t launch_build_cells(mfm_ctx *ctx, const mfm_particles *pp, int64_t *perm);
+hipError_t launch_candidates(mfm_ctx *ctx, const mfm_particles *pp);
 hipError_t launch_density(mfm_ctx *ctx, const mfm_particles *pp);
-hipError_t launch_build_lists(mfm_ctx *ctx, const mfm_particles *pp);
 hipError_t launch_gradients(mfm_ctx *ctx, const mfm_particles *pp, double dt_max, double *dt_dev);
 hipError_t launch_fluxes(mfm_ctx *ctx, const mfm_particles *pp, const double *dt_dev);
 hipError_t launch_update(mfm_ctx *ctx, const mfm_particles *pp, const double *dt_dev);
@@ -182,3 +200,27 @@ void stage_begin(mfm_ctx *ctx, int stage);
 void stage_end(mfm_ctx *ctx, int stage);
 
 static inline int blocks_for(int64_t n, int bs) { return (int)((n + bs - 1) / bs); }
+
+// Per-particle lists (candidates, faces) are stored in tiles of LIST_TILE
+// consecutive entries of one particle: entry k of particle i sits at
+// ((k / LIST_TILE) * n + i) * LIST_TILE + k % LIST_TILE.  LIST_TILE = 1 is the
+// k-major layout: the loops read entry k of 64 consecutive particles in
+// lockstep, one coalesced access (measured faster than 16-entry tiles, which
+// only help the appending writes).
+constexpr int LIST_TILE = 1;
+__host__ __device__ __forceinline__ int64_t list_at(int64_t i, int k, int64_t n) {
+  return (((int64_t)(k / LIST_TILE) * n + i) * LIST_TILE) + (k % LIST_TILE);
+}
+static inline size_t list_len(int max_list, int64_t n) {
+  return (size_t)((max_list + LIST_TILE - 1) / LIST_TILE) * LIST_TILE * (size_t)n;
+}
+
+// Particles per workgroup of the flux loop: faces inside a block are computed
+// once, faces crossing its boundary by both blocks (see fluxes.hip).
+constexpr int FLUX_BLOCK = 256;
+
+// Exactly one of emit(i, j), emit(j, i) holds, and about half of any
+// particle's in-block faces are its own whatever its rank in the block.
+__device__ __forceinline__ bool emit_face(int i, int j) {
+  return ((i ^ j) & 1) ? (i < j) : (i > j);
+}

@@ -22,7 +22,7 @@ MFM_FP64, MFM_MIXED = 0, 1
 MFM_GUESS_PLAIN, MFM_GUESS_LEARNED = 0, 1
 MFM_LIMIT_BJ, MFM_LIMIT_PAIRWISE = 1, 2
 MFM_NSTAGES = 6
-STAGES = ("cells", "density", "lists", "gradients", "fluxes", "update")
+STAGES = ("cells", "search", "density", "gradients", "fluxes", "update")
 
 
 class mfm_params(ctypes.Structure):

@@ -122,8 +122,8 @@ CASES = [
     ("kh20_mfm", lambda: W.kh(n=20, seed=2), {"scheme": "mfm"}),
     ("sedov24_mfm", lambda: W.sedov(n=24, seed=3), {"scheme": "mfm"}),
     ("sedov24_mfv", lambda: W.sedov(n=24, seed=3), {"scheme": "mfv"}),
-    ("random3000_mfv", lambda: W.random_gas(N=3000, seed=4), {"scheme": "mfv"}),
-    ("ragged_4099_mfm", lambda: W.random_gas(N=4099, seed=5), {"scheme": "mfm"}),
+    ("random3000_mfv", lambda: W.random_gas(N=3000, seed=4), {"scheme": "mfv", "max_list": 512}),
+    ("ragged_4099_mfm", lambda: W.random_gas(N=4099, seed=5), {"scheme": "mfm", "max_list": 512}),
 ]
 
 
