@@ -16,38 +16,57 @@
 // global atomics: FP64 global atomic adds run at ~23 G/s on this part, far
 // too slow for a scatter of ~10 per face.
 //
-// Arithmetic.  For gamma = m / (m - 2) with integer m every power in the exact
-// solver is an integer power of x^(1/m); for m = 5 (gamma 5/3) and m = 7
-// (gamma 7/5) that root is an FP32 seed polished by two FP64 Newton steps on
-// y^m = x (quadratic: 1e-7 -> 1e-14 -> roundoff).  Other gammas call pow().
+// Precision.  T = double is the FP64 path.  T = float is the mixed path: the
+// separation is formed in FP64 from FP64 positions and rounded; the face
+// vector, extrapolation, limiter and the Newton iteration of the Riemann solve
+// run in FP32; the solve is then checked in FP64 (one FP64 Newton step from
+// the FP32 root, more if that step is not already in the quadratic regime),
+// and every contribution is accumulated in FP64.
+//
+// Powers.  For gamma = m / (m - 2) with integer m every power in the exact
+// solver is an integer power of x^(1/m).  In FP64, for m = 5 (gamma 5/3) and
+// m = 7 (gamma 7/5), that root is an FP32 seed polished by two FP64 Newton
+// steps on y^m = x (quadratic: 1e-7 -> 1e-14 -> roundoff); in FP32 it is the
+// hardware exp2/log2.  Other gammas call pow().
 #include "mfm_internal.h"
 
 namespace {
 
 constexpr int FBS = FLUX_BLOCK;
 
+template <typename T>
 struct Gas {
-  double gamma, g1, g2, g3, g4, g5, g6, g7, inv_gm1;
-  int m;          // 1 / g1 when it is an integer (the root path), else 0
+  T gamma, g1, g2, g3, g4, g5, g6, g7, inv_gm1;
 };
 
 struct FluxArgs {
   int64_t n;
   const double *rec;
+  const double4 *pos;
   const int32_t *fslot, *fcnt;
   const double *dt;
   double *dQ;
   double box[3], half[3];
-  Gas G;
+  Gas<double> G;
+  Gas<float> Gf;
   double psi1, psi2, rtol;
+  float rtol_f;
   int rmaxit, limiter;
   int64_t *counters;
 };
 
-// x^(1/m), x > 0.
-template <int M>
-__device__ __forceinline__ double root_m(double x, const Gas &G) {
+template <typename T>
+__device__ __forceinline__ const Gas<T> &gas_of(const FluxArgs &a);
+template <>
+__device__ __forceinline__ const Gas<double> &gas_of<double>(const FluxArgs &a) { return a.G; }
+template <>
+__device__ __forceinline__ const Gas<float> &gas_of<float>(const FluxArgs &a) { return a.Gf; }
+
+// x^(1/m) (= x^g1), x > 0.
+template <typename T, int M>
+__device__ __forceinline__ T root_m(T x, const Gas<T> &G) {
   if (M == 0) return pow(x, G.g1);
+  if (sizeof(T) == sizeof(float)) return (T)exp2f(log2f((float)x) * (1.0f / (float)M));
   double y = (double)exp2f((1.0f / (float)M) * log2f((float)x));
   if (!(y > 0.0) || !isfinite(y)) return pow(x, G.g1);  // outside the FP32 range
   constexpr double im = 1.0 / (double)(M > 0 ? M : 1);
@@ -56,42 +75,34 @@ __device__ __forceinline__ double root_m(double x, const Gas &G) {
     double ym1 = 1.0;  // y^(m-1)
 #pragma unroll
     for (int k = 1; k < M; ++k) ym1 *= y;
-    y = y + (x / ym1 - y) * im;
+    y = y + ((double)x / ym1 - y) * im;
   }
-  return y;
+  return (T)y;
 }
 
-template <int K>
-__device__ __forceinline__ double ipow(double x) {
-  double r = 1.0;
+template <int K, typename T>
+__device__ __forceinline__ T ipow(T x) {
+  T r = T(1);
 #pragma unroll
   for (int q = 0; q < K; ++q) r *= x;
   return r;
 }
 
-// x^(g4) and x^(g3) (g4 = m - 2 and g3 = m on the root path).
-template <int M>
-__device__ __forceinline__ double pow_g4(double x, const Gas &G) {
-  return M ? ipow<(M > 2 ? M - 2 : 0)>(x) : pow(x, G.g4);
-}
-template <int M>
-__device__ __forceinline__ double pow_g3(double x, const Gas &G) {
-  return M ? ipow<M>(x) : pow(x, G.g3);
-}
-
+template <typename T>
 struct Side {
-  double r, u, p, c;
-  double ip;   // 1 / p
-  double A;    // 2 / ((gamma + 1) rho)
-  double B;    // (gamma - 1) / (gamma + 1) p
-  double prc;  // p / (rho c)
-  double g4c;  // 2 c / (gamma - 1)
+  T r, u, p, c;
+  T ip;   // 1 / p
+  T A;    // 2 / ((gamma + 1) rho)
+  T B;    // (gamma - 1) / (gamma + 1) p
+  T prc;  // p / (rho c)
+  T g4c;  // 2 c / (gamma - 1)
 };
 
-__device__ __forceinline__ Side make_side(double r, double u, double p, double c, const Gas &G) {
-  Side s;
+template <typename T>
+__device__ __forceinline__ Side<T> make_side(T r, T u, T p, T c, const Gas<T> &G) {
+  Side<T> s;
   s.r = r; s.u = u; s.p = p; s.c = c;
-  s.ip = 1.0 / p;
+  s.ip = T(1) / p;
   s.A = G.g5 / r;
   s.B = G.g6 * p;
   s.prc = p / (r * c);
@@ -100,129 +111,148 @@ __device__ __forceinline__ Side make_side(double r, double u, double p, double c
 }
 
 // Toro's pressure function of one side and its derivative at pressure ps (ips = 1/ps).
-template <int M>
-__device__ __forceinline__ void pressure_fn(double ps, double ips, const Side &s, const Gas &G,
-                                            double &f, double &df) {
+template <typename T, int M>
+__device__ __forceinline__ void pressure_fn(T ps, T ips, const Side<T> &s, const Gas<T> &G, T &f,
+                                            T &df) {
   if (ps <= s.p) {
-    const double e = root_m<M>(ps * s.ip, G);  // (p*/p_K)^((gamma-1)/(2 gamma))
-    f = s.g4c * (e - 1.0);
-    df = e * s.prc * ips;                          // (p*/p_K)^(g1 - 1) / (rho_K c_K)
+    const T e = root_m<T, M>(ps * s.ip, G);  // (p*/p_K)^((gamma-1)/(2 gamma))
+    f = s.g4c * (e - T(1));
+    df = e * s.prc * ips;                     // (p*/p_K)^(g1 - 1) / (rho_K c_K)
   } else {
-    const double t = 1.0 / (s.B + ps);
-    const double q = sqrt(s.A * t);
-    const double dp = ps - s.p;
+    const T t = T(1) / (s.B + ps);
+    const T q = sqrt(s.A * t);
+    const T dp = ps - s.p;
     f = dp * q;
-    df = q * (1.0 - 0.5 * dp * t);
+    df = q * (T(1) - T(0.5) * dp * t);
   }
 }
 
-// Exact Riemann solve: 0 converged, 1 vacuum, 2 iteration cap.
-template <int M>
-__device__ int riemann_solve(const Gas &G, const Side &L, const Side &R, double tol, int maxit,
-                             double &ps, double &us, int &iters) {
-  const double du = R.u - L.u;
-  iters = 0;
-  if (G.g4 * (L.c + R.c) <= du) {
-    ps = 0.0;
-    us = 0.5 * (L.u + R.u);
-    return 1;
-  }
-  const double pmin = fmin(L.p, R.p), pmax = fmax(L.p, R.p);
-  double ppv = 0.5 * (L.p + R.p) - 0.125 * du * (L.r + R.r) * (L.c + R.c);
-  ppv = fmax(ppv, 0.0);
-  double p0;
-  if (pmax <= 2.0 * pmin && pmin <= ppv && ppv <= pmax) {
-    p0 = ppv;
-  } else if (ppv < pmin) {
-    // two-rarefaction value: [(cL + cR - g7 du) / (cL pL^-g1 + cR pR^-g1)]^(1/g1)
-    const double num = L.c + R.c - G.g7 * du;
-    const double den = L.c / root_m<M>(L.p, G) + R.c / root_m<M>(R.p, G);
-    const double t = num / den;
-    p0 = M ? ipow<M>(t) : pow(t, 1.0 / G.g1);
-  } else {
-    const double gL = sqrt(L.A / (L.B + ppv));
-    const double gR = sqrt(R.A / (R.B + ppv));
-    p0 = (gL * L.p + gR * R.p - du) / (gL + gR);
-  }
-  const double pfloor = 1e-10 * 0.5 * (L.p + R.p);
-  if (!(p0 > pfloor)) p0 = pfloor;
-  double p = p0, fL, dfL, fR, dfR;
+// Newton iteration on f(p) = f_L(p) + f_R(p) + du from p0, then u*.  With
+// quadratic_exit, a step below sqrt(tol) ends the iteration (the next error is
+// the square of it) and u* uses the first-order update of f_L, f_R.
+template <typename T, int M>
+__device__ int riemann_newton(const Gas<T> &G, const Side<T> &L, const Side<T> &R, T p0,
+                              T pfloor, T tol, int maxit, bool quadratic_exit, T &ps, T &us,
+                              int &iters) {
+  const T du = R.u - L.u;
+  T p = p0, fL, dfL, fR, dfR;
   int status = 2;
   for (int it = 1; it <= maxit; ++it) {
-    const double ip = 1.0 / p;
-    pressure_fn<M>(p, ip, L, G, fL, dfL);
-    pressure_fn<M>(p, ip, R, G, fR, dfR);
-    double pn = p - (fL + fR + du) / (dfL + dfR);
-    if (pn < 0.0) pn = pfloor;
-    const bool done = 2.0 * fabs(pn - p) < tol * (pn + p);
+    const T ip = T(1) / p;
+    pressure_fn<T, M>(p, ip, L, G, fL, dfL);
+    pressure_fn<T, M>(p, ip, R, G, fR, dfR);
+    T pn = p - (fL + fR + du) / (dfL + dfR);
+    if (pn < T(0)) pn = pfloor;
+    const T step = T(2) * fabs(pn - p);  // relative change: step / (pn + p)
+    ++iters;
+    if (quadratic_exit && step * step < tol * (pn + p) * (pn + p)) {
+      const T dp = pn - p;
+      ps = pn;
+      us = T(0.5) * (L.u + R.u) + T(0.5) * ((fR + dfR * dp) - (fL + dfL * dp));
+      return 0;
+    }
+    const bool done = step < tol * (pn + p);
     p = pn;
-    iters = it;
     if (done) {
       status = 0;
       break;
     }
   }
-  const double ip = 1.0 / p;
-  pressure_fn<M>(p, ip, L, G, fL, dfL);
-  pressure_fn<M>(p, ip, R, G, fR, dfR);
+  const T ip = T(1) / p;
+  pressure_fn<T, M>(p, ip, L, G, fL, dfL);
+  pressure_fn<T, M>(p, ip, R, G, fR, dfR);
   ps = p;
-  us = 0.5 * (L.u + R.u) + 0.5 * (fR - fL);
+  us = T(0.5) * (L.u + R.u) + T(0.5) * (fR - fL);
   return status;
 }
 
+// Exact Riemann solve: 0 converged, 1 vacuum, 2 iteration cap.
+template <typename T, int M>
+__device__ int riemann_solve(const Gas<T> &G, const Side<T> &L, const Side<T> &R, T tol, int maxit,
+                             T &ps, T &us, int &iters) {
+  const T du = R.u - L.u;
+  iters = 0;
+  if (G.g4 * (L.c + R.c) <= du) {
+    ps = T(0);
+    us = T(0.5) * (L.u + R.u);
+    return 1;
+  }
+  const T pmin = fmin(L.p, R.p), pmax = fmax(L.p, R.p);
+  T ppv = T(0.5) * (L.p + R.p) - T(0.125) * du * (L.r + R.r) * (L.c + R.c);
+  ppv = fmax(ppv, T(0));
+  T p0;
+  if (pmax <= T(2) * pmin && pmin <= ppv && ppv <= pmax) {
+    p0 = ppv;
+  } else if (ppv < pmin) {
+    // two-rarefaction value: [(cL + cR - g7 du) / (cL pL^-g1 + cR pR^-g1)]^(1/g1)
+    const T num = L.c + R.c - G.g7 * du;
+    const T den = L.c / root_m<T, M>(L.p, G) + R.c / root_m<T, M>(R.p, G);
+    const T t = num / den;
+    p0 = M ? ipow<(M > 0 ? M : 1)>(t) : pow(t, T(1) / G.g1);
+  } else {
+    const T gL = sqrt(L.A / (L.B + ppv));
+    const T gR = sqrt(R.A / (R.B + ppv));
+    p0 = (gL * L.p + gR * R.p - du) / (gL + gR);
+  }
+  const T pfloor = T(1e-10) * T(0.5) * (L.p + R.p);
+  if (!(p0 > pfloor)) p0 = pfloor;
+  return riemann_newton<T, M>(G, L, R, p0, pfloor, tol, maxit, false, ps, us, iters);
+}
+
 // The exact solution at x/t = 0 in the face frame (Toro's sampling).
-template <int M>
-__device__ void sample_at_face(const Gas &G, const Side &L, const Side &R, double ps, double us,
-                               double &rf, double &uf, double &pf) {
-  if (0.0 <= us) {
+template <typename T, int M>
+__device__ void sample_at_face(const Gas<T> &G, const Side<T> &L, const Side<T> &R, T ps, T us,
+                               T &rf, T &uf, T &pf) {
+  constexpr int MG4 = M > 2 ? M - 2 : 0;  // g4 = m - 2, g3 = m, 1/gamma = (m - 2)/m
+  if (T(0) <= us) {
     if (ps <= L.p) {
-      if (0.0 <= L.u - L.c) {
+      if (T(0) <= L.u - L.c) {
         rf = L.r; uf = L.u; pf = L.p;
       } else {
-        const double t = ps * L.ip;
-        const double e = root_m<M>(t, G);
-        if (0.0 > us - L.c * e) {
-          rf = L.r * (M ? ipow<(M > 2 ? M - 2 : 0)>(e) : pow(t, 1.0 / G.gamma)); uf = us; pf = ps;
+        const T t = ps * L.ip;
+        const T e = root_m<T, M>(t, G);
+        if (T(0) > us - L.c * e) {
+          rf = L.r * (M ? ipow<MG4>(e) : pow(t, T(1) / G.gamma)); uf = us; pf = ps;
         } else {
-          const double cc = G.g5 * (L.c + G.g7 * L.u);
-          const double x = cc / L.c;
+          const T cc = G.g5 * (L.c + G.g7 * L.u);
+          const T x = cc / L.c;
           uf = cc;
-          rf = L.r * pow_g4<M>(x, G);
-          pf = L.p * pow_g3<M>(x, G);
+          rf = L.r * (M ? ipow<MG4>(x) : pow(x, G.g4));
+          pf = L.p * (M ? ipow<(M > 0 ? M : 1)>(x) : pow(x, G.g3));
         }
       }
     } else {
-      const double pml = ps * L.ip;
-      const double sl = L.u - L.c * sqrt(G.g2 * pml + G.g1);
-      if (0.0 <= sl) {
+      const T pml = ps * L.ip;
+      const T sl = L.u - L.c * sqrt(G.g2 * pml + G.g1);
+      if (T(0) <= sl) {
         rf = L.r; uf = L.u; pf = L.p;
       } else {
-        rf = L.r * (pml + G.g6) / (pml * G.g6 + 1.0); uf = us; pf = ps;
+        rf = L.r * (pml + G.g6) / (pml * G.g6 + T(1)); uf = us; pf = ps;
       }
     }
   } else {
     if (ps > R.p) {
-      const double pmr = ps * R.ip;
-      const double sr = R.u + R.c * sqrt(G.g2 * pmr + G.g1);
-      if (0.0 >= sr) {
+      const T pmr = ps * R.ip;
+      const T sr = R.u + R.c * sqrt(G.g2 * pmr + G.g1);
+      if (T(0) >= sr) {
         rf = R.r; uf = R.u; pf = R.p;
       } else {
-        rf = R.r * (pmr + G.g6) / (pmr * G.g6 + 1.0); uf = us; pf = ps;
+        rf = R.r * (pmr + G.g6) / (pmr * G.g6 + T(1)); uf = us; pf = ps;
       }
     } else {
-      if (0.0 >= R.u + R.c) {
+      if (T(0) >= R.u + R.c) {
         rf = R.r; uf = R.u; pf = R.p;
       } else {
-        const double t = ps * R.ip;
-        const double e = root_m<M>(t, G);
-        if (0.0 <= us + R.c * e) {
-          rf = R.r * (M ? ipow<(M > 2 ? M - 2 : 0)>(e) : pow(t, 1.0 / G.gamma)); uf = us; pf = ps;
+        const T t = ps * R.ip;
+        const T e = root_m<T, M>(t, G);
+        if (T(0) <= us + R.c * e) {
+          rf = R.r * (M ? ipow<MG4>(e) : pow(t, T(1) / G.gamma)); uf = us; pf = ps;
         } else {
-          const double cc = G.g5 * (R.c - G.g7 * R.u);
-          const double x = cc / R.c;
+          const T cc = G.g5 * (R.c - G.g7 * R.u);
+          const T x = cc / R.c;
           uf = -cc;
-          rf = R.r * pow_g4<M>(x, G);
-          pf = R.p * pow_g3<M>(x, G);
+          rf = R.r * (M ? ipow<MG4>(x) : pow(x, G.g4));
+          pf = R.p * (M ? ipow<(M > 0 ? M : 1)>(x) : pow(x, G.g3));
         }
       }
     }
@@ -231,93 +261,135 @@ __device__ void sample_at_face(const Gas &G, const Side &L, const Side &R, doubl
 
 // Pairwise limiter of a face value qf extrapolated from the own side (qo)
 // towards the other side (qn).
-__device__ __forceinline__ double pair_limit(double qf, double qo, double qn, double psi1,
-                                             double psi2) {
+template <typename T>
+__device__ __forceinline__ T pair_limit(T qf, T qo, T qn, T psi1, T psi2) {
   if (qo == qn) return qo;
-  const double dq = fabs(qo - qn);
-  const double d1 = psi1 * dq, d2 = psi2 * dq;
-  const double qbar = 0.5 * (qo + qn);
+  const T dq = fabs(qo - qn);
+  const T d1 = psi1 * dq, d2 = psi2 * dq;
+  const T qbar = T(0.5) * (qo + qn);
   if (qo < qn) {
-    const double lower = ((qo - d1) * qo > 0.0) ? qo - d1 : qo / (1.0 + d1 / fabs(qo));
+    const T lower = ((qo - d1) * qo > T(0)) ? qo - d1 : qo / (T(1) + d1 / fabs(qo));
     return fmax(lower, fmin(qbar + d2, qf));
   }
-  const double upper = ((qo + d1) * qo > 0.0) ? qo + d1 : qo / (1.0 + d1 / fabs(qo));
+  const T upper = ((qo + d1) * qo > T(0)) ? qo + d1 : qo / (T(1) + d1 / fabs(qo));
   return fmin(upper, fmax(qbar - d2, qf));
+}
+
+template <typename T>
+__device__ __forceinline__ T spline_wt(T q) {
+  if (q < T(0.5)) return T(1) + q * q * (T(6) * q - T(6));
+  if (q < T(1)) {
+    const T t = T(1) - q;
+    return T(2) * t * t * t;
+  }
+  return T(0);
+}
+
+// One side of a face as the face function reads it.
+template <typename T>
+struct FaceIn {
+  double x, y, z;
+  T ih, V, rho, irho, v[3], P, B[6], G[15];
+};
+
+__device__ __forceinline__ void load_side(const FluxArgs &a, int i, FaceIn<double> &s) {
+  const double *r = a.rec + (int64_t)i * R_STRIDE;
+  s.x = r[R_X]; s.y = r[R_Y]; s.z = r[R_Z];
+  s.ih = r[R_IH]; s.V = r[R_V]; s.rho = r[R_RHO]; s.irho = r[R_IRHO];
+  s.v[0] = r[R_VX]; s.v[1] = r[R_VY]; s.v[2] = r[R_VZ]; s.P = r[R_P];
+#pragma unroll
+  for (int k = 0; k < 6; ++k) s.B[k] = r[R_B + k];
+#pragma unroll
+  for (int k = 0; k < 15; ++k) s.G[k] = r[R_G + k];
+}
+
+__device__ __forceinline__ void load_side(const FluxArgs &a, int i, FaceIn<float> &s) {
+  const double4 p = a.pos[i];
+  s.x = p.x; s.y = p.y; s.z = p.z;
+  const float4 *r = reinterpret_cast<const float4 *>(a.rec) + (int64_t)i * (F_STRIDE / 4);
+  float f[F_STRIDE];
+#pragma unroll
+  for (int k = 0; k < F_STRIDE / 4; ++k) {
+    const float4 q = r[k];
+    f[4 * k] = q.x; f[4 * k + 1] = q.y; f[4 * k + 2] = q.z; f[4 * k + 3] = q.w;
+  }
+  s.ih = f[F_IH]; s.V = f[F_V]; s.rho = f[F_RHO]; s.irho = f[F_IRHO];
+  s.v[0] = f[F_VX]; s.v[1] = f[F_VY]; s.v[2] = f[F_VZ]; s.P = f[F_P];
+#pragma unroll
+  for (int k = 0; k < 6; ++k) s.B[k] = f[F_B + k];
+#pragma unroll
+  for (int k = 0; k < 15; ++k) s.G[k] = f[F_G + k];
 }
 
 enum { F_VACUUM = 1, F_POSITIVITY = 2, F_MAXIT = 4 };
 
 constexpr double W_NORM = 8.0 / 3.14159265358979323846;
 
-// Contribution c = |A_ij| F_ij of the face between records Lr (left) and Rr.
-template <int SCHEME, int M>
-__device__ void face_flux(const double *__restrict__ Lr, const double *__restrict__ Rr,
-                          const FluxArgs &a, double hdt, double c[5], int &iters, int &flags) {
-  const Gas &G = a.G;
+// Contribution c = |A_ij| F_ij of the face between sides Ls (left) and Rs.
+template <typename T, int SCHEME, int M>
+__device__ void face_flux(const FaceIn<T> &Ls, const FaceIn<T> &Rs, const FluxArgs &a, T hdt,
+                          double c[5], int &iters, int &flags) {
+  const Gas<T> &G = gas_of<T>(a);
   iters = 0;
   flags = 0;
 #pragma unroll
   for (int k = 0; k < 5; ++k) c[k] = 0.0;
-  double d[3];
-  d[0] = min_image(Rr[R_X] - Lr[R_X], a.box[0], a.half[0]);
-  d[1] = min_image(Rr[R_Y] - Lr[R_Y], a.box[1], a.half[1]);
-  d[2] = min_image(Rr[R_Z] - Lr[R_Z], a.box[2], a.half[2]);
-  const double r2 = d[0] * d[0] + d[1] * d[1] + d[2] * d[2];
-  if (r2 == 0.0) return;
-  const double r = sqrt(r2);
+  T d[3];
+  d[0] = T(min_image(Rs.x - Ls.x, a.box[0], a.half[0]));
+  d[1] = T(min_image(Rs.y - Ls.y, a.box[1], a.half[1]));
+  d[2] = T(min_image(Rs.z - Ls.z, a.box[2], a.half[2]));
+  const T r2 = d[0] * d[0] + d[1] * d[1] + d[2] * d[2];
+  if (r2 == T(0)) return;
+  const T r = sqrt(r2);
   // A_ij = V_i V_j (W(r, H_i) B_i + W(r, H_j) B_j) d
-  const double ihL = Lr[R_IH], ihR = Rr[R_IH];
-  const double WL = W_NORM * ihL * ihL * ihL * spline_w(r * ihL);
-  const double WR = W_NORM * ihR * ihR * ihR * spline_w(r * ihR);
-  const double *bL = Lr + R_B, *bR = Rr + R_B;
-  const double VV = Lr[R_V] * Rr[R_V];
-  double A[3];
+  const T WL = T(W_NORM) * Ls.ih * Ls.ih * Ls.ih * spline_wt<T>(r * Ls.ih);
+  const T WR = T(W_NORM) * Rs.ih * Rs.ih * Rs.ih * spline_wt<T>(r * Rs.ih);
+  const T *bL = Ls.B, *bR = Rs.B;
+  const T VV = Ls.V * Rs.V;
+  T A[3];
   A[0] = VV * (WL * (bL[0] * d[0] + bL[1] * d[1] + bL[2] * d[2]) +
                WR * (bR[0] * d[0] + bR[1] * d[1] + bR[2] * d[2]));
   A[1] = VV * (WL * (bL[1] * d[0] + bL[3] * d[1] + bL[4] * d[2]) +
                WR * (bR[1] * d[0] + bR[3] * d[1] + bR[4] * d[2]));
   A[2] = VV * (WL * (bL[2] * d[0] + bL[4] * d[1] + bL[5] * d[2]) +
                WR * (bR[2] * d[0] + bR[4] * d[1] + bR[5] * d[2]));
-  const double Am = sqrt(A[0] * A[0] + A[1] * A[1] + A[2] * A[2]);
-  if (Am == 0.0) return;
-  const double iA = 1.0 / Am;
-  const double nv[3] = {A[0] * iA, A[1] * iA, A[2] * iA};
+  const T Am = sqrt(A[0] * A[0] + A[1] * A[1] + A[2] * A[2]);
+  if (Am == T(0)) return;
+  const T iA = T(1) / Am;
+  const T nv[3] = {A[0] * iA, A[1] * iA, A[2] * iA};
 
-  double qi[5], qj[5], qL[5], qR[5];
-#pragma unroll
-  for (int q = 0; q < 5; ++q) {
-    qi[q] = Lr[R_RHO + (q ? q + 1 : 0)];
-    qj[q] = Rr[R_RHO + (q ? q + 1 : 0)];
-  }
-  const double *gi = Lr + R_G, *gj = Rr + R_G;
+  const T qi[5] = {Ls.rho, Ls.v[0], Ls.v[1], Ls.v[2], Ls.P};
+  const T qj[5] = {Rs.rho, Rs.v[0], Rs.v[1], Rs.v[2], Rs.P};
+  const T *gi = Ls.G, *gj = Rs.G;
+  T qL[5], qR[5];
   {
     // half-step Lagrangian predictor plus extrapolation to the mid-point face
-    const double dvi = gi[3] + gi[7] + gi[11];
-    const double dvj = gj[3] + gj[7] + gj[11];
-    const double iri = Lr[R_IRHO], irj = Rr[R_IRHO];
+    const T dvi = gi[3] + gi[7] + gi[11];
+    const T dvj = gj[3] + gj[7] + gj[11];
     qL[0] = qi[0] - hdt * qi[0] * dvi;
     qR[0] = qj[0] - hdt * qj[0] * dvj;
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
-      qL[1 + k] = qi[1 + k] - hdt * gi[12 + k] * iri;
-      qR[1 + k] = qj[1 + k] - hdt * gj[12 + k] * irj;
+      qL[1 + k] = qi[1 + k] - hdt * gi[12 + k] * Ls.irho;
+      qR[1 + k] = qj[1 + k] - hdt * gj[12 + k] * Rs.irho;
     }
     qL[4] = qi[4] - hdt * G.gamma * qi[4] * dvi;
     qR[4] = qj[4] - hdt * G.gamma * qj[4] * dvj;
 #pragma unroll
     for (int q = 0; q < 5; ++q) {
-      qL[q] += 0.5 * (gi[3 * q] * d[0] + gi[3 * q + 1] * d[1] + gi[3 * q + 2] * d[2]);
-      qR[q] -= 0.5 * (gj[3 * q] * d[0] + gj[3 * q + 1] * d[1] + gj[3 * q + 2] * d[2]);
+      qL[q] += T(0.5) * (gi[3 * q] * d[0] + gi[3 * q + 1] * d[1] + gi[3 * q + 2] * d[2]);
+      qR[q] -= T(0.5) * (gj[3 * q] * d[0] + gj[3 * q + 1] * d[1] + gj[3 * q + 2] * d[2]);
     }
   }
   if (a.limiter & MFM_LIMIT_PAIRWISE) {
+    const T psi1 = T(a.psi1), psi2 = T(a.psi2);
 #pragma unroll
     for (int q = 0; q < 5; ++q) {
-      qL[q] = pair_limit(qL[q], qi[q], qj[q], a.psi1, a.psi2);
-      qR[q] = pair_limit(qR[q], qj[q], qi[q], a.psi1, a.psi2);
+      qL[q] = pair_limit<T>(qL[q], qi[q], qj[q], psi1, psi2);
+      qR[q] = pair_limit<T>(qR[q], qj[q], qi[q], psi1, psi2);
     }
   }
-  if (!(qL[0] > 0.0 && qR[0] > 0.0 && qL[4] > 0.0 && qR[4] > 0.0)) {
+  if (!(qL[0] > T(0) && qR[0] > T(0) && qL[4] > T(0) && qR[4] > T(0))) {
 #pragma unroll
     for (int q = 0; q < 5; ++q) {
       qL[q] = qi[q];
@@ -325,54 +397,71 @@ __device__ void face_flux(const double *__restrict__ Lr, const double *__restric
     }
     flags |= F_POSITIVITY;
   }
-  const double vf[3] = {0.5 * (qi[1] + qj[1]), 0.5 * (qi[2] + qj[2]), 0.5 * (qi[3] + qj[3])};
-  double wL[3], wR[3];
+  const T vf[3] = {T(0.5) * (qi[1] + qj[1]), T(0.5) * (qi[2] + qj[2]), T(0.5) * (qi[3] + qj[3])};
+  T wL[3], wR[3];
 #pragma unroll
   for (int k = 0; k < 3; ++k) {
     wL[k] = qL[1 + k] - vf[k];
     wR[k] = qR[1 + k] - vf[k];
   }
-  const double uL = wL[0] * nv[0] + wL[1] * nv[1] + wL[2] * nv[2];
-  const double uR = wR[0] * nv[0] + wR[1] * nv[1] + wR[2] * nv[2];
-  const Side SL = make_side(qL[0], uL, qL[4], sqrt(G.gamma * qL[4] / qL[0]), G);
-  const Side SR = make_side(qR[0], uR, qR[4], sqrt(G.gamma * qR[4] / qR[0]), G);
-  double ps, us;
-  const int st = riemann_solve<M>(G, SL, SR, a.rtol, a.rmaxit, ps, us, iters);
+  const T uL = wL[0] * nv[0] + wL[1] * nv[1] + wL[2] * nv[2];
+  const T uR = wR[0] * nv[0] + wR[1] * nv[1] + wR[2] * nv[2];
+  const Side<T> SL = make_side<T>(qL[0], uL, qL[4], sqrt(G.gamma * qL[4] / qL[0]), G);
+  const Side<T> SR = make_side<T>(qR[0], uR, qR[4], sqrt(G.gamma * qR[4] / qR[0]), G);
+  T ps, us;
+  const T tol = sizeof(T) == sizeof(float) ? T(a.rtol_f) : T(a.rtol);
+  int st = riemann_solve<T, M>(G, SL, SR, tol, a.rmaxit, ps, us, iters);
   if (st == 1) {
     flags |= F_VACUUM;
     return;
   }
+  double ps64 = (double)ps, us64 = (double)us;
+  if (sizeof(T) == sizeof(float)) {
+    // FP64 check of the FP32 root: Newton steps in FP64 until the step is in
+    // the quadratic regime of the relative tolerance
+    const Gas<double> &G64 = a.G;
+    const double rl = qL[0], pl = qL[4], rr = qR[0], pr = qR[4];
+    const Side<double> L64 =
+        make_side<double>(rl, (double)uL, pl, sqrt(G64.gamma * pl / rl), G64);
+    const Side<double> R64 =
+        make_side<double>(rr, (double)uR, pr, sqrt(G64.gamma * pr / rr), G64);
+    const double pfloor = 1e-10 * 0.5 * (pl + pr);
+    st = riemann_newton<double, M>(G64, L64, R64, fmax(ps64, pfloor), pfloor, a.rtol, a.rmaxit,
+                                   true, ps64, us64, iters);
+  }
   if (st == 2) flags |= F_MAXIT;
-  const double vfn = vf[0] * nv[0] + vf[1] * nv[1] + vf[2] * nv[2];
+  const double vfn = (double)(vf[0] * nv[0] + vf[1] * nv[1] + vf[2] * nv[2]);
   if (SCHEME == MFM_SCHEME_MFM) {
-    const double Ap = Am * ps;
+    const double Ap = (double)Am * ps64;
     c[0] = 0.0;
 #pragma unroll
-    for (int k = 0; k < 3; ++k) c[1 + k] = Ap * nv[k];
-    c[4] = Ap * (us + vfn);
+    for (int k = 0; k < 3; ++k) c[1 + k] = Ap * (double)nv[k];
+    c[4] = Ap * (us64 + vfn);
   } else {
-    double rf, uf, pf;
-    sample_at_face<M>(G, SL, SR, ps, us, rf, uf, pf);
-    const double *wu = (us >= 0.0) ? wL : wR;
-    const double wun = wu[0] * nv[0] + wu[1] * nv[1] + wu[2] * nv[2];
-    double vfa[3];
+    T rf, uf, pf;
+    sample_at_face<T, M>(G, SL, SR, T(ps64), T(us64), rf, uf, pf);
+    const T *wu = (us64 >= 0.0) ? wL : wR;
+    const T wun = wu[0] * nv[0] + wu[1] * nv[1] + wu[2] * nv[2];
+    T vfa[3];
 #pragma unroll
     for (int k = 0; k < 3; ++k) vfa[k] = uf * nv[k] + (wu[k] - wun * nv[k]);
-    const double v2 = vfa[0] * vfa[0] + vfa[1] * vfa[1] + vfa[2] * vfa[2];
-    const double Fm = rf * uf;
-    double Fp[3];
+    const T v2 = vfa[0] * vfa[0] + vfa[1] * vfa[1] + vfa[2] * vfa[2];
+    const T Fm = rf * uf;
+    T Fp[3];
 #pragma unroll
     for (int k = 0; k < 3; ++k) Fp[k] = Fm * vfa[k] + pf * nv[k];
-    const double FE = uf * (pf * G.inv_gm1 + 0.5 * rf * v2 + pf);
-    const double vf2 = vf[0] * vf[0] + vf[1] * vf[1] + vf[2] * vf[2];
-    c[0] = Am * Fm;
+    const T FE = uf * (pf * G.inv_gm1 + T(0.5) * rf * v2 + pf);
+    const T vf2 = vf[0] * vf[0] + vf[1] * vf[1] + vf[2] * vf[2];
+    const double Amd = (double)Am;
+    c[0] = Amd * (double)Fm;
 #pragma unroll
-    for (int k = 0; k < 3; ++k) c[1 + k] = Am * (Fp[k] + vf[k] * Fm);
-    c[4] = Am * (FE + (vf[0] * Fp[0] + vf[1] * Fp[1] + vf[2] * Fp[2]) + 0.5 * vf2 * Fm);
+    for (int k = 0; k < 3; ++k) c[1 + k] = Amd * (double)(Fp[k] + vf[k] * Fm);
+    c[4] = Amd * (double)(FE + (vf[0] * Fp[0] + vf[1] * Fp[1] + vf[2] * Fp[2]) +
+                          T(0.5) * vf2 * Fm);
   }
 }
 
-template <int SCHEME, int M>
+template <typename T, int SCHEME, int M>
 __global__ void __launch_bounds__(FBS) fluxes_k(FluxArgs a) {
   __shared__ int pref[FBS + 1];
   __shared__ int wsum[FBS / 64];
@@ -382,10 +471,10 @@ __global__ void __launch_bounds__(FBS) fluxes_k(FluxArgs a) {
   const int b0 = blockIdx.x * FBS;
   const int nb = (int)min((int64_t)FBS, n - b0);
   // block exclusive prefix sum of the per-particle face counts
-  int cnt = tid < nb ? a.fcnt[b0 + tid] : 0;
+  const int cnt = tid < nb ? a.fcnt[b0 + tid] : 0;
   int incl = cnt;
   for (int o = 1; o < 64; o <<= 1) {
-    int u = __shfl_up(incl, o, 64);
+    const int u = __shfl_up(incl, o, 64);
     if (lane >= o) incl += u;
   }
   if (lane == 63) wsum[wid] = incl;
@@ -397,13 +486,13 @@ __global__ void __launch_bounds__(FBS) fluxes_k(FluxArgs a) {
   pref[tid] = woff + incl - cnt;
   if (tid == FBS - 1) pref[FBS] = woff + incl;
   __syncthreads();
-  const int T = pref[FBS];
+  const int T_faces = pref[FBS];
   const double dt = a.dt[0];
-  const double hdt = 0.5 * dt;
+  const T hdt = T(0.5 * dt);
   int64_t nfaces = 0, iters_sum = 0, vac = 0, pos = 0, maxit = 0;
-  for (int base = 0; base < T; base += FBS) {
+  for (int base = 0; base < T_faces; base += FBS) {
     const int f = base + tid;
-    const bool active = f < T;
+    const bool active = f < T_faces;
     int p = FBS;  // sentinel key for idle lanes (they sit at the wave's end)
     double c[5] = {0, 0, 0, 0, 0};
     if (active) {
@@ -417,9 +506,11 @@ __global__ void __launch_bounds__(FBS) fluxes_k(FluxArgs a) {
       const int i = b0 + p;
       const int j = a.fslot[list_at(i, f - pref[p], n)];
       const int L = i < j ? i : j, R = i < j ? j : i;
+      FaceIn<T> Ls, Rs;
+      load_side(a, L, Ls);
+      load_side(a, R, Rs);
       int it, fl;
-      face_flux<SCHEME, M>(a.rec + (int64_t)L * R_STRIDE, a.rec + (int64_t)R * R_STRIDE, a,
-                              hdt, c, it, fl);
+      face_flux<T, SCHEME, M>(Ls, Rs, a, hdt, c, it, fl);
       const double sgn = (i == L) ? -1.0 : 1.0;  // the left side loses c
 #pragma unroll
       for (int q = 0; q < 5; ++q) c[q] *= sgn;
@@ -466,14 +557,37 @@ __global__ void __launch_bounds__(FBS) fluxes_k(FluxArgs a) {
   count_add(a.counters + C_RIEMANN_MAXIT, maxit);
 }
 
-template <int SCHEME>
-void launch_scheme(const FluxArgs &a, int nb, hipStream_t st) {
-  if (a.G.m == 5)
-    fluxes_k<SCHEME, 5><<<nb, FBS, 0, st>>>(a);
-  else if (a.G.m == 7)
-    fluxes_k<SCHEME, 7><<<nb, FBS, 0, st>>>(a);
+template <typename T, int SCHEME>
+void launch_m(const FluxArgs &a, int m, int nb, hipStream_t st) {
+  if (m == 5)
+    fluxes_k<T, SCHEME, 5><<<nb, FBS, 0, st>>>(a);
+  else if (m == 7)
+    fluxes_k<T, SCHEME, 7><<<nb, FBS, 0, st>>>(a);
   else
-    fluxes_k<SCHEME, 0><<<nb, FBS, 0, st>>>(a);
+    fluxes_k<T, SCHEME, 0><<<nb, FBS, 0, st>>>(a);
+}
+
+template <typename T>
+void launch_t(const FluxArgs &a, int scheme, int m, int nb, hipStream_t st) {
+  if (scheme == MFM_SCHEME_MFM)
+    launch_m<T, MFM_SCHEME_MFM>(a, m, nb, st);
+  else
+    launch_m<T, MFM_SCHEME_MFV>(a, m, nb, st);
+}
+
+template <typename T>
+Gas<T> make_gas(double g) {
+  Gas<T> G;
+  G.gamma = T(g);
+  G.g1 = T((g - 1.0) / (2.0 * g));
+  G.g2 = T((g + 1.0) / (2.0 * g));
+  G.g3 = T(2.0 * g / (g - 1.0));
+  G.g4 = T(2.0 / (g - 1.0));
+  G.g5 = T(2.0 / (g + 1.0));
+  G.g6 = T((g - 1.0) / (g + 1.0));
+  G.g7 = T(0.5 * (g - 1.0));
+  G.inv_gm1 = T(1.0 / (g - 1.0));
+  return G;
 }
 
 }  // namespace
@@ -482,6 +596,7 @@ hipError_t launch_fluxes(mfm_ctx *ctx, const mfm_particles *pp, const double *dt
   FluxArgs a;
   a.n = pp->n;
   a.rec = ctx->rec;
+  a.pos = reinterpret_cast<const double4 *>(ctx->pos4);
   a.fslot = ctx->fslot;
   a.fcnt = ctx->fcnt;
   a.dt = dt_dev;
@@ -491,29 +606,23 @@ hipError_t launch_fluxes(mfm_ctx *ctx, const mfm_particles *pp, const double *dt
     a.half[k] = 0.5 * ctx->p.box[k];
   }
   const double g = ctx->p.gamma;
-  a.G.gamma = g;
-  a.G.g1 = (g - 1.0) / (2.0 * g);
-  a.G.g2 = (g + 1.0) / (2.0 * g);
-  a.G.g3 = 2.0 * g / (g - 1.0);
-  a.G.g4 = 2.0 / (g - 1.0);
-  a.G.g5 = 2.0 / (g + 1.0);
-  a.G.g6 = (g - 1.0) / (g + 1.0);
-  a.G.g7 = 0.5 * (g - 1.0);
-  a.G.inv_gm1 = 1.0 / (g - 1.0);
+  a.G = make_gas<double>(g);
+  a.Gf = make_gas<float>(g);
   // root path when 1/g1 = 2 gamma / (gamma - 1) is an integer m (gamma = m/(m-2))
-  const double mm = a.G.g3;
+  const double mm = 2.0 * g / (g - 1.0);
   const int mi = (int)(mm + 0.5);
-  a.G.m = (mi >= 3 && mi <= 16 && fabs(mm - mi) < 1e-12 * mm) ? mi : 0;
+  const int m = (mi >= 3 && mi <= 16 && fabs(mm - mi) < 1e-12 * mm) ? mi : 0;
   a.psi1 = ctx->p.psi1;
   a.psi2 = ctx->p.psi2;
   a.rtol = ctx->p.riemann_tol;
+  a.rtol_f = 1e-6f;  // FP32 Newton tolerance of the mixed path (the FP64 check follows)
   a.rmaxit = ctx->p.riemann_maxit;
   a.limiter = ctx->p.limiter;
   a.counters = ctx->counters;
   const int nb = blocks_for(pp->n, FBS);
-  if (ctx->p.scheme == MFM_SCHEME_MFM)
-    launch_scheme<MFM_SCHEME_MFM>(a, nb, ctx->stream);
+  if (ctx->p.precision == MFM_MIXED)
+    launch_t<float>(a, ctx->p.scheme, m, nb, ctx->stream);
   else
-    launch_scheme<MFM_SCHEME_MFV>(a, nb, ctx->stream);
+    launch_t<double>(a, ctx->p.scheme, m, nb, ctx->stream);
   return hipGetLastError();
 }

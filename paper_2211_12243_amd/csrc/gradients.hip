@@ -2,14 +2,20 @@
 // (Lanson-Vila) gradients with the conditioned slope limiter (sec. 2.3.3 and
 // 2.3.6) and the CFL time step (sec. 2.3.10), then the global minimum step.
 //
-// One lane per particle over its candidate list.  Each
-// neighbour (r < H_i) is gathered as one 128-byte record written by the
-// density loop.  Pass one accumulates E_i, the five gradient sums, the
-// neighbour extrema and the signal velocity, and records the faces this
-// particle will evaluate in the flux loop; B_i = E_i^-1 is the FP64 cofactor
-// inverse; pass two finds the extreme face extrapolations for the limiter.
-// The particle's flux record (positions, 1/H, V, primitives, 1/rho, B,
-// limited gradients: 256 bytes) is written packed.
+// One lane per particle over its candidate list.  Each neighbour (r < H_i)
+// is gathered as one 128-byte record written by the density loop.  Pass one
+// accumulates E_i, the five gradient sums, the neighbour extrema and the
+// signal velocity, and records the faces this particle will evaluate in the
+// flux loop; B_i = E_i^-1 is the cofactor inverse; pass two finds the extreme
+// face extrapolations for the limiter.  The particle's flux record is written
+// packed: 256 bytes in FP64 (positions included), 128 bytes in the mixed
+// path (FP32; positions stay FP64 in the separate position array).
+//
+// Precision.  T = double is the FP64 path.  T = float is the mixed path: the
+// separation is formed in FP64 and rounded, every pair term and sum is FP32;
+// an E_i whose FP32 condition number exceeds MIXED_FP64_NCOND is inverted
+// in FP64 (and the gradients formed with that inverse), as are the outputs
+// kept in FP64 arrays.
 #include "mfm_internal.h"
 
 namespace {
@@ -17,6 +23,7 @@ namespace {
 constexpr int BS = 256;
 constexpr int RED_BLOCKS = 1024;
 constexpr double PI = 3.14159265358979323846;
+constexpr float MIXED_FP64_NCOND = 10.0f;
 
 struct GradArgs {
   int64_t n;
@@ -33,26 +40,70 @@ struct GradArgs {
   int64_t *counters;
 };
 
+template <typename T>
+__device__ __forceinline__ T spline_wt(T q) {
+  if (q < T(0.5)) return T(1) + q * q * (T(6) * q - T(6));
+  if (q < T(1)) {
+    const T t = T(1) - q;
+    return T(2) * t * t * t;
+  }
+  return T(0);
+}
+
+// Inverse of a symmetric 3x3 (xx,xy,xz,yy,yz,zz) by cofactors; returns the determinant.
+template <typename T>
+__device__ __forceinline__ T sym_inv(const T e[6], T b[6]) {
+  T cf[6];
+  cf[0] = e[3] * e[5] - e[4] * e[4];
+  cf[1] = e[2] * e[4] - e[1] * e[5];
+  cf[2] = e[1] * e[4] - e[2] * e[3];
+  cf[3] = e[0] * e[5] - e[2] * e[2];
+  cf[4] = e[1] * e[2] - e[0] * e[4];
+  cf[5] = e[0] * e[3] - e[1] * e[1];
+  const T det = e[0] * cf[0] + e[1] * cf[1] + e[2] * cf[2];
+#pragma unroll
+  for (int k = 0; k < 6; ++k) b[k] = cf[k] / det;
+  return det;
+}
+
+template <typename T>
+__device__ __forceinline__ T sym_frob(const T a[6]) {
+  return sqrt(a[0] * a[0] + a[3] * a[3] + a[5] * a[5] +
+              T(2) * (a[1] * a[1] + a[2] * a[2] + a[4] * a[4]));
+}
+
+template <typename T>
+__device__ __forceinline__ void sym_apply(const T b[6], const T s[3], T g[3]) {
+  g[0] = b[0] * s[0] + b[1] * s[1] + b[2] * s[2];
+  g[1] = b[1] * s[0] + b[3] * s[1] + b[4] * s[2];
+  g[2] = b[2] * s[0] + b[4] * s[1] + b[5] * s[2];
+}
+
+template <typename T>
 __global__ void __launch_bounds__(BS) gradients_k(GradArgs a) {
   const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   const int64_t n = a.n;
-  int64_t pairs = 0, singular = 0;
+  int64_t pairs = 0, singular = 0, inv64 = 0;
   if (i < n) {
     const double *gi = a.gin + i * GIN_STRIDE;
     const double xi = gi[GIN_X], yi = gi[GIN_Y], zi = gi[GIN_Z], hi = gi[GIN_H];
-    const double h2 = hi * hi, ih = 1.0 / hi, wnorm = 8.0 / (PI * hi * h2);
-    const double qi[5] = {gi[GIN_RHO], gi[GIN_VX], gi[GIN_VY], gi[GIN_VZ], gi[GIN_P]};
-    const double ci = gi[GIN_C];
+    const double h2 = hi * hi;
+    const T ih = T(1.0 / hi), wnorm = T(8.0 / (PI * hi * h2));
+    // the primitives stay FP64 so that differences and extrema are exact before
+    // the FP32 pair arithmetic of the mixed path
+    const double q64[5] = {gi[GIN_RHO], gi[GIN_VX], gi[GIN_VY], gi[GIN_VZ], gi[GIN_P]};
+    const T qi[5] = {T(q64[0]), T(q64[1]), T(q64[2]), T(q64[3]), T(q64[4])};
+    const T ci = T(gi[GIN_C]);
     const int b0 = (int)(i / FLUX_BLOCK) * FLUX_BLOCK;
-    double e[6] = {0, 0, 0, 0, 0, 0};
-    double s[5][3];
+    T e[6] = {0, 0, 0, 0, 0, 0};
+    T s[5][3];
     double qmax[5], qmin[5];
 #pragma unroll
     for (int q = 0; q < 5; ++q) {
-      s[q][0] = s[q][1] = s[q][2] = 0.0;
-      qmax[q] = qmin[q] = qi[q];
+      s[q][0] = s[q][1] = s[q][2] = T(0);
+      qmax[q] = qmin[q] = q64[q];
     }
-    double vsig = 0.0;
+    T vsig = T(0);
     int nf = 0;
     const int cnt = a.cand_cnt[i];
     for (int k = 0; k < cnt; ++k) {
@@ -71,11 +122,11 @@ __global__ void __launch_bounds__(BS) gradients_k(GradArgs a) {
       const double *gj = a.gin + (int64_t)j * GIN_STRIDE;
       ++pairs;
       if (r2 == 0.0) continue;
-      const double d0 = min_image(gj[GIN_X] - xi, a.box[0], a.half[0]);
-      const double d1 = min_image(gj[GIN_Y] - yi, a.box[1], a.half[1]);
-      const double d2 = min_image(gj[GIN_Z] - zi, a.box[2], a.half[2]);
-      const double r = sqrt(r2);
-      const double wv = gj[GIN_V] * wnorm * spline_w(r * ih);
+      const T d0 = T(min_image(gj[GIN_X] - xi, a.box[0], a.half[0]));
+      const T d1 = T(min_image(gj[GIN_Y] - yi, a.box[1], a.half[1]));
+      const T d2 = T(min_image(gj[GIN_Z] - zi, a.box[2], a.half[2]));
+      const T r = T(sqrt(r2));
+      const T wv = T(gj[GIN_V]) * wnorm * spline_wt<T>(r * ih);
       e[0] += wv * d0 * d0;
       e[1] += wv * d0 * d1;
       e[2] += wv * d0 * d2;
@@ -83,9 +134,11 @@ __global__ void __launch_bounds__(BS) gradients_k(GradArgs a) {
       e[4] += wv * d1 * d2;
       e[5] += wv * d2 * d2;
       const double qj[5] = {gj[GIN_RHO], gj[GIN_VX], gj[GIN_VY], gj[GIN_VZ], gj[GIN_P]};
+      T dq[5];
 #pragma unroll
       for (int q = 0; q < 5; ++q) {
-        const double df = wv * (qj[q] - qi[q]);
+        dq[q] = T(qj[q] - q64[q]);
+        const T df = wv * dq[q];
         s[q][0] += df * d0;
         s[q][1] += df * d1;
         s[q][2] += df * d2;
@@ -93,95 +146,121 @@ __global__ void __launch_bounds__(BS) gradients_k(GradArgs a) {
         qmin[q] = fmin(qmin[q], qj[q]);
       }
       // signal velocity: x_i - x_j = -d
-      const double proj =
-          -(d0 * (qi[1] - qj[1]) + d1 * (qi[2] - qj[2]) + d2 * (qi[3] - qj[3])) / r;
-      vsig = fmax(vsig, ci + gj[GIN_C] - fmin(0.0, proj));
+      const T proj = (d0 * dq[1] + d1 * dq[2] + d2 * dq[3]) / r;
+      vsig = fmax(vsig, ci + T(gj[GIN_C]) - fmin(T(0), proj));
     }
-    // B = E^-1 by cofactors
-    double cf[6];
-    cf[0] = e[3] * e[5] - e[4] * e[4];
-    cf[1] = e[2] * e[4] - e[1] * e[5];
-    cf[2] = e[1] * e[4] - e[2] * e[3];
-    cf[3] = e[0] * e[5] - e[2] * e[2];
-    cf[4] = e[1] * e[2] - e[0] * e[4];
-    cf[5] = e[0] * e[3] - e[1] * e[1];
-    const double det = e[0] * cf[0] + e[1] * cf[1] + e[2] * cf[2];
-    if (!(det != 0.0) || !isfinite(det)) ++singular;
-    double b[6];
+    T b[6];
+    T det = sym_inv<T>(e, b);
+    T nc = sym_frob<T>(b) * sym_frob<T>(e) / T(3);
+    T g[5][3];
+    double b64[6];
+    if (sizeof(T) == sizeof(float) && !(nc <= T(MIXED_FP64_NCOND))) {
+      // ill-conditioned E in the mixed path: invert it in FP64
+      double e64[6];
 #pragma unroll
-    for (int k = 0; k < 6; ++k) b[k] = cf[k] / det;
-    double g[5][3];
+      for (int k = 0; k < 6; ++k) e64[k] = (double)e[k];
+      const double det64 = sym_inv<double>(e64, b64);
+      det = T(det64);
+      nc = T(sym_frob<double>(b64) * sym_frob<double>(e64) / 3.0);
 #pragma unroll
-    for (int q = 0; q < 5; ++q) {
-      g[q][0] = b[0] * s[q][0] + b[1] * s[q][1] + b[2] * s[q][2];
-      g[q][1] = b[1] * s[q][0] + b[3] * s[q][1] + b[4] * s[q][2];
-      g[q][2] = b[2] * s[q][0] + b[4] * s[q][1] + b[5] * s[q][2];
+      for (int q = 0; q < 5; ++q) {
+        double s64[3] = {(double)s[q][0], (double)s[q][1], (double)s[q][2]}, g64[3];
+        sym_apply<double>(b64, s64, g64);
+        g[q][0] = T(g64[0]);
+        g[q][1] = T(g64[1]);
+        g[q][2] = T(g64[2]);
+      }
+      ++inv64;
+    } else {
+#pragma unroll
+      for (int q = 0; q < 5; ++q) sym_apply<T>(b, s[q], g[q]);
+#pragma unroll
+      for (int k = 0; k < 6; ++k) b64[k] = (double)b[k];
     }
-    const double nb = sqrt(b[0] * b[0] + b[3] * b[3] + b[5] * b[5] +
-                           2.0 * (b[1] * b[1] + b[2] * b[2] + b[4] * b[4]));
-    const double ne = sqrt(e[0] * e[0] + e[3] * e[3] + e[5] * e[5] +
-                           2.0 * (e[1] * e[1] + e[2] * e[2] + e[4] * e[4]));
-    const double nc = nb * ne / 3.0;
-    double alpha[5] = {1.0, 1.0, 1.0, 1.0, 1.0};
+    if (!(det != T(0)) || !isfinite(det)) ++singular;
+    T alpha[5] = {T(1), T(1), T(1), T(1), T(1)};
     if (a.limiter & MFM_LIMIT_BJ) {
-      double dmax[5] = {0, 0, 0, 0, 0}, dmin[5] = {0, 0, 0, 0, 0};
+      T dmax[5] = {0, 0, 0, 0, 0}, dmin[5] = {0, 0, 0, 0, 0};
       for (int k = 0; k < cnt; ++k) {
         const int64_t at = list_at(i, k, n);
         const double r2 = a.cand_r2[at];
         if (!(r2 < h2)) continue;
         const double4 pj = a.pos[a.cand[at]];
-        const double d0 = min_image(pj.x - xi, a.box[0], a.half[0]);
-        const double d1 = min_image(pj.y - yi, a.box[1], a.half[1]);
-        const double d2 = min_image(pj.z - zi, a.box[2], a.half[2]);
+        const T d0 = T(min_image(pj.x - xi, a.box[0], a.half[0]));
+        const T d1 = T(min_image(pj.y - yi, a.box[1], a.half[1]));
+        const T d2 = T(min_image(pj.z - zi, a.box[2], a.half[2]));
 #pragma unroll
         for (int q = 0; q < 5; ++q) {
-          const double ex = 0.5 * (g[q][0] * d0 + g[q][1] * d1 + g[q][2] * d2);
+          const T ex = T(0.5) * (g[q][0] * d0 + g[q][1] * d1 + g[q][2] * d2);
           dmax[q] = fmax(dmax[q], ex);
           dmin[q] = fmin(dmin[q], ex);
         }
       }
-      double t = (a.ncond_max - nc) / (a.ncond_max - 1.0);
-      t = t > 0.0 ? (t < 1.0 ? t : 1.0) : 0.0;
-      const double beta = 1.0 + t;
+      T t = (T(a.ncond_max) - nc) / (T(a.ncond_max) - T(1));
+      t = t > T(0) ? (t < T(1) ? t : T(1)) : T(0);
+      const T beta = T(1) + t;
 #pragma unroll
       for (int q = 0; q < 5; ++q) {
-        double rp = __builtin_huge_val(), rm = __builtin_huge_val();
-        if (dmax[q] > 0.0) rp = (qmax[q] - qi[q]) / dmax[q];
-        if (dmin[q] < 0.0) rm = (qi[q] - qmin[q]) / (-dmin[q]);
-        alpha[q] = fmin(1.0, beta * fmin(rp, rm));
+        T rp = T(__builtin_huge_val()), rm = T(__builtin_huge_val());
+        if (dmax[q] > T(0)) rp = T(qmax[q] - q64[q]) / dmax[q];
+        if (dmin[q] < T(0)) rm = T(q64[q] - qmin[q]) / (-dmin[q]);
+        alpha[q] = fmin(T(1), beta * fmin(rp, rm));
       }
     }
-    double *rec = a.rec + i * R_STRIDE;
-    rec[R_X] = xi;
-    rec[R_Y] = yi;
-    rec[R_Z] = zi;
-    rec[R_IH] = ih;
-    rec[R_V] = gi[GIN_V];
-    rec[R_RHO] = qi[0];
-    rec[R_IRHO] = 1.0 / qi[0];
-    rec[R_VX] = qi[1];
-    rec[R_VY] = qi[2];
-    rec[R_VZ] = qi[3];
-    rec[R_P] = qi[4];
 #pragma unroll
-    for (int k = 0; k < 6; ++k) {
-      a.B[k * n + i] = b[k];
-      rec[R_B + k] = b[k];
+    for (int k = 0; k < 6; ++k) a.B[k * n + i] = b64[k];
+    if (sizeof(T) == sizeof(double)) {
+      double *rec = a.rec + i * R_STRIDE;
+      rec[R_X] = xi;
+      rec[R_Y] = yi;
+      rec[R_Z] = zi;
+      rec[R_IH] = (double)ih;
+      rec[R_V] = gi[GIN_V];
+      rec[R_RHO] = q64[0];
+      rec[R_IRHO] = 1.0 / q64[0];
+      rec[R_VX] = q64[1];
+      rec[R_VY] = q64[2];
+      rec[R_VZ] = q64[3];
+      rec[R_P] = q64[4];
+#pragma unroll
+      for (int k = 0; k < 6; ++k) rec[R_B + k] = b64[k];
+#pragma unroll
+      for (int q = 0; q < 5; ++q)
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+          const double v = (double)(alpha[q] * g[q][k]);
+          a.grad[(3 * q + k) * n + i] = v;
+          rec[R_G + 3 * q + k] = v;
+        }
+    } else {
+      float *rec = reinterpret_cast<float *>(a.rec) + i * F_STRIDE;
+      rec[F_IH] = (float)ih;
+      rec[F_V] = (float)gi[GIN_V];
+      rec[F_RHO] = (float)qi[0];
+      rec[F_IRHO] = (float)(1.0 / q64[0]);
+      rec[F_VX] = (float)qi[1];
+      rec[F_VY] = (float)qi[2];
+      rec[F_VZ] = (float)qi[3];
+      rec[F_P] = (float)qi[4];
+#pragma unroll
+      for (int k = 0; k < 6; ++k) rec[F_B + k] = (float)b64[k];
+#pragma unroll
+      for (int q = 0; q < 5; ++q)
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+          const float v = (float)(alpha[q] * g[q][k]);
+          a.grad[(3 * q + k) * n + i] = (double)v;
+          rec[F_G + 3 * q + k] = v;
+        }
+      rec[F_STRIDE - 3] = rec[F_STRIDE - 2] = rec[F_STRIDE - 1] = 0.0f;
     }
-#pragma unroll
-    for (int q = 0; q < 5; ++q)
-#pragma unroll
-      for (int k = 0; k < 3; ++k) {
-        const double v = alpha[q] * g[q][k];
-        a.grad[(3 * q + k) * n + i] = v;
-        rec[R_G + 3 * q + k] = v;
-      }
-    a.ncond[i] = nc;
-    a.dt_i[i] = vsig > 0.0 ? a.c_cfl * hi / vsig : __builtin_huge_val();
+    a.ncond[i] = (double)nc;
+    a.dt_i[i] = vsig > T(0) ? a.c_cfl * hi / (double)vsig : __builtin_huge_val();
     a.fcnt[i] = nf;
   }
   count_add(a.counters + C_GRAD_PAIRS, pairs);
   count_add(a.counters + C_SINGULAR_E, singular);
+  count_add(a.counters + C_FP64_INVERSE, inv64);
 }
 
 __global__ void min_partial_k(const double *__restrict__ v, int64_t n, double *partial) {
@@ -239,7 +318,10 @@ hipError_t launch_gradients(mfm_ctx *ctx, const mfm_particles *pp, double dt_max
   a.c_cfl = ctx->p.c_cfl;
   a.limiter = ctx->p.limiter;
   a.counters = ctx->counters;
-  gradients_k<<<blocks_for(pp->n, BS), BS, 0, ctx->stream>>>(a);
+  if (ctx->p.precision == MFM_MIXED)
+    gradients_k<float><<<blocks_for(pp->n, BS), BS, 0, ctx->stream>>>(a);
+  else
+    gradients_k<double><<<blocks_for(pp->n, BS), BS, 0, ctx->stream>>>(a);
   min_partial_k<<<RED_BLOCKS, BS, 0, ctx->stream>>>(pp->dt_i, pp->n, ctx->red);
   dt_final_k<<<1, BS, 0, ctx->stream>>>(ctx->red, RED_BLOCKS, dt_max, dt_dev, ctx->counters);
   return hipGetLastError();

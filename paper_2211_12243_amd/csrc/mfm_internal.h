@@ -56,6 +56,15 @@ enum {
   R_STRIDE = 32
 };
 
+// The mixed path's FP32 flux record (one 128-byte line; positions stay FP64
+// in the position array).
+enum {
+  F_IH = 0, F_V = 1, F_RHO = 2, F_IRHO = 3, F_VX = 4, F_VY = 5, F_VZ = 6, F_P = 7,
+  F_B = 8,      // 6 entries of B
+  F_G = 14,     // 15 entries of the limited gradients
+  F_STRIDE = 32
+};
+
 // Geometry of the cell grid, passed by value to kernels.
 struct CellGrid {
   int nc[3];          // cells per axis (>= 3)

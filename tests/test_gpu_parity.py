@@ -18,101 +18,11 @@ torch = pytest.importorskip("torch")
 
 pytestmark = pytest.mark.gpu
 
-import oracle  # noqa: E402
+from gpu_helpers import check_fields, run_both, _need_gpu  # noqa: E402
 from paper_2211_12243_amd import mfm  # noqa: E402
 from paper_2211_12243_amd import workloads as W  # noqa: E402
 
 TOL64 = 1e-12
-
-
-def _need_gpu():
-    if not torch.cuda.is_available():
-        pytest.skip("no HIP device")
-
-
-def run_both(cfg, st, dt_max=1.0, precision="fp64"):
-    _need_gpu()
-    n = len(st["x"])
-    params = mfm.params_from_dict(cfg, precision=precision)
-    ctx = mfm.Context(params, n)
-    ps = mfm.ParticleSet(st)
-    print(f"[parity] n={n} cfg={cfg} precision={precision}", flush=True)
-    mfm.mfm_reset_counters(ctx)
-    dt = mfm.run_pipeline(ctx, ps, dt_max, update=False)
-    torch.cuda.synchronize()
-    diag = mfm.mfm_diagnostics(ctx)
-    ids = ps["id"].cpu().numpy()
-    gpu = {}
-    for k in ("H", "V", "rho", "P", "c", "ncond", "dt_i"):
-        a = np.empty(n)
-        a[ids] = ps[k].cpu().numpy()
-        gpu[k] = a
-    for k in ("B", "grad", "dQ"):
-        t = ps[k].cpu().numpy()
-        a = np.empty_like(t)
-        a[:, ids] = t
-        gpu[k] = a
-    mfm.mfm_update(ctx, ps)
-    torch.cuda.synchronize()
-    new = {}
-    for k in ("x", "y", "z", "vx", "vy", "vz", "m", "E", "U"):
-        a = np.empty(n)
-        a[ids] = ps[k].cpu().numpy()
-        new[k] = a
-    ref = oracle.pipeline(cfg, st, dt_max)
-    ctx.close()
-    return gpu, new, dt, diag, ref
-
-
-def rel_err(a, b):
-    den = np.abs(b).max()
-    return np.abs(a - b).max() / den if den > 0 else np.abs(a - b).max()
-
-
-def check_fields(gpu, new, dt, diag, ref, tol, st):
-    d, g, f = ref["density"], ref["gradients"], ref["fluxes"]
-    errs = {
-        "H": rel_err(gpu["H"], d["H"]),
-        "V": rel_err(gpu["V"], d["V"]),
-        "rho": rel_err(gpu["rho"], g["rho"]),
-        "P": rel_err(gpu["P"], g["P"]),
-        "c": rel_err(gpu["c"], g["c"]),
-        "ncond": rel_err(gpu["ncond"], g["ncond"]),
-        "dt_i": rel_err(gpu["dt_i"], g["dt_i"]),
-        "B": max(rel_err(gpu["B"][k], g["B"][k]) for k in range(6)),
-        "grad": max(rel_err(gpu["grad"][k], g["grad"][k]) for k in range(15)),
-        "dt": abs(dt - ref["dt"]) / ref["dt"],
-    }
-    s = f["scale"]
-    dq = 0.0
-    for k in range(5):
-        mask = s[k] > 0
-        if mask.any():
-            dq = max(dq, (np.abs(gpu["dQ"][k] - f["dQ"][k])[mask] / s[k][mask]).max())
-        assert np.all(gpu["dQ"][k][~mask] == 0.0)
-    errs["dQ"] = dq
-    if dq > tol:
-        for k in range(5):
-            mask = s[k] > 0
-            r = np.zeros(len(s[k]))
-            r[mask] = np.abs(gpu["dQ"][k] - f["dQ"][k])[mask] / s[k][mask]
-            worst = np.argsort(r)[-3:]
-            print("dQ", k, [(int(i), f"{r[i]:.2e}", f"{s[k][i]:.2e}", f"{f['dQ'][k][i]:.3e}",
-                             f"{d['H'][i]:.6f}", f"{g['P'][i]:.2e}") for i in worst], flush=True)
-    for k in ("x", "y", "z"):
-        dx = np.abs(new[k] - ref["state"][k])
-        dx = np.minimum(dx, 1.0 - dx)
-        errs["pos_" + k] = dx.max()
-    for k in ("vx", "vy", "vz", "m", "E", "U"):
-        errs[k] = rel_err(new[k], ref["state"][k])
-    print({k: f"{v:.2e}" for k, v in errs.items()}, flush=True)
-    bad = {k: v for k, v in errs.items() if not (v <= tol)}
-    assert not bad, bad
-    # exact integer results
-    assert diag["h_noconv"] == 0 and ref["counters"]["h_noconv"] == 0
-    assert diag["grad_pairs"] == ref["counters"]["grad_pairs"]
-    assert diag["faces"] == ref["counters"]["faces"]
-    return errs
 
 
 CASES = [
@@ -124,6 +34,9 @@ CASES = [
     ("sedov24_mfv", lambda: W.sedov(n=24, seed=3), {"scheme": "mfv"}),
     ("random3000_mfv", lambda: W.random_gas(N=3000, seed=4), {"scheme": "mfv", "max_list": 512}),
     ("ragged_4099_mfm", lambda: W.random_gas(N=4099, seed=5), {"scheme": "mfm", "max_list": 512}),
+    # gamma 7/5 takes the m = 7 root path, gamma 1.3 the generic pow() path
+    ("sod_gamma14_mfv", lambda: W.sod(n=16, seed=6, gamma=1.4), {"scheme": "mfv", "gamma": 1.4}),
+    ("kh16_gamma13_mfv", lambda: W.kh(n=16, seed=7, gamma=1.3), {"scheme": "mfv", "gamma": 1.3}),
 ]
 
 
