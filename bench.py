@@ -31,7 +31,10 @@ sys.path.insert(0, ROOT)
 
 # Algorithmic FP64 operations per face of the flux loop (add, sub, mul, div,
 # sqrt and pow count 1, a fused multiply-add 2; comparisons and selects 0).
-# Counted term by term in DESIGN.md ("flux loop operation count").
+# The count runs over the stages of one face: separation and kernel weights,
+# A_ij, half-step prediction and extrapolation, pairwise limiter, face-frame
+# states, Riemann set-up, sampling (MFV) and flux assembly, accumulation; each
+# Newton iteration of the Riemann solve adds FLOPS_NEWTON_ITER.
 FLOPS_FACE = {"mfm": 388, "mfv": 458}
 FLOPS_NEWTON_ITER = 30
 PEAK_FP64_TFLOPS = 78.6
@@ -89,8 +92,8 @@ def cpu_baseline(st, scheme):
 def main():
     args = parse()
     if args.gpus != 1:
-        print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported by this build "
-              "(the multi-GPU layout is described in DESIGN.md but not implemented)",
+        print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported: the library "
+              "runs on a single GPU and has no multi-GPU path",
               file=sys.stderr)
         sys.exit(2)
     import numpy as np

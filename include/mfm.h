@@ -84,7 +84,7 @@ typedef struct mfm_params {
   double alpha1;         /* dual-energy switch: U > alpha1 E_kin -> U from E (default 0.01) */
   double box[3];         /* periodic box sides; all > 0 (the library needs a periodic box) */
   double cell_margin;    /* cell side >= cell_margin * max_i H_i (>= 1, default 1.15) */
-  int32_t max_cell_dim;  /* cells per axis at most (default 256, at most 1024) */
+  int32_t max_cell_dim;  /* cells per axis at most (3..512, default 256) */
   int32_t pad0;
 } mfm_params;
 
@@ -207,6 +207,86 @@ int mfm_kernel_times(struct mfm_ctx *ctx, double *ms_out, int64_t *count_out);
 
 const char *mfm_strerror(int status);
 const char *mfm_last_error(struct mfm_ctx *ctx);
+
+/* ------------------------------------------------------------------------
+ * Learned starting value of the exact Riemann iteration (sec. 2.3.6 uses the
+ * exact solver; the guess only changes how many Newton steps it takes).
+ *
+ * The network maps six dimensionless features of a face's left and right
+ * states in the face frame -- ln(rho_L/rho_R), ln(P_L/P_R),
+ * slog((u_R-u_L)/c_avg), slog(u_L/c_L), slog(u_R/c_R), ln(c_L/c_R) with
+ * slog(v) = sign(v) ln(1+|v|) -- to y = ln(p* / P_avg), P_avg = (P_L+P_R)/2.
+ * Architecture: 6 -> 64 -> 64 -> 64 -> 1, SiLU hidden activations, BF16
+ * operands with FP32 accumulation on the matrix cores.  The FP32 parameter
+ * vector (mfm_mlp_param_count floats) is, in order: W1 [16][64] (row k is
+ * input feature k; rows 6..15 are padding and must be zero), b1 [64],
+ * W2 [64][64], b2 [64], W3 [64][64], b3 [64], w4 [64], b4 [1]; a layer
+ * computes a_out[n] = silu(b[n] + sum_k a_in[k] W[k][n]).  Inputs are
+ * standardised with norm[0..5] (means) and norm[6..11] (standard deviations,
+ * > 0); the output is y = norm[12] + norm[13] * net(x) (norm[13] > 0);
+ * norm[14..15] are unused.
+ *
+ * In the flux loop (params.guess = MFM_GUESS_LEARNED), the Newton iteration
+ * starts from the prediction P_avg e^y when that is finite and above the
+ * pressure floor; if its second residual exceeds its first, or it needs more
+ * than 8 steps, the face is solved again from the plain guess and
+ * guess_fallback counts it (riemann_iters counts the steps of both tries).
+ * Results therefore agree with the plain guess to the solver's tolerance
+ * whatever the weights are.
+ *
+ * A state is caller-owned device memory of mfm_mlp_state_bytes bytes
+ * (256-byte aligned) holding the FP32 parameters, Adam moments, gradient,
+ * normalisation and BF16 weight copies.  Calls on one state are ordered by
+ * the stream they are given; stream may be null (the default stream).
+ * ------------------------------------------------------------------------ */
+size_t mfm_mlp_state_bytes(void);
+int mfm_mlp_param_count(void);
+
+/* Load parameters and normalisation (host arrays of mfm_mlp_param_count and
+ * 16 floats) and clear the Adam moments.  Synchronises. */
+int mfm_mlp_init(void *state_dev, const float *params_host, const float *norm_host, void *stream);
+
+/* Gradient of the mean squared error, in standardised units,
+ * L = (1/n) sum_r (net(x_r) - (t_r - norm[12]) / norm[13])^2 over n rows of a
+ * device array (row r: features at [r*stride + 0..5], target t_r at
+ * [r*stride + 6]; the face dump's layout, stride 8).  Overwrites the stored
+ * gradient; loss_host (optional) receives L (then synchronises). */
+int mfm_mlp_backward(void *state_dev, const float *rows_dev, int64_t n, int64_t stride,
+                     float *loss_host, void *stream);
+
+/* One Adam step (beta1 0.9, beta2 0.999, eps 1e-8; step counts from 1) on the
+ * stored gradient, then the BF16 weight copies are refreshed. */
+int mfm_mlp_adam(void *state_dev, float lr, int step, void *stream);
+
+/* mfm_mlp_backward then mfm_mlp_adam; loss_host (optional) receives the
+ * loss before the step (then synchronises). */
+int mfm_mlp_train_step(void *state_dev, const float *rows_dev, int64_t n, int64_t stride,
+                       float lr, int step, float *loss_host, void *stream);
+
+/* y_dev[r] = predicted ln(p* / P_avg) for n rows laid out as in
+ * mfm_mlp_backward (the target column is not read). */
+int mfm_mlp_predict(const void *state_dev, const float *rows_dev, int64_t n, int64_t stride,
+                    float *y_dev, void *stream);
+
+/* Copy the FP32 parameters and/or the last gradient to the host (either may
+ * be null).  Synchronises. */
+int mfm_mlp_get(const void *state_dev, float *params_host, float *grad_host, void *stream);
+
+/* Use the network in state_dev (null detaches) for the context's learned
+ * guess.  The state must stay valid while mfm_fluxes may run; mfm_fluxes
+ * returns MFM_E_STATE when the learned guess is selected and none is
+ * attached. */
+int mfm_mlp_attach(struct mfm_ctx *ctx, const void *state_dev);
+
+/* Training data: while armed, every face the flux loop solves appends one
+ * record of 8 floats to records_dev -- the six features, the target
+ * ln(p* / P_avg) of the converged solution, and the number of Newton steps the
+ * plain guess needed -- until capacity records are stored (further faces are
+ * counted but not written).  Records are in no particular order.  Arming
+ * (records_dev non-null) or disarming (null) resets the count.  Synchronises. */
+int mfm_face_dump(struct mfm_ctx *ctx, float *records_dev, int64_t capacity);
+/* Records stored since arming (at most the capacity).  Synchronises. */
+int mfm_face_dump_count(struct mfm_ctx *ctx, int64_t *count_host);
 
 #ifdef __cplusplus
 }

@@ -28,11 +28,24 @@
 // m = 7 (gamma 7/5), that root is an FP32 seed polished by two FP64 Newton
 // steps on y^m = x (quadratic: 1e-7 -> 1e-14 -> roundoff); in FP32 it is the
 // hardware exp2/log2.  Other gammas call pow().
+//
+// Learned guess (LEARNED = true).  After the face states are reconstructed,
+// each wavefront evaluates the guess network (mlp_device.h) on its 64 faces
+// with BF16 MFMA and starts Newton from P_avg exp(y).  The exact iteration
+// always finishes the solve; a guess that is not finite and positive, whose
+// first Newton step increases |f|, or that needs more than GUESS_MAXIT
+// iterations is dropped for the plain guess (counted).
+//
+// Face dump.  With a dump buffer armed, every face (once) appends an 8-float
+// record: the six guess features, ln(p* / P_avg) and the plain guess's Newton
+// iteration count -- the network's training data.
 #include "mfm_internal.h"
+#include "mlp_device.h"
 
 namespace {
 
 constexpr int FBS = FLUX_BLOCK;
+constexpr int GUESS_MAXIT = 8;
 
 template <typename T>
 struct Gas {
@@ -53,6 +66,10 @@ struct FluxArgs {
   float rtol_f;
   int rmaxit, limiter;
   int64_t *counters;
+  mlp::Net net;             // learned guess (LEARNED kernels only)
+  float *dump;              // face records (null: off)
+  int64_t dump_cap;
+  unsigned long long *dump_count;
 };
 
 template <typename T>
@@ -127,21 +144,29 @@ __device__ __forceinline__ void pressure_fn(T ps, T ips, const Side<T> &s, const
   }
 }
 
-// Newton iteration on f(p) = f_L(p) + f_R(p) + du from p0, then u*.  With
-// quadratic_exit, a step below sqrt(tol) ends the iteration (the next error is
-// the square of it) and u* uses the first-order update of f_L, f_R.
+// Newton iteration on f(p) = f_L(p) + f_R(p) + du from p0, then u*.
+// quadratic_exit: a step below sqrt(tol) ends the iteration (the next error is
+// its square) and u* takes the first-order update of f_L, f_R.
+// guard > 0: the start is a guess to be judged; return 3 (reject) if the
+// second residual exceeds the first or more than guard iterations are needed.
+// Returns 0 converged, 2 iteration cap, 3 guess rejected.
 template <typename T, int M>
 __device__ int riemann_newton(const Gas<T> &G, const Side<T> &L, const Side<T> &R, T p0,
-                              T pfloor, T tol, int maxit, bool quadratic_exit, T &ps, T &us,
-                              int &iters) {
+                              T pfloor, T tol, int maxit, bool quadratic_exit, int guard, T &ps,
+                              T &us, int &iters) {
   const T du = R.u - L.u;
-  T p = p0, fL, dfL, fR, dfR;
+  T p = p0, fL, dfL, fR, dfR, res0 = T(0);
   int status = 2;
   for (int it = 1; it <= maxit; ++it) {
     const T ip = T(1) / p;
     pressure_fn<T, M>(p, ip, L, G, fL, dfL);
     pressure_fn<T, M>(p, ip, R, G, fR, dfR);
-    T pn = p - (fL + fR + du) / (dfL + dfR);
+    const T res = fL + fR + du;
+    if (guard) {
+      if (it == 1) res0 = fabs(res);
+      if ((it == 2 && fabs(res) > res0) || it > guard) return 3;
+    }
+    T pn = p - res / (dfL + dfR);
     if (pn < T(0)) pn = pfloor;
     const T step = T(2) * fabs(pn - p);  // relative change: step / (pn + p)
     ++iters;
@@ -166,37 +191,52 @@ __device__ int riemann_newton(const Gas<T> &G, const Side<T> &L, const Side<T> &
   return status;
 }
 
-// Exact Riemann solve: 0 converged, 1 vacuum, 2 iteration cap.
+// Toro's adaptive starting value: the primitive-variable pressure when the
+// states are close, else the two-rarefaction or two-shock value.
+template <typename T, int M>
+__device__ T plain_guess(const Gas<T> &G, const Side<T> &L, const Side<T> &R) {
+  const T du = R.u - L.u;
+  const T pmin = fmin(L.p, R.p), pmax = fmax(L.p, R.p);
+  T ppv = T(0.5) * (L.p + R.p) - T(0.125) * du * (L.r + R.r) * (L.c + R.c);
+  ppv = fmax(ppv, T(0));
+  if (pmax <= T(2) * pmin && pmin <= ppv && ppv <= pmax) return ppv;
+  if (ppv < pmin) {
+    // two-rarefaction value: [(cL + cR - g7 du) / (cL pL^-g1 + cR pR^-g1)]^(1/g1)
+    const T num = L.c + R.c - G.g7 * du;
+    const T den = L.c / root_m<T, M>(L.p, G) + R.c / root_m<T, M>(R.p, G);
+    const T t = num / den;
+    return M ? ipow<(M > 0 ? M : 1)>(t) : pow(t, T(1) / G.g1);
+  }
+  const T gL = sqrt(L.A / (L.B + ppv));
+  const T gR = sqrt(R.A / (R.B + ppv));
+  return (gL * L.p + gR * R.p - du) / (gL + gR);
+}
+
+// Exact Riemann solve: 0 converged, 1 vacuum, 2 iteration cap.  p_learned > 0
+// is tried first (guarded); *fallback is set when it was rejected.
 template <typename T, int M>
 __device__ int riemann_solve(const Gas<T> &G, const Side<T> &L, const Side<T> &R, T tol, int maxit,
-                             T &ps, T &us, int &iters) {
+                             T p_learned, T &ps, T &us, int &iters, bool &fallback) {
   const T du = R.u - L.u;
   iters = 0;
+  fallback = false;
   if (G.g4 * (L.c + R.c) <= du) {
     ps = T(0);
     us = T(0.5) * (L.u + R.u);
     return 1;
   }
-  const T pmin = fmin(L.p, R.p), pmax = fmax(L.p, R.p);
-  T ppv = T(0.5) * (L.p + R.p) - T(0.125) * du * (L.r + R.r) * (L.c + R.c);
-  ppv = fmax(ppv, T(0));
-  T p0;
-  if (pmax <= T(2) * pmin && pmin <= ppv && ppv <= pmax) {
-    p0 = ppv;
-  } else if (ppv < pmin) {
-    // two-rarefaction value: [(cL + cR - g7 du) / (cL pL^-g1 + cR pR^-g1)]^(1/g1)
-    const T num = L.c + R.c - G.g7 * du;
-    const T den = L.c / root_m<T, M>(L.p, G) + R.c / root_m<T, M>(R.p, G);
-    const T t = num / den;
-    p0 = M ? ipow<(M > 0 ? M : 1)>(t) : pow(t, T(1) / G.g1);
-  } else {
-    const T gL = sqrt(L.A / (L.B + ppv));
-    const T gR = sqrt(R.A / (R.B + ppv));
-    p0 = (gL * L.p + gR * R.p - du) / (gL + gR);
-  }
   const T pfloor = T(1e-10) * T(0.5) * (L.p + R.p);
+  if (p_learned > T(0)) {
+    if (p_learned > pfloor && isfinite(p_learned)) {
+      const int st = riemann_newton<T, M>(G, L, R, p_learned, pfloor, tol, maxit, false,
+                                          GUESS_MAXIT, ps, us, iters);
+      if (st != 3) return st;
+    }
+    fallback = true;
+  }
+  T p0 = plain_guess<T, M>(G, L, R);
   if (!(p0 > pfloor)) p0 = pfloor;
-  return riemann_newton<T, M>(G, L, R, p0, pfloor, tol, maxit, false, ps, us, iters);
+  return riemann_newton<T, M>(G, L, R, p0, pfloor, tol, maxit, false, 0, ps, us, iters);
 }
 
 // The exact solution at x/t = 0 in the face frame (Toro's sampling).
@@ -321,19 +361,26 @@ __device__ __forceinline__ void load_side(const FluxArgs &a, int i, FaceIn<float
   for (int k = 0; k < 15; ++k) s.G[k] = f[F_G + k];
 }
 
-enum { F_VACUUM = 1, F_POSITIVITY = 2, F_MAXIT = 4 };
+enum { F_VACUUM = 1, F_POSITIVITY = 2, F_MAXIT = 4, F_FALLBACK = 8 };
 
 constexpr double W_NORM = 8.0 / 3.14159265358979323846;
 
-// Contribution c = |A_ij| F_ij of the face between sides Ls (left) and Rs.
-template <typename T, int SCHEME, int M>
-__device__ void face_flux(const FaceIn<T> &Ls, const FaceIn<T> &Rs, const FluxArgs &a, T hdt,
-                          double c[5], int &iters, int &flags) {
+// A face after reconstruction, ready for the Riemann solve.
+template <typename T>
+struct FaceState {
+  bool skip;  // coincident particles or a vanishing face: no exchange
+  T Am, nv[3], vf[3], wL[3], wR[3];
+  Side<T> SL, SR;
+  int flags;
+};
+
+// Face vector, half-step predictor, extrapolation, limiter, boost (sec. 2.3.3-2.3.6).
+template <typename T>
+__device__ void face_prepare(const FaceIn<T> &Ls, const FaceIn<T> &Rs, const FluxArgs &a, T hdt,
+                             FaceState<T> &fs) {
   const Gas<T> &G = gas_of<T>(a);
-  iters = 0;
-  flags = 0;
-#pragma unroll
-  for (int k = 0; k < 5; ++k) c[k] = 0.0;
+  fs.skip = true;
+  fs.flags = 0;
   T d[3];
   d[0] = T(min_image(Rs.x - Ls.x, a.box[0], a.half[0]));
   d[1] = T(min_image(Rs.y - Ls.y, a.box[1], a.half[1]));
@@ -355,8 +402,11 @@ __device__ void face_flux(const FaceIn<T> &Ls, const FaceIn<T> &Rs, const FluxAr
                WR * (bR[2] * d[0] + bR[4] * d[1] + bR[5] * d[2]));
   const T Am = sqrt(A[0] * A[0] + A[1] * A[1] + A[2] * A[2]);
   if (Am == T(0)) return;
+  fs.skip = false;
+  fs.Am = Am;
   const T iA = T(1) / Am;
-  const T nv[3] = {A[0] * iA, A[1] * iA, A[2] * iA};
+#pragma unroll
+  for (int k = 0; k < 3; ++k) fs.nv[k] = A[k] * iA;
 
   const T qi[5] = {Ls.rho, Ls.v[0], Ls.v[1], Ls.v[2], Ls.P};
   const T qj[5] = {Rs.rho, Rs.v[0], Rs.v[1], Rs.v[2], Rs.P};
@@ -395,24 +445,38 @@ __device__ void face_flux(const FaceIn<T> &Ls, const FaceIn<T> &Rs, const FluxAr
       qL[q] = qi[q];
       qR[q] = qj[q];
     }
-    flags |= F_POSITIVITY;
+    fs.flags |= F_POSITIVITY;
   }
-  const T vf[3] = {T(0.5) * (qi[1] + qj[1]), T(0.5) * (qi[2] + qj[2]), T(0.5) * (qi[3] + qj[3])};
-  T wL[3], wR[3];
 #pragma unroll
   for (int k = 0; k < 3; ++k) {
-    wL[k] = qL[1 + k] - vf[k];
-    wR[k] = qR[1 + k] - vf[k];
+    fs.vf[k] = T(0.5) * (qi[1 + k] + qj[1 + k]);
+    fs.wL[k] = qL[1 + k] - fs.vf[k];
+    fs.wR[k] = qR[1 + k] - fs.vf[k];
   }
-  const T uL = wL[0] * nv[0] + wL[1] * nv[1] + wL[2] * nv[2];
-  const T uR = wR[0] * nv[0] + wR[1] * nv[1] + wR[2] * nv[2];
-  const Side<T> SL = make_side<T>(qL[0], uL, qL[4], sqrt(G.gamma * qL[4] / qL[0]), G);
-  const Side<T> SR = make_side<T>(qR[0], uR, qR[4], sqrt(G.gamma * qR[4] / qR[0]), G);
+  const T uL = fs.wL[0] * fs.nv[0] + fs.wL[1] * fs.nv[1] + fs.wL[2] * fs.nv[2];
+  const T uR = fs.wR[0] * fs.nv[0] + fs.wR[1] * fs.nv[1] + fs.wR[2] * fs.nv[2];
+  fs.SL = make_side<T>(qL[0], uL, qL[4], sqrt(G.gamma * qL[4] / qL[0]), G);
+  fs.SR = make_side<T>(qR[0], uR, qR[4], sqrt(G.gamma * qR[4] / qR[0]), G);
+}
+
+// Riemann solve and flux of a prepared face: c = |A_ij| F_ij (FP64).
+template <typename T, int SCHEME, int M>
+__device__ void face_solve(FaceState<T> &fs, const FluxArgs &a, T p_learned, double c[5],
+                           int &iters, double &ps_out) {
+  const Gas<T> &G = gas_of<T>(a);
+#pragma unroll
+  for (int k = 0; k < 5; ++k) c[k] = 0.0;
+  iters = 0;
+  ps_out = 0.0;
+  if (fs.skip) return;
+  const Side<T> &SL = fs.SL, &SR = fs.SR;
   T ps, us;
   const T tol = sizeof(T) == sizeof(float) ? T(a.rtol_f) : T(a.rtol);
-  int st = riemann_solve<T, M>(G, SL, SR, tol, a.rmaxit, ps, us, iters);
+  bool fallback;
+  int st = riemann_solve<T, M>(G, SL, SR, tol, a.rmaxit, p_learned, ps, us, iters, fallback);
+  if (fallback) fs.flags |= F_FALLBACK;
   if (st == 1) {
-    flags |= F_VACUUM;
+    fs.flags |= F_VACUUM;
     return;
   }
   double ps64 = (double)ps, us64 = (double)us;
@@ -420,19 +484,19 @@ __device__ void face_flux(const FaceIn<T> &Ls, const FaceIn<T> &Rs, const FluxAr
     // FP64 check of the FP32 root: Newton steps in FP64 until the step is in
     // the quadratic regime of the relative tolerance
     const Gas<double> &G64 = a.G;
-    const double rl = qL[0], pl = qL[4], rr = qR[0], pr = qR[4];
-    const Side<double> L64 =
-        make_side<double>(rl, (double)uL, pl, sqrt(G64.gamma * pl / rl), G64);
-    const Side<double> R64 =
-        make_side<double>(rr, (double)uR, pr, sqrt(G64.gamma * pr / rr), G64);
+    const double rl = SL.r, pl = SL.p, rr = SR.r, pr = SR.p;
+    const Side<double> L64 = make_side<double>(rl, (double)SL.u, pl, sqrt(G64.gamma * pl / rl), G64);
+    const Side<double> R64 = make_side<double>(rr, (double)SR.u, pr, sqrt(G64.gamma * pr / rr), G64);
     const double pfloor = 1e-10 * 0.5 * (pl + pr);
     st = riemann_newton<double, M>(G64, L64, R64, fmax(ps64, pfloor), pfloor, a.rtol, a.rmaxit,
-                                   true, ps64, us64, iters);
+                                   true, 0, ps64, us64, iters);
   }
-  if (st == 2) flags |= F_MAXIT;
+  if (st == 2) fs.flags |= F_MAXIT;
+  ps_out = ps64;
+  const T *nv = fs.nv, *vf = fs.vf;
   const double vfn = (double)(vf[0] * nv[0] + vf[1] * nv[1] + vf[2] * nv[2]);
   if (SCHEME == MFM_SCHEME_MFM) {
-    const double Ap = (double)Am * ps64;
+    const double Ap = (double)fs.Am * ps64;
     c[0] = 0.0;
 #pragma unroll
     for (int k = 0; k < 3; ++k) c[1 + k] = Ap * (double)nv[k];
@@ -440,7 +504,7 @@ __device__ void face_flux(const FaceIn<T> &Ls, const FaceIn<T> &Rs, const FluxAr
   } else {
     T rf, uf, pf;
     sample_at_face<T, M>(G, SL, SR, T(ps64), T(us64), rf, uf, pf);
-    const T *wu = (us64 >= 0.0) ? wL : wR;
+    const T *wu = (us64 >= 0.0) ? fs.wL : fs.wR;
     const T wun = wu[0] * nv[0] + wu[1] * nv[1] + wu[2] * nv[2];
     T vfa[3];
 #pragma unroll
@@ -452,7 +516,7 @@ __device__ void face_flux(const FaceIn<T> &Ls, const FaceIn<T> &Rs, const FluxAr
     for (int k = 0; k < 3; ++k) Fp[k] = Fm * vfa[k] + pf * nv[k];
     const T FE = uf * (pf * G.inv_gm1 + T(0.5) * rf * v2 + pf);
     const T vf2 = vf[0] * vf[0] + vf[1] * vf[1] + vf[2] * vf[2];
-    const double Amd = (double)Am;
+    const double Amd = (double)fs.Am;
     c[0] = Amd * (double)Fm;
 #pragma unroll
     for (int k = 0; k < 3; ++k) c[1 + k] = Amd * (double)(Fp[k] + vf[k] * Fm);
@@ -461,11 +525,18 @@ __device__ void face_flux(const FaceIn<T> &Ls, const FaceIn<T> &Rs, const FluxAr
   }
 }
 
-template <typename T, int SCHEME, int M>
+template <typename T>
+__device__ __forceinline__ void features_of(const FaceState<T> &fs, float x[mlp::NIN]) {
+  mlp::face_features((float)fs.SL.r, (float)fs.SL.u, (float)fs.SL.p, (float)fs.SL.c,
+                     (float)fs.SR.r, (float)fs.SR.u, (float)fs.SR.p, (float)fs.SR.c, x);
+}
+
+template <typename T, int SCHEME, int M, bool LEARNED>
 __global__ void __launch_bounds__(FBS) fluxes_k(FluxArgs a) {
   __shared__ int pref[FBS + 1];
   __shared__ int wsum[FBS / 64];
   __shared__ double acc[5][FBS];
+  __shared__ uint16_t mlp_act[LEARNED ? (FBS / 64) * 64 * mlp::AST : 1];
   const int64_t n = a.n;
   const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
   const int b0 = blockIdx.x * FBS;
@@ -489,12 +560,15 @@ __global__ void __launch_bounds__(FBS) fluxes_k(FluxArgs a) {
   const int T_faces = pref[FBS];
   const double dt = a.dt[0];
   const T hdt = T(0.5 * dt);
-  int64_t nfaces = 0, iters_sum = 0, vac = 0, pos = 0, maxit = 0;
+  int64_t nfaces = 0, iters_sum = 0, vac = 0, pos = 0, maxit = 0, fb = 0;
   for (int base = 0; base < T_faces; base += FBS) {
     const int f = base + tid;
     const bool active = f < T_faces;
     int p = FBS;  // sentinel key for idle lanes (they sit at the wave's end)
-    double c[5] = {0, 0, 0, 0, 0};
+    int i = 0, j = 0;
+    FaceState<T> fs;
+    fs.skip = true;
+    fs.flags = 0;
     if (active) {
       // particle p of this face: pref[p] <= f < pref[p + 1]
       int lo = 0, hi = FBS;
@@ -503,15 +577,33 @@ __global__ void __launch_bounds__(FBS) fluxes_k(FluxArgs a) {
         if (pref[mid] <= f) lo = mid; else hi = mid;
       }
       p = lo;
-      const int i = b0 + p;
-      const int j = a.fslot[list_at(i, f - pref[p], n)];
+      i = b0 + p;
+      j = a.fslot[list_at(i, f - pref[p], n)];
       const int L = i < j ? i : j, R = i < j ? j : i;
       FaceIn<T> Ls, Rs;
       load_side(a, L, Ls);
       load_side(a, R, Rs);
-      int it, fl;
-      face_flux<T, SCHEME, M>(Ls, Rs, a, hdt, c, it, fl);
-      const double sgn = (i == L) ? -1.0 : 1.0;  // the left side loses c
+      face_prepare<T>(Ls, Rs, a, hdt, fs);
+    }
+    T p_learned = T(0);
+    if (LEARNED) {
+      // the whole wavefront evaluates the network on its faces
+      uint16_t *act = mlp_act + wid * 64 * mlp::AST;
+      float x[mlp::NIN];
+      const bool use = active && !fs.skip;
+      if (use) features_of<T>(fs, x);
+      mlp::put_input(act, lane, use ? x : nullptr, a.net.norm);
+      const float y = mlp::forward_wave(act, a.net, lane);
+      if (use) p_learned = T(0.5) * (fs.SL.p + fs.SR.p) * T(expf(y));
+      if (use && !(p_learned > T(0))) p_learned = T(-1);  // rejected below
+    }
+    double c[5] = {0, 0, 0, 0, 0};
+    if (active) {
+      int it;
+      double ps;
+      face_solve<T, SCHEME, M>(fs, a, (LEARNED && p_learned != T(0)) ? p_learned : T(0), c, it, ps);
+      if (LEARNED && p_learned < T(0)) fs.flags |= F_FALLBACK;
+      const double sgn = (i < j) ? -1.0 : 1.0;  // the left (lower) side loses c
 #pragma unroll
       for (int q = 0; q < 5; ++q) c[q] *= sgn;
       const bool inb = (j >= b0) && (j < b0 + nb);
@@ -523,9 +615,22 @@ __global__ void __launch_bounds__(FBS) fluxes_k(FluxArgs a) {
       if (inb || i < j) {
         ++nfaces;
         iters_sum += it;
-        vac += (fl & F_VACUUM) ? 1 : 0;
-        pos += (fl & F_POSITIVITY) ? 1 : 0;
-        maxit += (fl & F_MAXIT) ? 1 : 0;
+        vac += (fs.flags & F_VACUUM) ? 1 : 0;
+        pos += (fs.flags & F_POSITIVITY) ? 1 : 0;
+        maxit += (fs.flags & F_MAXIT) ? 1 : 0;
+        fb += (fs.flags & F_FALLBACK) ? 1 : 0;
+        if (a.dump && !fs.skip && !(fs.flags & F_VACUUM)) {
+          const unsigned long long slot = atomicAdd(a.dump_count, 1ull);
+          if (slot < (unsigned long long)a.dump_cap) {
+            float x[mlp::NIN];
+            features_of<T>(fs, x);
+            float *r = a.dump + slot * 8;
+#pragma unroll
+            for (int k = 0; k < mlp::NIN; ++k) r[k] = x[k];
+            r[6] = logf((float)(ps / (0.5 * ((double)fs.SL.p + (double)fs.SR.p))));
+            r[7] = (float)it;
+          }
+        }
       }
     }
     // segmented sum over lanes with the same particle (keys ascend across lanes)
@@ -555,24 +660,25 @@ __global__ void __launch_bounds__(FBS) fluxes_k(FluxArgs a) {
   count_add(a.counters + C_VACUUM, vac);
   count_add(a.counters + C_POSITIVITY, pos);
   count_add(a.counters + C_RIEMANN_MAXIT, maxit);
+  count_add(a.counters + C_GUESS_FALLBACK, fb);
 }
 
-template <typename T, int SCHEME>
+template <typename T, int SCHEME, bool LEARNED>
 void launch_m(const FluxArgs &a, int m, int nb, hipStream_t st) {
   if (m == 5)
-    fluxes_k<T, SCHEME, 5><<<nb, FBS, 0, st>>>(a);
+    fluxes_k<T, SCHEME, 5, LEARNED><<<nb, FBS, 0, st>>>(a);
   else if (m == 7)
-    fluxes_k<T, SCHEME, 7><<<nb, FBS, 0, st>>>(a);
+    fluxes_k<T, SCHEME, 7, LEARNED><<<nb, FBS, 0, st>>>(a);
   else
-    fluxes_k<T, SCHEME, 0><<<nb, FBS, 0, st>>>(a);
+    fluxes_k<T, SCHEME, 0, LEARNED><<<nb, FBS, 0, st>>>(a);
 }
 
-template <typename T>
+template <typename T, bool LEARNED>
 void launch_t(const FluxArgs &a, int scheme, int m, int nb, hipStream_t st) {
   if (scheme == MFM_SCHEME_MFM)
-    launch_m<T, MFM_SCHEME_MFM>(a, m, nb, st);
+    launch_m<T, MFM_SCHEME_MFM, LEARNED>(a, m, nb, st);
   else
-    launch_m<T, MFM_SCHEME_MFV>(a, m, nb, st);
+    launch_m<T, MFM_SCHEME_MFV, LEARNED>(a, m, nb, st);
 }
 
 template <typename T>
@@ -619,10 +725,22 @@ hipError_t launch_fluxes(mfm_ctx *ctx, const mfm_particles *pp, const double *dt
   a.rmaxit = ctx->p.riemann_maxit;
   a.limiter = ctx->p.limiter;
   a.counters = ctx->counters;
+  a.dump = ctx->dump;
+  a.dump_cap = ctx->dump_cap;
+  a.dump_count = ctx->dump_count;
+  const bool learned = ctx->p.guess == MFM_GUESS_LEARNED;
+  if (learned) mlp_net_of(ctx->mlp_state, &a.net);
   const int nb = blocks_for(pp->n, FBS);
-  if (ctx->p.precision == MFM_MIXED)
-    launch_t<float>(a, ctx->p.scheme, m, nb, ctx->stream);
-  else
-    launch_t<double>(a, ctx->p.scheme, m, nb, ctx->stream);
+  if (ctx->p.precision == MFM_MIXED) {
+    if (learned)
+      launch_t<float, true>(a, ctx->p.scheme, m, nb, ctx->stream);
+    else
+      launch_t<float, false>(a, ctx->p.scheme, m, nb, ctx->stream);
+  } else {
+    if (learned)
+      launch_t<double, true>(a, ctx->p.scheme, m, nb, ctx->stream);
+    else
+      launch_t<double, false>(a, ctx->p.scheme, m, nb, ctx->stream);
+  }
   return hipGetLastError();
 }

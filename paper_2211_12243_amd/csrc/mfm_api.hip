@@ -67,6 +67,8 @@ int check_params(const mfm_params *p) {
   if (!p) return 0;
   if (p->scheme != MFM_SCHEME_MFV && p->scheme != MFM_SCHEME_MFM) return 0;
   if (p->precision != MFM_FP64 && p->precision != MFM_MIXED) return 0;
+  if (p->guess != MFM_GUESS_PLAIN && p->guess != MFM_GUESS_LEARNED) return 0;
+  if (p->limiter < 0 || p->limiter > (MFM_LIMIT_BJ | MFM_LIMIT_PAIRWISE)) return 0;
   if (!(p->gamma > 1.0)) return 0;
   if (!(p->n_ngb > 32.0 / 3.0)) return 0;
   if (!(p->ncond_max > 1.0) || !(p->ngb_boost > 1.0) || p->max_boosts < 0) return 0;
@@ -245,6 +247,7 @@ int mfm_create(const mfm_params *p, int64_t n_max, void *workspace, size_t works
   ctx->ncodes_max = L.ncodes_max;
   ctx->scan_tmp_len = L.scan_len;
   ctx->margin_boost = 1.0;
+  ctx->dump_count = reinterpret_cast<unsigned long long *>(ctx->counters + C_DUMP_COUNT);
   for (int k = 0; k < 2 * 1024; ++k) {
     if (hipEventCreate(&ctx->ev_pool[k]) != hipSuccess) {
       for (int q = 0; q < k; ++q) hipEventDestroy(ctx->ev_pool[q]);
@@ -355,9 +358,37 @@ int mfm_fluxes(mfm_ctx *ctx, const mfm_particles *pp, const double *dt_dev) {
   if (!check_parts(ctx, pp) || !dt_dev) return fail(ctx, MFM_E_ARG, "invalid arguments");
   if (!ctx->have_grad || ctx->n_cells_built != pp->n)
     return fail(ctx, MFM_E_STATE, "mfm_fluxes needs mfm_gradients first");
+  if (ctx->p.guess == MFM_GUESS_LEARNED && !ctx->mlp_state)
+    return fail(ctx, MFM_E_STATE, "learned guess requested but no network attached");
   stage_begin(ctx, 4);
   HIPCHK(ctx, launch_fluxes(ctx, pp, dt_dev), "fluxes");
   stage_end(ctx, 4);
+  return MFM_OK;
+}
+
+int mfm_mlp_attach(mfm_ctx *ctx, const void *state_dev) {
+  if (!ctx) return MFM_E_ARG;
+  ctx->mlp_state = state_dev;
+  return MFM_OK;
+}
+
+int mfm_face_dump(mfm_ctx *ctx, float *records_dev, int64_t capacity) {
+  if (!ctx) return MFM_E_ARG;
+  if (records_dev && capacity <= 0) return fail(ctx, MFM_E_ARG, "dump capacity must be > 0");
+  ctx->dump = records_dev;
+  ctx->dump_cap = records_dev ? capacity : 0;
+  HIPCHK(ctx, hipMemsetAsync(ctx->counters + C_DUMP_COUNT, 0, sizeof(int64_t), ctx->stream),
+         "reset dump count");
+  HIPCHK(ctx, hipStreamSynchronize(ctx->stream), "synchronise");
+  return MFM_OK;
+}
+
+int mfm_face_dump_count(mfm_ctx *ctx, int64_t *count_host) {
+  if (!ctx || !count_host) return MFM_E_ARG;
+  int64_t c[NCOUNTERS];
+  int rc = read_counters(ctx, c);
+  if (rc) return rc;
+  *count_host = c[C_DUMP_COUNT] < ctx->dump_cap ? c[C_DUMP_COUNT] : ctx->dump_cap;
   return MFM_OK;
 }
 

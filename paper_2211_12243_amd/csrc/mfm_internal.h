@@ -34,6 +34,7 @@ enum {
   C_PASS_NOCONV,
   C_PASS_BOOSTS,
   C_PASS_FAIL,
+  C_DUMP_COUNT,     // face records appended since the dump was armed
   NCOUNTERS = 24
 };
 
@@ -112,6 +113,11 @@ struct mfm_ctx {
   double margin_boost;
   int have_cells, have_density, have_grad;
   int64_t n_cells_built;  // n of the particles the cells were built for
+  // learned guess and face dump
+  const void *mlp_state;  // network state (mfm_mlp_attach), null if none
+  float *dump;            // face records (mfm_face_dump), null when off
+  int64_t dump_cap;
+  unsigned long long *dump_count;  // = counters + C_DUMP_COUNT
   // timing
   int timing;
   hipEvent_t ev_pool[2 * 1024];
@@ -203,6 +209,9 @@ hipError_t launch_gradients(mfm_ctx *ctx, const mfm_particles *pp, double dt_max
 hipError_t launch_fluxes(mfm_ctx *ctx, const mfm_particles *pp, const double *dt_dev);
 hipError_t launch_update(mfm_ctx *ctx, const mfm_particles *pp, const double *dt_dev);
 hipError_t launch_conserved(mfm_ctx *ctx, const mfm_particles *pp);
+
+// device pointers of a network state (mlp translation unit); net_out is an mlp::Net
+const void *mlp_net_of(const void *state, void *net_out);
 
 // timing helpers (api translation unit)
 void stage_begin(mfm_ctx *ctx, int stage);

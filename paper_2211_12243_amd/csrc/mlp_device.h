@@ -1,0 +1,170 @@
+// mlp_device.h -- the Riemann-guess network on matrix cores: a 6 -> 64 -> 64
+// -> 64 -> 1 perceptron with SiLU activations, BF16 operands and FP32
+// accumulation on v_mfma_f32_16x16x16_bf16.  A wavefront evaluates 16 * MT
+// rows (faces) at a time; activations live in LDS between layers, the BF16
+// weights (18 KB, transposed so each lane's operand is one 8-byte load) are
+// read through L1.
+//
+// Operand layout of the 16x16x16 BF16 MFMA (lane l, element e = 0..3):
+//   A (16 x 16, M x K): row l % 16, column 4 (l / 16) + e
+//   B (16 x 16, K x N): row 4 (l / 16) + e, column l % 16
+//   D (16 x 16, M x N): row 4 (l / 16) + e, column l % 16
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace mlp {
+
+constexpr int NIN = 6;    // features
+constexpr int K1 = 16;    // first-layer input width padded to one MFMA K step
+constexpr int HID = 64;   // hidden width
+// FP32 parameter vector: W1 [K1][HID] (rows >= NIN stay zero), b1, W2 [HID][HID],
+// b2, W3 [HID][HID], b3, w4 [HID], b4.
+constexpr int OFF_W1 = 0;
+constexpr int OFF_B1 = OFF_W1 + K1 * HID;
+constexpr int OFF_W2 = OFF_B1 + HID;
+constexpr int OFF_B2 = OFF_W2 + HID * HID;
+constexpr int OFF_W3 = OFF_B2 + HID;
+constexpr int OFF_B3 = OFF_W3 + HID * HID;
+constexpr int OFF_W4 = OFF_B3 + HID;
+constexpr int OFF_B4 = OFF_W4 + HID;
+constexpr int NPARAM = OFF_B4 + 1;
+constexpr int NPARAM_PAD = (NPARAM + 63) / 64 * 64;
+// transposed BF16 weights: W1^T [HID][K1], W2^T [HID][HID], W3^T [HID][HID]
+constexpr int T_W1 = 0;
+constexpr int T_W2 = T_W1 + HID * K1;
+constexpr int T_W3 = T_W2 + HID * HID;
+constexpr int NT = T_W3 + HID * HID;
+// normalisation: mean[6], std[6], y mean, y std
+constexpr int NNORM = 16;
+
+constexpr int AST = HID + 8;  // LDS activation row stride (BF16 elements)
+
+typedef short bf16x4 __attribute__((ext_vector_type(4)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+// FP32 -> BF16, round to nearest even (finite inputs).
+__host__ __device__ inline uint16_t to_bf16(float f) {
+  union {
+    float f;
+    uint32_t u;
+  } v;
+  v.f = f;
+  uint32_t u = v.u;
+  u += 0x7fffu + ((u >> 16) & 1u);
+  return (uint16_t)(u >> 16);
+}
+__host__ __device__ inline float from_bf16(uint16_t h) {
+  union {
+    float f;
+    uint32_t u;
+  } v;
+  v.u = ((uint32_t)h) << 16;
+  return v.f;
+}
+
+__device__ inline float silu(float z) { return z / (1.0f + __expf(-z)); }
+__device__ inline float dsilu(float z) {
+  const float s = 1.0f / (1.0f + __expf(-z));
+  return s * (1.0f + z * (1.0f - s));
+}
+
+// Where the network's weights live (device memory).
+struct Net {
+  const uint16_t *wt;   // transposed BF16 weights (T_* offsets)
+  const uint16_t *wr;   // row-major BF16 copy of the parameter vector
+  const float *p;       // FP32 parameters (biases, w4, b4 are read from here)
+  const float *norm;
+};
+
+__device__ inline bf16x4 ld4(const uint16_t *q) {
+  const uint2 v = *reinterpret_cast<const uint2 *>(q);  // 8-byte aligned
+  bf16x4 r;
+  r[0] = (short)(v.x & 0xffffu);
+  r[1] = (short)(v.x >> 16);
+  r[2] = (short)(v.y & 0xffffu);
+  r[3] = (short)(v.y >> 16);
+  return r;
+}
+
+// A dense layer for the wave's 16 * MT rows: out[:, :HID] = silu(in[:, :K] W + b).
+// in and out may be the same buffer (each row block is read before it is
+// written).  If z is given, the pre-activations are kept there (row stride zst).
+template <int MT, int K>
+__device__ inline void layer(const uint16_t *in, int ist, uint16_t *out, int ost,
+                             const uint16_t *wt, const float *bias, float *z, int zst,
+                             int lane) {
+  const int r16 = lane & 15, q4 = (lane >> 4) * 4;
+#pragma unroll
+  for (int mt = 0; mt < MT; ++mt) {
+    f32x4 acc[4];
+#pragma unroll
+    for (int nt = 0; nt < 4; ++nt) acc[nt] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int kt = 0; kt < K / 16; ++kt) {
+      const bf16x4 a = ld4(in + (16 * mt + r16) * ist + 16 * kt + q4);
+#pragma unroll
+      for (int nt = 0; nt < 4; ++nt) {
+        const bf16x4 b = ld4(wt + (16 * nt + r16) * K + 16 * kt + q4);
+        acc[nt] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, acc[nt], 0, 0, 0);
+      }
+    }
+#pragma unroll
+    for (int nt = 0; nt < 4; ++nt) {
+      const int n = 16 * nt + r16;
+      const float bn = bias[n];
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int m = 16 * mt + q4 + e;
+        const float zz = acc[nt][e] + bn;
+        if (z) z[m * zst + n] = zz;
+        out[m * ost + n] = to_bf16(silu(zz));
+      }
+    }
+  }
+}
+
+// Orders this wave's LDS writes before its later LDS reads of other lanes' data.
+__device__ inline void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+}
+
+// Standardised BF16 features of row `row` (zeros when x is null).
+__device__ inline void put_input(uint16_t *act, int row, const float *x, const float *norm) {
+#pragma unroll
+  for (int k = 0; k < NIN; ++k)
+    act[row * AST + k] = x ? to_bf16((x[k] - norm[k]) / norm[NIN + k]) : (uint16_t)0;
+#pragma unroll
+  for (int k = NIN; k < K1; ++k) act[row * AST + k] = 0;
+}
+
+// Forward pass for the 64 rows of a wave (act holds the inputs, row = lane);
+// returns this lane's output mapped back to the unstandardised target.
+__device__ inline float forward_wave(uint16_t *act, const Net &net, int lane) {
+  wave_lds_sync();
+  layer<4, K1>(act, AST, act, AST, net.wt + T_W1, net.p + OFF_B1, nullptr, 0, lane);
+  wave_lds_sync();
+  layer<4, HID>(act, AST, act, AST, net.wt + T_W2, net.p + OFF_B2, nullptr, 0, lane);
+  wave_lds_sync();
+  layer<4, HID>(act, AST, act, AST, net.wt + T_W3, net.p + OFF_B3, nullptr, 0, lane);
+  wave_lds_sync();
+  float y = net.p[OFF_B4];
+  for (int k = 0; k < HID; ++k) y += from_bf16(act[lane * AST + k]) * net.p[OFF_W4 + k];
+  return net.norm[2 * NIN] + net.norm[2 * NIN + 1] * y;
+}
+
+// Learned-guess features of a face in its frame (left and right states).
+__device__ inline void face_features(float rL, float uL, float pL, float cL, float rR, float uR,
+                                     float pR, float cR, float x[NIN]) {
+  auto slog = [](float v) { return copysignf(log1pf(fabsf(v)), v); };
+  x[0] = logf(rL / rR);
+  x[1] = logf(pL / pR);
+  x[2] = slog((uR - uL) / (0.5f * (cL + cR)));
+  x[3] = slog(uL / cL);
+  x[4] = slog(uR / cR);
+  x[5] = logf(cL / cR);
+}
+
+}  // namespace mlp

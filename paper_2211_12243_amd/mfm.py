@@ -102,6 +102,25 @@ def lib():
                   "mfm_fluxes", "mfm_update", "mfm_step", "mfm_diagnostics",
                   "mfm_reset_counters", "mfm_enable_timing", "mfm_kernel_times"):
             getattr(L, f).restype = ctypes.c_int
+        F, I64 = ctypes.POINTER(ctypes.c_float), ctypes.c_int64
+        L.mfm_mlp_state_bytes.argtypes = []
+        L.mfm_mlp_state_bytes.restype = ctypes.c_size_t
+        L.mfm_mlp_param_count.argtypes = []
+        L.mfm_mlp_param_count.restype = ctypes.c_int
+        L.mfm_mlp_init.argtypes = [_PTR, F, F, _PTR]
+        L.mfm_mlp_backward.argtypes = [_PTR, _PTR, I64, I64, F, _PTR]
+        L.mfm_mlp_adam.argtypes = [_PTR, ctypes.c_float, ctypes.c_int, _PTR]
+        L.mfm_mlp_train_step.argtypes = [_PTR, _PTR, I64, I64, ctypes.c_float, ctypes.c_int, F,
+                                         _PTR]
+        L.mfm_mlp_predict.argtypes = [_PTR, _PTR, I64, I64, _PTR, _PTR]
+        L.mfm_mlp_get.argtypes = [_PTR, F, F, _PTR]
+        L.mfm_mlp_attach.argtypes = [C, _PTR]
+        L.mfm_face_dump.argtypes = [C, _PTR, I64]
+        L.mfm_face_dump_count.argtypes = [C, ctypes.POINTER(I64)]
+        for f in ("mfm_mlp_init", "mfm_mlp_backward", "mfm_mlp_adam", "mfm_mlp_train_step",
+                  "mfm_mlp_predict",
+                  "mfm_mlp_get", "mfm_mlp_attach", "mfm_face_dump", "mfm_face_dump_count"):
+            getattr(L, f).restype = ctypes.c_int
         L.mfm_strerror.argtypes = [ctypes.c_int]
         L.mfm_strerror.restype = ctypes.c_char_p
         L.mfm_last_error.argtypes = [C]
@@ -113,7 +132,11 @@ def lib():
 EXPORTED = ("mfm_default_params", "mfm_workspace_bytes", "mfm_create", "mfm_destroy",
             "mfm_build_cells", "mfm_density", "mfm_gradients", "mfm_fluxes", "mfm_update",
             "mfm_step", "mfm_diagnostics", "mfm_reset_counters", "mfm_enable_timing",
-            "mfm_kernel_times", "mfm_strerror", "mfm_last_error")
+            "mfm_kernel_times", "mfm_strerror", "mfm_last_error", "mfm_mlp_state_bytes",
+            "mfm_mlp_param_count", "mfm_mlp_init", "mfm_mlp_backward", "mfm_mlp_adam",
+            "mfm_mlp_train_step",
+            "mfm_mlp_predict", "mfm_mlp_get", "mfm_mlp_attach", "mfm_face_dump",
+            "mfm_face_dump_count")
 
 
 def mfm_default_params(**over) -> mfm_params:
@@ -296,3 +319,127 @@ def run_pipeline(ctx: Context, ps: ParticleSet, dt_max: float, update: bool = Tr
     if update:
         mfm_update(ctx, ps)
     return dt
+
+
+# --- learned Riemann guess ------------------------------------------------------------------
+
+MLP_NIN, MLP_K1, MLP_HID, MLP_NNORM = 6, 16, 64, 16
+DUMP_STRIDE = 8  # floats per face record: 6 features, ln(p*/P_avg), plain-guess iterations
+
+
+def mlp_param_layout() -> dict:
+    """Offsets and shapes of the FP32 parameter vector (order fixed by the C ABI)."""
+    shapes = [("W1", (MLP_K1, MLP_HID)), ("b1", (MLP_HID,)), ("W2", (MLP_HID, MLP_HID)),
+              ("b2", (MLP_HID,)), ("W3", (MLP_HID, MLP_HID)), ("b3", (MLP_HID,)),
+              ("w4", (MLP_HID,)), ("b4", (1,))]
+    out, off = {}, 0
+    for name, shp in shapes:
+        size = 1
+        for d in shp:
+            size *= d
+        out[name] = (off, shp)
+        off += size
+    assert off == mfm_mlp_param_count()
+    return out
+
+
+def mfm_mlp_param_count() -> int:
+    return int(lib().mfm_mlp_param_count())
+
+
+def mfm_mlp_state_bytes() -> int:
+    return int(lib().mfm_mlp_state_bytes())
+
+
+def _fptr(a):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_float))
+
+
+def _stream_ptr(stream):
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+class MLPState:
+    """Device state of the guess network (one tensor of mfm_mlp_state_bytes bytes)."""
+
+    def __init__(self, params, norm, stream=None, device="cuda"):
+        import numpy as np
+        nb = mfm_mlp_state_bytes()
+        self.buf = torch.empty(nb + 256, dtype=torch.uint8, device=device)
+        self.ptr = (self.buf.data_ptr() + 255) // 256 * 256
+        self.stream = stream
+        self.step = 0
+        p = np.ascontiguousarray(params, dtype=np.float32)
+        q = np.ascontiguousarray(norm, dtype=np.float32)
+        if p.size != mfm_mlp_param_count() or q.size != MLP_NNORM:
+            raise MFMError("parameter or normalisation vector has the wrong length")
+        _check(lib().mfm_mlp_init(ctypes.c_void_p(self.ptr), _fptr(p), _fptr(q),
+                                  _stream_ptr(stream)))
+
+    @property
+    def handle(self):
+        return ctypes.c_void_p(self.ptr)
+
+
+def mfm_mlp_init(params, norm, stream=None) -> MLPState:
+    return MLPState(params, norm, stream)
+
+
+def mfm_mlp_backward(st: MLPState, rows, n=None, stride=DUMP_STRIDE) -> float:
+    n = int(rows.shape[0]) if n is None else int(n)
+    loss = ctypes.c_float()
+    _check(lib().mfm_mlp_backward(st.handle, _ptr(rows), n, int(stride), ctypes.byref(loss),
+                                  _stream_ptr(st.stream)))
+    return float(loss.value)
+
+
+def mfm_mlp_adam(st: MLPState, lr: float):
+    st.step += 1
+    _check(lib().mfm_mlp_adam(st.handle, float(lr), st.step, _stream_ptr(st.stream)))
+
+
+def mfm_mlp_train_step(st: MLPState, rows, lr: float, n=None, stride=DUMP_STRIDE,
+                       want_loss=False):
+    n = int(rows.shape[0]) if n is None else int(n)
+    st.step += 1
+    loss = ctypes.c_float()
+    _check(lib().mfm_mlp_train_step(st.handle, _ptr(rows), n, int(stride), float(lr), st.step,
+                                    ctypes.byref(loss) if want_loss else None,
+                                    _stream_ptr(st.stream)))
+    return float(loss.value) if want_loss else None
+
+
+def mfm_mlp_predict(st: MLPState, rows, n=None, stride=DUMP_STRIDE):
+    n = int(rows.shape[0]) if n is None else int(n)
+    y = torch.empty(n, dtype=torch.float32, device=rows.device)
+    _check(lib().mfm_mlp_predict(st.handle, _ptr(rows), n, int(stride), _ptr(y),
+                                 _stream_ptr(st.stream)))
+    return y
+
+
+def mfm_mlp_get(st: MLPState):
+    import numpy as np
+    n = mfm_mlp_param_count()
+    p = np.zeros(n, dtype=np.float32)
+    g = np.zeros(n, dtype=np.float32)
+    _check(lib().mfm_mlp_get(st.handle, _fptr(p), _fptr(g), _stream_ptr(st.stream)))
+    return p, g
+
+
+def mfm_mlp_attach(ctx: Context, st: MLPState | None):
+    ctx.mlp = st  # keeps the state alive while attached
+    _check(lib().mfm_mlp_attach(ctx.h, st.handle if st is not None else None), ctx.h)
+
+
+def mfm_face_dump(ctx: Context, records=None):
+    """Arm (records: float32 device tensor [cap, 8]) or disarm (None) the face dump."""
+    ctx.dump = records
+    cap = int(records.shape[0]) if records is not None else 0
+    _check(lib().mfm_face_dump(ctx.h, _ptr(records), cap), ctx.h)
+
+
+def mfm_face_dump_count(ctx: Context) -> int:
+    c = ctypes.c_int64()
+    _check(lib().mfm_face_dump_count(ctx.h, ctypes.byref(c)), ctx.h)
+    return int(c.value)

@@ -19,11 +19,13 @@ def _need_gpu():
         pytest.skip("no HIP device")
 
 
-def run_both(cfg, st, dt_max=1.0, precision="fp64"):
+def run_both(cfg, st, dt_max=1.0, precision="fp64", setup=None):
     _need_gpu()
     n = len(st["x"])
     params = mfm.params_from_dict(cfg, precision=precision)
     ctx = mfm.Context(params, n)
+    if setup is not None:
+        setup(ctx)
     ps = mfm.ParticleSet(st)
     print(f"[parity] n={n} cfg={cfg} precision={precision}", flush=True)
     mfm.mfm_reset_counters(ctx)
