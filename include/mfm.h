@@ -209,7 +209,7 @@ const char *mfm_strerror(int status);
 const char *mfm_last_error(struct mfm_ctx *ctx);
 
 /* ------------------------------------------------------------------------
- * Learned starting value of the exact Riemann iteration (sec. 2.3.6 uses the
+ * Learned starting value of the exact Riemann iteration (sec. 2.3.3 uses the
  * exact solver; the guess only changes how many Newton steps it takes).
  *
  * The network maps six dimensionless features of a face's left and right

@@ -5,7 +5,7 @@ module; the HIP library never does.
 
 The network is an addition to the paper: it supplies the starting value of the
 Newton iteration of the exact Riemann solver the paper uses for its fluxes
-(sec. 2.3.6, Toro's solver), which then converges to the same root whatever
+(sec. 2.3.3, Toro's solver), which then converges to the same root whatever
 the start.  What is fixed here, in plain numpy and FP64:
 
 * the six dimensionless face features of the left and right states (face

@@ -34,7 +34,7 @@ struct CandArgs {
 };
 
 __global__ void __launch_bounds__(BS) cand_k(CandArgs a, CellGrid g) {
-  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  const int64_t i = xcd_block(blockIdx.x, gridDim.x) * (int64_t)blockDim.x + threadIdx.x;
   const int64_t n = a.n;
   int64_t overflow = 0;
   if (i < n) {
@@ -126,7 +126,7 @@ __device__ double cond3(const double e[6]) {
 }
 
 __global__ void __launch_bounds__(BS) density_k(DensityArgs a, CellGrid g) {
-  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  const int64_t i = xcd_block(blockIdx.x, gridDim.x) * (int64_t)blockDim.x + threadIdx.x;
   const int64_t n = a.n;
   int64_t noconv = 0, boosts = 0, fails = 0, overflow = 0;
   if (i < n) {

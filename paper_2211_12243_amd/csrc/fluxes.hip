@@ -532,14 +532,14 @@ __device__ __forceinline__ void features_of(const FaceState<T> &fs, float x[mlp:
 }
 
 template <typename T, int SCHEME, int M, bool LEARNED>
-__global__ void __launch_bounds__(FBS) fluxes_k(FluxArgs a) {
+__global__ void __launch_bounds__(FBS) __attribute__((amdgpu_waves_per_eu(LEARNED ? 2 : 1))) fluxes_k(FluxArgs a) {
   __shared__ int pref[FBS + 1];
   __shared__ int wsum[FBS / 64];
   __shared__ double acc[5][FBS];
-  __shared__ uint16_t mlp_act[LEARNED ? (FBS / 64) * 64 * mlp::AST : 1];
+  __shared__ uint16_t mlp_act[LEARNED ? (FBS / 64) * 16 * mlp::AST : 1];
   const int64_t n = a.n;
   const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
-  const int b0 = blockIdx.x * FBS;
+  const int b0 = xcd_block(blockIdx.x, gridDim.x) * FBS;
   const int nb = (int)min((int64_t)FBS, n - b0);
   // block exclusive prefix sum of the per-particle face counts
   const int cnt = tid < nb ? a.fcnt[b0 + tid] : 0;
@@ -587,15 +587,30 @@ __global__ void __launch_bounds__(FBS) fluxes_k(FluxArgs a) {
     }
     T p_learned = T(0);
     if (LEARNED) {
-      // the whole wavefront evaluates the network on its faces
-      uint16_t *act = mlp_act + wid * 64 * mlp::AST;
+      // the wavefront evaluates the network on the 16-face tiles that hold a
+      // face needing it (wave-uniform branches; other waves skip it)
       float x[mlp::NIN];
-      const bool use = active && !fs.skip;
-      if (use) features_of<T>(fs, x);
-      mlp::put_input(act, lane, use ? x : nullptr, a.net.norm);
-      const float y = mlp::forward_wave(act, a.net, lane);
-      if (use) p_learned = T(0.5) * (fs.SL.p + fs.SR.p) * T(expf(y));
-      if (use && !(p_learned > T(0))) p_learned = T(-1);  // rejected below
+      bool hard = false;
+      if (active && !fs.skip) {
+        features_of<T>(fs, x);
+        hard = mlp::needs_guess(x);
+      }
+      const uint64_t hmask = __ballot(hard);
+      if (hmask) {
+        uint16_t *tile = mlp_act + wid * 16 * mlp::AST;
+        float y = 0.f;
+#pragma unroll 1
+        for (int mt = 0; mt < 4; ++mt) {
+          if (((hmask >> (16 * mt)) & 0xffffull) == 0) continue;
+          if ((lane >> 4) == mt) mlp::put_input(tile, lane & 15, hard ? x : nullptr, a.net.norm);
+          const float yt = mlp::forward_tile(tile, a.net, lane);
+          if ((lane >> 4) == mt) y = yt;
+        }
+        if (hard) {
+          p_learned = T(0.5) * (fs.SL.p + fs.SR.p) * T(expf(y));
+          if (!(p_learned > T(0))) p_learned = T(-1);  // rejected below
+        }
+      }
     }
     double c[5] = {0, 0, 0, 0, 0};
     if (active) {

@@ -81,7 +81,7 @@ __device__ __forceinline__ void sym_apply(const T b[6], const T s[3], T g[3]) {
 
 template <typename T>
 __global__ void __launch_bounds__(BS) gradients_k(GradArgs a) {
-  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  const int64_t i = xcd_block(blockIdx.x, gridDim.x) * (int64_t)blockDim.x + threadIdx.x;
   const int64_t n = a.n;
   int64_t pairs = 0, singular = 0, inv64 = 0;
   if (i < n) {

@@ -217,6 +217,17 @@ const void *mlp_net_of(const void *state, void *net_out);
 void stage_begin(mfm_ctx *ctx, int stage);
 void stage_end(mfm_ctx *ctx, int stage);
 
+// The hardware hands workgroup b of a launch to XCD b % 8, and each XCD has
+// its own L2.  The neighbour loops renumber their workgroups so that every XCD
+// works through one contiguous range of the sorted (hence spatially compact)
+// particles and its L2 keeps serving the same neighbours.  A bijection on
+// [0, nb): XCD x takes nb / 8 workgroups, plus one if x < nb % 8.
+constexpr int NUM_XCD = 8;
+__host__ __device__ __forceinline__ int xcd_block(int b, int nb) {
+  const int q = nb / NUM_XCD, r = nb % NUM_XCD, x = b % NUM_XCD;
+  return x * q + (x < r ? x : r) + b / NUM_XCD;
+}
+
 static inline int blocks_for(int64_t n, int bs) { return (int)((n + bs - 1) / bs); }
 
 // Per-particle lists (candidates, faces) are stored in tiles of LIST_TILE

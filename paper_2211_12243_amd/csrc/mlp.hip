@@ -225,14 +225,13 @@ __global__ void adam_k(State s, float lr, float b1, float b2, float eps, int t) 
 
 __global__ void __launch_bounds__(64) mlp_predict_k(State s, const float *rows, int64_t n,
                                                     int64_t stride, float *y) {
-  __shared__ uint16_t act[64 * AST];
+  __shared__ uint16_t tile[16 * AST];
   const int lane = threadIdx.x;
   const int64_t row = (int64_t)blockIdx.x * 64 + lane;
   float x[NIN] = {0, 0, 0, 0, 0, 0};
   if (row < n)
     for (int k = 0; k < NIN; ++k) x[k] = rows[row * stride + k];
-  put_input(act, lane, row < n ? x : nullptr, s.norm);
-  const float out = forward_wave(act, net_of(s), lane);
+  const float out = forward_wave(tile, row < n ? x : nullptr, net_of(s), lane);
   if (row < n) y[row] = out;
 }
 

@@ -140,19 +140,48 @@ __device__ inline void put_input(uint16_t *act, int row, const float *x, const f
   for (int k = NIN; k < K1; ++k) act[row * AST + k] = 0;
 }
 
-// Forward pass for the 64 rows of a wave (act holds the inputs, row = lane);
-// returns this lane's output mapped back to the unstandardised target.
-__device__ inline float forward_wave(uint16_t *act, const Net &net, int lane) {
+// Forward pass of one 16-row tile held in act (row stride AST), in place.
+// Every lane returns the unstandardised output of row lane % 16.
+__device__ inline float forward_tile(uint16_t *act, const Net &net, int lane) {
   wave_lds_sync();
-  layer<4, K1>(act, AST, act, AST, net.wt + T_W1, net.p + OFF_B1, nullptr, 0, lane);
+  layer<1, K1>(act, AST, act, AST, net.wt + T_W1, net.p + OFF_B1, nullptr, 0, lane);
   wave_lds_sync();
-  layer<4, HID>(act, AST, act, AST, net.wt + T_W2, net.p + OFF_B2, nullptr, 0, lane);
+  layer<1, HID>(act, AST, act, AST, net.wt + T_W2, net.p + OFF_B2, nullptr, 0, lane);
   wave_lds_sync();
-  layer<4, HID>(act, AST, act, AST, net.wt + T_W3, net.p + OFF_B3, nullptr, 0, lane);
+  layer<1, HID>(act, AST, act, AST, net.wt + T_W3, net.p + OFF_B3, nullptr, 0, lane);
   wave_lds_sync();
-  float y = net.p[OFF_B4];
-  for (int k = 0; k < HID; ++k) y += from_bf16(act[lane * AST + k]) * net.p[OFF_W4 + k];
+  // output layer in FP32: lanes l, l+16, l+32, l+48 each sum 16 of the 64 terms
+  const int r = lane & 15, k0 = (lane >> 4) * 16;
+  float y = 0.f;
+#pragma unroll
+  for (int k = 0; k < 16; ++k) y += from_bf16(act[r * AST + k0 + k]) * net.p[OFF_W4 + k0 + k];
+  y += __shfl_xor(y, 16, 64);
+  y += __shfl_xor(y, 32, 64);
+  y += net.p[OFF_B4];
+  wave_lds_sync();
   return net.norm[2 * NIN] + net.norm[2 * NIN + 1] * y;
+}
+
+// Forward pass for the 64 rows of a wave, one tile at a time through a
+// 16-row buffer; lane l supplies row l (x null: a zero row) and gets its output.
+__device__ inline float forward_wave(uint16_t *tile, const float *x, const Net &net, int lane) {
+  float y = 0.f;
+  for (int mt = 0; mt < 4; ++mt) {
+    if ((lane >> 4) == mt) put_input(tile, lane & 15, x, net.norm);
+    const float yt = forward_tile(tile, net, lane);
+    if ((lane >> 4) == mt) y = yt;
+  }
+  return y;
+}
+
+// Faces whose plain starting value is least accurate -- a pressure ratio
+// above 2 (where the plain guess leaves the primitive-variable estimate) or a
+// normal velocity jump above half the mean sound speed.  Only these faces
+// are given to the network.
+constexpr float GATE_LOG_P = 0.69314718f;   // ln 2
+constexpr float GATE_DU = 0.40546511f;      // slog(0.5) = ln 1.5
+__device__ __host__ inline bool needs_guess(const float x[NIN]) {
+  return fabsf(x[1]) > GATE_LOG_P || fabsf(x[2]) > GATE_DU;
 }
 
 // Learned-guess features of a face in its frame (left and right states).

@@ -327,6 +327,16 @@ MLP_NIN, MLP_K1, MLP_HID, MLP_NNORM = 6, 16, 64, 16
 DUMP_STRIDE = 8  # floats per face record: 6 features, ln(p*/P_avg), plain-guess iterations
 
 
+GATE_LOG_P = 0.69314718  # ln 2: pressure ratio above 2
+GATE_DU = 0.40546511     # ln 1.5: |u_R - u_L| above half the mean sound speed
+
+
+def guess_gate(rows):
+    """Rows (torch tensor [n, 8] of face records) the flux loop would hand to
+    the network: the same test as the kernel's, on the stored features."""
+    return (rows[:, 1].abs() > GATE_LOG_P) | (rows[:, 2].abs() > GATE_DU)
+
+
 def mlp_param_layout() -> dict:
     """Offsets and shapes of the FP32 parameter vector (order fixed by the C ABI)."""
     shapes = [("W1", (MLP_K1, MLP_HID)), ("b1", (MLP_HID,)), ("W2", (MLP_HID, MLP_HID)),

@@ -119,10 +119,12 @@ def test_adam_first_step():
     assert np.all(step[pad] == 0.0)
 
 
-def _dump_faces(st, cfg, cap, precision="fp64"):
+def _dump_faces(st, cfg, cap, precision="fp64", steps_before=0):
     params = mfm.params_from_dict(cfg, precision=precision)
     ctx = mfm.Context(params, len(st["x"]))
     ps = mfm.ParticleSet(st)
+    for _ in range(steps_before):
+        mfm.mfm_step(ctx, ps, 1.0)
     rec = torch.zeros((cap, mfm.DUMP_STRIDE), dtype=torch.float32, device="cuda")
     mfm.mfm_face_dump(ctx, rec)
     mfm.mfm_reset_counters(ctx)
@@ -187,14 +189,21 @@ def _train(rows_dev, steps, lr, batch, seed=0):
 
 def test_training_and_learned_guess_parity():
     _need_gpu()
-    cfg = {"scheme": "mfm"}
-    print("[mlp] train on sedov32 faces", flush=True)
-    rec, _ = _dump_faces(W.sedov(n=32, seed=11), cfg, 4_000_000)
-    st, losses = _train(rec, 400, 3e-3, 8192)
+    print("[mlp] train on faces of sod24 and sedov32 (after 5 steps)", flush=True)
+    parts = []
+    for st, cfg, k in ((W.sod(n=24, seed=21), {"scheme": "mfv"}, 0),
+                       (W.sedov(n=32, seed=11), {"scheme": "mfm"}, 5)):
+        rec, _ = _dump_faces(st, cfg, 4_000_000, steps_before=k)
+        parts.append(rec[mfm.guess_gate(rec)])
+    rec = torch.cat(parts)
+    print(f"{rec.shape[0]} training faces pass the gate", flush=True)
+    assert rec.shape[0] > 1000
+    st, losses = _train(rec, 400, 3e-3, 4096)
     print("losses", [f"{v:.3e}" for v in losses], flush=True)
     assert losses[-1] < 0.3 * losses[0]
     # held-out set: prediction error of ln(p*/P_avg)
-    test_rows, _ = _dump_faces(W.sedov(n=24, seed=12), cfg, 2_000_000)
+    test_rows, _ = _dump_faces(W.sod(n=16, seed=12), {"scheme": "mfv"}, 2_000_000)
+    test_rows = test_rows[mfm.guess_gate(test_rows)]
     y = mfm.mfm_mlp_predict(st, test_rows).cpu().numpy()
     t = test_rows[:, 6].cpu().numpy()
     print(f"held-out rms error of ln(p*/P_avg): {np.sqrt(np.mean((y - t) ** 2)):.3e}, "
@@ -203,15 +212,25 @@ def test_training_and_learned_guess_parity():
     def attach(ctx):
         mfm.mfm_mlp_attach(ctx, st)
 
-    sedov = W.sedov(n=24, seed=3)
-    for precision, tol in (("fp64", 1e-12), ("mixed", 1e-5)):
-        print(f"[mlp] learned-guess parity sedov24 {precision}", flush=True)
-        gpu, new, dt, diag, ref = run_both(dict(cfg, guess=1), sedov, precision=precision,
-                                           setup=attach)
-        check_fields(gpu, new, dt, diag, ref, tol, sedov, normwise=(precision == "mixed"))
-        print(f"learned: iterations/face {diag['riemann_iters'] / diag['faces']:.3f}, "
-              f"fallbacks {diag['guess_fallback']} of {diag['faces']}", flush=True)
-        assert diag["guess_fallback"] < diag["faces"]
+    cases = (("sod16", W.sod(n=16, seed=1), {"scheme": "mfv"}),
+             ("sedov24", W.sedov(n=24, seed=3), {"scheme": "mfm"}))
+    for name, state, cfg in cases:
+        for precision, tol in (("fp64", 1e-12), ("mixed", 1e-5)):
+            plain_rec, plain = _dump_faces(state, cfg, 2_000_000, precision)
+            hard = mfm.guess_gate(plain_rec)
+            nh = max(int(hard.sum()), 1)
+            it_hard_plain = float(plain_rec[hard][:, 7].sum())
+            print(f"[mlp] learned-guess parity {name} {precision}", flush=True)
+            gpu, new, dt, diag, ref = run_both(dict(cfg, guess=1), state, precision=precision,
+                                               setup=attach)
+            check_fields(gpu, new, dt, diag, ref, tol, state, normwise=(precision == "mixed"))
+            saved = plain["riemann_iters"] - diag["riemann_iters"]
+            print(f"{name} {precision}: {int(hard.sum())} of {diag['faces']} faces gated; Newton "
+                  f"steps on them plain {it_hard_plain / nh:.3f}/face, learned "
+                  f"{(it_hard_plain - saved) / nh:.3f}/face; fallbacks "
+                  f"{diag['guess_fallback']}", flush=True)
+            assert diag["faces"] == plain["faces"]
+            assert diag["guess_fallback"] < nh
 
 
 def test_garbage_weights_fall_back():
@@ -224,11 +243,14 @@ def test_garbage_weights_fall_back():
     st = mfm.MLPState(params, norm)
     cfg = {"scheme": "mfv", "guess": 1}
     sod = W.sod(n=16, seed=1)
+    rec, _ = _dump_faces(sod, {"scheme": "mfv"}, 1_000_000)
+    n_hard = int(mfm.guess_gate(rec).sum())
+    assert n_hard > 0
     print("[mlp] garbage weights sod16", flush=True)
     gpu, new, dt, diag, ref = run_both(cfg, sod, setup=lambda ctx: mfm.mfm_mlp_attach(ctx, st))
     check_fields(gpu, new, dt, diag, ref, 1e-12, sod)
-    # huge outputs overflow exp(): every solved face falls back
-    assert diag["guess_fallback"] == diag["faces"] - diag["vacuum"]
+    # huge outputs overflow exp(): every face given to the network falls back
+    assert diag["guess_fallback"] == n_hard
 
 
 def test_learned_guess_without_network_is_an_error():
