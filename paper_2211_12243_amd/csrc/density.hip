@@ -3,8 +3,9 @@
 //
 // cand_k: one lane per particle scans the 27 cells around its own (cell side
 // >= cell_margin * max H, so every pair closer than the side is found) and
-// keeps the candidates with r < side as (index, r^2) in a tiled list (see
-// list_at: each lane fills whole cache lines of its own entries).  The list is a superset of every neighbour set the step uses:
+// keeps the candidates with r < side as (index, r^2) in the k-major list
+// (list_at), staged through LDS so that HBM sees whole planes.  The list is a
+// superset of every neighbour set the step uses:
 // the gradient loop filters r < H_i and the flux loop r < max(H_i, H_j).
 //
 // density_k: each lane solves
@@ -33,62 +34,122 @@ struct CandArgs {
   int64_t *counters;
 };
 
-__global__ void __launch_bounds__(BS) cand_k(CandArgs a, CellGrid g) {
-  const int64_t i = xcd_block(blockIdx.x, gridDim.x) * (int64_t)blockDim.x + threadIdx.x;
+// The search runs one wavefront per workgroup.  List entries are appended in
+// a per-lane order, so a lane's k-th entry would be a lone 4- and 8-byte store
+// into plane k; such scattered partial lines were evicted from L2 and written
+// to HBM several times over.  Each lane therefore keeps its newest entries in
+// a ring of RING planes in LDS (lane-private columns: no barrier is needed),
+// and a plane is written out -- 64 consecutive particles, one coalesced
+// store per array -- as soon as every lane of the wave has passed it.  A lane
+// running more than RING entries ahead of the slowest one stores directly
+// from then on.
+constexpr int CBS = 64;
+constexpr int RING = 16;
+constexpr int UNR = 4;  // candidate loads issued together
+
+__device__ __forceinline__ int wave_min_i32(int v) {
+  for (int o = 32; o > 0; o >>= 1) v = min(v, __shfl_xor(v, o, 64));
+  return v;
+}
+__device__ __forceinline__ int wave_max_i32(int v) {
+  for (int o = 32; o > 0; o >>= 1) v = max(v, __shfl_xor(v, o, 64));
+  return v;
+}
+
+__global__ void __launch_bounds__(CBS) cand_k(CandArgs a, CellGrid g) {
+  __shared__ int32_t s_idx[RING][CBS];
+  __shared__ double s_r2[RING][CBS];
+  const int lane = threadIdx.x;
+  const int64_t i = (int64_t)xcd_block(blockIdx.x, gridDim.x) * CBS + lane;
   const int64_t n = a.n;
-  int64_t overflow = 0;
-  if (i < n) {
-    const double4 pi = a.pos[i];
-    const int cx = cell_coord(pi.x, g.inv[0], g.nc[0]);
-    const int cy = cell_coord(pi.y, g.inv[1], g.nc[1]);
-    const int cz = cell_coord(pi.z, g.inv[2], g.nc[2]);
-    const double R2 = g.side_min * g.side_min;
-    // position inside the own cell in cell units; a neighbour cell whose
-    // nearest point is farther than the search radius is skipped (the test is
-    // in FP32 with a margin, so it only ever skips cells that hold no candidate)
-    const float fx = (float)(pi.x * g.inv[0] - cx), fy = (float)(pi.y * g.inv[1] - cy),
-                fz = (float)(pi.z * g.inv[2] - cz);
-    const float sx = (float)(1.0 / g.inv[0]), sy = (float)(1.0 / g.inv[1]),
-                sz = (float)(1.0 / g.inv[2]);
-    const float lim = (float)R2 * 1.0001f;
-    int k = 0;
-    for (int dz = -1; dz <= 1; ++dz) {
-      const float gz = sz * fmaxf(dz > 0 ? 1.0f - fz : (dz < 0 ? fz : 0.0f), 0.0f);
-      int zz = cz + dz;
-      zz = zz < 0 ? zz + g.nc[2] : (zz >= g.nc[2] ? zz - g.nc[2] : zz);
-      for (int dy = -1; dy <= 1; ++dy) {
-        const float gy = sy * fmaxf(dy > 0 ? 1.0f - fy : (dy < 0 ? fy : 0.0f), 0.0f);
-        int yy = cy + dy;
-        yy = yy < 0 ? yy + g.nc[1] : (yy >= g.nc[1] ? yy - g.nc[1] : yy);
-        for (int dx = -1; dx <= 1; ++dx) {
-          const float gx = sx * fmaxf(dx > 0 ? 1.0f - fx : (dx < 0 ? fx : 0.0f), 0.0f);
-          if (gx * gx + gy * gy + gz * gz > lim) continue;
+  const bool active = i < n;
+  const int cap = a.max_list;
+  const double4 pi = a.pos[active ? i : n - 1];
+  const int cx = cell_coord(pi.x, g.inv[0], g.nc[0]);
+  const int cy = cell_coord(pi.y, g.inv[1], g.nc[1]);
+  const int cz = cell_coord(pi.z, g.inv[2], g.nc[2]);
+  const double R2 = g.side_min * g.side_min;
+  // position inside the own cell in cell units; a neighbour cell whose
+  // nearest point is farther than the search radius is skipped (the test is
+  // in FP32 with a margin, so it only ever skips cells that hold no candidate)
+  const float fx = (float)(pi.x * g.inv[0] - cx), fy = (float)(pi.y * g.inv[1] - cy),
+              fz = (float)(pi.z * g.inv[2] - cz);
+  const float sx = (float)(1.0 / g.inv[0]), sy = (float)(1.0 / g.inv[1]),
+              sz = (float)(1.0 / g.inv[2]);
+  const float lim = (float)R2 * 1.0001f;
+  int k = 0;                 // entries found (may exceed cap: overflow)
+  int direct_from = 1 << 30; // first entry this lane stored directly
+  int base = 0;              // planes [0, base) are written out (wave-uniform)
+  for (int dz = -1; dz <= 1; ++dz) {
+    const float gz = sz * fmaxf(dz > 0 ? 1.0f - fz : (dz < 0 ? fz : 0.0f), 0.0f);
+    int zz = cz + dz;
+    zz = zz < 0 ? zz + g.nc[2] : (zz >= g.nc[2] ? zz - g.nc[2] : zz);
+    for (int dy = -1; dy <= 1; ++dy) {
+      const float gy = sy * fmaxf(dy > 0 ? 1.0f - fy : (dy < 0 ? fy : 0.0f), 0.0f);
+      int yy = cy + dy;
+      yy = yy < 0 ? yy + g.nc[1] : (yy >= g.nc[1] ? yy - g.nc[1] : yy);
+      for (int dx = -1; dx <= 1; ++dx) {
+        const float gx = sx * fmaxf(dx > 0 ? 1.0f - fx : (dx < 0 ? fx : 0.0f), 0.0f);
+        if (active && gx * gx + gy * gy + gz * gz <= lim) {
           int xx = cx + dx;
           xx = xx < 0 ? xx + g.nc[0] : (xx >= g.nc[0] ? xx - g.nc[0] : xx);
           const int2 rg = g.range[morton3(xx, yy, zz)];
-          for (int j = rg.x; j < rg.x + rg.y; ++j) {
-            const double4 pj = a.pos[j];
-            double ex = min_image(pj.x - pi.x, g.box[0], g.half[0]);
-            double ey = min_image(pj.y - pi.y, g.box[1], g.half[1]);
-            double ez = min_image(pj.z - pi.z, g.box[2], g.half[2]);
-            double r2 = ex * ex + ey * ey + ez * ez;
-            if (r2 < R2 && j != i) {
-              if (k < a.max_list) {
-                const int64_t at = list_at(i, k, n);
-                a.cand[at] = j;
-                a.cand_r2[at] = r2;
+          const int jend = rg.x + rg.y;
+          // UNR independent loads in flight per lane, then the tests in order
+          for (int j0 = rg.x; j0 < jend; j0 += UNR) {
+            double4 pj[UNR];
+#pragma unroll
+            for (int u = 0; u < UNR; ++u) pj[u] = a.pos[j0 + u < jend ? j0 + u : j0];
+#pragma unroll
+            for (int u = 0; u < UNR; ++u) {
+              const int j = j0 + u;
+              const double ex = min_image(pj[u].x - pi.x, g.box[0], g.half[0]);
+              const double ey = min_image(pj[u].y - pi.y, g.box[1], g.half[1]);
+              const double ez = min_image(pj[u].z - pi.z, g.box[2], g.half[2]);
+              const double r2 = ex * ex + ey * ey + ez * ez;
+              if (j < jend && r2 < R2 && j != i) {
+                if (k < cap) {
+                  if (k < direct_from && k < base + RING) {
+                    s_idx[k % RING][lane] = j;
+                    s_r2[k % RING][lane] = r2;
+                  } else {
+                    if (k < direct_from) direct_from = k;
+                    const int64_t at = list_at(i, k, n);
+                    a.cand[at] = j;
+                    a.cand_r2[at] = r2;
+                  }
+                }
+                ++k;
               }
-              ++k;
             }
           }
         }
+        // write out the planes every lane has passed
+        const int done = wave_min_i32(active ? min(k, cap) : (1 << 30));
+        for (int p = base; p < done; ++p) {
+          if (active && p < direct_from) {
+            const int64_t at = list_at(i, p, n);
+            a.cand[at] = s_idx[p % RING][lane];
+            a.cand_r2[at] = s_r2[p % RING][lane];
+          }
+        }
+        base = done > base ? done : base;
       }
     }
-    if (k > a.max_list) {
-      overflow = 1;
-      k = a.max_list;
+  }
+  const int kc = min(k, cap);
+  const int last = wave_max_i32(active ? kc : 0);
+  for (int p = base; p < last; ++p) {
+    if (active && p < kc && p < direct_from) {
+      const int64_t at = list_at(i, p, n);
+      a.cand[at] = s_idx[p % RING][lane];
+      a.cand_r2[at] = s_r2[p % RING][lane];
     }
-    a.cand_cnt[i] = k;
+  }
+  int64_t overflow = 0;
+  if (active) {
+    overflow = k > cap ? 1 : 0;
+    a.cand_cnt[i] = kc;
   }
   count_add(a.counters + C_LIST_OVERFLOW, overflow);
 }
@@ -241,7 +302,7 @@ hipError_t launch_candidates(mfm_ctx *ctx, const mfm_particles *pp) {
   a.cand_r2 = ctx->cand_r2;
   a.cand_cnt = ctx->cand_cnt;
   a.counters = ctx->counters;
-  cand_k<<<blocks_for(pp->n, BS), BS, 0, ctx->stream>>>(a, ctx->grid);
+  cand_k<<<blocks_for(pp->n, CBS), CBS, 0, ctx->stream>>>(a, ctx->grid);
   return hipGetLastError();
 }
 
