@@ -50,6 +50,7 @@ constexpr int GUESS_MAXIT = 8;
 template <typename T>
 struct Gas {
   T gamma, g1, g2, g3, g4, g5, g6, g7, inv_gm1;
+  T sg5;  // sqrt(g5)
 };
 
 struct FluxArgs {
@@ -79,30 +80,81 @@ __device__ __forceinline__ const Gas<double> &gas_of<double>(const FluxArgs &a) 
 template <>
 __device__ __forceinline__ const Gas<float> &gas_of<float>(const FluxArgs &a) { return a.Gf; }
 
-// x^(1/m) (= x^g1), x > 0.
-template <typename T, int M>
-__device__ __forceinline__ T root_m(T x, const Gas<T> &G) {
-  if (M == 0) return pow(x, G.g1);
-  if (sizeof(T) == sizeof(float)) return (T)exp2f(log2f((float)x) * (1.0f / (float)M));
-  double y = (double)exp2f((1.0f / (float)M) * log2f((float)x));
-  if (!(y > 0.0) || !isfinite(y)) return pow(x, G.g1);  // outside the FP32 range
-  constexpr double im = 1.0 / (double)(M > 0 ? M : 1);
-#pragma unroll
-  for (int it = 0; it < 2; ++it) {
-    double ym1 = 1.0;  // y^(m-1)
-#pragma unroll
-    for (int k = 1; k < M; ++k) ym1 *= y;
-    y = y + ((double)x / ym1 - y) * im;
-  }
-  return (T)y;
-}
-
 template <int K, typename T>
 __device__ __forceinline__ T ipow(T x) {
   T r = T(1);
 #pragma unroll
   for (int q = 0; q < K; ++q) r *= x;
   return r;
+}
+
+// Reciprocal and reciprocal square root from the hardware estimates.  FP64:
+// two Newton steps on the estimate (error a few ulp, against the half ulp of
+// the IEEE division and square-root sequences, at half their instructions);
+// FP32: the estimate itself (1 ulp).  Arguments are finite and positive.
+template <typename T>
+__device__ __forceinline__ T frcp(T x);
+template <>
+__device__ __forceinline__ double frcp<double>(double x) {
+  double r = __builtin_amdgcn_rcp(x);
+  r = fma(r, fma(-x, r, 1.0), r);
+  return fma(r, fma(-x, r, 1.0), r);
+}
+template <>
+__device__ __forceinline__ float frcp<float>(float x) { return __builtin_amdgcn_rcpf(x); }
+
+template <typename T>
+__device__ __forceinline__ T frsq(T x);
+template <>
+__device__ __forceinline__ double frsq<double>(double x) {
+  double y = __builtin_amdgcn_rsq(x);
+  const double hx = 0.5 * x;
+  y = y * fma(-hx * y, y, 1.5);
+  return y * fma(-hx * y, y, 1.5);
+}
+template <>
+__device__ __forceinline__ float frsq<float>(float x) { return __builtin_amdgcn_rsqf(x); }
+
+// The same for any x > 0: below the normal range (where the estimates flush
+// to infinity) the IEEE sequences.  A face whose separation sits just inside
+// the larger support radius has a kernel weight, and so a |A|^2, that can
+// underflow FP32.
+template <typename T>
+__device__ __forceinline__ T rsq_any(T x) {
+  constexpr T tiny = sizeof(T) == sizeof(float) ? T(1.17549435e-38f) : T(2.2250738585072014e-308);
+  if (x >= tiny) return frsq<T>(x);
+  return T(1) / sqrt(x);
+}
+template <typename T>
+__device__ __forceinline__ T rcp_any(T x) {
+  constexpr T tiny = sizeof(T) == sizeof(float) ? T(1.17549435e-38f) : T(2.2250738585072014e-308);
+  if (x >= tiny) return frcp<T>(x);
+  return T(1) / x;
+}
+
+// x^(-1/m) (= x^-g1), x > 0.  FP64 (m = 5, 7): an FP32 seed and two
+// division-free Newton steps z += z (1 - x z^m) / m (quadratic: ~1e-7 ->
+// ~1e-13 -> roundoff); FP32: the hardware exp2/log2.  Other m: pow().
+template <typename T, int M>
+__device__ __forceinline__ T iroot_m(T x, const Gas<T> &G) {
+  if (M == 0) return pow(x, -G.g1);
+  if (sizeof(T) == sizeof(float)) return (T)exp2f(log2f((float)x) * (-1.0f / (float)M));
+  constexpr int MM = M > 0 ? M : 1;
+  constexpr double im = 1.0 / (double)MM;
+  double z = (double)exp2f((-1.0f / (float)MM) * log2f((float)x));
+  if (!(z > 0.0) || !isfinite(z)) return pow(x, -G.g1);  // outside the FP32 range
+#pragma unroll
+  for (int it = 0; it < 2; ++it) z = fma(z * im, fma(-(double)x, ipow<MM>(z), 1.0), z);
+  return (T)z;
+}
+
+// x^(1/m) = x * (x^(-1/m))^(m-1), x > 0.
+template <typename T, int M>
+__device__ __forceinline__ T root_m(T x, const Gas<T> &G) {
+  if (M == 0) return pow(x, G.g1);
+  if (sizeof(T) == sizeof(float)) return (T)exp2f(log2f((float)x) * (1.0f / (float)M));
+  constexpr int MM = M > 0 ? M : 1;
+  return x * ipow<MM - 1>(iroot_m<T, M>(x, G));
 }
 
 template <typename T>
@@ -113,17 +165,23 @@ struct Side {
   T B;    // (gamma - 1) / (gamma + 1) p
   T prc;  // p / (rho c)
   T g4c;  // 2 c / (gamma - 1)
+  T sA;   // sqrt(A)
 };
 
 template <typename T>
-__device__ __forceinline__ Side<T> make_side(T r, T u, T p, T c, const Gas<T> &G) {
+__device__ __forceinline__ Side<T> make_side(T r, T u, T p, const Gas<T> &G) {
   Side<T> s;
-  s.r = r; s.u = u; s.p = p; s.c = c;
-  s.ip = T(1) / p;
-  s.A = G.g5 / r;
+  const T ir = frcp<T>(r);
+  const T c2 = G.gamma * p * ir;
+  const T ic = frsq<T>(c2);  // 1 / c
+  s.r = r; s.u = u; s.p = p;
+  s.c = c2 * ic;
+  s.ip = frcp<T>(p);
+  s.A = G.g5 * ir;
+  s.sA = G.sg5 * frsq<T>(r);
   s.B = G.g6 * p;
-  s.prc = p / (r * c);
-  s.g4c = G.g4 * c;
+  s.prc = p * ir * ic;
+  s.g4c = G.g4 * s.c;
   return s;
 }
 
@@ -136,29 +194,31 @@ __device__ __forceinline__ void pressure_fn(T ps, T ips, const Side<T> &s, const
     f = s.g4c * (e - T(1));
     df = e * s.prc * ips;                     // (p*/p_K)^(g1 - 1) / (rho_K c_K)
   } else {
-    const T t = T(1) / (s.B + ps);
-    const T q = sqrt(s.A * t);
+    const T y = frsq<T>(s.B + ps);  // (B + p)^(-1/2)
+    const T q = s.sA * y;           // sqrt(A / (B + p))
     const T dp = ps - s.p;
     f = dp * q;
-    df = q * (T(1) - T(0.5) * dp * t);
+    df = q * (T(1) - T(0.5) * dp * y * y);
   }
 }
 
 // Newton iteration on f(p) = f_L(p) + f_R(p) + du from p0, then u*.
-// quadratic_exit: a step below sqrt(tol) ends the iteration (the next error is
-// its square) and u* takes the first-order update of f_L, f_R.
+// qtol > 0: a relative step below sqrt(qtol) ends the iteration -- the error
+// left after it is of the order of its square -- and u* takes the first-order
+// update of f_L, f_R (this saves the final evaluation of both pressure
+// functions).
 // guard > 0: the start is a guess to be judged; return 3 (reject) if the
 // second residual exceeds the first or more than guard iterations are needed.
 // Returns 0 converged, 2 iteration cap, 3 guess rejected.
 template <typename T, int M>
 __device__ int riemann_newton(const Gas<T> &G, const Side<T> &L, const Side<T> &R, T p0,
-                              T pfloor, T tol, int maxit, bool quadratic_exit, int guard, T &ps,
-                              T &us, int &iters) {
+                              T pfloor, T tol, int maxit, T qtol, int guard, T &ps, T &us,
+                              int &iters) {
   const T du = R.u - L.u;
   T p = p0, fL, dfL, fR, dfR, res0 = T(0);
   int status = 2;
   for (int it = 1; it <= maxit; ++it) {
-    const T ip = T(1) / p;
+    const T ip = frcp<T>(p);
     pressure_fn<T, M>(p, ip, L, G, fL, dfL);
     pressure_fn<T, M>(p, ip, R, G, fR, dfR);
     const T res = fL + fR + du;
@@ -166,11 +226,11 @@ __device__ int riemann_newton(const Gas<T> &G, const Side<T> &L, const Side<T> &
       if (it == 1) res0 = fabs(res);
       if ((it == 2 && fabs(res) > res0) || it > guard) return 3;
     }
-    T pn = p - res / (dfL + dfR);
+    T pn = p - res * frcp<T>(dfL + dfR);
     if (pn < T(0)) pn = pfloor;
     const T step = T(2) * fabs(pn - p);  // relative change: step / (pn + p)
     ++iters;
-    if (quadratic_exit && step * step < tol * (pn + p) * (pn + p)) {
+    if (step * step < qtol * (pn + p) * (pn + p)) {
       const T dp = pn - p;
       ps = pn;
       us = T(0.5) * (L.u + R.u) + T(0.5) * ((fR + dfR * dp) - (fL + dfL * dp));
@@ -183,7 +243,7 @@ __device__ int riemann_newton(const Gas<T> &G, const Side<T> &L, const Side<T> &
       break;
     }
   }
-  const T ip = T(1) / p;
+  const T ip = frcp<T>(p);
   pressure_fn<T, M>(p, ip, L, G, fL, dfL);
   pressure_fn<T, M>(p, ip, R, G, fR, dfR);
   ps = p;
@@ -203,13 +263,13 @@ __device__ T plain_guess(const Gas<T> &G, const Side<T> &L, const Side<T> &R) {
   if (ppv < pmin) {
     // two-rarefaction value: [(cL + cR - g7 du) / (cL pL^-g1 + cR pR^-g1)]^(1/g1)
     const T num = L.c + R.c - G.g7 * du;
-    const T den = L.c / root_m<T, M>(L.p, G) + R.c / root_m<T, M>(R.p, G);
-    const T t = num / den;
+    const T den = L.c * iroot_m<T, M>(L.p, G) + R.c * iroot_m<T, M>(R.p, G);
+    const T t = num * frcp<T>(den);
     return M ? ipow<(M > 0 ? M : 1)>(t) : pow(t, T(1) / G.g1);
   }
-  const T gL = sqrt(L.A / (L.B + ppv));
-  const T gR = sqrt(R.A / (R.B + ppv));
-  return (gL * L.p + gR * R.p - du) / (gL + gR);
+  const T gL = L.sA * frsq<T>(L.B + ppv);
+  const T gR = R.sA * frsq<T>(R.B + ppv);
+  return (gL * L.p + gR * R.p - du) * frcp<T>(gL + gR);
 }
 
 // Exact Riemann solve: 0 converged, 1 vacuum, 2 iteration cap.  p_learned > 0
@@ -226,9 +286,12 @@ __device__ int riemann_solve(const Gas<T> &G, const Side<T> &L, const Side<T> &R
     return 1;
   }
   const T pfloor = T(1e-10) * T(0.5) * (L.p + R.p);
+  // FP64: stop once a step is below 1e-2 sqrt(tol); the root is then within
+  // ~1e-4 tol.  FP32: run to the tolerance (the FP64 check follows).
+  const T qtol = sizeof(T) == sizeof(double) ? T(1e-4) * tol : T(0);
   if (p_learned > T(0)) {
     if (p_learned > pfloor && isfinite(p_learned)) {
-      const int st = riemann_newton<T, M>(G, L, R, p_learned, pfloor, tol, maxit, false,
+      const int st = riemann_newton<T, M>(G, L, R, p_learned, pfloor, tol, maxit, qtol,
                                           GUESS_MAXIT, ps, us, iters);
       if (st != 3) return st;
     }
@@ -236,7 +299,7 @@ __device__ int riemann_solve(const Gas<T> &G, const Side<T> &L, const Side<T> &R
   }
   T p0 = plain_guess<T, M>(G, L, R);
   if (!(p0 > pfloor)) p0 = pfloor;
-  return riemann_newton<T, M>(G, L, R, p0, pfloor, tol, maxit, false, 0, ps, us, iters);
+  return riemann_newton<T, M>(G, L, R, p0, pfloor, tol, maxit, qtol, 0, ps, us, iters);
 }
 
 // The exact solution at x/t = 0 in the face frame (Toro's sampling).
@@ -307,11 +370,14 @@ __device__ __forceinline__ T pair_limit(T qf, T qo, T qn, T psi1, T psi2) {
   const T dq = fabs(qo - qn);
   const T d1 = psi1 * dq, d2 = psi2 * dq;
   const T qbar = T(0.5) * (qo + qn);
+  // qo / (1 + d1 / |qo|) written with one reciprocal (d1 > 0 here)
+  const T aq = fabs(qo);
+  const T soft = qo * aq * rcp_any<T>(aq + d1);
   if (qo < qn) {
-    const T lower = ((qo - d1) * qo > T(0)) ? qo - d1 : qo / (T(1) + d1 / fabs(qo));
+    const T lower = ((qo - d1) * qo > T(0)) ? qo - d1 : soft;
     return fmax(lower, fmin(qbar + d2, qf));
   }
-  const T upper = ((qo + d1) * qo > T(0)) ? qo + d1 : qo / (T(1) + d1 / fabs(qo));
+  const T upper = ((qo + d1) * qo > T(0)) ? qo + d1 : soft;
   return fmin(upper, fmax(qbar - d2, qf));
 }
 
@@ -387,7 +453,7 @@ __device__ void face_prepare(const FaceIn<T> &Ls, const FaceIn<T> &Rs, const Flu
   d[2] = T(min_image(Rs.z - Ls.z, a.box[2], a.half[2]));
   const T r2 = d[0] * d[0] + d[1] * d[1] + d[2] * d[2];
   if (r2 == T(0)) return;
-  const T r = sqrt(r2);
+  const T r = r2 * rsq_any<T>(r2);
   // A_ij = V_i V_j (W(r, H_i) B_i + W(r, H_j) B_j) d
   const T WL = T(W_NORM) * Ls.ih * Ls.ih * Ls.ih * spline_wt<T>(r * Ls.ih);
   const T WR = T(W_NORM) * Rs.ih * Rs.ih * Rs.ih * spline_wt<T>(r * Rs.ih);
@@ -400,11 +466,11 @@ __device__ void face_prepare(const FaceIn<T> &Ls, const FaceIn<T> &Rs, const Flu
                WR * (bR[1] * d[0] + bR[3] * d[1] + bR[4] * d[2]));
   A[2] = VV * (WL * (bL[2] * d[0] + bL[4] * d[1] + bL[5] * d[2]) +
                WR * (bR[2] * d[0] + bR[4] * d[1] + bR[5] * d[2]));
-  const T Am = sqrt(A[0] * A[0] + A[1] * A[1] + A[2] * A[2]);
-  if (Am == T(0)) return;
+  const T Am2 = A[0] * A[0] + A[1] * A[1] + A[2] * A[2];
+  if (Am2 == T(0)) return;
+  const T iA = rsq_any<T>(Am2);
   fs.skip = false;
-  fs.Am = Am;
-  const T iA = T(1) / Am;
+  fs.Am = Am2 * iA;
 #pragma unroll
   for (int k = 0; k < 3; ++k) fs.nv[k] = A[k] * iA;
 
@@ -455,8 +521,8 @@ __device__ void face_prepare(const FaceIn<T> &Ls, const FaceIn<T> &Rs, const Flu
   }
   const T uL = fs.wL[0] * fs.nv[0] + fs.wL[1] * fs.nv[1] + fs.wL[2] * fs.nv[2];
   const T uR = fs.wR[0] * fs.nv[0] + fs.wR[1] * fs.nv[1] + fs.wR[2] * fs.nv[2];
-  fs.SL = make_side<T>(qL[0], uL, qL[4], sqrt(G.gamma * qL[4] / qL[0]), G);
-  fs.SR = make_side<T>(qR[0], uR, qR[4], sqrt(G.gamma * qR[4] / qR[0]), G);
+  fs.SL = make_side<T>(qL[0], uL, qL[4], G);
+  fs.SR = make_side<T>(qR[0], uR, qR[4], G);
 }
 
 // Riemann solve and flux of a prepared face: c = |A_ij| F_ij (FP64).
@@ -485,11 +551,11 @@ __device__ void face_solve(FaceState<T> &fs, const FluxArgs &a, T p_learned, dou
     // the quadratic regime of the relative tolerance
     const Gas<double> &G64 = a.G;
     const double rl = SL.r, pl = SL.p, rr = SR.r, pr = SR.p;
-    const Side<double> L64 = make_side<double>(rl, (double)SL.u, pl, sqrt(G64.gamma * pl / rl), G64);
-    const Side<double> R64 = make_side<double>(rr, (double)SR.u, pr, sqrt(G64.gamma * pr / rr), G64);
+    const Side<double> L64 = make_side<double>(rl, (double)SL.u, pl, G64);
+    const Side<double> R64 = make_side<double>(rr, (double)SR.u, pr, G64);
     const double pfloor = 1e-10 * 0.5 * (pl + pr);
     st = riemann_newton<double, M>(G64, L64, R64, fmax(ps64, pfloor), pfloor, a.rtol, a.rmaxit,
-                                   true, 0, ps64, us64, iters);
+                                   a.rtol, 0, ps64, us64, iters);
   }
   if (st == 2) fs.flags |= F_MAXIT;
   ps_out = ps64;
@@ -532,7 +598,7 @@ __device__ __forceinline__ void features_of(const FaceState<T> &fs, float x[mlp:
 }
 
 template <typename T, int SCHEME, int M, bool LEARNED>
-__global__ void __launch_bounds__(FBS) __attribute__((amdgpu_waves_per_eu(LEARNED ? 2 : 1))) fluxes_k(FluxArgs a) {
+__global__ void __launch_bounds__(FBS) __attribute__((amdgpu_waves_per_eu(2))) fluxes_k(FluxArgs a) {
   __shared__ int pref[FBS + 1];
   __shared__ int wsum[FBS / 64];
   __shared__ double acc[5][FBS];
@@ -708,6 +774,7 @@ Gas<T> make_gas(double g) {
   G.g6 = T((g - 1.0) / (g + 1.0));
   G.g7 = T(0.5 * (g - 1.0));
   G.inv_gm1 = T(1.0 / (g - 1.0));
+  G.sg5 = T(sqrt(2.0 / (g + 1.0)));
   return G;
 }
 
