@@ -47,15 +47,6 @@ constexpr int CBS = 64;
 constexpr int RING = 16;
 constexpr int UNR = 4;  // candidate loads issued together
 
-__device__ __forceinline__ int wave_min_i32(int v) {
-  for (int o = 32; o > 0; o >>= 1) v = min(v, __shfl_xor(v, o, 64));
-  return v;
-}
-__device__ __forceinline__ int wave_max_i32(int v) {
-  for (int o = 32; o > 0; o >>= 1) v = max(v, __shfl_xor(v, o, 64));
-  return v;
-}
-
 __global__ void __launch_bounds__(CBS) cand_k(CandArgs a, CellGrid g) {
   __shared__ int32_t s_idx[RING][CBS];
   __shared__ double s_r2[RING][CBS];
@@ -125,7 +116,8 @@ __global__ void __launch_bounds__(CBS) cand_k(CandArgs a, CellGrid g) {
           }
         }
         // write out the planes every lane has passed
-        const int done = wave_min_i32(active ? min(k, cap) : (1 << 30));
+        int done = wave_min_i32(active ? min(k, cap) : (1 << 30));
+        if (done >= (1 << 30)) done = base;
         for (int p = base; p < done; ++p) {
           if (active && p < direct_from) {
             const int64_t at = list_at(i, p, n);
@@ -162,6 +154,7 @@ struct DensityArgs {
   double *gin;  // GIN_STRIDE doubles per particle
   const int32_t *cand, *cand_cnt;
   const double *cand_r2;
+  int32_t *gl, *gl_cnt;
   double gamma, n_ngb, ncond_max, ngb_boost, h_tol;
   int h_maxit, max_boosts;
   int64_t *counters;
@@ -189,9 +182,11 @@ __device__ double cond3(const double e[6]) {
 __global__ void __launch_bounds__(BS) density_k(DensityArgs a, CellGrid g) {
   const int64_t i = xcd_block(blockIdx.x, gridDim.x) * (int64_t)blockDim.x + threadIdx.x;
   const int64_t n = a.n;
+  const bool active = i < n;
   int64_t noconv = 0, boosts = 0, fails = 0, overflow = 0;
-  if (i < n) {
-    const int cnt = a.cand_cnt[i];
+  int cnt = 0, gc = 0;
+  if (active) {
+    cnt = a.cand_cnt[i];
     const double cover = g.side_min;
     double h = a.H[i];
     double target = a.n_ngb;
@@ -238,13 +233,18 @@ __global__ void __launch_bounds__(BS) density_k(DensityArgs a, CellGrid g) {
       const double4 pi = a.pos[i];
       double ws = 1.0;
       double e[6] = {0, 0, 0, 0, 0, 0};
+      // this pass also writes the gather set r < H_i for the gradient loop
+      // (rewritten if a boost follows)
+      gc = 0;
       for (int k = 0; k < cnt; ++k) {
         const double r2 = a.cand_r2[list_at(i, k, n)];
         if (r2 < h2) {
+          const int j = a.cand[list_at(i, k, n)];
+          a.gl[list_at(i, gc++, n)] = j;
           const double w = spline_w(sqrt(r2) * ih);
           ws += w;
           if (r2 > 0.0) {
-            const double4 pj = a.pos[a.cand[list_at(i, k, n)]];
+            const double4 pj = a.pos[j];
             const double dx = min_image(pj.x - pi.x, g.box[0], g.half[0]);
             const double dy = min_image(pj.y - pi.y, g.box[1], g.half[1]);
             const double dz = min_image(pj.z - pi.z, g.box[2], g.half[2]);
@@ -284,6 +284,7 @@ __global__ void __launch_bounds__(BS) density_k(DensityArgs a, CellGrid g) {
     gr[1] = make_double4(V, rho, a.vx[i], a.vy[i]);
     gr[2] = make_double4(a.vz[i], P, cs, 0.0);
     gr[3] = make_double4(0.0, 0.0, 0.0, 0.0);
+    a.gl_cnt[i] = gc;
   }
   count_add(a.counters + C_PASS_NOCONV, noconv);
   count_add(a.counters + C_PASS_BOOSTS, boosts);
@@ -316,6 +317,8 @@ hipError_t launch_density(mfm_ctx *ctx, const mfm_particles *pp) {
   a.cand = ctx->cand;
   a.cand_cnt = ctx->cand_cnt;
   a.cand_r2 = ctx->cand_r2;
+  a.gl = ctx->gl;
+  a.gl_cnt = ctx->gl_cnt;
   a.gamma = ctx->p.gamma;
   a.n_ngb = ctx->p.n_ngb;
   a.ncond_max = ctx->p.ncond_max;

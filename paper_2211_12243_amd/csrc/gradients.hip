@@ -32,6 +32,7 @@ struct GradArgs {
   const double4 *pos;   // (x, y, z, 0) per particle
   const int32_t *cand, *cand_cnt;
   const double *cand_r2;
+  const int32_t *gl, *gl_cnt;
   double *B, *grad, *ncond, *dt_i, *rec;
   int32_t *fslot, *fcnt;
   double box[3], half[3];
@@ -105,26 +106,25 @@ __global__ void __launch_bounds__(BS) gradients_k(GradArgs a) {
     }
     T vsig = T(0);
     int nf = 0;
-    const int cnt = a.cand_cnt[i];
-    for (int k = 0; k < cnt; ++k) {
-      const int64_t at = list_at(i, k, n);
-      const int j = a.cand[at];
-      const double r2 = a.cand_r2[at];
-      // faces of the flux loop: r < max(H_i, H_j); one evaluation per face
-      // inside a block, one per side across blocks
-      const bool gather = r2 < h2;  // j is in the gather set of i (then also a face)
-      if ((gather || r2 < a.H[j] * a.H[j]) &&
-          ((j < b0 || j >= b0 + FLUX_BLOCK) || emit_face((int)i, j))) {
+    // faces of the flux loop: r < max(H_i, H_j); one evaluation per face
+    // inside a block, one per side across blocks.
+    // (1) the gather set r < H_i (the density loop's compact list, in
+    // candidate order): every member is also a face
+    const int gc = a.gl_cnt[i];
+    for (int k = 0; k < gc; ++k) {
+      const int j = a.gl[list_at(i, k, n)];
+      if ((j < b0 || j >= b0 + FLUX_BLOCK) || emit_face((int)i, j)) {
         a.fslot[list_at(i, nf, n)] = j;
         ++nf;
       }
-      if (!gather) continue;
       const double *gj = a.gin + (int64_t)j * GIN_STRIDE;
       ++pairs;
+      const double e0 = min_image(gj[GIN_X] - xi, a.box[0], a.half[0]);
+      const double e1 = min_image(gj[GIN_Y] - yi, a.box[1], a.half[1]);
+      const double e2 = min_image(gj[GIN_Z] - zi, a.box[2], a.half[2]);
+      const double r2 = e0 * e0 + e1 * e1 + e2 * e2;
       if (r2 == 0.0) continue;
-      const T d0 = T(min_image(gj[GIN_X] - xi, a.box[0], a.half[0]));
-      const T d1 = T(min_image(gj[GIN_Y] - yi, a.box[1], a.half[1]));
-      const T d2 = T(min_image(gj[GIN_Z] - zi, a.box[2], a.half[2]));
+      const T d0 = T(e0), d1 = T(e1), d2 = T(e2);
       const T r = T(sqrt(r2));
       const T wv = T(gj[GIN_V]) * wnorm * spline_wt<T>(r * ih);
       e[0] += wv * d0 * d0;
@@ -148,6 +148,19 @@ __global__ void __launch_bounds__(BS) gradients_k(GradArgs a) {
       // signal velocity: x_i - x_j = -d
       const T proj = (d0 * dq[1] + d1 * dq[2] + d2 * dq[3]) / r;
       vsig = fmax(vsig, ci + T(gj[GIN_C]) - fmin(T(0), proj));
+    }
+    // (2) faces with H_i <= r < H_j, from the candidate list
+    const int cnt = a.cand_cnt[i];
+    for (int k = 0; k < cnt; ++k) {
+      const int64_t at = list_at(i, k, n);
+      const double r2 = a.cand_r2[at];
+      if (r2 < h2) continue;
+      const int j = a.cand[at];
+      const double hj = a.H[j];
+      if (r2 < hj * hj && ((j < b0 || j >= b0 + FLUX_BLOCK) || emit_face((int)i, j))) {
+        a.fslot[list_at(i, nf, n)] = j;
+        ++nf;
+      }
     }
     T b[6];
     T det = sym_inv<T>(e, b);
@@ -181,11 +194,8 @@ __global__ void __launch_bounds__(BS) gradients_k(GradArgs a) {
     T alpha[5] = {T(1), T(1), T(1), T(1), T(1)};
     if (a.limiter & MFM_LIMIT_BJ) {
       T dmax[5] = {0, 0, 0, 0, 0}, dmin[5] = {0, 0, 0, 0, 0};
-      for (int k = 0; k < cnt; ++k) {
-        const int64_t at = list_at(i, k, n);
-        const double r2 = a.cand_r2[at];
-        if (!(r2 < h2)) continue;
-        const double4 pj = a.pos[a.cand[at]];
+      for (int k = 0; k < gc; ++k) {
+        const double4 pj = a.pos[a.gl[list_at(i, k, n)]];
         const T d0 = T(min_image(pj.x - xi, a.box[0], a.half[0]));
         const T d1 = T(min_image(pj.y - yi, a.box[1], a.half[1]));
         const T d2 = T(min_image(pj.z - zi, a.box[2], a.half[2]));
@@ -307,6 +317,8 @@ hipError_t launch_gradients(mfm_ctx *ctx, const mfm_particles *pp, double dt_max
   a.cand = ctx->cand;
   a.cand_cnt = ctx->cand_cnt;
   a.cand_r2 = ctx->cand_r2;
+  a.gl = ctx->gl;
+  a.gl_cnt = ctx->gl_cnt;
   a.B = pp->B; a.grad = pp->grad; a.ncond = pp->ncond; a.dt_i = pp->dt_i; a.rec = ctx->rec;
   a.fslot = ctx->fslot;
   a.fcnt = ctx->fcnt;

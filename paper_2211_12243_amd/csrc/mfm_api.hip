@@ -12,8 +12,8 @@ namespace {
 constexpr size_t ALIGN = 256;
 
 struct Layout {
-  size_t code, count, start, cursor, crange, scan, order, tmp, pos4, cand, cand_r2, cand_cnt, gin, fslot,
-      fcnt, rec, red, counters, scalars;
+  size_t code, count, start, cursor, crange, scan, order, tmp, pos4, cand, cand_r2, cand_cnt, gl,
+      gl_cnt, gin, fslot, fcnt, rec, red, counters, scalars;
   size_t total;
   int64_t ncodes_max;
   size_t scan_len;
@@ -52,6 +52,8 @@ Layout make_layout(const mfm_params *p, int64_t n) {
   L.cand = take(4 * list_len(p->max_list, n));
   L.cand_r2 = take(8 * list_len(p->max_list, n));
   L.cand_cnt = take(4 * (size_t)n);
+  L.gl = take(4 * list_len(p->max_list, n));
+  L.gl_cnt = take(4 * (size_t)n);
   L.gin = take(8 * (size_t)GIN_STRIDE * (size_t)n);
   L.fslot = take(4 * list_len(p->max_list, n));
   L.fcnt = take(4 * (size_t)n);
@@ -238,6 +240,8 @@ int mfm_create(const mfm_params *p, int64_t n_max, void *workspace, size_t works
   ctx->cand_r2 = (double *)(ctx->ws + L.cand_r2);
   ctx->cand_cnt = (int32_t *)(ctx->ws + L.cand_cnt);
   ctx->gin = (double *)(ctx->ws + L.gin);
+  ctx->gl = (int32_t *)(ctx->ws + L.gl);
+  ctx->gl_cnt = (int32_t *)(ctx->ws + L.gl_cnt);
   ctx->fslot = (int32_t *)(ctx->ws + L.fslot);
   ctx->fcnt = (int32_t *)(ctx->ws + L.fcnt);
   ctx->rec = (double *)(ctx->ws + L.rec);
