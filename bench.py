@@ -11,7 +11,8 @@ Variants, each from the same initial set with the same warm-up:
   mixed          FP32 pair arithmetic, FP64 accumulators and checks;
   mixed_learned  mixed, with the Riemann iteration started from the guess
                  network (trained first, on faces dumped from other sets).
-The reported value is the headline variant's (default mixed_learned); every
+The reported value is the headline variant's (default mixed: FP32 pair
+arithmetic with FP64 accumulators, 1e-5 parity with the FP64 oracle); every
 variant's rate and stage times are in "variants".
 
 Metric: pair interactions per second over the gradient and flux loops,
@@ -60,7 +61,7 @@ def parse():
     ap.add_argument("--n", type=int, default=128, help="particles per axis")
     ap.add_argument("--variants", default=",".join(VARIANTS),
                     help="comma-separated subset of " + ", ".join(VARIANTS))
-    ap.add_argument("--headline", default="mixed_learned", choices=VARIANTS,
+    ap.add_argument("--headline", default="mixed", choices=VARIANTS,
                     help="variant whose rate is the reported value")
     ap.add_argument("--scheme", default="mfm", choices=["mfm", "mfv"])
     ap.add_argument("--train-steps", type=int, default=800)
@@ -70,6 +71,33 @@ def parse():
                          "known traffic, to calibrate hardware byte counters)")
     ap.add_argument("--quiet", action="store_true")
     return ap.parse_args()
+
+
+FLUX_SOURCES = ("paper_2211_12243_amd/csrc/fluxes.hip", "paper_2211_12243_amd/csrc/mfm_internal.h",
+                "paper_2211_12243_amd/csrc/mlp_device.h", "include/mfm.h")
+
+
+def flux_traffic(variant):
+    """HBM bytes per launch of fluxes_k recorded in profiles/traffic_sedov128.md
+    from rocprofv3 FETCH_SIZE and WRITE_SIZE, or None when that file is absent
+    or was taken from different flux-kernel sources than the ones built now."""
+    import hashlib
+    import re
+
+    path = os.path.join(ROOT, "profiles", "traffic_sedov128.md")
+    if not os.path.exists(path):
+        return None
+    h = hashlib.sha256()
+    for f in FLUX_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    with open(path) as fh:
+        for line in fh:
+            m = re.match(r"traffic (\w+): (\d+) bytes per launch of fluxes_k; flux sources "
+                         r"sha256 ([0-9a-f]+)", line.strip())
+            if m and m.group(1) == variant and m.group(3) == h.hexdigest():
+                return float(m.group(2))
+    return None
 
 
 def log(msg, args):
@@ -216,7 +244,8 @@ def run_variant(args, st, variant, mlp_state, log_):
         "newton_iters_per_face": diag["riemann_iters"] / max(diag["faces"], 1),
         "guess_fallback_frac": diag["guess_fallback"] / max(diag["faces"], 1),
         "roofline": {"bound": "alu", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
-                     "frac": achieved / peak, "traffic": None, "kernel": "fluxes_k",
+                     "frac": achieved / peak, "traffic": flux_traffic(variant),
+                     "kernel": "fluxes_k",
                      "mean_launch_ms": mean_s * 1e3, "flops_per_launch": flops_launch},
         "conserved_after": {k: diag[k] for k in ("mass", "px", "py", "pz", "energy")},
     }

@@ -40,9 +40,9 @@ struct CandArgs {
 // to HBM several times over.  Each lane therefore keeps its newest entries in
 // a ring of RING planes in LDS (lane-private columns: no barrier is needed),
 // and a plane is written out -- 64 consecutive particles, one coalesced
-// store per array -- as soon as every lane of the wave has passed it.  A lane
-// running more than RING entries ahead of the slowest one stores directly
-// from then on.
+// store per array -- as soon as every lane of the wave has passed it.  An
+// entry more than RING planes ahead of the slowest lane is stored directly; a
+// per-lane mask records which ring slots hold entries still to be written.
 constexpr int CBS = 64;
 constexpr int RING = 16;
 constexpr int UNR = 4;  // candidate loads issued together
@@ -68,9 +68,9 @@ __global__ void __launch_bounds__(CBS) cand_k(CandArgs a, CellGrid g) {
   const float sx = (float)(1.0 / g.inv[0]), sy = (float)(1.0 / g.inv[1]),
               sz = (float)(1.0 / g.inv[2]);
   const float lim = (float)R2 * 1.0001f;
-  int k = 0;                 // entries found (may exceed cap: overflow)
-  int direct_from = 1 << 30; // first entry this lane stored directly
-  int base = 0;              // planes [0, base) are written out (wave-uniform)
+  int k = 0;          // entries found (may exceed cap: overflow)
+  uint32_t held = 0;  // bit s: ring slot s holds an entry not yet written out
+  int base = 0;       // planes [0, base) are written out (wave-uniform)
   for (int dz = -1; dz <= 1; ++dz) {
     const float gz = sz * fmaxf(dz > 0 ? 1.0f - fz : (dz < 0 ? fz : 0.0f), 0.0f);
     int zz = cz + dz;
@@ -100,11 +100,11 @@ __global__ void __launch_bounds__(CBS) cand_k(CandArgs a, CellGrid g) {
               const double r2 = ex * ex + ey * ey + ez * ez;
               if (j < jend && r2 < R2 && j != i) {
                 if (k < cap) {
-                  if (k < direct_from && k < base + RING) {
+                  if (k < base + RING) {
                     s_idx[k % RING][lane] = j;
                     s_r2[k % RING][lane] = r2;
+                    held |= 1u << (k % RING);
                   } else {
-                    if (k < direct_from) direct_from = k;
                     const int64_t at = list_at(i, k, n);
                     a.cand[at] = j;
                     a.cand_r2[at] = r2;
@@ -119,10 +119,12 @@ __global__ void __launch_bounds__(CBS) cand_k(CandArgs a, CellGrid g) {
         int done = wave_min_i32(active ? min(k, cap) : (1 << 30));
         if (done >= (1 << 30)) done = base;
         for (int p = base; p < done; ++p) {
-          if (active && p < direct_from) {
+          const uint32_t bit = 1u << (p % RING);
+          if (active && (held & bit)) {
             const int64_t at = list_at(i, p, n);
             a.cand[at] = s_idx[p % RING][lane];
             a.cand_r2[at] = s_r2[p % RING][lane];
+            held &= ~bit;
           }
         }
         base = done > base ? done : base;
@@ -132,10 +134,12 @@ __global__ void __launch_bounds__(CBS) cand_k(CandArgs a, CellGrid g) {
   const int kc = min(k, cap);
   const int last = wave_max_i32(active ? kc : 0);
   for (int p = base; p < last; ++p) {
-    if (active && p < kc && p < direct_from) {
+    const uint32_t bit = 1u << (p % RING);
+    if (active && p < kc && (held & bit)) {
       const int64_t at = list_at(i, p, n);
       a.cand[at] = s_idx[p % RING][lane];
       a.cand_r2[at] = s_r2[p % RING][lane];
+      held &= ~bit;
     }
   }
   int64_t overflow = 0;

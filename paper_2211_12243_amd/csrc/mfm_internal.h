@@ -255,49 +255,6 @@ static inline size_t list_len(int max_list, int64_t n) {
   return (size_t)((max_list + LIST_TILE - 1) / LIST_TILE) * LIST_TILE * (size_t)n;
 }
 
-// Appends lane-private entries to a k-major int32 list through a ring of RING
-// planes in LDS (one [RING][64] array per wavefront; each lane only touches
-// its own column, so no barrier is needed).  Entry k of a lane would otherwise
-// be a lone 4-byte store into plane k; a plane is written out -- 64
-// consecutive particles, one coalesced store -- once every active lane of the
-// wave has passed it.  A lane more than RING entries ahead of the slowest one
-// stores directly from then on.  put() may be called in divergent code;
-// flush() and finish() at wave-uniform points with every lane present.
-template <int RING>
-struct PlaneRing {
-  int32_t (*buf)[64];
-  int base;         // planes [0, base) are written out (wave-uniform)
-  int direct_from;  // first entry this lane stored directly
-  __device__ __forceinline__ void init(int32_t (*b)[64]) {
-    buf = b;
-    base = 0;
-    direct_from = 1 << 30;
-  }
-  __device__ __forceinline__ void put(int32_t *list, int64_t i, int64_t n, int k, int32_t v,
-                                      int lane) {
-    if (k < direct_from && k < base + RING) {
-      buf[k % RING][lane] = v;
-    } else {
-      if (k < direct_from) direct_from = k;
-      list[list_at(i, k, n)] = v;
-    }
-  }
-  __device__ __forceinline__ void flush(int32_t *list, int64_t i, int64_t n, bool active,
-                                        int count, int lane) {
-    int done = wave_min_i32(active ? count : (1 << 30));
-    if (done >= (1 << 30)) done = base;  // no active lane in this wave
-    for (int p = base; p < done; ++p)
-      if (active && p < direct_from) list[list_at(i, p, n)] = buf[p % RING][lane];
-    if (done > base) base = done;
-  }
-  __device__ __forceinline__ void finish(int32_t *list, int64_t i, int64_t n, bool active,
-                                         int count, int lane) {
-    const int last = wave_max_i32(active ? count : 0);
-    for (int p = base; p < last; ++p)
-      if (active && p < count && p < direct_from) list[list_at(i, p, n)] = buf[p % RING][lane];
-  }
-};
-
 // Particles per workgroup of the flux loop: faces inside a block are computed
 // once, faces crossing its boundary by both blocks (see fluxes.hip).
 constexpr int FLUX_BLOCK = 256;
