@@ -45,7 +45,7 @@ struct CandArgs {
 // per-lane mask records which ring slots hold entries still to be written.
 constexpr int CBS = 64;
 constexpr int RING = 16;
-constexpr int UNR = 4;  // candidate loads issued together
+constexpr int UNR = 8;  // candidate loads issued together
 
 __global__ void __launch_bounds__(CBS) cand_k(CandArgs a, CellGrid g) {
   __shared__ int32_t s_idx[RING][CBS];

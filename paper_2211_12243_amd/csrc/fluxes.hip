@@ -44,7 +44,10 @@
 
 namespace {
 
-constexpr int FBS = FLUX_BLOCK;
+constexpr int FBS = FLUX_BLOCK;  // particles per workgroup
+constexpr int FTH = 256;         // threads per workgroup
+constexpr int PPT = FBS / FTH;   // particles per thread in the block prefix sum
+static_assert(FBS % FTH == 0, "flux block must be a multiple of the workgroup size");
 constexpr int GUESS_MAXIT = 8;
 
 template <typename T>
@@ -598,36 +601,49 @@ __device__ __forceinline__ void features_of(const FaceState<T> &fs, float x[mlp:
 }
 
 template <typename T, int SCHEME, int M, bool LEARNED>
-__global__ void __launch_bounds__(FBS) __attribute__((amdgpu_waves_per_eu(2))) fluxes_k(FluxArgs a) {
+__global__ void __launch_bounds__(FTH) __attribute__((amdgpu_waves_per_eu(2))) fluxes_k(FluxArgs a) {
   __shared__ int pref[FBS + 1];
-  __shared__ int wsum[FBS / 64];
+  __shared__ int wsum[FTH / 64];
   __shared__ double acc[5][FBS];
-  __shared__ uint16_t mlp_act[LEARNED ? (FBS / 64) * 16 * mlp::AST : 1];
+  __shared__ uint16_t mlp_act[LEARNED ? (FTH / 64) * 16 * mlp::AST : 1];
   const int64_t n = a.n;
   const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
   const int b0 = xcd_block(blockIdx.x, gridDim.x) * FBS;
   const int nb = (int)min((int64_t)FBS, n - b0);
-  // block exclusive prefix sum of the per-particle face counts
-  const int cnt = tid < nb ? a.fcnt[b0 + tid] : 0;
-  int incl = cnt;
+  // block exclusive prefix sum of the per-particle face counts: each thread
+  // sums PPT consecutive particles, then a wave scan and the wave offsets
+  int cnt[PPT], tsum = 0;
+#pragma unroll
+  for (int q = 0; q < PPT; ++q) {
+    const int t = tid * PPT + q;
+    cnt[q] = t < nb ? a.fcnt[b0 + t] : 0;
+    tsum += cnt[q];
+  }
+  int incl = tsum;
   for (int o = 1; o < 64; o <<= 1) {
     const int u = __shfl_up(incl, o, 64);
     if (lane >= o) incl += u;
   }
   if (lane == 63) wsum[wid] = incl;
+  for (int t = tid; t < FBS; t += FTH) {
 #pragma unroll
-  for (int f = 0; f < 5; ++f) acc[f][tid] = 0.0;
+    for (int f = 0; f < 5; ++f) acc[f][t] = 0.0;
+  }
   __syncthreads();
-  int woff = 0;
-  for (int w = 0; w < wid; ++w) woff += wsum[w];
-  pref[tid] = woff + incl - cnt;
-  if (tid == FBS - 1) pref[FBS] = woff + incl;
+  int run = incl - tsum;
+  for (int w = 0; w < wid; ++w) run += wsum[w];
+#pragma unroll
+  for (int q = 0; q < PPT; ++q) {
+    pref[tid * PPT + q] = run;
+    run += cnt[q];
+  }
+  if (tid == FTH - 1) pref[FBS] = run;
   __syncthreads();
   const int T_faces = pref[FBS];
   const double dt = a.dt[0];
   const T hdt = T(0.5 * dt);
   int64_t nfaces = 0, iters_sum = 0, vac = 0, pos = 0, maxit = 0, fb = 0;
-  for (int base = 0; base < T_faces; base += FBS) {
+  for (int base = 0; base < T_faces; base += FTH) {
     const int f = base + tid;
     const bool active = f < T_faces;
     int p = FBS;  // sentinel key for idle lanes (they sit at the wave's end)
@@ -732,9 +748,9 @@ __global__ void __launch_bounds__(FBS) __attribute__((amdgpu_waves_per_eu(2))) f
     }
   }
   __syncthreads();
-  if (tid < nb) {
+  for (int t = tid; t < nb; t += FTH) {
 #pragma unroll
-    for (int q = 0; q < 5; ++q) a.dQ[(int64_t)q * n + b0 + tid] = dt * acc[q][tid];
+    for (int q = 0; q < 5; ++q) a.dQ[(int64_t)q * n + b0 + t] = dt * acc[q][t];
   }
   count_add(a.counters + C_FACES, nfaces);
   count_add(a.counters + C_RIEMANN_ITERS, iters_sum);
@@ -747,11 +763,11 @@ __global__ void __launch_bounds__(FBS) __attribute__((amdgpu_waves_per_eu(2))) f
 template <typename T, int SCHEME, bool LEARNED>
 void launch_m(const FluxArgs &a, int m, int nb, hipStream_t st) {
   if (m == 5)
-    fluxes_k<T, SCHEME, 5, LEARNED><<<nb, FBS, 0, st>>>(a);
+    fluxes_k<T, SCHEME, 5, LEARNED><<<nb, FTH, 0, st>>>(a);
   else if (m == 7)
-    fluxes_k<T, SCHEME, 7, LEARNED><<<nb, FBS, 0, st>>>(a);
+    fluxes_k<T, SCHEME, 7, LEARNED><<<nb, FTH, 0, st>>>(a);
   else
-    fluxes_k<T, SCHEME, 0, LEARNED><<<nb, FBS, 0, st>>>(a);
+    fluxes_k<T, SCHEME, 0, LEARNED><<<nb, FTH, 0, st>>>(a);
 }
 
 template <typename T, bool LEARNED>
