@@ -194,7 +194,7 @@ __global__ void __launch_bounds__(BS) density_k(DensityArgs a, CellGrid g) {
     const double cover = g.side_min;
     double h = a.H[i];
     double target = a.n_ngb;
-    double winv = 0.0, nc = 1.0;
+    double winv = 0.0, nc = 1.0, s_last = 1.0;
     for (int b = 0;; ++b) {
       double lo = 0.0, hi = cover;
       if (!(h > lo && h < hi)) h = 0.5 * hi;
@@ -210,6 +210,7 @@ __global__ void __launch_bounds__(BS) density_k(DensityArgs a, CellGrid g) {
             ds += spline_qdw(q);
           }
         }
+        s_last = s;
         const double gv = (32.0 / 3.0) * s - target;
         const double dg = -(32.0 / 3.0) * ds * ih;
         if (gv == 0.0) {
@@ -271,7 +272,13 @@ __global__ void __launch_bounds__(BS) density_k(DensityArgs a, CellGrid g) {
       target *= a.ngb_boost;
       ++boosts;
     }
-    if (h >= cover * (1.0 - 1e-12)) ++overflow;
+    if (h >= cover * (1.0 - 1e-12)) {
+      // the root lies beyond the cell side: this pass is redone on a coarser
+      // grid, sized from an estimate of the root (at fixed number density the
+      // neighbour number grows as H^3), written as the start value
+      ++overflow;
+      h = cover * cbrt(target / fmax((32.0 / 3.0) * s_last, 1.0)) * 1.05;
+    }
     const double V = 1.0 / winv;
     const double rho = a.m[i] / V;
     const double P = (a.gamma - 1.0) * a.U[i] / V;

@@ -317,6 +317,10 @@ int mfm_density(mfm_ctx *ctx, const mfm_particles *pp) {
   int64_t c[NCOUNTERS];
   int rc = read_counters(ctx, c);
   if (rc) return rc;
+  // truncated candidate lists make every later result meaningless (and can
+  // push H to the cell side): report them first
+  if (c[C_LIST_OVERFLOW] > 0)
+    return fail(ctx, MFM_E_LIST, "candidate list capacity exceeded (raise max_list)");
   if (c[C_CELL_OVERFLOW] > 0) {
     // some H reached the cell side: this pass is discarded (its counts too)
     // and the next build uses larger cells
@@ -325,7 +329,9 @@ int mfm_density(mfm_ctx *ctx, const mfm_particles *pp) {
                                sizeof(int64_t), hipMemcpyHostToDevice, ctx->stream),
            "count rebuild");
     HIPCHK(ctx, hipStreamSynchronize(ctx->stream), "synchronise");
-    ctx->margin_boost *= 1.3;
+    // the density loop has written an estimate of each outgrown root as its
+    // start value; a small extra margin guards against underestimates
+    ctx->margin_boost *= 1.1;
     ctx->have_cells = 0;
     return fail(ctx, MFM_E_CELLS, "smoothing lengths outgrew the cell grid; rebuild cells");
   }
@@ -337,10 +343,11 @@ int mfm_density(mfm_ctx *ctx, const mfm_particles *pp) {
                              ctx->stream),
          "fold pass counters");
   HIPCHK(ctx, hipStreamSynchronize(ctx->stream), "synchronise");
-  if (c[C_LIST_OVERFLOW] > 0)
-    return fail(ctx, MFM_E_LIST, "candidate list capacity exceeded (raise max_list)");
+  ctx->margin_boost = 1.0;
   ctx->have_density = 1;
   ctx->have_grad = 0;
+  if (c[C_PASS_NOCONV] > 0)
+    return fail(ctx, MFM_E_H_NOCONV, "smoothing-length solve did not converge");
   return MFM_OK;
 }
 
