@@ -673,7 +673,11 @@ __global__ void __launch_bounds__(FTH) __attribute__((amdgpu_waves_per_eu(2))) f
       // face needing it (wave-uniform branches; other waves skip it)
       float x[mlp::NIN];
       bool hard = false;
-      if (active && !fs.skip) {
+      // a cheap superset of the gate first (pressure ratio above 1.9 or
+      // |du| above 0.48 c_avg), then the exact gate on the features
+      if (active && !fs.skip &&
+          (fs.SL.p > T(1.9) * fs.SR.p || fs.SR.p > T(1.9) * fs.SL.p ||
+           fabs(fs.SR.u - fs.SL.u) > T(0.24) * (fs.SL.c + fs.SR.c))) {
         features_of<T>(fs, x);
         hard = mlp::needs_guess(x);
       }
@@ -685,7 +689,7 @@ __global__ void __launch_bounds__(FTH) __attribute__((amdgpu_waves_per_eu(2))) f
         for (int mt = 0; mt < 4; ++mt) {
           if (((hmask >> (16 * mt)) & 0xffffull) == 0) continue;
           if ((lane >> 4) == mt) mlp::put_input(tile, lane & 15, hard ? x : nullptr, a.net.norm);
-          const float yt = mlp::forward_tile(tile, a.net, lane);
+          const float yt = mlp::forward_tile_call(tile, a.net.wt, a.net.p, a.net.norm, lane);
           if ((lane >> 4) == mt) y = yt;
         }
         if (hard) {

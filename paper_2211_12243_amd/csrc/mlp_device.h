@@ -162,6 +162,20 @@ __device__ inline float forward_tile(uint16_t *act, const Net &net, int lane) {
   return net.norm[2 * NIN] + net.norm[2 * NIN + 1] * y;
 }
 
+// forward_tile as a real call: the flux loop evaluates the network rarely
+// (only tiles holding a gated face), so the network's registers are kept out
+// of the flux kernel's allocation and spilled around the call instead.
+__device__ __attribute__((noinline)) float forward_tile_call(uint16_t *act, const uint16_t *wt,
+                                                             const float *p, const float *norm,
+                                                             int lane) {
+  Net net;
+  net.wt = wt;
+  net.wr = nullptr;
+  net.p = p;
+  net.norm = norm;
+  return forward_tile(act, net, lane);
+}
+
 // Forward pass for the 64 rows of a wave, one tile at a time through a
 // 16-row buffer; lane l supplies row l (x null: a zero row) and gets its output.
 __device__ inline float forward_wave(uint16_t *tile, const float *x, const Net &net, int lane) {
