@@ -183,7 +183,7 @@ __device__ double cond3(const double e[6]) {
   return frob_sym(b) / fabs(det) * frob_sym(e) / 3.0;
 }
 
-__global__ void __launch_bounds__(BS) density_k(DensityArgs a, CellGrid g) {
+__global__ void __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(7))) density_k(DensityArgs a, CellGrid g) {
   const int64_t i = xcd_block(blockIdx.x, gridDim.x) * (int64_t)blockDim.x + threadIdx.x;
   const int64_t n = a.n;
   const bool active = i < n;
