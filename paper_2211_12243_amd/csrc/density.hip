@@ -294,7 +294,9 @@ __global__ void __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(7))) de
     gr[0] = make_double4(pi.x, pi.y, pi.z, h);
     gr[1] = make_double4(V, rho, a.vx[i], a.vy[i]);
     gr[2] = make_double4(a.vz[i], P, cs, 0.0);
-    gr[3] = make_double4(0.0, 0.0, 0.0, 0.0);
+    float4 *gf = reinterpret_cast<float4 *>(a.gin + i * GIN_STRIDE + GIN_F32);
+    gf[0] = make_float4((float)V, (float)rho, (float)a.vx[i], (float)a.vy[i]);
+    gf[1] = make_float4((float)a.vz[i], (float)P, (float)cs, 0.0f);
     a.gl_cnt[i] = gc;
   }
   count_add(a.counters + C_PASS_NOCONV, noconv);

@@ -126,14 +126,29 @@ __global__ void __launch_bounds__(BS) gradients_k(GradArgs a) {
       if (r2 == 0.0) continue;
       const T d0 = T(e0), d1 = T(e1), d2 = T(e2);
       const T r = T(sqrt(r2));
-      const T wv = T(gj[GIN_V]) * wnorm * spline_wt<T>(r * ih);
+      // neighbour values: FP64 on the FP64 path; on the mixed path their FP32
+      // copies (half the bytes through the cache; the separation stays FP64)
+      double qj[5];
+      T vj, cj;
+      if constexpr (sizeof(T) == sizeof(float)) {
+        const float4 *gf = reinterpret_cast<const float4 *>(gj + GIN_F32);
+        const float4 f0 = gf[0], f1 = gf[1];
+        vj = f0.x;
+        qj[0] = f0.y; qj[1] = f0.z; qj[2] = f0.w; qj[3] = f1.x; qj[4] = f1.y;
+        cj = f1.z;
+      } else {
+        vj = T(gj[GIN_V]);
+        qj[0] = gj[GIN_RHO]; qj[1] = gj[GIN_VX]; qj[2] = gj[GIN_VY]; qj[3] = gj[GIN_VZ];
+        qj[4] = gj[GIN_P];
+        cj = T(gj[GIN_C]);
+      }
+      const T wv = vj * wnorm * spline_wt<T>(r * ih);
       e[0] += wv * d0 * d0;
       e[1] += wv * d0 * d1;
       e[2] += wv * d0 * d2;
       e[3] += wv * d1 * d1;
       e[4] += wv * d1 * d2;
       e[5] += wv * d2 * d2;
-      const double qj[5] = {gj[GIN_RHO], gj[GIN_VX], gj[GIN_VY], gj[GIN_VZ], gj[GIN_P]};
       T dq[5];
 #pragma unroll
       for (int q = 0; q < 5; ++q) {
@@ -147,7 +162,7 @@ __global__ void __launch_bounds__(BS) gradients_k(GradArgs a) {
       }
       // signal velocity: x_i - x_j = -d
       const T proj = (d0 * dq[1] + d1 * dq[2] + d2 * dq[3]) / r;
-      vsig = fmax(vsig, ci + T(gj[GIN_C]) - fmin(T(0), proj));
+      vsig = fmax(vsig, ci + cj - fmin(T(0), proj));
     }
     // (2) faces with H_i <= r < H_j, from the candidate list
     const int cnt = a.cand_cnt[i];

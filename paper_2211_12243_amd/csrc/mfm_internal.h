@@ -41,6 +41,7 @@ enum {
 // Packed per-particle record the gradient loop gathers for each neighbour
 // (written by the density loop; one 128-byte line).
 enum { GIN_X = 0, GIN_Y, GIN_Z, GIN_H, GIN_V, GIN_RHO, GIN_VX, GIN_VY, GIN_VZ, GIN_P, GIN_C,
+       GIN_F32 = 12,  // from here: V, rho, vx, vy, vz, P, c rounded to FP32 (the mixed path's gather)
        GIN_STRIDE = 16 };
 
 // Packed per-particle record the flux loop gathers for each face side
