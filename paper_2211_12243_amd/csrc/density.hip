@@ -4,19 +4,20 @@
 // cand_cell_k: for every particle, the candidates in the 27 cells around its
 // own (cell side >= cell_margin * max H, so every pair closer than the side
 // is found) with r < side, as (index, r^2) in the k-major list (list_at).
-// The list is a superset of every neighbour set the step uses: the density
-// loop solves over it, the gradient loop takes r < H_i and the flux loop
-// r < max(H_i, H_j).
+// The list is a superset of every neighbour set the step uses.
 //
-// density_k: each lane solves
+// density_k solves, for each particle,
 //   g(H) = (32/3) sum_j w(r_ij / H) - N_NGB = 0
 // ((4 pi / 3) H^3 omega^-1 = N_NGB with omega^-1 = sum_j W(r_ij, H)) by Newton
-// steps kept inside a bisection bracket (0, side); each evaluation streams only
-// the lane's own r^2 list.  The solve ends on a small Newton step, so H is the
-// root to roundoff.  Reaching the side is flagged and the host rebuilds the
-// grid with larger cells.  Then the number density, the unweighted E~ of the
-// condition-number check (with N_NGB boosts), the primitives and the packed
-// 128-byte record the gradient loop gathers.
+// steps kept inside a bisection bracket (0, side) over its candidate r^2.
+// The solve ends on a small Newton step, so H is the root to roundoff.
+// Reaching the side is flagged and the host rebuilds the grid with larger
+// cells.  Then the number density, the unweighted E~ of the condition-number
+// check (with N_NGB boosts), the primitives and the packed 128-byte record
+// the gradient loop gathers.  It leaves two lists, both in candidate order:
+//   gl                the gather set r < H_i (the gradient loop's pairs);
+//   cand / rest_r2    the other candidates, r >= H_i, with r^2 in FP32, where
+//                     the gradient loop finds the faces with H_i <= r < H_j.
 #include "mfm_internal.h"
 
 namespace {
@@ -205,13 +206,36 @@ struct DensityArgs {
   const double *m, *U, *vx, *vy, *vz;
   double *H, *V, *rho, *P, *c, *ncond;
   double *gin;  // GIN_STRIDE doubles per particle
-  const int32_t *cand, *cand_cnt;
+  int32_t *cand, *cand_cnt;
   const double *cand_r2;
+  float *rest_r2;
   int32_t *gl, *gl_cnt;
   double gamma, n_ngb, ncond_max, ngb_boost, h_tol;
   int h_maxit, max_boosts;
   int64_t *counters;
 };
+
+// The density loop: DT particles per wavefront, DG = 64 / DT lanes per
+// particle, each lane holding DM entries of the particle's list (entries
+// sub, sub + DG, ...) in registers, so one particle's list of up to
+// DCAP = DG * DM entries is read from HBM once for all its Newton passes.
+// Measured at 2.1M particles (about 84 candidates each): DM = 12 (161 VGPRs,
+// 3 waves per SIMD) 1.74 ms, DM = 16 (194 VGPRs, 2 waves) 2.30 ms; 4
+// particles per wavefront with 16 lanes each, 2.5-2.7 ms.  Longer lists go to
+// density_long_k.
+constexpr int DT = 8;
+constexpr int DG = 64 / DT;
+constexpr int DM = 12;
+constexpr int DCAP = DG * DM;
+
+// Sum over the G lanes of an aligned group (butterfly: every lane gets the
+// same bits, since each pairwise sum is formed from the same two operands).
+template <int G>
+__device__ __forceinline__ double group_sum(double v) {
+#pragma unroll
+  for (int o = 1; o < G; o <<= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
 
 __device__ __forceinline__ double frob_sym(const double e[6]) {
   return sqrt(e[0] * e[0] + e[3] * e[3] + e[5] * e[5] +
@@ -232,121 +256,295 @@ __device__ double cond3(const double e[6]) {
   return frob_sym(b) / fabs(det) * frob_sym(e) / 3.0;
 }
 
-__global__ void __launch_bounds__(BS) __attribute__((amdgpu_waves_per_eu(7))) density_k(DensityArgs a, CellGrid g) {
-  const int64_t i = xcd_block(blockIdx.x, gridDim.x) * (int64_t)blockDim.x + threadIdx.x;
-  const int64_t n = a.n;
-  const bool active = i < n;
-  int64_t noconv = 0, boosts = 0, fails = 0, overflow = 0;
-  int cnt = 0, gc = 0;
-  if (active) {
-    cnt = a.cand_cnt[i];
-    const double cover = g.side_min;
-    double h = a.H[i];
-    double target = a.n_ngb;
-    double winv = 0.0, nc = 1.0, s_last = 1.0;
-    for (int b = 0;; ++b) {
-      double lo = 0.0, hi = cover;
-      if (!(h > lo && h < hi)) h = 0.5 * hi;
-      bool conv = false;
-      for (int it = 0; it < a.h_maxit; ++it) {
-        const double h2 = h * h, ih = 1.0 / h;
-        double s = 1.0, ds = 0.0;  // the particle itself: w(0) = 1
-        for (int k = 0; k < cnt; ++k) {
-          const double r2 = a.cand_r2[list_at(i, k, n)];
-          if (r2 < h2) {
-            const double q = sqrt(r2) * ih;
-            s += spline_w(q);
-            ds += spline_qdw(q);
-          }
-        }
-        s_last = s;
-        const double gv = (32.0 / 3.0) * s - target;
-        const double dg = -(32.0 / 3.0) * ds * ih;
-        if (gv == 0.0) {
-          conv = true;
-          break;
-        }
-        if (gv < 0.0)
-          lo = h;
-        else
-          hi = h;
-        double hn = (dg > 0.0) ? h - gv / dg : -1.0;
-        // stop on a small Newton step only (never on a bisection step): its
-        // quadratic convergence leaves H at the root to roundoff
-        if (fabs(hn - h) <= a.h_tol * hn) {
-          h = hn;
-          conv = true;
-          break;
-        }
-        if (!(hn > lo && hn < hi)) hn = 0.5 * (lo + hi);
-        h = hn;
-      }
-      if (!conv) ++noconv;
-      // number density at the solution and the unweighted E~ of the check
-      const double h2 = h * h, ih = 1.0 / h;
-      const double4 pi = a.pos[i];
-      double ws = 1.0;
-      double e[6] = {0, 0, 0, 0, 0, 0};
-      // this pass also writes the gather set r < H_i for the gradient loop
-      // (rewritten if a boost follows)
-      gc = 0;
-      for (int k = 0; k < cnt; ++k) {
-        const double r2 = a.cand_r2[list_at(i, k, n)];
-        if (r2 < h2) {
-          const int j = a.cand[list_at(i, k, n)];
-          a.gl[list_at(i, gc++, n)] = j;
-          const double w = spline_w(sqrt(r2) * ih);
-          ws += w;
-          if (r2 > 0.0) {
-            const double4 pj = a.pos[j];
-            const double dx = min_image(pj.x - pi.x, g.box[0], g.half[0]);
-            const double dy = min_image(pj.y - pi.y, g.box[1], g.half[1]);
-            const double dz = min_image(pj.z - pi.z, g.box[2], g.half[2]);
-            e[0] += w * dx * dx;
-            e[1] += w * dx * dy;
-            e[2] += w * dx * dz;
-            e[3] += w * dy * dy;
-            e[4] += w * dy * dz;
-            e[5] += w * dz * dz;
-          }
-        }
-      }
-      winv = 8.0 / (PI * h * h2) * ws;
-      nc = cond3(e);  // the kernel's normalisation drops out of the condition number
-      if (!(nc > a.ncond_max)) break;
-      if (b == a.max_boosts) {
-        ++fails;
+struct HSolve {
+  double h;        // the root (the list split uses it)
+  double h_store;  // what is written as H: the root, or a start value for a coarser grid
+  double winv, nc;
+  int noconv, boosts, fails, overflow;
+};
+
+// The smoothing-length solve of one particle from the start value h.
+//   sums(h2, ih, s, ds):  s = sum w(q), ds = sum q w'(q) over the list entries
+//                         with r^2 < h2 (q = r / h, ih = 1 / h);
+//   esums(h2, ih, ws, e): ws = sum w(q) and the unweighted E~ = sum w(q) d d^T.
+// The particle itself (w(0) = 1) is added here.  Both must return the same
+// value in every lane that calls them together.
+template <typename Sums, typename ESums>
+__device__ __forceinline__ HSolve newton_h(const DensityArgs &a, const CellGrid &g, double h,
+                                           Sums sums, ESums esums) {
+  HSolve r{};
+  const double cover = g.side_min;
+  const double qtol = fmax(a.h_tol, 1e-2 * sqrt(a.h_tol));
+  double target = a.n_ngb;
+  double s_last = 1.0;
+  for (int b = 0;; ++b) {
+    double lo = 0.0, hi = cover;
+    if (!(h > lo && h < hi)) h = 0.5 * hi;
+    bool conv = false;
+    for (int it = 0; it < a.h_maxit; ++it) {
+      const double ih = 1.0 / h;
+      double s, ds;
+      sums(h * h, ih, s, ds);
+      s += 1.0;
+      s_last = s;
+      const double gv = (32.0 / 3.0) * s - target;
+      const double dg = -(32.0 / 3.0) * ds * ih;
+      if (gv == 0.0) {
+        conv = true;
         break;
       }
-      target *= a.ngb_boost;
-      ++boosts;
+      if (gv < 0.0)
+        lo = h;
+      else
+        hi = h;
+      double hn = (dg > 0.0) ? h - gv / dg : -1.0;
+      // stop on a small Newton step only (never on a bisection step).  In the
+      // quadratic regime the error after a step of relative size d is of
+      // order d^2, so a step below qtol = 1e-2 sqrt(h_tol) already leaves H
+      // at the root to far below h_tol: the pass that would only confirm it
+      // is skipped
+      if (fabs(hn - h) <= qtol * hn) {
+        h = hn;
+        conv = true;
+        break;
+      }
+      if (!(hn > lo && hn < hi)) hn = 0.5 * (lo + hi);
+      h = hn;
     }
-    if (h >= cover * (1.0 - 1e-12)) {
-      // the root lies beyond the cell side: this pass is redone on a coarser
-      // grid, sized from an estimate of the root (at fixed number density the
-      // neighbour number grows as H^3), written as the start value
-      ++overflow;
-      h = cover * cbrt(target / fmax((32.0 / 3.0) * s_last, 1.0)) * 1.05;
+    if (!conv) ++r.noconv;
+    // number density at the solution and the unweighted E~ of the check
+    const double h2 = h * h;
+    double ws, e[6];
+    esums(h2, 1.0 / h, ws, e);
+    ws += 1.0;
+    r.winv = 8.0 / (PI * h * h2) * ws;
+    r.nc = cond3(e);  // the kernel's normalisation drops out of the condition number
+    if (!(r.nc > a.ncond_max)) break;
+    if (b == a.max_boosts) {
+      ++r.fails;
+      break;
     }
-    const double V = 1.0 / winv;
-    const double rho = a.m[i] / V;
-    const double P = (a.gamma - 1.0) * a.U[i] / V;
-    const double cs = sqrt(a.gamma * P / rho);
-    a.H[i] = h;
-    a.V[i] = V;
-    a.rho[i] = rho;
-    a.P[i] = P;
-    a.c[i] = cs;
-    a.ncond[i] = nc;
+    target *= a.ngb_boost;
+    ++r.boosts;
+  }
+  r.h = h;
+  r.h_store = h;
+  if (h >= cover * (1.0 - 1e-12)) {
+    // the root lies beyond the cell side: this pass is redone on a coarser
+    // grid, sized from an estimate of the root (at fixed number density the
+    // neighbour number grows as H^3), written as the start value
+    r.overflow = 1;
+    r.h_store = cover * cbrt(target / fmax((32.0 / 3.0) * s_last, 1.0)) * 1.05;
+  }
+  return r;
+}
+
+__device__ __forceinline__ void add_pair(double &s, double &ds, double r2, double ih) {
+  const double q = sqrt(r2) * ih;
+  s += spline_w(q);
+  ds += spline_qdw(q);
+}
+
+__device__ __forceinline__ void add_e(double &ws, double e[6], double r2, double ih,
+                                      double4 pj, double4 pi, const CellGrid &g) {
+  const double w = spline_w(sqrt(r2) * ih);
+  ws += w;
+  if (r2 > 0.0) {
+    const double dx = min_image(pj.x - pi.x, g.box[0], g.half[0]);
+    const double dy = min_image(pj.y - pi.y, g.box[1], g.half[1]);
+    const double dz = min_image(pj.z - pi.z, g.box[2], g.half[2]);
+    e[0] += w * dx * dx;
+    e[1] += w * dx * dy;
+    e[2] += w * dx * dz;
+    e[3] += w * dy * dy;
+    e[4] += w * dy * dz;
+    e[5] += w * dz * dz;
+  }
+}
+
+// H, the number density, the primitives and the gradient loop's record of particle i.
+__device__ __forceinline__ void finish_particle(const DensityArgs &a, int64_t i, const HSolve &r) {
+  const double h = r.h_store;
+  const double V = 1.0 / r.winv;
+  const double rho = a.m[i] / V;
+  const double P = (a.gamma - 1.0) * a.U[i] / V;
+  const double cs = sqrt(a.gamma * P / rho);
+  a.H[i] = h;
+  a.V[i] = V;
+  a.rho[i] = rho;
+  a.P[i] = P;
+  a.c[i] = cs;
+  a.ncond[i] = r.nc;
+  const double4 pi = a.pos[i];
+  const double vx = a.vx[i], vy = a.vy[i], vz = a.vz[i];
+  double4 *gr = reinterpret_cast<double4 *>(a.gin + i * GIN_STRIDE);
+  gr[0] = make_double4(pi.x, pi.y, pi.z, h);
+  gr[1] = make_double4(V, rho, vx, vy);
+  gr[2] = make_double4(vz, P, cs, 0.0);
+  float4 *gf = reinterpret_cast<float4 *>(a.gin + i * GIN_STRIDE + GIN_F32);
+  gf[0] = make_float4((float)V, (float)rho, (float)vx, (float)vy);
+  gf[1] = make_float4((float)vz, (float)P, (float)cs, 0.0f);
+}
+
+// One wavefront per DT consecutive particles.  A particle's candidate list is
+// loaded once into the registers of its DG lanes; every Newton pass and the
+// final pass run from there (group sums by lane exchange).  The list is then
+// split at r = H_i, in candidate order: the gather set goes to gl, the rest
+// (index and FP32 r^2) back into cand / rest_r2.  Both are staged in LDS and
+// leave as k-major planes of DT consecutive particles.  A list longer than
+// DCAP is left whole, marked gl_cnt = -1, for density_long_k.
+__global__ void __launch_bounds__(64) density_k(DensityArgs a, CellGrid g) {
+  __shared__ int32_t s_i[DCAP][DT];  // gather set from the front, rest indices from the back
+  __shared__ float s_f[DCAP][DT];    // rest r^2
+  __shared__ int s_gn[DT], s_rn[DT];
+  const int lane = threadIdx.x;
+  const int gt = lane / DG, sub = lane % DG;
+  const uint64_t below = (1ull << lane) - 1ull;
+  const uint64_t gmask = ((1ull << DG) - 1ull) << (gt * DG);
+  const int64_t n = a.n;
+  const int64_t i0 = xcd_block(blockIdx.x, gridDim.x) * (int64_t)DT;
+  const int64_t i = i0 + gt;
+  const bool valid = i < n;
+  const int cnt = valid ? a.cand_cnt[i] : 0;
+  int64_t noconv = 0, boosts = 0, fails = 0, overflow = 0;
+  if (valid && cnt <= DCAP) {
+    double rr[DM];
+    int jr[DM];
+#pragma unroll
+    for (int m = 0; m < DM; ++m) {
+      const int k = sub + DG * m;
+      rr[m] = __builtin_huge_val();  // beyond the list: never inside any H
+      jr[m] = 0;
+      if (k < cnt) {
+        rr[m] = a.cand_r2[list_at(i, k, n)];
+        jr[m] = a.cand[list_at(i, k, n)];
+      }
+    }
     const double4 pi = a.pos[i];
-    double4 *gr = reinterpret_cast<double4 *>(a.gin + i * GIN_STRIDE);
-    gr[0] = make_double4(pi.x, pi.y, pi.z, h);
-    gr[1] = make_double4(V, rho, a.vx[i], a.vy[i]);
-    gr[2] = make_double4(a.vz[i], P, cs, 0.0);
-    float4 *gf = reinterpret_cast<float4 *>(a.gin + i * GIN_STRIDE + GIN_F32);
-    gf[0] = make_float4((float)V, (float)rho, (float)a.vx[i], (float)a.vy[i]);
-    gf[1] = make_float4((float)a.vz[i], (float)P, (float)cs, 0.0f);
-    a.gl_cnt[i] = gc;
+    auto sums = [&](double h2, double ih, double &s, double &ds) {
+      s = 0.0;
+      ds = 0.0;
+#pragma unroll
+      for (int m = 0; m < DM; ++m)
+        if (rr[m] < h2) add_pair(s, ds, rr[m], ih);
+      s = group_sum<DG>(s);
+      ds = group_sum<DG>(ds);
+    };
+    auto esums = [&](double h2, double ih, double &ws, double e[6]) {
+      ws = 0.0;
+#pragma unroll
+      for (int q = 0; q < 6; ++q) e[q] = 0.0;
+#pragma unroll
+      for (int m = 0; m < DM; ++m)
+        if (rr[m] < h2) add_e(ws, e, rr[m], ih, a.pos[jr[m]], pi, g);
+      ws = group_sum<DG>(ws);
+#pragma unroll
+      for (int q = 0; q < 6; ++q) e[q] = group_sum<DG>(e[q]);
+    };
+    const HSolve r = newton_h(a, g, a.H[i], sums, esums);
+    const double h2 = r.h * r.h;
+    int gn = 0, rn = 0;
+#pragma unroll
+    for (int m = 0; m < DM; ++m) {
+      const bool in = sub + DG * m < cnt;
+      const bool near = in && rr[m] < h2;
+      const bool far = in && !near;
+      const uint64_t mn = __ballot(near) & gmask, mf = __ballot(far) & gmask;
+      if (near) s_i[gn + __popcll(mn & below)][gt] = jr[m];
+      if (far) {
+        const int p = rn + __popcll(mf & below);
+        s_i[DCAP - 1 - p][gt] = jr[m];
+        s_f[p][gt] = (float)rr[m];
+      }
+      gn += __popcll(mn);
+      rn += __popcll(mf);
+    }
+    if (sub == 0) {
+      s_gn[gt] = gn;
+      s_rn[gt] = rn;
+      finish_particle(a, i, r);
+      noconv = r.noconv;
+      boosts = r.boosts;
+      fails = r.fails;
+      overflow = r.overflow;
+    }
+  } else if (valid && sub == 0) {
+    s_gn[gt] = -1;  // left whole in cand for density_long_k
+    s_rn[gt] = -1;
+  }
+  __syncthreads();
+  // the staged lists, plane by plane: lane -> (plane kk + lane / DT, particle lane % DT)
+  const int tl = lane % DT;
+  const int64_t pl = i0 + tl;
+  const bool own = pl < n && s_gn[tl] >= 0;
+  const int glim = own ? s_gn[tl] : 0;
+  const int rlim = own ? s_rn[tl] : 0;
+  const int kmax = wave_max_i32(max(glim, rlim));
+  for (int kk = 0; kk < kmax; kk += 64 / DT) {
+    const int k = kk + lane / DT;
+    if (k < glim) a.gl[list_at(pl, k, n)] = s_i[k][tl];
+    if (k < rlim) {
+      a.cand[list_at(pl, k, n)] = s_i[DCAP - 1 - k][tl];
+      a.rest_r2[list_at(pl, k, n)] = s_f[k][tl];
+    }
+  }
+  if (lane < DT && pl < n) {
+    a.gl_cnt[pl] = own ? glim : -1;
+    if (own) a.cand_cnt[pl] = rlim;
+  }
+  count_add(a.counters + C_PASS_NOCONV, noconv);
+  count_add(a.counters + C_PASS_BOOSTS, boosts);
+  count_add(a.counters + C_PASS_FAIL, fails);
+  count_add(a.counters + C_CELL_OVERFLOW, overflow);
+}
+
+// The lists density_k could not hold (gl_cnt = -1): one lane per particle,
+// the list streamed from HBM on every pass, then split in place (an entry
+// moves only to a slot at or before its own).
+__global__ void __launch_bounds__(BS) density_long_k(DensityArgs a, CellGrid g) {
+  const int64_t i = xcd_block(blockIdx.x, gridDim.x) * (int64_t)blockDim.x + threadIdx.x;
+  const int64_t n = a.n;
+  int64_t noconv = 0, boosts = 0, fails = 0, overflow = 0;
+  if (i < n && a.gl_cnt[i] < 0) {
+    const int cnt = a.cand_cnt[i];
+    auto at = [&](int k) { return list_at(i, k, n); };
+    const double4 pi = a.pos[i];
+    auto sums = [&](double h2, double ih, double &s, double &ds) {
+      s = 0.0;
+      ds = 0.0;
+      for (int k = 0; k < cnt; ++k) {
+        const double r2 = a.cand_r2[at(k)];
+        if (r2 < h2) add_pair(s, ds, r2, ih);
+      }
+    };
+    auto esums = [&](double h2, double ih, double &ws, double e[6]) {
+      ws = 0.0;
+      for (int q = 0; q < 6; ++q) e[q] = 0.0;
+      for (int k = 0; k < cnt; ++k) {
+        const double r2 = a.cand_r2[at(k)];
+        if (r2 < h2) add_e(ws, e, r2, ih, a.pos[a.cand[at(k)]], pi, g);
+      }
+    };
+    const HSolve r = newton_h(a, g, a.H[i], sums, esums);
+    const double h2 = r.h * r.h;
+    int gn = 0, rn = 0;
+    for (int k = 0; k < cnt; ++k) {
+      const double r2 = a.cand_r2[at(k)];
+      const int j = a.cand[at(k)];
+      if (r2 < h2) {
+        a.gl[at(gn++)] = j;
+      } else {
+        a.cand[at(rn)] = j;
+        a.rest_r2[at(rn++)] = (float)r2;
+      }
+    }
+    a.gl_cnt[i] = gn;
+    a.cand_cnt[i] = rn;
+    finish_particle(a, i, r);
+    noconv = r.noconv;
+    boosts = r.boosts;
+    fails = r.fails;
+    overflow = r.overflow;
   }
   count_add(a.counters + C_PASS_NOCONV, noconv);
   count_add(a.counters + C_PASS_BOOSTS, boosts);
@@ -380,6 +578,7 @@ hipError_t launch_density(mfm_ctx *ctx, const mfm_particles *pp) {
   a.cand = ctx->cand;
   a.cand_cnt = ctx->cand_cnt;
   a.cand_r2 = ctx->cand_r2;
+  a.rest_r2 = ctx->rest_r2;
   a.gl = ctx->gl;
   a.gl_cnt = ctx->gl_cnt;
   a.gamma = ctx->p.gamma;
@@ -390,6 +589,7 @@ hipError_t launch_density(mfm_ctx *ctx, const mfm_particles *pp) {
   a.h_maxit = ctx->p.h_maxit;
   a.max_boosts = ctx->p.max_boosts;
   a.counters = ctx->counters;
-  density_k<<<blocks_for(pp->n, BS), BS, 0, ctx->stream>>>(a, ctx->grid);
+  density_k<<<(unsigned)((pp->n + DT - 1) / DT), 64, 0, ctx->stream>>>(a, ctx->grid);
+  density_long_k<<<blocks_for(pp->n, BS), BS, 0, ctx->stream>>>(a, ctx->grid);
   return hipGetLastError();
 }

@@ -30,8 +30,8 @@ struct GradArgs {
   const double *gin;
   const double *H;      // converged support radii (SoA: 16 particles per cache line)
   const double4 *pos;   // (x, y, z, 0) per particle
-  const int32_t *cand, *cand_cnt;
-  const double *cand_r2;
+  const int32_t *cand, *cand_cnt;  // candidates with r >= H_i
+  const float *rest_r2;             // their r^2, rounded to FP32
   const int32_t *gl, *gl_cnt;
   double *B, *grad, *ncond, *dt_i, *rec;
   int32_t *fslot, *fcnt;
@@ -164,15 +164,26 @@ __global__ void __launch_bounds__(BS) gradients_k(GradArgs a) {
       const T proj = (d0 * dq[1] + d1 * dq[2] + d2 * dq[3]) / r;
       vsig = fmax(vsig, ci + cj - fmin(T(0), proj));
     }
-    // (2) faces with H_i <= r < H_j, from the candidate list
+    // (2) faces with H_i <= r < H_j, from the other candidates (r >= H_i).
+    // Their r^2 is stored in FP32 (relative error <= 2^-24): a neighbour
+    // clearly inside or outside H_j is decided from it, one within a band of
+    // 2^-22 around H_j^2 from the exact FP64 r^2 of the positions.
     const int cnt = a.cand_cnt[i];
     for (int k = 0; k < cnt; ++k) {
       const int64_t at = list_at(i, k, n);
-      const double r2 = a.cand_r2[at];
-      if (r2 < h2) continue;
       const int j = a.cand[at];
+      const double r2f = (double)a.rest_r2[at];
       const double hj = a.H[j];
-      if (r2 < hj * hj && ((j < b0 || j >= b0 + FLUX_BLOCK) || emit_face((int)i, j))) {
+      const double hj2 = hj * hj;
+      bool in = r2f < hj2 * (1.0 - 0x1p-22) && r2f > 1e-30;
+      if (!in && !(r2f > hj2 * (1.0 + 0x1p-22) && r2f > 1e-30)) {
+        const double4 pj = a.pos[j];
+        const double e0 = min_image(pj.x - xi, a.box[0], a.half[0]);
+        const double e1 = min_image(pj.y - yi, a.box[1], a.half[1]);
+        const double e2 = min_image(pj.z - zi, a.box[2], a.half[2]);
+        in = e0 * e0 + e1 * e1 + e2 * e2 < hj2;
+      }
+      if (in && ((j < b0 || j >= b0 + FLUX_BLOCK) || emit_face((int)i, j))) {
         a.fslot[list_at(i, nf, n)] = j;
         ++nf;
       }
@@ -331,7 +342,7 @@ hipError_t launch_gradients(mfm_ctx *ctx, const mfm_particles *pp, double dt_max
   a.pos = reinterpret_cast<const double4 *>(ctx->pos4);
   a.cand = ctx->cand;
   a.cand_cnt = ctx->cand_cnt;
-  a.cand_r2 = ctx->cand_r2;
+  a.rest_r2 = ctx->rest_r2;
   a.gl = ctx->gl;
   a.gl_cnt = ctx->gl_cnt;
   a.B = pp->B; a.grad = pp->grad; a.ncond = pp->ncond; a.dt_i = pp->dt_i; a.rec = ctx->rec;

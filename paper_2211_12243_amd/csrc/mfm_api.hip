@@ -12,8 +12,8 @@ namespace {
 constexpr size_t ALIGN = 256;
 
 struct Layout {
-  size_t code, count, start, cursor, crange, scan, order, tmp, pos4, cand, cand_r2, cand_cnt, gl,
-      gl_cnt, gin, fslot, fcnt, rec, red, counters, scalars;
+  size_t code, count, start, cursor, crange, scan, order, tmp, pos4, cand, cand_r2, rest_r2,
+      cand_cnt, gl, gl_cnt, gin, fslot, fcnt, rec, red, counters, scalars;
   size_t total;
   int64_t ncodes_max;
   size_t scan_len;
@@ -51,6 +51,7 @@ Layout make_layout(const mfm_params *p, int64_t n) {
   L.pos4 = take(32 * (size_t)n);
   L.cand = take(4 * list_len(p->max_list, n));
   L.cand_r2 = take(8 * list_len(p->max_list, n));
+  L.rest_r2 = take(4 * list_len(p->max_list, n));
   L.cand_cnt = take(4 * (size_t)n);
   L.gl = take(4 * list_len(p->max_list, n));
   L.gl_cnt = take(4 * (size_t)n);
@@ -238,6 +239,7 @@ int mfm_create(const mfm_params *p, int64_t n_max, void *workspace, size_t works
   ctx->pos4 = (double *)(ctx->ws + L.pos4);
   ctx->cand = (int32_t *)(ctx->ws + L.cand);
   ctx->cand_r2 = (double *)(ctx->ws + L.cand_r2);
+  ctx->rest_r2 = (float *)(ctx->ws + L.rest_r2);
   ctx->cand_cnt = (int32_t *)(ctx->ws + L.cand_cnt);
   ctx->gin = (double *)(ctx->ws + L.gin);
   ctx->gl = (int32_t *)(ctx->ws + L.gl);

@@ -95,8 +95,10 @@ struct mfm_ctx {
   int32_t *order;      // n: input slot of each sorted slot
   double *tmp;         // 11 n doubles: gather buffer of the permutation
   double *pos4;        // 4 n: (x, y, z, 0) per particle, for the neighbour search
-  int32_t *cand;       // max_list * n candidates (r < cell side), entry k of i at [k * n + i]
-  double *cand_r2;     // max_list * n: their squared distances
+  int32_t *cand;       // max_list * n candidates (r < cell side), entry k of i at [k * n + i];
+                       // after the density loop: the candidates with r >= H_i
+  double *cand_r2;     // max_list * n: their squared distances (FP64, from the search)
+  float *rest_r2;      // max_list * n: squared distances of the r >= H_i list, rounded to FP32
   int32_t *cand_cnt;   // n
   int32_t *gl;         // max_list * n: gather set r < H_i of each particle (k-major), from the density loop
   int32_t *gl_cnt;     // n
