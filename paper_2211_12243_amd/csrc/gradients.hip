@@ -24,6 +24,12 @@ constexpr int BS = 256;
 constexpr int RED_BLOCKS = 1024;
 constexpr double PI = 3.14159265358979323846;
 constexpr float MIXED_FP64_NCOND = 10.0f;
+// Face slots leave through a ring of RING planes per wavefront in LDS: a
+// lane appends at its own rate, and a plane is stored (64 consecutive
+// particles, one 256-byte write) once every lane has passed it.  A lone
+// 4-byte store per lane into separate planes cost a full sector of HBM
+// write each (measured 1.6 GB written per launch instead of 0.8).
+constexpr int RING = 16;
 
 struct GradArgs {
   int64_t n;
@@ -82,11 +88,16 @@ __device__ __forceinline__ void sym_apply(const T b[6], const T s[3], T g[3]) {
 
 template <typename T>
 __global__ void __launch_bounds__(BS) gradients_k(GradArgs a) {
+  __shared__ int32_t s_ring[BS / 64][RING][64];
   const int64_t i = xcd_block(blockIdx.x, gridDim.x) * (int64_t)blockDim.x + threadIdx.x;
   const int64_t n = a.n;
   int64_t pairs = 0, singular = 0, inv64 = 0;
-  if (i < n) {
-    const double *gi = a.gin + i * GIN_STRIDE;
+  // every lane runs the loops below (the ring's plane bookkeeping is a
+  // wavefront reduction); a lane past the end works on particle 0 and
+  // writes nothing
+  const bool live = i < n;
+  {
+    const double *gi = a.gin + (live ? i : 0) * GIN_STRIDE;
     const double xi = gi[GIN_X], yi = gi[GIN_Y], zi = gi[GIN_Z], hi = gi[GIN_H];
     const double h2 = hi * hi;
     const T ih = T(1.0 / hi), wnorm = T(8.0 / (PI * hi * h2));
@@ -106,88 +117,119 @@ __global__ void __launch_bounds__(BS) gradients_k(GradArgs a) {
     }
     T vsig = T(0);
     int nf = 0;
+    // the face ring: planes [0, flushed) are stored; a lane's face number nf
+    // >= flushed sits in slot nf % RING, one below flushed (a lane that fell
+    // behind a forced store) goes straight to HBM
+    const int wv = threadIdx.x >> 6, ln = threadIdx.x & 63;
+    int flushed = 0;
+    auto put_face = [&](int j) {
+      if (nf >= flushed)
+        s_ring[wv][nf % RING][ln] = j;
+      else
+        a.fslot[list_at(i, nf, n)] = j;
+      ++nf;
+    };
+    auto store_plane = [&](int p) {
+      if (live && nf > p) a.fslot[list_at(i, p, n)] = s_ring[wv][p % RING][ln];
+    };
+    // before a step that may add one face per lane: keep every slot inside the ring
+    auto make_room = [&]() {
+      const int hi = wave_max_i32(nf);
+      while (hi >= flushed + RING) store_plane(flushed++);
+    };
+    // after it: store the planes every lane has passed
+    auto store_done = [&]() {
+      const int lo = wave_min_i32(live ? nf : 0x7fffffff);
+      while (flushed < lo) store_plane(flushed++);
+    };
     // faces of the flux loop: r < max(H_i, H_j); one evaluation per face
     // inside a block, one per side across blocks.
     // (1) the gather set r < H_i (the density loop's compact list, in
     // candidate order): every member is also a face
-    const int gc = a.gl_cnt[i];
-    for (int k = 0; k < gc; ++k) {
-      const int j = a.gl[list_at(i, k, n)];
-      if ((j < b0 || j >= b0 + FLUX_BLOCK) || emit_face((int)i, j)) {
-        a.fslot[list_at(i, nf, n)] = j;
-        ++nf;
-      }
-      const double *gj = a.gin + (int64_t)j * GIN_STRIDE;
-      ++pairs;
-      const double e0 = min_image(gj[GIN_X] - xi, a.box[0], a.half[0]);
-      const double e1 = min_image(gj[GIN_Y] - yi, a.box[1], a.half[1]);
-      const double e2 = min_image(gj[GIN_Z] - zi, a.box[2], a.half[2]);
-      const double r2 = e0 * e0 + e1 * e1 + e2 * e2;
-      if (r2 == 0.0) continue;
-      const T d0 = T(e0), d1 = T(e1), d2 = T(e2);
-      const T r = T(sqrt(r2));
-      // neighbour values: FP64 on the FP64 path; on the mixed path their FP32
-      // copies (half the bytes through the cache; the separation stays FP64)
-      double qj[5];
-      T vj, cj;
-      if constexpr (sizeof(T) == sizeof(float)) {
-        const float4 *gf = reinterpret_cast<const float4 *>(gj + GIN_F32);
-        const float4 f0 = gf[0], f1 = gf[1];
-        vj = f0.x;
-        qj[0] = f0.y; qj[1] = f0.z; qj[2] = f0.w; qj[3] = f1.x; qj[4] = f1.y;
-        cj = f1.z;
-      } else {
-        vj = T(gj[GIN_V]);
-        qj[0] = gj[GIN_RHO]; qj[1] = gj[GIN_VX]; qj[2] = gj[GIN_VY]; qj[3] = gj[GIN_VZ];
-        qj[4] = gj[GIN_P];
-        cj = T(gj[GIN_C]);
-      }
-      const T wv = vj * wnorm * spline_wt<T>(r * ih);
-      e[0] += wv * d0 * d0;
-      e[1] += wv * d0 * d1;
-      e[2] += wv * d0 * d2;
-      e[3] += wv * d1 * d1;
-      e[4] += wv * d1 * d2;
-      e[5] += wv * d2 * d2;
-      T dq[5];
+    const int gc = live ? a.gl_cnt[i] : 0;
+    const int gmax = wave_max_i32(gc);
+    for (int k = 0; k < gmax; ++k) {
+      make_room();
+      if (k < gc) {
+        const int j = a.gl[list_at(i, k, n)];
+        if ((j < b0 || j >= b0 + FLUX_BLOCK) || emit_face((int)i, j)) put_face(j);
+        const double *gj = a.gin + (int64_t)j * GIN_STRIDE;
+        ++pairs;
+        const double e0 = min_image(gj[GIN_X] - xi, a.box[0], a.half[0]);
+        const double e1 = min_image(gj[GIN_Y] - yi, a.box[1], a.half[1]);
+        const double e2 = min_image(gj[GIN_Z] - zi, a.box[2], a.half[2]);
+        const double r2 = e0 * e0 + e1 * e1 + e2 * e2;
+        if (r2 != 0.0) {
+          const T d0 = T(e0), d1 = T(e1), d2 = T(e2);
+          const T r = T(sqrt(r2));
+          // neighbour values: FP64 on the FP64 path; on the mixed path their FP32
+          // copies (half the bytes through the cache; the separation stays FP64)
+          double qj[5];
+          T vj, cj;
+          if constexpr (sizeof(T) == sizeof(float)) {
+            const float4 *gf = reinterpret_cast<const float4 *>(gj + GIN_F32);
+            const float4 f0 = gf[0], f1 = gf[1];
+            vj = f0.x;
+            qj[0] = f0.y; qj[1] = f0.z; qj[2] = f0.w; qj[3] = f1.x; qj[4] = f1.y;
+            cj = f1.z;
+          } else {
+            vj = T(gj[GIN_V]);
+            qj[0] = gj[GIN_RHO]; qj[1] = gj[GIN_VX]; qj[2] = gj[GIN_VY]; qj[3] = gj[GIN_VZ];
+            qj[4] = gj[GIN_P];
+            cj = T(gj[GIN_C]);
+          }
+          const T wv = vj * wnorm * spline_wt<T>(r * ih);
+          e[0] += wv * d0 * d0;
+          e[1] += wv * d0 * d1;
+          e[2] += wv * d0 * d2;
+          e[3] += wv * d1 * d1;
+          e[4] += wv * d1 * d2;
+          e[5] += wv * d2 * d2;
+          T dq[5];
 #pragma unroll
-      for (int q = 0; q < 5; ++q) {
-        dq[q] = T(qj[q] - q64[q]);
-        const T df = wv * dq[q];
-        s[q][0] += df * d0;
-        s[q][1] += df * d1;
-        s[q][2] += df * d2;
-        qmax[q] = fmax(qmax[q], qj[q]);
-        qmin[q] = fmin(qmin[q], qj[q]);
+          for (int q = 0; q < 5; ++q) {
+            dq[q] = T(qj[q] - q64[q]);
+            const T df = wv * dq[q];
+            s[q][0] += df * d0;
+            s[q][1] += df * d1;
+            s[q][2] += df * d2;
+            qmax[q] = fmax(qmax[q], qj[q]);
+            qmin[q] = fmin(qmin[q], qj[q]);
+          }
+          // signal velocity: x_i - x_j = -d
+          const T proj = (d0 * dq[1] + d1 * dq[2] + d2 * dq[3]) / r;
+          vsig = fmax(vsig, ci + cj - fmin(T(0), proj));
+        }
       }
-      // signal velocity: x_i - x_j = -d
-      const T proj = (d0 * dq[1] + d1 * dq[2] + d2 * dq[3]) / r;
-      vsig = fmax(vsig, ci + cj - fmin(T(0), proj));
+      store_done();
     }
     // (2) faces with H_i <= r < H_j, from the other candidates (r >= H_i).
     // Their r^2 is stored in FP32 (relative error <= 2^-24): a neighbour
     // clearly inside or outside H_j is decided from it, one within a band of
     // 2^-22 around H_j^2 from the exact FP64 r^2 of the positions.
-    const int cnt = a.cand_cnt[i];
-    for (int k = 0; k < cnt; ++k) {
-      const int64_t at = list_at(i, k, n);
-      const int j = a.cand[at];
-      const double r2f = (double)a.rest_r2[at];
-      const double hj = a.H[j];
-      const double hj2 = hj * hj;
-      bool in = r2f < hj2 * (1.0 - 0x1p-22) && r2f > 1e-30;
-      if (!in && !(r2f > hj2 * (1.0 + 0x1p-22) && r2f > 1e-30)) {
-        const double4 pj = a.pos[j];
-        const double e0 = min_image(pj.x - xi, a.box[0], a.half[0]);
-        const double e1 = min_image(pj.y - yi, a.box[1], a.half[1]);
-        const double e2 = min_image(pj.z - zi, a.box[2], a.half[2]);
-        in = e0 * e0 + e1 * e1 + e2 * e2 < hj2;
+    const int cnt = live ? a.cand_cnt[i] : 0;
+    const int cmax = wave_max_i32(cnt);
+    for (int k = 0; k < cmax; ++k) {
+      make_room();
+      if (k < cnt) {
+        const int64_t at = list_at(i, k, n);
+        const int j = a.cand[at];
+        const double r2f = (double)a.rest_r2[at];
+        const double hj = a.H[j];
+        const double hj2 = hj * hj;
+        bool in = r2f < hj2 * (1.0 - 0x1p-22) && r2f > 1e-30;
+        if (!in && !(r2f > hj2 * (1.0 + 0x1p-22) && r2f > 1e-30)) {
+          const double4 pj = a.pos[j];
+          const double e0 = min_image(pj.x - xi, a.box[0], a.half[0]);
+          const double e1 = min_image(pj.y - yi, a.box[1], a.half[1]);
+          const double e2 = min_image(pj.z - zi, a.box[2], a.half[2]);
+          in = e0 * e0 + e1 * e1 + e2 * e2 < hj2;
+        }
+        if (in && ((j < b0 || j >= b0 + FLUX_BLOCK) || emit_face((int)i, j))) put_face(j);
       }
-      if (in && ((j < b0 || j >= b0 + FLUX_BLOCK) || emit_face((int)i, j))) {
-        a.fslot[list_at(i, nf, n)] = j;
-        ++nf;
-      }
+      store_done();
     }
+    for (const int top = wave_max_i32(nf); flushed < top;) store_plane(flushed++);
     T b[6];
     T det = sym_inv<T>(e, b);
     T nc = sym_frob<T>(b) * sym_frob<T>(e) / T(3);
@@ -209,14 +251,14 @@ __global__ void __launch_bounds__(BS) gradients_k(GradArgs a) {
         g[q][1] = T(g64[1]);
         g[q][2] = T(g64[2]);
       }
-      ++inv64;
+      if (live) ++inv64;
     } else {
 #pragma unroll
       for (int q = 0; q < 5; ++q) sym_apply<T>(b, s[q], g[q]);
 #pragma unroll
       for (int k = 0; k < 6; ++k) b64[k] = (double)b[k];
     }
-    if (!(det != T(0)) || !isfinite(det)) ++singular;
+    if (live && (!(det != T(0)) || !isfinite(det))) ++singular;
     T alpha[5] = {T(1), T(1), T(1), T(1), T(1)};
     if (a.limiter & MFM_LIMIT_BJ) {
       T dmax[5] = {0, 0, 0, 0, 0}, dmin[5] = {0, 0, 0, 0, 0};
@@ -243,56 +285,58 @@ __global__ void __launch_bounds__(BS) gradients_k(GradArgs a) {
         alpha[q] = fmin(T(1), beta * fmin(rp, rm));
       }
     }
+    if (live) {
 #pragma unroll
-    for (int k = 0; k < 6; ++k) a.B[k * n + i] = b64[k];
-    if (sizeof(T) == sizeof(double)) {
-      double *rec = a.rec + i * R_STRIDE;
-      rec[R_X] = xi;
-      rec[R_Y] = yi;
-      rec[R_Z] = zi;
-      rec[R_IH] = (double)ih;
-      rec[R_V] = gi[GIN_V];
-      rec[R_RHO] = q64[0];
-      rec[R_IRHO] = 1.0 / q64[0];
-      rec[R_VX] = q64[1];
-      rec[R_VY] = q64[2];
-      rec[R_VZ] = q64[3];
-      rec[R_P] = q64[4];
+      for (int k = 0; k < 6; ++k) a.B[k * n + i] = b64[k];
+      if (sizeof(T) == sizeof(double)) {
+        double *rec = a.rec + i * R_STRIDE;
+        rec[R_X] = xi;
+        rec[R_Y] = yi;
+        rec[R_Z] = zi;
+        rec[R_IH] = (double)ih;
+        rec[R_V] = gi[GIN_V];
+        rec[R_RHO] = q64[0];
+        rec[R_IRHO] = 1.0 / q64[0];
+        rec[R_VX] = q64[1];
+        rec[R_VY] = q64[2];
+        rec[R_VZ] = q64[3];
+        rec[R_P] = q64[4];
 #pragma unroll
-      for (int k = 0; k < 6; ++k) rec[R_B + k] = b64[k];
+        for (int k = 0; k < 6; ++k) rec[R_B + k] = b64[k];
 #pragma unroll
-      for (int q = 0; q < 5; ++q)
+        for (int q = 0; q < 5; ++q)
 #pragma unroll
-        for (int k = 0; k < 3; ++k) {
-          const double v = (double)(alpha[q] * g[q][k]);
-          a.grad[(3 * q + k) * n + i] = v;
-          rec[R_G + 3 * q + k] = v;
-        }
-    } else {
-      float *rec = reinterpret_cast<float *>(a.rec) + i * F_STRIDE;
-      rec[F_IH] = (float)ih;
-      rec[F_V] = (float)gi[GIN_V];
-      rec[F_RHO] = (float)qi[0];
-      rec[F_IRHO] = (float)(1.0 / q64[0]);
-      rec[F_VX] = (float)qi[1];
-      rec[F_VY] = (float)qi[2];
-      rec[F_VZ] = (float)qi[3];
-      rec[F_P] = (float)qi[4];
+          for (int k = 0; k < 3; ++k) {
+            const double v = (double)(alpha[q] * g[q][k]);
+            a.grad[(3 * q + k) * n + i] = v;
+            rec[R_G + 3 * q + k] = v;
+          }
+      } else {
+        float *rec = reinterpret_cast<float *>(a.rec) + i * F_STRIDE;
+        rec[F_IH] = (float)ih;
+        rec[F_V] = (float)gi[GIN_V];
+        rec[F_RHO] = (float)qi[0];
+        rec[F_IRHO] = (float)(1.0 / q64[0]);
+        rec[F_VX] = (float)qi[1];
+        rec[F_VY] = (float)qi[2];
+        rec[F_VZ] = (float)qi[3];
+        rec[F_P] = (float)qi[4];
 #pragma unroll
-      for (int k = 0; k < 6; ++k) rec[F_B + k] = (float)b64[k];
+        for (int k = 0; k < 6; ++k) rec[F_B + k] = (float)b64[k];
 #pragma unroll
-      for (int q = 0; q < 5; ++q)
+        for (int q = 0; q < 5; ++q)
 #pragma unroll
-        for (int k = 0; k < 3; ++k) {
-          const float v = (float)(alpha[q] * g[q][k]);
-          a.grad[(3 * q + k) * n + i] = (double)v;
-          rec[F_G + 3 * q + k] = v;
-        }
-      rec[F_STRIDE - 3] = rec[F_STRIDE - 2] = rec[F_STRIDE - 1] = 0.0f;
+          for (int k = 0; k < 3; ++k) {
+            const float v = (float)(alpha[q] * g[q][k]);
+            a.grad[(3 * q + k) * n + i] = (double)v;
+            rec[F_G + 3 * q + k] = v;
+          }
+        rec[F_STRIDE - 3] = rec[F_STRIDE - 2] = rec[F_STRIDE - 1] = 0.0f;
+      }
+      a.ncond[i] = (double)nc;
+      a.dt_i[i] = vsig > T(0) ? a.c_cfl * hi / (double)vsig : __builtin_huge_val();
+      a.fcnt[i] = nf;
     }
-    a.ncond[i] = (double)nc;
-    a.dt_i[i] = vsig > T(0) ? a.c_cfl * hi / (double)vsig : __builtin_huge_val();
-    a.fcnt[i] = nf;
   }
   count_add(a.counters + C_GRAD_PAIRS, pairs);
   count_add(a.counters + C_SINGULAR_E, singular);

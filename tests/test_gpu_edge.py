@@ -120,3 +120,13 @@ def test_cells_rebuilt_when_smoothing_lengths_grow():
     check_fields(gpu, new, dt, diag, ref, 1e-12, st)
     print("cell rebuilds", diag["cell_rebuilds"], flush=True)
     assert diag["cell_rebuilds"] >= 1
+
+
+def test_long_and_short_candidate_lists():
+    """Cells of 1.3 max H on a random gas: about two thirds of the candidate
+    lists are longer than the density loop holds in registers (96 entries) and
+    take its one-lane path, the others the register path, in the same pass."""
+    st = W.random_gas(N=3000, seed=9)
+    print("[edge] long and short candidate lists", flush=True)
+    gpu, new, dt, diag, ref = run_both({"scheme": "mfv", "max_list": 512, "cell_margin": 1.3}, st)
+    check_fields(gpu, new, dt, diag, ref, 1e-12, st)
