@@ -163,7 +163,19 @@ __global__ void writeback_k(int64_t n, Fields fs, const double *__restrict__ tmp
 #pragma unroll
   for (int f = 0; f < 10; ++f) fs.f[f][k] = tmp[f * n + k];
   if (fs.id) fs.id[k] = ((const int64_t *)(tmp + 10 * n))[k];
-  pos4[k] = make_double4(tmp[k], tmp[n + k], tmp[2 * n + k], 0.0);
+  pos4[k] = make_double4(tmp[k], tmp[n + k], tmp[2 * n + k], tmp[9 * n + k]);
+}
+
+// Largest H of each cell at the build (0 for an empty cell): the search
+// sizes each cell's candidate radius from its 27-cell neighbourhood.
+__global__ void cell_hmax_k(int64_t ncodes, const int2 *__restrict__ range,
+                            const double4 *__restrict__ pos4, double *chmax) {
+  const int64_t c = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (c >= ncodes) return;
+  const int2 r = range[c];
+  double m = 0.0;
+  for (int k = 0; k < r.y; ++k) m = fmax(m, pos4[r.x + k].w);
+  chmax[c] = m;
 }
 
 }  // namespace
@@ -200,5 +212,7 @@ hipError_t launch_build_cells(mfm_ctx *ctx, const mfm_particles *pp, int64_t *pe
   gather_k<<<blocks_for(n, BS), BS, 0, st>>>(n, fs, ctx->order, ctx->tmp, perm);
   writeback_k<<<blocks_for(n, BS), BS, 0, st>>>(n, fs, ctx->tmp,
                                                 reinterpret_cast<double4 *>(ctx->pos4));
+  cell_hmax_k<<<blocks_for(ctx->ncodes, BS), BS, 0, st>>>(
+      ctx->ncodes, ctx->crange, reinterpret_cast<const double4 *>(ctx->pos4), ctx->chmax);
   return hipGetLastError();
 }

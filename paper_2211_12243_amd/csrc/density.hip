@@ -3,8 +3,12 @@
 //
 // cand_cell_k: for every particle, the candidates in the 27 cells around its
 // own (cell side >= cell_margin * max H, so every pair closer than the side
-// is found) with r < side, as (index, r^2) in the k-major list (list_at).
-// The list is a superset of every neighbour set the step uses.
+// is found) with r < R_c, as (index, r^2) in the k-major list (list_at).
+// R_c = min(side, cell_margin * the largest H at the build in the 27 cells):
+// the density loop bounds each H by cell_margin times its value at the build
+// (else the pass is redone), so every H_j of the step stays below the R_c of
+// every cell around j's, and the list is a superset of every neighbour set
+// the step uses, however unequal the H.
 //
 // density_k solves, for each particle,
 //   g(H) = (32/3) sum_j w(r_ij / H) - N_NGB = 0
@@ -90,14 +94,17 @@ __global__ void __launch_bounds__(64) cand_cell_k(CandArgs a, CellGrid g) {
   const int cap = a.max_list;
   // the 27 neighbour ranges in the search order, and their prefix sums
   int cnt27 = 0, st27 = 0;
+  double hnb = 0.0;
   if (lane < 27) {
     int zz = cz + lane / 9 - 1, yy = cy + (lane / 3) % 3 - 1, xx = cx + lane % 3 - 1;
     zz = zz < 0 ? zz + g.nc[2] : (zz >= g.nc[2] ? zz - g.nc[2] : zz);
     yy = yy < 0 ? yy + g.nc[1] : (yy >= g.nc[1] ? yy - g.nc[1] : yy);
     xx = xx < 0 ? xx + g.nc[0] : (xx >= g.nc[0] ? xx - g.nc[0] : xx);
-    const int2 rg = g.range[morton3(xx, yy, zz)];
+    const uint32_t nb = morton3(xx, yy, zz);
+    const int2 rg = g.range[nb];
     st27 = rg.x;
     cnt27 = rg.y;
+    hnb = g.chmax[nb];
   }
   int inc = cnt27;
   for (int o = 1; o < 32; o <<= 1) {
@@ -111,7 +118,8 @@ __global__ void __launch_bounds__(64) cand_cell_k(CandArgs a, CellGrid g) {
   if (lane == 0) s_pre[0] = 0;
   __syncthreads();
   const int C = s_pre[27];
-  const double R2 = g.side_min * g.side_min;
+  const double rc = fmin(g.side_min, g.hfac * wave_max_f64(hnb));
+  const double R2 = rc * rc;
   const uint64_t below = (1ull << lane) - 1ull;
   for (int t0 = 0; t0 < own.y; t0 += TCH) {
     const int T = min(TCH, own.y - t0);
@@ -263,17 +271,18 @@ struct HSolve {
   int noconv, boosts, fails, overflow;
 };
 
-// The smoothing-length solve of one particle from the start value h.
+// The smoothing-length solve of one particle from the start value h, inside
+// the bracket (0, hcap): hcap = min(cell side, cell_margin * H at the build).
 //   sums(h2, ih, s, ds):  s = sum w(q), ds = sum q w'(q) over the list entries
 //                         with r^2 < h2 (q = r / h, ih = 1 / h);
 //   esums(h2, ih, ws, e): ws = sum w(q) and the unweighted E~ = sum w(q) d d^T.
 // The particle itself (w(0) = 1) is added here.  Both must return the same
 // value in every lane that calls them together.
 template <typename Sums, typename ESums>
-__device__ __forceinline__ HSolve newton_h(const DensityArgs &a, const CellGrid &g, double h,
-                                           Sums sums, ESums esums) {
+__device__ __forceinline__ HSolve newton_h(const DensityArgs &a, double hcap, double h, Sums sums,
+                                           ESums esums) {
   HSolve r{};
-  const double cover = g.side_min;
+  const double cover = hcap;
   const double qtol = fmax(a.h_tol, 1e-2 * sqrt(a.h_tol));
   double target = a.n_ngb;
   double s_last = 1.0;
@@ -330,8 +339,9 @@ __device__ __forceinline__ HSolve newton_h(const DensityArgs &a, const CellGrid 
   r.h = h;
   r.h_store = h;
   if (h >= cover * (1.0 - 1e-12)) {
-    // the root lies beyond the cell side: this pass is redone on a coarser
-    // grid, sized from an estimate of the root (at fixed number density the
+    // the root lies beyond the cell side or grew by more than cell_margin
+    // since the build: this pass is redone on a grid (and candidate radii)
+    // sized from an estimate of the root (at fixed number density the
     // neighbour number grows as H^3), written as the start value
     r.overflow = 1;
     r.h_store = cover * cbrt(target / fmax((32.0 / 3.0) * s_last, 1.0)) * 1.05;
@@ -360,6 +370,11 @@ __device__ __forceinline__ void add_e(double &ws, double e[6], double r2, double
     e[4] += w * dy * dz;
     e[5] += w * dz * dz;
   }
+}
+
+// Upper end of a particle's bracket (pi.w: its H at the build).
+__device__ __forceinline__ double hcap_of(const CellGrid &g, double4 pi) {
+  return pi.w > 0.0 ? fmin(g.side_min, g.hfac * pi.w) : g.side_min;
 }
 
 // H, the number density, the primitives and the gradient loop's record of particle i.
@@ -441,7 +456,7 @@ __global__ void __launch_bounds__(64) density_k(DensityArgs a, CellGrid g) {
 #pragma unroll
       for (int q = 0; q < 6; ++q) e[q] = group_sum<DG>(e[q]);
     };
-    const HSolve r = newton_h(a, g, a.H[i], sums, esums);
+    const HSolve r = newton_h(a, hcap_of(g, pi), a.H[i], sums, esums);
     const double h2 = r.h * r.h;
     int gn = 0, rn = 0;
 #pragma unroll
@@ -525,7 +540,7 @@ __global__ void __launch_bounds__(BS) density_long_k(DensityArgs a, CellGrid g) 
         if (r2 < h2) add_e(ws, e, r2, ih, a.pos[a.cand[at(k)]], pi, g);
       }
     };
-    const HSolve r = newton_h(a, g, a.H[i], sums, esums);
+    const HSolve r = newton_h(a, hcap_of(g, pi), a.H[i], sums, esums);
     const double h2 = r.h * r.h;
     int gn = 0, rn = 0;
     for (int k = 0; k < cnt; ++k) {

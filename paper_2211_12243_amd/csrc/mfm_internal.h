@@ -74,6 +74,8 @@ struct CellGrid {
   double box[3];      // periodic sides
   double half[3];     // box / 2
   double side_min;    // smallest cell side: every pair closer than this is in the 27-cell stencil
+  double hfac;        // cell_margin (times the rebuild boost): bound on H / H at the build
+  const double *chmax;   // indexed by Morton code: the cell's largest H at the build
   const int32_t *start;  // indexed by Morton code
   const int32_t *count;  // indexed by Morton code
   const int2 *range;     // (start, count) by Morton code, one load per cell
@@ -94,7 +96,8 @@ struct mfm_ctx {
   int32_t *scan_tmp;   // block sums of the scans
   int32_t *order;      // n: input slot of each sorted slot
   double *tmp;         // 11 n doubles: gather buffer of the permutation
-  double *pos4;        // 4 n: (x, y, z, 0) per particle, for the neighbour search
+  double *pos4;        // 4 n: (x, y, z, H at the build) per particle
+  double *chmax;       // ncodes_max: largest H at the build per cell
   int32_t *cand;       // max_list * n candidates (r < cell side), entry k of i at [k * n + i];
                        // after the density loop: the candidates with r >= H_i
   double *cand_r2;     // max_list * n: their squared distances (FP64, from the search)
@@ -189,6 +192,10 @@ __device__ __forceinline__ int64_t wave_sum_i64(int64_t v) {
 }
 __device__ __forceinline__ double wave_min_f64(double v) {
   for (int o = 32; o > 0; o >>= 1) v = fmin(v, __shfl_xor(v, o, 64));
+  return v;
+}
+__device__ __forceinline__ double wave_max_f64(double v) {
+  for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
   return v;
 }
 __device__ __forceinline__ double wave_sum_f64(double v) {
