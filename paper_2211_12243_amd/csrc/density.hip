@@ -81,6 +81,7 @@ __global__ void __launch_bounds__(64) cand_cell_k(CandArgs a, CellGrid g) {
   __shared__ double s_r2[TCH][LCAP];
   __shared__ int s_start[27];
   __shared__ int s_pre[28];
+  __shared__ double s_shift[27][3];
   __shared__ int s_cnt[TCH];
   const int lane = threadIdx.x;
   const int64_t n = a.n;
@@ -97,6 +98,11 @@ __global__ void __launch_bounds__(64) cand_cell_k(CandArgs a, CellGrid g) {
   double hnb = 0.0;
   if (lane < 27) {
     int zz = cz + lane / 9 - 1, yy = cy + (lane / 3) % 3 - 1, xx = cx + lane % 3 - 1;
+    // a neighbour across the periodic boundary: its particles are taken at
+    // the image next to this cell
+    s_shift[lane][2] = zz < 0 ? -g.box[2] : (zz >= g.nc[2] ? g.box[2] : 0.0);
+    s_shift[lane][1] = yy < 0 ? -g.box[1] : (yy >= g.nc[1] ? g.box[1] : 0.0);
+    s_shift[lane][0] = xx < 0 ? -g.box[0] : (xx >= g.nc[0] ? g.box[0] : 0.0);
     zz = zz < 0 ? zz + g.nc[2] : (zz >= g.nc[2] ? zz - g.nc[2] : zz);
     yy = yy < 0 ? yy + g.nc[1] : (yy >= g.nc[1] ? yy - g.nc[1] : yy);
     xx = xx < 0 ? xx + g.nc[0] : (xx >= g.nc[0] ? xx - g.nc[0] : xx);
@@ -148,7 +154,9 @@ __global__ void __launch_bounds__(64) cand_cell_k(CandArgs a, CellGrid g) {
           const int j = s_start[lo] + (c - s_pre[lo]);
           const double4 pj = a.pos[j];
           jj[s] = j;
-          px[s] = pj.x; py[s] = pj.y; pz[s] = pj.z;
+          px[s] = pj.x + s_shift[lo][0];
+          py[s] = pj.y + s_shift[lo][1];
+          pz[s] = pj.z + s_shift[lo][2];
         }
       }
       for (int t = 0; t < T; ++t) {
@@ -161,9 +169,9 @@ __global__ void __launch_bounds__(64) cand_cell_k(CandArgs a, CellGrid g) {
           bool hit = false;
           double r2 = 0.0;
           if (jj[s] >= 0 && jj[s] != ti) {
-            const double ex = min_image(px[s] - ptx, g.box[0], g.half[0]);
-            const double ey = min_image(py[s] - pty, g.box[1], g.half[1]);
-            const double ez = min_image(pz[s] - ptz, g.box[2], g.half[2]);
+            // the image taken above is the nearest one for every pair closer
+            // than the cell side (at least 3 cells per axis)
+            const double ex = px[s] - ptx, ey = py[s] - pty, ez = pz[s] - ptz;
             r2 = ex * ex + ey * ey + ez * ez;
             hit = r2 < R2;
           }
