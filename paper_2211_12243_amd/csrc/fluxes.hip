@@ -290,8 +290,9 @@ __device__ int riemann_solve(const Gas<T> &G, const Side<T> &L, const Side<T> &R
   }
   const T pfloor = T(1e-10) * T(0.5) * (L.p + R.p);
   // FP64: stop once a step is below 1e-2 sqrt(tol); the root is then within
-  // ~1e-4 tol.  FP32: run to the tolerance (the FP64 check follows).
-  const T qtol = sizeof(T) == sizeof(double) ? T(1e-4) * tol : T(0);
+  // ~1e-4 tol.  FP32: stop once a step is below 1e-4, which leaves the root
+  // at FP32 precision; the FP64 check that follows sets p* and u*.
+  const T qtol = sizeof(T) == sizeof(double) ? T(1e-4) * tol : T(1e-8);
   if (p_learned > T(0)) {
     if (p_learned > pfloor && isfinite(p_learned)) {
       const int st = riemann_newton<T, M>(G, L, R, p_learned, pfloor, tol, maxit, qtol,
