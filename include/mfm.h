@@ -46,7 +46,7 @@ extern "C" {
 #define MFM_E_WORKSPACE (-2)  /* workspace missing or smaller than mfm_workspace_bytes() */
 #define MFM_E_HIP (-3)        /* HIP runtime error (text in mfm_last_error) */
 #define MFM_E_H_NOCONV (-4)   /* some smoothing-length solve hit its iteration cap */
-#define MFM_E_CELLS (-5)      /* smoothing lengths outgrew the cell grid after rebuilds */
+#define MFM_E_CELLS (-5)      /* smoothing lengths outgrew the cell grid: rebuild and repeat */
 #define MFM_E_LIST (-6)       /* a particle has more neighbours than the list capacity */
 #define MFM_E_NONFINITE (-7)  /* a non-finite time step or state was produced */
 #define MFM_E_STATE (-8)      /* call order violated (e.g. mfm_fluxes before mfm_gradients) */
@@ -77,13 +77,20 @@ typedef struct mfm_params {
   double n_ngb;          /* neighbour number N_NGB (> 32/3, non-integer allowed) */
   double ncond_max;      /* condition-number threshold (default 100) */
   double ngb_boost;      /* N_NGB factor when a particle fails the check (default 1.2) */
-  double h_tol;          /* relative tolerance of the smoothing-length solve (default 1e-13) */
+  double h_tol;          /* relative tolerance of the smoothing-length solve (default 1e-13):
+                            it ends on a Newton step below h_tol H, or below
+                            1e-2 sqrt(h_tol) H, where its quadratic convergence
+                            leaves H far closer than h_tol to the root */
   double c_cfl;          /* CFL factor (default 0.2) */
   double psi1, psi2;     /* pairwise limiter constants */
   double riemann_tol;    /* relative Newton step tolerance of the exact solver (default 1e-10) */
   double alpha1;         /* dual-energy switch: U > alpha1 E_kin -> U from E (default 0.01) */
   double box[3];         /* periodic box sides; all > 0 (the library needs a periodic box) */
-  double cell_margin;    /* cell side >= cell_margin * max_i H_i (>= 1, default 1.15) */
+  double cell_margin;    /* cell side >= cell_margin * max_i H_i (>= 1, default 1.15).
+                            Also the largest growth of an H in one density pass
+                            (H <= cell_margin * its value at the cell build);
+                            a cell's candidate radius is cell_margin times the
+                            largest H of its 27-cell neighbourhood */
   int32_t max_cell_dim;  /* cells per axis at most (3..512, default 256) */
   int32_t pad0;
 } mfm_params;
@@ -154,6 +161,7 @@ int mfm_destroy(struct mfm_ctx *ctx);
  * that spatial neighbours are contiguous) and permute the state arrays
  * (x..H) IN PLACE into that order.  perm (device int64, n, may be NULL)
  * receives for each new slot k the slot the particle had before the call.
+ * The H values at this call bound the next mfm_density (see cell_margin).
  * Synchronises (it reads max H to size the grid). */
 int mfm_build_cells(struct mfm_ctx *ctx, const mfm_particles *parts, int64_t *perm);
 
@@ -162,8 +170,12 @@ int mfm_build_cells(struct mfm_ctx *ctx, const mfm_particles *parts, int64_t *pe
  * (self included); if the condition number of E~ = sum_j W d d^T exceeds
  * ncond_max, multiply N_NGB by ngb_boost and solve again.  Writes H, V, rho,
  * P, c, ncond and the neighbour lists used by the next two loops.  Requires
- * mfm_build_cells on the same positions.  If some H reaches the cell side the
- * call rebuilds the cells and repeats (this synchronises). */
+ * mfm_build_cells on the same positions.  If some H reaches its bound (the
+ * cell side, or cell_margin times its value at the build) the pass is
+ * discarded: those H are replaced by estimates of their roots, the next
+ * mfm_build_cells uses a larger margin, and the call returns MFM_E_CELLS;
+ * build and density are then repeated (mfm_step does this, up to 4 times).
+ * Synchronises (it reads the pass counters). */
 int mfm_density(struct mfm_ctx *ctx, const mfm_particles *parts);
 
 /* Loops (2) and (4), sec. 2.3.3, 2.3.6, 2.3.10: E_i = sum_j V_j W_ij d d^T,
