@@ -129,8 +129,9 @@ __global__ void __launch_bounds__(64) cand_cell_k(CandArgs a, CellGrid g) {
   const uint64_t below = (1ull << lane) - 1ull;
   for (int t0 = 0; t0 < own.y; t0 += TCH) {
     const int T = min(TCH, own.y - t0);
-    if (lane < TCH) s_cnt[lane] = 0;
-    // lane t holds particle t of the chunk; the loop below broadcasts it
+    // lane t holds particle t of the chunk and the length of its list; the
+    // loop below broadcasts both
+    int tcnt = 0;
     double tx = 0.0, ty = 0.0, tz = 0.0;
     if (lane < T) {
       const double4 pt = a.pos[own.x + t0 + lane];
@@ -163,7 +164,7 @@ __global__ void __launch_bounds__(64) cand_cell_k(CandArgs a, CellGrid g) {
         const int ti = own.x + t0 + t;
         const double ptx = readlane_f64(tx, t), pty = readlane_f64(ty, t),
                      ptz = readlane_f64(tz, t);
-        int base = s_cnt[t];
+        int base = __builtin_amdgcn_readlane(tcnt, t);
 #pragma unroll
         for (int s = 0; s < SLOTS; ++s) {
           bool hit = false;
@@ -189,10 +190,12 @@ __global__ void __launch_bounds__(64) cand_cell_k(CandArgs a, CellGrid g) {
           }
           base += __popcll(m);
         }
-        if (lane == 0) s_cnt[t] = base;  // read again by this wavefront only: LDS keeps its order
+        tcnt = lane == t ? base : tcnt;
       }
       __syncthreads();
     }
+    if (lane < TCH) s_cnt[lane] = tcnt;
+    __syncthreads();
     // the chunk's staged lists, plane by plane: lane -> (plane kk + lane / TCH, particle lane % TCH)
     int mine = lane < T ? min(s_cnt[lane], min(LCAP, cap)) : 0;
     const int kmax = wave_max_i32(mine);
