@@ -148,10 +148,14 @@ __global__ void __launch_bounds__(BS) gradients_k(GradArgs a) {
     // candidate order): every member is also a face
     const int gc = live ? a.gl_cnt[i] : 0;
     const int gmax = wave_max_i32(gc);
+    // each loop below loads its next list entry one iteration ahead, so that
+    // only the dependent gather is on the critical path
+    int jn = gc > 0 ? a.gl[list_at(i, 0, n)] : 0;
     for (int k = 0; k < gmax; ++k) {
       make_room();
       if (k < gc) {
-        const int j = a.gl[list_at(i, k, n)];
+        const int j = jn;
+        if (k + 1 < gc) jn = a.gl[list_at(i, k + 1, n)];
         if ((j < b0 || j >= b0 + FLUX_BLOCK) || emit_face((int)i, j)) put_face(j);
         const double *gj = a.gin + (int64_t)j * GIN_STRIDE;
         ++pairs;
@@ -209,12 +213,17 @@ __global__ void __launch_bounds__(BS) gradients_k(GradArgs a) {
     // 2^-22 around H_j^2 from the exact FP64 r^2 of the positions.
     const int cnt = live ? a.cand_cnt[i] : 0;
     const int cmax = wave_max_i32(cnt);
+    int cj = cnt > 0 ? a.cand[list_at(i, 0, n)] : 0;
+    float cr = cnt > 0 ? a.rest_r2[list_at(i, 0, n)] : 0.0f;
     for (int k = 0; k < cmax; ++k) {
       make_room();
       if (k < cnt) {
-        const int64_t at = list_at(i, k, n);
-        const int j = a.cand[at];
-        const double r2f = (double)a.rest_r2[at];
+        const int j = cj;
+        const double r2f = (double)cr;
+        if (k + 1 < cnt) {
+          cj = a.cand[list_at(i, k + 1, n)];
+          cr = a.rest_r2[list_at(i, k + 1, n)];
+        }
         const double hj = a.H[j];
         const double hj2 = hj * hj;
         bool in = r2f < hj2 * (1.0 - 0x1p-22) && r2f > 1e-30;
@@ -262,8 +271,10 @@ __global__ void __launch_bounds__(BS) gradients_k(GradArgs a) {
     T alpha[5] = {T(1), T(1), T(1), T(1), T(1)};
     if (a.limiter & MFM_LIMIT_BJ) {
       T dmax[5] = {0, 0, 0, 0, 0}, dmin[5] = {0, 0, 0, 0, 0};
+      int bn = gc > 0 ? a.gl[list_at(i, 0, n)] : 0;
       for (int k = 0; k < gc; ++k) {
-        const double4 pj = a.pos[a.gl[list_at(i, k, n)]];
+        const double4 pj = a.pos[bn];
+        if (k + 1 < gc) bn = a.gl[list_at(i, k + 1, n)];
         const T d0 = T(min_image(pj.x - xi, a.box[0], a.half[0]));
         const T d1 = T(min_image(pj.y - yi, a.box[1], a.half[1]));
         const T d2 = T(min_image(pj.z - zi, a.box[2], a.half[2]));
