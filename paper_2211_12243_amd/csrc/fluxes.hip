@@ -644,24 +644,35 @@ __global__ void __launch_bounds__(FTH) __attribute__((amdgpu_waves_per_eu(2))) f
   const double dt = a.dt[0];
   const T hdt = T(0.5 * dt);
   int64_t nfaces = 0, iters_sum = 0, vac = 0, pos = 0, maxit = 0, fb = 0;
+  // face f of the block: its particle p (pref[p] <= f < pref[p + 1]) and its
+  // partner j, found one round ahead so that the partner's load is in flight
+  // while the current face is solved
+  auto locate = [&](int f, int &pf, int &jf) {
+    int lo = 0, hi = FBS;
+    while (hi - lo > 1) {
+      const int mid = (lo + hi) >> 1;
+      if (pref[mid] <= f) lo = mid; else hi = mid;
+    }
+    pf = lo;
+    jf = a.fslot[list_at(b0 + lo, f - pref[lo], n)];
+  };
+  int p_next = FBS, j_next = 0;
+  if (tid < T_faces) locate(tid, p_next, j_next);
   for (int base = 0; base < T_faces; base += FTH) {
     const int f = base + tid;
     const bool active = f < T_faces;
     int p = FBS;  // sentinel key for idle lanes (they sit at the wave's end)
     int i = 0, j = 0;
+    if (active) {
+      p = p_next;
+      j = j_next;
+    }
+    if (f + FTH < T_faces) locate(f + FTH, p_next, j_next);
     FaceState<T> fs;
     fs.skip = true;
     fs.flags = 0;
     if (active) {
-      // particle p of this face: pref[p] <= f < pref[p + 1]
-      int lo = 0, hi = FBS;
-      while (hi - lo > 1) {
-        const int mid = (lo + hi) >> 1;
-        if (pref[mid] <= f) lo = mid; else hi = mid;
-      }
-      p = lo;
       i = b0 + p;
-      j = a.fslot[list_at(i, f - pref[p], n)];
       const int L = i < j ? i : j, R = i < j ? j : i;
       FaceIn<T> Ls, Rs;
       load_side(a, L, Ls);
