@@ -54,9 +54,15 @@ struct CandArgs {
 // path once per cell instead of once per particle, the particle positions
 // arrive by scalar broadcast, and the lists leave HBM-friendly: 2.2 GB
 // written instead of 4.9.
-constexpr int SLOTS = 6;   // candidates per lane per round: 384 per wavefront
+// Shape (measured at 128^3, search + density ms): SLOTS 6 / LCAP 64, 1.48 +
+// 1.58; SLOTS 6 / LCAP 48, 1.20 + 1.61; SLOTS 8 / LCAP 48, 1.17 + 1.62;
+// LCAP 32, 1.39-1.42 + 1.63; 8 particles per chunk with LCAP 64, 1.29 + 1.63.
+// The LDS a workgroup holds sets how many wavefronts a CU runs: fewer
+// staged entries per particle buy occupancy at the price of more direct
+// stores.
+constexpr int SLOTS = 8;   // candidates per lane per round: 512 per wavefront
 constexpr int TCH = 16;    // particles per staged chunk
-constexpr int LCAP = 64;   // list entries per particle staged in LDS (more are stored directly)
+constexpr int LCAP = 48;   // list entries per particle staged in LDS (more are stored directly)
 
 __device__ __forceinline__ uint32_t compact_bits3(uint32_t v) {
   v &= 0x09249249u;
