@@ -4,17 +4,18 @@
 //
 // Work split.  A workgroup owns a block of FLUX_BLOCK consecutive particles of
 // the Z-ordered list and an LDS accumulator per particle.  The gradient loop
-// has listed, per particle, the faces it evaluates: a face inside the block
-// once (the side emit_face picks), a face crossing the block boundary on both
-// sides.  Here the block's faces are laid out one per lane (a block prefix sum
-// of the per-particle counts, then a binary search maps lane -> particle), so
-// the Riemann solves run on full wavefronts.  The face function always takes
-// the lower slot as the left state, so both evaluations of a crossing face are
-// bitwise identical and every pair stays exactly antisymmetric.  The owning
-// side is summed with a segmented wave reduction (a wave's faces belong to a
-// few consecutive particles), the in-block other side with an LDS atomic.  No
-// global atomics: FP64 global atomic adds run at ~23 G/s on this part, far
-// too slow for a scatter of ~10 per face.
+// has listed every face once, under the particle emit_face picks.  Here the
+// block's faces are laid out one per lane (a block prefix sum of the
+// per-particle counts, then a binary search maps lane -> particle), so the
+// Riemann solves run on full wavefronts.  The face function always takes the
+// lower slot as the left state and the two particles receive exactly opposite
+// values, so every pair stays antisymmetric.  The owning side is summed with a
+// segmented wave reduction (a wave's faces belong to a few consecutive
+// particles), an in-block other side with an LDS atomic, an other side in
+// another block with a native FP64 global atomic add into dq_ext, which is
+// folded into dQ after the loop.  Evaluating a block-crossing face on both
+// sides instead (no global atomics) costs 25% more face evaluations at 1024
+// particles per block.
 //
 // Precision.  T = double is the FP64 path.  T = float is the mixed path: the
 // separation is formed in FP64 from FP64 positions and rounded; the face
@@ -63,6 +64,7 @@ struct FluxArgs {
   const int32_t *fslot, *fcnt;
   const double *dt;
   double *dQ;
+  double *dq_ext;  // dt F A of faces whose other particle lies outside the block
   double box[3], half[3];
   Gas<double> G;
   Gas<float> Gf;
@@ -724,8 +726,13 @@ __global__ void __launch_bounds__(FTH) __attribute__((amdgpu_waves_per_eu(2))) f
 #pragma unroll
         for (int q = (SCHEME == MFM_SCHEME_MFM ? 1 : 0); q < 5; ++q)
           atomicAdd(&acc[q][j - b0], -c[q]);
+      } else {
+        // the partner belongs to another block: its share goes to HBM
+#pragma unroll
+        for (int q = (SCHEME == MFM_SCHEME_MFM ? 1 : 0); q < 5; ++q)
+          unsafeAtomicAdd(&a.dq_ext[(int64_t)q * n + j], -dt * c[q]);
       }
-      if (inb || i < j) {
+      {
         ++nfaces;
         iters_sum += it;
         vac += (fs.flags & F_VACUUM) ? 1 : 0;
@@ -774,6 +781,18 @@ __global__ void __launch_bounds__(FTH) __attribute__((amdgpu_waves_per_eu(2))) f
   count_add(a.counters + C_POSITIVITY, pos);
   count_add(a.counters + C_RIEMANN_MAXIT, maxit);
   count_add(a.counters + C_GUESS_FALLBACK, fb);
+}
+
+// dq_ext is cleared before the flux loop and folded into dQ after it.
+__global__ void zero_f64_k(double *v, int64_t m) {
+  for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < m;
+       k += (int64_t)gridDim.x * blockDim.x)
+    v[k] = 0.0;
+}
+__global__ void fold_f64_k(double *dst, const double *src, int64_t m) {
+  for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < m;
+       k += (int64_t)gridDim.x * blockDim.x)
+    dst[k] += src[k];
 }
 
 template <typename T, int SCHEME, bool LEARNED>
@@ -842,9 +861,14 @@ hipError_t launch_fluxes(mfm_ctx *ctx, const mfm_particles *pp, const double *dt
   a.dump = ctx->dump;
   a.dump_cap = ctx->dump_cap;
   a.dump_count = ctx->dump_count;
+  a.dq_ext = ctx->dq_ext;
   const bool learned = ctx->p.guess == MFM_GUESS_LEARNED;
   if (learned) mlp_net_of(ctx->mlp_state, &a.net);
   const int nb = blocks_for(pp->n, FBS);
+  const int64_t m5 = 5 * pp->n;
+  const int fb = (int)std::min<int64_t>(blocks_for(m5, 256), 8192);
+  zero_f64_k<<<fb, 256, 0, ctx->stream>>>(ctx->dq_ext, m5);
+  stage_begin(ctx, 4);
   if (ctx->p.precision == MFM_MIXED) {
     if (learned)
       launch_t<float, true>(a, ctx->p.scheme, m, nb, ctx->stream);
@@ -856,5 +880,7 @@ hipError_t launch_fluxes(mfm_ctx *ctx, const mfm_particles *pp, const double *dt
     else
       launch_t<double, false>(a, ctx->p.scheme, m, nb, ctx->stream);
   }
+  stage_end(ctx, 4);
+  fold_f64_k<<<fb, 256, 0, ctx->stream>>>(pp->dQ, ctx->dq_ext, m5);
   return hipGetLastError();
 }

@@ -106,7 +106,6 @@ __global__ void __launch_bounds__(BS) gradients_k(GradArgs a) {
     const double q64[5] = {gi[GIN_RHO], gi[GIN_VX], gi[GIN_VY], gi[GIN_VZ], gi[GIN_P]};
     const T qi[5] = {T(q64[0]), T(q64[1]), T(q64[2]), T(q64[3]), T(q64[4])};
     const T ci = T(gi[GIN_C]);
-    const int b0 = (int)(i / FLUX_BLOCK) * FLUX_BLOCK;
     T e[6] = {0, 0, 0, 0, 0, 0};
     T s[5][3];
     double qmax[5], qmin[5];
@@ -156,7 +155,7 @@ __global__ void __launch_bounds__(BS) gradients_k(GradArgs a) {
       if (k < gc) {
         const int j = jn;
         if (k + 1 < gc) jn = a.gl[list_at(i, k + 1, n)];
-        if ((j < b0 || j >= b0 + FLUX_BLOCK) || emit_face((int)i, j)) put_face(j);
+        if (emit_face((int)i, j)) put_face(j);
         const double *gj = a.gin + (int64_t)j * GIN_STRIDE;
         ++pairs;
         const double e0 = min_image(gj[GIN_X] - xi, a.box[0], a.half[0]);
@@ -234,7 +233,7 @@ __global__ void __launch_bounds__(BS) gradients_k(GradArgs a) {
           const double e2 = min_image(pj.z - zi, a.box[2], a.half[2]);
           in = e0 * e0 + e1 * e1 + e2 * e2 < hj2;
         }
-        if (in && ((j < b0 || j >= b0 + FLUX_BLOCK) || emit_face((int)i, j))) put_face(j);
+        if (in && emit_face((int)i, j)) put_face(j);
       }
       store_done();
     }

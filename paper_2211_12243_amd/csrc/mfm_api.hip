@@ -13,7 +13,7 @@ constexpr size_t ALIGN = 256;
 
 struct Layout {
   size_t code, count, start, cursor, crange, chmax, scan, order, tmp, pos4, cand, cand_r2, rest_r2,
-      cand_cnt, gl, gl_cnt, gin, fslot, fcnt, rec, red, counters, scalars;
+      cand_cnt, gl, gl_cnt, gin, fslot, fcnt, dq_ext, rec, red, counters, scalars;
   size_t total;
   int64_t ncodes_max;
   size_t scan_len;
@@ -59,6 +59,7 @@ Layout make_layout(const mfm_params *p, int64_t n) {
   L.gin = take(8 * (size_t)GIN_STRIDE * (size_t)n);
   L.fslot = take(4 * list_len(p->max_list, n));
   L.fcnt = take(4 * (size_t)n);
+  L.dq_ext = take(8 * 5 * (size_t)n);
   L.rec = take(8 * (size_t)R_STRIDE * (size_t)n);
   L.red = take(8 * 5 * 1024);
   L.counters = take(8 * NCOUNTERS);
@@ -250,6 +251,7 @@ int mfm_create(const mfm_params *p, int64_t n_max, void *workspace, size_t works
   ctx->gl_cnt = (int32_t *)(ctx->ws + L.gl_cnt);
   ctx->fslot = (int32_t *)(ctx->ws + L.fslot);
   ctx->fcnt = (int32_t *)(ctx->ws + L.fcnt);
+  ctx->dq_ext = (double *)(ctx->ws + L.dq_ext);
   ctx->rec = (double *)(ctx->ws + L.rec);
   ctx->red = (double *)(ctx->ws + L.red);
   ctx->counters = (int64_t *)(ctx->ws + L.counters);
@@ -377,9 +379,7 @@ int mfm_fluxes(mfm_ctx *ctx, const mfm_particles *pp, const double *dt_dev) {
     return fail(ctx, MFM_E_STATE, "mfm_fluxes needs mfm_gradients first");
   if (ctx->p.guess == MFM_GUESS_LEARNED && !ctx->mlp_state)
     return fail(ctx, MFM_E_STATE, "learned guess requested but no network attached");
-  stage_begin(ctx, 4);
   HIPCHK(ctx, launch_fluxes(ctx, pp, dt_dev), "fluxes");
-  stage_end(ctx, 4);
   return MFM_OK;
 }
 

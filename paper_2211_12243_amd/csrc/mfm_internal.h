@@ -108,6 +108,7 @@ struct mfm_ctx {
   double *gin;         // GIN_STRIDE * n packed gradient-loop records
   int32_t *fslot;      // max_list * n: faces each particle evaluates (k-major)
   int32_t *fcnt;       // n
+  double *dq_ext;      // 5 n: flux contributions to particles outside the evaluating block
   double *rec;         // R_STRIDE * n packed flux records
   double *red;         // reduction partials
   int64_t *counters;   // NCOUNTERS
@@ -227,7 +228,11 @@ hipError_t launch_build_cells(mfm_ctx *ctx, const mfm_particles *pp, int64_t *pe
 hipError_t launch_candidates(mfm_ctx *ctx, const mfm_particles *pp);
 hipError_t launch_density(mfm_ctx *ctx, const mfm_particles *pp);
 hipError_t launch_gradients(mfm_ctx *ctx, const mfm_particles *pp, double dt_max, double *dt_dev);
+// Records the flux stage's timing events around the flux kernel itself (the
+// clear and fold of dq_ext lie outside).
 hipError_t launch_fluxes(mfm_ctx *ctx, const mfm_particles *pp, const double *dt_dev);
+void stage_begin(mfm_ctx *ctx, int stage);
+void stage_end(mfm_ctx *ctx, int stage);
 hipError_t launch_update(mfm_ctx *ctx, const mfm_particles *pp, const double *dt_dev);
 hipError_t launch_conserved(mfm_ctx *ctx, const mfm_particles *pp);
 
