@@ -64,15 +64,6 @@ constexpr int SLOTS = 8;   // candidates per lane per round: 512 per wavefront
 constexpr int TCH = 16;    // particles per staged chunk
 constexpr int LCAP = 48;   // list entries per particle staged in LDS (more are stored directly)
 
-__device__ __forceinline__ uint32_t compact_bits3(uint32_t v) {
-  v &= 0x09249249u;
-  v = (v | (v >> 2)) & 0x030C30C3u;
-  v = (v | (v >> 4)) & 0x0300F00Fu;
-  v = (v | (v >> 8)) & 0x030000FFu;
-  v = (v | (v >> 16)) & 0x000003FFu;
-  return v;
-}
-
 // Lane l's value in every lane (a scalar broadcast, no memory traffic).
 __device__ __forceinline__ double readlane_f64(double v, int l) {
   const int2 w = *reinterpret_cast<const int2 *>(&v);

@@ -30,6 +30,7 @@ constexpr float MIXED_FP64_NCOND = 10.0f;
 // 4-byte store per lane into separate planes cost a full sector of HBM
 // write each (measured 1.6 GB written per launch instead of 0.8).
 constexpr int RING = 16;
+constexpr int RSTEP = 4;  // list entries between two looks at the ring's fill
 
 struct GradArgs {
   int64_t n;
@@ -131,10 +132,11 @@ __global__ void __launch_bounds__(BS) gradients_k(GradArgs a) {
     auto store_plane = [&](int p) {
       if (live && nf > p) a.fslot[list_at(i, p, n)] = s_ring[wv][p % RING][ln];
     };
-    // before a step that may add one face per lane: keep every slot inside the ring
+    // before RSTEP list entries (at most one face each per lane): keep every
+    // slot they may take inside the ring
     auto make_room = [&]() {
       const int hi = wave_max_i32(nf);
-      while (hi >= flushed + RING) store_plane(flushed++);
+      while (hi + RSTEP > flushed + RING) store_plane(flushed++);
     };
     // after it: store the planes every lane has passed
     auto store_done = [&]() {
@@ -151,7 +153,7 @@ __global__ void __launch_bounds__(BS) gradients_k(GradArgs a) {
     // only the dependent gather is on the critical path
     int jn = gc > 0 ? a.gl[list_at(i, 0, n)] : 0;
     for (int k = 0; k < gmax; ++k) {
-      make_room();
+      if (k % RSTEP == 0) make_room();
       if (k < gc) {
         const int j = jn;
         if (k + 1 < gc) jn = a.gl[list_at(i, k + 1, n)];
@@ -204,7 +206,7 @@ __global__ void __launch_bounds__(BS) gradients_k(GradArgs a) {
           vsig = fmax(vsig, ci + cj - fmin(T(0), proj));
         }
       }
-      store_done();
+      if (k % RSTEP == RSTEP - 1) store_done();
     }
     // (2) faces with H_i <= r < H_j, from the other candidates (r >= H_i).
     // Their r^2 is stored in FP32 (relative error <= 2^-24): a neighbour
@@ -215,7 +217,7 @@ __global__ void __launch_bounds__(BS) gradients_k(GradArgs a) {
     int cj = cnt > 0 ? a.cand[list_at(i, 0, n)] : 0;
     float cr = cnt > 0 ? a.rest_r2[list_at(i, 0, n)] : 0.0f;
     for (int k = 0; k < cmax; ++k) {
-      make_room();
+      if (k % RSTEP == 0) make_room();
       if (k < cnt) {
         const int j = cj;
         const double r2f = (double)cr;
@@ -235,7 +237,7 @@ __global__ void __launch_bounds__(BS) gradients_k(GradArgs a) {
         }
         if (in && emit_face((int)i, j)) put_face(j);
       }
-      store_done();
+      if (k % RSTEP == RSTEP - 1) store_done();
     }
     for (const int top = wave_max_i32(nf); flushed < top;) store_plane(flushed++);
     T b[6];

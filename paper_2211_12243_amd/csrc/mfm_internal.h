@@ -181,6 +181,15 @@ __device__ __forceinline__ uint32_t morton3(int cx, int cy, int cz) {
   return spread_bits3((uint32_t)cx) | (spread_bits3((uint32_t)cy) << 1) |
          (spread_bits3((uint32_t)cz) << 2);
 }
+// Inverse of spread_bits3: every third bit of v, packed.
+__device__ __forceinline__ uint32_t compact_bits3(uint32_t v) {
+  v &= 0x09249249u;
+  v = (v | (v >> 2)) & 0x030C30C3u;
+  v = (v | (v >> 4)) & 0x0300F00Fu;
+  v = (v | (v >> 8)) & 0x030000FFu;
+  v = (v | (v >> 16)) & 0x000003FFu;
+  return v;
+}
 __device__ __forceinline__ int cell_coord(double x, double inv, int nc) {
   int c = (int)(x * inv);
   return c < 0 ? 0 : (c >= nc ? nc - 1 : c);
