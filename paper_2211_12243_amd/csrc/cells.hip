@@ -49,18 +49,43 @@ __global__ void max_final_k(const double *partial, int np, double *out) {
   }
 }
 
+// Runs of equal keys among the lanes of a wavefront (every lane must take
+// part): whether this lane starts a run, the run's length (valid at its
+// start) and the lane that starts this lane's run.  The particles arrive in
+// last step's cell order, so runs are long and one atomic per run replaces
+// one per particle.
+__device__ __forceinline__ void key_runs(uint32_t key, int lane, bool &head, int &len,
+                                         int &head_lane) {
+  const uint32_t prev = __shfl_up(key, 1, 64);
+  head = lane == 0 || prev != key;
+  const uint64_t hm = __ballot(head);
+  const uint64_t upto = (2ull << lane) - 1ull;  // lanes 0..lane (all 64 bits at lane 63)
+  const uint64_t after = hm & ~upto;
+  len = (after ? __ffsll((unsigned long long)after) - 1 : 64) - lane;
+  head_lane = 63 - __clzll(hm & upto);
+}
+
+constexpr uint32_t NO_KEY = 0xffffffffu;  // lanes past the end (no cell has this code)
+
 // Morton code of each particle's cell and the per-cell histogram.
 __global__ void cell_code_k(int64_t n, const double *__restrict__ x, const double *__restrict__ y,
                             const double *__restrict__ z, CellGrid g, uint32_t *code,
                             int32_t *count) {
-  int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  int cx = cell_coord(x[i], g.inv[0], g.nc[0]);
-  int cy = cell_coord(y[i], g.inv[1], g.nc[1]);
-  int cz = cell_coord(z[i], g.inv[2], g.nc[2]);
-  uint32_t c = morton3(cx, cy, cz);
-  code[i] = c;
-  atomicAdd(count + c, 1);
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  const int lane = threadIdx.x & 63;
+  const bool live = i < n;
+  uint32_t c = NO_KEY;
+  if (live) {
+    const int cx = cell_coord(x[i], g.inv[0], g.nc[0]);
+    const int cy = cell_coord(y[i], g.inv[1], g.nc[1]);
+    const int cz = cell_coord(z[i], g.inv[2], g.nc[2]);
+    c = morton3(cx, cy, cz);
+    code[i] = c;
+  }
+  bool head;
+  int len, hl;
+  key_runs(c, lane, head, len, hl);
+  if (live && head) atomicAdd(count + c, len);
 }
 
 // Exclusive scan, 1024 elements per block (4 per thread), block totals out.
@@ -108,10 +133,17 @@ hipError_t scan_exclusive(hipStream_t st, const int32_t *in, int32_t *out, int64
 
 __global__ void scatter_k(int64_t n, const uint32_t *__restrict__ code, int32_t *cursor,
                           int32_t *order) {
-  int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  int32_t dst = atomicAdd(cursor + code[i], 1);
-  order[dst] = (int32_t)i;
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  const int lane = threadIdx.x & 63;
+  const bool live = i < n;
+  const uint32_t c = live ? code[i] : NO_KEY;
+  bool head;
+  int len, hl;
+  key_runs(c, lane, head, len, hl);
+  int base = 0;
+  if (live && head) base = atomicAdd(cursor + c, len);
+  base = __shfl(base, hl, 64);
+  if (live) order[base + (lane - hl)] = (int32_t)i;
 }
 
 // Within a cell, order the particles by their slot before the sort, so the
@@ -169,12 +201,12 @@ __global__ void writeback_k(int64_t n, Fields fs, const double *__restrict__ tmp
 // Largest H of each cell at the build (0 for an empty cell): the search
 // sizes each cell's candidate radius from its 27-cell neighbourhood.
 __global__ void cell_hmax_k(int64_t ncodes, const int2 *__restrict__ range,
-                            const double4 *__restrict__ pos4, double *chmax) {
+                            const double *__restrict__ H, double *chmax) {
   const int64_t c = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (c >= ncodes) return;
   const int2 r = range[c];
   double m = 0.0;
-  for (int k = 0; k < r.y; ++k) m = fmax(m, pos4[r.x + k].w);
+  for (int k = 0; k < r.y; ++k) m = fmax(m, H[r.x + k]);
   chmax[c] = m;
 }
 
@@ -213,6 +245,6 @@ hipError_t launch_build_cells(mfm_ctx *ctx, const mfm_particles *pp, int64_t *pe
   writeback_k<<<blocks_for(n, BS), BS, 0, st>>>(n, fs, ctx->tmp,
                                                 reinterpret_cast<double4 *>(ctx->pos4));
   cell_hmax_k<<<blocks_for(ctx->ncodes, BS), BS, 0, st>>>(
-      ctx->ncodes, ctx->crange, reinterpret_cast<const double4 *>(ctx->pos4), ctx->chmax);
+      ctx->ncodes, ctx->crange, pp->H, ctx->chmax);
   return hipGetLastError();
 }
