@@ -244,12 +244,30 @@ constexpr int DG = 64 / DT;
 constexpr int DM = 12;
 constexpr int DCAP = DG * DM;
 
-// Sum over the G lanes of an aligned group (butterfly: every lane gets the
-// same bits, since each pairwise sum is formed from the same two operands).
+// A double moved across lanes by a DPP control (both halves).
+template <int CTRL>
+__device__ __forceinline__ double dpp_f64(double v) {
+  const int2 w = *reinterpret_cast<const int2 *>(&v);
+  int2 r;
+  r.x = __builtin_amdgcn_mov_dpp(w.x, CTRL, 0xf, 0xf, false);
+  r.y = __builtin_amdgcn_mov_dpp(w.y, CTRL, 0xf, 0xf, false);
+  return *reinterpret_cast<const double *>(&r);
+}
+
+// Sum over the G lanes of an aligned group, as a butterfly: lane pairs
+// 1 apart, then 2 apart, then the other quad.  Every lane gets the same bits,
+// since each pairwise sum is formed from the same two operands.  For G = 8
+// the exchanges are DPP moves (quad permutations, then the half-row mirror,
+// whose partner lane already holds the other quad's sum) instead of LDS
+// permutes.
 template <int G>
 __device__ __forceinline__ double group_sum(double v) {
-#pragma unroll
-  for (int o = 1; o < G; o <<= 1) v += __shfl_xor(v, o, 64);
+  static_assert(G == 1 || G == 8, "group sums are built for 1 or 8 lanes");
+  if constexpr (G == 8) {
+    v += dpp_f64<0xB1>(v);   // quad_perm [1, 0, 3, 2]: partner lane ^ 1
+    v += dpp_f64<0x4E>(v);   // quad_perm [2, 3, 0, 1]: partner lane ^ 2
+    v += dpp_f64<0x141>(v);  // row_half_mirror: lane 7 - l of its 8
+  }
   return v;
 }
 
