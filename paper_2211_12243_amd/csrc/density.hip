@@ -78,7 +78,6 @@ __global__ void __launch_bounds__(64) cand_cell_k(CandArgs a, CellGrid g) {
   __shared__ double s_r2[TCH][LCAP];
   __shared__ int s_start[27];
   __shared__ int s_pre[28];
-  __shared__ double s_shift[27][3];
   __shared__ int s_cnt[TCH];
   const int lane = threadIdx.x;
   const int64_t n = a.n;
@@ -95,11 +94,6 @@ __global__ void __launch_bounds__(64) cand_cell_k(CandArgs a, CellGrid g) {
   double hnb = 0.0;
   if (lane < 27) {
     int zz = cz + lane / 9 - 1, yy = cy + (lane / 3) % 3 - 1, xx = cx + lane % 3 - 1;
-    // a neighbour across the periodic boundary: its particles are taken at
-    // the image next to this cell
-    s_shift[lane][2] = zz < 0 ? -g.box[2] : (zz >= g.nc[2] ? g.box[2] : 0.0);
-    s_shift[lane][1] = yy < 0 ? -g.box[1] : (yy >= g.nc[1] ? g.box[1] : 0.0);
-    s_shift[lane][0] = xx < 0 ? -g.box[0] : (xx >= g.nc[0] ? g.box[0] : 0.0);
     zz = zz < 0 ? zz + g.nc[2] : (zz >= g.nc[2] ? zz - g.nc[2] : zz);
     yy = yy < 0 ? yy + g.nc[1] : (yy >= g.nc[1] ? yy - g.nc[1] : yy);
     xx = xx < 0 ? xx + g.nc[0] : (xx >= g.nc[0] ? xx - g.nc[0] : xx);
@@ -121,6 +115,8 @@ __global__ void __launch_bounds__(64) cand_cell_k(CandArgs a, CellGrid g) {
   if (lane == 0) s_pre[0] = 0;
   __syncthreads();
   const int C = s_pre[27];
+  const bool wraps = cx == 0 || cy == 0 || cz == 0 || cx == g.nc[0] - 1 ||
+                     cy == g.nc[1] - 1 || cz == g.nc[2] - 1;
   const double rc = fmin(g.side_min, g.hfac * wave_max_f64(hnb));
   const double R2 = rc * rc;
   const uint64_t below = (1ull << lane) - 1ull;
@@ -152,11 +148,17 @@ __global__ void __launch_bounds__(64) cand_cell_k(CandArgs a, CellGrid g) {
           const int j = s_start[lo] + (c - s_pre[lo]);
           const double4 pj = a.pos[j];
           jj[s] = j;
-          px[s] = pj.x + s_shift[lo][0];
-          py[s] = pj.y + s_shift[lo][1];
-          pz[s] = pj.z + s_shift[lo][2];
+          px[s] = pj.x;
+          py[s] = pj.y;
+          pz[s] = pj.z;
         }
       }
+      // the particles of the chunk against the candidates in registers; a
+      // cell whose stencil crosses the periodic boundary takes the minimum
+      // image, any other the plain difference (the same value: no pair
+      // closer than the cell side is wrapped there)
+      auto test_chunk = [&](auto wrap) {
+      constexpr bool WRAP = decltype(wrap)::value;
       for (int t = 0; t < T; ++t) {
         const int ti = own.x + t0 + t;
         const double ptx = readlane_f64(tx, t), pty = readlane_f64(ty, t),
@@ -167,9 +169,12 @@ __global__ void __launch_bounds__(64) cand_cell_k(CandArgs a, CellGrid g) {
           bool hit = false;
           double r2 = 0.0;
           if (jj[s] >= 0 && jj[s] != ti) {
-            // the image taken above is the nearest one for every pair closer
-            // than the cell side (at least 3 cells per axis)
-            const double ex = px[s] - ptx, ey = py[s] - pty, ez = pz[s] - ptz;
+            double ex = px[s] - ptx, ey = py[s] - pty, ez = pz[s] - ptz;
+            if (WRAP) {
+              ex = min_image(ex, g.box[0], g.half[0]);
+              ey = min_image(ey, g.box[1], g.half[1]);
+              ez = min_image(ez, g.box[2], g.half[2]);
+            }
             r2 = ex * ex + ey * ey + ez * ez;
             hit = r2 < R2;
           }
@@ -189,6 +194,11 @@ __global__ void __launch_bounds__(64) cand_cell_k(CandArgs a, CellGrid g) {
         }
         tcnt = lane == t ? base : tcnt;
       }
+      };
+      if (wraps)
+        test_chunk(std::true_type{});
+      else
+        test_chunk(std::false_type{});
       __syncthreads();
     }
     if (lane < TCH) s_cnt[lane] = tcnt;
