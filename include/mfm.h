@@ -86,7 +86,7 @@ typedef struct mfm_params {
   double riemann_tol;    /* relative Newton step tolerance of the exact solver (default 1e-10) */
   double alpha1;         /* dual-energy switch: U > alpha1 E_kin -> U from E (default 0.01) */
   double box[3];         /* periodic box sides; all > 0 (the library needs a periodic box) */
-  double cell_margin;    /* cell side >= cell_margin * max_i H_i (>= 1, default 1.15).
+  double cell_margin;    /* cell side >= cell_margin * max_i H_i (>= 1, default 1.10).
                             Also the largest growth of an H in one density pass
                             (H <= cell_margin * its value at the cell build);
                             a cell's candidate radius is cell_margin times the

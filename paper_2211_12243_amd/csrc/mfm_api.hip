@@ -208,7 +208,7 @@ void mfm_default_params(mfm_params *p) {
   p->riemann_tol = 1e-10;
   p->alpha1 = 0.01;
   p->box[0] = p->box[1] = p->box[2] = 1.0;
-  p->cell_margin = 1.15;
+  p->cell_margin = 1.10;
   p->max_cell_dim = 256;
 }
 
