@@ -9,13 +9,13 @@
 // per-particle counts, then a binary search maps lane -> particle), so the
 // Riemann solves run on full wavefronts.  The face function always takes the
 // lower slot as the left state and the two particles receive exactly opposite
-// values, so every pair stays antisymmetric.  The owning side is summed with a
-// segmented wave reduction (a wave's faces belong to a few consecutive
-// particles), an in-block other side with an LDS atomic, an other side in
-// another block with a native FP64 global atomic add into dq_ext, which is
-// folded into dQ after the loop.  Evaluating a block-crossing face on both
-// sides instead (no global atomics) costs 25% more face evaluations at 1024
-// particles per block.
+// values, so every pair stays antisymmetric.  Both sides of an in-block face
+// are added with FP64 LDS atomics (measured 5% faster than a segmented wave
+// reduction of the owning side), an other side in another block with a
+// native FP64 global atomic add into dq_ext, which is folded into dQ after
+// the loop.  Evaluating a block-crossing face on both sides instead (no
+// global atomics) costs 25% more face evaluations at 1024 particles per
+// block.
 //
 // Precision.  T = double is the FP64 path.  T = float is the mixed path: the
 // separation is formed in FP64 from FP64 positions and rounded; the face
@@ -753,19 +753,7 @@ __global__ void __launch_bounds__(FTH) __attribute__((amdgpu_waves_per_eu(2))) f
         }
       }
     }
-    // segmented sum over lanes with the same particle (keys ascend across lanes)
-#pragma unroll
-    for (int o = 1; o < 64; o <<= 1) {
-      const int kp = __shfl_up(p, o, 64);
-      const bool same = lane >= o && kp == p;
-#pragma unroll
-      for (int q = 0; q < 5; ++q) {
-        const double u = __shfl_up(c[q], o, 64);
-        if (same) c[q] += u;
-      }
-    }
-    const int kn = __shfl_down(p, 1, 64);
-    if (active && (lane == 63 || kn != p)) {
+    if (active) {
 #pragma unroll
       for (int q = (SCHEME == MFM_SCHEME_MFM ? 1 : 0); q < 5; ++q) atomicAdd(&acc[q][p], c[q]);
     }
