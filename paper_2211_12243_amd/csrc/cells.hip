@@ -198,18 +198,6 @@ __global__ void writeback_k(int64_t n, Fields fs, const double *__restrict__ tmp
   pos4[k] = make_double4(tmp[k], tmp[n + k], tmp[2 * n + k], tmp[9 * n + k]);
 }
 
-// Largest H of each cell at the build (0 for an empty cell): the search
-// sizes each cell's candidate radius from its 27-cell neighbourhood.
-__global__ void cell_hmax_k(int64_t ncodes, const int2 *__restrict__ range,
-                            const double *__restrict__ H, double *chmax) {
-  const int64_t c = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (c >= ncodes) return;
-  const int2 r = range[c];
-  double m = 0.0;
-  for (int k = 0; k < r.y; ++k) m = fmax(m, H[r.x + k]);
-  chmax[c] = m;
-}
-
 }  // namespace
 
 hipError_t launch_max_h(mfm_ctx *ctx, const mfm_particles *pp) {
@@ -244,7 +232,5 @@ hipError_t launch_build_cells(mfm_ctx *ctx, const mfm_particles *pp, int64_t *pe
   gather_k<<<blocks_for(n, BS), BS, 0, st>>>(n, fs, ctx->order, ctx->tmp, perm);
   writeback_k<<<blocks_for(n, BS), BS, 0, st>>>(n, fs, ctx->tmp,
                                                 reinterpret_cast<double4 *>(ctx->pos4));
-  cell_hmax_k<<<blocks_for(ctx->ncodes, BS), BS, 0, st>>>(
-      ctx->ncodes, ctx->crange, pp->H, ctx->chmax);
   return hipGetLastError();
 }

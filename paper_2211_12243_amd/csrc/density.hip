@@ -3,12 +3,12 @@
 //
 // cand_cell_k: for every particle, the candidates in the 27 cells around its
 // own (cell side >= cell_margin * max H, so every pair closer than the side
-// is found) with r < R_c, as (index, r^2) in the k-major list (list_at).
-// R_c = min(side, cell_margin * the largest H at the build in the 27 cells):
-// the density loop bounds each H by cell_margin times its value at the build
-// (else the pass is redone), so every H_j of the step stays below the R_c of
-// every cell around j's, and the list is a superset of every neighbour set
-// the step uses, however unequal the H.
+// is found) with r < cell_margin * max(H_i, H_j), both H at the build, as
+// (index, r^2) in the k-major list (list_at).  The density loop bounds each H
+// by cell_margin times its value at the build (else the pass is redone), so
+// every pair closer than max(H_i, H_j) of the step is in the list, and the
+// list is a superset of every neighbour set the step uses, however unequal
+// the H.  (That radius is at most the cell side.)
 //
 // density_k solves, for each particle,
 //   g(H) = (32/3) sum_j w(r_ij / H) - N_NGB = 0
@@ -73,7 +73,7 @@ __device__ __forceinline__ double readlane_f64(double v, int l) {
   return *reinterpret_cast<const double *>(&r);
 }
 
-__global__ void __launch_bounds__(64) cand_cell_k(CandArgs a, CellGrid g) {
+__global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) cand_cell_k(CandArgs a, CellGrid g) {
   __shared__ int32_t s_idx[TCH][LCAP];
   __shared__ double s_r2[TCH][LCAP];
   __shared__ int s_start[27];
@@ -91,7 +91,6 @@ __global__ void __launch_bounds__(64) cand_cell_k(CandArgs a, CellGrid g) {
   const int cap = a.max_list;
   // the 27 neighbour ranges in the search order, and their prefix sums
   int cnt27 = 0, st27 = 0;
-  double hnb = 0.0;
   if (lane < 27) {
     int zz = cz + lane / 9 - 1, yy = cy + (lane / 3) % 3 - 1, xx = cx + lane % 3 - 1;
     zz = zz < 0 ? zz + g.nc[2] : (zz >= g.nc[2] ? zz - g.nc[2] : zz);
@@ -101,7 +100,6 @@ __global__ void __launch_bounds__(64) cand_cell_k(CandArgs a, CellGrid g) {
     const int2 rg = g.range[nb];
     st27 = rg.x;
     cnt27 = rg.y;
-    hnb = g.chmax[nb];
   }
   int inc = cnt27;
   for (int o = 1; o < 32; o <<= 1) {
@@ -117,28 +115,27 @@ __global__ void __launch_bounds__(64) cand_cell_k(CandArgs a, CellGrid g) {
   const int C = s_pre[27];
   const bool wraps = cx == 0 || cy == 0 || cz == 0 || cx == g.nc[0] - 1 ||
                      cy == g.nc[1] - 1 || cz == g.nc[2] - 1;
-  const double rc = fmin(g.side_min, g.hfac * wave_max_f64(hnb));
-  const double R2 = rc * rc;
   const uint64_t below = (1ull << lane) - 1ull;
   for (int t0 = 0; t0 < own.y; t0 += TCH) {
     const int T = min(TCH, own.y - t0);
     // lane t holds particle t of the chunk and the length of its list; the
     // loop below broadcasts both
     int tcnt = 0;
-    double tx = 0.0, ty = 0.0, tz = 0.0;
+    double tx = 0.0, ty = 0.0, tz = 0.0, tq = 0.0;
     if (lane < T) {
       const double4 pt = a.pos[own.x + t0 + lane];
       tx = pt.x; ty = pt.y; tz = pt.z;
+      tq = (g.hfac * pt.w) * (g.hfac * pt.w);  // squared radius of the particle's own H
     }
     __syncthreads();
     for (int cb = 0; cb < C; cb += 64 * SLOTS) {
-      double px[SLOTS], py[SLOTS], pz[SLOTS];
+      double px[SLOTS], py[SLOTS], pz[SLOTS], pq[SLOTS];
       int jj[SLOTS];
 #pragma unroll
       for (int s = 0; s < SLOTS; ++s) {
         const int c = cb + s * 64 + lane;
         jj[s] = -1;
-        px[s] = py[s] = pz[s] = 0.0;
+        px[s] = py[s] = pz[s] = pq[s] = 0.0;
         if (c < C) {
           int lo = 0, hi = 27;  // range r with s_pre[r] <= c < s_pre[r + 1]
           while (hi - lo > 1) {
@@ -151,6 +148,7 @@ __global__ void __launch_bounds__(64) cand_cell_k(CandArgs a, CellGrid g) {
           px[s] = pj.x;
           py[s] = pj.y;
           pz[s] = pj.z;
+          pq[s] = (g.hfac * pj.w) * (g.hfac * pj.w);
         }
       }
       // the particles of the chunk against the candidates in registers; a
@@ -162,7 +160,7 @@ __global__ void __launch_bounds__(64) cand_cell_k(CandArgs a, CellGrid g) {
       for (int t = 0; t < T; ++t) {
         const int ti = own.x + t0 + t;
         const double ptx = readlane_f64(tx, t), pty = readlane_f64(ty, t),
-                     ptz = readlane_f64(tz, t);
+                     ptz = readlane_f64(tz, t), ptq = readlane_f64(tq, t);
         int base = __builtin_amdgcn_readlane(tcnt, t);
 #pragma unroll
         for (int s = 0; s < SLOTS; ++s) {
@@ -176,7 +174,7 @@ __global__ void __launch_bounds__(64) cand_cell_k(CandArgs a, CellGrid g) {
               ez = min_image(ez, g.box[2], g.half[2]);
             }
             r2 = ex * ex + ey * ey + ez * ez;
-            hit = r2 < R2;
+            hit = r2 < fmax(ptq, pq[s]);
           }
           const uint64_t m = __ballot(hit);
           if (hit) {

@@ -12,7 +12,7 @@ namespace {
 constexpr size_t ALIGN = 256;
 
 struct Layout {
-  size_t code, count, start, cursor, crange, chmax, scan, order, tmp, pos4, cand, cand_r2, rest_r2,
+  size_t code, count, start, cursor, crange, scan, order, tmp, pos4, cand, cand_r2, rest_r2,
       cand_cnt, gl, gl_cnt, gin, fslot, fcnt, dq_ext, rec, red, counters, scalars;
   size_t total;
   int64_t ncodes_max;
@@ -45,7 +45,6 @@ Layout make_layout(const mfm_params *p, int64_t n) {
   L.start = take(4 * (size_t)L.ncodes_max);
   L.cursor = take(4 * (size_t)L.ncodes_max);
   L.crange = take(8 * (size_t)L.ncodes_max);
-  L.chmax = take(8 * (size_t)L.ncodes_max);
   L.scan = take(4 * scan_len);
   L.order = take(4 * (size_t)n);
   L.tmp = take(8 * 11 * (size_t)n);
@@ -126,7 +125,6 @@ int setup_grid(mfm_ctx *ctx, double hmax) {
   CellGrid &g = ctx->grid;
   double s = hmax * ctx->p.cell_margin * ctx->margin_boost;
   g.hfac = ctx->p.cell_margin * ctx->margin_boost;
-  g.chmax = ctx->chmax;
   if (!(s > 0.0) || !isfinite(s)) return fail(ctx, MFM_E_ARG, "smoothing lengths must be > 0");
   int ncmax = 0;
   g.side_min = 1e300;
@@ -237,7 +235,6 @@ int mfm_create(const mfm_params *p, int64_t n_max, void *workspace, size_t works
   ctx->cell_start = (int32_t *)(ctx->ws + L.start);
   ctx->cursor = (int32_t *)(ctx->ws + L.cursor);
   ctx->crange = (int2 *)(ctx->ws + L.crange);
-  ctx->chmax = (double *)(ctx->ws + L.chmax);
   ctx->scan_tmp = (int32_t *)(ctx->ws + L.scan);
   ctx->order = (int32_t *)(ctx->ws + L.order);
   ctx->tmp = (double *)(ctx->ws + L.tmp);

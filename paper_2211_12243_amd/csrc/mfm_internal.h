@@ -75,7 +75,6 @@ struct CellGrid {
   double half[3];     // box / 2
   double side_min;    // smallest cell side: every pair closer than this is in the 27-cell stencil
   double hfac;        // cell_margin (times the rebuild boost): bound on H / H at the build
-  const double *chmax;   // indexed by Morton code: the cell's largest H at the build
   const int32_t *start;  // indexed by Morton code
   const int32_t *count;  // indexed by Morton code
   const int2 *range;     // (start, count) by Morton code, one load per cell
@@ -97,7 +96,6 @@ struct mfm_ctx {
   int32_t *order;      // n: input slot of each sorted slot
   double *tmp;         // 11 n doubles: gather buffer of the permutation
   double *pos4;        // 4 n: (x, y, z, H at the build) per particle
-  double *chmax;       // ncodes_max: largest H at the build per cell
   int32_t *cand;       // max_list * n candidates (r < cell side), entry k of i at [k * n + i];
                        // after the density loop: the candidates with r >= H_i
   double *cand_r2;     // max_list * n: their squared distances (FP64, from the search)
