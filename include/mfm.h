@@ -89,8 +89,8 @@ typedef struct mfm_params {
   double cell_margin;    /* cell side >= cell_margin * max_i H_i (>= 1, default 1.10).
                             Also the largest growth of an H in one density pass
                             (H <= cell_margin * its value at the cell build);
-                            a cell's candidate radius is cell_margin times the
-                            largest H of its 27-cell neighbourhood */
+                            a pair is a candidate when r < cell_margin *
+                            max(H_i, H_j) at the build */
   int32_t max_cell_dim;  /* cells per axis at most (3..512, default 256) */
   int32_t pad0;
 } mfm_params;
