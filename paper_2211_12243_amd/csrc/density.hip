@@ -243,13 +243,15 @@ struct DensityArgs {
 // particle, each lane holding DM entries of the particle's list (entries
 // sub, sub + DG, ...) in registers, so one particle's list of up to
 // DCAP = DG * DM entries is read from HBM once for all its Newton passes.
-// Measured at 2.1M particles (about 84 candidates each): DM = 12 (161 VGPRs,
-// 3 waves per SIMD) 1.74 ms, DM = 16 (194 VGPRs, 2 waves) 2.30 ms; 4
-// particles per wavefront with 16 lanes each, 2.5-2.7 ms.  Longer lists go to
-// density_long_k.
+// Measured at 2.1M particles: with about 84 candidates each (an earlier, wider
+// candidate radius), DM = 12 (161 VGPRs, 3 waves per SIMD) 1.74 ms, DM = 16
+// (194 VGPRs, 2 waves) 2.30 ms, 4 particles per wavefront with 16 lanes
+// each 2.5-2.7 ms; with about 40 (the pair radius), DM = 12 1.25 ms, DM = 10
+// 1.20, DM = 8 at 3 waves 1.18, DM = 8 held to 128 VGPRs for 4 waves 1.15.
+// Longer lists go to density_long_k.
 constexpr int DT = 8;
 constexpr int DG = 64 / DT;
-constexpr int DM = 12;
+constexpr int DM = 8;
 constexpr int DCAP = DG * DM;
 
 // A double moved across lanes by a DPP control (both halves).
@@ -442,7 +444,7 @@ __device__ __forceinline__ void finish_particle(const DensityArgs &a, int64_t i,
 // (index and FP32 r^2) back into cand / rest_r2.  Both are staged in LDS and
 // leave as k-major planes of DT consecutive particles.  A list longer than
 // DCAP is left whole, marked gl_cnt = -1, for density_long_k.
-__global__ void __launch_bounds__(64) density_k(DensityArgs a, CellGrid g) {
+__global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) density_k(DensityArgs a, CellGrid g) {
   __shared__ int32_t s_i[DCAP][DT];  // gather set from the front, rest indices from the back
   __shared__ float s_f[DCAP][DT];    // rest r^2
   __shared__ int s_gn[DT], s_rn[DT];
