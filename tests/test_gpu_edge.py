@@ -123,8 +123,8 @@ def test_cells_rebuilt_when_smoothing_lengths_grow():
 
 
 def test_long_and_short_candidate_lists():
-    """Cells of 1.3 max H on a random gas: about two thirds of the candidate
-    lists are longer than the density loop holds in registers (96 entries) and
+    """cell_margin 1.3 on a random gas: about three quarters of the candidate
+    lists are longer than the density loop holds in registers (64 entries) and
     take its one-lane path, the others the register path, in the same pass."""
     st = W.random_gas(N=3000, seed=9)
     print("[edge] long and short candidate lists", flush=True)
