@@ -149,9 +149,13 @@ void mfm_default_params(mfm_params *p);
 size_t mfm_workspace_bytes(const mfm_params *p, int64_t n_max);
 
 /* Create a context.  workspace: device pointer of at least
- * mfm_workspace_bytes(p, n_max) bytes, 256-byte aligned.  stream: a
- * hipStream_t (NULL = the default stream).  Returns MFM_E_ARG for invalid
- * parameters, MFM_E_WORKSPACE when the workspace is missing or too small. */
+ * mfm_workspace_bytes(p, n_max) bytes, 256-byte aligned, in ordinary
+ * (coarse-grained) device memory such as hipMalloc returns: the flux loop
+ * adds into it with the GPU's native FP64 atomics, which fine-grained or
+ * host-coherent memory does not support.  The context owns its contents
+ * until mfm_destroy.  stream: a hipStream_t (NULL = the default stream).
+ * Returns MFM_E_ARG for invalid parameters, MFM_E_WORKSPACE when the
+ * workspace is missing or too small. */
 int mfm_create(const mfm_params *p, int64_t n_max, void *workspace, size_t workspace_bytes,
                void *stream, struct mfm_ctx **out);
 int mfm_destroy(struct mfm_ctx *ctx);
