@@ -59,8 +59,9 @@ struct CandArgs {
 // LCAP 32, 1.39-1.42 + 1.63; 8 particles per chunk with LCAP 64, 1.29 + 1.63.
 // The LDS a workgroup holds sets how many wavefronts a CU runs: fewer
 // staged entries per particle buy occupancy at the price of more direct
-// stores.
-constexpr int SLOTS = 8;   // candidates per lane per round: 512 per wavefront
+// stores.  Since a round loads and tests only its occupied slots, the slot
+// count matters less (search 0.951 ms with 6, 0.964 with 8; 10 spills).
+constexpr int SLOTS = 6;   // candidates per lane per round: 384 per wavefront
 constexpr int TCH = 16;    // particles per staged chunk
 constexpr int LCAP = 48;   // list entries per particle staged in LDS (more are stored directly)
 
@@ -115,7 +116,6 @@ __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) ca
   const int C = s_pre[27];
   const bool wraps = cx == 0 || cy == 0 || cz == 0 || cx == g.nc[0] - 1 ||
                      cy == g.nc[1] - 1 || cz == g.nc[2] - 1;
-  const uint64_t below = (1ull << lane) - 1ull;
   for (int t0 = 0; t0 < own.y; t0 += TCH) {
     const int T = min(TCH, own.y - t0);
     // lane t holds particle t of the chunk and the length of its list; the
@@ -129,13 +129,20 @@ __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) ca
     }
     __syncthreads();
     for (int cb = 0; cb < C; cb += 64 * SLOTS) {
+      // slots holding at least one candidate (the rest are neither loaded
+      // nor tested: the last round of a stencil is often nearly empty)
+      const int nsl = min(SLOTS, (C - cb + 63) / 64);
       double px[SLOTS], py[SLOTS], pz[SLOTS], pq[SLOTS];
       int jj[SLOTS];
 #pragma unroll
       for (int s = 0; s < SLOTS; ++s) {
+        if (s >= nsl) break;
         const int c = cb + s * 64 + lane;
+        // an empty lane: never the particle itself, and its distance
+        // overflows to +inf, which fails every test
         jj[s] = -1;
-        px[s] = py[s] = pz[s] = pq[s] = 0.0;
+        px[s] = py[s] = pz[s] = 1e300;
+        pq[s] = 0.0;
         if (c < C) {
           int lo = 0, hi = 27;  // range r with s_pre[r] <= c < s_pre[r + 1]
           while (hi - lo > 1) {
@@ -164,21 +171,34 @@ __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) ca
         int base = __builtin_amdgcn_readlane(tcnt, t);
 #pragma unroll
         for (int s = 0; s < SLOTS; ++s) {
-          bool hit = false;
-          double r2 = 0.0;
-          if (jj[s] >= 0 && jj[s] != ti) {
-            double ex = px[s] - ptx, ey = py[s] - pty, ez = pz[s] - ptz;
-            if (WRAP) {
-              ex = min_image(ex, g.box[0], g.half[0]);
-              ey = min_image(ey, g.box[1], g.half[1]);
-              ez = min_image(ez, g.box[2], g.half[2]);
-            }
-            r2 = ex * ex + ey * ey + ez * ez;
-            hit = r2 < fmax(ptq, pq[s]);
+          if (s >= nsl) break;
+          double ex = px[s] - ptx, ey = py[s] - pty, ez = pz[s] - ptz;
+          if (WRAP) {
+            ex = min_image(ex, g.box[0], g.half[0]);
+            ey = min_image(ey, g.box[1], g.half[1]);
+            ez = min_image(ez, g.box[2], g.half[2]);
           }
-          const uint64_t m = __ballot(hit);
-          if (hit) {
-            const int k = base + __popcll(m & below);
+          const double r2 = ex * ex + ey * ey + ez * ez;
+          // r2 < max(ptq, pq) as two compares, the particle's own radius by
+          // the integer order of the bit patterns (the same order for the
+          // non-negative values here, +inf included) so that the compiler
+          // keeps them apart, and one lane mask per compare: no branch and
+          // no per-slot canonicalisation of the operands
+          const bool na = r2 < pq[s];
+          const bool nt = __double_as_longlong(r2) < __double_as_longlong(ptq);
+          const bool other = jj[s] != ti;
+          const bool hit = (na | nt) & other;
+          const uint64_t m = (__builtin_amdgcn_ballot_w64(na) | __builtin_amdgcn_ballot_w64(nt)) &
+                             __builtin_amdgcn_ballot_w64(other);
+          const int k = base + (int)__builtin_amdgcn_mbcnt_hi(
+                                   (uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+          const int nb = base + __popcll(m);
+          if (nb <= LCAP) {  // wave-uniform: every hit of the slot is staged
+            if (hit) {
+              s_idx[t][k] = jj[s];
+              s_r2[t][k] = r2;
+            }
+          } else if (hit) {
             if (k < LCAP) {
               s_idx[t][k] = jj[s];
               s_r2[t][k] = r2;
@@ -188,7 +208,7 @@ __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) ca
               a.cand_r2[at] = r2;
             }
           }
-          base += __popcll(m);
+          base = nb;
         }
         tcnt = lane == t ? base : tcnt;
       }
