@@ -87,6 +87,40 @@ __device__ __forceinline__ void sym_apply(const T b[6], const T s[3], T g[3]) {
   g[2] = b[2] * s[0] + b[4] * s[1] + b[5] * s[2];
 }
 
+// What the first loop gathers of one neighbour's record: the FP64 position
+// and, on the mixed path, the FP32 tail (V, rho, vx, vy, vz, P, c); on the
+// FP64 path the FP64 values.
+template <typename T> struct NbRec;
+template <> struct NbRec<float> {
+  double x, y, z;
+  float4 f0, f1;
+  __device__ __forceinline__ void load(const double *gj) {
+    x = gj[GIN_X]; y = gj[GIN_Y]; z = gj[GIN_Z];
+    const float4 *gf = reinterpret_cast<const float4 *>(gj + GIN_F32);
+    f0 = gf[0]; f1 = gf[1];
+  }
+  __device__ __forceinline__ void values(double q[5], float &v, float &c) const {
+    v = f0.x;
+    q[0] = f0.y; q[1] = f0.z; q[2] = f0.w; q[3] = f1.x; q[4] = f1.y;
+    c = f1.z;
+  }
+};
+template <> struct NbRec<double> {
+  double x, y, z, v, q[5], c;
+  __device__ __forceinline__ void load(const double *gj) {
+    x = gj[GIN_X]; y = gj[GIN_Y]; z = gj[GIN_Z];
+    v = gj[GIN_V];
+    q[0] = gj[GIN_RHO]; q[1] = gj[GIN_VX]; q[2] = gj[GIN_VY]; q[3] = gj[GIN_VZ]; q[4] = gj[GIN_P];
+    c = gj[GIN_C];
+  }
+  __device__ __forceinline__ void values(double qo[5], double &vo, double &co) const {
+    vo = v;
+#pragma unroll
+    for (int k = 0; k < 5; ++k) qo[k] = q[k];
+    co = c;
+  }
+};
+
 template <typename T>
 __global__ void __launch_bounds__(BS) gradients_k(GradArgs a) {
   __shared__ int32_t s_ring[BS / 64][RING][64];
@@ -149,20 +183,29 @@ __global__ void __launch_bounds__(BS) gradients_k(GradArgs a) {
     // candidate order): every member is also a face
     const int gc = live ? a.gl_cnt[i] : 0;
     const int gmax = wave_max_i32(gc);
-    // each loop below loads its next list entry one iteration ahead, so that
-    // only the dependent gather is on the critical path
+    // the first loop runs two entries ahead for the list index and one ahead
+    // for the neighbour's record, so that a gather is in flight while the
+    // previous entry is summed; the others load their next entry one
+    // iteration ahead
     int jn = gc > 0 ? a.gl[list_at(i, 0, n)] : 0;
+    int jn2 = gc > 1 ? a.gl[list_at(i, 1, n)] : 0;
+    NbRec<T> nb;
+    if (gc > 0) nb.load(a.gin + (int64_t)jn * GIN_STRIDE);
     for (int k = 0; k < gmax; ++k) {
       if (k % RSTEP == 0) make_room();
       if (k < gc) {
         const int j = jn;
-        if (k + 1 < gc) jn = a.gl[list_at(i, k + 1, n)];
+        const NbRec<T> cur = nb;
+        if (k + 1 < gc) {
+          jn = jn2;
+          nb.load(a.gin + (int64_t)jn * GIN_STRIDE);
+          if (k + 2 < gc) jn2 = a.gl[list_at(i, k + 2, n)];
+        }
         if (emit_face((int)i, j)) put_face(j);
-        const double *gj = a.gin + (int64_t)j * GIN_STRIDE;
         ++pairs;
-        const double e0 = min_image(gj[GIN_X] - xi, a.box[0], a.half[0]);
-        const double e1 = min_image(gj[GIN_Y] - yi, a.box[1], a.half[1]);
-        const double e2 = min_image(gj[GIN_Z] - zi, a.box[2], a.half[2]);
+        const double e0 = min_image(cur.x - xi, a.box[0], a.half[0]);
+        const double e1 = min_image(cur.y - yi, a.box[1], a.half[1]);
+        const double e2 = min_image(cur.z - zi, a.box[2], a.half[2]);
         const double r2 = e0 * e0 + e1 * e1 + e2 * e2;
         if (r2 != 0.0) {
           const T d0 = T(e0), d1 = T(e1), d2 = T(e2);
@@ -171,18 +214,7 @@ __global__ void __launch_bounds__(BS) gradients_k(GradArgs a) {
           // copies (half the bytes through the cache; the separation stays FP64)
           double qj[5];
           T vj, cj;
-          if constexpr (sizeof(T) == sizeof(float)) {
-            const float4 *gf = reinterpret_cast<const float4 *>(gj + GIN_F32);
-            const float4 f0 = gf[0], f1 = gf[1];
-            vj = f0.x;
-            qj[0] = f0.y; qj[1] = f0.z; qj[2] = f0.w; qj[3] = f1.x; qj[4] = f1.y;
-            cj = f1.z;
-          } else {
-            vj = T(gj[GIN_V]);
-            qj[0] = gj[GIN_RHO]; qj[1] = gj[GIN_VX]; qj[2] = gj[GIN_VY]; qj[3] = gj[GIN_VZ];
-            qj[4] = gj[GIN_P];
-            cj = T(gj[GIN_C]);
-          }
+          cur.values(qj, vj, cj);
           const T wv = vj * wnorm * spline_wt<T>(r * ih);
           e[0] += wv * d0 * d0;
           e[1] += wv * d0 * d1;
@@ -272,10 +304,14 @@ __global__ void __launch_bounds__(BS) gradients_k(GradArgs a) {
     T alpha[5] = {T(1), T(1), T(1), T(1), T(1)};
     if (a.limiter & MFM_LIMIT_BJ) {
       T dmax[5] = {0, 0, 0, 0, 0}, dmin[5] = {0, 0, 0, 0, 0};
-      int bn = gc > 0 ? a.gl[list_at(i, 0, n)] : 0;
+      int bn = gc > 1 ? a.gl[list_at(i, 1, n)] : 0;
+      double4 pn = gc > 0 ? a.pos[a.gl[list_at(i, 0, n)]] : make_double4(0, 0, 0, 0);
       for (int k = 0; k < gc; ++k) {
-        const double4 pj = a.pos[bn];
-        if (k + 1 < gc) bn = a.gl[list_at(i, k + 1, n)];
+        const double4 pj = pn;
+        if (k + 1 < gc) {
+          pn = a.pos[bn];
+          if (k + 2 < gc) bn = a.gl[list_at(i, k + 2, n)];
+        }
         const T d0 = T(min_image(pj.x - xi, a.box[0], a.half[0]));
         const T d1 = T(min_image(pj.y - yi, a.box[1], a.half[1]));
         const T d2 = T(min_image(pj.z - zi, a.box[2], a.half[2]));
