@@ -329,9 +329,9 @@ struct HSolve {
 
 // The smoothing-length solve of one particle from the start value h, inside
 // the bracket (0, hcap): hcap = min(cell side, cell_margin * H at the build).
-//   sums(h2, ih, s, ds):  s = sum w(q), ds = sum q w'(q) over the list entries
-//                         with r^2 < h2 (q = r / h, ih = 1 / h);
-//   esums(h2, ih, ws, e): ws = sum w(q) and the unweighted E~ = sum w(q) d d^T.
+//   sums(h, ih, s, ds):  s = sum w(q), ds = sum q w'(q) over the list entries
+//                        with r < h (q = r / h, ih = 1 / h);
+//   esums(h, ih, ws, e): ws = sum w(q) and the unweighted E~ = sum w(q) d d^T.
 // The particle itself (w(0) = 1) is added here.  Both must return the same
 // value in every lane that calls them together.
 template <typename Sums, typename ESums>
@@ -349,7 +349,7 @@ __device__ __forceinline__ HSolve newton_h(const DensityArgs &a, double hcap, do
     for (int it = 0; it < a.h_maxit; ++it) {
       const double ih = 1.0 / h;
       double s, ds;
-      sums(h * h, ih, s, ds);
+      sums(h, ih, s, ds);
       s += 1.0;
       s_last = s;
       const double gv = (32.0 / 3.0) * s - target;
@@ -380,7 +380,7 @@ __device__ __forceinline__ HSolve newton_h(const DensityArgs &a, double hcap, do
     // number density at the solution and the unweighted E~ of the check
     const double h2 = h * h;
     double ws, e[6];
-    esums(h2, 1.0 / h, ws, e);
+    esums(h, 1.0 / h, ws, e);
     ws += 1.0;
     r.winv = 8.0 / (PI * h * h2) * ws;
     r.nc = cond3(e);  // the kernel's normalisation drops out of the condition number
@@ -405,17 +405,18 @@ __device__ __forceinline__ HSolve newton_h(const DensityArgs &a, double hcap, do
   return r;
 }
 
-__device__ __forceinline__ void add_pair(double &s, double &ds, double r2, double ih) {
-  const double q = sqrt(r2) * ih;
+// r: the pair's distance, sqrt(r^2)
+__device__ __forceinline__ void add_pair(double &s, double &ds, double r, double ih) {
+  const double q = r * ih;
   s += spline_w(q);
   ds += spline_qdw(q);
 }
 
-__device__ __forceinline__ void add_e(double &ws, double e[6], double r2, double ih,
+__device__ __forceinline__ void add_e(double &ws, double e[6], double r, double ih,
                                       double4 pj, double4 pi, const CellGrid &g) {
-  const double w = spline_w(sqrt(r2) * ih);
+  const double w = spline_w(r * ih);
   ws += w;
-  if (r2 > 0.0) {
+  if (r > 0.0) {
     const double dx = min_image(pj.x - pi.x, g.box[0], g.half[0]);
     const double dy = min_image(pj.y - pi.y, g.box[1], g.half[1]);
     const double dz = min_image(pj.z - pi.z, g.box[2], g.half[2]);
@@ -479,53 +480,54 @@ __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) de
   const int cnt = valid ? a.cand_cnt[i] : 0;
   int64_t noconv = 0, boosts = 0, fails = 0, overflow = 0;
   if (valid && cnt <= DCAP) {
-    double rr[DM];
+    // the distances r (not r^2): the square root is taken once here, not at
+    // every Newton pass, and membership is r < h as in the kernel's support
+    double rs[DM];
     int jr[DM];
 #pragma unroll
     for (int m = 0; m < DM; ++m) {
       const int k = sub + DG * m;
-      rr[m] = __builtin_huge_val();  // beyond the list: never inside any H
+      rs[m] = __builtin_huge_val();  // beyond the list: never inside any H
       jr[m] = 0;
       if (k < cnt) {
-        rr[m] = a.cand_r2[list_at(i, k, n)];
+        rs[m] = sqrt(a.cand_r2[list_at(i, k, n)]);
         jr[m] = a.cand[list_at(i, k, n)];
       }
     }
     const double4 pi = a.pos[i];
-    auto sums = [&](double h2, double ih, double &s, double &ds) {
+    auto sums = [&](double h, double ih, double &s, double &ds) {
       s = 0.0;
       ds = 0.0;
 #pragma unroll
       for (int m = 0; m < DM; ++m)
-        if (rr[m] < h2) add_pair(s, ds, rr[m], ih);
+        if (rs[m] < h) add_pair(s, ds, rs[m], ih);
       s = group_sum<DG>(s);
       ds = group_sum<DG>(ds);
     };
-    auto esums = [&](double h2, double ih, double &ws, double e[6]) {
+    auto esums = [&](double h, double ih, double &ws, double e[6]) {
       ws = 0.0;
 #pragma unroll
       for (int q = 0; q < 6; ++q) e[q] = 0.0;
 #pragma unroll
       for (int m = 0; m < DM; ++m)
-        if (rr[m] < h2) add_e(ws, e, rr[m], ih, a.pos[jr[m]], pi, g);
+        if (rs[m] < h) add_e(ws, e, rs[m], ih, a.pos[jr[m]], pi, g);
       ws = group_sum<DG>(ws);
 #pragma unroll
       for (int q = 0; q < 6; ++q) e[q] = group_sum<DG>(e[q]);
     };
     const HSolve r = newton_h(a, hcap_of(g, pi), a.H[i], sums, esums);
-    const double h2 = r.h * r.h;
     int gn = 0, rn = 0;
 #pragma unroll
     for (int m = 0; m < DM; ++m) {
       const bool in = sub + DG * m < cnt;
-      const bool near = in && rr[m] < h2;
+      const bool near = in && rs[m] < r.h;
       const bool far = in && !near;
       const uint64_t mn = __ballot(near) & gmask, mf = __ballot(far) & gmask;
       if (near) s_i[gn + __popcll(mn & below)][gt] = jr[m];
       if (far) {
         const int p = rn + __popcll(mf & below);
         s_i[DCAP - 1 - p][gt] = jr[m];
-        s_f[p][gt] = (float)rr[m];
+        s_f[p][gt] = (float)(rs[m] * rs[m]);  // within an FP32 rounding of r^2
       }
       gn += __popcll(mn);
       rn += __popcll(mf);
@@ -580,29 +582,28 @@ __global__ void __launch_bounds__(BS) density_long_k(DensityArgs a, CellGrid g) 
     const int cnt = a.cand_cnt[i];
     auto at = [&](int k) { return list_at(i, k, n); };
     const double4 pi = a.pos[i];
-    auto sums = [&](double h2, double ih, double &s, double &ds) {
+    auto sums = [&](double h, double ih, double &s, double &ds) {
       s = 0.0;
       ds = 0.0;
       for (int k = 0; k < cnt; ++k) {
-        const double r2 = a.cand_r2[at(k)];
-        if (r2 < h2) add_pair(s, ds, r2, ih);
+        const double r = sqrt(a.cand_r2[at(k)]);
+        if (r < h) add_pair(s, ds, r, ih);
       }
     };
-    auto esums = [&](double h2, double ih, double &ws, double e[6]) {
+    auto esums = [&](double h, double ih, double &ws, double e[6]) {
       ws = 0.0;
       for (int q = 0; q < 6; ++q) e[q] = 0.0;
       for (int k = 0; k < cnt; ++k) {
-        const double r2 = a.cand_r2[at(k)];
-        if (r2 < h2) add_e(ws, e, r2, ih, a.pos[a.cand[at(k)]], pi, g);
+        const double r = sqrt(a.cand_r2[at(k)]);
+        if (r < h) add_e(ws, e, r, ih, a.pos[a.cand[at(k)]], pi, g);
       }
     };
     const HSolve r = newton_h(a, hcap_of(g, pi), a.H[i], sums, esums);
-    const double h2 = r.h * r.h;
     int gn = 0, rn = 0;
     for (int k = 0; k < cnt; ++k) {
       const double r2 = a.cand_r2[at(k)];
       const int j = a.cand[at(k)];
-      if (r2 < h2) {
+      if (sqrt(r2) < r.h) {
         a.gl[at(gn++)] = j;
       } else {
         a.cand[at(rn)] = j;
