@@ -163,7 +163,9 @@ int mfm_destroy(struct mfm_ctx *ctx);
 /* Sort the particles into cells on a Morton (Z-order) curve of cells of side
  * >= cell_margin * max H (sec. 2.2.1: particles are reordered in memory so
  * that spatial neighbours are contiguous) and permute the state arrays
- * (x..H) IN PLACE into that order.  perm (device int64, n, may be NULL)
+ * (x..H) IN PLACE into that order.  The sort is stable: within a cell the
+ * particles keep their order from before the call, so a second call on
+ * unchanged particles is the identity.  perm (device int64, n, may be NULL)
  * receives for each new slot k the slot the particle had before the call.
  * The H values at this call bound the next mfm_density (see cell_margin).
  * Synchronises (it reads max H to size the grid). */

@@ -147,22 +147,34 @@ __global__ void scatter_k(int64_t n, const uint32_t *__restrict__ code, int32_t 
 }
 
 // Within a cell, order the particles by their slot before the sort, so the
-// result does not depend on the order the atomics were served in.
+// result does not depend on the order the atomics were served in.  One
+// wavefront per cell (grid-stride over the cell codes): a lane holds one
+// member, and its place is the number of smaller members (the slots are
+// distinct).  A cell of more than 64 particles is sorted by one lane.
 __global__ void cell_sort_k(int64_t ncodes, const int32_t *__restrict__ start,
                             const int32_t *__restrict__ count, int32_t *order) {
-  int64_t c = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (c >= ncodes) return;
-  int k = count[c];
-  if (k < 2) return;
-  int32_t *a = order + start[c];
-  for (int s = 1; s < k; ++s) {
-    int32_t v = a[s];
-    int t = s - 1;
-    while (t >= 0 && a[t] > v) {
-      a[t + 1] = a[t];
-      --t;
+  const int lane = threadIdx.x & 63;
+  const int64_t nw = ((int64_t)gridDim.x * blockDim.x) >> 6;
+  for (int64_t c = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) >> 6; c < ncodes; c += nw) {
+    const int k = count[c];  // the same in every lane: the branches below are uniform
+    if (k < 2) continue;
+    int32_t *a = order + start[c];
+    if (k <= 64) {
+      const int32_t v = lane < k ? a[lane] : 0x7fffffff;
+      int rank = 0;
+      for (int t = 0; t < k; ++t) rank += __builtin_amdgcn_readlane(v, t) < v ? 1 : 0;
+      if (lane < k) a[rank] = v;  // every read above has completed
+    } else if (lane == 0) {
+      for (int s = 1; s < k; ++s) {
+        int32_t v = a[s];
+        int t = s - 1;
+        while (t >= 0 && a[t] > v) {
+          a[t + 1] = a[t];
+          --t;
+        }
+        a[t + 1] = v;
+      }
     }
-    a[t + 1] = v;
   }
 }
 
@@ -221,8 +233,9 @@ hipError_t launch_build_cells(mfm_ctx *ctx, const mfm_particles *pp, int64_t *pe
                      hipMemcpyDeviceToDevice, st);
   if (e != hipSuccess) return e;
   scatter_k<<<blocks_for(n, BS), BS, 0, st>>>(n, ctx->code, ctx->cursor, ctx->order);
-  cell_sort_k<<<blocks_for(ctx->ncodes, BS), BS, 0, st>>>(ctx->ncodes, ctx->cell_start,
-                                                           ctx->cell_count, ctx->order);
+  int sb = (int)((ctx->ncodes + BS / 64 - 1) / (BS / 64));  // one wavefront per cell code
+  if (sb > 16384) sb = 16384;
+  cell_sort_k<<<sb, BS, 0, st>>>(ctx->ncodes, ctx->cell_start, ctx->cell_count, ctx->order);
   range_k<<<blocks_for(ctx->ncodes, BS), BS, 0, st>>>(ctx->ncodes, ctx->cell_start,
                                                        ctx->cell_count, ctx->crange);
   Fields fs;

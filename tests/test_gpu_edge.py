@@ -130,3 +130,33 @@ def test_long_and_short_candidate_lists():
     print("[edge] long and short candidate lists", flush=True)
     gpu, new, dt, diag, ref = run_both({"scheme": "mfv", "max_list": 512, "cell_margin": 1.3}, st)
     check_fields(gpu, new, dt, diag, ref, 1e-12, st)
+
+
+@pytest.mark.parametrize("margin", [1.1, 2.5])
+def test_cell_order_is_stable(margin):
+    """The cell build is a stable sort by cell: perm is a permutation of the
+    slots, the state moves with it, and a second build on the sorted particles
+    is the identity.  With cell_margin 1.1 the 4000 particles sit about 12 to a
+    cell (cells of up to 64 are sorted by a wavefront); with 2.5 about 150 to
+    a cell (larger cells are sorted by one lane)."""
+    _need_gpu()
+    st = W.random_gas(N=4000, seed=11)
+    order = np.random.default_rng(12).permutation(len(st["x"]))
+    st = {k: (np.asarray(v)[order] if np.ndim(v) == 1 and len(v) == len(order) else v)
+          for k, v in st.items()}
+    n = len(st["x"])
+    ctx, ps = _ctx({"scheme": "mfm"}, st, cell_margin=margin)
+    print(f"[edge] stable cell order, cell_margin {margin}", flush=True)
+    perm = torch.empty(n, dtype=torch.int64, device="cuda")
+    mfm.mfm_build_cells(ctx, ps, perm)
+    torch.cuda.synchronize()
+    p = perm.cpu().numpy()
+    assert np.array_equal(np.sort(p), np.arange(n))
+    h = ps.host(["x", "y", "z", "H", "id"])
+    for k in ("x", "y", "z", "H"):
+        assert np.array_equal(h[k], np.asarray(st[k])[p])
+    assert np.array_equal(h["id"], p)
+    mfm.mfm_build_cells(ctx, ps, perm)
+    torch.cuda.synchronize()
+    assert np.array_equal(perm.cpu().numpy(), np.arange(n))
+    ctx.close()
