@@ -17,6 +17,12 @@ Recipes (all in a periodic unit box, lattice spacing D = 1/n, each particle at
   weights of support equal to the distance of the 34th nearest (cf. sec. 3.1.5).
 * ``uniform`` -- uniform gas (density 1, pressure 1), optional bulk velocity;
   with ``jitter = 0`` a perfect lattice.
+* ``soundwave`` -- a linear sound wave along x (sec. 3.1.1): an unjittered
+  lattice of N particles along x and ``nyz`` across y and z, in the periodic
+  box (1, nyz / N, nyz / N); density 1 + A cos(2 pi x) through the particle
+  mass, vx = A c cos(2 pi x), pressure 1 + A gamma cos(2 pi x), with
+  c = sqrt(gamma) (unit background density and pressure).  Not cubic: its box
+  comes from ``soundwave_box``.
 * ``clustered`` -- log-normal density field with a k^-2 spectrum, particles
   Poisson-sampled per grid cell, Zel'dovich-like velocities (a stand-in for the
   clustered cosmological gas the paper's scaling runs use, which are not
@@ -69,6 +75,33 @@ def sod(n: int = 16, seed: int = 1, gamma: float = 5.0 / 3.0, n_ngb: float = 32.
     m = rho_n * D ** 3
     v = np.zeros((3, N))
     return _finish(pos, m, v, Pn, gamma, rho_n, n_ngb, N)
+
+
+def soundwave_box(N: int, nyz: int = 8):
+    """The periodic box of ``soundwave(N, nyz)``: unit length along x."""
+    return (1.0, nyz / N, nyz / N)
+
+
+def soundwave(N: int = 32, nyz: int = 8, A: float = 1e-3, gamma: float = 1.4,
+              n_ngb: float = 32.0):
+    D = 1.0 / N
+    gx = (np.arange(N, dtype=np.float64) + 0.5) * D
+    gy = (np.arange(nyz, dtype=np.float64) + 0.5) * D
+    X, Y, Z = np.meshgrid(gx, gy, gy, indexing="ij")
+    pos = np.stack([X.ravel(), Y.ravel(), Z.ravel()])
+    n = pos.shape[1]
+    cs = math.sqrt(gamma)
+    wave = np.cos(2.0 * math.pi * pos[0])
+    rho = 1.0 + A * wave
+    P = 1.0 + A * gamma * wave
+    v = np.zeros((3, n))
+    v[0] = A * cs * wave
+    m = rho * D ** 3
+    st = _finish(pos, m, v, P, gamma, rho, n_ngb, n)
+    # _finish sizes H for n particles in a unit volume; here the number
+    # density is N^3
+    st["H"] = np.full(n, (3.0 * n_ngb / (4.0 * math.pi)) ** (1.0 / 3.0) * D)
+    return st
 
 
 def kh(n: int = 64, seed: int = 2, gamma: float = 5.0 / 3.0, n_ngb: float = 32.0,
