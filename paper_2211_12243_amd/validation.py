@@ -8,8 +8,13 @@ once, so the exact density is the initial one again), with the gradient
 limiter off and N_NGB = 32.  Every step runs on the GPU; the host only
 loops, sums the errors and keeps the clock.
 
-Two L1 norms of the density are returned, both with rho_i from a density
-pass at the final positions:
+``run_sod`` is its shock tube (sec. 3.1.2): the density jump set by the
+number density of equal-mass particles, N_NGB = 64, evolved to t = 0.13;
+it returns the particle fields for a comparison with the exact solution of
+the Riemann problem at x = 0.5.
+
+For the sound wave, two L1 norms of the density are returned, both with
+rho_i from a density pass at the final positions:
 
 * ``L1``: mean_i |rho_i(T) - rho_i(0)|, against each particle's own density
   estimate at t = 0 (the exact solution returns to the initial state after
@@ -93,6 +98,45 @@ def run_soundwave(N: int, scheme: str = "mfm", precision: str = "fp64", nyz: int
     return {"N": N, "n": n, "scheme": scheme, "precision": precision, "L1": l1,
             "L1_exact": l1_exact, "L1_exact_0": l1_exact_0, "steps": steps, "t": t,
             "wall_s": wall}
+
+
+def run_sod(scheme: str = "mfm", precision: str = "fp64", nx_left: int = 100, nyz: int = 16,
+            k_right: int = 10, t_end: float = 0.13, gamma: float = 1.4, n_ngb: float = 64.0,
+            max_steps: int = 100000) -> dict:
+    """The shock tube to t_end; fields (in the initial particle order) from a
+    density pass at the final positions: x, rho, vx and P."""
+    st, rho_r = W.sod_tube(nx_left, nyz=nyz, k_right=k_right, gamma=gamma, n_ngb=n_ngb)
+    n = len(st["x"])
+    # N_NGB = 64 and candidate radii up to cell_margin x max(H_i, H_j) across
+    # the jump: lists of up to about 200
+    cfg = {"scheme": scheme, "gamma": gamma, "n_ngb": n_ngb, "max_list": 384,
+           "box": W.sod_tube_box(nx_left, nyz)}
+    ctx = mfm.Context(mfm.params_from_dict(cfg, precision=precision), n)
+    try:
+        ps = mfm.ParticleSet(st)
+        t, steps = 0.0, 0
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        while t < t_end * (1.0 - 1e-12):
+            if steps >= max_steps:
+                raise RuntimeError(f"shock tube: {max_steps} steps before t = {t_end}")
+            t += mfm.mfm_step(ctx, ps, t_end - t)
+            steps += 1
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        density_at_positions(ctx, ps)
+        torch.cuda.synchronize()
+        ids = ps["id"].cpu().numpy()
+        out = {}
+        for k in ("x", "rho", "vx", "P"):
+            a = np.empty(n)
+            a[ids] = ps[k].cpu().numpy()
+            out[k] = a
+    finally:
+        ctx.close()
+    out.update({"n": n, "scheme": scheme, "precision": precision, "rho_right": rho_r,
+                "steps": steps, "t": t, "wall_s": wall})
+    return out
 
 
 def convergence_order(results: list) -> list:

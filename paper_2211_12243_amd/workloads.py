@@ -23,6 +23,14 @@ Recipes (all in a periodic unit box, lattice spacing D = 1/n, each particle at
   mass, vx = A c cos(2 pi x), pressure 1 + A gamma cos(2 pi x), with
   c = sqrt(gamma) (unit background density and pressure).  Not cubic: its box
   comes from ``soundwave_box``.
+* ``sod_tube`` -- the paper's shock tube (sec. 3.1.2): (rho, v, P) = (1, 0, 1)
+  for x < 0.5 and (0.25, 0, 0.1795) beyond, gamma = 1.4, the density jump set
+  by the number density of equal-mass particles (an unjittered lattice of
+  spacing D = 0.5 / nx_left on the left; on the right ``k_right`` particles
+  across and the x spacing that gives a quarter of the left number density,
+  rounded to whole layers, so the right density is within a few per cent of
+  0.25 and is returned exactly).  The box is periodic, so a mirrored tube sits
+  at x = 0; its box comes from ``sod_tube_box``.
 * ``clustered`` -- log-normal density field with a k^-2 spectrum, particles
   Poisson-sampled per grid cell, Zel'dovich-like velocities (a stand-in for the
   clustered cosmological gas the paper's scaling runs use, which are not
@@ -102,6 +110,39 @@ def soundwave(N: int = 32, nyz: int = 8, A: float = 1e-3, gamma: float = 1.4,
     # density is N^3
     st["H"] = np.full(n, (3.0 * n_ngb / (4.0 * math.pi)) ** (1.0 / 3.0) * D)
     return st
+
+
+def sod_tube_box(nx_left: int = 100, nyz: int = 16):
+    """The periodic box of ``sod_tube(nx_left, nyz)``: unit length along x."""
+    T = nyz * 0.5 / nx_left
+    return (1.0, T, T)
+
+
+def sod_tube(nx_left: int = 100, nyz: int = 16, k_right: int = 10, gamma: float = 1.4,
+             n_ngb: float = 64.0, rho=(1.0, 0.25), P=(1.0, 0.1795)):
+    """Returns (state, rho_right): the right density the lattice realises."""
+    D = 0.5 / nx_left
+    T = nyz * D
+    m = rho[0] * D ** 3
+    dy_r = T / k_right
+    n_r = max(1, int(round(0.5 / (m / (rho[1] * dy_r ** 2)))))
+    dx_r = 0.5 / n_r
+    rho_r = m / (dx_r * dy_r ** 2)
+    gl = (np.arange(nyz, dtype=np.float64) + 0.5) * D
+    X, Y, Z = np.meshgrid((np.arange(nx_left, dtype=np.float64) + 0.5) * D, gl, gl, indexing="ij")
+    gr = (np.arange(k_right, dtype=np.float64) + 0.5) * dy_r
+    Xr, Yr, Zr = np.meshgrid(0.5 + (np.arange(n_r, dtype=np.float64) + 0.5) * dx_r, gr, gr,
+                             indexing="ij")
+    pos = np.concatenate([np.stack([X.ravel(), Y.ravel(), Z.ravel()]),
+                          np.stack([Xr.ravel(), Yr.ravel(), Zr.ravel()])], axis=1)
+    n = pos.shape[1]
+    left = pos[0] < 0.5
+    rho_n = np.where(left, rho[0], rho_r)
+    Pn = np.where(left, P[0], P[1])
+    masses = np.full(n, m)
+    st = _finish(pos, masses, np.zeros((3, n)), Pn, gamma, rho_n, n_ngb, n)
+    st["H"] = (3.0 * n_ngb * masses / (4.0 * math.pi * rho_n)) ** (1.0 / 3.0)
+    return st, rho_r
 
 
 def kh(n: int = 64, seed: int = 2, gamma: float = 5.0 / 3.0, n_ngb: float = 32.0,

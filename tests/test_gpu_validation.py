@@ -57,3 +57,40 @@ def test_soundwave_mfv_converges():
     res, orders = _series("mfv", "fp64", 1e-5, (16, 32, 64))
     print("orders", orders, flush=True)
     assert all(o >= 0.9 for o in orders), orders
+
+
+@pytest.mark.parametrize("scheme,bound", [("mfm", 0.012), ("mfv", 0.014)])
+def test_sod_shock_tube(scheme, bound):
+    """The paper's shock tube (sec. 3.1.2) at t = 0.13 against the exact
+    solution of its Riemann problem (the oracle's exact solver, sampled at
+    (x - 0.5) / t), over 0.25 < x < 0.75, away from the mirrored tube at
+    x = 0.  Observed L1 of (rho, vx, P): MFM 0.0074, 0.0145, 0.0075; MFV
+    0.0087, 0.0177, 0.0093.  The plateaus between the rarefaction and the
+    shock hold the exact star pressure and post-shock density within 2%."""
+    import numpy as np
+
+    import oracle
+
+    _need_gpu()
+    print(f"[sod] {scheme}", flush=True)
+    r = V.run_sod(scheme)
+    g, rl, pl, rr, pr = 1.4, 1.0, 1.0, r["rho_right"], 0.1795
+    st, ps, us, _ = oracle.riemann(g, rl, 0.0, pl, rr, 0.0, pr)
+    assert st == 0
+    x = r["x"]
+    w = (x > 0.25) & (x < 0.75)
+    ex = np.array([oracle.riemann_sample(g, rl, 0.0, pl, rr, 0.0, pr, ps, us, (xi - 0.5) / r["t"])
+                   for xi in x[w]])
+    l1 = [float(np.mean(np.abs(a - b))) for a, b in
+          ((r["rho"][w], ex[:, 0]), (r["vx"][w], ex[:, 1]), (r["P"][w], ex[:, 2]))]
+    print(f"  {r['n']} particles, {r['steps']} steps, {r['wall_s']:.3f} s; "
+          f"L1 rho {l1[0]:.4f}, vx {l1[1]:.4f}, P {l1[2]:.4f}", flush=True)
+    assert abs(r["t"] - 0.13) <= 1e-12
+    assert l1[0] <= bound and l1[1] <= 2.0 * bound and l1[2] <= bound
+    # plateaus: the star pressure between the rarefaction tail and the
+    # shock, the post-shock density between the contact and the shock
+    star = (x > 0.50) & (x < 0.66)
+    post = (x > 0.60) & (x < 0.66)
+    shock_rho = oracle.riemann_sample(g, rl, 0.0, pl, rr, 0.0, pr, ps, us, (0.63 - 0.5) / r["t"])[0]
+    assert abs(np.median(r["P"][star]) - ps) <= 0.02 * ps
+    assert abs(np.median(r["rho"][post]) - shock_rho) <= 0.02 * shock_rho

@@ -30,3 +30,24 @@ def test_soundwave_set():
     assert abs(st["m"].sum() / (box[0] * box[1] * box[2]) - 1.0) < 1e-12
     # H encloses N_NGB lattice particles on average: (4 pi / 3) H^3 N^3 = 32
     assert abs(4.0 * math.pi / 3.0 * st["H"][0] ** 3 * N ** 3 - 32.0) < 1e-9
+
+
+def test_sod_tube_set():
+    st, rho_r = W.sod_tube()
+    box = W.sod_tube_box()
+    n = len(st["x"])
+    assert box == (1.0, 0.08, 0.08)
+    for k, L in zip("xyz", box):
+        assert st[k].min() > 0.0 and st[k].max() < L
+    # equal masses; the density jump through the number density
+    assert np.all(st["m"] == st["m"][0])
+    left = st["x"] < 0.5
+    nl, nr = left.sum(), n - left.sum()
+    vol = 0.5 * box[1] * box[2]
+    assert abs(nl * st["m"][0] / vol - 1.0) < 1e-12
+    assert abs(nr * st["m"][0] / vol - rho_r) < 1e-12
+    assert abs(rho_r - 0.25) < 0.01
+    rho = np.where(left, 1.0, rho_r)
+    P = (1.4 - 1.0) * st["U"] * rho / st["m"]
+    assert np.allclose(P, np.where(left, 1.0, 0.1795), rtol=1e-13, atol=0)
+    assert not st["vx"].any() and np.array_equal(st["E"], st["U"])
