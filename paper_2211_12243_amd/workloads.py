@@ -31,6 +31,11 @@ Recipes (all in a periodic unit box, lattice spacing D = 1/n, each particle at
   rounded to whole layers, so the right density is within a few per cent of
   0.25 and is returned exactly).  The box is periodic, so a mirrored tube sits
   at x = 0; its box comes from ``sod_tube_box``.
+* ``sedov_point`` -- the paper's Sedov validation set (sec. 3.1.5): an
+  unjittered n^3 lattice of density 1, gamma 5/3, a background of total
+  energy E0 = 1e-5 spread evenly, and unit internal energy in one particle,
+  the one at lattice index (n/2, n/2, n/2) (the lattice has no particle at
+  the exact centre).
 * ``clustered`` -- log-normal density field with a k^-2 spectrum, particles
   Poisson-sampled per grid cell, Zel'dovich-like velocities (a stand-in for the
   clustered cosmological gas the paper's scaling runs use, which are not
@@ -143,6 +148,20 @@ def sod_tube(nx_left: int = 100, nyz: int = 16, k_right: int = 10, gamma: float 
     st = _finish(pos, masses, np.zeros((3, n)), Pn, gamma, rho_n, n_ngb, n)
     st["H"] = (3.0 * n_ngb * masses / (4.0 * math.pi * rho_n)) ** (1.0 / 3.0)
     return st, rho_r
+
+
+def sedov_point(n: int = 64, gamma: float = 5.0 / 3.0, n_ngb: float = 32.0, E0: float = 1e-5,
+                E_blast: float = 1.0):
+    """Returns (state, index of the blast particle)."""
+    lat, pos, D = _lattice(n, 0.0, np.random.default_rng(0))
+    N = pos.shape[1]
+    m = np.full(N, D ** 3)
+    st = _finish(pos, m, np.zeros((3, N)), np.zeros(N), gamma, np.ones(N), n_ngb, N)
+    st["U"] = np.full(N, E0 / N)
+    c = (n // 2) * n * n + (n // 2) * n + n // 2
+    st["U"][c] = E_blast
+    st["E"] = st["U"].copy()
+    return st, c
 
 
 def kh(n: int = 64, seed: int = 2, gamma: float = 5.0 / 3.0, n_ngb: float = 32.0,

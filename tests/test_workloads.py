@@ -51,3 +51,16 @@ def test_sod_tube_set():
     P = (1.4 - 1.0) * st["U"] * rho / st["m"]
     assert np.allclose(P, np.where(left, 1.0, 0.1795), rtol=1e-13, atol=0)
     assert not st["vx"].any() and np.array_equal(st["E"], st["U"])
+
+
+def test_sedov_point_set():
+    st, c = W.sedov_point(16)
+    n = 16 ** 3
+    assert len(st["x"]) == n
+    # the blast particle is the lattice point (8, 8, 8) + 1/2, next to the centre
+    assert (st["x"][c], st["y"][c], st["z"][c]) == (8.5 / 16, 8.5 / 16, 8.5 / 16)
+    assert st["U"][c] == 1.0
+    others = np.delete(st["U"], c)
+    assert np.all(others == others[0]) and abs(others.sum() + others[0] - 1e-5) < 1e-18
+    assert abs(st["m"].sum() - 1.0) < 1e-12
+    assert np.array_equal(st["E"], st["U"]) and not st["vx"].any()
