@@ -36,6 +36,12 @@ Recipes (all in a periodic unit box, lattice spacing D = 1/n, each particle at
   energy E0 = 1e-5 spread evenly, and unit internal energy in one particle,
   the one at lattice index (n/2, n/2, n/2) (the lattice has no particle at
   the exact centre).
+* ``gresho`` -- the paper's Gresho-Chan vortex (sec. 3.1.3): an unjittered
+  lattice of n x n particles per plane of side 2 and ``nz`` planes, centred
+  on (1, 1); v_phi = 5r (r <= 0.2), 2 - 5r (0.2 < r < 0.4), 0 beyond;
+  density 1, gamma 1.4, and the pressure of hydrostatic equilibrium with
+  p(0) = 5: 5 + 12.5 r^2, then 9 + 12.5 r^2 - 20 r + 4 ln(5 r), then
+  3 + 4 ln 2.  Its box comes from ``gresho_box``.
 * ``clustered`` -- log-normal density field with a k^-2 spectrum, particles
   Poisson-sampled per grid cell, Zel'dovich-like velocities (a stand-in for the
   clustered cosmological gas the paper's scaling runs use, which are not
@@ -162,6 +168,39 @@ def sedov_point(n: int = 64, gamma: float = 5.0 / 3.0, n_ngb: float = 32.0, E0: 
     st["U"][c] = E_blast
     st["E"] = st["U"].copy()
     return st, c
+
+
+def gresho_box(n: int = 64, nz: int = 8):
+    """The periodic box of ``gresho(n, nz)``."""
+    return (2.0, 2.0, nz * 2.0 / n)
+
+
+def gresho_vphi(r):
+    """The vortex's tangential velocity profile."""
+    r = np.asarray(r, dtype=np.float64)
+    return np.where(r <= 0.2, 5.0 * r, np.where(r < 0.4, 2.0 - 5.0 * r, 0.0))
+
+
+def gresho(n: int = 64, nz: int = 8, gamma: float = 1.4, n_ngb: float = 32.0):
+    D = 2.0 / n
+    g = (np.arange(n, dtype=np.float64) + 0.5) * D
+    gz = (np.arange(nz, dtype=np.float64) + 0.5) * D
+    X, Y, Z = np.meshgrid(g, g, gz, indexing="ij")
+    pos = np.stack([X.ravel(), Y.ravel(), Z.ravel()])
+    N = pos.shape[1]
+    dx, dy = pos[0] - 1.0, pos[1] - 1.0
+    r = np.sqrt(dx * dx + dy * dy)
+    vphi = gresho_vphi(r)
+    rs = np.where(r > 0.0, r, 1.0)
+    v = np.zeros((3, N))
+    v[0] = -vphi * dy / rs
+    v[1] = vphi * dx / rs
+    mid = 9.0 + 12.5 * r * r - 20.0 * r + 4.0 * np.log(np.maximum(5.0 * r, 1e-300))
+    P = np.where(r <= 0.2, 5.0 + 12.5 * r * r, np.where(r < 0.4, mid, 3.0 + 4.0 * math.log(2.0)))
+    m = np.full(N, D ** 3)
+    st = _finish(pos, m, v, P, gamma, np.ones(N), n_ngb, N)
+    st["H"] = np.full(N, (3.0 * n_ngb / (4.0 * math.pi)) ** (1.0 / 3.0) * D)
+    return st
 
 
 def kh(n: int = 64, seed: int = 2, gamma: float = 5.0 / 3.0, n_ngb: float = 32.0,

@@ -64,3 +64,30 @@ def test_sedov_point_set():
     assert np.all(others == others[0]) and abs(others.sum() + others[0] - 1e-5) < 1e-18
     assert abs(st["m"].sum() - 1.0) < 1e-12
     assert np.array_equal(st["E"], st["U"]) and not st["vx"].any()
+
+
+def test_gresho_set():
+    st = W.gresho(32, 4)
+    box = W.gresho_box(32, 4)
+    assert box == (2.0, 2.0, 0.25) and len(st["x"]) == 32 * 32 * 4
+    dx, dy = st["x"] - 1.0, st["y"] - 1.0
+    r = np.sqrt(dx * dx + dy * dy)
+    vphi = (dx * st["vy"] - dy * st["vx"]) / r
+    assert np.allclose(vphi, W.gresho_vphi(r), rtol=0, atol=1e-14)
+    assert np.allclose(dx * st["vx"] + dy * st["vy"], 0.0, atol=1e-14)
+    P = 0.4 * st["U"] / st["m"]  # density 1
+    # hydrostatic equilibrium: dP/dr = v_phi^2 / r, by finite differences of
+    # the profile the set uses, and continuity at r = 0.2 and 0.4
+    def prof(x):
+        return np.where(x <= 0.2, 5.0 + 12.5 * x * x,
+                        np.where(x < 0.4, 9.0 + 12.5 * x * x - 20.0 * x
+                                 + 4.0 * np.log(np.maximum(5.0 * x, 1e-300)),
+                                 3.0 + 4.0 * math.log(2.0)))
+    assert np.allclose(P, prof(r), rtol=1e-13, atol=0)
+    for x in (0.05, 0.15, 0.25, 0.35, 0.45):
+        h = 1e-6
+        dP = (prof(x + h) - prof(x - h)) / (2 * h)
+        assert abs(dP - W.gresho_vphi(x) ** 2 / x) < 1e-6
+    for x in (0.2, 0.4):
+        assert abs(prof(x - 1e-12) - prof(x + 1e-12)) < 1e-9
+    assert abs(prof(0.0) - 5.0) < 1e-15
