@@ -782,8 +782,12 @@ int orc_face(const orc_params *p, int64_t n, int64_t i, int64_t j, const double 
     if (cnt) cnt->positivity++;
   }
   /* Boost into the frame of the face, v_frame = (v_i + v_j)/2, and project on
-   * the face normal (sec. 2.3.3). */
-  double vf[3] = {0.5 * (vx[i] + vx[j]), 0.5 * (vy[i] + vy[j]), 0.5 * (vz[i] + vz[j])};
+   * the face normal (sec. 2.3.3).  reading: v_i and v_j at the half step (the
+   * predicted velocities above), the time the fluxes stand for (eq.
+   * hydro_discr); with the start-of-step velocities the MFV sound wave
+   * (sec. 3.1.1) converges only at first order. */
+  double vf[3] = {0.5 * (qpi[Q_VX] + qpj[Q_VX]), 0.5 * (qpi[Q_VY] + qpj[Q_VY]),
+                  0.5 * (qpi[Q_VZ] + qpj[Q_VZ])};
   double wL[3], wR[3];
   for (int k = 0; k < 3; ++k) {
     wL[k] = qL[Q_VX + k] - vf[k];

@@ -494,6 +494,9 @@ __device__ void face_prepare(const FaceIn<T> &Ls, const FaceIn<T> &Rs, const Flu
     for (int k = 0; k < 3; ++k) {
       qL[1 + k] = qi[1 + k] - hdt * gi[12 + k] * Ls.irho;
       qR[1 + k] = qj[1 + k] - hdt * gj[12 + k] * Rs.irho;
+      // the face moves with the mean of the two particles' velocities at the
+      // half step, the time the fluxes stand for
+      fs.vf[k] = T(0.5) * (qL[1 + k] + qR[1 + k]);
     }
     qL[4] = qi[4] - hdt * G.gamma * qi[4] * dvi;
     qR[4] = qj[4] - hdt * G.gamma * qj[4] * dvj;
@@ -521,7 +524,6 @@ __device__ void face_prepare(const FaceIn<T> &Ls, const FaceIn<T> &Rs, const Flu
   }
 #pragma unroll
   for (int k = 0; k < 3; ++k) {
-    fs.vf[k] = T(0.5) * (qi[1 + k] + qj[1 + k]);
     fs.wL[k] = qL[1 + k] - fs.vf[k];
     fs.wR[k] = qR[1 + k] - fs.vf[k];
   }

@@ -5,12 +5,10 @@ limiter).  The error is the L1 norm of the density against each particle's
 own estimate at t = 0; ``paper_2211_12243_amd.validation`` documents why.
 
 Observed on MI355X (FP64, A = 1e-5, N = 16, 32, 64): MFM 1.48e-7, 2.74e-8,
-5.97e-9 (orders 2.43, 2.20); MFV 8.46e-7, 3.20e-7, 1.43e-7 (orders 1.40,
-1.16).  The paper reports second order for both schemes; here MFV converges
-at first order, and a four times smaller CFL factor lowers its error at high
-resolution by 2.4x, so its leading error is a first-order term in the time
-step.  The GPU path and the oracle agree on it step by step
-(test_gpu_multistep), so it belongs to the method as read, not to a kernel."""
+5.97e-9 (orders 2.43, 2.20); MFV 5.46e-7, 1.31e-7, 3.21e-8 (orders 2.06,
+2.02).  Both schemes converge at second order, as in the paper, once the
+face moves with the particles' mean velocity at the half step; with their
+start-of-step velocities MFV converged at first order (1.40, 1.16)."""
 import pytest
 
 torch = pytest.importorskip("torch")
@@ -51,12 +49,10 @@ def test_soundwave_mfm_mixed_tracks_fp64():
         assert abs(a["L1"] - b["L1"]) <= 0.05 * b["L1"], (a["L1"], b["L1"])
 
 
-def test_soundwave_mfv_converges():
-    """MFV: the error falls with resolution at first order or better (see the
-    module docstring for the gap to the paper's second order)."""
+def test_soundwave_mfv_is_second_order():
     res, orders = _series("mfv", "fp64", 1e-5, (16, 32, 64))
     print("orders", orders, flush=True)
-    assert all(o >= 0.9 for o in orders), orders
+    assert all(o >= 1.8 for o in orders), orders
 
 
 @pytest.mark.parametrize("scheme,bound", [("mfm", 0.012), ("mfv", 0.014)])
