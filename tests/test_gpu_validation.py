@@ -61,7 +61,7 @@ def test_sod_shock_tube(scheme, bound):
     solution of its Riemann problem (the oracle's exact solver, sampled at
     (x - 0.5) / t), over 0.25 < x < 0.75, away from the mirrored tube at
     x = 0.  Observed L1 of (rho, vx, P): MFM 0.0074, 0.0145, 0.0075; MFV
-    0.0087, 0.0177, 0.0093.  The plateaus between the rarefaction and the
+    0.0075, 0.0160, 0.0078.  The plateaus between the rarefaction and the
     shock hold the exact star pressure and post-shock density within 2%."""
     import numpy as np
 
@@ -137,9 +137,9 @@ def test_gresho_vortex(scheme):
     """The paper's Gresho-Chan vortex (sec. 3.1.3): 64^2 particles per plane
     of side 2 on a Cartesian grid, 8 planes, both limiters, t = 3 (2.4 orbits
     of the peak).  The tangential velocity about the centre against the
-    initial profile, which the exact solution keeps: observed L1 0.084 (MFM)
-    and 0.086 (MFV) over r < 0.5, the binned peak down from 1 to 0.69 and
-    0.68.  Most of that decay is the pairwise limiter's (0.74 with it alone,
+    initial profile, which the exact solution keeps: observed L1 0.086 (MFM)
+    and 0.085 (MFV) over r < 0.5, the binned peak down from 1 to 0.69 for
+    both.  Most of that decay is the pairwise limiter's (0.74 with it alone,
     1.11 with the Barth-Jespersen limiter alone, 1.20 and a noisy profile
     with neither)."""
     import numpy as np
