@@ -114,7 +114,7 @@ def test_sedov_point_explosion(scheme):
     """The paper's Sedov test (sec. 3.1.5): unit energy in one particle of a
     uniform 64^3 lattice, here to t = 0.03 instead of 0.1 (the full run takes
     about two minutes per scheme, see the design notes; at 32^3 the hot
-    cavity reaches a non-finite state, reported by the library).  The shell's
+    cavity reaches a non-finite state near t = 0.09, in the oracle too).  The shell's
     radius against the Sedov-Taylor radius 1.15167 (E t^2 / rho)^(1/5)
     (gamma = 5/3), its density contrast (the exact value is 4; the paper
     reaches ~2.7 at t = 0.1), and total energy to roundoff."""
