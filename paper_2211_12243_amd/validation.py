@@ -11,7 +11,12 @@ loops, sums the errors and keeps the clock.
 ``run_sod`` is its shock tube (sec. 3.1.2): the density jump set by the
 number density of equal-mass particles, N_NGB = 64, evolved to t = 0.13;
 it returns the particle fields for a comparison with the exact solution of
-the Riemann problem at x = 0.5.
+the Riemann problem at x = 0.5.  ``run_gresho`` is the Gresho-Chan vortex
+(sec. 3.1.3) to t = 3, returning the tangential velocity about the centre;
+``run_sedov`` the point explosion (sec. 3.1.5), returning the fields, the
+blast particle's start position and the total energy before and after.
+The reference solutions (exact Riemann problem, initial vortex profile,
+Sedov-Taylor radius) are left to the caller.
 
 For the sound wave, two L1 norms of the density are returned, both with
 rho_i from a density pass at the final positions:
