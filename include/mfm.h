@@ -137,7 +137,9 @@ typedef struct mfm_diag {
   int64_t singular_e;    /* particles with a singular E matrix */
   int64_t guess_fallback;/* learned guesses rejected for the plain one */
   int64_t fp64_inverse;  /* mixed path: E matrices inverted in FP64 */
-  int64_t pad[3];
+  int64_t u_guard;       /* particles whose updated internal energy was not positive; they
+                            keep their start-of-step value (mfm_update) */
+  int64_t pad[2];
   double mass, px, py, pz, energy; /* sums over particles of m, m v, E */
 } mfm_diag;
 
@@ -202,7 +204,9 @@ int mfm_fluxes(struct mfm_ctx *ctx, const mfm_particles *parts, const double *dt
 
 /* Close of the step, eq. hydro_discr and sec. 2.3.7: m += dQ_m, m v += dQ_p,
  * E += dQ_E, U += dQ_E - v.dQ_p + v^2/2 dQ_m, U := E - E_kin when
- * U > alpha1 E_kin, and the drift x += dt (v_old + v_new)/2 (periodic wrap). */
+ * E - E_kin > alpha1 E_kin, and the drift x += dt (v_old + v_new)/2
+ * (periodic wrap).  An internal energy that would not be positive keeps its
+ * start-of-step value (counted in mfm_diag.u_guard). */
 int mfm_update(struct mfm_ctx *ctx, const mfm_particles *parts, const double *dt_dev);
 
 /* One full step: cells, density, gradients, fluxes, update.  dt_host receives

@@ -12,6 +12,7 @@ Pins (what fixes each function independently of itself) are in
 """
 from __future__ import annotations
 
+import contextlib
 import ctypes
 import os
 import subprocess
@@ -52,7 +53,8 @@ class Params(ctypes.Structure):
 class Counters(ctypes.Structure):
     _fields_ = [(k, ctypes.c_int64) for k in (
         "h_noconv", "ncond_boosts", "ncond_fail", "h_fallback", "grad_pairs", "faces",
-        "riemann_iters", "riemann_maxit", "vacuum", "positivity", "neg_mass", "singular_e")]
+        "riemann_iters", "riemann_maxit", "vacuum", "positivity", "neg_mass", "singular_e",
+        "u_guard")]
 
     def as_dict(self):
         return {k: int(getattr(self, k)) for k, _ in self._fields_}
@@ -93,27 +95,64 @@ def lib():
     if _lib is None:
         if not os.path.exists(_LIB):
             build(force=False)
-        L = ctypes.CDLL(_LIB)
-        P = ctypes.POINTER(Params)
-        C = ctypes.POINTER(Counters)
-        i64 = ctypes.c_int64
-        L.orc_kernel_W.restype = ctypes.c_double
-        L.orc_kernel_W.argtypes = [ctypes.c_double, ctypes.c_double]
-        L.orc_neighbours.argtypes = [P, i64, _D, _D, _D, _D, ctypes.c_int, _I64, _I32]
-        L.orc_density.argtypes = [P, i64, _D, _D, _D, _D, _D, _D, _D, C]
-        L.orc_gradients.argtypes = [P, i64] + [_D] * 10 + [_D] * 8 + [C]
-        L.orc_riemann.argtypes = [ctypes.c_double] * 8 + [ctypes.c_int, _D, _D,
-                                                            ctypes.POINTER(ctypes.c_int)]
-        L.orc_riemann_sample.argtypes = [ctypes.c_double] * 10 + [_D, _D, _D]
-        L.orc_face.argtypes = [P, i64, i64, i64] + [_D] * 12 + [ctypes.c_double, _D, C]
-        L.orc_fluxes.argtypes = [P, i64] + [_D] * 12 + [ctypes.c_double, _D, _D, C]
-        L.orc_update.argtypes = [P, i64] + [_D] * 9 + [_D, ctypes.c_double, C]
-        L.orc_step.argtypes = [P, i64] + [_D] * 10 + [ctypes.c_double, _D, C]
-        for f in ("orc_neighbours", "orc_density", "orc_gradients", "orc_riemann",
-                  "orc_riemann_sample", "orc_face", "orc_fluxes", "orc_update", "orc_step"):
-            getattr(L, f).restype = ctypes.c_int
-        _lib = L
+        _lib = _bind(ctypes.CDLL(_LIB))
     return _lib
+
+
+@contextlib.contextmanager
+def use_library(path: str):
+    """Run the oracle from another build of its source (the mutation tests
+    check that the pins reject deliberately broken copies)."""
+    global _lib
+    saved = lib()
+    _lib = _bind(ctypes.CDLL(path))
+    try:
+        yield
+    finally:
+        _lib = saved
+
+
+def build_variant(src_text: str, out_path: str) -> str:
+    """Compile C source text with the oracle's flags into out_path."""
+    src = out_path + ".c"
+    with open(src, "w") as fh:
+        fh.write(src_text)
+    subprocess.check_call(
+        ["gcc", "-O2", "-std=c11", "-fopenmp", "-fPIC", "-shared", "-fno-fast-math",
+         "-ffp-contract=off", "-I", _HERE, "-o", out_path, src, "-lm"])
+    return out_path
+
+
+def source() -> str:
+    with open(_SRC) as fh:
+        return fh.read()
+
+
+def _bind(L):
+    """Declare the argument and result types of the oracle's C functions."""
+    P = ctypes.POINTER(Params)
+    C = ctypes.POINTER(Counters)
+    i64 = ctypes.c_int64
+    L.orc_kernel_W.restype = ctypes.c_double
+    L.orc_kernel_W.argtypes = [ctypes.c_double, ctypes.c_double]
+    L.orc_neighbours.argtypes = [P, i64, _D, _D, _D, _D, ctypes.c_int, _I64, _I32]
+    L.orc_density.argtypes = [P, i64, _D, _D, _D, _D, _D, _D, _D, C]
+    L.orc_gradients.argtypes = [P, i64] + [_D] * 10 + [_D] * 8 + [C]
+    L.orc_riemann.argtypes = [ctypes.c_double] * 8 + [ctypes.c_int, _D, _D,
+                                                        ctypes.POINTER(ctypes.c_int)]
+    L.orc_riemann_sample.argtypes = [ctypes.c_double] * 10 + [_D, _D, _D]
+    L.orc_face_list_copy.argtypes = [P, i64, _D, _D, _D, _D, i64, _I64, _I64, _I64]
+    L.orc_face_list_copy.restype = ctypes.c_int
+    L.orc_pair_limit.restype = ctypes.c_double
+    L.orc_pair_limit.argtypes = [ctypes.c_double] * 5
+    L.orc_face.argtypes = [P, i64, i64, i64] + [_D] * 12 + [ctypes.c_double, _D, C]
+    L.orc_fluxes.argtypes = [P, i64] + [_D] * 12 + [ctypes.c_double, _D, _D, C]
+    L.orc_update.argtypes = [P, i64] + [_D] * 9 + [_D, ctypes.c_double, C]
+    L.orc_step.argtypes = [P, i64] + [_D] * 10 + [ctypes.c_double, _D, C]
+    for f in ("orc_neighbours", "orc_density", "orc_gradients", "orc_riemann",
+              "orc_riemann_sample", "orc_face", "orc_fluxes", "orc_update", "orc_step"):
+        getattr(L, f).restype = ctypes.c_int
+    return L
 
 
 def _p(a):
@@ -197,6 +236,11 @@ def riemann_sample(gamma, rhoL, uL, PL, rhoR, uR, PR, ps, us, xi):
     return r.value, u.value, P.value
 
 
+def pair_limit(qf, qo, qn, psi1=0.5, psi2=0.25):
+    """Pairwise limiter of face value qf from the own side qo towards qn (sec. 2.3.6)."""
+    return lib().orc_pair_limit(float(qf), float(qo), float(qn), float(psi1), float(psi2))
+
+
 def face(cfg: dict, i, j, x, y, z, H, V, rho, vx, vy, vz, P, B, grad, dt):
     """Contribution c = |A_ij| F_ij of one face, oriented from i to j."""
     p = make_params(cfg)
@@ -209,6 +253,23 @@ def face(cfg: dict, i, j, x, y, z, H, V, rho, vx, vy, vz, P, B, grad, dt):
     lib().orc_face(ctypes.byref(p), n, int(i), int(j), *[_p(a) for a in arrs], _p(B), _p(grad),
                    float(dt), _p(c), ctypes.byref(cnt))
     return c, cnt.as_dict()
+
+
+def fluxes_face_list(cfg: dict, x, y, z, H):
+    """The flux loop's faces {i, j}, r_ij < max(H_i, H_j), as (lower, higher) index arrays."""
+    p = make_params(cfg)
+    x, y, z, H = (_f64(a) for a in (x, y, z, H))
+    nf = ctypes.c_int64()
+    L = lib()
+    rc = L.orc_face_list_copy(ctypes.byref(p), x.size, _p(x), _p(y), _p(z), _p(H), 0, None,
+                              None, ctypes.byref(nf))
+    assert rc == 0
+    fa = np.zeros(max(nf.value, 1), dtype=np.int64)
+    fb = np.zeros(max(nf.value, 1), dtype=np.int64)
+    rc = L.orc_face_list_copy(ctypes.byref(p), x.size, _p(x), _p(y), _p(z), _p(H), nf.value,
+                              fa.ctypes.data_as(_I64), fb.ctypes.data_as(_I64), ctypes.byref(nf))
+    assert rc == 0
+    return fa[:nf.value], fb[:nf.value]
 
 
 def fluxes(cfg: dict, x, y, z, H, V, rho, vx, vy, vz, P, B, grad, dt):

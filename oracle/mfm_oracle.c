@@ -127,6 +127,15 @@ static void grid_free(orc_grid *g) {
   free(g->cell_idx);
 }
 
+/* Operation counting: oracle/opcount.cpp compiles this file with a counting
+ * number type and defines these two hooks, so that the arithmetic of the
+ * candidate scans is attributed to the neighbour search and not to the loop
+ * that called it.  In the plain build they do nothing. */
+#ifndef ORC_SEARCH_BEGIN
+#define ORC_SEARCH_BEGIN()
+#define ORC_SEARCH_END()
+#endif
+
 /* Visit the candidates of particle i.  The visitor returns nothing; it sees j
  * and the exact minimum-image separation. */
 typedef void (*visit_fn)(void *ctx, int64_t j, const double d[3], double r2);
@@ -135,11 +144,13 @@ static void for_candidates(const orc_params *p, int64_t n, const double *x, cons
                            const double *z, const orc_grid *g, int use_grid, int64_t i,
                            visit_fn f, void *ctx) {
   double d[3];
+  ORC_SEARCH_BEGIN();
   if (!use_grid) {
     for (int64_t j = 0; j < n; ++j) {
       separation(p, x, y, z, i, j, d);
       f(ctx, j, d, d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
     }
+    ORC_SEARCH_END();
     return;
   }
   const double *pos[3] = {x, y, z};
@@ -162,6 +173,7 @@ static void for_candidates(const orc_params *p, int64_t n, const double *x, cons
           f(ctx, j, d, d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
         }
       }
+  ORC_SEARCH_END();
 }
 
 typedef struct {
@@ -691,7 +703,7 @@ int orc_riemann_sample(double gam, double rhoL, double uL, double PL, double rho
  * (value qn) may overshoot the midpoint by at most psi_2 |qo - qn| and the
  * pair minimum / maximum by psi_1 |qo - qn| (a sign-preserving ratio when that
  * would cross zero). */
-static double pair_limit(double qf, double qo, double qn, double psi1, double psi2) {
+double orc_pair_limit(double qf, double qo, double qn, double psi1, double psi2) {
   if (qo == qn) return qo;
   double dq = fabs(qo - qn);
   double d1 = psi1 * dq, d2 = psi2 * dq;
@@ -768,8 +780,8 @@ int orc_face(const orc_params *p, int64_t n, int64_t i, int64_t j, const double 
   }
   if (p->limiter & 2) {
     for (int q = 0; q < NQ; ++q) {
-      qL[q] = pair_limit(qL[q], qi[q], qj[q], p->psi1, p->psi2);
-      qR[q] = pair_limit(qR[q], qj[q], qi[q], p->psi1, p->psi2);
+      qL[q] = orc_pair_limit(qL[q], qi[q], qj[q], p->psi1, p->psi2);
+      qR[q] = orc_pair_limit(qR[q], qj[q], qi[q], p->psi1, p->psi2);
     }
   }
   /* reading: a non-positive reconstructed density or pressure falls back to
@@ -838,12 +850,10 @@ int orc_face(const orc_params *p, int64_t n, int64_t i, int64_t j, const double 
   return 0;
 }
 
-int orc_fluxes(const orc_params *p, int64_t n, const double *x, const double *y,
-               const double *z, const double *H, const double *V, const double *rho,
-               const double *vx, const double *vy, const double *vz, const double *P,
-               const double *B, const double *grad, double dt, double *dQ, double *scale,
-               orc_counters *cnt) {
-  if (!p || n <= 0) return -1;
+int orc_face_list(const orc_params *p, int64_t n, const double *x, const double *y,
+                  const double *z, const double *H, int64_t *nf_out, int64_t **fa_out,
+                  int64_t **fb_out) {
+  if (!p || n <= 0 || !nf_out || !fa_out || !fb_out) return -1;
   int64_t *start;
   int32_t *idx;
   if (build_lists(p, n, x, y, z, H, &start, &idx)) return -2;
@@ -867,7 +877,6 @@ int orc_fluxes(const orc_params *p, int64_t n, const double *x, const double *y,
   int64_t nf = fcount[n];
   int64_t *fa = (int64_t *)malloc((size_t)(nf > 0 ? nf : 1) * sizeof(int64_t));
   int64_t *fb = (int64_t *)malloc((size_t)(nf > 0 ? nf : 1) * sizeof(int64_t));
-  double *fc = (double *)malloc((size_t)(nf > 0 ? nf : 1) * 5 * sizeof(double));
 #pragma omp parallel for schedule(dynamic, 256)
   for (int64_t i = 0; i < n; ++i) {
     int64_t f = fcount[i];
@@ -886,6 +895,40 @@ int orc_fluxes(const orc_params *p, int64_t n, const double *x, const double *y,
   }
   free(start);
   free(idx);
+  free(fcount);
+  *nf_out = nf;
+  *fa_out = fa;
+  *fb_out = fb;
+  return 0;
+}
+
+int orc_face_list_copy(const orc_params *p, int64_t n, const double *x, const double *y,
+                       const double *z, const double *H, int64_t cap, int64_t *fa,
+                       int64_t *fb, int64_t *nf_out) {
+  int64_t nf, *a, *b;
+  int rc = orc_face_list(p, n, x, y, z, H, &nf, &a, &b);
+  if (rc) return rc;
+  *nf_out = nf;
+  if (fa && fb)
+    for (int64_t f = 0; f < nf && f < cap; ++f) {
+      fa[f] = a[f];
+      fb[f] = b[f];
+    }
+  free(a);
+  free(b);
+  return 0;
+}
+
+int orc_fluxes(const orc_params *p, int64_t n, const double *x, const double *y,
+               const double *z, const double *H, const double *V, const double *rho,
+               const double *vx, const double *vy, const double *vz, const double *P,
+               const double *B, const double *grad, double dt, double *dQ, double *scale,
+               orc_counters *cnt) {
+  if (!p || n <= 0) return -1;
+  int64_t nf, *fa, *fb;
+  int rc = orc_face_list(p, n, x, y, z, H, &nf, &fa, &fb);
+  if (rc) return rc;
+  double *fc = (double *)malloc((size_t)(nf > 0 ? nf : 1) * 5 * sizeof(double));
   /* Each face once; counters are per-thread then summed. */
   int64_t iters = 0, vac = 0, pos = 0, mx = 0;
 #pragma omp parallel for schedule(dynamic, 1024) reduction(+ : iters, vac, pos, mx)
@@ -918,7 +961,6 @@ int orc_fluxes(const orc_params *p, int64_t n, const double *x, const double *y,
   free(fa);
   free(fb);
   free(fc);
-  free(fcount);
   cnt->faces += nf;
   cnt->riemann_iters += iters;
   cnt->vacuum += vac;
@@ -935,7 +977,7 @@ int orc_update(const orc_params *p, int64_t n, double *x, double *y, double *z, 
                double dt, orc_counters *cnt) {
   if (!p || n <= 0) return -1;
   double *pos[3] = {x, y, z};
-  int64_t neg = 0;
+  int64_t neg = 0, guard = 0;
   for (int64_t i = 0; i < n; ++i) {
     double dm = dQ[i], dp[3] = {dQ[n + i], dQ[2 * n + i], dQ[3 * n + i]}, dE = dQ[4 * n + i];
     double v0[3] = {vx[i], vy[i], vz[i]};
@@ -949,10 +991,24 @@ int orc_update(const orc_params *p, int64_t n, double *x, double *y, double *z, 
     double E1 = E[i] + dE;
     double U1 = U[i] + dU;
     /* Pressure switch (sec. 2.3.7) without gravity and with the entropy branch
-     * off: when U exceeds alpha_1 E_kin the internal energy is recovered from
-     * the total energy, otherwise the integrated U is kept. */
+     * off: the internal energy is recovered from the total energy when it is
+     * not small against the kinetic energy, otherwise the integrated U is
+     * kept.  reading: the test of criterion (i) is made on the internal
+     * energy the total energy gives, E - E_kin > alpha_1 E_kin (the
+     * dual-energy test of the method the section cites).  Tested on the
+     * integrated U instead, a particle whose momentum changes by more than
+     * its integrated internal energy allows (|dP|^2 / 2m > U) is handed a
+     * negative E - E_kin, hence a negative pressure. */
     double ekin = (p1[0] * p1[0] + p1[1] * p1[1] + p1[2] * p1[2]) / (2.0 * m1);
-    if (U1 > p->alpha1 * ekin) U1 = E1 - ekin;
+    if (E1 - ekin > p->alpha1 * ekin) U1 = E1 - ekin;
+    /* reading: where the kinetic energy dominates, dE ~ v.dP and the
+     * integrated U can be driven through zero by that noise (the section
+     * names the regime); the internal energy then keeps its value from the
+     * start of the step (counted), so the pressure stays positive. */
+    if (!(U1 > 0.0)) {
+      U1 = U[i];
+      guard++;
+    }
     /* reading: drift with the mean of the old and new velocities, periodic wrap */
     for (int k = 0; k < 3; ++k) {
       double xn = pos[k][i] + dt * 0.5 * (v0[k] + v1[k]);
@@ -971,6 +1027,7 @@ int orc_update(const orc_params *p, int64_t n, double *x, double *y, double *z, 
     U[i] = U1;
   }
   cnt->neg_mass += neg;
+  cnt->u_guard += guard;
   return 0;
 }
 

@@ -57,6 +57,7 @@ typedef struct {
   int64_t positivity;    /* faces that fell back to first-order states */
   int64_t neg_mass;      /* MFV particles whose mass became non-positive */
   int64_t singular_e;    /* particles with a singular E matrix */
+  int64_t u_guard;       /* particles whose new internal energy was not positive (kept) */
 } orc_counters;
 
 /* The cubic-spline kernel W(r, H) with compact support H (sec. 2.3.2). */
@@ -99,6 +100,10 @@ int orc_riemann_sample(double gamma, double rhoL, double uL, double PL, double r
                        double PR, double pstar, double ustar, double xi, double *rho, double *u,
                        double *P);
 
+/* Pairwise limiter of a face value qf extrapolated from the own side (value
+ * qo) towards the other side (value qn), sec. 2.3.6 with psi_1, psi_2. */
+double orc_pair_limit(double qf, double qo, double qn, double psi1, double psi2);
+
 /* The flux of one face (i, j) as the oracle computes it: contribution vector
  * c = |A_ij| F_ij (5 components) oriented from i (left) to j (right). */
 int orc_face(const orc_params *p, int64_t n, int64_t i, int64_t j, const double *x,
@@ -106,6 +111,17 @@ int orc_face(const orc_params *p, int64_t n, int64_t i, int64_t j, const double 
              const double *rho, const double *vx, const double *vy, const double *vz,
              const double *P, const double *B, const double *grad, double dt, double *c,
              orc_counters *cnt);
+
+/* The flux loop's faces: every unordered pair {i, j} with r_ij < max(H_i, H_j),
+ * as (lower index, higher index).  orc_face_list allocates fa and fb (free
+ * them); orc_face_list_copy copies at most cap faces into caller arrays and
+ * returns the total in nf_out (call with fa = fb = NULL to size them). */
+int orc_face_list(const orc_params *p, int64_t n, const double *x, const double *y,
+                  const double *z, const double *H, int64_t *nf_out, int64_t **fa_out,
+                  int64_t **fb_out);
+int orc_face_list_copy(const orc_params *p, int64_t n, const double *x, const double *y,
+                       const double *z, const double *H, int64_t cap, int64_t *fa,
+                       int64_t *fb, int64_t *nf_out);
 
 /* Flux loop (sec. 2.3.3, 2.3.4, 2.3.6): for every unordered pair with
  * r_ij < max(H_i, H_j), dQ_i -= dt c_ij and dQ_j += dt c_ij.

@@ -461,7 +461,7 @@ int mfm_diagnostics(mfm_ctx *ctx, const mfm_particles *pp, mfm_diag *out) {
   int rc = read_counters(ctx, c);
   if (rc) return rc;
   int64_t *dst = &out->h_noconv;
-  for (int k = 0; k <= C_FP64_INVERSE; ++k) dst[k] = c[k];
+  for (int k = 0; k <= C_U_GUARD; ++k) dst[k] = c[k];
   if (pp) {
     out->mass = sums[0];
     out->px = sums[1];

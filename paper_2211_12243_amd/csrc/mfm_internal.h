@@ -27,6 +27,7 @@ enum {
   C_SINGULAR_E,
   C_GUESS_FALLBACK,
   C_FP64_INVERSE,
+  C_U_GUARD,
   C_CELL_OVERFLOW,  // internal: some H reached the cell side in the last density pass
   C_NONFINITE,      // internal: non-finite dt or state
   // counts of the density pass in flight; folded into the slots above only

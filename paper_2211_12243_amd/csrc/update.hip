@@ -19,7 +19,7 @@ struct UpdateArgs {
 
 __global__ void __launch_bounds__(BS) update_k(UpdateArgs a) {
   const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  int64_t neg = 0, bad = 0;
+  int64_t neg = 0, bad = 0, guard = 0;
   if (i < a.n) {
     const int64_t n = a.n;
     const double dt = a.dt[0];
@@ -35,8 +35,17 @@ __global__ void __launch_bounds__(BS) update_k(UpdateArgs a) {
     const double v1x = px / m1, v1y = py / m1, v1z = pz / m1;
     const double E1 = a.E[i] + dE;
     double U1 = a.U[i] + dU;
+    // dual-energy switch: U from the total energy when E - E_kin is not small
+    // against E_kin (the test is made on E - E_kin itself, so the recovered
+    // internal energy is positive), else the integrated U
     const double ekin = (px * px + py * py + pz * pz) / (2.0 * m1);
-    if (U1 > a.alpha1 * ekin) U1 = E1 - ekin;
+    if (E1 - ekin > a.alpha1 * ekin) U1 = E1 - ekin;
+    // where kinetic energy dominates, the noise of dE - v.dP can drive the
+    // integrated U through zero: it then keeps its start-of-step value
+    if (!(U1 > 0.0)) {
+      U1 = a.U[i];
+      guard = 1;
+    }
     double xn[3] = {a.x[i] + dt * 0.5 * (v0x + v1x), a.y[i] + dt * 0.5 * (v0y + v1y),
                     a.z[i] + dt * 0.5 * (v0z + v1z)};
 #pragma unroll
@@ -57,6 +66,7 @@ __global__ void __launch_bounds__(BS) update_k(UpdateArgs a) {
   }
   count_add(a.counters + C_NEG_MASS, neg);
   count_add(a.counters + C_NONFINITE, bad);
+  count_add(a.counters + C_U_GUARD, guard);
 }
 
 // Partial sums of (m, m vx, m vy, m vz, E) per block.

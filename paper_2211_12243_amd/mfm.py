@@ -52,11 +52,11 @@ class mfm_particles(ctypes.Structure):
 
 _DIAG_INT = ("h_noconv", "ncond_boosts", "ncond_fail", "cell_rebuilds", "list_overflow",
              "grad_pairs", "faces", "riemann_iters", "riemann_maxit", "vacuum", "positivity",
-             "neg_mass", "singular_e", "guess_fallback", "fp64_inverse")
+             "neg_mass", "singular_e", "guess_fallback", "fp64_inverse", "u_guard")
 
 
 class mfm_diag(ctypes.Structure):
-    _fields_ = ([(k, ctypes.c_int64) for k in _DIAG_INT] + [("pad", ctypes.c_int64 * 3)]
+    _fields_ = ([(k, ctypes.c_int64) for k in _DIAG_INT] + [("pad", ctypes.c_int64 * 2)]
                 + [(k, ctypes.c_double) for k in ("mass", "px", "py", "pz", "energy")])
 
     def as_dict(self):

@@ -1,0 +1,83 @@
+"""The pins of test_oracle_pins.py must reject a plausible mistake in each
+reading they pin.  Each case copies the oracle's C source, plants one mistake
+by a textual edit, builds the copy with the oracle's flags, and runs the pin
+that must catch it against that copy (the real oracle is untouched).
+"""
+import math
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+import test_oracle_pins as pins
+
+
+def _mutant(tmp_path, name, edits):
+    src = oracle.source()
+    for old, new in edits:
+        assert src.count(old) >= 1, (name, old)
+        src = src.replace(old, new)
+    return oracle.build_variant(src, str(tmp_path / f"liborc_{name}.so"))
+
+
+SWAP_PSI = [("qL[q] = orc_pair_limit(qL[q], qi[q], qj[q], p->psi1, p->psi2);",
+             "qL[q] = orc_pair_limit(qL[q], qi[q], qj[q], p->psi2, p->psi1);"),
+            ("qR[q] = orc_pair_limit(qR[q], qj[q], qi[q], p->psi1, p->psi2);",
+             "qR[q] = orc_pair_limit(qR[q], qj[q], qi[q], p->psi2, p->psi1);")]
+SWAP_PSI_INSIDE = [("double d1 = psi1 * dq, d2 = psi2 * dq;",
+                    "double d1 = psi2 * dq, d2 = psi1 * dq;")]
+NO_PREDICTOR = [("0.5 * dt * ", "0.0 * dt * ")]
+START_FRAME = [("double vf[3] = {0.5 * (qpi[Q_VX] + qpj[Q_VX]), 0.5 * (qpi[Q_VY] + qpj[Q_VY]),",
+                "double vf[3] = {0.5 * (qi[Q_VX] + qj[Q_VX]), 0.5 * (qi[Q_VY] + qj[Q_VY]),"),
+               ("0.5 * (qpi[Q_VZ] + qpj[Q_VZ])};", "0.5 * (qi[Q_VZ] + qj[Q_VZ])};")]
+WRONG_UPWIND = [("const double *wu = (us >= 0.0) ? wL : wR;",
+                 "const double *wu = (us >= 0.0) ? wR : wL;")]
+BETA_INVERTED = [("double t = (p->ncond_max - nc) / (p->ncond_max - 1.0);",
+                  "double t = (nc - 1.0) / (p->ncond_max - 1.0);")]
+NO_HALF = [("double ex = 0.5 * (g[q][0] * d[0]", "double ex = 1.0 * (g[q][0] * d[0]")]
+
+
+def test_swapped_psi_at_the_face_is_caught(tmp_path):
+    with oracle.use_library(_mutant(tmp_path, "swap_psi", SWAP_PSI)):
+        with pytest.raises(AssertionError):
+            pins.test_face_uses_the_pair_limited_states()
+
+
+def test_swapped_psi_in_the_limiter_is_caught(tmp_path):
+    with oracle.use_library(_mutant(tmp_path, "swap_psi_inside", SWAP_PSI_INSIDE)):
+        with pytest.raises(AssertionError):
+            pins.test_pair_limiter_branches(*pins.PAIR_CASES[0])
+
+
+def test_wrong_upwind_side_is_caught(tmp_path):
+    with oracle.use_library(_mutant(tmp_path, "upwind", WRONG_UPWIND)):
+        with pytest.raises(AssertionError):
+            pins.test_mfv_face_flux_is_the_moving_surface_flux(*pins.FACE_STATES[0])
+
+
+def test_inverted_beta_ramp_is_caught(tmp_path):
+    with oracle.use_library(_mutant(tmp_path, "beta", BETA_INVERTED)):
+        with pytest.raises(AssertionError):
+            pins.test_conditioned_bj_limiter_by_hand(0.14, (20.0, 80.0))
+
+
+def test_full_step_extrapolation_in_the_limiter_is_caught(tmp_path):
+    with oracle.use_library(_mutant(tmp_path, "nohalf", NO_HALF)):
+        with pytest.raises(AssertionError):
+            pins.test_conditioned_bj_limiter_by_hand(0.1, (1.0, 1.0))
+
+
+def _order(scheme):
+    e16, _ = pins.oracle_soundwave_L1(16, scheme)
+    e32, _ = pins.oracle_soundwave_L1(32, scheme)
+    return math.log2(e16 / e32)
+
+
+@pytest.mark.parametrize("name,edits", [("no_predictor", NO_PREDICTOR),
+                                        ("start_of_step_frame", START_FRAME)])
+def test_first_order_time_integration_is_caught(tmp_path, name, edits):
+    with oracle.use_library(_mutant(tmp_path, name, edits)):
+        order = _order("mfv")
+    print(name, f"MFV order {order:.2f}")
+    assert order < 1.8
