@@ -93,6 +93,11 @@ typedef struct mfm_params {
                             max(H_i, H_j) at the build */
   int32_t max_cell_dim;  /* cells per axis at most (3..512, default 256) */
   int32_t pad0;
+  double mixed_jump;     /* mixed path: a face whose two particles' pressures or densities
+                            differ by more than this factor is computed in FP64 (in the flux
+                            loop's second pass); default 8, 0 = none.  Across strong jumps the
+                            FP32 face arithmetic loses accuracy (cancelling extrapolations,
+                            strong shocks and rarefactions) */
 } mfm_params;
 
 /* The particle set: device pointers, each of n FP64 values (B: 6n, grad: 15n,
@@ -139,7 +144,10 @@ typedef struct mfm_diag {
   int64_t fp64_inverse;  /* mixed path: E matrices inverted in FP64 */
   int64_t u_guard;       /* particles whose updated internal energy was not positive; they
                             keep their start-of-step value (mfm_update) */
-  int64_t pad[2];
+  int64_t hard_faces;    /* faces solved in the flux loop's FP64 second pass (mixed_jump,
+                            learned guess) */
+  int64_t hard_overflow; /* faces that found the second pass's queue full and were solved in
+                            the first pass */
   double mass, px, py, pz, energy; /* sums over particles of m, m v, E */
 } mfm_diag;
 
@@ -221,9 +229,10 @@ int mfm_reset_counters(struct mfm_ctx *ctx);
 /* Kernel timing on the context's stream with HIP events.  While enabled every
  * launch of the loops is bracketed by events; mfm_kernel_times (synchronises)
  * returns, per stage (0 cells, 1 neighbour search, 2 density, 3 gradients,
- * 4 fluxes, 5 update), the summed milliseconds and launch counts since
- * enabling. */
-#define MFM_NSTAGES 6
+ * 4 fluxes: the whole flux loop, 5 update, 6 the flux loop's first-pass
+ * kernel alone, 7 its FP64 second pass alone), the summed milliseconds and
+ * launch counts since enabling. */
+#define MFM_NSTAGES 8
 int mfm_enable_timing(struct mfm_ctx *ctx, int on);
 int mfm_kernel_times(struct mfm_ctx *ctx, double *ms_out, int64_t *count_out);
 

@@ -76,6 +76,15 @@ struct FluxArgs {
   float *dump;              // face records (null: off)
   int64_t dump_cap;
   unsigned long long *dump_count;
+  // the FP64 second pass: faces the first pass hands over
+  int2 *hard_q;             // (lower, higher) slot of each queued face
+  int64_t hard_cap;
+  unsigned long long *hard_count;
+  float jump;               // mixed path: pressure or density ratio that sends a face to FP64
+  // the caller's FP64 particle arrays, which the second pass reads in place of
+  // the mixed path's FP32 record (near the edge of the support, W(r, H) moves
+  // by 3 (1 - r/H)^-1 times the relative error of 1/H)
+  const double *x, *y, *z, *H, *V, *rho, *vx, *vy, *vz, *P;
 };
 
 template <typename T>
@@ -605,12 +614,35 @@ __device__ __forceinline__ void features_of(const FaceState<T> &fs, float x[mlp:
                      (float)fs.SR.r, (float)fs.SR.u, (float)fs.SR.p, (float)fs.SR.c, x);
 }
 
+// Faces the first pass hands to the FP64 second pass, judged (besides the
+// particles' own jump) on the face states it has reconstructed.  Mixed path:
+// their pressures or densities differ by more than a.jump, or the face fell
+// back to first-order states -- where FP32 extrapolations cancel and the
+// Riemann problem is strongest.
+// Learned guess: a superset of the network's gate (pressure ratio above 1.9
+// or a normal velocity jump above 0.48 of the mean sound speed, against 2 and
+// 0.5 in the gate itself); the second pass applies the exact gate.
+template <typename T, bool LEARNED>
+__device__ __forceinline__ bool hand_over(const FaceState<T> &fs, const FluxArgs &a) {
+  if (fs.skip) return false;
+  const T pL = fs.SL.p, pR = fs.SR.p;
+  bool h = false;
+  if (sizeof(T) == sizeof(float) && a.jump > 0.0f) {
+    const T J = T(a.jump);
+    h = fmax(pL, pR) > J * fmin(pL, pR) || fmax(fs.SL.r, fs.SR.r) > J * fmin(fs.SL.r, fs.SR.r) ||
+        (fs.flags & F_POSITIVITY);
+  }
+  if (LEARNED)
+    h = h || pL > T(1.9) * pR || pR > T(1.9) * pL ||
+        fabs(fs.SR.u - fs.SL.u) > T(0.24) * (fs.SL.c + fs.SR.c);
+  return h;
+}
+
 template <typename T, int SCHEME, int M, bool LEARNED>
 __global__ void __launch_bounds__(FTH) __attribute__((amdgpu_waves_per_eu(2))) fluxes_k(FluxArgs a) {
   __shared__ int pref[FBS + 1];
   __shared__ int wsum[FTH / 64];
   __shared__ double acc[5][FBS];
-  __shared__ uint16_t mlp_act[LEARNED ? (FTH / 64) * 16 * mlp::AST : 1];
   const int64_t n = a.n;
   const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
   const int b0 = xcd_block(blockIdx.x, gridDim.x) * FBS;
@@ -647,7 +679,7 @@ __global__ void __launch_bounds__(FTH) __attribute__((amdgpu_waves_per_eu(2))) f
   const int T_faces = pref[FBS];
   const double dt = a.dt[0];
   const T hdt = T(0.5 * dt);
-  int64_t nfaces = 0, iters_sum = 0, vac = 0, pos = 0, maxit = 0, fb = 0;
+  int64_t nfaces = 0, iters_sum = 0, vac = 0, pos = 0, maxit = 0, fb = 0, overflow = 0;
   // face f of the block: its particle p (pref[p] <= f < pref[p + 1]) and its
   // partner j, found one round ahead so that the partner's load is in flight
   // while the current face is solved
@@ -675,51 +707,53 @@ __global__ void __launch_bounds__(FTH) __attribute__((amdgpu_waves_per_eu(2))) f
     FaceState<T> fs;
     fs.skip = true;
     fs.flags = 0;
+    bool defer = false;
+    int Lslot = 0, Rslot = 0;
     if (active) {
       i = b0 + p;
-      const int L = i < j ? i : j, R = i < j ? j : i;
+      Lslot = i < j ? i : j;
+      Rslot = i < j ? j : i;
       FaceIn<T> Ls, Rs;
-      load_side(a, L, Ls);
-      load_side(a, R, Rs);
-      face_prepare<T>(Ls, Rs, a, hdt, fs);
-    }
-    T p_learned = T(0);
-    if (LEARNED) {
-      // the wavefront evaluates the network on the 16-face tiles that hold a
-      // face needing it (wave-uniform branches; other waves skip it)
-      float x[mlp::NIN];
-      bool hard = false;
-      // a cheap superset of the gate first (pressure ratio above 1.9 or
-      // |du| above 0.48 c_avg), then the exact gate on the features
-      if (active && !fs.skip &&
-          (fs.SL.p > T(1.9) * fs.SR.p || fs.SR.p > T(1.9) * fs.SL.p ||
-           fabs(fs.SR.u - fs.SL.u) > T(0.24) * (fs.SL.c + fs.SR.c))) {
-        features_of<T>(fs, x);
-        hard = mlp::needs_guess(x);
+      load_side(a, Lslot, Ls);
+      load_side(a, Rslot, Rs);
+      // the particles' own jump (mixed path): where it is strong the face's
+      // FP32 extrapolations and predictor lose accuracy even when the
+      // reconstructed states have come close
+      if (sizeof(T) == sizeof(float) && a.jump > 0.0f) {
+        const T J = T(a.jump);
+        defer = fmax(Ls.P, Rs.P) > J * fmin(Ls.P, Rs.P) ||
+                fmax(Ls.rho, Rs.rho) > J * fmin(Ls.rho, Rs.rho);
       }
-      const uint64_t hmask = __ballot(hard);
-      if (hmask) {
-        uint16_t *tile = mlp_act + wid * 16 * mlp::AST;
-        float y = 0.f;
-#pragma unroll 1
-        for (int mt = 0; mt < 4; ++mt) {
-          if (((hmask >> (16 * mt)) & 0xffffull) == 0) continue;
-          if ((lane >> 4) == mt) mlp::put_input(tile, lane & 15, hard ? x : nullptr, a.net.norm);
-          const float yt = mlp::forward_tile_call(tile, a.net.wt, a.net.p, a.net.norm, lane);
-          if ((lane >> 4) == mt) y = yt;
-        }
-        if (hard) {
-          p_learned = T(0.5) * (fs.SL.p + fs.SR.p) * T(expf(y));
-          if (!(p_learned > T(0))) p_learned = T(-1);  // rejected below
+      face_prepare<T>(Ls, Rs, a, hdt, fs);
+      if (LEARNED || sizeof(T) == sizeof(float)) defer = defer || hand_over<T, LEARNED>(fs, a);
+    }
+    if (LEARNED || sizeof(T) == sizeof(float)) {
+      // queue the wave's handed-over faces with one atomic per wave; a face
+      // that finds the queue full is solved here
+      const uint64_t dmask = __ballot(defer);
+      if (dmask) {
+        const int leader = __ffsll((unsigned long long)dmask) - 1;
+        unsigned long long base = 0;
+        if (lane == leader) base = atomicAdd(a.hard_count, (unsigned long long)__popcll(dmask));
+        base = __shfl(base, leader, 64);
+        if (defer) {
+          const unsigned long long below = __builtin_amdgcn_mbcnt_hi(
+              (uint32_t)(dmask >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)dmask, 0u));
+          const unsigned long long slot = base + below;
+          if (slot < (unsigned long long)a.hard_cap) {
+            a.hard_q[slot] = make_int2(Lslot, Rslot);
+          } else {
+            defer = false;
+            ++overflow;
+          }
         }
       }
     }
     double c[5] = {0, 0, 0, 0, 0};
-    if (active) {
+    if (active && !defer) {
       int it;
       double ps;
-      face_solve<T, SCHEME, M>(fs, a, (LEARNED && p_learned != T(0)) ? p_learned : T(0), c, it, ps);
-      if (LEARNED && p_learned < T(0)) fs.flags |= F_FALLBACK;
+      face_solve<T, SCHEME, M>(fs, a, T(0), c, it, ps);
       const double sgn = (i < j) ? -1.0 : 1.0;  // the left (lower) side loses c
 #pragma unroll
       for (int q = 0; q < 5; ++q) c[q] *= sgn;
@@ -755,10 +789,11 @@ __global__ void __launch_bounds__(FTH) __attribute__((amdgpu_waves_per_eu(2))) f
         }
       }
     }
-    if (active) {
+    if (active && !defer) {
 #pragma unroll
       for (int q = (SCHEME == MFM_SCHEME_MFM ? 1 : 0); q < 5; ++q) atomicAdd(&acc[q][p], c[q]);
     }
+    if (defer) ++nfaces;  // counted here, solved in the second pass
   }
   __syncthreads();
   for (int t = tid; t < nb; t += FTH) {
@@ -771,10 +806,141 @@ __global__ void __launch_bounds__(FTH) __attribute__((amdgpu_waves_per_eu(2))) f
   count_add(a.counters + C_POSITIVITY, pos);
   count_add(a.counters + C_RIEMANN_MAXIT, maxit);
   count_add(a.counters + C_GUESS_FALLBACK, fb);
+  count_add(a.counters + C_HARD_OVERFLOW, overflow);
 }
 
-// dq_ext is cleared before the flux loop and folded into dQ after it.
-__global__ void zero_f64_k(double *v, int64_t m) {
+// One side of a face in FP64 for the second pass.  The mixed path's record is
+// FP32: the particle's own values come from the FP64 particle arrays instead,
+// B and the gradients (computed in FP32) are widened.
+template <bool F32REC>
+__device__ __forceinline__ void load_side64(const FluxArgs &a, int i, FaceIn<double> &s) {
+  if (!F32REC) {
+    load_side(a, i, s);
+    return;
+  }
+  const float4 *r = reinterpret_cast<const float4 *>(a.rec) + (int64_t)i * (F_STRIDE / 4);
+  float f[F_STRIDE];
+#pragma unroll
+  for (int k = 2; k < F_STRIDE / 4; ++k) {
+    const float4 q = r[k];
+    f[4 * k] = q.x; f[4 * k + 1] = q.y; f[4 * k + 2] = q.z; f[4 * k + 3] = q.w;
+  }
+  static_assert(F_B == 8, "B and the gradients start at the third float4 of the record");
+  s.x = a.x[i]; s.y = a.y[i]; s.z = a.z[i];
+  s.ih = 1.0 / a.H[i];
+  s.V = a.V[i];
+  s.rho = a.rho[i];
+  s.irho = 1.0 / s.rho;
+  s.v[0] = a.vx[i]; s.v[1] = a.vy[i]; s.v[2] = a.vz[i];
+  s.P = a.P[i];
+#pragma unroll
+  for (int k = 0; k < 6; ++k) s.B[k] = f[F_B + k];
+#pragma unroll
+  for (int k = 0; k < 15; ++k) s.G[k] = f[F_G + k];
+}
+
+// Second pass of the flux loop: the handed-over faces, one per lane, in FP64
+// (and, with the learned guess, the network's starting value for those that
+// pass its gate).  Both sides receive their share through FP64 atomics into
+// dq_ext, which is folded into dQ after this pass.  The queue length is read
+// on the device; the grid strides over it.
+template <bool F32REC, int SCHEME, int M, bool LEARNED>
+__global__ void __launch_bounds__(FTH) hard_faces_k(FluxArgs a) {
+  __shared__ uint16_t mlp_act[LEARNED ? (FTH / 64) * 16 * mlp::AST : 1];
+  const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+  const unsigned long long queued = *a.hard_count;
+  const int64_t nq = (int64_t)(queued < (unsigned long long)a.hard_cap ? queued
+                                                                        : (unsigned long long)a.hard_cap);
+  const double dt = a.dt[0];
+  const double hdt = 0.5 * dt;
+  const int64_t n = a.n;
+  int64_t nfaces = 0, iters_sum = 0, vac = 0, pos = 0, maxit = 0, fb = 0;
+  for (int64_t base = (int64_t)blockIdx.x * FTH; base < nq; base += (int64_t)gridDim.x * FTH) {
+    const int64_t f = base + tid;
+    const bool active = f < nq;
+    FaceState<double> fs;
+    fs.skip = true;
+    fs.flags = 0;
+    int L = 0, R = 0;
+    if (active) {
+      const int2 q = a.hard_q[f];
+      L = q.x;
+      R = q.y;
+      FaceIn<double> Ls, Rs;
+      load_side64<F32REC>(a, L, Ls);
+      load_side64<F32REC>(a, R, Rs);
+      face_prepare<double>(Ls, Rs, a, hdt, fs);
+    }
+    double p_learned = 0.0;
+    if (LEARNED) {
+      // the wavefront evaluates the network on the 16-face tiles that hold a
+      // face passing its gate (wave-uniform branches)
+      float x[mlp::NIN];
+      bool gated = false;
+      if (active && !fs.skip) {
+        features_of<double>(fs, x);
+        gated = mlp::needs_guess(x);
+      }
+      const uint64_t gmask = __ballot(gated);
+      if (gmask) {
+        uint16_t *tile = mlp_act + wid * 16 * mlp::AST;
+        float y = 0.f;
+#pragma unroll 1
+        for (int mt = 0; mt < 4; ++mt) {
+          if (((gmask >> (16 * mt)) & 0xffffull) == 0) continue;
+          if ((lane >> 4) == mt) mlp::put_input(tile, lane & 15, gated ? x : nullptr, a.net.norm);
+          const float yt = mlp::forward_tile(tile, a.net, lane);
+          if ((lane >> 4) == mt) y = yt;
+        }
+        if (gated) {
+          p_learned = 0.5 * (fs.SL.p + fs.SR.p) * (double)expf(y);
+          if (!(p_learned > 0.0)) p_learned = -1.0;  // rejected below
+        }
+      }
+    }
+    if (active) {
+      double c[5];
+      int it;
+      double ps;
+      face_solve<double, SCHEME, M>(fs, a, p_learned != 0.0 ? p_learned : 0.0, c, it, ps);
+      if (LEARNED && p_learned < 0.0) fs.flags |= F_FALLBACK;
+#pragma unroll
+      for (int q = (SCHEME == MFM_SCHEME_MFM ? 1 : 0); q < 5; ++q) {
+        unsafeAtomicAdd(&a.dq_ext[(int64_t)q * n + L], -dt * c[q]);
+        unsafeAtomicAdd(&a.dq_ext[(int64_t)q * n + R], dt * c[q]);
+      }
+      ++nfaces;
+      iters_sum += it;
+      vac += (fs.flags & F_VACUUM) ? 1 : 0;
+      pos += (fs.flags & F_POSITIVITY) ? 1 : 0;
+      maxit += (fs.flags & F_MAXIT) ? 1 : 0;
+      fb += (fs.flags & F_FALLBACK) ? 1 : 0;
+      if (a.dump && !fs.skip && !(fs.flags & F_VACUUM)) {
+        const unsigned long long slot = atomicAdd(a.dump_count, 1ull);
+        if (slot < (unsigned long long)a.dump_cap) {
+          float x[mlp::NIN];
+          features_of<double>(fs, x);
+          float *r = a.dump + slot * 8;
+#pragma unroll
+          for (int k = 0; k < mlp::NIN; ++k) r[k] = x[k];
+          r[6] = logf((float)(ps / (0.5 * (fs.SL.p + fs.SR.p))));
+          r[7] = (float)it;
+        }
+      }
+    }
+  }
+  count_add(a.counters + C_HARD_FACES, nfaces);
+  count_add(a.counters + C_RIEMANN_ITERS, iters_sum);
+  count_add(a.counters + C_VACUUM, vac);
+  count_add(a.counters + C_POSITIVITY, pos);
+  count_add(a.counters + C_RIEMANN_MAXIT, maxit);
+  count_add(a.counters + C_GUESS_FALLBACK, fb);
+}
+
+// dq_ext (and the second pass's queue length) is cleared before the flux
+// loop and folded into dQ after it.
+__global__ void zero_f64_k(double *v, int64_t m, unsigned long long *queue_len) {
+  if (blockIdx.x == 0 && threadIdx.x == 0) *queue_len = 0ull;
   for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < m;
        k += (int64_t)gridDim.x * blockDim.x)
     v[k] = 0.0;
@@ -801,6 +967,24 @@ void launch_t(const FluxArgs &a, int scheme, int m, int nb, hipStream_t st) {
     launch_m<T, MFM_SCHEME_MFM, LEARNED>(a, m, nb, st);
   else
     launch_m<T, MFM_SCHEME_MFV, LEARNED>(a, m, nb, st);
+}
+
+template <bool F32REC, int SCHEME, bool LEARNED>
+void launch_hard_m(const FluxArgs &a, int m, int nb, hipStream_t st) {
+  if (m == 5)
+    hard_faces_k<F32REC, SCHEME, 5, LEARNED><<<nb, FTH, 0, st>>>(a);
+  else if (m == 7)
+    hard_faces_k<F32REC, SCHEME, 7, LEARNED><<<nb, FTH, 0, st>>>(a);
+  else
+    hard_faces_k<F32REC, SCHEME, 0, LEARNED><<<nb, FTH, 0, st>>>(a);
+}
+
+template <bool F32REC, bool LEARNED>
+void launch_hard(const FluxArgs &a, int scheme, int m, int nb, hipStream_t st) {
+  if (scheme == MFM_SCHEME_MFM)
+    launch_hard_m<F32REC, MFM_SCHEME_MFM, LEARNED>(a, m, nb, st);
+  else
+    launch_hard_m<F32REC, MFM_SCHEME_MFV, LEARNED>(a, m, nb, st);
 }
 
 template <typename T>
@@ -852,14 +1036,22 @@ hipError_t launch_fluxes(mfm_ctx *ctx, const mfm_particles *pp, const double *dt
   a.dump_cap = ctx->dump_cap;
   a.dump_count = ctx->dump_count;
   a.dq_ext = ctx->dq_ext;
+  a.hard_q = ctx->hard_q;
+  a.hard_cap = ctx->hard_cap;
+  a.hard_count = reinterpret_cast<unsigned long long *>(ctx->counters + C_HARD_QUEUE);
+  a.jump = (float)ctx->p.mixed_jump;
+  a.x = pp->x; a.y = pp->y; a.z = pp->z; a.H = pp->H; a.V = pp->V; a.rho = pp->rho;
+  a.vx = pp->vx; a.vy = pp->vy; a.vz = pp->vz; a.P = pp->P;
   const bool learned = ctx->p.guess == MFM_GUESS_LEARNED;
+  const bool mixed = ctx->p.precision == MFM_MIXED;
   if (learned) mlp_net_of(ctx->mlp_state, &a.net);
   const int nb = blocks_for(pp->n, FBS);
   const int64_t m5 = 5 * pp->n;
   const int fb = (int)std::min<int64_t>(blocks_for(m5, 256), 8192);
-  zero_f64_k<<<fb, 256, 0, ctx->stream>>>(ctx->dq_ext, m5);
-  stage_begin(ctx, 4);
-  if (ctx->p.precision == MFM_MIXED) {
+  const int ev_all = stage_begin(ctx, 4);
+  zero_f64_k<<<fb, 256, 0, ctx->stream>>>(ctx->dq_ext, m5, a.hard_count);
+  const int ev_main = stage_begin(ctx, 6);
+  if (mixed) {
     if (learned)
       launch_t<float, true>(a, ctx->p.scheme, m, nb, ctx->stream);
     else
@@ -870,7 +1062,21 @@ hipError_t launch_fluxes(mfm_ctx *ctx, const mfm_particles *pp, const double *dt
     else
       launch_t<double, false>(a, ctx->p.scheme, m, nb, ctx->stream);
   }
-  stage_end(ctx, 4);
+  stage_end(ctx, ev_main);
+  if (mixed || learned) {
+    // the second pass strides over the queue with a grid of its own (its
+    // length is known only on the device); an empty queue ends it at once
+    const int hb = 1024;
+    const int ev_hard = stage_begin(ctx, 7);
+    if (mixed) {
+      if (learned) launch_hard<true, true>(a, ctx->p.scheme, m, hb, ctx->stream);
+      else launch_hard<true, false>(a, ctx->p.scheme, m, hb, ctx->stream);
+    } else {
+      launch_hard<false, true>(a, ctx->p.scheme, m, hb, ctx->stream);
+    }
+    stage_end(ctx, ev_hard);
+  }
   fold_f64_k<<<fb, 256, 0, ctx->stream>>>(pp->dQ, ctx->dq_ext, m5);
+  stage_end(ctx, ev_all);
   return hipGetLastError();
 }

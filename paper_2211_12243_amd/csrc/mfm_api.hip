@@ -13,7 +13,8 @@ constexpr size_t ALIGN = 256;
 
 struct Layout {
   size_t code, count, start, cursor, crange, scan, order, tmp, pos4, cand, cand_r2, rest_r2,
-      cand_cnt, gl, gl_cnt, gin, fslot, fcnt, dq_ext, rec, red, counters, scalars;
+      cand_cnt, gl, gl_cnt, gin, fslot, fcnt, dq_ext, hard_q, rec, red, counters, scalars;
+  int64_t hard_cap;
   size_t total;
   int64_t ncodes_max;
   size_t scan_len;
@@ -59,6 +60,9 @@ Layout make_layout(const mfm_params *p, int64_t n) {
   L.fslot = take(4 * list_len(p->max_list, n));
   L.fcnt = take(4 * (size_t)n);
   L.dq_ext = take(8 * 5 * (size_t)n);
+  // the FP64 pass's queue holds as many faces as half the face lists
+  L.hard_cap = (int64_t)(list_len(p->max_list, n) / 2);
+  L.hard_q = take(8 * (size_t)L.hard_cap);
   L.rec = take(8 * (size_t)R_STRIDE * (size_t)n);
   L.red = take(8 * 5 * 1024);
   L.counters = take(8 * NCOUNTERS);
@@ -82,6 +86,7 @@ int check_params(const mfm_params *p) {
   if (p->max_list < 1 || p->max_list > 4096) return 0;
   if (!(p->cell_margin >= 1.0)) return 0;
   if (p->max_cell_dim < 3 || p->max_cell_dim > 512) return 0;
+  if (!(p->mixed_jump == 0.0 || p->mixed_jump >= 1.0)) return 0;
   for (int k = 0; k < 3; ++k)
     if (!(p->box[k] > 0.0)) return 0;
   return 1;
@@ -155,23 +160,24 @@ int setup_grid(mfm_ctx *ctx, double hmax) {
 // ---------------------------------------------------------------------------
 // timing
 // ---------------------------------------------------------------------------
-void stage_begin(mfm_ctx *ctx, int stage) {
-  if (!ctx->timing || ctx->ev_used >= 1024) return;
-  int k = ctx->ev_used;
+int stage_begin(mfm_ctx *ctx, int stage) {
+  if (!ctx->timing || ctx->ev_used >= MAX_EVENT_PAIRS) return -1;
+  const int k = ctx->ev_used++;
   ctx->ev_stage[k] = stage;
+  ctx->ev_open[k] = 1;
   hipEventRecord(ctx->ev_pool[2 * k], ctx->stream);
+  return k;
 }
 
-void stage_end(mfm_ctx *ctx, int stage) {
-  (void)stage;
-  if (!ctx->timing || ctx->ev_used >= 1024) return;
-  int k = ctx->ev_used;
-  hipEventRecord(ctx->ev_pool[2 * k + 1], ctx->stream);
-  ctx->ev_used = k + 1;
+void stage_end(mfm_ctx *ctx, int slot) {
+  if (slot < 0) return;
+  hipEventRecord(ctx->ev_pool[2 * slot + 1], ctx->stream);
+  ctx->ev_open[slot] = 0;
 }
 
 static void harvest_events(mfm_ctx *ctx) {
   for (int k = 0; k < ctx->ev_used; ++k) {
+    if (ctx->ev_open[k]) continue;
     float ms = 0.0f;
     hipEventSynchronize(ctx->ev_pool[2 * k + 1]);
     if (hipEventElapsedTime(&ms, ctx->ev_pool[2 * k], ctx->ev_pool[2 * k + 1]) == hipSuccess) {
@@ -208,6 +214,7 @@ void mfm_default_params(mfm_params *p) {
   p->box[0] = p->box[1] = p->box[2] = 1.0;
   p->cell_margin = 1.10;
   p->max_cell_dim = 256;
+  p->mixed_jump = 8.0;
 }
 
 size_t mfm_workspace_bytes(const mfm_params *p, int64_t n_max) {
@@ -249,6 +256,8 @@ int mfm_create(const mfm_params *p, int64_t n_max, void *workspace, size_t works
   ctx->fslot = (int32_t *)(ctx->ws + L.fslot);
   ctx->fcnt = (int32_t *)(ctx->ws + L.fcnt);
   ctx->dq_ext = (double *)(ctx->ws + L.dq_ext);
+  ctx->hard_q = (int2 *)(ctx->ws + L.hard_q);
+  ctx->hard_cap = L.hard_cap;
   ctx->rec = (double *)(ctx->ws + L.rec);
   ctx->red = (double *)(ctx->ws + L.red);
   ctx->counters = (int64_t *)(ctx->ws + L.counters);
@@ -257,17 +266,9 @@ int mfm_create(const mfm_params *p, int64_t n_max, void *workspace, size_t works
   ctx->scan_tmp_len = L.scan_len;
   ctx->margin_boost = 1.0;
   ctx->dump_count = reinterpret_cast<unsigned long long *>(ctx->counters + C_DUMP_COUNT);
-  for (int k = 0; k < 2 * 1024; ++k) {
-    if (hipEventCreate(&ctx->ev_pool[k]) != hipSuccess) {
-      for (int q = 0; q < k; ++q) hipEventDestroy(ctx->ev_pool[q]);
-      free(ctx);
-      return MFM_E_HIP;
-    }
-  }
   hipError_t e = hipMemsetAsync(ctx->counters, 0, sizeof(int64_t) * NCOUNTERS, ctx->stream);
   if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
   if (e != hipSuccess) {
-    for (int q = 0; q < 2 * 1024; ++q) hipEventDestroy(ctx->ev_pool[q]);
     free(ctx);
     return MFM_E_HIP;
   }
@@ -278,7 +279,8 @@ int mfm_create(const mfm_params *p, int64_t n_max, void *workspace, size_t works
 int mfm_destroy(mfm_ctx *ctx) {
   if (!ctx) return MFM_E_ARG;
   hipStreamSynchronize(ctx->stream);
-  for (int q = 0; q < 2 * 1024; ++q) hipEventDestroy(ctx->ev_pool[q]);
+  if (ctx->ev_created)
+    for (int q = 0; q < 2 * MAX_EVENT_PAIRS; ++q) hipEventDestroy(ctx->ev_pool[q]);
   free(ctx);
   return MFM_OK;
 }
@@ -286,7 +288,7 @@ int mfm_destroy(mfm_ctx *ctx) {
 int mfm_build_cells(mfm_ctx *ctx, const mfm_particles *pp, int64_t *perm) {
   if (!ctx) return MFM_E_ARG;
   if (!check_parts(ctx, pp)) return fail(ctx, MFM_E_ARG, "invalid particle set");
-  stage_begin(ctx, 0);
+  const int ev = stage_begin(ctx, 0);
   HIPCHK(ctx, launch_max_h(ctx, pp), "max H");
   double hmax = 0.0;
   HIPCHK(ctx, hipMemcpyAsync(&hmax, ctx->scalars, sizeof(double), hipMemcpyDeviceToHost,
@@ -296,7 +298,7 @@ int mfm_build_cells(mfm_ctx *ctx, const mfm_particles *pp, int64_t *perm) {
   int rc = setup_grid(ctx, hmax);
   if (rc) return rc;
   HIPCHK(ctx, launch_build_cells(ctx, pp, perm), "cells");
-  stage_end(ctx, 0);
+  stage_end(ctx, ev);
   ctx->have_cells = 1;
   ctx->have_density = 0;
   ctx->have_grad = 0;
@@ -313,12 +315,12 @@ int mfm_density(mfm_ctx *ctx, const mfm_particles *pp) {
                              ctx->stream), "clear pass counters");
   HIPCHK(ctx, hipMemsetAsync(ctx->counters + C_PASS_NOCONV, 0, 3 * sizeof(int64_t),
                              ctx->stream), "clear pass counters");
-  stage_begin(ctx, 1);
+  int ev = stage_begin(ctx, 1);
   HIPCHK(ctx, launch_candidates(ctx, pp), "neighbour search");
-  stage_end(ctx, 1);
-  stage_begin(ctx, 2);
+  stage_end(ctx, ev);
+  ev = stage_begin(ctx, 2);
   HIPCHK(ctx, launch_density(ctx, pp), "density");
-  stage_end(ctx, 2);
+  stage_end(ctx, ev);
   int64_t c[NCOUNTERS];
   int rc = read_counters(ctx, c);
   if (rc) return rc;
@@ -362,9 +364,9 @@ int mfm_gradients(mfm_ctx *ctx, const mfm_particles *pp, double dt_max, double *
     return fail(ctx, MFM_E_ARG, "invalid arguments");
   if (!ctx->have_density || ctx->n_cells_built != pp->n)
     return fail(ctx, MFM_E_STATE, "mfm_gradients needs mfm_density first");
-  stage_begin(ctx, 3);
+  const int ev = stage_begin(ctx, 3);
   HIPCHK(ctx, launch_gradients(ctx, pp, dt_max, dt_dev), "gradients");
-  stage_end(ctx, 3);
+  stage_end(ctx, ev);
   ctx->have_grad = 1;
   return MFM_OK;
 }
@@ -409,9 +411,9 @@ int mfm_face_dump_count(mfm_ctx *ctx, int64_t *count_host) {
 int mfm_update(mfm_ctx *ctx, const mfm_particles *pp, const double *dt_dev) {
   if (!ctx) return MFM_E_ARG;
   if (!check_parts(ctx, pp) || !dt_dev) return fail(ctx, MFM_E_ARG, "invalid arguments");
-  stage_begin(ctx, 5);
+  const int ev = stage_begin(ctx, 5);
   HIPCHK(ctx, launch_update(ctx, pp, dt_dev), "update");
-  stage_end(ctx, 5);
+  stage_end(ctx, ev);
   ctx->have_cells = 0;
   ctx->have_density = 0;
   ctx->have_grad = 0;
@@ -461,7 +463,7 @@ int mfm_diagnostics(mfm_ctx *ctx, const mfm_particles *pp, mfm_diag *out) {
   int rc = read_counters(ctx, c);
   if (rc) return rc;
   int64_t *dst = &out->h_noconv;
-  for (int k = 0; k <= C_U_GUARD; ++k) dst[k] = c[k];
+  for (int k = 0; k <= C_HARD_OVERFLOW; ++k) dst[k] = c[k];
   if (pp) {
     out->mass = sums[0];
     out->px = sums[1];
@@ -483,6 +485,18 @@ int mfm_reset_counters(mfm_ctx *ctx) {
 int mfm_enable_timing(mfm_ctx *ctx, int on) {
   if (!ctx) return MFM_E_ARG;
   HIPCHK(ctx, hipStreamSynchronize(ctx->stream), "synchronise");
+  if (on && !ctx->ev_created) {
+    // the events are made on first use, so that a context that is never
+    // timed creates none
+    for (int k = 0; k < 2 * MAX_EVENT_PAIRS; ++k) {
+      hipError_t e = hipEventCreate(&ctx->ev_pool[k]);
+      if (e != hipSuccess) {
+        for (int q = 0; q < k; ++q) hipEventDestroy(ctx->ev_pool[q]);
+        return hip_fail(ctx, e, "create timing events");
+      }
+    }
+    ctx->ev_created = 1;
+  }
   harvest_events(ctx);
   ctx->timing = on ? 1 : 0;
   for (int s = 0; s < MFM_NSTAGES; ++s) {

@@ -28,6 +28,8 @@ enum {
   C_GUESS_FALLBACK,
   C_FP64_INVERSE,
   C_U_GUARD,
+  C_HARD_FACES,
+  C_HARD_OVERFLOW,
   C_CELL_OVERFLOW,  // internal: some H reached the cell side in the last density pass
   C_NONFINITE,      // internal: non-finite dt or state
   // counts of the density pass in flight; folded into the slots above only
@@ -36,7 +38,8 @@ enum {
   C_PASS_BOOSTS,
   C_PASS_FAIL,
   C_DUMP_COUNT,     // face records appended since the dump was armed
-  NCOUNTERS = 24
+  C_HARD_QUEUE,     // faces queued for the flux loop's FP64 pass in the current call
+  NCOUNTERS = 32
 };
 
 // Packed per-particle record the gradient loop gathers for each neighbour
@@ -81,6 +84,8 @@ struct CellGrid {
   const int2 *range;     // (start, count) by Morton code, one load per cell
 };
 
+constexpr int MAX_EVENT_PAIRS = 1024;  // timed launches held between two harvests
+
 struct mfm_ctx {
   mfm_params p;
   int64_t n_max;
@@ -108,6 +113,9 @@ struct mfm_ctx {
   int32_t *fslot;      // max_list * n: faces each particle evaluates (k-major)
   int32_t *fcnt;       // n
   double *dq_ext;      // 5 n: flux contributions to particles outside the evaluating block
+                       // and of the FP64 second pass, folded into dQ after the loop
+  int2 *hard_q;        // faces (lower, higher slot) queued for the flux loop's FP64 pass
+  int64_t hard_cap;    // its capacity
   double *rec;         // R_STRIDE * n packed flux records
   double *red;         // reduction partials
   int64_t *counters;   // NCOUNTERS
@@ -127,9 +135,10 @@ struct mfm_ctx {
   int64_t dump_cap;
   unsigned long long *dump_count;  // = counters + C_DUMP_COUNT
   // timing
-  int timing;
-  hipEvent_t ev_pool[2 * 1024];
-  int ev_stage[1024];
+  int timing, ev_created;
+  hipEvent_t ev_pool[2 * MAX_EVENT_PAIRS];
+  int ev_stage[MAX_EVENT_PAIRS];
+  int ev_open[MAX_EVENT_PAIRS];
   int ev_used;
   double stage_ms[MFM_NSTAGES];
   int64_t stage_count[MFM_NSTAGES];
@@ -236,20 +245,20 @@ hipError_t launch_build_cells(mfm_ctx *ctx, const mfm_particles *pp, int64_t *pe
 hipError_t launch_candidates(mfm_ctx *ctx, const mfm_particles *pp);
 hipError_t launch_density(mfm_ctx *ctx, const mfm_particles *pp);
 hipError_t launch_gradients(mfm_ctx *ctx, const mfm_particles *pp, double dt_max, double *dt_dev);
-// Records the flux stage's timing events around the flux kernel itself (the
-// clear and fold of dq_ext lie outside).
+// Times the whole flux loop as stage 4, its first-pass kernel as stage 6 and
+// its FP64 second pass as stage 7.
 hipError_t launch_fluxes(mfm_ctx *ctx, const mfm_particles *pp, const double *dt_dev);
-void stage_begin(mfm_ctx *ctx, int stage);
-void stage_end(mfm_ctx *ctx, int stage);
 hipError_t launch_update(mfm_ctx *ctx, const mfm_particles *pp, const double *dt_dev);
 hipError_t launch_conserved(mfm_ctx *ctx, const mfm_particles *pp);
 
 // device pointers of a network state (mlp translation unit); net_out is an mlp::Net
 const void *mlp_net_of(const void *state, void *net_out);
 
-// timing helpers (api translation unit)
-void stage_begin(mfm_ctx *ctx, int stage);
-void stage_end(mfm_ctx *ctx, int stage);
+// timing helpers (api translation unit): stage_begin records a start event
+// for the stage and returns its slot (-1 when timing is off or the pool is
+// full), stage_end the matching end event; pairs may nest
+int stage_begin(mfm_ctx *ctx, int stage);
+void stage_end(mfm_ctx *ctx, int slot);
 
 // The hardware hands workgroup b of a launch to XCD b % 8, and each XCD has
 // its own L2.  The neighbour loops renumber their workgroups so that every XCD

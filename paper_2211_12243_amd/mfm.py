@@ -21,8 +21,9 @@ MFM_SCHEME_MFV, MFM_SCHEME_MFM = 0, 1
 MFM_FP64, MFM_MIXED = 0, 1
 MFM_GUESS_PLAIN, MFM_GUESS_LEARNED = 0, 1
 MFM_LIMIT_BJ, MFM_LIMIT_PAIRWISE = 1, 2
-MFM_NSTAGES = 6
-STAGES = ("cells", "search", "density", "gradients", "fluxes", "update")
+MFM_NSTAGES = 8
+STAGES = ("cells", "search", "density", "gradients", "fluxes", "update", "flux_kernel",
+          "flux_hard")
 
 
 class mfm_params(ctypes.Structure):
@@ -36,7 +37,7 @@ class mfm_params(ctypes.Structure):
         ("psi1", ctypes.c_double), ("psi2", ctypes.c_double), ("riemann_tol", ctypes.c_double),
         ("alpha1", ctypes.c_double), ("box", ctypes.c_double * 3),
         ("cell_margin", ctypes.c_double), ("max_cell_dim", ctypes.c_int32),
-        ("pad0", ctypes.c_int32),
+        ("pad0", ctypes.c_int32), ("mixed_jump", ctypes.c_double),
     ]
 
 
@@ -52,11 +53,12 @@ class mfm_particles(ctypes.Structure):
 
 _DIAG_INT = ("h_noconv", "ncond_boosts", "ncond_fail", "cell_rebuilds", "list_overflow",
              "grad_pairs", "faces", "riemann_iters", "riemann_maxit", "vacuum", "positivity",
-             "neg_mass", "singular_e", "guess_fallback", "fp64_inverse", "u_guard")
+             "neg_mass", "singular_e", "guess_fallback", "fp64_inverse", "u_guard",
+             "hard_faces", "hard_overflow")
 
 
 class mfm_diag(ctypes.Structure):
-    _fields_ = ([(k, ctypes.c_int64) for k in _DIAG_INT] + [("pad", ctypes.c_int64 * 2)]
+    _fields_ = ([(k, ctypes.c_int64) for k in _DIAG_INT]
                 + [(k, ctypes.c_double) for k in ("mass", "px", "py", "pz", "energy")])
 
     def as_dict(self):
@@ -159,7 +161,8 @@ def params_from_dict(cfg: dict, **over) -> mfm_params:
     """The library's parameter struct from the plain dict the tests share."""
     keys = ("scheme", "limiter", "max_boosts", "h_maxit", "riemann_maxit", "gamma", "n_ngb",
             "ncond_max", "ngb_boost", "h_tol", "c_cfl", "psi1", "psi2", "riemann_tol", "alpha1",
-            "box", "precision", "max_list", "cell_margin", "max_cell_dim", "guess")
+            "box", "precision", "max_list", "cell_margin", "max_cell_dim", "guess",
+            "mixed_jump")
     d = {k: cfg[k] for k in keys if k in cfg}
     d.update(over)
     return mfm_default_params(**d)

@@ -4,8 +4,9 @@ The workloads are the 64^3 Kelvin-Helmholtz layers (262144 particles) and the
 128^3 Sedov blast (2097152 particles, the benchmark set), run through the C
 entry points with the parameters bench.py uses.  The FP64 oracle runs the
 same step on the host (a few seconds with all host threads), so no sampling
-is needed.  Tolerances as in the small cases: 1e-12 (FP64), 1e-5 normwise
-(mixed), exact pair and face counts.
+is needed.  Tolerances as in the small cases: 1e-12 (FP64), 1e-5 (mixed:
+fields against their largest magnitude, flux sums per particle against the
+particle's own scales), exact pair and face counts.
 """
 import numpy as np
 import pytest
