@@ -241,7 +241,7 @@ __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) ca
     }
     __syncthreads();
   }
-  count_add(a.counters + C_LIST_OVERFLOW, overflow);
+  count_add(a.counters + C_PASS_LIST, overflow);
 }
 
 struct DensityArgs {
@@ -624,7 +624,27 @@ __global__ void __launch_bounds__(BS) density_long_k(DensityArgs a, CellGrid g) 
   count_add(a.counters + C_CELL_OVERFLOW, overflow);
 }
 
+__global__ void validate_k(int64_t *c, const double *hmax_build, double hmax_grid) {
+  if (threadIdx.x != 0) return;
+  const bool bad_grid = !(hmax_build[0] <= hmax_grid);
+  if (c[C_PASS_LIST] > 0 || c[C_CELL_OVERFLOW] > 0 || bad_grid) {
+    c[C_STEP_SKIP] = 1;
+    if (c[C_CELL_OVERFLOW] > 0 || bad_grid) c[C_CELL_REBUILDS] += 1;
+    c[C_LIST_OVERFLOW] += c[C_PASS_LIST];
+    return;
+  }
+  c[C_STEP_SKIP] = 0;
+  c[C_H_NOCONV] += c[C_PASS_NOCONV];
+  c[C_NCOND_BOOSTS] += c[C_PASS_BOOSTS];
+  c[C_NCOND_FAIL] += c[C_PASS_FAIL];
+}
+
 }  // namespace
+
+hipError_t launch_validate(mfm_ctx *ctx, double hmax_grid) {
+  validate_k<<<1, 64, 0, ctx->stream>>>(ctx->counters, ctx->scalars, hmax_grid);
+  return hipGetLastError();
+}
 
 hipError_t launch_candidates(mfm_ctx *ctx, const mfm_particles *pp) {
   CandArgs a;

@@ -640,6 +640,7 @@ __device__ __forceinline__ bool hand_over(const FaceState<T> &fs, const FluxArgs
 
 template <typename T, int SCHEME, int M, bool LEARNED>
 __global__ void __launch_bounds__(FTH) __attribute__((amdgpu_waves_per_eu(2))) fluxes_k(FluxArgs a) {
+  if (a.counters[C_STEP_SKIP]) return;  // the density pass was rejected
   __shared__ int pref[FBS + 1];
   __shared__ int wsum[FTH / 64];
   __shared__ double acc[5][FBS];
@@ -846,6 +847,7 @@ __device__ __forceinline__ void load_side64(const FluxArgs &a, int i, FaceIn<dou
 // on the device; the grid strides over it.
 template <bool F32REC, int SCHEME, int M, bool LEARNED>
 __global__ void __launch_bounds__(FTH) hard_faces_k(FluxArgs a) {
+  if (a.counters[C_STEP_SKIP]) return;  // the density pass was rejected
   __shared__ uint16_t mlp_act[LEARNED ? (FTH / 64) * 16 * mlp::AST : 1];
   const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
   const unsigned long long queued = *a.hard_count;
@@ -939,13 +941,16 @@ __global__ void __launch_bounds__(FTH) hard_faces_k(FluxArgs a) {
 
 // dq_ext (and the second pass's queue length) is cleared before the flux
 // loop and folded into dQ after it.
-__global__ void zero_f64_k(double *v, int64_t m, unsigned long long *queue_len) {
+__global__ void zero_f64_k(double *v, int64_t m, unsigned long long *queue_len,
+                           const int64_t *counters) {
+  if (counters[C_STEP_SKIP]) return;
   if (blockIdx.x == 0 && threadIdx.x == 0) *queue_len = 0ull;
   for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < m;
        k += (int64_t)gridDim.x * blockDim.x)
     v[k] = 0.0;
 }
-__global__ void fold_f64_k(double *dst, const double *src, int64_t m) {
+__global__ void fold_f64_k(double *dst, const double *src, int64_t m, const int64_t *counters) {
+  if (counters[C_STEP_SKIP]) return;
   for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < m;
        k += (int64_t)gridDim.x * blockDim.x)
     dst[k] += src[k];
@@ -1049,7 +1054,7 @@ hipError_t launch_fluxes(mfm_ctx *ctx, const mfm_particles *pp, const double *dt
   const int64_t m5 = 5 * pp->n;
   const int fb = (int)std::min<int64_t>(blocks_for(m5, 256), 8192);
   const int ev_all = stage_begin(ctx, 4);
-  zero_f64_k<<<fb, 256, 0, ctx->stream>>>(ctx->dq_ext, m5, a.hard_count);
+  zero_f64_k<<<fb, 256, 0, ctx->stream>>>(ctx->dq_ext, m5, a.hard_count, ctx->counters);
   const int ev_main = stage_begin(ctx, 6);
   if (mixed) {
     if (learned)
@@ -1076,7 +1081,7 @@ hipError_t launch_fluxes(mfm_ctx *ctx, const mfm_particles *pp, const double *dt
     }
     stage_end(ctx, ev_hard);
   }
-  fold_f64_k<<<fb, 256, 0, ctx->stream>>>(pp->dQ, ctx->dq_ext, m5);
+  fold_f64_k<<<fb, 256, 0, ctx->stream>>>(pp->dQ, ctx->dq_ext, m5, ctx->counters);
   stage_end(ctx, ev_all);
   return hipGetLastError();
 }

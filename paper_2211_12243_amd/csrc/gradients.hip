@@ -123,6 +123,7 @@ template <> struct NbRec<double> {
 
 template <typename T>
 __global__ void __launch_bounds__(BS) gradients_k(GradArgs a) {
+  if (a.counters[C_STEP_SKIP]) return;  // the density pass was rejected
   __shared__ int32_t s_ring[BS / 64][RING][64];
   const int64_t i = xcd_block(blockIdx.x, gridDim.x) * (int64_t)blockDim.x + threadIdx.x;
   const int64_t n = a.n;
@@ -391,7 +392,9 @@ __global__ void __launch_bounds__(BS) gradients_k(GradArgs a) {
   count_add(a.counters + C_FP64_INVERSE, inv64);
 }
 
-__global__ void min_partial_k(const double *__restrict__ v, int64_t n, double *partial) {
+__global__ void min_partial_k(const double *__restrict__ v, int64_t n, double *partial,
+                              const int64_t *counters) {
+  if (counters[C_STEP_SKIP]) return;
   __shared__ double s[BS / 64];
   double m = __builtin_huge_val();
   for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < n;
@@ -408,6 +411,7 @@ __global__ void min_partial_k(const double *__restrict__ v, int64_t n, double *p
 
 __global__ void dt_final_k(const double *partial, int np, double dt_max, double *dt,
                            int64_t *counters) {
+  if (counters[C_STEP_SKIP]) return;
   __shared__ double s[BS / 64];
   double m = __builtin_huge_val();
   for (int k = threadIdx.x; k < np; k += blockDim.x) m = fmin(m, partial[k]);
@@ -452,7 +456,7 @@ hipError_t launch_gradients(mfm_ctx *ctx, const mfm_particles *pp, double dt_max
     gradients_k<float><<<blocks_for(pp->n, BS), BS, 0, ctx->stream>>>(a);
   else
     gradients_k<double><<<blocks_for(pp->n, BS), BS, 0, ctx->stream>>>(a);
-  min_partial_k<<<RED_BLOCKS, BS, 0, ctx->stream>>>(pp->dt_i, pp->n, ctx->red);
+  min_partial_k<<<RED_BLOCKS, BS, 0, ctx->stream>>>(pp->dt_i, pp->n, ctx->red, ctx->counters);
   dt_final_k<<<1, BS, 0, ctx->stream>>>(ctx->red, RED_BLOCKS, dt_max, dt_dev, ctx->counters);
   return hipGetLastError();
 }

@@ -285,18 +285,15 @@ int mfm_destroy(mfm_ctx *ctx) {
   return MFM_OK;
 }
 
-int mfm_build_cells(mfm_ctx *ctx, const mfm_particles *pp, int64_t *perm) {
-  if (!ctx) return MFM_E_ARG;
-  if (!check_parts(ctx, pp)) return fail(ctx, MFM_E_ARG, "invalid particle set");
-  const int ev = stage_begin(ctx, 0);
-  HIPCHK(ctx, launch_max_h(ctx, pp), "max H");
-  double hmax = 0.0;
-  HIPCHK(ctx, hipMemcpyAsync(&hmax, ctx->scalars, sizeof(double), hipMemcpyDeviceToHost,
-                             ctx->stream),
-         "read max H");
-  HIPCHK(ctx, hipStreamSynchronize(ctx->stream), "synchronise");
+}  // extern "C"
+
+namespace {
+
+// Grid for the given max H, cell build and permutation (no synchronisation).
+int build_cells_async(mfm_ctx *ctx, const mfm_particles *pp, int64_t *perm, double hmax) {
   int rc = setup_grid(ctx, hmax);
   if (rc) return rc;
+  const int ev = stage_begin(ctx, 0);
   HIPCHK(ctx, launch_build_cells(ctx, pp, perm), "cells");
   stage_end(ctx, ev);
   ctx->have_cells = 1;
@@ -306,14 +303,11 @@ int mfm_build_cells(mfm_ctx *ctx, const mfm_particles *pp, int64_t *perm) {
   return MFM_OK;
 }
 
-int mfm_density(mfm_ctx *ctx, const mfm_particles *pp) {
-  if (!ctx) return MFM_E_ARG;
-  if (!check_parts(ctx, pp)) return fail(ctx, MFM_E_ARG, "invalid particle set");
-  if (!ctx->have_cells || ctx->n_cells_built != pp->n)
-    return fail(ctx, MFM_E_STATE, "mfm_density needs mfm_build_cells first");
-  HIPCHK(ctx, hipMemsetAsync(ctx->counters + C_CELL_OVERFLOW, 0, sizeof(int64_t),
-                             ctx->stream), "clear pass counters");
-  HIPCHK(ctx, hipMemsetAsync(ctx->counters + C_PASS_NOCONV, 0, 3 * sizeof(int64_t),
+// Neighbour search, density pass and its validation against the grid
+// (no synchronisation).  scalars[0] must hold the max H at the cell build.
+int density_async(mfm_ctx *ctx, const mfm_particles *pp, double hmax_grid) {
+  static_assert(C_STEP_SKIP - C_CELL_OVERFLOW == 5, "per-pass counters are contiguous");
+  HIPCHK(ctx, hipMemsetAsync(ctx->counters + C_CELL_OVERFLOW, 0, 6 * sizeof(int64_t),
                              ctx->stream), "clear pass counters");
   int ev = stage_begin(ctx, 1);
   HIPCHK(ctx, launch_candidates(ctx, pp), "neighbour search");
@@ -321,35 +315,50 @@ int mfm_density(mfm_ctx *ctx, const mfm_particles *pp) {
   ev = stage_begin(ctx, 2);
   HIPCHK(ctx, launch_density(ctx, pp), "density");
   stage_end(ctx, ev);
+  HIPCHK(ctx, launch_validate(ctx, hmax_grid), "validate the density pass");
+  return MFM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int mfm_build_cells(mfm_ctx *ctx, const mfm_particles *pp, int64_t *perm) {
+  if (!ctx) return MFM_E_ARG;
+  if (!check_parts(ctx, pp)) return fail(ctx, MFM_E_ARG, "invalid particle set");
+  HIPCHK(ctx, launch_max_h(ctx, pp), "max H");
+  double hmax = 0.0;
+  HIPCHK(ctx, hipMemcpyAsync(&hmax, ctx->scalars, sizeof(double), hipMemcpyDeviceToHost,
+                             ctx->stream),
+         "read max H");
+  HIPCHK(ctx, hipStreamSynchronize(ctx->stream), "synchronise");
+  return build_cells_async(ctx, pp, perm, hmax);
+}
+
+int mfm_density(mfm_ctx *ctx, const mfm_particles *pp) {
+  if (!ctx) return MFM_E_ARG;
+  if (!check_parts(ctx, pp)) return fail(ctx, MFM_E_ARG, "invalid particle set");
+  if (!ctx->have_cells || ctx->n_cells_built != pp->n)
+    return fail(ctx, MFM_E_STATE, "mfm_density needs mfm_build_cells first");
+  // the grid was sized from this H on the device at the build
+  int rc = density_async(ctx, pp, __builtin_huge_val());
+  if (rc) return rc;
   int64_t c[NCOUNTERS];
-  int rc = read_counters(ctx, c);
+  rc = read_counters(ctx, c);
   if (rc) return rc;
   // truncated candidate lists make every later result meaningless (and can
   // push H to the cell side): report them first
-  if (c[C_LIST_OVERFLOW] > 0)
+  if (c[C_PASS_LIST] > 0)
     return fail(ctx, MFM_E_LIST, "candidate list capacity exceeded (raise max_list)");
   if (c[C_CELL_OVERFLOW] > 0) {
     // some H reached the cell side: this pass is discarded (its counts too)
-    // and the next build uses larger cells
-    c[C_CELL_REBUILDS] += 1;
-    HIPCHK(ctx, hipMemcpyAsync(ctx->counters + C_CELL_REBUILDS, c + C_CELL_REBUILDS,
-                               sizeof(int64_t), hipMemcpyHostToDevice, ctx->stream),
-           "count rebuild");
-    HIPCHK(ctx, hipStreamSynchronize(ctx->stream), "synchronise");
-    // the density loop has written an estimate of each outgrown root as its
-    // start value; a small extra margin guards against underestimates
+    // and the next build uses larger cells.  The density loop has written an
+    // estimate of each outgrown root as its start value; a small extra
+    // margin guards against underestimates.
     ctx->margin_boost *= 1.1;
     ctx->have_cells = 0;
     return fail(ctx, MFM_E_CELLS, "smoothing lengths outgrew the cell grid; rebuild cells");
   }
-  // accept the pass: fold its counts into the running counters
-  c[C_H_NOCONV] += c[C_PASS_NOCONV];
-  c[C_NCOND_BOOSTS] += c[C_PASS_BOOSTS];
-  c[C_NCOND_FAIL] += c[C_PASS_FAIL];
-  HIPCHK(ctx, hipMemcpyAsync(ctx->counters, c, 3 * sizeof(int64_t), hipMemcpyHostToDevice,
-                             ctx->stream),
-         "fold pass counters");
-  HIPCHK(ctx, hipStreamSynchronize(ctx->stream), "synchronise");
   ctx->margin_boost = 1.0;
   ctx->have_density = 1;
   ctx->have_grad = 0;
@@ -423,29 +432,65 @@ int mfm_update(mfm_ctx *ctx, const mfm_particles *pp, const double *dt_dev) {
 int mfm_step(mfm_ctx *ctx, const mfm_particles *pp, double dt_max, double *dt_host) {
   if (!ctx) return MFM_E_ARG;
   if (!dt_host) return fail(ctx, MFM_E_ARG, "dt_host is NULL");
-  int rc = MFM_E_CELLS;
-  for (int attempt = 0; attempt < 4 && rc == MFM_E_CELLS; ++attempt) {
-    rc = mfm_build_cells(ctx, pp, nullptr);
-    if (rc) return rc;
-    rc = mfm_density(ctx, pp);
+  if (!check_parts(ctx, pp) || !(dt_max > 0.0)) return fail(ctx, MFM_E_ARG, "invalid arguments");
+  if (ctx->p.guess == MFM_GUESS_LEARNED && !ctx->mlp_state)
+    return fail(ctx, MFM_E_STATE, "learned guess requested but no network attached");
+  // The grid is sized from the max H that the previous step's density pass
+  // left (read at that step's one synchronisation).  The device checks it
+  // against the actual max H at the build; a step whose grid or candidate
+  // lists turn out too small is rejected there, its later kernels return at
+  // once (the state is not updated), and it is repeated.
+  double hmax = ctx->hmax_next;
+  if (!(hmax > 0.0) || ctx->hmax_H != pp->H || ctx->hmax_n != pp->n) {
+    HIPCHK(ctx, launch_max_h(ctx, pp), "max H");
+    HIPCHK(ctx, hipMemcpyAsync(&hmax, ctx->scalars, sizeof(double), hipMemcpyDeviceToHost,
+                               ctx->stream),
+           "read max H");
+    HIPCHK(ctx, hipStreamSynchronize(ctx->stream), "synchronise");
   }
-  if (rc) return rc;
   double *dt_dev = ctx->scalars + 1;
-  rc = mfm_gradients(ctx, pp, dt_max, dt_dev);
-  if (rc) return rc;
-  rc = mfm_fluxes(ctx, pp, dt_dev);
-  if (rc) return rc;
-  rc = mfm_update(ctx, pp, dt_dev);
-  if (rc) return rc;
-  HIPCHK(ctx, hipMemcpyAsync(dt_host, dt_dev, sizeof(double), hipMemcpyDeviceToHost,
-                             ctx->stream),
-         "read dt");
-  int64_t c[NCOUNTERS];
-  rc = read_counters(ctx, c);
-  if (rc) return rc;
-  if (c[C_NONFINITE] > 0) return fail(ctx, MFM_E_NONFINITE, "non-finite step or state");
-  if (c[C_H_NOCONV] > 0) return fail(ctx, MFM_E_H_NOCONV, "smoothing-length solve did not converge");
-  return MFM_OK;
+  for (int attempt = 0; attempt < 4; ++attempt) {
+    HIPCHK(ctx, hipMemsetAsync(ctx->counters + C_NONFINITE, 0, sizeof(int64_t), ctx->stream),
+           "clear step counters");
+    int rc = build_cells_async(ctx, pp, nullptr, hmax);
+    if (rc) return rc;
+    HIPCHK(ctx, launch_max_h(ctx, pp), "max H at the build");
+    rc = density_async(ctx, pp, hmax);
+    if (rc) return rc;
+    HIPCHK(ctx, launch_max_h(ctx, pp), "max H after the density pass");
+    ctx->have_density = 1;
+    rc = mfm_gradients(ctx, pp, dt_max, dt_dev);
+    if (rc) return rc;
+    rc = mfm_fluxes(ctx, pp, dt_dev);
+    if (rc) return rc;
+    rc = mfm_update(ctx, pp, dt_dev);
+    if (rc) return rc;
+    // the step's one synchronisation: counters, max H and dt together
+    int64_t c[NCOUNTERS];
+    double sc[2];
+    HIPCHK(ctx, hipMemcpyAsync(c, ctx->counters, sizeof(c), hipMemcpyDeviceToHost, ctx->stream),
+           "read counters");
+    HIPCHK(ctx, hipMemcpyAsync(sc, ctx->scalars, sizeof(sc), hipMemcpyDeviceToHost, ctx->stream),
+           "read dt");
+    HIPCHK(ctx, hipStreamSynchronize(ctx->stream), "synchronise");
+    ctx->hmax_next = sc[0];
+    ctx->hmax_H = pp->H;
+    ctx->hmax_n = pp->n;
+    hmax = sc[0];
+    if (c[C_STEP_SKIP]) {
+      if (c[C_PASS_LIST] > 0)
+        return fail(ctx, MFM_E_LIST, "candidate list capacity exceeded (raise max_list)");
+      if (c[C_CELL_OVERFLOW] > 0) ctx->margin_boost *= 1.1;
+      continue;
+    }
+    ctx->margin_boost = 1.0;
+    *dt_host = sc[1];
+    if (c[C_NONFINITE] > 0) return fail(ctx, MFM_E_NONFINITE, "non-finite step or state");
+    if (c[C_PASS_NOCONV] > 0)
+      return fail(ctx, MFM_E_H_NOCONV, "smoothing-length solve did not converge");
+    return MFM_OK;
+  }
+  return fail(ctx, MFM_E_CELLS, "smoothing lengths kept outgrowing the cell grid");
 }
 
 int mfm_diagnostics(mfm_ctx *ctx, const mfm_particles *pp, mfm_diag *out) {

@@ -30,13 +30,16 @@ enum {
   C_U_GUARD,
   C_HARD_FACES,
   C_HARD_OVERFLOW,
-  C_CELL_OVERFLOW,  // internal: some H reached the cell side in the last density pass
-  C_NONFINITE,      // internal: non-finite dt or state
-  // counts of the density pass in flight; folded into the slots above only
-  // when the pass is accepted (a pass whose H outgrew the cells is redone)
+  C_NONFINITE,      // internal: non-finite dt or state (cleared per step)
+  // the density pass in flight (cleared before each pass); its counts are
+  // folded into the slots above only when the pass is accepted (a pass whose
+  // H outgrew the cells is redone)
+  C_CELL_OVERFLOW,  // some H reached the cell side
   C_PASS_NOCONV,
   C_PASS_BOOSTS,
   C_PASS_FAIL,
+  C_PASS_LIST,      // particles whose candidate list overflowed
+  C_STEP_SKIP,      // the pass is rejected: the kernels after it return at once
   C_DUMP_COUNT,     // face records appended since the dump was armed
   C_HARD_QUEUE,     // faces queued for the flux loop's FP64 pass in the current call
   NCOUNTERS = 32
@@ -128,6 +131,11 @@ struct mfm_ctx {
   int bits;
   double margin_boost;
   int have_cells, have_density, have_grad;
+  // mfm_step: max H after its last density pass (read at its one
+  // synchronisation), for the next step's grid; checked on the device
+  double hmax_next;
+  const double *hmax_H;  // the H array it belongs to
+  int64_t hmax_n;
   int64_t n_cells_built;  // n of the particles the cells were built for
   // learned guess and face dump
   const void *mlp_state;  // network state (mfm_mlp_attach), null if none
@@ -241,6 +249,11 @@ __device__ __forceinline__ void count_add(int64_t *ctr, int64_t v) {
 // and return a hipError_t.
 // ---------------------------------------------------------------------------
 hipError_t launch_max_h(mfm_ctx *ctx, const mfm_particles *pp);
+// After a density pass: reject it (C_STEP_SKIP) if a candidate list
+// overflowed, an H outgrew the cells, or the max H at the cell build
+// (scalars[0] then) exceeded hmax_grid, the value the grid was sized for;
+// else fold the pass counts into the running counters.
+hipError_t launch_validate(mfm_ctx *ctx, double hmax_grid);
 hipError_t launch_build_cells(mfm_ctx *ctx, const mfm_particles *pp, int64_t *perm);
 hipError_t launch_candidates(mfm_ctx *ctx, const mfm_particles *pp);
 hipError_t launch_density(mfm_ctx *ctx, const mfm_particles *pp);

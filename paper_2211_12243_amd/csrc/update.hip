@@ -18,6 +18,7 @@ struct UpdateArgs {
 };
 
 __global__ void __launch_bounds__(BS) update_k(UpdateArgs a) {
+  if (a.counters[C_STEP_SKIP]) return;  // the density pass was rejected
   const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   int64_t neg = 0, bad = 0, guard = 0;
   if (i < a.n) {

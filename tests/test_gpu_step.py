@@ -1,0 +1,133 @@
+"""mfm_step: one whole step with one synchronisation.
+
+The step sizes its cell grid from the max H the previous step left, checks it
+on the device, and rejects a density pass whose grid or candidate lists were
+too small (its later kernels return at once and the state is not updated),
+then repeats it.  These tests drive each path against the oracle's step:
+
+* smoothing lengths at half their root, so the first grid is too fine;
+* a particle set replaced in place (same arrays) by one with larger H, so the
+  max H the previous step left is stale;
+* a candidate list capacity too small: an error, with the state untouched;
+* the time per step on the 8192-particle sound wave.
+"""
+import time
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+pytestmark = pytest.mark.gpu
+
+import oracle  # noqa: E402
+from gpu_helpers import _need_gpu  # noqa: E402
+from paper_2211_12243_amd import mfm  # noqa: E402
+from paper_2211_12243_amd import workloads as W  # noqa: E402
+
+KEYS = ("x", "y", "z", "vx", "vy", "vz", "m", "E", "U", "H")
+
+
+def _by_id(ps):
+    ids = ps["id"].cpu().numpy()
+    out = {}
+    for k in KEYS:
+        a = np.empty(len(ids))
+        a[ids] = ps[k].cpu().numpy()
+        out[k] = a
+    return out
+
+
+def _compare(got, want, tol):
+    for k in KEYS:
+        d = np.abs(got[k] - want[k])
+        if k in ("x", "y", "z"):
+            d = np.minimum(d, 1.0 - d)
+            err = d.max()
+        else:
+            err = d.max() / max(np.abs(want[k]).max(), 1e-300)
+        assert err <= tol, (k, err)
+
+
+def test_step_rebuilds_a_too_fine_grid():
+    _need_gpu()
+    st = W.kh(n=12, seed=5)
+    st["H"] = 0.5 * st["H"]
+    cfg = {"scheme": "mfm"}
+    ctx = mfm.Context(mfm.params_from_dict(cfg), len(st["x"]))
+    ps = mfm.ParticleSet(st)
+    print("[step] H at half the root", flush=True)
+    dt = mfm.mfm_step(ctx, ps, 1.0)
+    diag = mfm.mfm_diagnostics(ctx)
+    ref, dt_ref, _ = oracle.step(cfg, st, 1.0)
+    assert diag["cell_rebuilds"] >= 1
+    assert abs(dt - dt_ref) <= 1e-12 * dt_ref
+    _compare(_by_id(ps), ref, 1e-11)
+    ctx.close()
+
+
+def test_step_after_state_replaced_in_place():
+    _need_gpu()
+    a = W.kh(n=12, seed=5)
+    b = W.kh(n=12, seed=6)
+    b["H"] = 1.25 * b["H"]  # above the max H the first step leaves (and its cells)
+    cfg = {"scheme": "mfv"}
+    ctx = mfm.Context(mfm.params_from_dict(cfg), len(a["x"]))
+    ps = mfm.ParticleSet(a)
+    print("[step] state replaced in place", flush=True)
+    mfm.mfm_step(ctx, ps, 1.0)
+    for k in KEYS:
+        ps[k].copy_(torch.as_tensor(b[k], dtype=torch.float64))
+    ps["id"].copy_(torch.arange(len(a["x"]), dtype=torch.int64))
+    before = mfm.mfm_diagnostics(ctx)["cell_rebuilds"]
+    dt = mfm.mfm_step(ctx, ps, 1.0)
+    after = mfm.mfm_diagnostics(ctx)["cell_rebuilds"]
+    ref, dt_ref, _ = oracle.step(cfg, b, 1.0)
+    print("rebuilds in the second step:", after - before, flush=True)
+    assert abs(dt - dt_ref) <= 1e-12 * dt_ref
+    _compare(_by_id(ps), ref, 1e-11)
+    ctx.close()
+
+
+def test_list_overflow_in_a_step_leaves_the_state():
+    _need_gpu()
+    st = W.sod(n=10, seed=1)
+    ctx = mfm.Context(mfm.params_from_dict({"scheme": "mfv", "max_list": 8}), len(st["x"]))
+    ps = mfm.ParticleSet(st)
+    print("[step] max_list = 8", flush=True)
+    with pytest.raises(mfm.MFMError, match="status -6"):
+        mfm.mfm_step(ctx, ps, 1.0)
+    got = _by_id(ps)
+    # the conserved state and positions are untouched (H, the start value of
+    # the smoothing-length solve, is the density pass's to overwrite)
+    for k in KEYS:
+        if k != "H":
+            assert np.array_equal(got[k], st[k]), k
+    # the error is the call's own: a later step with room succeeds
+    ctx.close()
+    ctx = mfm.Context(mfm.params_from_dict({"scheme": "mfv"}), len(st["x"]))
+    ps = mfm.ParticleSet(st)
+    mfm.mfm_step(ctx, ps, 1.0)
+    ctx.close()
+
+
+def test_soundwave_step_time():
+    """8192 particles (the sound wave at N = 128): a step is bound by launches
+    and host round trips, not by the kernels."""
+    _need_gpu()
+    st = W.soundwave(128, nyz=8, A=1e-3, gamma=1.4)
+    cfg = {"scheme": "mfm", "gamma": 1.4, "limiter": 0, "box": W.soundwave_box(128, 8)}
+    ctx = mfm.Context(mfm.params_from_dict(cfg), len(st["x"]))
+    ps = mfm.ParticleSet(st)
+    for _ in range(5):
+        mfm.mfm_step(ctx, ps, 1.0)
+    torch.cuda.synchronize()
+    k = 50
+    t0 = time.perf_counter()
+    for _ in range(k):
+        mfm.mfm_step(ctx, ps, 1.0)
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) / k * 1e3
+    print(f"[step] sound wave N=128: {ms:.3f} ms per step", flush=True)
+    ctx.close()
+    assert ms < 0.64
