@@ -170,6 +170,26 @@ int mfm_create(const mfm_params *p, int64_t n_max, void *workspace, size_t works
                void *stream, struct mfm_ctx **out);
 int mfm_destroy(struct mfm_ctx *ctx);
 
+/* For callers that cannot allocate device memory -- code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc: a context
+ * like mfm_create's whose workspace is the library's own static device array
+ * on the current GPU (mfm_static_workspace_bytes() = 64 MiB; each GPU the
+ * library runs on holds one until the process ends).  The call allocates
+ * nothing: no hipMalloc, no library allocator.  The caller still owns the
+ * particle arrays.
+ *   - Limit: mfm_workspace_bytes(p, n_max) must fit in the array (about
+ *     15 000 particles at max_list 128 with max_cell_dim 32; the cell tables
+ *     grow with max_cell_dim^3); larger requests return MFM_E_WORKSPACE.
+ *   - One such context per GPU at a time (MFM_E_STATE while one exists;
+ *     mfm_destroy releases it).  All its calls share the GPU's array, which
+ *     keeps the last call's contents: calls that overlap on one GPU race.
+ *   - Counters start at zero; every other part of the array is written
+ *     before it is read.
+ * Returns MFM_E_ARG for invalid parameters, MFM_E_HIP if the device or the
+ * array's address cannot be obtained. */
+size_t mfm_static_workspace_bytes(void);
+int mfm_create_static(const mfm_params *p, int64_t n_max, void *stream, struct mfm_ctx **out);
+
 /* Sort the particles into cells on a Morton (Z-order) curve of cells of side
  * >= cell_margin * max H (sec. 2.2.1: particles are reordered in memory so
  * that spatial neighbours are contiguous) and permute the state arrays

@@ -5,6 +5,8 @@
 #include <stdlib.h>
 #include <string.h>
 
+#include <mutex>
+
 #include "mfm_internal.h"
 
 namespace {
@@ -222,16 +224,15 @@ size_t mfm_workspace_bytes(const mfm_params *p, int64_t n_max) {
   return make_layout(p, n_max).total;
 }
 
-int mfm_create(const mfm_params *p, int64_t n_max, void *workspace, size_t workspace_bytes,
-               void *stream, mfm_ctx **out) {
-  if (!out) return MFM_E_ARG;
-  *out = nullptr;
-  if (!check_params(p) || n_max <= 0 || n_max > 0x7fffffff) return MFM_E_ARG;
+}  // extern "C"
+
+namespace {
+
+// Fill a zeroed context: parameters, stream and the carve of its workspace;
+// clear its counters.
+int init_ctx(mfm_ctx *ctx, const mfm_params *p, int64_t n_max, void *workspace,
+             size_t workspace_bytes, void *stream) {
   Layout L = make_layout(p, n_max);
-  if (!workspace || workspace_bytes < L.total || ((uintptr_t)workspace % ALIGN) != 0)
-    return MFM_E_WORKSPACE;
-  mfm_ctx *ctx = (mfm_ctx *)calloc(1, sizeof(mfm_ctx));
-  if (!ctx) return MFM_E_ARG;
   ctx->p = *p;
   ctx->n_max = n_max;
   ctx->stream = (hipStream_t)stream;
@@ -266,12 +267,75 @@ int mfm_create(const mfm_params *p, int64_t n_max, void *workspace, size_t works
   ctx->scan_tmp_len = L.scan_len;
   ctx->margin_boost = 1.0;
   ctx->dump_count = reinterpret_cast<unsigned long long *>(ctx->counters + C_DUMP_COUNT);
+  // counters start at zero whatever the workspace held (the static scratch
+  // keeps the last context's contents)
   hipError_t e = hipMemsetAsync(ctx->counters, 0, sizeof(int64_t) * NCOUNTERS, ctx->stream);
   if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
-  if (e != hipSuccess) {
+  return e == hipSuccess ? MFM_OK : MFM_E_HIP;
+}
+
+// ---------------------------------------------------------------------------
+// The workspace of mfm_create_static: a file-scope device array.  Each GPU
+// holds its own copy for the life of the process; host code reaches it only
+// through the device address hipGetSymbolAddress returns for that GPU (the
+// array's name is a host-side stand-in).  One context per GPU may use it at
+// a time; its host context lives in static storage too.
+// ---------------------------------------------------------------------------
+constexpr size_t STATIC_SCRATCH_BYTES = (size_t)64 << 20;
+constexpr int STATIC_MAX_DEVICES = 16;
+__device__ __align__(256) char scratch[STATIC_SCRATCH_BYTES];
+void *scratch_dev[STATIC_MAX_DEVICES];        // device address per GPU, 0 until looked up
+mfm_ctx static_ctx[STATIC_MAX_DEVICES];       // host context per GPU
+int static_busy[STATIC_MAX_DEVICES];
+std::mutex static_mu;
+
+}  // namespace
+
+extern "C" {
+
+int mfm_create(const mfm_params *p, int64_t n_max, void *workspace, size_t workspace_bytes,
+               void *stream, mfm_ctx **out) {
+  if (!out) return MFM_E_ARG;
+  *out = nullptr;
+  if (!check_params(p) || n_max <= 0 || n_max > 0x7fffffff) return MFM_E_ARG;
+  Layout L = make_layout(p, n_max);
+  if (!workspace || workspace_bytes < L.total || ((uintptr_t)workspace % ALIGN) != 0)
+    return MFM_E_WORKSPACE;
+  mfm_ctx *ctx = (mfm_ctx *)calloc(1, sizeof(mfm_ctx));
+  if (!ctx) return MFM_E_ARG;
+  int rc = init_ctx(ctx, p, n_max, workspace, workspace_bytes, stream);
+  if (rc) {
     free(ctx);
-    return MFM_E_HIP;
+    return rc;
   }
+  *out = ctx;
+  return MFM_OK;
+}
+
+size_t mfm_static_workspace_bytes(void) { return STATIC_SCRATCH_BYTES; }
+
+int mfm_create_static(const mfm_params *p, int64_t n_max, void *stream, mfm_ctx **out) {
+  if (!out) return MFM_E_ARG;
+  *out = nullptr;
+  if (!check_params(p) || n_max <= 0 || n_max > 0x7fffffff) return MFM_E_ARG;
+  if (make_layout(p, n_max).total > STATIC_SCRATCH_BYTES) return MFM_E_WORKSPACE;
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= STATIC_MAX_DEVICES)
+    return MFM_E_HIP;
+  std::lock_guard<std::mutex> lock(static_mu);
+  if (static_busy[dev]) return MFM_E_STATE;
+  if (!scratch_dev[dev]) {
+    // once per GPU, with that GPU current: the device address of its copy
+    void *ptr = nullptr;
+    if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess || !ptr) return MFM_E_HIP;
+    scratch_dev[dev] = ptr;
+  }
+  mfm_ctx *ctx = &static_ctx[dev];
+  memset(ctx, 0, sizeof(*ctx));
+  int rc = init_ctx(ctx, p, n_max, scratch_dev[dev], STATIC_SCRATCH_BYTES, stream);
+  if (rc) return rc;
+  ctx->static_dev = dev + 1;
+  static_busy[dev] = 1;
   *out = ctx;
   return MFM_OK;
 }
@@ -281,6 +345,12 @@ int mfm_destroy(mfm_ctx *ctx) {
   hipStreamSynchronize(ctx->stream);
   if (ctx->ev_created)
     for (int q = 0; q < 2 * MAX_EVENT_PAIRS; ++q) hipEventDestroy(ctx->ev_pool[q]);
+  if (ctx->static_dev) {
+    std::lock_guard<std::mutex> lock(static_mu);
+    static_busy[ctx->static_dev - 1] = 0;
+    ctx->static_dev = 0;
+    return MFM_OK;
+  }
   free(ctx);
   return MFM_OK;
 }

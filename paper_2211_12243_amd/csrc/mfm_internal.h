@@ -150,6 +150,7 @@ struct mfm_ctx {
   int ev_used;
   double stage_ms[MFM_NSTAGES];
   int64_t stage_count[MFM_NSTAGES];
+  int static_dev;  // 1 + the GPU whose static scratch this context uses (0: caller's workspace)
   char err[512];
 };
 

@@ -89,6 +89,10 @@ def lib():
         L.mfm_create.argtypes = [P, ctypes.c_int64, _PTR, ctypes.c_size_t, _PTR,
                                  ctypes.POINTER(_PTR)]
         L.mfm_destroy.argtypes = [C]
+        L.mfm_create_static.argtypes = [P, ctypes.c_int64, _PTR, ctypes.POINTER(_PTR)]
+        L.mfm_create_static.restype = ctypes.c_int
+        L.mfm_static_workspace_bytes.argtypes = []
+        L.mfm_static_workspace_bytes.restype = ctypes.c_size_t
         L.mfm_build_cells.argtypes = [C, PP, _PTR]
         L.mfm_density.argtypes = [C, PP]
         L.mfm_gradients.argtypes = [C, PP, ctypes.c_double, _PTR]
@@ -132,6 +136,7 @@ def lib():
 
 
 EXPORTED = ("mfm_default_params", "mfm_workspace_bytes", "mfm_create", "mfm_destroy",
+            "mfm_create_static", "mfm_static_workspace_bytes",
             "mfm_build_cells", "mfm_density", "mfm_gradients", "mfm_fluxes", "mfm_update",
             "mfm_step", "mfm_diagnostics", "mfm_reset_counters", "mfm_enable_timing",
             "mfm_kernel_times", "mfm_strerror", "mfm_last_error", "mfm_mlp_state_bytes",
@@ -212,22 +217,30 @@ class ParticleSet:
 class Context:
     """A libmfm context with its workspace tensor, bound to one stream."""
 
-    def __init__(self, params: mfm_params, n_max: int, stream=None, device="cuda"):
+    def __init__(self, params: mfm_params, n_max: int, stream=None, device="cuda",
+                 static: bool = False):
         L = lib()
         self.params = params
         self.n_max = int(n_max)
+        self.stream = stream if stream is not None else torch.cuda.current_stream(device)
+        self.h = ctypes.c_void_p()
+        self.dt_dev = torch.zeros(1, dtype=torch.float64, device=device)
+        if static:
+            # the library's own device scratch: mfm_create_static allocates nothing
+            self.ws = None
+            _check(L.mfm_create_static(ctypes.byref(params), self.n_max,
+                                       ctypes.c_void_p(self.stream.cuda_stream),
+                                       ctypes.byref(self.h)))
+            return
         nbytes = L.mfm_workspace_bytes(ctypes.byref(params), self.n_max)
         if nbytes == 0:
             raise MFMError("invalid parameters (mfm_workspace_bytes returned 0)")
         self.ws = torch.empty(nbytes + 256, dtype=torch.uint8, device=device)
         base = self.ws.data_ptr()
         self.ws_ptr = (base + 255) // 256 * 256
-        self.stream = stream if stream is not None else torch.cuda.current_stream(device)
-        self.h = ctypes.c_void_p()
         _check(L.mfm_create(ctypes.byref(params), self.n_max, ctypes.c_void_p(self.ws_ptr),
                             nbytes, ctypes.c_void_p(self.stream.cuda_stream),
                             ctypes.byref(self.h)))
-        self.dt_dev = torch.zeros(1, dtype=torch.float64, device=device)
 
     def close(self):
         if self.h:
