@@ -7,25 +7,28 @@ neighbour search, density / smoothing-length loop, gradients + time step,
 fluxes, update -- the whole hot path, inputs resident in HBM.
 
 Variants, each from the same initial set with the same warm-up:
-  fp64           all pair arithmetic in FP64;
-  mixed          FP32 pair arithmetic, FP64 accumulators and checks;
+  fp64           all pair arithmetic in FP64 (the paper's precision);
+  mixed          FP32 pair arithmetic, FP64 accumulators and checks, faces
+                 across strong jumps in FP64;
   mixed_learned  mixed, with the Riemann iteration started from the guess
                  network (trained first, on faces dumped from other sets).
-The reported value is the headline variant's (default mixed: FP32 pair
-arithmetic with FP64 accumulators, 1e-5 parity with the FP64 oracle); every
-variant's rate and stage times are in "variants".
+The reported value is the headline variant's (default fp64); every variant's
+rate, stage times and per-kernel roofline fractions are in "variants".
 
 Metric: pair interactions per second over the gradient and flux loops,
 (gradient pairs + flux faces) / (t_gradients + t_fluxes), with the loop times
-from HIP events the library records on its own stream; ms per full step is
-reported beside it.
+from HIP events the library records on its own stream (the flux loop's time
+covers both of its passes and the clear and fold of its partial sums); ms per
+full step is reported beside it.
 
 The JSON line also carries
-  roofline     -- the dominant kernel (the flux loop) against the vector ALU
-                  peak: algorithmic flops per launch / mean launch time;
+  roofline     -- the dominant kernel (the flux loop's first pass, fluxes_k)
+                  against the vector ALU peak: the oracle's operation count
+                  per face times the faces it solves, over its mean launch time;
   cpu_baseline -- the FP64 CPU oracle timed on the host on one full step of
-                  the same particle set (density, gradients, fluxes), all
-                  host threads.
+                  the same particle set (density, gradients, fluxes) with all
+                  host threads, single-thread steps of two smaller sets, the
+                  CPU model, and each field's error at step 1 against it.
 """
 from __future__ import annotations
 
@@ -38,16 +41,28 @@ import time
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-# Algorithmic FP64 operations per face of the flux loop (add, sub, mul, div,
-# sqrt and pow count 1, a fused multiply-add 2; comparisons and selects 0).
-# The count runs over the stages of one face: separation and kernel weights,
-# A_ij, half-step prediction and extrapolation, pairwise limiter, face-frame
-# states, Riemann set-up, sampling (MFV) and flux assembly, accumulation; each
-# Newton iteration of the Riemann solve adds FLOPS_NEWTON_ITER.
-FLOPS_FACE = {"mfm": 388, "mfv": 458}
-FLOPS_NEWTON_ITER = 30
+# Algorithmic work of the loops, from the oracle's operation counter
+# (oracle/opcount.cpp: the oracle compiled with a number type that counts
+# every add, multiply, divide, square root and power; python -m
+# oracle.opcount 128 prints these; tests/test_opcount.py checks them):
+# flops per face of the flux loop, mean over a 20000-face sample of the first
+# step of the 128^3 Sedov set (Newton iterations included), and flops per
+# ordered pair of the gradient loop (limiter and time step included).
+FLOPS_PER_FACE = {"mfm": 458.29, "mfv": 545.29}
+FLOPS_PER_GRAD_PAIR = 151.0
+# Algorithmic HBM bytes per particle: the fields a loop must read and write
+# once (FP64 path):
+#   cells     key + order (8 B), gather and write-back of the 11-double state
+#             (176 B), cell tables: 184 B
+#   density   x, y, z, H read, H, V, rho, P, c, ncond written: 80 B
+#   gradients the density loop's record (11 doubles) read, B (6), grad (15),
+#             dt_i, ncond written: 288 B
+#   fluxes    B, grad, primitives, position, V, 1/H read (32 doubles), dQ (5)
+#             written: 296 B
+BYTES_PER_PARTICLE = {"cells": 184, "density": 80, "gradients": 288, "fluxes": 296}
 PEAK_FP64_TFLOPS = 78.6
 PEAK_FP32_TFLOPS = 157.3
+PEAK_HBM_TBS = 8.0
 
 
 VARIANTS = ("fp64", "mixed", "mixed_learned")
@@ -56,12 +71,12 @@ VARIANTS = ("fp64", "mixed", "mixed_learned")
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=10)
-    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--n", type=int, default=128, help="particles per axis")
     ap.add_argument("--variants", default=",".join(VARIANTS),
                     help="comma-separated subset of " + ", ".join(VARIANTS))
-    ap.add_argument("--headline", default="mixed", choices=VARIANTS,
+    ap.add_argument("--headline", default="fp64", choices=VARIANTS,
                     help="variant whose rate is the reported value")
     ap.add_argument("--scheme", default="mfm", choices=["mfm", "mfv"])
     ap.add_argument("--train-steps", type=int, default=800)
@@ -105,8 +120,70 @@ def log(msg, args):
         print(msg, file=sys.stderr, flush=True)
 
 
-def cpu_baseline(st, scheme):
-    """The oracle (unchanged) on one step of the same set; pair interactions/s."""
+SINGLE_THREAD_SNIPPET = """
+import json, sys, time
+sys.path.insert(0, %r)
+import oracle
+from paper_2211_12243_amd import workloads as W
+out = {}
+for name, st, cfg in (("sod16_mfv", W.sod(n=16, seed=1), {"scheme": "mfv"}),
+                      ("kh64_mfv", W.kh(n=64, seed=2), {"scheme": "mfv"})):
+    t0 = time.perf_counter()
+    oracle.step(cfg, st, 1.0)
+    out[name] = time.perf_counter() - t0
+print(json.dumps(out))
+"""
+
+
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def field_errors(gpu, d, g, f, mixed):
+    """Step-1 error of each field against the oracle: max_i |gpu - ref| over
+    max_i |ref| per field (gradients per field as vectors, B as a matrix);
+    the flux sums per particle against the particle's own scales (mixed:
+    momentum against |s_p|, energy against s_E + c |s_p|)."""
+    import numpy as np
+
+    def rel(a, b):
+        den = np.abs(b).max()
+        return float(np.abs(a - b).max() / den) if den > 0 else float(np.abs(a - b).max())
+
+    ref = {"H": d["H"], "V": d["V"], "rho": g["rho"], "P": g["P"], "c": g["c"],
+           "ncond": g["ncond"], "dt_i": g["dt_i"]}
+    out = {k: rel(gpu[k], v) for k, v in ref.items()}
+    out["B"] = rel(gpu["B"], g["B"])
+    out["grad"] = max(rel(gpu["grad"][3 * q:3 * q + 3], g["grad"][3 * q:3 * q + 3])
+                      for q in range(5))
+    s = f["scale"]
+    diff = np.abs(gpu["dQ"] - f["dQ"])
+    den = s.copy()
+    if mixed:
+        sp = np.sqrt((s[1:4] ** 2).sum(0))
+        den[1:4] = sp[None, :]
+        den[4] = s[4] + g["c"] * sp
+    names = ("dQ_mass", "dQ_px", "dQ_py", "dQ_pz", "dQ_E")
+    for k in range(5):
+        m = den[k] > 0
+        out[names[k]] = float((diff[k][m] / den[k][m]).max()) if m.any() else 0.0
+    return out
+
+
+def cpu_baseline(st, scheme, step1_fields):
+    """The oracle (unchanged) on one step of the same set; pair interactions/s.
+    Also: the single-thread time of one oracle step of the 16^3 shock tube and
+    the 64^3 shear layers (a child process with one OpenMP thread), the CPU
+    model, and the GPU variants' step-1 errors against this step."""
+    import subprocess
+
     import numpy as np
 
     import oracle
@@ -124,15 +201,54 @@ def cpu_baseline(st, scheme):
     t3 = time.perf_counter()
     pairs = c2["grad_pairs"] + c3["faces"]
     threads = int(os.environ.get("OMP_NUM_THREADS", 0)) or len(os.sched_getaffinity(0))
+    env = dict(os.environ, OMP_NUM_THREADS="1")
+    single = None
+    try:
+        r = subprocess.run([sys.executable, "-c", SINGLE_THREAD_SNIPPET % ROOT], env=env,
+                           capture_output=True, text=True, timeout=120)
+        if r.returncode == 0:
+            single = {k + "_step_s": v for k, v in json.loads(r.stdout.strip().splitlines()[-1]).items()}
+    except (subprocess.TimeoutExpired, ValueError, IndexError):
+        single = None
+    errors = {v: field_errors(fl, d, g, f, v != "fp64") for v, fl in step1_fields.items()}
     return {
         "value": pairs / ((t2 - t1) + (t3 - t2)),
         "unit": "pair interactions/s",
         "cores": threads,
         "kind": "oracle",
+        "cpu_model": cpu_model(),
         "sample": (f"one step (density, gradients, fluxes) of the full {len(st['x'])}-particle "
                    f"set; density {t1 - t0:.2f} s, gradients {t2 - t1:.2f} s, "
                    f"fluxes {t3 - t2:.2f} s"),
+        "single_thread": single,
+        "step1_errors": errors,
     }
+
+
+def step1_fields(args, st, variant):
+    """The GPU's fields after density, gradients and fluxes of the first step
+    (host copies, original particle order), for the comparison with the oracle."""
+    import numpy as np
+    import torch
+
+    from paper_2211_12243_amd import mfm
+
+    precision = "fp64" if variant == "fp64" else "mixed"
+    ctx = mfm.Context(mfm.params_from_dict({"scheme": args.scheme}, precision=precision),
+                      len(st["x"]))
+    ps = mfm.ParticleSet(st)
+    mfm.run_pipeline(ctx, ps, 1.0, update=False)
+    torch.cuda.synchronize()
+    ids = ps["id"].cpu().numpy()
+    out = {}
+    for k in ("H", "V", "rho", "P", "c", "ncond", "dt_i", "B", "grad", "dQ"):
+        t = ps[k].cpu().numpy()
+        a = np.empty_like(t)
+        a[..., ids] = t
+        out[k] = a
+    ctx.close()
+    del ps
+    return out
 
 
 def train_guess(args, log_):
@@ -225,28 +341,52 @@ def run_variant(args, st, variant, mlp_state, log_):
     t1 = time.perf_counter()
     times = mfm.mfm_kernel_times(ctx)
     diag = mfm.mfm_diagnostics(ctx, ps)
+    diag["n"] = ps.n
     ctx.close()
     K = args.steps
     t_grad = times["gradients"][0] / 1e3
-    t_flux = times["fluxes"][0] / 1e3
+    t_flux = times["fluxes"][0] / 1e3  # the whole flux loop: both passes, clear and fold
     pairs = diag["grad_pairs"] + diag["faces"]
-    n_launch = max(times["fluxes"][1], 1)
-    mean_s = t_flux / n_launch
-    flops_launch = (diag["faces"] * FLOPS_FACE[args.scheme]
-                    + diag["riemann_iters"] * FLOPS_NEWTON_ITER) / n_launch
     peak = PEAK_FP64_TFLOPS if precision == "fp64" else PEAK_FP32_TFLOPS
-    achieved = flops_launch / mean_s / 1e12
+    N = diag["n"]
+
+    def mean_launch(stage):
+        return times[stage][0] / 1e3 / max(times[stage][1], 1)
+
+    # the dominant kernel: the flux loop's first pass (every face but those
+    # handed to the FP64 second pass), op-counted flops per launch
+    n_launch = max(times["flux_kernel"][1], 1)
+    faces_main = (diag["faces"] - diag["hard_faces"]) / n_launch
+    t_main = mean_launch("flux_kernel")
+    flops_main = faces_main * FLOPS_PER_FACE[args.scheme]
+    achieved = flops_main / t_main / 1e12
+    kernels = {}
+    for stage, unit_flops in (("gradients", FLOPS_PER_GRAD_PAIR * diag["grad_pairs"] / K),
+                              ("fluxes", FLOPS_PER_FACE[args.scheme] * diag["faces"] / K),
+                              ("density", None), ("cells", None)):
+        t = times[stage][0] / 1e3 / K
+        hbm = BYTES_PER_PARTICLE[stage] * N / t / 1e12
+        e = {"ms": t * 1e3, "hbm_TBs": hbm, "hbm_frac": hbm / PEAK_HBM_TBS}
+        if unit_flops is not None:
+            e["TFLOPs"] = unit_flops / t / 1e12
+            e["valu_frac"] = e["TFLOPs"] / peak
+        e["frac"] = max(e.get("valu_frac", 0.0), e["hbm_frac"])
+        kernels[stage] = e
+    kernels["search"] = {"ms": times["search"][0] / K}
     res = {
         "value": pairs / (t_grad + t_flux),
         "ms_per_step": (t1 - t0) / K * 1e3,
         "stage_ms_per_step": {k: v[0] / K for k, v in times.items()},
         "pairs_per_step": {"gradient": diag["grad_pairs"] / K, "flux_faces": diag["faces"] / K},
         "newton_iters_per_face": diag["riemann_iters"] / max(diag["faces"], 1),
+        "fp64_pass_faces_frac": diag["hard_faces"] / max(diag["faces"], 1),
         "guess_fallback_frac": diag["guess_fallback"] / max(diag["faces"], 1),
         "roofline": {"bound": "alu", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
                      "frac": achieved / peak, "traffic": flux_traffic(variant),
-                     "kernel": "fluxes_k",
-                     "mean_launch_ms": mean_s * 1e3, "flops_per_launch": flops_launch},
+                     "kernel": "fluxes_k", "mean_launch_ms": t_main * 1e3,
+                     "flops_per_launch": flops_main,
+                     "flops_per_face": FLOPS_PER_FACE[args.scheme]},
+        "kernels": kernels,
         "conserved_after": {k: diag[k] for k in ("mass", "px", "py", "pz", "energy")},
     }
     log_(f"[bench] {variant}: {res}")
@@ -314,14 +454,16 @@ def main():
                    "variant": args.headline, "n_ngb": 32, "gamma": 5.0 / 3.0},
         "roofline": h["roofline"],
         "variants": {v: {k: r[k] for k in ("value", "ms_per_step", "stage_ms_per_step",
-                                           "newton_iters_per_face", "guess_fallback_frac")}
+                                           "newton_iters_per_face", "fp64_pass_faces_frac",
+                                           "guess_fallback_frac", "kernels")}
                      for v, r in res.items()},
         "pairs_per_step": h["pairs_per_step"],
         "guess_training": train_info,
     }
     if not args.no_cpu_baseline:
+        fields = {v: step1_fields(args, st, v) for v in ("fp64", "mixed") if v in variants}
         log_("[bench] timing the CPU oracle on one step of the same set")
-        out["cpu_baseline"] = cpu_baseline(st, args.scheme)
+        out["cpu_baseline"] = cpu_baseline(st, args.scheme, fields)
     else:
         out["cpu_baseline"] = None
     print(json.dumps(out), flush=True)
