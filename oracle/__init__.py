@@ -47,6 +47,17 @@ class Params(ctypes.Structure):
         ("psi1", ctypes.c_double), ("psi2", ctypes.c_double),
         ("riemann_tol", ctypes.c_double), ("alpha1", ctypes.c_double),
         ("box", ctypes.c_double * 3),
+        ("alpha2", ctypes.c_double), ("alpha3", ctypes.c_double),
+        ("entropy_switch", ctypes.c_int32), ("pad1", ctypes.c_int32),
+    ]
+
+
+class Sources(ctypes.Structure):
+    """Source terms of one step (sec. 2.3.7-2.3.9)."""
+    _fields_ = [
+        ("accel", ctypes.c_void_p), ("inv_a", ctypes.c_double),
+        ("hubble_n", ctypes.c_double), ("hubble_np1", ctypes.c_double),
+        ("S", ctypes.c_void_p), ("emode", ctypes.c_void_p),
     ]
 
 
@@ -78,6 +89,9 @@ def make_params(cfg: dict) -> Params:
     p.psi2 = float(cfg.get("psi2", 0.25))
     p.riemann_tol = float(cfg.get("riemann_tol", 1e-10))
     p.alpha1 = float(cfg.get("alpha1", 0.01))
+    p.alpha2 = float(cfg.get("alpha2", 1e-3))
+    p.alpha3 = float(cfg.get("alpha3", 1e-3))
+    p.entropy_switch = int(cfg.get("entropy_switch", 0))
     box = cfg.get("box", (1.0, 1.0, 1.0))
     for k in range(3):
         p.box[k] = float(box[k])
@@ -149,6 +163,17 @@ def _bind(L):
     L.orc_fluxes.argtypes = [P, i64] + [_D] * 12 + [ctypes.c_double, _D, _D, C]
     L.orc_update.argtypes = [P, i64] + [_D] * 9 + [_D, ctypes.c_double, C]
     L.orc_step.argtypes = [P, i64] + [_D] * 10 + [ctypes.c_double, _D, C]
+    SP = ctypes.POINTER(Sources)
+    L.orc_fluxes_src.argtypes = ([P, i64] + [_D] * 12 + [ctypes.c_double, ctypes.c_double, _D,
+                                 _D, _D, C])
+    L.orc_ekin_max.argtypes = [P, i64] + [_D] * 8
+    L.orc_entropy_pressure.argtypes = [P, i64, _D, _D, _D, _D, _I32]
+    L.orc_update_src.argtypes = ([P, i64] + [_D] * 9 + [_D, ctypes.c_double, SP, _D, _D, _D, _D,
+                                 C])
+    L.orc_step_src.argtypes = [P, i64] + [_D] * 10 + [ctypes.c_double, SP, _D, C]
+    for f in ("orc_fluxes_src", "orc_ekin_max", "orc_entropy_pressure", "orc_update_src",
+              "orc_step_src"):
+        getattr(L, f).restype = ctypes.c_int
     for f in ("orc_neighbours", "orc_density", "orc_gradients", "orc_riemann",
               "orc_riemann_sample", "orc_face", "orc_fluxes", "orc_update", "orc_step"):
         getattr(L, f).restype = ctypes.c_int
@@ -335,3 +360,104 @@ def pipeline(cfg: dict, state: dict, dt_max: float):
     out = {"density": d, "gradients": g, "fluxes": f, "dt": dt, "state": new,
            "counters": counters}
     return out
+
+
+# --- source terms (sec. 2.3.7-2.3.9) -------------------------------------------------------
+
+def _opt(a):
+    return a.ctypes.data_as(_D) if a is not None else None
+
+
+def make_sources(n, accel=None, inv_a=1.0, hubble=(0.0, 0.0), S=None, emode=None):
+    """Sources struct plus the numpy arrays it points at (kept alive by the caller)."""
+    src = Sources()
+    keep = {}
+    if accel is not None:
+        keep["accel"] = _f64(accel).reshape(3, n)
+        src.accel = keep["accel"].ctypes.data
+    src.inv_a = float(inv_a)
+    src.hubble_n, src.hubble_np1 = float(hubble[0]), float(hubble[1])
+    if S is not None:
+        keep["S"] = S
+        src.S = S.ctypes.data
+        keep["emode"] = emode
+        src.emode = emode.ctypes.data
+    return src, keep
+
+
+def step_src(cfg: dict, state: dict, dt_max: float, accel=None, inv_a=1.0, hubble=(0.0, 0.0),
+             S=None, emode=None):
+    """One full step with source terms on a copy of ``state``; S (float64) and
+    emode (int32) arrays, when given, are updated in place.  Returns
+    (new_state, dt, counters)."""
+    p = make_params(cfg)
+    s = {k: _f64(state[k]).copy() for k in STATE_KEYS}
+    n = s["x"].size
+    src, keep = make_sources(n, accel, inv_a, hubble, S, emode)
+    dt = ctypes.c_double()
+    cnt = Counters()
+    rc = lib().orc_step_src(ctypes.byref(p), n, *[_p(s[k]) for k in STATE_KEYS], float(dt_max),
+                            ctypes.byref(src), ctypes.byref(dt), ctypes.byref(cnt))
+    if rc:
+        raise RuntimeError(f"orc_step_src failed: {rc}")
+    return s, dt.value, cnt.as_dict()
+
+
+def ekin_max(cfg: dict, x, y, z, H, m, vx, vy, vz):
+    """E_kin^max_i = max_j 1/2 m_i |v_j - v_i|^2 over r_ij < H_i (sec. 2.3.7)."""
+    p = make_params(cfg)
+    arrs = [_f64(a) for a in (x, y, z, H, m, vx, vy, vz)]
+    out = np.empty(arrs[0].size)
+    rc = lib().orc_ekin_max(ctypes.byref(p), arrs[0].size, *[_p(a) for a in arrs], _p(out))
+    assert rc == 0
+    return out
+
+
+def fluxes_src(cfg: dict, x, y, z, H, V, rho, vx, vy, vz, P, B, grad, dt, inv_a=1.0,
+               gwork=False):
+    """Flux loop with the comoving factor; returns dQ, scale and (if asked)
+    gwork[3, n] = sum_j dm_ij (x_j - x_i)."""
+    p = make_params(cfg)
+    arrs = [_f64(a) for a in (x, y, z, H, V, rho, vx, vy, vz, P)]
+    B = _f64(B)
+    grad = _f64(grad)
+    n = arrs[0].size
+    dQ = np.empty((5, n))
+    scale = np.empty((5, n))
+    gw = np.empty((3, n)) if gwork else None
+    cnt = Counters()
+    rc = lib().orc_fluxes_src(ctypes.byref(p), n, *[_p(a) for a in arrs], _p(B), _p(grad),
+                              float(dt), float(inv_a), _p(dQ), _p(scale), _opt(gw),
+                              ctypes.byref(cnt))
+    if rc:
+        raise RuntimeError(f"orc_fluxes_src failed: {rc}")
+    return {"dQ": dQ, "scale": scale, "gwork": gw}, cnt.as_dict()
+
+
+def update_src(cfg: dict, state: dict, dQ, dt, accel=None, inv_a=1.0, hubble=(0.0, 0.0),
+               S=None, emode=None, gwork=None, ekin_max=None, V=None, H=None):
+    """Close of the step with source terms on a copy of ``state``."""
+    p = make_params(cfg)
+    s = {k: _f64(state[k]).copy() for k in ("x", "y", "z", "m", "vx", "vy", "vz", "E", "U")}
+    n = s["x"].size
+    src, keep = make_sources(n, accel, inv_a, hubble, S, emode)
+    cnt = Counters()
+    rc = lib().orc_update_src(ctypes.byref(p), n, *[_p(s[k]) for k in
+                                                    ("x", "y", "z", "m", "vx", "vy", "vz", "E",
+                                                     "U")],
+                              _p(_f64(dQ)), float(dt), ctypes.byref(src),
+                              _opt(None if gwork is None else _f64(gwork)),
+                              _opt(None if ekin_max is None else _f64(ekin_max)),
+                              _opt(None if V is None else _f64(V)),
+                              _opt(None if H is None else _f64(H)), ctypes.byref(cnt))
+    if rc:
+        raise RuntimeError(f"orc_update_src failed: {rc}")
+    return s, cnt.as_dict()
+
+
+def entropy_pressure(cfg: dict, m, V, U, S, emode):
+    """U and S after a density pass (in place on U and S)."""
+    p = make_params(cfg)
+    rc = lib().orc_entropy_pressure(ctypes.byref(p), U.size, _p(_f64(m)), _p(_f64(V)), _p(U),
+                                    _p(S), emode.ctypes.data_as(_I32))
+    assert rc == 0

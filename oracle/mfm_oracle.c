@@ -924,18 +924,28 @@ int orc_fluxes(const orc_params *p, int64_t n, const double *x, const double *y,
                const double *vx, const double *vy, const double *vz, const double *P,
                const double *B, const double *grad, double dt, double *dQ, double *scale,
                orc_counters *cnt) {
+  return orc_fluxes_src(p, n, x, y, z, H, V, rho, vx, vy, vz, P, B, grad, dt, 1.0, dQ, scale,
+                        NULL, cnt);
+}
+
+int orc_fluxes_src(const orc_params *p, int64_t n, const double *x, const double *y,
+                   const double *z, const double *H, const double *V, const double *rho,
+                   const double *vx, const double *vy, const double *vz, const double *P,
+                   const double *B, const double *grad, double dt, double inv_a, double *dQ,
+                   double *scale, double *gwork, orc_counters *cnt) {
   if (!p || n <= 0) return -1;
   int64_t nf, *fa, *fb;
   int rc = orc_face_list(p, n, x, y, z, H, &nf, &fa, &fb);
   if (rc) return rc;
   double *fc = (double *)malloc((size_t)(nf > 0 ? nf : 1) * 5 * sizeof(double));
+  const double dte = dt * inv_a;
   /* Each face once; counters are per-thread then summed. */
   int64_t iters = 0, vac = 0, pos = 0, mx = 0;
 #pragma omp parallel for schedule(dynamic, 1024) reduction(+ : iters, vac, pos, mx)
   for (int64_t f = 0; f < nf; ++f) {
     orc_counters local;
     memset(&local, 0, sizeof(local));
-    orc_face(p, n, fa[f], fb[f], x, y, z, H, V, rho, vx, vy, vz, P, B, grad, dt, fc + 5 * f,
+    orc_face(p, n, fa[f], fb[f], x, y, z, H, V, rho, vx, vy, vz, P, B, grad, dte, fc + 5 * f,
              &local);
     iters += local.riemann_iters;
     vac += local.vacuum;
@@ -943,19 +953,36 @@ int orc_fluxes(const orc_params *p, int64_t n, const double *x, const double *y,
     mx += local.riemann_maxit;
   }
   /* eq. hydro_discr: U_i <- U_i - dt sum_j F_ij A_ij, applied as -c to i and
-   * +c to j so that the pair is exactly antisymmetric. */
+   * +c to j so that the pair is exactly antisymmetric.  In comoving
+   * coordinates every spatial derivative carries 1/a (sec. 2.3.9): the
+   * fluxes, and (reading) the gradients of the half-step predictor, which
+   * the faces above were given with dt / a. */
   for (int64_t k = 0; k < 5 * n; ++k) {
     dQ[k] = 0.0;
     scale[k] = 0.0;
   }
+  if (gwork)
+    for (int64_t k = 0; k < 3 * n; ++k) gwork[k] = 0.0;
   for (int64_t f = 0; f < nf; ++f) {
     int64_t a = fa[f], b = fb[f];
     for (int k = 0; k < 5; ++k) {
-      double v = dt * fc[5 * f + k];
+      double v = dte * fc[5 * f + k];
       dQ[(int64_t)k * n + a] -= v;
       dQ[(int64_t)k * n + b] += v;
       scale[(int64_t)k * n + a] += fabs(v);
       scale[(int64_t)k * n + b] += fabs(v);
+    }
+    if (gwork) {
+      /* eq. gravity_source: the mass dm that goes from a to b crosses
+       * x_b - x_a; each side is credited half of the work a.dm (x_b - x_a)
+       * with its own acceleration, so both add dm (x_b - x_a) */
+      double d[3];
+      separation(p, x, y, z, a, b, d);
+      double dm = dte * fc[5 * f];
+      for (int k = 0; k < 3; ++k) {
+        gwork[(int64_t)k * n + a] += dm * d[k];
+        gwork[(int64_t)k * n + b] += dm * d[k];
+      }
     }
   }
   free(fa);
@@ -975,8 +1002,34 @@ int orc_fluxes(const orc_params *p, int64_t n, const double *x, const double *y,
 int orc_update(const orc_params *p, int64_t n, double *x, double *y, double *z, double *m,
                double *vx, double *vy, double *vz, double *E, double *U, const double *dQ,
                double dt, orc_counters *cnt) {
+  return orc_update_src(p, n, x, y, z, m, vx, vy, vz, E, U, dQ, dt, NULL, NULL, NULL, NULL, NULL,
+                        cnt);
+}
+
+/* The implicit Hubble-source update of sec. 2.3.9:
+ * X^{n+1} = (X~ - eta dt H^n X^n) / (1 + eta dt H^{n+1}). */
+static double hubble(double xt, double x0, double eta, double dt, double hn, double hn1) {
+  return (xt - eta * dt * hn * x0) / (1.0 + eta * dt * hn1);
+}
+
+int orc_update_src(const orc_params *p, int64_t n, double *x, double *y, double *z, double *m,
+                   double *vx, double *vy, double *vz, double *E, double *U, const double *dQ,
+                   double dt, const orc_sources *src, const double *gwork,
+                   const double *ekin_max, const double *V, const double *H,
+                   orc_counters *cnt) {
   if (!p || n <= 0) return -1;
   double *pos[3] = {x, y, z};
+  const double gam = p->gamma;
+  const double *acc = src ? src->accel : NULL;
+  const double inv_a = src ? src->inv_a : 1.0;
+  const double hn = src ? src->hubble_n : 0.0, hn1 = src ? src->hubble_np1 : 0.0;
+  const int comoving = hn != 0.0 || hn1 != 0.0;
+  /* reading: eta of each equation from its source term as printed, with
+   * u-hat = u and p-hat = p a^3: momentum -H P (eta 1/2); total energy
+   * -H (rho v^2 + 3 p) = -2 H E for gamma = 5/3 (eta 1); internal energy
+   * -3 H (gamma - 1) U and the entropy of a comoving adiabat likewise
+   * (eta 3 (gamma - 1) / 2, which is 1 for gamma = 5/3) */
+  const double eta_u = 1.5 * (gam - 1.0);
   int64_t neg = 0, guard = 0;
   for (int64_t i = 0; i < n; ++i) {
     double dm = dQ[i], dp[3] = {dQ[n + i], dQ[2 * n + i], dQ[3 * n + i]}, dE = dQ[4 * n + i];
@@ -986,21 +1039,53 @@ int orc_update(const orc_params *p, int64_t n, double *x, double *y, double *z, 
     double dU = dE - (v0[0] * dp[0] + v0[1] * dp[1] + v0[2] * dp[2]) + 0.5 * v0sq * dm;
     double m1 = m[i] + dm;
     if (!(m1 > 0.0)) neg++; /* MFV mass depletion is counted, not clamped */
-    double p1[3] = {m[i] * v0[0] + dp[0], m[i] * v0[1] + dp[1], m[i] * v0[2] + dp[2]};
-    double v1[3] = {p1[0] / m1, p1[1] / m1, p1[2] / m1};
+    double p0[3] = {m[i] * v0[0], m[i] * v0[1], m[i] * v0[2]};
+    double p1[3] = {p0[0] + dp[0], p0[1] + dp[1], p0[2] + dp[2]};
     double E1 = E[i] + dE;
     double U1 = U[i] + dU;
-    /* Pressure switch (sec. 2.3.7) without gravity and with the entropy branch
-     * off: the internal energy is recovered from the total energy when it is
-     * not small against the kinetic energy, otherwise the integrated U is
-     * kept.  reading: the test of criterion (i) is made on the internal
-     * energy the total energy gives, E - E_kin > alpha_1 E_kin (the
-     * dual-energy test of the method the section cites).  Tested on the
-     * integrated U instead, a particle whose momentum changes by more than
-     * its integrated internal energy allows (|dP|^2 / 2m > U) is handed a
-     * negative E - E_kin, hence a negative pressure. */
+    double amag = 0.0;
+    if (acc) {
+      /* gravity, eq. gravity_source integrated by eq. source_term_discr:
+       * S = (0, m a, P.a + W/dt) at the start of the step and at the hydro
+       * update U~, with W = 1/2 a . sum_j dm_ij r_ij over the step; the
+       * acceleration is the caller's, the same at both ends (reading) */
+      double a3[3] = {acc[i], acc[n + i], acc[2 * n + i]};
+      amag = sqrt(a3[0] * a3[0] + a3[1] * a3[1] + a3[2] * a3[2]);
+      double work = 0.0;
+      if (gwork)
+        work = 0.5 * (a3[0] * gwork[i] + a3[1] * gwork[n + i] + a3[2] * gwork[2 * n + i]);
+      double pa = 0.5 * dt * ((p0[0] + p1[0]) * a3[0] + (p0[1] + p1[1]) * a3[1] +
+                              (p0[2] + p1[2]) * a3[2]);
+      for (int k = 0; k < 3; ++k) p1[k] += 0.5 * dt * (m[i] + m1) * a3[k];
+      E1 += pa + work;
+    }
+    if (comoving) {
+      for (int k = 0; k < 3; ++k) p1[k] = hubble(p1[k], p0[k], 0.5, dt, hn, hn1);
+      E1 = hubble(E1, E[i], 1.0, dt, hn, hn1);
+      U1 = hubble(U1, U[i], eta_u, dt, hn, hn1);
+      if (src->S) src->S[i] = hubble(src->S[i], src->S[i], eta_u, dt, hn, hn1);
+    }
+    double v1[3] = {p1[0] / m1, p1[1] / m1, p1[2] / m1};
+    /* Pressure switch (sec. 2.3.7).  reading: the test of criterion (i) is
+     * made on the internal energy the total energy gives, E - E_kin >
+     * alpha_1 (E_grav + E_kin) (the dual-energy test of the method the
+     * section cites).  Tested on the integrated U instead, a particle whose
+     * momentum changes by more than its integrated internal energy allows
+     * (|dP|^2 / 2m > U) is handed a negative E - E_kin, hence a negative
+     * pressure.  Criterion (ii), when the entropy switch is on: the flow is
+     * cold and smooth, U < alpha_2 (E_kin^max + U) or U < alpha_3 E_grav,
+     * and the next density pass takes the pressure from the entropy.
+     * Otherwise (iii) the integrated U is kept. */
     double ekin = (p1[0] * p1[0] + p1[1] * p1[1] + p1[2] * p1[2]) / (2.0 * m1);
-    if (E1 - ekin > p->alpha1 * ekin) U1 = E1 - ekin;
+    double egrav = (acc && H) ? m1 * amag * H[i] : 0.0;
+    int mode = 0;
+    if (E1 - ekin > p->alpha1 * (egrav + ekin)) {
+      U1 = E1 - ekin;
+    } else if (p->entropy_switch && src && src->S && ekin_max &&
+               (U1 < p->alpha2 * (ekin_max[i] + U1) || U1 < p->alpha3 * egrav)) {
+      mode = 1;
+    }
+    if (src && src->emode) src->emode[i] = mode;
     /* reading: where the kinetic energy dominates, dE ~ v.dP and the
      * integrated U can be driven through zero by that noise (the section
      * names the regime); the internal energy then keeps its value from the
@@ -1009,9 +1094,10 @@ int orc_update(const orc_params *p, int64_t n, double *x, double *y, double *z, 
       U1 = U[i];
       guard++;
     }
-    /* reading: drift with the mean of the old and new velocities, periodic wrap */
+    /* reading: drift with the mean of the old and new velocities (comoving:
+     * dx/dt = v / a), periodic wrap */
     for (int k = 0; k < 3; ++k) {
-      double xn = pos[k][i] + dt * 0.5 * (v0[k] + v1[k]);
+      double xn = pos[k][i] + dt * inv_a * 0.5 * (v0[k] + v1[k]);
       double L = p->box[k];
       if (L > 0.0) {
         if (xn < 0.0) xn += L;
@@ -1026,9 +1112,88 @@ int orc_update(const orc_params *p, int64_t n, double *x, double *y, double *z, 
     E[i] = E1;
     U[i] = U1;
   }
+  (void)V;
   cnt->neg_mass += neg;
   cnt->u_guard += guard;
   return 0;
+}
+
+int orc_ekin_max(const orc_params *p, int64_t n, const double *x, const double *y,
+                 const double *z, const double *H, const double *m, const double *vx,
+                 const double *vy, const double *vz, double *ekin_max) {
+  if (!p || n <= 0 || !ekin_max) return -1;
+  int64_t *start;
+  int32_t *idx;
+  if (build_lists(p, n, x, y, z, H, &start, &idx)) return -2;
+  for (int64_t i = 0; i < n; ++i) {
+    double e = 0.0;
+    for (int64_t k = start[i]; k < start[i + 1]; ++k) {
+      int64_t j = idx[k];
+      if (j == i) continue;
+      double d0 = vx[j] - vx[i], d1 = vy[j] - vy[i], d2 = vz[j] - vz[i];
+      double ek = 0.5 * m[i] * (d0 * d0 + d1 * d1 + d2 * d2);
+      if (ek > e) e = ek;
+    }
+    ekin_max[i] = e;
+  }
+  free(start);
+  free(idx);
+  return 0;
+}
+
+int orc_entropy_pressure(const orc_params *p, int64_t n, const double *m, const double *V,
+                         double *U, double *S, const int32_t *emode) {
+  if (!p || n <= 0 || !m || !V || !U || !S) return -1;
+  const double gam = p->gamma;
+  for (int64_t i = 0; i < n; ++i) {
+    double rho = m[i] / V[i];
+    if (emode && emode[i]) {
+      /* p = S omega^-1 rho^(gamma-1) = (S / m) rho^gamma (reading of the
+       * printed p = S omega rho^(gamma-1), whose omega is read as omega^-1:
+       * with S extensive this is the adiabat P / rho^gamma = S / m) */
+      double P = S[i] / m[i] * pow(rho, gam);
+      U[i] = P * V[i] / (gam - 1.0);
+    } else {
+      double P = (gam - 1.0) * U[i] / V[i];
+      S[i] = m[i] * P / pow(rho, gam);
+    }
+  }
+  return 0;
+}
+
+int orc_step_src(const orc_params *p, int64_t n, double *x, double *y, double *z, double *m,
+                 double *vx, double *vy, double *vz, double *E, double *U, double *H,
+                 double dt_max, const orc_sources *src, double *dt_out, orc_counters *cnt) {
+  if (!p || n <= 0 || !dt_out || !cnt) return -1;
+  size_t sz = (size_t)n * sizeof(double);
+  double *V = (double *)malloc(sz), *nc0 = (double *)malloc(sz), *nng = (double *)malloc(sz);
+  double *rho = (double *)malloc(sz), *P = (double *)malloc(sz), *c = (double *)malloc(sz);
+  double *B = (double *)malloc(6 * sz), *grad = (double *)malloc(15 * sz);
+  double *alpha = (double *)malloc(5 * sz), *nc = (double *)malloc(sz);
+  double *dti = (double *)malloc(sz), *dQ = (double *)malloc(5 * sz);
+  double *scale = (double *)malloc(5 * sz), *ekm = (double *)malloc(sz);
+  double *gw = (double *)malloc(3 * sz);
+  int rc = orc_density(p, n, x, y, z, H, V, nc0, nng, cnt);
+  if (!rc && src && src->S) rc = orc_entropy_pressure(p, n, m, V, U, src->S, src->emode);
+  if (!rc)
+    rc = orc_gradients(p, n, x, y, z, H, V, m, vx, vy, vz, U, rho, P, c, B, grad, alpha, nc, dti,
+                       cnt);
+  if (!rc && p->entropy_switch) rc = orc_ekin_max(p, n, x, y, z, H, m, vx, vy, vz, ekm);
+  double dt = dt_max;
+  const int grav_work = src && src->accel && p->scheme == 0;
+  if (!rc) {
+    for (int64_t i = 0; i < n; ++i)
+      if (dti[i] < dt) dt = dti[i];
+    rc = orc_fluxes_src(p, n, x, y, z, H, V, rho, vx, vy, vz, P, B, grad, dt,
+                        src ? src->inv_a : 1.0, dQ, scale, grav_work ? gw : NULL, cnt);
+  }
+  if (!rc)
+    rc = orc_update_src(p, n, x, y, z, m, vx, vy, vz, E, U, dQ, dt, src, grav_work ? gw : NULL,
+                        p->entropy_switch ? ekm : NULL, V, H, cnt);
+  *dt_out = dt;
+  free(V); free(nc0); free(nng); free(rho); free(P); free(c); free(B); free(grad);
+  free(alpha); free(nc); free(dti); free(dQ); free(scale); free(ekm); free(gw);
+  return rc;
 }
 
 int orc_step(const orc_params *p, int64_t n, double *x, double *y, double *z, double *m,

@@ -42,7 +42,20 @@ typedef struct {
   double riemann_tol;    /* relative Newton step tolerance of the Riemann solve */
   double alpha1;         /* dual-energy switch constant alpha_1 = 1/100 (sec. 2.3.7) */
   double box[3];         /* periodic box sides (0 = open) */
+  double alpha2, alpha3; /* entropy switch constants alpha_2, alpha_3 = 1/1000 (sec. 2.3.7) */
+  int32_t entropy_switch;/* 1: criterion (ii) of sec. 2.3.7 is on */
+  int32_t pad1;
 } orc_params;
+
+/* Source terms of one step (sec. 2.3.7-2.3.9); all optional. */
+typedef struct {
+  const double *accel;   /* 3n: external gravitational acceleration, a[k*n + i] (NULL: none) */
+  double inv_a;          /* comoving integration: 1/a, the factor of the fluxes and of the
+                            drift (1 = physical coordinates) */
+  double hubble_n, hubble_np1; /* Hubble rate at the start and at the end of the step */
+  double *S;             /* n: extensive entropy m P / rho^gamma (in/out; NULL: switch off) */
+  int32_t *emode;        /* n: 1 where the next density pass takes the pressure from S */
+} orc_sources;
 
 typedef struct {
   int64_t h_noconv;      /* smoothing-length solves that hit the iteration cap */
@@ -132,6 +145,43 @@ int orc_fluxes(const orc_params *p, int64_t n, const double *x, const double *y,
                const double *vx, const double *vy, const double *vz, const double *P,
                const double *B, const double *grad, double dt, double *dQ, double *scale,
                orc_counters *cnt);
+
+/* Flux loop with the comoving factor and the gravity work of the exchanged
+ * mass: dQ_i -= dt inv_a c_ij, and, when gwork (3n) is given, every face adds
+ * dm_ij (x_j - x_i) to gwork of both particles, dm_ij = dt inv_a c_m,ij the
+ * mass that goes from i to j (sec. 2.3.8, eq. gravity_source). */
+int orc_fluxes_src(const orc_params *p, int64_t n, const double *x, const double *y,
+                   const double *z, const double *H, const double *V, const double *rho,
+                   const double *vx, const double *vy, const double *vz, const double *P,
+                   const double *B, const double *grad, double dt, double inv_a, double *dQ,
+                   double *scale, double *gwork, orc_counters *cnt);
+
+/* E_kin^max,i = max_j 1/2 m_i |v_j - v_i|^2 over the neighbours r_ij < H_i
+ * (sec. 2.3.7). */
+int orc_ekin_max(const orc_params *p, int64_t n, const double *x, const double *y,
+                 const double *z, const double *H, const double *m, const double *vx,
+                 const double *vy, const double *vz, double *ekin_max);
+
+/* After the density pass: where emode is set, the pressure comes from the
+ * entropy, U := P V / (gamma - 1) with P = (S / m) rho^gamma; elsewhere S is
+ * reset from U, S := m P / rho^gamma with P = (gamma - 1) U / V. */
+int orc_entropy_pressure(const orc_params *p, int64_t n, const double *m, const double *V,
+                         double *U, double *S, const int32_t *emode);
+
+/* Close of the step with source terms (sec. 2.3.4 eq. source_term_discr,
+ * 2.3.7, 2.3.8, 2.3.9): hydro update, gravity source, Hubble terms, the
+ * three-way pressure switch, drift (scaled by inv_a).  gwork and ekin_max
+ * may be NULL; V and H are the step's volumes and support radii. */
+int orc_update_src(const orc_params *p, int64_t n, double *x, double *y, double *z, double *m,
+                   double *vx, double *vy, double *vz, double *E, double *U, const double *dQ,
+                   double dt, const orc_sources *src, const double *gwork,
+                   const double *ekin_max, const double *V, const double *H,
+                   orc_counters *cnt);
+
+/* One full step with source terms. */
+int orc_step_src(const orc_params *p, int64_t n, double *x, double *y, double *z, double *m,
+                 double *vx, double *vy, double *vz, double *E, double *U, double *H,
+                 double dt_max, const orc_sources *src, double *dt_out, orc_counters *cnt);
 
 /* Close of the step (eq. hydro_discr, internal-energy integration and the
  * pressure switch of sec. 2.3.7, drift).  Updates x,y,z,m,vx,vy,vz,E,U in place. */

@@ -11,6 +11,7 @@ import pytest
 
 import oracle
 import test_oracle_pins as pins
+import test_oracle_sources as sources
 
 
 def _mutant(tmp_path, name, edits):
@@ -81,3 +82,28 @@ def test_first_order_time_integration_is_caught(tmp_path, name, edits):
         order = _order("mfv")
     print(name, f"MFV order {order:.2f}")
     assert order < 1.8
+
+
+ETA_PRINTED = [("const double eta_u = 1.5 * (gam - 1.0);", "const double eta_u = 1.5;")]
+GWORK_SIGN = [("gwork[(int64_t)k * n + a] += dm * d[k];", "gwork[(int64_t)k * n + a] -= dm * d[k];")]
+# S~ taken after the gravity kick (momentum P~ + m a dt) instead of at the hydro update
+KICKED_SOURCE = [("(p0[2] + p1[2]) * a3[2]);", "(p0[2] + p1[2] + dt * m1 * a3[2]) * a3[2]);")]
+
+
+def test_hubble_eta_of_the_list_is_caught(tmp_path):
+    # eta = 3/2 for U, as listed beside the equations: u ~ a^-3, not the adiabat a^-2
+    with oracle.use_library(_mutant(tmp_path, "eta", ETA_PRINTED)):
+        with pytest.raises(AssertionError):
+            sources.test_comoving_adiabatic_expansion_second_order(1e30)
+
+
+def test_mass_exchange_work_sign_is_caught(tmp_path):
+    with oracle.use_library(_mutant(tmp_path, "gwork", GWORK_SIGN)):
+        with pytest.raises(AssertionError):
+            sources.test_mass_exchange_work_identity()
+
+
+def test_source_at_the_kicked_state_is_caught(tmp_path):
+    with oracle.use_library(_mutant(tmp_path, "kick", KICKED_SOURCE)):
+        with pytest.raises(AssertionError):
+            sources.test_free_fall_in_a_uniform_field()
