@@ -93,6 +93,11 @@ typedef struct mfm_params {
                             max(H_i, H_j) at the build */
   int32_t max_cell_dim;  /* cells per axis at most (3..512, default 256) */
   int32_t pad0;
+  double alpha2, alpha3; /* entropy switch (sec. 2.3.7): the pressure comes from the entropy
+                            when U < alpha2 (E_kin^max + U) or U < alpha3 E_grav (default
+                            1/1000 each) */
+  int32_t entropy_switch;/* 1: criterion (ii) of the pressure switch is on (needs S, emode) */
+  int32_t pad1;
   double mixed_jump;     /* mixed path: a face whose two particles' pressures or densities
                             differ by more than this factor is computed in FP64 (in the flux
                             loop's second pass); default 8, 0 = none.  Across strong jumps the
@@ -123,6 +128,10 @@ typedef struct mfm_particles {
   double *V, *rho, *P, *c, *ncond;
   double *B, *grad, *dQ, *dt_i;
   int64_t *id; /* optional (may be NULL): caller's particle labels, permuted with the state */
+  /* source terms (sec. 2.3.7, 2.3.8), optional, permuted with the state: */
+  double *S;      /* extensive entropy S = m P / rho^gamma (needed by the entropy switch) */
+  int32_t *emode; /* 1 where the next density pass takes the pressure from S (switch) */
+  double *accel;  /* 3n: external gravitational acceleration, entry k of i at [k n + i] */
 } mfm_particles;
 
 /* Counters and conserved totals (filled by mfm_diagnostics). */
@@ -230,11 +239,26 @@ int mfm_gradients(struct mfm_ctx *ctx, const mfm_particles *parts, double dt_max
  * mfm_gradients). */
 int mfm_fluxes(struct mfm_ctx *ctx, const mfm_particles *parts, const double *dt_dev);
 
+/* Comoving integration (sec. 2.3.9) for the following steps: inv_a = 1/a
+ * multiplies every spatial derivative -- the fluxes, the gradients of the
+ * half-step predictor -- and the drift; hubble_n, hubble_np1 are the Hubble
+ * rate at the start and end of the step, used in the implicit update
+ * X = (X~ - eta dt H^n X^n) / (1 + eta dt H^(n+1)) of momentum (eta 1/2),
+ * total energy (1), internal energy and entropy (3 (gamma - 1) / 2).  The
+ * total-energy form holds for gamma = 5/3 only: other gammas with a nonzero
+ * Hubble rate return MFM_E_ARG.  Defaults 1, 0, 0 (physical coordinates). */
+int mfm_set_cosmology(struct mfm_ctx *ctx, double inv_a, double hubble_n, double hubble_np1);
+
 /* Close of the step, eq. hydro_discr and sec. 2.3.7: m += dQ_m, m v += dQ_p,
- * E += dQ_E, U += dQ_E - v.dQ_p + v^2/2 dQ_m, U := E - E_kin when
- * E - E_kin > alpha1 E_kin, and the drift x += dt (v_old + v_new)/2
- * (periodic wrap).  An internal energy that would not be positive keeps its
- * start-of-step value (counted in mfm_diag.u_guard). */
+ * E += dQ_E, U += dQ_E - v.dQ_p + v^2/2 dQ_m; with accel, the gravity source
+ * of sec. 2.3.8 by eq. source_term_discr (momentum m a, work P.a and
+ * 1/2 a . sum_j dm_ij r_ij); the Hubble terms (mfm_set_cosmology); the
+ * pressure switch: U := E - E_kin when E - E_kin > alpha1 (E_grav + E_kin),
+ * else with the entropy switch emode := 1 when U < alpha2 (E_kin^max + U) or
+ * U < alpha3 E_grav, else the integrated U; and the drift
+ * x += dt inv_a (v_old + v_new)/2 (periodic wrap).  An internal energy that
+ * would not be positive keeps its start-of-step value (counted in
+ * mfm_diag.u_guard). */
 int mfm_update(struct mfm_ctx *ctx, const mfm_particles *parts, const double *dt_dev);
 
 /* One full step: cells, density, gradients, fluxes, update.  dt_host receives

@@ -184,9 +184,14 @@ __global__ void range_k(int64_t ncodes, const int32_t *__restrict__ start,
   if (c < ncodes) range[c] = make_int2(start[c], count[c]);
 }
 
+// The state arrays the permutation moves: the ten FP64 fields, the labels,
+// and the optional source-term arrays (entropy, the three acceleration
+// components, the entropy-mode flags); absent ones are null.
 struct Fields {
   double *f[10];
   int64_t *id;
+  double *x[4];
+  int32_t *emode;
 };
 
 __global__ void gather_k(int64_t n, Fields fs, const int32_t *__restrict__ order, double *tmp,
@@ -197,6 +202,10 @@ __global__ void gather_k(int64_t n, Fields fs, const int32_t *__restrict__ order
 #pragma unroll
   for (int f = 0; f < 10; ++f) tmp[f * n + k] = fs.f[f][o];
   if (fs.id) ((int64_t *)(tmp + 10 * n))[k] = fs.id[o];
+#pragma unroll
+  for (int e = 0; e < 4; ++e)
+    if (fs.x[e]) tmp[(11 + e) * n + k] = fs.x[e][o];
+  if (fs.emode) ((int32_t *)(tmp + 15 * n))[k] = fs.emode[o];
   if (perm) perm[k] = o;
 }
 
@@ -207,6 +216,10 @@ __global__ void writeback_k(int64_t n, Fields fs, const double *__restrict__ tmp
 #pragma unroll
   for (int f = 0; f < 10; ++f) fs.f[f][k] = tmp[f * n + k];
   if (fs.id) fs.id[k] = ((const int64_t *)(tmp + 10 * n))[k];
+#pragma unroll
+  for (int e = 0; e < 4; ++e)
+    if (fs.x[e]) fs.x[e][k] = tmp[(11 + e) * n + k];
+  if (fs.emode) fs.emode[k] = ((const int32_t *)(tmp + 15 * n))[k];
   pos4[k] = make_double4(tmp[k], tmp[n + k], tmp[2 * n + k], tmp[9 * n + k]);
 }
 
@@ -242,6 +255,9 @@ hipError_t launch_build_cells(mfm_ctx *ctx, const mfm_particles *pp, int64_t *pe
   double *src[10] = {pp->x, pp->y, pp->z, pp->vx, pp->vy, pp->vz, pp->m, pp->E, pp->U, pp->H};
   for (int f = 0; f < 10; ++f) fs.f[f] = src[f];
   fs.id = pp->id;
+  fs.x[0] = pp->S;
+  for (int e = 0; e < 3; ++e) fs.x[1 + e] = pp->accel ? pp->accel + (int64_t)e * n : nullptr;
+  fs.emode = pp->emode;
   gather_k<<<blocks_for(n, BS), BS, 0, st>>>(n, fs, ctx->order, ctx->tmp, perm);
   writeback_k<<<blocks_for(n, BS), BS, 0, st>>>(n, fs, ctx->tmp,
                                                 reinterpret_cast<double4 *>(ctx->pos4));

@@ -247,8 +247,11 @@ __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) ca
 struct DensityArgs {
   int64_t n;
   const double4 *pos;
-  const double *m, *U, *vx, *vy, *vz;
+  const double *m, *vx, *vy, *vz;
+  double *U;
   double *H, *V, *rho, *P, *c, *ncond;
+  double *S;              // entropy switch: extensive entropy (null when off)
+  const int32_t *emode;   // 1: the pressure comes from S
   double *gin;  // GIN_STRIDE doubles per particle
   int32_t *cand, *cand_cnt;
   const double *cand_r2;
@@ -439,7 +442,18 @@ __device__ __forceinline__ void finish_particle(const DensityArgs &a, int64_t i,
   const double h = r.h_store;
   const double V = 1.0 / r.winv;
   const double rho = a.m[i] / V;
-  const double P = (a.gamma - 1.0) * a.U[i] / V;
+  double P = (a.gamma - 1.0) * a.U[i] / V;
+  if (a.S) {
+    // the entropy switch (sec. 2.3.7): a particle the last close of the step
+    // put in the entropy branch takes P = (S / m) rho^gamma and the U that
+    // gives it; every other particle resets S from its U
+    if (a.emode[i]) {
+      P = a.S[i] / a.m[i] * pow(rho, a.gamma);
+      a.U[i] = P * V / (a.gamma - 1.0);
+    } else {
+      a.S[i] = a.m[i] * P / pow(rho, a.gamma);
+    }
+  }
   const double cs = sqrt(a.gamma * P / rho);
   a.H[i] = h;
   a.V[i] = V;
@@ -666,6 +680,8 @@ hipError_t launch_density(mfm_ctx *ctx, const mfm_particles *pp) {
   a.pos = reinterpret_cast<const double4 *>(ctx->pos4);
   a.m = pp->m; a.U = pp->U; a.vx = pp->vx; a.vy = pp->vy; a.vz = pp->vz;
   a.H = pp->H; a.V = pp->V; a.rho = pp->rho; a.P = pp->P; a.c = pp->c; a.ncond = pp->ncond;
+  a.S = ctx->p.entropy_switch ? pp->S : nullptr;
+  a.emode = pp->emode;
   a.gin = ctx->gin;
   a.cand = ctx->cand;
   a.cand_cnt = ctx->cand_cnt;

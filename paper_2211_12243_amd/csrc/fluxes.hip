@@ -85,7 +85,28 @@ struct FluxArgs {
   // the mixed path's FP32 record (near the edge of the support, W(r, H) moves
   // by 3 (1 - r/H)^-1 times the relative error of 1/H)
   const double *x, *y, *z, *H, *V, *rho, *vx, *vy, *vz, *P;
+  // comoving integration: every spatial derivative (fluxes, predictor
+  // gradients) carries inv_a = 1/a; 1 in physical coordinates
+  double inv_a;
+  // MFV with gravity: sum_j dm_ij (x_j - x_i) per particle (3 n; null: off)
+  double *gwork;
 };
+
+// The work term of the exchanged mass (sec. 2.3.8): the mass dm that goes
+// from L to R crosses x_R - x_L; both sides add dm (x_R - x_L), each later
+// weighted with its own acceleration.
+__device__ __forceinline__ void add_gwork(const FluxArgs &a, int L, int R, double dm) {
+  const double d0 = min_image(a.x[R] - a.x[L], a.box[0], a.half[0]);
+  const double d1 = min_image(a.y[R] - a.y[L], a.box[1], a.half[1]);
+  const double d2 = min_image(a.z[R] - a.z[L], a.box[2], a.half[2]);
+  const int64_t n = a.n;
+  const double d[3] = {d0, d1, d2};
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    unsafeAtomicAdd(&a.gwork[(int64_t)k * n + L], dm * d[k]);
+    unsafeAtomicAdd(&a.gwork[(int64_t)k * n + R], dm * d[k]);
+  }
+}
 
 template <typename T>
 __device__ __forceinline__ const Gas<T> &gas_of(const FluxArgs &a);
@@ -678,7 +699,7 @@ __global__ void __launch_bounds__(FTH) __attribute__((amdgpu_waves_per_eu(2))) f
   if (tid == FTH - 1) pref[FBS] = run;
   __syncthreads();
   const int T_faces = pref[FBS];
-  const double dt = a.dt[0];
+  const double dt = a.dt[0] * a.inv_a;  // the step times 1/a (comoving)
   const T hdt = T(0.5 * dt);
   int64_t nfaces = 0, iters_sum = 0, vac = 0, pos = 0, maxit = 0, fb = 0, overflow = 0;
   // face f of the block: its particle p (pref[p] <= f < pref[p + 1]) and its
@@ -755,6 +776,7 @@ __global__ void __launch_bounds__(FTH) __attribute__((amdgpu_waves_per_eu(2))) f
       int it;
       double ps;
       face_solve<T, SCHEME, M>(fs, a, T(0), c, it, ps);
+      if (SCHEME == MFM_SCHEME_MFV && a.gwork) add_gwork(a, Lslot, Rslot, dt * c[0]);
       const double sgn = (i < j) ? -1.0 : 1.0;  // the left (lower) side loses c
 #pragma unroll
       for (int q = 0; q < 5; ++q) c[q] *= sgn;
@@ -853,7 +875,7 @@ __global__ void __launch_bounds__(FTH) hard_faces_k(FluxArgs a) {
   const unsigned long long queued = *a.hard_count;
   const int64_t nq = (int64_t)(queued < (unsigned long long)a.hard_cap ? queued
                                                                         : (unsigned long long)a.hard_cap);
-  const double dt = a.dt[0];
+  const double dt = a.dt[0] * a.inv_a;  // the step times 1/a (comoving)
   const double hdt = 0.5 * dt;
   const int64_t n = a.n;
   int64_t nfaces = 0, iters_sum = 0, vac = 0, pos = 0, maxit = 0, fb = 0;
@@ -911,6 +933,7 @@ __global__ void __launch_bounds__(FTH) hard_faces_k(FluxArgs a) {
         unsafeAtomicAdd(&a.dq_ext[(int64_t)q * n + L], -dt * c[q]);
         unsafeAtomicAdd(&a.dq_ext[(int64_t)q * n + R], dt * c[q]);
       }
+      if (SCHEME == MFM_SCHEME_MFV && a.gwork) add_gwork(a, L, R, dt * c[0]);
       ++nfaces;
       iters_sum += it;
       vac += (fs.flags & F_VACUUM) ? 1 : 0;
@@ -942,12 +965,16 @@ __global__ void __launch_bounds__(FTH) hard_faces_k(FluxArgs a) {
 // dq_ext (and the second pass's queue length) is cleared before the flux
 // loop and folded into dQ after it.
 __global__ void zero_f64_k(double *v, int64_t m, unsigned long long *queue_len,
-                           const int64_t *counters) {
+                           const int64_t *counters, double *w, int64_t mw) {
   if (counters[C_STEP_SKIP]) return;
   if (blockIdx.x == 0 && threadIdx.x == 0) *queue_len = 0ull;
   for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < m;
        k += (int64_t)gridDim.x * blockDim.x)
     v[k] = 0.0;
+  if (w)
+    for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < mw;
+         k += (int64_t)gridDim.x * blockDim.x)
+      w[k] = 0.0;
 }
 __global__ void fold_f64_k(double *dst, const double *src, int64_t m, const int64_t *counters) {
   if (counters[C_STEP_SKIP]) return;
@@ -1047,6 +1074,8 @@ hipError_t launch_fluxes(mfm_ctx *ctx, const mfm_particles *pp, const double *dt
   a.jump = (float)ctx->p.mixed_jump;
   a.x = pp->x; a.y = pp->y; a.z = pp->z; a.H = pp->H; a.V = pp->V; a.rho = pp->rho;
   a.vx = pp->vx; a.vy = pp->vy; a.vz = pp->vz; a.P = pp->P;
+  a.inv_a = ctx->inv_a;
+  a.gwork = (pp->accel && ctx->p.scheme == MFM_SCHEME_MFV) ? ctx->gwork : nullptr;
   const bool learned = ctx->p.guess == MFM_GUESS_LEARNED;
   const bool mixed = ctx->p.precision == MFM_MIXED;
   if (learned) mlp_net_of(ctx->mlp_state, &a.net);
@@ -1054,7 +1083,8 @@ hipError_t launch_fluxes(mfm_ctx *ctx, const mfm_particles *pp, const double *dt
   const int64_t m5 = 5 * pp->n;
   const int fb = (int)std::min<int64_t>(blocks_for(m5, 256), 8192);
   const int ev_all = stage_begin(ctx, 4);
-  zero_f64_k<<<fb, 256, 0, ctx->stream>>>(ctx->dq_ext, m5, a.hard_count, ctx->counters);
+  zero_f64_k<<<fb, 256, 0, ctx->stream>>>(ctx->dq_ext, m5, a.hard_count, ctx->counters, a.gwork,
+                                          3 * pp->n);
   const int ev_main = stage_begin(ctx, 6);
   if (mixed) {
     if (learned)

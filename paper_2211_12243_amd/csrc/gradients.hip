@@ -46,6 +46,8 @@ struct GradArgs {
   double ncond_max, c_cfl;
   int limiter;
   int64_t *counters;
+  const double *m;  // masses, for E_kin^max
+  double *ekm;      // E_kin^max = max_j m_i |v_j - v_i|^2 / 2 (null: not wanted)
 };
 
 template <typename T>
@@ -151,6 +153,7 @@ __global__ void __launch_bounds__(BS) gradients_k(GradArgs a) {
       qmax[q] = qmin[q] = q64[q];
     }
     T vsig = T(0);
+    double dv2max = 0.0;  // max_j |v_j - v_i|^2 over the gather set (E_kin^max)
     int nf = 0;
     // the face ring: planes [0, flushed) are stored; a lane's face number nf
     // >= flushed sits in slot nf % RING, one below flushed (a lane that fell
@@ -208,14 +211,18 @@ __global__ void __launch_bounds__(BS) gradients_k(GradArgs a) {
         const double e1 = min_image(cur.y - yi, a.box[1], a.half[1]);
         const double e2 = min_image(cur.z - zi, a.box[2], a.half[2]);
         const double r2 = e0 * e0 + e1 * e1 + e2 * e2;
+        // neighbour values: FP64 on the FP64 path; on the mixed path their FP32
+        // copies (half the bytes through the cache; the separation stays FP64)
+        double qj[5];
+        T vj, cj;
+        cur.values(qj, vj, cj);
+        {
+          const double w0 = qj[1] - q64[1], w1 = qj[2] - q64[2], w2 = qj[3] - q64[3];
+          dv2max = fmax(dv2max, w0 * w0 + w1 * w1 + w2 * w2);
+        }
         if (r2 != 0.0) {
           const T d0 = T(e0), d1 = T(e1), d2 = T(e2);
           const T r = T(sqrt(r2));
-          // neighbour values: FP64 on the FP64 path; on the mixed path their FP32
-          // copies (half the bytes through the cache; the separation stays FP64)
-          double qj[5];
-          T vj, cj;
-          cur.values(qj, vj, cj);
           const T wv = vj * wnorm * spline_wt<T>(r * ih);
           e[0] += wv * d0 * d0;
           e[1] += wv * d0 * d1;
@@ -383,6 +390,7 @@ __global__ void __launch_bounds__(BS) gradients_k(GradArgs a) {
         rec[F_STRIDE - 3] = rec[F_STRIDE - 2] = rec[F_STRIDE - 1] = 0.0f;
       }
       a.ncond[i] = (double)nc;
+      if (a.ekm) a.ekm[i] = 0.5 * a.m[i] * dv2max;
       a.dt_i[i] = vsig > T(0) ? a.c_cfl * hi / (double)vsig : __builtin_huge_val();
       a.fcnt[i] = nf;
     }
@@ -452,6 +460,8 @@ hipError_t launch_gradients(mfm_ctx *ctx, const mfm_particles *pp, double dt_max
   a.c_cfl = ctx->p.c_cfl;
   a.limiter = ctx->p.limiter;
   a.counters = ctx->counters;
+  a.m = pp->m;
+  a.ekm = ctx->p.entropy_switch ? ctx->ekm : nullptr;
   if (ctx->p.precision == MFM_MIXED)
     gradients_k<float><<<blocks_for(pp->n, BS), BS, 0, ctx->stream>>>(a);
   else

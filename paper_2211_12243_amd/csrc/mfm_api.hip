@@ -15,7 +15,8 @@ constexpr size_t ALIGN = 256;
 
 struct Layout {
   size_t code, count, start, cursor, crange, scan, order, tmp, pos4, cand, cand_r2, rest_r2,
-      cand_cnt, gl, gl_cnt, gin, fslot, fcnt, dq_ext, hard_q, rec, red, counters, scalars;
+      cand_cnt, gl, gl_cnt, gin, fslot, fcnt, dq_ext, hard_q, rec, ekm, gwork, red, counters,
+      scalars;
   int64_t hard_cap;
   size_t total;
   int64_t ncodes_max;
@@ -50,7 +51,7 @@ Layout make_layout(const mfm_params *p, int64_t n) {
   L.crange = take(8 * (size_t)L.ncodes_max);
   L.scan = take(4 * scan_len);
   L.order = take(4 * (size_t)n);
-  L.tmp = take(8 * 11 * (size_t)n);
+  L.tmp = take(8 * 16 * (size_t)n);
   L.pos4 = take(32 * (size_t)n);
   L.cand = take(4 * list_len(p->max_list, n));
   L.cand_r2 = take(8 * list_len(p->max_list, n));
@@ -66,6 +67,8 @@ Layout make_layout(const mfm_params *p, int64_t n) {
   L.hard_cap = (int64_t)(list_len(p->max_list, n) / 2);
   L.hard_q = take(8 * (size_t)L.hard_cap);
   L.rec = take(8 * (size_t)R_STRIDE * (size_t)n);
+  L.ekm = take(8 * (size_t)n);
+  L.gwork = take(8 * 3 * (size_t)n);
   L.red = take(8 * 5 * 1024);
   L.counters = take(8 * NCOUNTERS);
   L.scalars = take(8 * 16);
@@ -89,6 +92,8 @@ int check_params(const mfm_params *p) {
   if (!(p->cell_margin >= 1.0)) return 0;
   if (p->max_cell_dim < 3 || p->max_cell_dim > 512) return 0;
   if (!(p->mixed_jump == 0.0 || p->mixed_jump >= 1.0)) return 0;
+  if (!(p->alpha2 >= 0.0) || !(p->alpha3 >= 0.0)) return 0;
+  if (p->entropy_switch != 0 && p->entropy_switch != 1) return 0;
   for (int k = 0; k < 3; ++k)
     if (!(p->box[k] > 0.0)) return 0;
   return 1;
@@ -101,6 +106,7 @@ int check_parts(const mfm_ctx *ctx, const mfm_particles *pp) {
                        pp->dQ, pp->dt_i};
   for (const void *q : req)
     if (!q) return 0;
+  if (ctx->p.entropy_switch && (!pp->S || !pp->emode)) return 0;
   return 1;
 }
 
@@ -217,6 +223,9 @@ void mfm_default_params(mfm_params *p) {
   p->cell_margin = 1.10;
   p->max_cell_dim = 256;
   p->mixed_jump = 8.0;
+  p->alpha2 = 1e-3;
+  p->alpha3 = 1e-3;
+  p->entropy_switch = 0;
 }
 
 size_t mfm_workspace_bytes(const mfm_params *p, int64_t n_max) {
@@ -260,6 +269,10 @@ int init_ctx(mfm_ctx *ctx, const mfm_params *p, int64_t n_max, void *workspace,
   ctx->hard_q = (int2 *)(ctx->ws + L.hard_q);
   ctx->hard_cap = L.hard_cap;
   ctx->rec = (double *)(ctx->ws + L.rec);
+  ctx->ekm = (double *)(ctx->ws + L.ekm);
+  ctx->gwork = (double *)(ctx->ws + L.gwork);
+  ctx->inv_a = 1.0;
+  ctx->hubble_n = ctx->hubble_np1 = 0.0;
   ctx->red = (double *)(ctx->ws + L.red);
   ctx->counters = (int64_t *)(ctx->ws + L.counters);
   ctx->scalars = (double *)(ctx->ws + L.scalars);
@@ -458,6 +471,18 @@ int mfm_fluxes(mfm_ctx *ctx, const mfm_particles *pp, const double *dt_dev) {
   if (ctx->p.guess == MFM_GUESS_LEARNED && !ctx->mlp_state)
     return fail(ctx, MFM_E_STATE, "learned guess requested but no network attached");
   HIPCHK(ctx, launch_fluxes(ctx, pp, dt_dev), "fluxes");
+  return MFM_OK;
+}
+
+int mfm_set_cosmology(mfm_ctx *ctx, double inv_a, double hubble_n, double hubble_np1) {
+  if (!ctx) return MFM_E_ARG;
+  if (!(inv_a > 0.0) || !isfinite(inv_a) || !isfinite(hubble_n) || !isfinite(hubble_np1))
+    return fail(ctx, MFM_E_ARG, "invalid cosmology");
+  if ((hubble_n != 0.0 || hubble_np1 != 0.0) && fabs(ctx->p.gamma - 5.0 / 3.0) > 1e-12)
+    return fail(ctx, MFM_E_ARG, "the Hubble update of the total energy needs gamma = 5/3");
+  ctx->inv_a = inv_a;
+  ctx->hubble_n = hubble_n;
+  ctx->hubble_np1 = hubble_np1;
   return MFM_OK;
 }
 

@@ -103,7 +103,7 @@ struct mfm_ctx {
   int2 *crange;        // ncodes_max: (start, count) per cell
   int32_t *scan_tmp;   // block sums of the scans
   int32_t *order;      // n: input slot of each sorted slot
-  double *tmp;         // 11 n doubles: gather buffer of the permutation
+  double *tmp;         // 16 n doubles: gather buffer of the permutation
   double *pos4;        // 4 n: (x, y, z, H at the build) per particle
   int32_t *cand;       // max_list * n candidates (r < cell side), entry k of i at [k * n + i];
                        // after the density loop: the candidates with r >= H_i
@@ -120,6 +120,10 @@ struct mfm_ctx {
   int2 *hard_q;        // faces (lower, higher slot) queued for the flux loop's FP64 pass
   int64_t hard_cap;    // its capacity
   double *rec;         // R_STRIDE * n packed flux records
+  double *ekm;         // n: E_kin^max of the entropy switch (gradient loop)
+  double *gwork;       // 3 n: sum_j dm_ij (x_j - x_i) (flux loop, MFV with gravity)
+  // comoving integration (mfm_set_cosmology)
+  double inv_a, hubble_n, hubble_np1;
   double *red;         // reduction partials
   int64_t *counters;   // NCOUNTERS
   double *scalars;     // small device scalars: [0] max H, [1] dt, [2..6] conserved sums

@@ -13,9 +13,23 @@ struct UpdateArgs {
   double *x, *y, *z, *vx, *vy, *vz, *m, *E, *U;
   const double *dQ, *dt;
   double box[3];
-  double alpha1;
+  double alpha1, alpha2, alpha3;
+  int entropy_switch;
+  const double *accel;  // 3 n external acceleration (null: none)
+  const double *gwork;  // 3 n sum_j dm_ij (x_j - x_i) (null: none)
+  const double *ekm;    // E_kin^max (entropy switch)
+  const double *H;      // support radii (E_grav = m |a| H)
+  double *S;            // entropy (Hubble term)
+  int32_t *emode;       // out: 1 where the next density pass takes P from S
+  double inv_a, hubble_n, hubble_np1, eta_u;
   int64_t *counters;
 };
+
+// X^{n+1} = (X~ - eta dt H^n X^n) / (1 + eta dt H^{n+1}) (sec. 2.3.9)
+__device__ __forceinline__ double hubble(double xt, double x0, double eta, double dt, double hn,
+                                         double hn1) {
+  return (xt - eta * dt * hn * x0) / (1.0 + eta * dt * hn1);
+}
 
 __global__ void __launch_bounds__(BS) update_k(UpdateArgs a) {
   if (a.counters[C_STEP_SKIP]) return;  // the density pass was rejected
@@ -32,23 +46,60 @@ __global__ void __launch_bounds__(BS) update_k(UpdateArgs a) {
     const double dU = dE - (v0x * dpx + v0y * dpy + v0z * dpz) + 0.5 * v0sq * dm;
     const double m1 = m0 + dm;
     if (!(m1 > 0.0)) neg = 1;
-    const double px = m0 * v0x + dpx, py = m0 * v0y + dpy, pz = m0 * v0z + dpz;
+    const double p0x = m0 * v0x, p0y = m0 * v0y, p0z = m0 * v0z;
+    double px = p0x + dpx, py = p0y + dpy, pz = p0z + dpz;
+    const double E0 = a.E[i], U0 = a.U[i];
+    double E1 = E0 + dE;
+    double U1 = U0 + dU;
+    double amag = 0.0;
+    if (a.accel) {
+      // gravity (sec. 2.3.8) by eq. source_term_discr: momentum m a, work P.a
+      // at the start and at the hydro update, and the exchanged mass's work
+      const double ax = a.accel[i], ay = a.accel[n + i], az = a.accel[2 * n + i];
+      amag = sqrt(ax * ax + ay * ay + az * az);
+      double work = 0.0;
+      if (a.gwork) work = 0.5 * (ax * a.gwork[i] + ay * a.gwork[n + i] + az * a.gwork[2 * n + i]);
+      const double pa = 0.5 * dt * ((p0x + px) * ax + (p0y + py) * ay + (p0z + pz) * az);
+      const double hm = 0.5 * dt * (m0 + m1);
+      px += hm * ax;
+      py += hm * ay;
+      pz += hm * az;
+      E1 += pa + work;
+    }
+    if (a.hubble_n != 0.0 || a.hubble_np1 != 0.0) {
+      const double hn = a.hubble_n, hn1 = a.hubble_np1;
+      px = hubble(px, p0x, 0.5, dt, hn, hn1);
+      py = hubble(py, p0y, 0.5, dt, hn, hn1);
+      pz = hubble(pz, p0z, 0.5, dt, hn, hn1);
+      E1 = hubble(E1, E0, 1.0, dt, hn, hn1);
+      U1 = hubble(U1, U0, a.eta_u, dt, hn, hn1);
+      if (a.S) a.S[i] = hubble(a.S[i], a.S[i], a.eta_u, dt, hn, hn1);
+    }
     const double v1x = px / m1, v1y = py / m1, v1z = pz / m1;
-    const double E1 = a.E[i] + dE;
-    double U1 = a.U[i] + dU;
-    // dual-energy switch: U from the total energy when E - E_kin is not small
-    // against E_kin (the test is made on E - E_kin itself, so the recovered
-    // internal energy is positive), else the integrated U
+    // pressure switch (sec. 2.3.7): U from the total energy when E - E_kin is
+    // not small against E_grav + E_kin (the test is made on E - E_kin itself,
+    // so the recovered internal energy is positive); else, with the entropy
+    // switch, the pressure from the entropy where the flow is cold and
+    // smooth; else the integrated U
     const double ekin = (px * px + py * py + pz * pz) / (2.0 * m1);
-    if (E1 - ekin > a.alpha1 * ekin) U1 = E1 - ekin;
+    const double egrav = a.accel ? m1 * amag * a.H[i] : 0.0;
+    int mode = 0;
+    if (E1 - ekin > a.alpha1 * (egrav + ekin)) {
+      U1 = E1 - ekin;
+    } else if (a.entropy_switch &&
+               (U1 < a.alpha2 * (a.ekm[i] + U1) || U1 < a.alpha3 * egrav)) {
+      mode = 1;
+    }
+    if (a.emode) a.emode[i] = mode;
     // where kinetic energy dominates, the noise of dE - v.dP can drive the
     // integrated U through zero: it then keeps its start-of-step value
     if (!(U1 > 0.0)) {
-      U1 = a.U[i];
+      U1 = U0;
       guard = 1;
     }
-    double xn[3] = {a.x[i] + dt * 0.5 * (v0x + v1x), a.y[i] + dt * 0.5 * (v0y + v1y),
-                    a.z[i] + dt * 0.5 * (v0z + v1z)};
+    const double dtx = dt * a.inv_a;  // comoving: dx/dt = v / a
+    double xn[3] = {a.x[i] + dtx * 0.5 * (v0x + v1x), a.y[i] + dtx * 0.5 * (v0y + v1y),
+                    a.z[i] + dtx * 0.5 * (v0z + v1z)};
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
       if (xn[k] < 0.0) xn[k] += a.box[k];
@@ -120,6 +171,19 @@ hipError_t launch_update(mfm_ctx *ctx, const mfm_particles *pp, const double *dt
   a.dt = dt_dev;
   for (int k = 0; k < 3; ++k) a.box[k] = ctx->p.box[k];
   a.alpha1 = ctx->p.alpha1;
+  a.alpha2 = ctx->p.alpha2;
+  a.alpha3 = ctx->p.alpha3;
+  a.entropy_switch = ctx->p.entropy_switch;
+  a.accel = pp->accel;
+  a.gwork = (pp->accel && ctx->p.scheme == MFM_SCHEME_MFV) ? ctx->gwork : nullptr;
+  a.ekm = ctx->ekm;
+  a.H = pp->H;
+  a.S = ctx->p.entropy_switch ? pp->S : nullptr;
+  a.emode = ctx->p.entropy_switch ? pp->emode : nullptr;
+  a.inv_a = ctx->inv_a;
+  a.hubble_n = ctx->hubble_n;
+  a.hubble_np1 = ctx->hubble_np1;
+  a.eta_u = 1.5 * (ctx->p.gamma - 1.0);
   a.counters = ctx->counters;
   update_k<<<blocks_for(pp->n, BS), BS, 0, ctx->stream>>>(a);
   return hipGetLastError();

@@ -37,7 +37,9 @@ class mfm_params(ctypes.Structure):
         ("psi1", ctypes.c_double), ("psi2", ctypes.c_double), ("riemann_tol", ctypes.c_double),
         ("alpha1", ctypes.c_double), ("box", ctypes.c_double * 3),
         ("cell_margin", ctypes.c_double), ("max_cell_dim", ctypes.c_int32),
-        ("pad0", ctypes.c_int32), ("mixed_jump", ctypes.c_double),
+        ("pad0", ctypes.c_int32), ("alpha2", ctypes.c_double), ("alpha3", ctypes.c_double),
+        ("entropy_switch", ctypes.c_int32), ("pad1", ctypes.c_int32),
+        ("mixed_jump", ctypes.c_double),
     ]
 
 
@@ -48,7 +50,7 @@ _DERIVED = ("V", "rho", "P", "c", "ncond")
 
 class mfm_particles(ctypes.Structure):
     _fields_ = ([("n", ctypes.c_int64)] + [(k, _PTR) for k in _STATE + _DERIVED]
-                + [(k, _PTR) for k in ("B", "grad", "dQ", "dt_i", "id")])
+                + [(k, _PTR) for k in ("B", "grad", "dQ", "dt_i", "id", "S", "emode", "accel")])
 
 
 _DIAG_INT = ("h_noconv", "ncond_boosts", "ncond_fail", "cell_rebuilds", "list_overflow",
@@ -89,6 +91,8 @@ def lib():
         L.mfm_create.argtypes = [P, ctypes.c_int64, _PTR, ctypes.c_size_t, _PTR,
                                  ctypes.POINTER(_PTR)]
         L.mfm_destroy.argtypes = [C]
+        L.mfm_set_cosmology.argtypes = [C, ctypes.c_double, ctypes.c_double, ctypes.c_double]
+        L.mfm_set_cosmology.restype = ctypes.c_int
         L.mfm_create_static.argtypes = [P, ctypes.c_int64, _PTR, ctypes.POINTER(_PTR)]
         L.mfm_create_static.restype = ctypes.c_int
         L.mfm_static_workspace_bytes.argtypes = []
@@ -136,7 +140,7 @@ def lib():
 
 
 EXPORTED = ("mfm_default_params", "mfm_workspace_bytes", "mfm_create", "mfm_destroy",
-            "mfm_create_static", "mfm_static_workspace_bytes",
+            "mfm_create_static", "mfm_static_workspace_bytes", "mfm_set_cosmology",
             "mfm_build_cells", "mfm_density", "mfm_gradients", "mfm_fluxes", "mfm_update",
             "mfm_step", "mfm_diagnostics", "mfm_reset_counters", "mfm_enable_timing",
             "mfm_kernel_times", "mfm_strerror", "mfm_last_error", "mfm_mlp_state_bytes",
@@ -167,7 +171,7 @@ def params_from_dict(cfg: dict, **over) -> mfm_params:
     keys = ("scheme", "limiter", "max_boosts", "h_maxit", "riemann_maxit", "gamma", "n_ngb",
             "ncond_max", "ngb_boost", "h_tol", "c_cfl", "psi1", "psi2", "riemann_tol", "alpha1",
             "box", "precision", "max_list", "cell_margin", "max_cell_dim", "guess",
-            "mixed_jump")
+            "mixed_jump", "alpha2", "alpha3", "entropy_switch")
     d = {k: cfg[k] for k in keys if k in cfg}
     d.update(over)
     return mfm_default_params(**d)
@@ -189,7 +193,11 @@ def _ptr(t):
 class ParticleSet:
     """Device arrays of one particle set (torch tensors) and their C struct."""
 
-    def __init__(self, state: dict, device="cuda", ids: bool = True):
+    def __init__(self, state: dict, device="cuda", ids: bool = True, entropy: bool = False,
+                 accel=None):
+        """state: host arrays x..H.  entropy: allocate S and emode (the
+        entropy switch; S is set from U by the first density pass).  accel:
+        optional (3, n) external acceleration."""
         n = int(len(state["x"]))
         self.n = n
         f64 = dict(dtype=torch.float64, device=device)
@@ -200,9 +208,14 @@ class ParticleSet:
         self.t["grad"] = torch.zeros(15, n, **f64)
         self.t["dQ"] = torch.zeros(5, n, **f64)
         self.t["id"] = (torch.arange(n, dtype=torch.int64, device=device) if ids else None)
+        self.t["S"] = torch.zeros(n, **f64) if entropy else None
+        self.t["emode"] = (torch.zeros(n, dtype=torch.int32, device=device) if entropy
+                           else None)
+        self.t["accel"] = (torch.as_tensor(accel, **f64).reshape(3, n).contiguous().clone()
+                           if accel is not None else None)
         self.s = mfm_particles()
         self.s.n = n
-        for k in _STATE + _DERIVED + ("B", "grad", "dQ", "dt_i", "id"):
+        for k in _STATE + _DERIVED + ("B", "grad", "dQ", "dt_i", "id", "S", "emode", "accel"):
             t = self.t[k]
             setattr(self.s, k, t.data_ptr() if t is not None else None)
 
@@ -262,6 +275,11 @@ def mfm_create(params: mfm_params, n_max: int, stream=None) -> Context:
 
 def mfm_destroy(ctx: Context):
     ctx.close()
+
+
+def mfm_set_cosmology(ctx: Context, inv_a: float, hubble_n: float, hubble_np1: float):
+    _check(lib().mfm_set_cosmology(ctx.h, float(inv_a), float(hubble_n), float(hubble_np1)),
+           ctx.h)
 
 
 def mfm_build_cells(ctx: Context, ps: ParticleSet, perm=None):

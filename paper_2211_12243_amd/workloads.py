@@ -204,7 +204,7 @@ def gresho(n: int = 64, nz: int = 8, gamma: float = 1.4, n_ngb: float = 32.0):
 
 
 def kh(n: int = 64, seed: int = 2, gamma: float = 5.0 / 3.0, n_ngb: float = 32.0,
-       jitter: float = 0.1):
+       jitter: float = 0.1, P: float = 2.5):
     rng = np.random.default_rng(seed)
     lat, pos, D = _lattice(n, jitter, rng)
     N = pos.shape[1]
@@ -214,7 +214,7 @@ def kh(n: int = 64, seed: int = 2, gamma: float = 5.0 / 3.0, n_ngb: float = 32.0
     v = np.zeros((3, N))
     v[0] = np.where(inside, 0.5, -0.5)
     v[1] = 0.01 * np.sin(4.0 * math.pi * pos[0])
-    Pn = np.full(N, 2.5)
+    Pn = np.full(N, P)
     return _finish(pos, m, v, Pn, gamma, rho_n, n_ngb, N)
 
 

@@ -55,12 +55,15 @@ def test_default_params_are_the_papers(L):
     assert p.psi1 == 0.5 and p.psi2 == 0.25 and p.alpha1 == 0.01
     assert p.riemann_tol == 1e-10 and p.guess == mfm.MFM_GUESS_PLAIN
     assert tuple(p.box) == (1.0, 1.0, 1.0)
+    # sec. 2.3.7: alpha_2 = alpha_3 = 1/1000; the entropy switch is off by default
+    assert p.alpha2 == 1e-3 and p.alpha3 == 1e-3 and p.entropy_switch == 0
 
 
 @pytest.mark.parametrize("field,value", [
     ("gamma", 1.0), ("n_ngb", 5.0), ("box", (1.0, 0.0, 1.0)), ("max_list", 5000),
     ("max_cell_dim", 2), ("cell_margin", 0.5), ("scheme", 7), ("precision", 3), ("guess", 2),
-    ("riemann_maxit", 0), ("h_maxit", 0), ("c_cfl", 0.0),
+    ("riemann_maxit", 0), ("h_maxit", 0), ("c_cfl", 0.0), ("alpha2", -1.0),
+    ("entropy_switch", 2), ("mixed_jump", 0.5),
 ])
 def test_invalid_parameters_give_no_workspace(L, field, value):
     p = mfm.mfm_default_params(**{field: value})
