@@ -151,6 +151,7 @@ def _bind(L):
     L.orc_kernel_W.argtypes = [ctypes.c_double, ctypes.c_double]
     L.orc_neighbours.argtypes = [P, i64, _D, _D, _D, _D, ctypes.c_int, _I64, _I32]
     L.orc_density.argtypes = [P, i64, _D, _D, _D, _D, _D, _D, _D, C]
+    L.orc_density_at.argtypes = [P, i64, _D, _D, _D, _D, i64, _I64, _D, _D, _D, _D, C]
     L.orc_gradients.argtypes = [P, i64] + [_D] * 10 + [_D] * 8 + [C]
     L.orc_riemann.argtypes = [ctypes.c_double] * 8 + [ctypes.c_int, _D, _D,
                                                         ctypes.POINTER(ctypes.c_int)]
@@ -174,7 +175,7 @@ def _bind(L):
     for f in ("orc_fluxes_src", "orc_ekin_max", "orc_entropy_pressure", "orc_update_src",
               "orc_step_src"):
         getattr(L, f).restype = ctypes.c_int
-    for f in ("orc_neighbours", "orc_density", "orc_gradients", "orc_riemann",
+    for f in ("orc_neighbours", "orc_density", "orc_density_at", "orc_gradients", "orc_riemann",
               "orc_riemann_sample", "orc_face", "orc_fluxes", "orc_update", "orc_step"):
         getattr(L, f).restype = ctypes.c_int
     return L
@@ -223,6 +224,23 @@ def density(cfg: dict, x, y, z, H):
     if rc:
         raise RuntimeError(f"orc_density failed: {rc}")
     return {"H": H, "V": V, "ncond_tilde": nc, "nngb": nngb}, cnt.as_dict()
+
+
+def density_at(cfg: dict, x, y, z, H, idx):
+    """Loop (1) for the particles idx only (every particle a candidate): the
+    H, V, ncond and N_NGB that density() gives them."""
+    p = make_params(cfg)
+    x, y, z, H = (_f64(a) for a in (x, y, z, H))
+    idx = np.ascontiguousarray(idx, dtype=np.int64)
+    nq = idx.size
+    Ho, V, nc, nngb = (np.empty(nq) for _ in range(4))
+    cnt = Counters()
+    rc = lib().orc_density_at(ctypes.byref(p), x.size, _p(x), _p(y), _p(z), _p(H), nq,
+                              idx.ctypes.data_as(_I64), _p(Ho), _p(V), _p(nc), _p(nngb),
+                              ctypes.byref(cnt))
+    if rc:
+        raise RuntimeError(f"orc_density_at failed: {rc}")
+    return {"H": Ho, "V": V, "ncond_tilde": nc, "nngb": nngb}, cnt.as_dict()
 
 
 def gradients(cfg: dict, x, y, z, H, V, m, vx, vy, vz, U):

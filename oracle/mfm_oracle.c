@@ -366,15 +366,79 @@ static void cand_visit(void *vctx, int64_t j, const double d[3], double r2) {
   c->count++;
 }
 
+/* One particle of the density loop: H from the start value H0 within the
+ * candidate radius R, the anisotropy boosts, V, and the counts of what went
+ * wrong.  use_grid = 0 takes every particle as a candidate. */
+typedef struct {
+  int64_t noconv, boosts, fails, fallback;
+} dens_counts;
+
+static void density_one(const orc_params *p, int64_t n, const double *x, const double *y,
+                        const double *z, const orc_grid *g, int use_grid, int periodic,
+                        double half, double R, int64_t i, double H0, double *H, double *V,
+                        double *ncond, double *nngb, dens_counts *k) {
+  cand_ctx c = {NULL, NULL, 0, 0, R * R};
+  for_candidates(p, n, x, y, z, g, use_grid, i, cand_visit, &c);
+  double hi = R;
+  double gv, dg;
+  g_eval(c.r, c.count, hi, p->n_ngb, &gv, &dg);
+  if (!periodic || gv < 0.0) {
+    /* widen: every particle is a candidate */
+    k->fallback += periodic ? 1 : 0;
+    c.count = 0;
+    c.R2 = INFINITY;
+    for_candidates(p, n, x, y, z, g, 0, i, cand_visit, &c);
+    if (periodic) {
+      hi = half;
+    } else {
+      double rm = 0.0;
+      for (int64_t q = 0; q < c.count; ++q) rm = fmax(rm, c.r[q]);
+      hi = 2.0 * rm + 1e-300;
+    }
+  }
+  double target = p->n_ngb;
+  double h = H0;
+  int b = 0;
+  double nc;
+  for (;;) {
+    int it = solve_h(c.r, c.count, target, hi, p->h_tol, p->h_maxit, &h);
+    if (it < 0) k->noconv++;
+    nc = ncond_unweighted(c.d, c.r, c.count, h);
+    if (!(nc > p->ncond_max)) break;
+    if (b == p->max_boosts) {
+      k->fails++;
+      break;
+    }
+    target *= p->ngb_boost;
+    b++;
+    k->boosts++;
+  }
+  double winv = 0.0;
+  for (int64_t q = 0; q < c.count; ++q)
+    if (c.r[q] < h) winv += orc_kernel_W(c.r[q], h);
+  *H = h;
+  *V = 1.0 / winv;
+  *ncond = nc;
+  *nngb = target;
+  free(c.r);
+  free(c.d);
+}
+
+static void density_limits(const orc_params *p, int *periodic, double *half) {
+  *periodic = is_periodic(p);
+  *half = INFINITY;
+  if (*periodic)
+    for (int k = 0; k < 3; ++k) *half = fmin(*half, 0.5 * p->box[k]);
+}
+
 int orc_density(const orc_params *p, int64_t n, const double *x, const double *y,
                 const double *z, double *H, double *V, double *ncond, double *nngb,
                 orc_counters *cnt) {
   if (!p || n <= 0 || !x || !y || !z || !H || !V || !ncond || !nngb || !cnt) return -1;
   if (!(p->n_ngb > 32.0 / 3.0)) return -1; /* the self term alone would exceed N_NGB */
-  int periodic = is_periodic(p);
-  double half = INFINITY;
-  if (periodic)
-    for (int k = 0; k < 3; ++k) half = fmin(half, 0.5 * p->box[k]);
+  int periodic;
+  double half;
+  density_limits(p, &periodic, &half);
   /* Candidate radius: twice the start value (covers the N_NGB boosts), at
    * most half the box.  A particle whose root is not bracketed falls back to
    * a brute-force search with the widest radius. */
@@ -390,54 +454,51 @@ int orc_density(const orc_params *p, int64_t n, const double *x, const double *y
   int64_t noconv = 0, boosts = 0, fails = 0, fallback = 0;
 #pragma omp parallel for schedule(dynamic, 64) reduction(+ : noconv, boosts, fails, fallback)
   for (int64_t i = 0; i < n; ++i) {
-    cand_ctx c = {NULL, NULL, 0, 0, R[i] * R[i]};
-    for_candidates(p, n, x, y, z, &g, have_grid, i, cand_visit, &c);
-    double hi = R[i];
-    double gv, dg;
-    g_eval(c.r, c.count, hi, p->n_ngb, &gv, &dg);
-    if (!periodic || gv < 0.0) {
-      /* widen: every particle is a candidate */
-      fallback += periodic ? 1 : 0;
-      c.count = 0;
-      c.R2 = INFINITY;
-      for_candidates(p, n, x, y, z, &g, 0, i, cand_visit, &c);
-      if (periodic) {
-        hi = half;
-      } else {
-        double rm = 0.0;
-        for (int64_t k = 0; k < c.count; ++k) rm = fmax(rm, c.r[k]);
-        hi = 2.0 * rm + 1e-300;
-      }
-    }
-    double target = p->n_ngb;
-    double h = H[i];
-    int b = 0;
-    double nc;
-    for (;;) {
-      int it = solve_h(c.r, c.count, target, hi, p->h_tol, p->h_maxit, &h);
-      if (it < 0) noconv++;
-      nc = ncond_unweighted(c.d, c.r, c.count, h);
-      if (!(nc > p->ncond_max)) break;
-      if (b == p->max_boosts) {
-        fails++;
-        break;
-      }
-      target *= p->ngb_boost;
-      b++;
-      boosts++;
-    }
-    double winv = 0.0;
-    for (int64_t k = 0; k < c.count; ++k)
-      if (c.r[k] < h) winv += orc_kernel_W(c.r[k], h);
-    H[i] = h;
-    V[i] = 1.0 / winv;
-    ncond[i] = nc;
-    nngb[i] = target;
-    free(c.r);
-    free(c.d);
+    dens_counts k = {0, 0, 0, 0};
+    density_one(p, n, x, y, z, &g, have_grid, periodic, half, R[i], i, H[i], &H[i], &V[i],
+                &ncond[i], &nngb[i], &k);
+    noconv += k.noconv;
+    boosts += k.boosts;
+    fails += k.fails;
+    fallback += k.fallback;
   }
   if (have_grid) grid_free(&g);
   free(R);
+  cnt->h_noconv += noconv;
+  cnt->ncond_boosts += boosts;
+  cnt->ncond_fail += fails;
+  cnt->h_fallback += fallback;
+  return 0;
+}
+
+/* The density loop for the nq particles listed in idx only (every particle
+ * a candidate, so that a sample of a large set costs nq n separations): the
+ * same H, V, ncond and N_NGB as orc_density gives them, written to entry q
+ * of the outputs for particle idx[q]. */
+int orc_density_at(const orc_params *p, int64_t n, const double *x, const double *y,
+                   const double *z, const double *H0, int64_t nq, const int64_t *idx,
+                   double *H, double *V, double *ncond, double *nngb, orc_counters *cnt) {
+  if (!p || n <= 0 || nq < 0 || !x || !y || !z || !H0 || !idx || !H || !V || !ncond || !nngb ||
+      !cnt)
+    return -1;
+  if (!(p->n_ngb > 32.0 / 3.0)) return -1;
+  for (int64_t q = 0; q < nq; ++q)
+    if (idx[q] < 0 || idx[q] >= n) return -1;
+  int periodic;
+  double half;
+  density_limits(p, &periodic, &half);
+  int64_t noconv = 0, boosts = 0, fails = 0, fallback = 0;
+#pragma omp parallel for schedule(dynamic, 1) reduction(+ : noconv, boosts, fails, fallback)
+  for (int64_t q = 0; q < nq; ++q) {
+    const int64_t i = idx[q];
+    dens_counts k = {0, 0, 0, 0};
+    density_one(p, n, x, y, z, NULL, 0, periodic, half, fmin(2.0 * H0[i], half), i, H0[i],
+                &H[q], &V[q], &ncond[q], &nngb[q], &k);
+    noconv += k.noconv;
+    boosts += k.boosts;
+    fails += k.fails;
+    fallback += k.fallback;
+  }
   cnt->h_noconv += noconv;
   cnt->ncond_boosts += boosts;
   cnt->ncond_fail += fails;

@@ -93,6 +93,13 @@ int orc_density(const orc_params *p, int64_t n, const double *x, const double *y
                 const double *z, double *H, double *V, double *ncond, double *nngb,
                 orc_counters *cnt);
 
+/* The same for the nq particles idx[0..nq) only, with every particle a
+ * candidate (a sample of a large set).  In: x,y,z, H0 (start values, all n).
+ * Out: H, V, ncond, nngb of particle idx[q] at entry q (nq entries each). */
+int orc_density_at(const orc_params *p, int64_t n, const double *x, const double *y,
+                   const double *z, const double *H0, int64_t nq, const int64_t *idx,
+                   double *H, double *V, double *ncond, double *nngb, orc_counters *cnt);
+
 /* Gradient loop (sec. 2.3.3, 2.3.6) and time-step loop (sec. 2.3.10).
  * In: x,y,z,H,V,m,vx,vy,vz,U.  Out: rho, P, c, B[6n], grad[15n] (already
  * multiplied by the limiter), alpha[5n] (limiter factors), ncond (weighted E),
