@@ -81,6 +81,8 @@ def parse():
     ap.add_argument("--scheme", default="mfm", choices=["mfm", "mfv"])
     ap.add_argument("--train-steps", type=int, default=800)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--clustered", type=int, default=256,
+                    help="particles per axis of the clustered-gas leg (0: skip it)")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="first copy a buffer of this many MiB on the device (a kernel of "
                          "known traffic, to calibrate hardware byte counters)")
@@ -393,6 +395,67 @@ def run_variant(args, st, variant, mlp_state, log_):
     return res
 
 
+def run_clustered(args, log_):
+    """The clustered gas (log-normal density, sigma_ln = 1.5; smoothing lengths
+    spread over a factor of about 30): mixed MFM, the first step from the
+    initial state (it counts the neighbour lists before planning them) and
+    then steady steps."""
+    import torch
+
+    from paper_2211_12243_amd import mfm
+    from paper_2211_12243_amd import workloads as W
+
+    t = time.perf_counter()
+    st = W.clustered(n=args.clustered, seed=4)
+    n = st["x"].size
+    log_(f"[bench] clustered n={args.clustered}^3 ({n} particles) made in "
+         f"{time.perf_counter() - t:.1f}s")
+    ctx = mfm.Context(mfm.params_from_dict({"scheme": "mfm"}, precision="mixed"), n)
+    ps = mfm.ParticleSet(st, ids=False)
+    del st
+    mfm.mfm_enable_timing(ctx, True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    mfm.mfm_step(ctx, ps, 1.0)
+    torch.cuda.synchronize()
+    first_ms = (time.perf_counter() - t0) * 1e3
+    d1 = mfm.mfm_diagnostics(ctx, ps)
+    first_times = mfm.mfm_kernel_times(ctx)
+    mfm.mfm_enable_timing(ctx, True)  # restarts the stage clocks
+    mfm.mfm_reset_counters(ctx)
+    K = 3
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(K):
+        mfm.mfm_step(ctx, ps, 1.0)
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) / K * 1e3
+    times = mfm.mfm_kernel_times(ctx)
+    diag = mfm.mfm_diagnostics(ctx, ps)
+    H = ps["H"]
+    spread = float((H.max() / H.min()).item())
+    ctx.close()
+    t_pairs = (times["gradients"][0] + times["fluxes"][0]) / 1e3
+    res = {
+        "workload": f"clustered gas {args.clustered}^3 (log-normal, sigma_ln 1.5, vrms 10 c_s), "
+                    "MFM mixed",
+        "particles": n,
+        "first_step_ms": first_ms,
+        "first_step_rebuilds": d1["cell_rebuilds"],
+        "first_step_stage_ms": {k: v[0] for k, v in first_times.items()},
+        "ms_per_step": ms,
+        "steps": K,
+        "pair_interactions_per_s": (diag["grad_pairs"] + diag["faces"]) / t_pairs,
+        "stage_ms_per_step": {k: v[0] / K for k, v in times.items()},
+        "pairs_per_step": {"gradient": diag["grad_pairs"] / K, "flux_faces": diag["faces"] / K},
+        "list_retries": diag["list_overflow"],
+        "h_spread": spread,
+        "vacuum_faces_per_step": diag["vacuum"] / K,
+    }
+    log_(f"[bench] clustered: {res}")
+    return res
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -435,6 +498,7 @@ def main():
     if "mixed_learned" in variants:
         mlp_state, train_info = train_guess(args, log_)
     res = {v: run_variant(args, st, v, mlp_state, log_) for v in variants}
+    clustered = run_clustered(args, log_) if args.clustered > 0 else None
     h = res[args.headline]
     out = {
         "metric": "pair interactions/s (grad+flux) & hydro-step ms, 2.1M Sedov, mixed vs FP64",
@@ -459,6 +523,7 @@ def main():
                      for v, r in res.items()},
         "pairs_per_step": h["pairs_per_step"],
         "guess_training": train_info,
+        "clustered": clustered,
     }
     if not args.no_cpu_baseline:
         fields = {v: step1_fields(args, st, v) for v in ("fp64", "mixed") if v in variants}

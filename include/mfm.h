@@ -46,8 +46,8 @@ extern "C" {
 #define MFM_E_WORKSPACE (-2)  /* workspace missing or smaller than mfm_workspace_bytes() */
 #define MFM_E_HIP (-3)        /* HIP runtime error (text in mfm_last_error) */
 #define MFM_E_H_NOCONV (-4)   /* some smoothing-length solve hit its iteration cap */
-#define MFM_E_CELLS (-5)      /* smoothing lengths outgrew the cell grid: rebuild and repeat */
-#define MFM_E_LIST (-6)       /* a particle has more neighbours than the list capacity */
+#define MFM_E_CELLS (-5)      /* smoothing lengths outgrew their search radii: rebuild and repeat */
+#define MFM_E_LIST (-6)       /* the neighbour lists do not fit the list pool (see max_list) */
 #define MFM_E_NONFINITE (-7)  /* a non-finite time step or state was produced */
 #define MFM_E_STATE (-8)      /* call order violated (e.g. mfm_fluxes before mfm_gradients) */
 
@@ -72,7 +72,11 @@ typedef struct mfm_params {
   int32_t h_maxit;       /* smoothing-length iteration cap (default 64) */
   int32_t riemann_maxit; /* Riemann Newton cap (default 100) */
   int32_t guess;         /* MFM_GUESS_PLAIN or MFM_GUESS_LEARNED */
-  int32_t max_list;      /* candidate list capacity per particle (default 128) */
+  int32_t max_list;      /* list pool, in entries per particle (default 128): the
+                            lists of each chunk of 16 consecutive particles take
+                            16 x (the chunk's longest candidate list + 1/8 + 4),
+                            planned from the previous search, so a few long
+                            lists cost little; the pool must hold the sum */
   double gamma;          /* adiabatic index (> 1) */
   double n_ngb;          /* neighbour number N_NGB (> 32/3, non-integer allowed) */
   double ncond_max;      /* condition-number threshold (default 100) */
@@ -86,12 +90,11 @@ typedef struct mfm_params {
   double riemann_tol;    /* relative Newton step tolerance of the exact solver (default 1e-10) */
   double alpha1;         /* dual-energy switch: U > alpha1 E_kin -> U from E (default 0.01) */
   double box[3];         /* periodic box sides; all > 0 (the library needs a periodic box) */
-  double cell_margin;    /* cell side >= cell_margin * max_i H_i (>= 1, default 1.10).
-                            Also the largest growth of an H in one density pass
-                            (H <= cell_margin * its value at the cell build);
-                            a pair is a candidate when r < cell_margin *
-                            max(H_i, H_j) at the build */
-  int32_t max_cell_dim;  /* cells per axis at most (3..512, default 256) */
+  double cell_margin;    /* search margin (>= 1, default 1.10): a pair is a
+                            candidate when r < cell_margin * max(H_i, H_j) at
+                            the build, and an H may grow by at most this
+                            factor in one density pass */
+  int32_t reserved;      /* must be 0 */
   int32_t pad0;
   double alpha2, alpha3; /* entropy switch (sec. 2.3.7): the pressure comes from the entropy
                             when U < alpha2 (E_kin^max + U) or U < alpha3 E_grav (default
@@ -140,7 +143,7 @@ typedef struct mfm_diag {
   int64_t ncond_boosts;  /* N_NGB boosts applied */
   int64_t ncond_fail;    /* particles still above ncond_max after max_boosts */
   int64_t cell_rebuilds; /* cell grids rebuilt because H outgrew them */
-  int64_t list_overflow; /* particles with more than max_list neighbours */
+  int64_t list_overflow; /* particles whose lists outgrew their planned block (pass redone) */
   int64_t grad_pairs;    /* sum_i #{j != i : r_ij < H_i} of the last mfm_gradients */
   int64_t faces;         /* #{unordered pairs : r_ij < max(H_i, H_j)} of the last mfm_fluxes */
   int64_t riemann_iters; /* Newton iterations of the last mfm_fluxes */
@@ -187,8 +190,8 @@ int mfm_destroy(struct mfm_ctx *ctx);
  * nothing: no hipMalloc, no library allocator.  The caller still owns the
  * particle arrays.
  *   - Limit: mfm_workspace_bytes(p, n_max) must fit in the array (about
- *     15 000 particles at max_list 128 with max_cell_dim 32; the cell tables
- *     grow with max_cell_dim^3); larger requests return MFM_E_WORKSPACE.
+ *     15 000 particles at max_list 128); larger requests return
+ *     MFM_E_WORKSPACE.
  *   - One such context per GPU at a time (MFM_E_STATE while one exists;
  *     mfm_destroy releases it).  All its calls share the GPU's array, which
  *     keeps the last call's contents: calls that overlap on one GPU race.
@@ -199,15 +202,17 @@ int mfm_destroy(struct mfm_ctx *ctx);
 size_t mfm_static_workspace_bytes(void);
 int mfm_create_static(const mfm_params *p, int64_t n_max, void *stream, struct mfm_ctx **out);
 
-/* Sort the particles into cells on a Morton (Z-order) curve of cells of side
- * >= cell_margin * max H (sec. 2.2.1: particles are reordered in memory so
- * that spatial neighbours are contiguous) and permute the state arrays
- * (x..H) IN PLACE into that order.  The sort is stable: within a cell the
- * particles keep their order from before the call, so a second call on
- * unchanged particles is the identity.  perm (device int64, n, may be NULL)
- * receives for each new slot k the slot the particle had before the call.
- * The H values at this call bound the next mfm_density (see cell_margin).
- * Synchronises (it reads max H to size the grid). */
+/* Sort the particles along a Morton (Z-order) curve of 10 bits per axis of
+ * their place in the box (sec. 2.2.1: particles are reordered in memory so
+ * that spatial neighbours are contiguous), permute the state arrays (x..H,
+ * and S, emode, accel when given) IN PLACE into that order, and build the
+ * neighbour-search tree over buckets of 64 consecutive particles (sec.
+ * 2.2.3): per node the bounding box and cell_margin times the largest H.
+ * The sort is stable: particles with the same key keep their order from
+ * before the call, so a second call on unchanged particles is the identity.
+ * perm (device int64, n, may be NULL) receives for each new slot k the slot
+ * the particle had before the call.  The H values at this call bound the
+ * next mfm_density (see cell_margin).  Does not synchronise. */
 int mfm_build_cells(struct mfm_ctx *ctx, const mfm_particles *parts, int64_t *perm);
 
 /* Loop (1), sec. 2.3.2 and 2.3.5: per particle, solve
@@ -215,11 +220,16 @@ int mfm_build_cells(struct mfm_ctx *ctx, const mfm_particles *parts, int64_t *pe
  * (self included); if the condition number of E~ = sum_j W d d^T exceeds
  * ncond_max, multiply N_NGB by ngb_boost and solve again.  Writes H, V, rho,
  * P, c, ncond and the neighbour lists used by the next two loops.  Requires
- * mfm_build_cells on the same positions.  If some H reaches its bound (the
- * cell side, or cell_margin times its value at the build) the pass is
- * discarded: those H are replaced by estimates of their roots, the next
- * mfm_build_cells uses a larger margin, and the call returns MFM_E_CELLS;
- * build and density are then repeated (mfm_step does this, up to 4 times).
+ * mfm_build_cells on the same positions.  If some H reaches its bound (half
+ * the smallest box side, or cell_margin times its value at the build) the
+ * pass is discarded: every H is replaced by its root, or by an estimate of it
+ * where the bound was reached, the next mfm_build_cells searches with those
+ * (and a larger margin after a second such pass in a row), and the call
+ * returns MFM_E_CELLS; build and density are then repeated (mfm_step does
+ * this, up to 6 attempts).  The neighbour lists go to blocks planned from the
+ * previous search's list lengths; a list longer than its block leaves the
+ * state untouched and the pass is planned again from the lengths it found
+ * (inside this call; mfm_step takes another attempt).
  * Synchronises (it reads the pass counters). */
 int mfm_density(struct mfm_ctx *ctx, const mfm_particles *parts);
 

@@ -1,99 +1,29 @@
-// cells.hip -- neighbour-cell build: Morton order of cells, counting sort of
-// the particles into it, and the in-place permutation of the state arrays.
+// cells.hip -- the particle order and the neighbour-search tree: Morton
+// (Z-order) keys of the particles' positions, a stable radix sort by them,
+// the in-place permutation of the state arrays, and the bucket tree.
 //
 // The paper reorders its particle array so that the particles of a tree node
 // are contiguous (sec. 2.2.1) and searches neighbours per bucket of particles
-// (sec. 2.2.3).  Here the buckets are cells of a uniform periodic grid whose
-// side is at least the largest support radius, laid out along a Z-order curve,
-// so every pair closer than max(H_i, H_j) is found in the 27 cells around a
-// particle's own, and a 64-lane wavefront of consecutive particles touches a
-// compact set of cells.
+// (sec. 2.2.3).  Here the keys carry KEY_BITS bits per axis, fine enough that
+// the sorted array follows a Z-order curve through the particles even where
+// they cluster; buckets are runs of BUCKET consecutive particles, and a tree
+// over them (TREE_FANOUT consecutive nodes per parent) carries each node's
+// bounding box and largest candidate radius.  The search (density.hip) walks
+// that tree per chunk of a bucket, so a particle's candidates follow its own
+// H and its neighbours', not the largest H of the set.
 #include "mfm_internal.h"
 
 namespace {
 
 constexpr int BS = 256;
-constexpr int RED_BLOCKS = 1024;
-
-__global__ void fill_i32_k(int32_t *a, int64_t n, int32_t v) {
-  for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < n;
-       k += (int64_t)gridDim.x * blockDim.x)
-    a[k] = v;
-}
-
-__global__ void max_partial_k(const double *__restrict__ v, int64_t n, double *partial) {
-  __shared__ double s[BS / 64];
-  double m = 0.0;
-  for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < n;
-       k += (int64_t)gridDim.x * blockDim.x)
-    m = fmax(m, v[k]);
-  for (int o = 32; o > 0; o >>= 1) m = fmax(m, __shfl_xor(m, o, 64));
-  if ((threadIdx.x & 63) == 0) s[threadIdx.x >> 6] = m;
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    for (int w = 1; w < BS / 64; ++w) m = fmax(m, s[w]);
-    partial[blockIdx.x] = m;
-  }
-}
-
-__global__ void max_final_k(const double *partial, int np, double *out) {
-  __shared__ double s[BS / 64];
-  double m = 0.0;
-  for (int k = threadIdx.x; k < np; k += blockDim.x) m = fmax(m, partial[k]);
-  for (int o = 32; o > 0; o >>= 1) m = fmax(m, __shfl_xor(m, o, 64));
-  if ((threadIdx.x & 63) == 0) s[threadIdx.x >> 6] = m;
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    for (int w = 1; w < BS / 64; ++w) m = fmax(m, s[w]);
-    out[0] = m;
-  }
-}
-
-// Runs of equal keys among the lanes of a wavefront (every lane must take
-// part): whether this lane starts a run, the run's length (valid at its
-// start) and the lane that starts this lane's run.  The particles arrive in
-// last step's cell order, so runs are long and one atomic per run replaces
-// one per particle.
-__device__ __forceinline__ void key_runs(uint32_t key, int lane, bool &head, int &len,
-                                         int &head_lane) {
-  const uint32_t prev = __shfl_up(key, 1, 64);
-  head = lane == 0 || prev != key;
-  const uint64_t hm = __ballot(head);
-  const uint64_t upto = (2ull << lane) - 1ull;  // lanes 0..lane (all 64 bits at lane 63)
-  const uint64_t after = hm & ~upto;
-  len = (after ? __ffsll((unsigned long long)after) - 1 : 64) - lane;
-  head_lane = 63 - __clzll(hm & upto);
-}
-
-constexpr uint32_t NO_KEY = 0xffffffffu;  // lanes past the end (no cell has this code)
-
-// Morton code of each particle's cell and the per-cell histogram.
-__global__ void cell_code_k(int64_t n, const double *__restrict__ x, const double *__restrict__ y,
-                            const double *__restrict__ z, CellGrid g, uint32_t *code,
-                            int32_t *count) {
-  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  const int lane = threadIdx.x & 63;
-  const bool live = i < n;
-  uint32_t c = NO_KEY;
-  if (live) {
-    const int cx = cell_coord(x[i], g.inv[0], g.nc[0]);
-    const int cy = cell_coord(y[i], g.inv[1], g.nc[1]);
-    const int cz = cell_coord(z[i], g.inv[2], g.nc[2]);
-    c = morton3(cx, cy, cz);
-    code[i] = c;
-  }
-  bool head;
-  int len, hl;
-  key_runs(c, lane, head, len, hl);
-  if (live && head) atomicAdd(count + c, len);
-}
 
 // Exclusive scan, 1024 elements per block (4 per thread), block totals out.
-__global__ void scan_block_k(const int32_t *in, int32_t *out, int64_t n, int32_t *block_sums) {
-  __shared__ int32_t s[BS];
+template <typename T>
+__global__ void scan_block_k(const T *in, T *out, int64_t n, T *block_sums) {
+  __shared__ T s[BS];
   int64_t base = blockIdx.x * (int64_t)(4 * BS) + 4 * threadIdx.x;
-  int32_t v[4];
-  int32_t t = 0;
+  T v[4];
+  T t = 0;
   for (int k = 0; k < 4; ++k) {
     v[k] = (base + k < n) ? in[base + k] : 0;
     t += v[k];
@@ -101,12 +31,12 @@ __global__ void scan_block_k(const int32_t *in, int32_t *out, int64_t n, int32_t
   s[threadIdx.x] = t;
   __syncthreads();
   for (int off = 1; off < BS; off <<= 1) {
-    int32_t add = (threadIdx.x >= (unsigned)off) ? s[threadIdx.x - off] : 0;
+    T add = (threadIdx.x >= (unsigned)off) ? s[threadIdx.x - off] : 0;
     __syncthreads();
     s[threadIdx.x] += add;
     __syncthreads();
   }
-  int32_t run = s[threadIdx.x] - t;  // exclusive prefix of this thread
+  T run = s[threadIdx.x] - t;  // exclusive prefix of this thread
   for (int k = 0; k < 4; ++k) {
     if (base + k < n) out[base + k] = run;
     run += v[k];
@@ -114,84 +44,191 @@ __global__ void scan_block_k(const int32_t *in, int32_t *out, int64_t n, int32_t
   if (threadIdx.x == BS - 1) block_sums[blockIdx.x] = s[BS - 1];
 }
 
-__global__ void scan_add_k(int32_t *out, int64_t n, const int32_t *block_offsets) {
+template <typename T>
+__global__ void scan_add_k(T *out, int64_t n, const T *block_offsets) {
   int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (i < n) out[i] += block_offsets[i / (4 * BS)];
 }
 
-hipError_t scan_exclusive(hipStream_t st, const int32_t *in, int32_t *out, int64_t n,
-                          int32_t *tmp) {
+// In place is allowed (in == out); tmp holds the block sums of every level.
+template <typename T>
+hipError_t scan_exclusive_t(hipStream_t st, const T *in, T *out, int64_t n, T *tmp) {
   int64_t nb = (n + 4 * BS - 1) / (4 * BS);
-  scan_block_k<<<(int)nb, BS, 0, st>>>(in, out, n, tmp);
+  scan_block_k<T><<<(int)nb, BS, 0, st>>>(in, out, n, tmp);
   if (nb > 1) {
-    hipError_t e = scan_exclusive(st, tmp, tmp, nb, tmp + nb);
+    hipError_t e = scan_exclusive_t<T>(st, tmp, tmp, nb, tmp + nb);
     if (e != hipSuccess) return e;
-    scan_add_k<<<blocks_for(n, BS), BS, 0, st>>>(out, n, tmp);
+    scan_add_k<T><<<blocks_for(n, BS), BS, 0, st>>>(out, n, tmp);
   }
   return hipGetLastError();
 }
 
-__global__ void scatter_k(int64_t n, const uint32_t *__restrict__ code, int32_t *cursor,
-                          int32_t *order) {
-  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  const int lane = threadIdx.x & 63;
-  const bool live = i < n;
-  const uint32_t c = live ? code[i] : NO_KEY;
-  bool head;
-  int len, hl;
-  key_runs(c, lane, head, len, hl);
-  int base = 0;
-  if (live && head) base = atomicAdd(cursor + c, len);
-  base = __shfl(base, hl, 64);
-  if (live) order[base + (lane - hl)] = (int32_t)i;
+hipError_t scan_exclusive(hipStream_t st, const int32_t *in, int32_t *out, int64_t n,
+                          int32_t *tmp) {
+  return scan_exclusive_t<int32_t>(st, in, out, n, tmp);
 }
 
-// Within a cell, order the particles by their slot before the sort, so the
-// result does not depend on the order the atomics were served in.  One
-// wavefront per cell (grid-stride over the cell codes): a lane holds one
-// member, and its place is the number of smaller members (the slots are
-// distinct).  A cell of more than 64 particles is sorted by one lane.
-__global__ void cell_sort_k(int64_t ncodes, const int32_t *__restrict__ start,
-                            const int32_t *__restrict__ count, int32_t *order) {
-  const int lane = threadIdx.x & 63;
-  const int64_t nw = ((int64_t)gridDim.x * blockDim.x) >> 6;
-  for (int64_t c = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) >> 6; c < ncodes; c += nw) {
-    const int k = count[c];  // the same in every lane: the branches below are uniform
-    if (k < 2) continue;
-    int32_t *a = order + start[c];
-    if (k <= 64) {
-      const int32_t v = lane < k ? a[lane] : 0x7fffffff;
-      int rank = 0;
-      for (int t = 0; t < k; ++t) rank += __builtin_amdgcn_readlane(v, t) < v ? 1 : 0;
-      if (lane < k) a[rank] = v;  // every read above has completed
-    } else if (lane == 0) {
-      for (int s = 1; s < k; ++s) {
-        int32_t v = a[s];
-        int t = s - 1;
-        while (t >= 0 && a[t] > v) {
-          a[t + 1] = a[t];
-          --t;
-        }
-        a[t + 1] = v;
-      }
+// Lanes of the wavefront whose 8-bit digit equals this lane's, among the
+// live ones (every lane must take part).
+__device__ __forceinline__ uint64_t match_digit(uint32_t d, bool live) {
+  uint64_t m = __ballot(live);
+#pragma unroll
+  for (int b = 0; b < RADIX_BITS; ++b) {
+    const uint64_t t = __ballot((d >> b) & 1u);
+    m &= ((d >> b) & 1u) ? t : ~t;
+  }
+  return m;
+}
+
+__device__ __forceinline__ int lanes_below(uint64_t m) {
+  return (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32),
+                                        __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+}
+
+// Morton key of each particle (bits per axis of its place in the box) and
+// its slot, the value the sort carries.
+__global__ void key_k(int64_t n, const double *__restrict__ x, const double *__restrict__ y,
+                      const double *__restrict__ z, double sx, double sy, double sz, int bits,
+                      uint32_t *key, int32_t *val) {
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const int top = (1 << bits) - 1;
+  auto q = [top](double v, double s) {
+    const int c = (int)(v * s);
+    return c < 0 ? 0 : (c > top ? top : c);
+  };
+  key[i] = morton3(q(x[i], sx), q(y[i], sy), q(z[i], sz));
+  val[i] = (int32_t)i;
+}
+
+// One pass of the least-significant-digit radix sort: each workgroup counts
+// the digits of its tile (SORT_TILE consecutive items) into hist, digit-major
+// (hist[d * nb + b]), so that an exclusive scan of hist gives every
+// workgroup's first output slot for every digit.
+__global__ void __launch_bounds__(SORT_BS) radix_hist_k(int64_t n, const uint32_t *__restrict__ key,
+                                                        int shift, int nb, int32_t *hist) {
+  __shared__ int32_t s[RADIX];
+  const int t = threadIdx.x;
+  s[t] = 0;
+  __syncthreads();
+  const int64_t base = (int64_t)blockIdx.x * SORT_TILE;
+  for (int r = 0; r < SORT_ITEMS; ++r) {
+    const int64_t i = base + r * SORT_BS + t;
+    if (base + r * SORT_BS >= n) break;  // uniform
+    const bool live = i < n;
+    const uint32_t d = live ? (key[i] >> shift) & (RADIX - 1) : 0u;
+    const uint64_t m = match_digit(d, live);
+    if (live && lanes_below(m) == 0) atomicAdd(&s[d], __popcll(m));
+  }
+  __syncthreads();
+  hist[(int64_t)t * nb + blockIdx.x] = s[t];
+}
+
+// The scatter of the same pass.  The tile goes round by round (SORT_BS
+// items), wavefront by wavefront, lane by lane: an item's slot is its
+// workgroup's first slot for the digit, plus the items of that digit in the
+// earlier rounds, the earlier wavefronts of the round and the lower lanes.
+// Equal digits keep their order, so the sort is stable and the result does
+// not depend on scheduling.
+__global__ void __launch_bounds__(SORT_BS) radix_scatter_k(
+    int64_t n, const uint32_t *__restrict__ key, const int32_t *__restrict__ val, int shift, int nb,
+    const int32_t *__restrict__ first, uint32_t *key_out, int32_t *val_out) {
+  constexpr int NW = SORT_BS / 64;
+  __shared__ int32_t s_base[RADIX];
+  __shared__ int32_t s_w[NW][RADIX];
+  const int t = threadIdx.x, w = t >> 6;
+  s_base[t] = first[(int64_t)t * nb + blockIdx.x];
+#pragma unroll
+  for (int q = 0; q < NW; ++q) s_w[q][t] = 0;
+  __syncthreads();
+  const int64_t base = (int64_t)blockIdx.x * SORT_TILE;
+  for (int r = 0; r < SORT_ITEMS; ++r) {
+    if (base + r * SORT_BS >= n) break;  // uniform
+    const int64_t i = base + r * SORT_BS + t;
+    const bool live = i < n;
+    uint32_t k = 0u, d = 0u;
+    int32_t v = 0;
+    if (live) {
+      k = key[i];
+      v = val[i];
+      d = (k >> shift) & (RADIX - 1);
     }
+    const uint64_t m = match_digit(d, live);
+    const int below = lanes_below(m);
+    if (live && below == 0) s_w[w][d] = __popcll(m);
+    __syncthreads();
+    if (live) {
+      int at = s_base[d] + below;
+      for (int q = 0; q < w; ++q) at += s_w[q][d];
+      key_out[at] = k;
+      val_out[at] = v;
+    }
+    __syncthreads();
+    int tot = 0;
+#pragma unroll
+    for (int q = 0; q < NW; ++q) {
+      tot += s_w[q][t];
+      s_w[q][t] = 0;
+    }
+    s_base[t] += tot;
+    __syncthreads();
   }
 }
 
-__global__ void range_k(int64_t ncodes, const int32_t *__restrict__ start,
-                        const int32_t *__restrict__ count, int2 *range) {
-  int64_t c = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (c < ncodes) range[c] = make_int2(start[c], count[c]);
+// Level 0 of the tree: one wavefront per bucket reduces the bounding box and
+// the largest H (at the build) of its particles.
+__global__ void __launch_bounds__(64) leaf_box_k(int64_t n, const double4 *__restrict__ pos4,
+                                                 double hfac, double *node) {
+  const int64_t b = blockIdx.x;
+  const int64_t i = b * BUCKET + threadIdx.x;
+  const bool live = i < n;
+  const double4 p = pos4[live ? i : b * BUCKET];  // a bucket has at least one particle
+  double lo[3] = {p.x, p.y, p.z}, hi[3] = {p.x, p.y, p.z}, h = live ? p.w : 0.0;
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    lo[k] = wave_min_f64(lo[k]);
+    hi[k] = wave_max_f64(hi[k]);
+  }
+  h = wave_max_f64(h);
+  if (threadIdx.x < TNODE) {
+    const double v[TNODE] = {lo[0], lo[1], lo[2], hi[0], hi[1], hi[2], hfac * h, 0.0};
+    node[b * TNODE + threadIdx.x] = v[threadIdx.x];
+  }
+}
+
+// Level l + 1 from level l: each node the union of its children's boxes and
+// the largest of their radii.
+__global__ void inner_box_k(const double *__restrict__ child, int nchild, double *parent,
+                            int nparent) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= nparent) return;
+  double v[TNODE];
+  const int c0 = k * TREE_FANOUT, c1 = min(c0 + TREE_FANOUT, nchild);
+#pragma unroll
+  for (int q = 0; q < TNODE; ++q) v[q] = child[(int64_t)c0 * TNODE + q];
+  for (int c = c0 + 1; c < c1; ++c) {
+    const double *w = child + (int64_t)c * TNODE;
+#pragma unroll
+    for (int q = 0; q < 3; ++q) {
+      v[q] = fmin(v[q], w[q]);
+      v[3 + q] = fmax(v[3 + q], w[3 + q]);
+    }
+    v[6] = fmax(v[6], w[6]);
+  }
+#pragma unroll
+  for (int q = 0; q < TNODE; ++q) parent[(int64_t)k * TNODE + q] = v[q];
 }
 
 // The state arrays the permutation moves: the ten FP64 fields, the labels,
-// and the optional source-term arrays (entropy, the three acceleration
-// components, the entropy-mode flags); absent ones are null.
+// the optional source-term arrays (entropy, the three acceleration
+// components, the entropy-mode flags; absent ones are null) and the
+// candidate counts of the last search (the next list plan's input).
 struct Fields {
   double *f[10];
   int64_t *id;
   double *x[4];
   int32_t *emode;
+  int32_t *ncand;
 };
 
 __global__ void gather_k(int64_t n, Fields fs, const int32_t *__restrict__ order, double *tmp,
@@ -206,6 +243,7 @@ __global__ void gather_k(int64_t n, Fields fs, const int32_t *__restrict__ order
   for (int e = 0; e < 4; ++e)
     if (fs.x[e]) tmp[(11 + e) * n + k] = fs.x[e][o];
   if (fs.emode) ((int32_t *)(tmp + 15 * n))[k] = fs.emode[o];
+  ((int32_t *)(tmp + 15 * n))[n + k] = fs.ncand[o];
   if (perm) perm[k] = o;
 }
 
@@ -220,37 +258,46 @@ __global__ void writeback_k(int64_t n, Fields fs, const double *__restrict__ tmp
   for (int e = 0; e < 4; ++e)
     if (fs.x[e]) fs.x[e][k] = tmp[(11 + e) * n + k];
   if (fs.emode) fs.emode[k] = ((const int32_t *)(tmp + 15 * n))[k];
+  fs.ncand[k] = ((const int32_t *)(tmp + 15 * n))[n + k];
   pos4[k] = make_double4(tmp[k], tmp[n + k], tmp[2 * n + k], tmp[9 * n + k]);
 }
 
 }  // namespace
 
-hipError_t launch_max_h(mfm_ctx *ctx, const mfm_particles *pp) {
-  max_partial_k<<<RED_BLOCKS, BS, 0, ctx->stream>>>(pp->H, pp->n, ctx->red);
-  max_final_k<<<1, BS, 0, ctx->stream>>>(ctx->red, RED_BLOCKS, ctx->scalars);
-  return hipGetLastError();
+hipError_t scan_exclusive_i64(hipStream_t st, const int64_t *in, int64_t *out, int64_t n,
+                              int64_t *tmp) {
+  return scan_exclusive_t<int64_t>(st, in, out, n, tmp);
 }
 
 hipError_t launch_build_cells(mfm_ctx *ctx, const mfm_particles *pp, int64_t *perm) {
   hipStream_t st = ctx->stream;
   const int64_t n = pp->n;
-  const CellGrid &g = ctx->grid;
-  int fb = (int)(ctx->ncodes / BS + 1);
-  if (fb > 4096) fb = 4096;
-  fill_i32_k<<<fb, BS, 0, st>>>(ctx->cell_count, ctx->ncodes, 0);
-  cell_code_k<<<blocks_for(n, BS), BS, 0, st>>>(n, pp->x, pp->y, pp->z, g, ctx->code,
-                                                 ctx->cell_count);
-  hipError_t e = scan_exclusive(st, ctx->cell_count, ctx->cell_start, ctx->ncodes, ctx->scan_tmp);
-  if (e != hipSuccess) return e;
-  e = hipMemcpyAsync(ctx->cursor, ctx->cell_start, ctx->ncodes * sizeof(int32_t),
-                     hipMemcpyDeviceToDevice, st);
-  if (e != hipSuccess) return e;
-  scatter_k<<<blocks_for(n, BS), BS, 0, st>>>(n, ctx->code, ctx->cursor, ctx->order);
-  int sb = (int)((ctx->ncodes + BS / 64 - 1) / (BS / 64));  // one wavefront per cell code
-  if (sb > 16384) sb = 16384;
-  cell_sort_k<<<sb, BS, 0, st>>>(ctx->ncodes, ctx->cell_start, ctx->cell_count, ctx->order);
-  range_k<<<blocks_for(ctx->ncodes, BS), BS, 0, st>>>(ctx->ncodes, ctx->cell_start,
-                                                       ctx->cell_count, ctx->crange);
+  const Tree &g = ctx->tree;
+  // small sets take coarser keys and half the passes (their cost is the
+  // launches); both pass counts are even, so the sorted slots end in
+  // ctx->order, and the second buffers are the front of the gather buffer
+  const int bits = n <= SMALL_SORT ? SMALL_KEY_BITS : KEY_BITS;
+  const int passes = (3 * bits + RADIX_BITS - 1) / RADIX_BITS;
+  const double scale = (double)(1 << bits);
+  key_k<<<blocks_for(n, BS), BS, 0, st>>>(n, pp->x, pp->y, pp->z, scale / g.box[0],
+                                          scale / g.box[1], scale / g.box[2], bits, ctx->code,
+                                          ctx->order);
+  uint32_t *ka = ctx->code, *kb = reinterpret_cast<uint32_t *>(ctx->tmp);
+  int32_t *va = ctx->order, *vb = reinterpret_cast<int32_t *>(ctx->tmp) + n;
+  const int nb = blocks_for(n, SORT_TILE);
+  for (int p = 0; p < passes; ++p) {
+    const int shift = p * RADIX_BITS;
+    radix_hist_k<<<nb, SORT_BS, 0, st>>>(n, ka, shift, nb, ctx->hist);
+    hipError_t e = scan_exclusive(st, ctx->hist, ctx->hist, (int64_t)RADIX * nb, ctx->scan_tmp);
+    if (e != hipSuccess) return e;
+    radix_scatter_k<<<nb, SORT_BS, 0, st>>>(n, ka, va, shift, nb, ctx->hist, kb, vb);
+    uint32_t *tk = ka;
+    ka = kb;
+    kb = tk;
+    int32_t *tv = va;
+    va = vb;
+    vb = tv;
+  }
   Fields fs;
   double *src[10] = {pp->x, pp->y, pp->z, pp->vx, pp->vy, pp->vz, pp->m, pp->E, pp->U, pp->H};
   for (int f = 0; f < 10; ++f) fs.f[f] = src[f];
@@ -258,8 +305,16 @@ hipError_t launch_build_cells(mfm_ctx *ctx, const mfm_particles *pp, int64_t *pe
   fs.x[0] = pp->S;
   for (int e = 0; e < 3; ++e) fs.x[1 + e] = pp->accel ? pp->accel + (int64_t)e * n : nullptr;
   fs.emode = pp->emode;
+  fs.ncand = ctx->ncand;
   gather_k<<<blocks_for(n, BS), BS, 0, st>>>(n, fs, ctx->order, ctx->tmp, perm);
   writeback_k<<<blocks_for(n, BS), BS, 0, st>>>(n, fs, ctx->tmp,
                                                 reinterpret_cast<double4 *>(ctx->pos4));
+  // the tree over the sorted particles
+  leaf_box_k<<<g.lev_cnt[0], 64, 0, st>>>(n, reinterpret_cast<const double4 *>(ctx->pos4),
+                                           g.hfac, ctx->tnode + (int64_t)g.lev_off[0] * TNODE);
+  for (int l = 1; l < g.nlev; ++l)
+    inner_box_k<<<blocks_for(g.lev_cnt[l], 64), 64, 0, st>>>(
+        ctx->tnode + (int64_t)g.lev_off[l - 1] * TNODE, g.lev_cnt[l - 1],
+        ctx->tnode + (int64_t)g.lev_off[l] * TNODE, g.lev_cnt[l]);
   return hipGetLastError();
 }

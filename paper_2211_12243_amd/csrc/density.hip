@@ -1,22 +1,21 @@
 // density.hip -- loop (1) of the scheme: smoothing length and number density
 // (sec. 2.3.2 and 2.3.5), plus the one neighbour search of the step.
 //
-// cand_cell_k: for every particle, the candidates in the 27 cells around its
-// own (cell side >= cell_margin * max H, so every pair closer than the side
-// is found) with r < cell_margin * max(H_i, H_j), both H at the build, as
-// (index, r^2) in the k-major list (list_at).  The density loop bounds each H
-// by cell_margin times its value at the build (else the pass is redone), so
-// every pair closer than max(H_i, H_j) of the step is in the list, and the
-// list is a superset of every neighbour set the step uses, however unequal
-// the H.  (That radius is at most the cell side.)
+// cand_tree_k: for every particle, the candidates with
+// r < cell_margin * max(H_i, H_j), both H at the build, found by a walk of the
+// bucket tree (cells.hip), as (index, r^2) in the k-major list (list_at).
+// The density loop bounds each H by cell_margin times its value at the build
+// (else the pass is redone), so every pair closer than max(H_i, H_j) of the
+// step is in the list, and the list is a superset of every neighbour set the
+// step uses, however unequal the H.
 //
 // density_k solves, for each particle,
 //   g(H) = (32/3) sum_j w(r_ij / H) - N_NGB = 0
 // ((4 pi / 3) H^3 omega^-1 = N_NGB with omega^-1 = sum_j W(r_ij, H)) by Newton
-// steps kept inside a bisection bracket (0, side) over its candidate r^2.
-// The solve ends on a small Newton step, so H is the root to roundoff.
-// Reaching the side is flagged and the host rebuilds the grid with larger
-// cells.  Then the number density, the unweighted E~ of the condition-number
+// steps kept inside a bisection bracket (0, cell_margin H_build) over its
+// candidate r^2.  The solve ends on a small Newton step, so H is the root to
+// roundoff.  Reaching the bracket's end is flagged and the pass is redone
+// with larger candidate radii.  Then the number density, the unweighted E~ of the condition-number
 // check (with N_NGB boosts), the primitives and the packed 128-byte record
 // the gradient loop gathers.  It leaves two lists, both in candidate order:
 //   gl                the gather set r < H_i (the gradient loop's pairs);
@@ -31,39 +30,43 @@ constexpr double PI = 3.14159265358979323846;
 
 struct CandArgs {
   int64_t n;
-  int64_t ncodes;       // Morton codes of the grid (cell search)
   const double4 *pos;
-  int max_list;
+  const int64_t *lseg;  // list blocks of the chunks (list_at)
+  int32_t *ncand;       // out: each particle's candidate count (the next plan's input)
+  int count_only;       // record ncand only; write no list
   int32_t *cand;
   double *cand_r2;
   int32_t *cand_cnt;
   int64_t *counters;
 };
 
-// The neighbour search: one wavefront per cell.  The 27 cells
-// around it hold every candidate of every particle of the cell; the lanes load
-// those candidates once (coalesced ranges, SLOTS per lane) and keep them in
-// registers, then take the cell's particles one at a time: each lane tests
-// its candidates against the particle (a uniform load), and the matches are
-// compacted with a ballot into that particle's list, staged in LDS.  The lists
-// of up to TCH particles leave as k-major planes: each plane of a chunk is a
-// run of consecutive particles.  Candidate order is the per-lane search's
-// (cells in dz, dy, dx order, particles in index order).  Against one lane
-// per particle walking its own 27 cells (measured 3.2 ms at 128^3 against
-// 2.4 ms for this form), the candidate positions cross the cache-to-register
-// path once per cell instead of once per particle, the particle positions
-// arrive by scalar broadcast, and the lists leave HBM-friendly: 2.2 GB
-// written instead of 4.9.
-// Shape (measured at 128^3, search + density ms): SLOTS 6 / LCAP 64, 1.48 +
-// 1.58; SLOTS 6 / LCAP 48, 1.20 + 1.61; SLOTS 8 / LCAP 48, 1.17 + 1.62;
-// LCAP 32, 1.39-1.42 + 1.63; 8 particles per chunk with LCAP 64, 1.29 + 1.63.
-// The LDS a workgroup holds sets how many wavefronts a CU runs: fewer
-// staged entries per particle buy occupancy at the price of more direct
-// stores.  Since a round loads and tests only its occupied slots, the slot
-// count matters less (search 0.951 ms with 6, 0.964 with 8; 10 spills).
+// The neighbour search: one wavefront per bucket of BUCKET consecutive
+// particles, taken in chunks of TCH.  For a chunk, the wavefront walks the
+// bucket tree breadth first: a node is opened when its box comes closer to
+// the chunk's box than the larger of the two candidate radii (each
+// cell_margin times the largest H at the build inside), which every pair
+// with r < cell_margin max(H_i, H_j) satisfies; 64 children are tested at a
+// time and the accepted ones compacted with a ballot, so the accepted
+// buckets come out in index order.  Runs of consecutive buckets become
+// particle ranges.  The lanes then load those candidates (coalesced ranges,
+// SLOTS per lane) and keep them in registers, and take the chunk's particles
+// one at a time: each lane tests its candidates against the particle (a
+// uniform load), and the matches are compacted with a ballot into that
+// particle's list, staged in LDS.  The lists leave as k-major planes: each
+// plane of a chunk is a run of consecutive particles.
+// Against a uniform grid whose cells must hold the largest H of the set, the
+// walk keeps each chunk's candidates to its own radius and its neighbours',
+// whatever the spread of H (the paper's bucket search, sec. 2.2.3).
+// Shape of the pair loop (measured on the grid search at 128^3, search +
+// density ms): SLOTS 6 / LCAP 64, 1.48 + 1.58; SLOTS 6 / LCAP 48, 1.20 +
+// 1.61; SLOTS 8 / LCAP 48, 1.17 + 1.62; LCAP 32, 1.39-1.42 + 1.63.  The LDS a
+// workgroup holds sets how many wavefronts a CU runs: fewer staged entries
+// per particle buy occupancy at the price of more direct stores.
 constexpr int SLOTS = 6;   // candidates per lane per round: 384 per wavefront
-constexpr int TCH = 16;    // particles per staged chunk
+constexpr int TCH = LCH;   // particles per chunk: one list chunk
+static_assert(BUCKET % TCH == 0, "a bucket holds whole chunks");
 constexpr int LCAP = 48;   // list entries per particle staged in LDS (more are stored directly)
+constexpr int MAXF = 256;  // accepted nodes of one tree level per chunk
 
 // Lane l's value in every lane (a scalar broadcast, no memory traffic).
 __device__ __forceinline__ double readlane_f64(double v, int l) {
@@ -74,82 +77,178 @@ __device__ __forceinline__ double readlane_f64(double v, int l) {
   return *reinterpret_cast<const double *>(&r);
 }
 
-__global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) cand_cell_k(CandArgs a, CellGrid g) {
+__device__ __forceinline__ int lanes_below(uint64_t m) {
+  return (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32),
+                                        __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+}
+
+__global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) cand_tree_k(CandArgs a, Tree g) {
   __shared__ int32_t s_idx[TCH][LCAP];
   __shared__ double s_r2[TCH][LCAP];
-  __shared__ int s_start[27];
-  __shared__ int s_pre[28];
+  __shared__ int s_f[2][MAXF];   // accepted nodes of the current and next level
+  __shared__ int s_cand[64 * SLOTS];  // filtered candidates of a round
   __shared__ int s_cnt[TCH];
   const int lane = threadIdx.x;
   const int64_t n = a.n;
   int64_t overflow = 0;
-  const uint32_t code = blockIdx.x;
-  const int cx = (int)compact_bits3(code), cy = (int)compact_bits3(code >> 1),
-            cz = (int)compact_bits3(code >> 2);
-  if (cx >= g.nc[0] || cy >= g.nc[1] || cz >= g.nc[2]) return;
-  const int2 own = g.range[code];
-  if (own.y == 0) return;
-  const int cap = a.max_list;
-  // the 27 neighbour ranges in the search order, and their prefix sums
-  int cnt27 = 0, st27 = 0;
-  if (lane < 27) {
-    int zz = cz + lane / 9 - 1, yy = cy + (lane / 3) % 3 - 1, xx = cx + lane % 3 - 1;
-    zz = zz < 0 ? zz + g.nc[2] : (zz >= g.nc[2] ? zz - g.nc[2] : zz);
-    yy = yy < 0 ? yy + g.nc[1] : (yy >= g.nc[1] ? yy - g.nc[1] : yy);
-    xx = xx < 0 ? xx + g.nc[0] : (xx >= g.nc[0] ? xx - g.nc[0] : xx);
-    const uint32_t nb = morton3(xx, yy, zz);
-    const int2 rg = g.range[nb];
-    st27 = rg.x;
-    cnt27 = rg.y;
-  }
-  int inc = cnt27;
-  for (int o = 1; o < 32; o <<= 1) {
-    const int u = __shfl_up(inc, o, 64);
-    if (lane >= o) inc += u;
-  }
-  if (lane < 27) {
-    s_start[lane] = st27;
-    s_pre[lane + 1] = inc;
-  }
-  if (lane == 0) s_pre[0] = 0;
-  __syncthreads();
-  const int C = s_pre[27];
-  const bool wraps = cx == 0 || cy == 0 || cz == 0 || cx == g.nc[0] - 1 ||
-                     cy == g.nc[1] - 1 || cz == g.nc[2] - 1;
-  for (int t0 = 0; t0 < own.y; t0 += TCH) {
-    const int T = min(TCH, own.y - t0);
+  const int bucket = xcd_block(blockIdx.x, gridDim.x);
+  const int own_x = bucket * BUCKET;
+  const int own_y = (int)min((int64_t)BUCKET, n - own_x);
+  // a planned pool that does not fit leaves every chunk without room (and
+  // the pass fails as a list overflow)
+  const bool no_room = a.count_only || a.counters[C_LIST_POOL] != 0;
+  for (int t0 = 0; t0 < own_y; t0 += TCH) {
+    const int T = min(TCH, own_y - t0);
+    const int64_t chunk = (own_x + t0) / LCH;
+    const int64_t seg0 = no_room ? 0 : a.lseg[chunk];
+    const int cap = no_room ? 0 : (int)((a.lseg[chunk + 1] - seg0) / LCH);
     // lane t holds particle t of the chunk and the length of its list; the
     // loop below broadcasts both
     int tcnt = 0;
-    double tx = 0.0, ty = 0.0, tz = 0.0, tq = 0.0;
+    double tx = 0.0, ty = 0.0, tz = 0.0, tq = 0.0, th = 0.0;
+    const double4 p0 = a.pos[own_x + t0];
+    double blo[3] = {p0.x, p0.y, p0.z}, bhi[3] = {p0.x, p0.y, p0.z};
     if (lane < T) {
-      const double4 pt = a.pos[own.x + t0 + lane];
+      const double4 pt = a.pos[own_x + t0 + lane];
       tx = pt.x; ty = pt.y; tz = pt.z;
-      tq = (g.hfac * pt.w) * (g.hfac * pt.w);  // squared radius of the particle's own H
+      th = g.hfac * pt.w;
+      tq = th * th;  // squared radius of the particle's own H
+      blo[0] = bhi[0] = tx;
+      blo[1] = bhi[1] = ty;
+      blo[2] = bhi[2] = tz;
     }
+    // the chunk's box and radius
+    double bc[3], bh[3];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      const double lo = wave_min_f64(blo[k]), hi = wave_max_f64(bhi[k]);
+      bc[k] = 0.5 * (lo + hi);
+      bh[k] = 0.5 * (hi - lo);
+    }
+    const double Rc = wave_max_f64(th);
+    // a node is opened when its box and the chunk's are closer than the
+    // larger radius (raised by 1e-12 so that rounding in the box distance
+    // cannot drop a pair at the edge)
+    auto opens = [&](const double *nd) {
+      double gap2 = 0.0;
+#pragma unroll
+      for (int k = 0; k < 3; ++k) {
+        double d = fabs(0.5 * (nd[k] + nd[3 + k]) - bc[k]);
+        d = fmin(d, g.box[k] - d);  // periodic images of the centres
+        const double gk = fmax(0.0, d - 0.5 * (nd[3 + k] - nd[k]) - bh[k]);
+        gap2 += gk * gk;
+      }
+      const double R = fmax(Rc, nd[6]) * (1.0 + 1e-12);
+      return gap2 < R * R;
+    };
+    // breadth-first walk from the top node.  When a level would accept more
+    // nodes than the LDS holds (a chunk of wide particles), the walk stops
+    // above it and the buckets under the accepted nodes are tested one by
+    // one below.
+    int cur = 0, nf = 1, lev_stop = 0;
+    if (lane == 0) s_f[0][0] = 0;
     __syncthreads();
-    for (int cb = 0; cb < C; cb += 64 * SLOTS) {
+    for (int lev = g.nlev - 1; lev > 0; --lev) {
+      const int cl = lev - 1, cnt_c = g.lev_cnt[cl];
+      const double *nodes = g.node + (int64_t)g.lev_off[cl] * TNODE;
+      int nn = 0;
+      const int total = nf * TREE_FANOUT;
+      for (int u0 = 0; u0 < total; u0 += 64) {
+        const int u = u0 + lane;
+        bool open = false;
+        int child = 0;
+        if (u < total) {
+          child = s_f[cur][u / TREE_FANOUT] * TREE_FANOUT + u % TREE_FANOUT;
+          if (child < cnt_c) open = opens(nodes + (int64_t)child * TNODE);
+        }
+        const uint64_t m = __ballot(open);
+        const int k = nn + lanes_below(m);
+        if (open && k < MAXF) s_f[cur ^ 1][k] = child;
+        nn += __popcll(m);
+      }
+      __syncthreads();
+      if (nn > MAXF) {  // wave-uniform
+        lev_stop = lev;
+        break;
+      }
+      cur ^= 1;
+      nf = nn;
+    }
+    // the accepted buckets in index order: the frontier's nodes, each
+    // expanded to the buckets under it when the walk stopped early
+    const int span = 3 * lev_stop;  // TREE_FANOUT = 2^3 nodes per level
+    const int64_t nb0 = g.lev_cnt[0];
+    int q = 0;
+    int64_t bk = 0, bend = 0;
+    auto next_bucket = [&]() -> int64_t {
+      for (;;) {
+        if (bk >= bend) {
+          if (q >= nf) return -1;
+          const int64_t v = s_f[cur][q++];
+          if (span == 0) return v;  // accepted by the walk
+          bk = v << span;
+          bend = min((v + 1) << span, nb0);
+          continue;
+        }
+        const int64_t b = bk++;
+        if (opens(g.node + ((int64_t)g.lev_off[0] + b) * TNODE)) return b;
+      }
+    };
+    // the accepted buckets' particles, filtered by their distance from the
+    // chunk's box (every pair partner is within the larger radius of that
+    // box), compacted into s_cand a round at a time
+    for (bool more = true; more;) {
+      int nsel = 0;
+      bool far = false;
+      while (nsel <= 64 * (SLOTS - 1)) {
+        const int64_t bkt = next_bucket();
+        if (bkt < 0) {
+          more = false;
+          break;
+        }
+        const int64_t j = bkt * BUCKET + lane;
+        bool keep = false;
+        if (j < n) {
+          const double4 pj = a.pos[j];
+          const double pk[3] = {pj.x, pj.y, pj.z};
+          double gap2 = 0.0;
+          bool wrap = false;
+#pragma unroll
+          for (int k = 0; k < 3; ++k) {
+            double d = fabs(pk[k] - bc[k]);
+            // a candidate whose separation from some particle of the chunk
+            // may need the periodic image
+            wrap = wrap || d + bh[k] > g.half[k];
+            d = fmin(d, g.box[k] - d);
+            const double gk = fmax(0.0, d - bh[k]);
+            gap2 += gk * gk;
+          }
+          const double R = fmax(Rc, g.hfac * pj.w) * (1.0 + 1e-12);
+          keep = gap2 < R * R;
+          far = far || (keep && wrap);
+        }
+        const uint64_t m = __ballot(keep);
+        if (keep) s_cand[nsel + lanes_below(m)] = (int)j;
+        nsel += __popcll(m);
+      }
+      if (nsel == 0) break;  // wave-uniform: nothing left
+      __syncthreads();
       // slots holding at least one candidate (the rest are neither loaded
-      // nor tested: the last round of a stencil is often nearly empty)
-      const int nsl = min(SLOTS, (C - cb + 63) / 64);
+      // nor tested)
+      const int nsl = (nsel + 63) / 64;
       double px[SLOTS], py[SLOTS], pz[SLOTS], pq[SLOTS];
       int jj[SLOTS];
 #pragma unroll
       for (int s = 0; s < SLOTS; ++s) {
         if (s >= nsl) break;
-        const int c = cb + s * 64 + lane;
+        const int c = s * 64 + lane;
         // an empty lane: never the particle itself, and its distance
         // overflows to +inf, which fails every test
         jj[s] = -1;
         px[s] = py[s] = pz[s] = 1e300;
         pq[s] = 0.0;
-        if (c < C) {
-          int lo = 0, hi = 27;  // range r with s_pre[r] <= c < s_pre[r + 1]
-          while (hi - lo > 1) {
-            const int mid = (lo + hi) >> 1;
-            if (s_pre[mid] <= c) lo = mid; else hi = mid;
-          }
-          const int j = s_start[lo] + (c - s_pre[lo]);
+        if (c < nsel) {
+          const int j = s_cand[c];
           const double4 pj = a.pos[j];
           jj[s] = j;
           px[s] = pj.x;
@@ -159,13 +258,13 @@ __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) ca
         }
       }
       // the particles of the chunk against the candidates in registers; a
-      // cell whose stencil crosses the periodic boundary takes the minimum
-      // image, any other the plain difference (the same value: no pair
-      // closer than the cell side is wrapped there)
+      // round with a candidate that may sit across the periodic boundary
+      // takes the minimum image, any other the plain difference (the same
+      // value there)
       auto test_chunk = [&](auto wrap) {
       constexpr bool WRAP = decltype(wrap)::value;
       for (int t = 0; t < T; ++t) {
-        const int ti = own.x + t0 + t;
+        const int ti = own_x + t0 + t;
         const double ptx = readlane_f64(tx, t), pty = readlane_f64(ty, t),
                      ptz = readlane_f64(tz, t), ptq = readlane_f64(tq, t);
         int base = __builtin_amdgcn_readlane(tcnt, t);
@@ -190,8 +289,7 @@ __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) ca
           const bool hit = (na | nt) & other;
           const uint64_t m = (__builtin_amdgcn_ballot_w64(na) | __builtin_amdgcn_ballot_w64(nt)) &
                              __builtin_amdgcn_ballot_w64(other);
-          const int k = base + (int)__builtin_amdgcn_mbcnt_hi(
-                                   (uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+          const int k = base + lanes_below(m);
           const int nb = base + __popcll(m);
           if (nb <= LCAP) {  // wave-uniform: every hit of the slot is staged
             if (hit) {
@@ -203,7 +301,7 @@ __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) ca
               s_idx[t][k] = jj[s];
               s_r2[t][k] = r2;
             } else if (k < cap) {
-              const int64_t at = list_at(ti, k, n);
+              const int64_t at = list_at(seg0 + t, k);
               a.cand[at] = jj[s];
               a.cand_r2[at] = r2;
             }
@@ -213,7 +311,7 @@ __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) ca
         tcnt = lane == t ? base : tcnt;
       }
       };
-      if (wraps)
+      if (__ballot(far))
         test_chunk(std::true_type{});
       else
         test_chunk(std::false_type{});
@@ -229,14 +327,15 @@ __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) ca
     for (int kk = 0; kk < kmax; kk += 64 / TCH) {
       const int k = kk + lane / TCH;
       if (k < lim) {
-        const int64_t at = list_at(own.x + t0 + tl, k, n);
+        const int64_t at = list_at(seg0 + tl, k);
         a.cand[at] = s_idx[tl][k];
         a.cand_r2[at] = s_r2[tl][k];
       }
     }
-    if (lane < T) {
+    if (lane < T) a.ncand[own_x + t0 + lane] = s_cnt[lane];
+    if (lane < T && !a.count_only) {
       const int c = s_cnt[lane];
-      a.cand_cnt[own.x + t0 + lane] = min(c, cap);
+      a.cand_cnt[own_x + t0 + lane] = min(c, cap);
       overflow += c > cap ? 1 : 0;
     }
     __syncthreads();
@@ -257,6 +356,7 @@ struct DensityArgs {
   const double *cand_r2;
   float *rest_r2;
   int32_t *gl, *gl_cnt;
+  const int64_t *lseg;    // list blocks of the chunks (list_at)
   double gamma, n_ngb, ncond_max, ngb_boost, h_tol;
   int h_maxit, max_boosts;
   int64_t *counters;
@@ -276,6 +376,7 @@ constexpr int DT = 8;
 constexpr int DG = 64 / DT;
 constexpr int DM = 8;
 constexpr int DCAP = DG * DM;
+static_assert(LCH % DT == 0, "a wavefront's particles share one list chunk");
 
 // A double moved across lanes by a DPP control (both halves).
 template <int CTRL>
@@ -416,7 +517,7 @@ __device__ __forceinline__ void add_pair(double &s, double &ds, double r, double
 }
 
 __device__ __forceinline__ void add_e(double &ws, double e[6], double r, double ih,
-                                      double4 pj, double4 pi, const CellGrid &g) {
+                                      double4 pj, double4 pi, const Tree &g) {
   const double w = spline_w(r * ih);
   ws += w;
   if (r > 0.0) {
@@ -433,7 +534,7 @@ __device__ __forceinline__ void add_e(double &ws, double e[6], double r, double 
 }
 
 // Upper end of a particle's bracket (pi.w: its H at the build).
-__device__ __forceinline__ double hcap_of(const CellGrid &g, double4 pi) {
+__device__ __forceinline__ double hcap_of(const Tree &g, double4 pi) {
   return pi.w > 0.0 ? fmin(g.side_min, g.hfac * pi.w) : g.side_min;
 }
 
@@ -468,8 +569,7 @@ __device__ __forceinline__ void finish_particle(const DensityArgs &a, int64_t i,
   gr[1] = make_double4(V, rho, vx, vy);
   gr[2] = make_double4(vz, P, cs, 0.0);
   float4 *gf = reinterpret_cast<float4 *>(a.gin + i * GIN_STRIDE + GIN_F32);
-  gf[0] = make_float4((float)V, (float)rho, (float)vx, (float)vy);
-  gf[1] = make_float4((float)vz, (float)P, (float)cs, 0.0f);
+  gf[0] = make_float4((float)V, (float)rho, (float)P, (float)cs);
 }
 
 // One wavefront per DT consecutive particles.  A particle's candidate list is
@@ -479,7 +579,7 @@ __device__ __forceinline__ void finish_particle(const DensityArgs &a, int64_t i,
 // (index and FP32 r^2) back into cand / rest_r2.  Both are staged in LDS and
 // leave as k-major planes of DT consecutive particles.  A list longer than
 // DCAP is left whole, marked gl_cnt = -1, for density_long_k.
-__global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) density_k(DensityArgs a, CellGrid g) {
+__global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) density_k(DensityArgs a, Tree g) {
   __shared__ int32_t s_i[DCAP][DT];  // gather set from the front, rest indices from the back
   __shared__ float s_f[DCAP][DT];    // rest r^2
   __shared__ int s_gn[DT], s_rn[DT];
@@ -488,10 +588,14 @@ __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) de
   const uint64_t below = (1ull << lane) - 1ull;
   const uint64_t gmask = ((1ull << DG) - 1ull) << (gt * DG);
   const int64_t n = a.n;
+  // a search whose lists overflowed leaves the pass to be redone: nothing
+  // here may change the state
+  if (a.counters[C_PASS_LIST] != 0) return;
   const int64_t i0 = xcd_block(blockIdx.x, gridDim.x) * (int64_t)DT;
   const int64_t i = i0 + gt;
   const bool valid = i < n;
   const int cnt = valid ? a.cand_cnt[i] : 0;
+  const int64_t lb = valid ? list_base(a.lseg, i) : 0;
   int64_t noconv = 0, boosts = 0, fails = 0, overflow = 0;
   if (valid && cnt <= DCAP) {
     // the distances r (not r^2): the square root is taken once here, not at
@@ -504,8 +608,8 @@ __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) de
       rs[m] = __builtin_huge_val();  // beyond the list: never inside any H
       jr[m] = 0;
       if (k < cnt) {
-        rs[m] = sqrt(a.cand_r2[list_at(i, k, n)]);
-        jr[m] = a.cand[list_at(i, k, n)];
+        rs[m] = sqrt(a.cand_r2[list_at(lb, k)]);
+        jr[m] = a.cand[list_at(lb, k)];
       }
     }
     const double4 pi = a.pos[i];
@@ -567,12 +671,13 @@ __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) de
   const int glim = own ? s_gn[tl] : 0;
   const int rlim = own ? s_rn[tl] : 0;
   const int kmax = wave_max_i32(max(glim, rlim));
+  const int64_t pb = pl < n ? list_base(a.lseg, pl) : 0;
   for (int kk = 0; kk < kmax; kk += 64 / DT) {
     const int k = kk + lane / DT;
-    if (k < glim) a.gl[list_at(pl, k, n)] = s_i[k][tl];
+    if (k < glim) a.gl[list_at(pb, k)] = s_i[k][tl];
     if (k < rlim) {
-      a.cand[list_at(pl, k, n)] = s_i[DCAP - 1 - k][tl];
-      a.rest_r2[list_at(pl, k, n)] = s_f[k][tl];
+      a.cand[list_at(pb, k)] = s_i[DCAP - 1 - k][tl];
+      a.rest_r2[list_at(pb, k)] = s_f[k][tl];
     }
   }
   if (lane < DT && pl < n) {
@@ -588,13 +693,15 @@ __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) de
 // The lists density_k could not hold (gl_cnt = -1): one lane per particle,
 // the list streamed from HBM on every pass, then split in place (an entry
 // moves only to a slot at or before its own).
-__global__ void __launch_bounds__(BS) density_long_k(DensityArgs a, CellGrid g) {
+__global__ void __launch_bounds__(BS) density_long_k(DensityArgs a, Tree g) {
   const int64_t i = xcd_block(blockIdx.x, gridDim.x) * (int64_t)blockDim.x + threadIdx.x;
   const int64_t n = a.n;
+  if (a.counters[C_PASS_LIST] != 0) return;  // as in density_k
   int64_t noconv = 0, boosts = 0, fails = 0, overflow = 0;
   if (i < n && a.gl_cnt[i] < 0) {
     const int cnt = a.cand_cnt[i];
-    auto at = [&](int k) { return list_at(i, k, n); };
+    const int64_t lb = list_base(a.lseg, i);
+    auto at = [&](int k) { return list_at(lb, k); };
     const double4 pi = a.pos[i];
     auto sums = [&](double h, double ih, double &s, double &ds) {
       s = 0.0;
@@ -638,12 +745,11 @@ __global__ void __launch_bounds__(BS) density_long_k(DensityArgs a, CellGrid g) 
   count_add(a.counters + C_CELL_OVERFLOW, overflow);
 }
 
-__global__ void validate_k(int64_t *c, const double *hmax_build, double hmax_grid) {
+__global__ void validate_k(int64_t *c) {
   if (threadIdx.x != 0) return;
-  const bool bad_grid = !(hmax_build[0] <= hmax_grid);
-  if (c[C_PASS_LIST] > 0 || c[C_CELL_OVERFLOW] > 0 || bad_grid) {
+  if (c[C_PASS_LIST] > 0 || c[C_CELL_OVERFLOW] > 0) {
     c[C_STEP_SKIP] = 1;
-    if (c[C_CELL_OVERFLOW] > 0 || bad_grid) c[C_CELL_REBUILDS] += 1;
+    if (c[C_CELL_OVERFLOW] > 0) c[C_CELL_REBUILDS] += 1;
     c[C_LIST_OVERFLOW] += c[C_PASS_LIST];
     return;
   }
@@ -653,24 +759,56 @@ __global__ void validate_k(int64_t *c, const double *hmax_build, double hmax_gri
   c[C_NCOND_FAIL] += c[C_PASS_FAIL];
 }
 
+// The planned capacity of each chunk: the longest candidate list its
+// particles had in the last search (the counts move with the particles
+// through the sort), an eighth more and 4 (positions and H drift between
+// searches), times LCH.  The entry past the last chunk is 0, so that the
+// scan ends with the total.
+__global__ void plan_k(int64_t n, int64_t nch, const int32_t *__restrict__ ncand, int64_t *cap) {
+  const int64_t c = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (c > nch) return;
+  int64_t k = 0;
+  if (c < nch) {
+    int l = 0;
+    for (int64_t i = c * LCH; i < min(n, (c + 1) * LCH); ++i) l = max(l, ncand[i]);
+    k = (int64_t)l + l / 8 + 4;
+  }
+  cap[c] = k * LCH;
+}
+
+__global__ void pool_check_k(const int64_t *__restrict__ lseg, int64_t nch, int64_t pool,
+                             int64_t *counters) {
+  if (threadIdx.x == 0) counters[C_LIST_POOL] = lseg[nch] > pool ? 1 : 0;
+}
+
 }  // namespace
 
-hipError_t launch_validate(mfm_ctx *ctx, double hmax_grid) {
-  validate_k<<<1, 64, 0, ctx->stream>>>(ctx->counters, ctx->scalars, hmax_grid);
+hipError_t launch_plan_lists(mfm_ctx *ctx, int64_t n) {
+  const int64_t nch = list_chunks(n);
+  plan_k<<<blocks_for(nch + 1, BS), BS, 0, ctx->stream>>>(n, nch, ctx->ncand, ctx->lcap);
+  hipError_t e = scan_exclusive_i64(ctx->stream, ctx->lcap, ctx->lseg, nch + 1, ctx->scan64);
+  if (e != hipSuccess) return e;
+  pool_check_k<<<1, 64, 0, ctx->stream>>>(ctx->lseg, nch, (int64_t)ctx->pool, ctx->counters);
   return hipGetLastError();
 }
 
-hipError_t launch_candidates(mfm_ctx *ctx, const mfm_particles *pp) {
+hipError_t launch_validate(mfm_ctx *ctx) {
+  validate_k<<<1, 64, 0, ctx->stream>>>(ctx->counters);
+  return hipGetLastError();
+}
+
+hipError_t launch_candidates(mfm_ctx *ctx, const mfm_particles *pp, bool count_only) {
   CandArgs a;
   a.n = pp->n;
   a.pos = reinterpret_cast<const double4 *>(ctx->pos4);
-  a.max_list = ctx->p.max_list;
+  a.lseg = ctx->lseg;
+  a.ncand = ctx->ncand;
+  a.count_only = count_only ? 1 : 0;
   a.cand = ctx->cand;
   a.cand_r2 = ctx->cand_r2;
   a.cand_cnt = ctx->cand_cnt;
   a.counters = ctx->counters;
-  a.ncodes = ctx->ncodes;
-  cand_cell_k<<<(unsigned)ctx->ncodes, 64, 0, ctx->stream>>>(a, ctx->grid);
+  cand_tree_k<<<(unsigned)ctx->tree.lev_cnt[0], 64, 0, ctx->stream>>>(a, ctx->tree);
   return hipGetLastError();
 }
 
@@ -689,6 +827,7 @@ hipError_t launch_density(mfm_ctx *ctx, const mfm_particles *pp) {
   a.rest_r2 = ctx->rest_r2;
   a.gl = ctx->gl;
   a.gl_cnt = ctx->gl_cnt;
+  a.lseg = ctx->lseg;
   a.gamma = ctx->p.gamma;
   a.n_ngb = ctx->p.n_ngb;
   a.ncond_max = ctx->p.ncond_max;
@@ -697,7 +836,7 @@ hipError_t launch_density(mfm_ctx *ctx, const mfm_particles *pp) {
   a.h_maxit = ctx->p.h_maxit;
   a.max_boosts = ctx->p.max_boosts;
   a.counters = ctx->counters;
-  density_k<<<(unsigned)((pp->n + DT - 1) / DT), 64, 0, ctx->stream>>>(a, ctx->grid);
-  density_long_k<<<blocks_for(pp->n, BS), BS, 0, ctx->stream>>>(a, ctx->grid);
+  density_k<<<(unsigned)((pp->n + DT - 1) / DT), 64, 0, ctx->stream>>>(a, ctx->tree);
+  density_long_k<<<blocks_for(pp->n, BS), BS, 0, ctx->stream>>>(a, ctx->tree);
   return hipGetLastError();
 }

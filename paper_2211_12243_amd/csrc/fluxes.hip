@@ -62,6 +62,7 @@ struct FluxArgs {
   const double *rec;
   const double4 *pos;
   const int32_t *fslot, *fcnt;
+  const int64_t *lseg;  // list blocks of the chunks (list_at)
   const double *dt;
   double *dQ;
   double *dq_ext;  // dt F A of faces whose other particle lies outside the block
@@ -712,7 +713,7 @@ __global__ void __launch_bounds__(FTH) __attribute__((amdgpu_waves_per_eu(2))) f
       if (pref[mid] <= f) lo = mid; else hi = mid;
     }
     pf = lo;
-    jf = a.fslot[list_at(b0 + lo, f - pref[lo], n)];
+    jf = a.fslot[list_at(list_base(a.lseg, b0 + lo), f - pref[lo])];
   };
   int p_next = FBS, j_next = 0;
   if (tid < T_faces) locate(tid, p_next, j_next);
@@ -1043,6 +1044,7 @@ hipError_t launch_fluxes(mfm_ctx *ctx, const mfm_particles *pp, const double *dt
   a.rec = ctx->rec;
   a.pos = reinterpret_cast<const double4 *>(ctx->pos4);
   a.fslot = ctx->fslot;
+  a.lseg = ctx->lseg;
   a.fcnt = ctx->fcnt;
   a.dt = dt_dev;
   a.dQ = pp->dQ;

@@ -40,6 +40,7 @@ struct GradArgs {
   const int32_t *cand, *cand_cnt;  // candidates with r >= H_i
   const float *rest_r2;             // their r^2, rounded to FP32
   const int32_t *gl, *gl_cnt;
+  const int64_t *lseg;  // list blocks of the chunks (list_at)
   double *B, *grad, *ncond, *dt_i, *rec;
   int32_t *fslot, *fcnt;
   double box[3], half[3];
@@ -48,6 +49,7 @@ struct GradArgs {
   int64_t *counters;
   const double *m;  // masses, for E_kin^max
   double *ekm;      // E_kin^max = max_j m_i |v_j - v_i|^2 / 2 (null: not wanted)
+  int32_t *grad_q;  // mixed path: particles whose E is redone in FP64 (grad_fix_k)
 };
 
 template <typename T>
@@ -90,21 +92,24 @@ __device__ __forceinline__ void sym_apply(const T b[6], const T s[3], T g[3]) {
 }
 
 // What the first loop gathers of one neighbour's record: the FP64 position
-// and, on the mixed path, the FP32 tail (V, rho, vx, vy, vz, P, c); on the
-// FP64 path the FP64 values.
+// and velocity and, on the mixed path, the FP32 tail (V, rho, P, c); on the
+// FP64 path the FP64 values.  The velocity stays FP64 on the mixed path for
+// the same reason as the position: a bulk flow much faster than the
+// velocity differences across the kernel would leave those differences to
+// the rounding of FP32 copies.
 template <typename T> struct NbRec;
 template <> struct NbRec<float> {
-  double x, y, z;
-  float4 f0, f1;
+  double x, y, z, vx, vy, vz;
+  float4 f0;
   __device__ __forceinline__ void load(const double *gj) {
     x = gj[GIN_X]; y = gj[GIN_Y]; z = gj[GIN_Z];
-    const float4 *gf = reinterpret_cast<const float4 *>(gj + GIN_F32);
-    f0 = gf[0]; f1 = gf[1];
+    vx = gj[GIN_VX]; vy = gj[GIN_VY]; vz = gj[GIN_VZ];
+    f0 = *reinterpret_cast<const float4 *>(gj + GIN_F32);
   }
   __device__ __forceinline__ void values(double q[5], float &v, float &c) const {
     v = f0.x;
-    q[0] = f0.y; q[1] = f0.z; q[2] = f0.w; q[3] = f1.x; q[4] = f1.y;
-    c = f1.z;
+    q[0] = f0.y; q[1] = vx; q[2] = vy; q[3] = vz; q[4] = f0.z;
+    c = f0.w;
   }
 };
 template <> struct NbRec<double> {
@@ -134,6 +139,7 @@ __global__ void __launch_bounds__(BS) gradients_k(GradArgs a) {
   // wavefront reduction); a lane past the end works on particle 0 and
   // writes nothing
   const bool live = i < n;
+  const int64_t lb = list_base(a.lseg, live ? i : 0);
   {
     const double *gi = a.gin + (live ? i : 0) * GIN_STRIDE;
     const double xi = gi[GIN_X], yi = gi[GIN_Y], zi = gi[GIN_Z], hi = gi[GIN_H];
@@ -164,11 +170,11 @@ __global__ void __launch_bounds__(BS) gradients_k(GradArgs a) {
       if (nf >= flushed)
         s_ring[wv][nf % RING][ln] = j;
       else
-        a.fslot[list_at(i, nf, n)] = j;
+        a.fslot[list_at(lb, nf)] = j;
       ++nf;
     };
     auto store_plane = [&](int p) {
-      if (live && nf > p) a.fslot[list_at(i, p, n)] = s_ring[wv][p % RING][ln];
+      if (live && nf > p) a.fslot[list_at(lb, p)] = s_ring[wv][p % RING][ln];
     };
     // before RSTEP list entries (at most one face each per lane): keep every
     // slot they may take inside the ring
@@ -191,8 +197,8 @@ __global__ void __launch_bounds__(BS) gradients_k(GradArgs a) {
     // for the neighbour's record, so that a gather is in flight while the
     // previous entry is summed; the others load their next entry one
     // iteration ahead
-    int jn = gc > 0 ? a.gl[list_at(i, 0, n)] : 0;
-    int jn2 = gc > 1 ? a.gl[list_at(i, 1, n)] : 0;
+    int jn = gc > 0 ? a.gl[list_at(lb, 0)] : 0;
+    int jn2 = gc > 1 ? a.gl[list_at(lb, 1)] : 0;
     NbRec<T> nb;
     if (gc > 0) nb.load(a.gin + (int64_t)jn * GIN_STRIDE);
     for (int k = 0; k < gmax; ++k) {
@@ -203,7 +209,7 @@ __global__ void __launch_bounds__(BS) gradients_k(GradArgs a) {
         if (k + 1 < gc) {
           jn = jn2;
           nb.load(a.gin + (int64_t)jn * GIN_STRIDE);
-          if (k + 2 < gc) jn2 = a.gl[list_at(i, k + 2, n)];
+          if (k + 2 < gc) jn2 = a.gl[list_at(lb, k + 2)];
         }
         if (emit_face((int)i, j)) put_face(j);
         ++pairs;
@@ -254,16 +260,16 @@ __global__ void __launch_bounds__(BS) gradients_k(GradArgs a) {
     // 2^-22 around H_j^2 from the exact FP64 r^2 of the positions.
     const int cnt = live ? a.cand_cnt[i] : 0;
     const int cmax = wave_max_i32(cnt);
-    int cj = cnt > 0 ? a.cand[list_at(i, 0, n)] : 0;
-    float cr = cnt > 0 ? a.rest_r2[list_at(i, 0, n)] : 0.0f;
+    int cj = cnt > 0 ? a.cand[list_at(lb, 0)] : 0;
+    float cr = cnt > 0 ? a.rest_r2[list_at(lb, 0)] : 0.0f;
     for (int k = 0; k < cmax; ++k) {
       if (k % RSTEP == 0) make_room();
       if (k < cnt) {
         const int j = cj;
         const double r2f = (double)cr;
         if (k + 1 < cnt) {
-          cj = a.cand[list_at(i, k + 1, n)];
-          cr = a.rest_r2[list_at(i, k + 1, n)];
+          cj = a.cand[list_at(lb, k + 1)];
+          cr = a.rest_r2[list_at(lb, k + 1)];
         }
         const double hj = a.H[j];
         const double hj2 = hj * hj;
@@ -309,16 +315,33 @@ __global__ void __launch_bounds__(BS) gradients_k(GradArgs a) {
       for (int k = 0; k < 6; ++k) b64[k] = (double)b[k];
     }
     if (live && (!(det != T(0)) || !isfinite(det))) ++singular;
+    if (sizeof(T) == sizeof(float)) {
+      // an ill-conditioned E: FP32 sums leave B, the gradients and the
+      // limiter to rounding amplified by the condition number; grad_fix_k
+      // redoes the particle in FP64 after this launch
+      const bool redo = live && !(nc <= T(MIXED_FP64_NCOND));
+      const uint64_t m = __ballot(redo);
+      int base = 0;
+      if (m && (threadIdx.x & 63) == 0)
+        base = (int)atomicAdd((unsigned long long *)(a.counters + C_GRAD_QUEUE),
+                              (unsigned long long)__popcll(m));
+      base = __shfl(base, 0, 64);
+      if (redo) {
+        const int rank = (int)__builtin_amdgcn_mbcnt_hi(
+            (uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+        a.grad_q[base + rank] = (int32_t)i;
+      }
+    }
     T alpha[5] = {T(1), T(1), T(1), T(1), T(1)};
     if (a.limiter & MFM_LIMIT_BJ) {
       T dmax[5] = {0, 0, 0, 0, 0}, dmin[5] = {0, 0, 0, 0, 0};
-      int bn = gc > 1 ? a.gl[list_at(i, 1, n)] : 0;
-      double4 pn = gc > 0 ? a.pos[a.gl[list_at(i, 0, n)]] : make_double4(0, 0, 0, 0);
+      int bn = gc > 1 ? a.gl[list_at(lb, 1)] : 0;
+      double4 pn = gc > 0 ? a.pos[a.gl[list_at(lb, 0)]] : make_double4(0, 0, 0, 0);
       for (int k = 0; k < gc; ++k) {
         const double4 pj = pn;
         if (k + 1 < gc) {
           pn = a.pos[bn];
-          if (k + 2 < gc) bn = a.gl[list_at(i, k + 2, n)];
+          if (k + 2 < gc) bn = a.gl[list_at(lb, k + 2)];
         }
         const T d0 = T(min_image(pj.x - xi, a.box[0], a.half[0]));
         const T d1 = T(min_image(pj.y - yi, a.box[1], a.half[1]));
@@ -400,6 +423,119 @@ __global__ void __launch_bounds__(BS) gradients_k(GradArgs a) {
   count_add(a.counters + C_FP64_INVERSE, inv64);
 }
 
+// The mixed path's FP64 redo of the particles gradients_k queued: E, the
+// gradient sums, B = E^-1, the limiter and the flux record's B and
+// gradients, all in FP64 from the FP64 neighbour records (one wavefront per
+// particle, lanes over its gather set).  The face lists, the signal velocity
+// and the rest of the record stay as gradients_k wrote them.
+__global__ void __launch_bounds__(64) grad_fix_k(GradArgs a) {
+  if (a.counters[C_STEP_SKIP]) return;
+  const int64_t count = a.counters[C_GRAD_QUEUE];
+  const int lane = threadIdx.x;
+  const int64_t n = a.n;
+  for (int64_t qn = blockIdx.x; qn < count; qn += gridDim.x) {
+    const int64_t i = a.grad_q[qn];
+    const double *gi = a.gin + i * GIN_STRIDE;
+    const double xi = gi[GIN_X], yi = gi[GIN_Y], zi = gi[GIN_Z], hi = gi[GIN_H];
+    const double ih = 1.0 / hi, wnorm = 8.0 / (PI * hi * hi * hi);
+    const double q64[5] = {gi[GIN_RHO], gi[GIN_VX], gi[GIN_VY], gi[GIN_VZ], gi[GIN_P]};
+    const int gc = a.gl_cnt[i];
+    const int64_t lb = list_base(a.lseg, i);
+    double e[6] = {0, 0, 0, 0, 0, 0}, s[5][3], qmax[5], qmin[5];
+#pragma unroll
+    for (int q = 0; q < 5; ++q) {
+      s[q][0] = s[q][1] = s[q][2] = 0.0;
+      qmax[q] = qmin[q] = q64[q];
+    }
+    auto sep = [&](const double *gj, double d[3]) {
+      d[0] = min_image(gj[GIN_X] - xi, a.box[0], a.half[0]);
+      d[1] = min_image(gj[GIN_Y] - yi, a.box[1], a.half[1]);
+      d[2] = min_image(gj[GIN_Z] - zi, a.box[2], a.half[2]);
+    };
+    for (int k = lane; k < gc; k += 64) {
+      const double *gj = a.gin + (int64_t)a.gl[list_at(lb, k)] * GIN_STRIDE;
+      double d[3];
+      sep(gj, d);
+      const double r2 = d[0] * d[0] + d[1] * d[1] + d[2] * d[2];
+      if (r2 == 0.0) continue;
+      const double wv = gj[GIN_V] * wnorm * spline_wt<double>(sqrt(r2) * ih);
+      e[0] += wv * d[0] * d[0];
+      e[1] += wv * d[0] * d[1];
+      e[2] += wv * d[0] * d[2];
+      e[3] += wv * d[1] * d[1];
+      e[4] += wv * d[1] * d[2];
+      e[5] += wv * d[2] * d[2];
+      const double qj[5] = {gj[GIN_RHO], gj[GIN_VX], gj[GIN_VY], gj[GIN_VZ], gj[GIN_P]};
+#pragma unroll
+      for (int q = 0; q < 5; ++q) {
+        const double df = wv * (qj[q] - q64[q]);
+        s[q][0] += df * d[0];
+        s[q][1] += df * d[1];
+        s[q][2] += df * d[2];
+        qmax[q] = fmax(qmax[q], qj[q]);
+        qmin[q] = fmin(qmin[q], qj[q]);
+      }
+    }
+#pragma unroll
+    for (int k = 0; k < 6; ++k) e[k] = wave_sum_f64(e[k]);
+#pragma unroll
+    for (int q = 0; q < 5; ++q) {
+#pragma unroll
+      for (int k = 0; k < 3; ++k) s[q][k] = wave_sum_f64(s[q][k]);
+      qmax[q] = wave_max_f64(qmax[q]);
+      qmin[q] = wave_min_f64(qmin[q]);
+    }
+    double b[6], g[5][3];
+    sym_inv<double>(e, b);
+    const double nc = sym_frob<double>(b) * sym_frob<double>(e) / 3.0;
+#pragma unroll
+    for (int q = 0; q < 5; ++q) sym_apply<double>(b, s[q], g[q]);
+    double alpha[5] = {1, 1, 1, 1, 1};
+    if (a.limiter & MFM_LIMIT_BJ) {
+      double dmax[5] = {0, 0, 0, 0, 0}, dmin[5] = {0, 0, 0, 0, 0};
+      for (int k = lane; k < gc; k += 64) {
+        double d[3];
+        sep(a.gin + (int64_t)a.gl[list_at(lb, k)] * GIN_STRIDE, d);
+#pragma unroll
+        for (int q = 0; q < 5; ++q) {
+          const double ex = 0.5 * (g[q][0] * d[0] + g[q][1] * d[1] + g[q][2] * d[2]);
+          dmax[q] = fmax(dmax[q], ex);
+          dmin[q] = fmin(dmin[q], ex);
+        }
+      }
+      double t = (a.ncond_max - nc) / (a.ncond_max - 1.0);
+      t = t > 0.0 ? (t < 1.0 ? t : 1.0) : 0.0;
+      const double beta = 1.0 + t;
+#pragma unroll
+      for (int q = 0; q < 5; ++q) {
+        dmax[q] = wave_max_f64(dmax[q]);
+        dmin[q] = wave_min_f64(dmin[q]);
+        double rp = __builtin_huge_val(), rm = __builtin_huge_val();
+        if (dmax[q] > 0.0) rp = (qmax[q] - q64[q]) / dmax[q];
+        if (dmin[q] < 0.0) rm = (q64[q] - qmin[q]) / (-dmin[q]);
+        alpha[q] = fmin(1.0, beta * fmin(rp, rm));
+      }
+    }
+    if (lane == 0) {
+      float *rec = reinterpret_cast<float *>(a.rec) + i * F_STRIDE;
+#pragma unroll
+      for (int k = 0; k < 6; ++k) {
+        a.B[k * n + i] = b[k];
+        rec[F_B + k] = (float)b[k];
+      }
+#pragma unroll
+      for (int q = 0; q < 5; ++q)
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+          const double v = alpha[q] * g[q][k];
+          a.grad[(3 * q + k) * n + i] = v;
+          rec[F_G + 3 * q + k] = (float)v;
+        }
+      a.ncond[i] = nc;
+    }
+  }
+}
+
 __global__ void min_partial_k(const double *__restrict__ v, int64_t n, double *partial,
                               const int64_t *counters) {
   if (counters[C_STEP_SKIP]) return;
@@ -448,6 +584,7 @@ hipError_t launch_gradients(mfm_ctx *ctx, const mfm_particles *pp, double dt_max
   a.cand_cnt = ctx->cand_cnt;
   a.rest_r2 = ctx->rest_r2;
   a.gl = ctx->gl;
+  a.lseg = ctx->lseg;
   a.gl_cnt = ctx->gl_cnt;
   a.B = pp->B; a.grad = pp->grad; a.ncond = pp->ncond; a.dt_i = pp->dt_i; a.rec = ctx->rec;
   a.fslot = ctx->fslot;
@@ -462,10 +599,16 @@ hipError_t launch_gradients(mfm_ctx *ctx, const mfm_particles *pp, double dt_max
   a.counters = ctx->counters;
   a.m = pp->m;
   a.ekm = ctx->p.entropy_switch ? ctx->ekm : nullptr;
-  if (ctx->p.precision == MFM_MIXED)
+  a.grad_q = ctx->grad_q;
+  if (ctx->p.precision == MFM_MIXED) {
+    hipError_t e = hipMemsetAsync(ctx->counters + C_GRAD_QUEUE, 0, sizeof(int64_t), ctx->stream);
+    if (e != hipSuccess) return e;
     gradients_k<float><<<blocks_for(pp->n, BS), BS, 0, ctx->stream>>>(a);
-  else
+    // one wavefront per queued particle, the queue's length read on the device
+    grad_fix_k<<<1024, 64, 0, ctx->stream>>>(a);
+  } else {
     gradients_k<double><<<blocks_for(pp->n, BS), BS, 0, ctx->stream>>>(a);
+  }
   min_partial_k<<<RED_BLOCKS, BS, 0, ctx->stream>>>(pp->dt_i, pp->n, ctx->red, ctx->counters);
   dt_final_k<<<1, BS, 0, ctx->stream>>>(ctx->red, RED_BLOCKS, dt_max, dt_dev, ctx->counters);
   return hipGetLastError();

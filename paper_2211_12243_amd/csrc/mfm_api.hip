@@ -14,30 +14,23 @@ namespace {
 constexpr size_t ALIGN = 256;
 
 struct Layout {
-  size_t code, count, start, cursor, crange, scan, order, tmp, pos4, cand, cand_r2, rest_r2,
-      cand_cnt, gl, gl_cnt, gin, fslot, fcnt, dq_ext, hard_q, rec, ekm, gwork, red, counters,
+  size_t code, hist, tnode, scan, lseg, lcap, scan64, ncand, order, tmp, pos4, cand, cand_r2, rest_r2,
+      cand_cnt, gl, gl_cnt, gin, fslot, fcnt, dq_ext, hard_q, rec, ekm, grad_q, gwork, red, counters,
       scalars;
   int64_t hard_cap;
   size_t total;
-  int64_t ncodes_max;
   size_t scan_len;
 };
 
-int ceil_log2(int v) {
-  int b = 0;
-  while ((1 << b) < v) ++b;
-  return b;
-}
 
 size_t up(size_t v) { return (v + ALIGN - 1) / ALIGN * ALIGN; }
 
 Layout make_layout(const mfm_params *p, int64_t n) {
   Layout L;
-  int bits = ceil_log2(p->max_cell_dim < 3 ? 3 : p->max_cell_dim);
-  L.ncodes_max = (int64_t)1 << (3 * bits);
-  size_t scan_len = 64;
-  for (int64_t m = L.ncodes_max; m > 1; m = (m + 1023) / 1024) scan_len += (size_t)(m + 1023) / 1024;
-  L.scan_len = scan_len;
+  // the sort's digit counts: RADIX per workgroup tile, and the block sums
+  // of their scan
+  const int64_t hist_len = (int64_t)RADIX * ((n + SORT_TILE - 1) / SORT_TILE);
+  L.scan_len = scan_len(hist_len);
   size_t off = 0;
   auto take = [&](size_t bytes) {
     size_t o = off;
@@ -45,11 +38,21 @@ Layout make_layout(const mfm_params *p, int64_t n) {
     return o;
   };
   L.code = take(4 * (size_t)n);
-  L.count = take(4 * (size_t)L.ncodes_max);
-  L.start = take(4 * (size_t)L.ncodes_max);
-  L.cursor = take(4 * (size_t)L.ncodes_max);
-  L.crange = take(8 * (size_t)L.ncodes_max);
-  L.scan = take(4 * scan_len);
+  L.hist = take(4 * (size_t)hist_len);
+  // tree nodes: one per bucket, then each level an eighth of the last
+  int64_t nodes = 0;
+  for (int64_t c = (n + BUCKET - 1) / BUCKET;; c = (c + TREE_FANOUT - 1) / TREE_FANOUT) {
+    nodes += c;
+    if (c <= 1) break;
+  }
+  L.tnode = take(8 * TNODE * (size_t)nodes);
+  L.scan = take(4 * L.scan_len);
+  // the list blocks: one per chunk of LCH particles, planned and scanned
+  const int64_t nch = list_chunks(n);
+  L.lseg = take(8 * (size_t)(nch + 1));
+  L.lcap = take(8 * (size_t)(nch + 1));
+  L.scan64 = take(8 * scan_len(nch + 1));
+  L.ncand = take(4 * (size_t)n);
   L.order = take(4 * (size_t)n);
   L.tmp = take(8 * 16 * (size_t)n);
   L.pos4 = take(32 * (size_t)n);
@@ -68,6 +71,7 @@ Layout make_layout(const mfm_params *p, int64_t n) {
   L.hard_q = take(8 * (size_t)L.hard_cap);
   L.rec = take(8 * (size_t)R_STRIDE * (size_t)n);
   L.ekm = take(8 * (size_t)n);
+  L.grad_q = take(4 * (size_t)n);
   L.gwork = take(8 * 3 * (size_t)n);
   L.red = take(8 * 5 * 1024);
   L.counters = take(8 * NCOUNTERS);
@@ -90,7 +94,7 @@ int check_params(const mfm_params *p) {
   if (!(p->riemann_tol > 0.0) || p->riemann_maxit < 1) return 0;
   if (p->max_list < 1 || p->max_list > 4096) return 0;
   if (!(p->cell_margin >= 1.0)) return 0;
-  if (p->max_cell_dim < 3 || p->max_cell_dim > 512) return 0;
+  if (p->reserved != 0) return 0;
   if (!(p->mixed_jump == 0.0 || p->mixed_jump >= 1.0)) return 0;
   if (!(p->alpha2 >= 0.0) || !(p->alpha3 >= 0.0)) return 0;
   if (p->entropy_switch != 0 && p->entropy_switch != 1) return 0;
@@ -134,32 +138,27 @@ int read_counters(mfm_ctx *ctx, int64_t *host) {
   return MFM_OK;
 }
 
-int setup_grid(mfm_ctx *ctx, double hmax) {
-  CellGrid &g = ctx->grid;
-  double s = hmax * ctx->p.cell_margin * ctx->margin_boost;
+// The box and the tree's level sizes, from n and the parameters alone.
+int setup_tree(mfm_ctx *ctx, int64_t n) {
+  Tree &g = ctx->tree;
   g.hfac = ctx->p.cell_margin * ctx->margin_boost;
-  if (!(s > 0.0) || !isfinite(s)) return fail(ctx, MFM_E_ARG, "smoothing lengths must be > 0");
-  int ncmax = 0;
   g.side_min = 1e300;
   for (int k = 0; k < 3; ++k) {
-    double L = ctx->p.box[k];
-    double c = floor(L / s);
-    if (c > ctx->p.max_cell_dim) c = ctx->p.max_cell_dim;
-    if (c < 3.0)
-      return fail(ctx, MFM_E_CELLS, "support radius too large: fewer than 3 cells per axis");
-    g.nc[k] = (int)c;
-    g.inv[k] = c / L;
-    g.box[k] = L;
-    g.half[k] = 0.5 * L;
-    double side = L / c;
-    if (side < g.side_min) g.side_min = side;
-    if (g.nc[k] > ncmax) ncmax = g.nc[k];
+    g.box[k] = ctx->p.box[k];
+    g.half[k] = 0.5 * ctx->p.box[k];
+    g.side_min = fmin(g.side_min, 0.5 * ctx->p.box[k]);
   }
-  ctx->bits = ceil_log2(ncmax);
-  ctx->ncodes = (int64_t)1 << (3 * ctx->bits);
-  g.start = ctx->cell_start;
-  g.count = ctx->cell_count;
-  g.range = ctx->crange;
+  g.node = ctx->tnode;
+  g.nlev = 0;
+  int off = 0;
+  for (int64_t c = (n + BUCKET - 1) / BUCKET;; c = (c + TREE_FANOUT - 1) / TREE_FANOUT) {
+    if (g.nlev == MAX_TREE_LEVELS) return fail(ctx, MFM_E_ARG, "too many particles for the tree");
+    g.lev_off[g.nlev] = off;
+    g.lev_cnt[g.nlev] = (int)c;
+    ++g.nlev;
+    off += (int)c;
+    if (c <= 1) break;
+  }
   return MFM_OK;
 }
 
@@ -221,7 +220,6 @@ void mfm_default_params(mfm_params *p) {
   p->alpha1 = 0.01;
   p->box[0] = p->box[1] = p->box[2] = 1.0;
   p->cell_margin = 1.10;
-  p->max_cell_dim = 256;
   p->mixed_jump = 8.0;
   p->alpha2 = 1e-3;
   p->alpha3 = 1e-3;
@@ -248,10 +246,15 @@ int init_ctx(mfm_ctx *ctx, const mfm_params *p, int64_t n_max, void *workspace,
   ctx->ws = (char *)workspace;
   ctx->ws_bytes = workspace_bytes;
   ctx->code = (uint32_t *)(ctx->ws + L.code);
-  ctx->cell_count = (int32_t *)(ctx->ws + L.count);
-  ctx->cell_start = (int32_t *)(ctx->ws + L.start);
-  ctx->cursor = (int32_t *)(ctx->ws + L.cursor);
-  ctx->crange = (int2 *)(ctx->ws + L.crange);
+  ctx->hist = (int32_t *)(ctx->ws + L.hist);
+  ctx->lseg = (int64_t *)(ctx->ws + L.lseg);
+  ctx->lcap = (int64_t *)(ctx->ws + L.lcap);
+  ctx->scan64 = (int64_t *)(ctx->ws + L.scan64);
+  ctx->ncand = (int32_t *)(ctx->ws + L.ncand);
+  ctx->pool = (int64_t)list_len(p->max_list, n_max);
+  ctx->have_need = 0;
+  ctx->need_n = 0;
+  ctx->tnode = (double *)(ctx->ws + L.tnode);
   ctx->scan_tmp = (int32_t *)(ctx->ws + L.scan);
   ctx->order = (int32_t *)(ctx->ws + L.order);
   ctx->tmp = (double *)(ctx->ws + L.tmp);
@@ -270,15 +273,16 @@ int init_ctx(mfm_ctx *ctx, const mfm_params *p, int64_t n_max, void *workspace,
   ctx->hard_cap = L.hard_cap;
   ctx->rec = (double *)(ctx->ws + L.rec);
   ctx->ekm = (double *)(ctx->ws + L.ekm);
+  ctx->grad_q = (int32_t *)(ctx->ws + L.grad_q);
   ctx->gwork = (double *)(ctx->ws + L.gwork);
   ctx->inv_a = 1.0;
   ctx->hubble_n = ctx->hubble_np1 = 0.0;
   ctx->red = (double *)(ctx->ws + L.red);
   ctx->counters = (int64_t *)(ctx->ws + L.counters);
   ctx->scalars = (double *)(ctx->ws + L.scalars);
-  ctx->ncodes_max = L.ncodes_max;
   ctx->scan_tmp_len = L.scan_len;
   ctx->margin_boost = 1.0;
+  ctx->overflow_streak = 0;
   ctx->dump_count = reinterpret_cast<unsigned long long *>(ctx->counters + C_DUMP_COUNT);
   // counters start at zero whatever the workspace held (the static scratch
   // keeps the last context's contents)
@@ -372,9 +376,16 @@ int mfm_destroy(mfm_ctx *ctx) {
 
 namespace {
 
-// Grid for the given max H, cell build and permutation (no synchronisation).
-int build_cells_async(mfm_ctx *ctx, const mfm_particles *pp, int64_t *perm, double hmax) {
-  int rc = setup_grid(ctx, hmax);
+// After a density pass some of whose H outgrew cell_margin times their value
+// at the build: those H now hold estimates of their roots (the next build's
+// radii follow them).  A second overflow in a row widens every radius too.
+void grow_margin(mfm_ctx *ctx) {
+  if (++ctx->overflow_streak >= 2) ctx->margin_boost *= 1.1;
+}
+
+// Sort, permutation and tree build (no synchronisation).
+int build_cells_async(mfm_ctx *ctx, const mfm_particles *pp, int64_t *perm) {
+  int rc = setup_tree(ctx, pp->n);
   if (rc) return rc;
   const int ev = stage_begin(ctx, 0);
   HIPCHK(ctx, launch_build_cells(ctx, pp, perm), "cells");
@@ -386,19 +397,25 @@ int build_cells_async(mfm_ctx *ctx, const mfm_particles *pp, int64_t *perm, doub
   return MFM_OK;
 }
 
-// Neighbour search, density pass and its validation against the grid
-// (no synchronisation).  scalars[0] must hold the max H at the cell build.
-int density_async(mfm_ctx *ctx, const mfm_particles *pp, double hmax_grid) {
+// Neighbour search, density pass and its validation (no synchronisation).
+int density_async(mfm_ctx *ctx, const mfm_particles *pp) {
   static_assert(C_STEP_SKIP - C_CELL_OVERFLOW == 5, "per-pass counters are contiguous");
   HIPCHK(ctx, hipMemsetAsync(ctx->counters + C_CELL_OVERFLOW, 0, 6 * sizeof(int64_t),
                              ctx->stream), "clear pass counters");
   int ev = stage_begin(ctx, 1);
-  HIPCHK(ctx, launch_candidates(ctx, pp), "neighbour search");
+  // the list blocks follow the last search's list lengths; without them
+  // (the first pass, or another particle count) a counting search runs first
+  if (!ctx->have_need || ctx->need_n != pp->n)
+    HIPCHK(ctx, launch_candidates(ctx, pp, true), "neighbour count");
+  HIPCHK(ctx, launch_plan_lists(ctx, pp->n), "plan the lists");
+  HIPCHK(ctx, launch_candidates(ctx, pp, false), "neighbour search");
+  ctx->have_need = 1;
+  ctx->need_n = pp->n;
   stage_end(ctx, ev);
   ev = stage_begin(ctx, 2);
   HIPCHK(ctx, launch_density(ctx, pp), "density");
   stage_end(ctx, ev);
-  HIPCHK(ctx, launch_validate(ctx, hmax_grid), "validate the density pass");
+  HIPCHK(ctx, launch_validate(ctx), "validate the density pass");
   return MFM_OK;
 }
 
@@ -409,13 +426,7 @@ extern "C" {
 int mfm_build_cells(mfm_ctx *ctx, const mfm_particles *pp, int64_t *perm) {
   if (!ctx) return MFM_E_ARG;
   if (!check_parts(ctx, pp)) return fail(ctx, MFM_E_ARG, "invalid particle set");
-  HIPCHK(ctx, launch_max_h(ctx, pp), "max H");
-  double hmax = 0.0;
-  HIPCHK(ctx, hipMemcpyAsync(&hmax, ctx->scalars, sizeof(double), hipMemcpyDeviceToHost,
-                             ctx->stream),
-         "read max H");
-  HIPCHK(ctx, hipStreamSynchronize(ctx->stream), "synchronise");
-  return build_cells_async(ctx, pp, perm, hmax);
+  return build_cells_async(ctx, pp, perm);
 }
 
 int mfm_density(mfm_ctx *ctx, const mfm_particles *pp) {
@@ -423,26 +434,33 @@ int mfm_density(mfm_ctx *ctx, const mfm_particles *pp) {
   if (!check_parts(ctx, pp)) return fail(ctx, MFM_E_ARG, "invalid particle set");
   if (!ctx->have_cells || ctx->n_cells_built != pp->n)
     return fail(ctx, MFM_E_STATE, "mfm_density needs mfm_build_cells first");
-  // the grid was sized from this H on the device at the build
-  int rc = density_async(ctx, pp, __builtin_huge_val());
-  if (rc) return rc;
   int64_t c[NCOUNTERS];
-  rc = read_counters(ctx, c);
-  if (rc) return rc;
-  // truncated candidate lists make every later result meaningless (and can
-  // push H to the cell side): report them first
+  // a chunk whose lists outgrew the blocks planned from the last search
+  // leaves the state untouched and its lengths recorded: the second pass is
+  // planned from them
+  for (int pass = 0; pass < 2; ++pass) {
+    int rc = density_async(ctx, pp);
+    if (rc) return rc;
+    rc = read_counters(ctx, c);
+    if (rc) return rc;
+    if (c[C_PASS_LIST] == 0) break;
+    if (c[C_LIST_POOL])
+      return fail(ctx, MFM_E_LIST, "neighbour lists exceed the list pool (raise max_list)");
+  }
   if (c[C_PASS_LIST] > 0)
-    return fail(ctx, MFM_E_LIST, "candidate list capacity exceeded (raise max_list)");
+    return fail(ctx, MFM_E_LIST, "neighbour lists outgrew their planned blocks twice");
   if (c[C_CELL_OVERFLOW] > 0) {
-    // some H reached the cell side: this pass is discarded (its counts too)
-    // and the next build uses larger cells.  The density loop has written an
-    // estimate of each outgrown root as its start value; a small extra
-    // margin guards against underestimates.
-    ctx->margin_boost *= 1.1;
+    // some H reached cell_margin times its value at the build: this pass is
+    // discarded (its counts too) and the next build searches wider.  The
+    // density loop has written an estimate of each outgrown root as its
+    // start value; a small extra margin guards against underestimates.
+    grow_margin(ctx);
     ctx->have_cells = 0;
-    return fail(ctx, MFM_E_CELLS, "smoothing lengths outgrew the cell grid; rebuild cells");
+    ctx->have_need = 0;  // new radii: the next search counts its lists first
+    return fail(ctx, MFM_E_CELLS, "smoothing lengths outgrew their search radii; rebuild cells");
   }
   ctx->margin_boost = 1.0;
+  ctx->overflow_streak = 0;
   ctx->have_density = 1;
   ctx->have_grad = 0;
   if (c[C_PASS_NOCONV] > 0)
@@ -530,29 +548,18 @@ int mfm_step(mfm_ctx *ctx, const mfm_particles *pp, double dt_max, double *dt_ho
   if (!check_parts(ctx, pp) || !(dt_max > 0.0)) return fail(ctx, MFM_E_ARG, "invalid arguments");
   if (ctx->p.guess == MFM_GUESS_LEARNED && !ctx->mlp_state)
     return fail(ctx, MFM_E_STATE, "learned guess requested but no network attached");
-  // The grid is sized from the max H that the previous step's density pass
-  // left (read at that step's one synchronisation).  The device checks it
-  // against the actual max H at the build; a step whose grid or candidate
-  // lists turn out too small is rejected there, its later kernels return at
-  // once (the state is not updated), and it is repeated.
-  double hmax = ctx->hmax_next;
-  if (!(hmax > 0.0) || ctx->hmax_H != pp->H || ctx->hmax_n != pp->n) {
-    HIPCHK(ctx, launch_max_h(ctx, pp), "max H");
-    HIPCHK(ctx, hipMemcpyAsync(&hmax, ctx->scalars, sizeof(double), hipMemcpyDeviceToHost,
-                               ctx->stream),
-           "read max H");
-    HIPCHK(ctx, hipStreamSynchronize(ctx->stream), "synchronise");
-  }
+  // A density pass whose candidate radii or list blocks turn out too small
+  // is rejected on the device; the kernels after it return at once (the
+  // state is not updated), and the step is repeated with larger radii or
+  // blocks.
   double *dt_dev = ctx->scalars + 1;
-  for (int attempt = 0; attempt < 4; ++attempt) {
+  for (int attempt = 0; attempt < 6; ++attempt) {
     HIPCHK(ctx, hipMemsetAsync(ctx->counters + C_NONFINITE, 0, sizeof(int64_t), ctx->stream),
            "clear step counters");
-    int rc = build_cells_async(ctx, pp, nullptr, hmax);
+    int rc = build_cells_async(ctx, pp, nullptr);
     if (rc) return rc;
-    HIPCHK(ctx, launch_max_h(ctx, pp), "max H at the build");
-    rc = density_async(ctx, pp, hmax);
+    rc = density_async(ctx, pp);
     if (rc) return rc;
-    HIPCHK(ctx, launch_max_h(ctx, pp), "max H after the density pass");
     ctx->have_density = 1;
     rc = mfm_gradients(ctx, pp, dt_max, dt_dev);
     if (rc) return rc;
@@ -560,7 +567,7 @@ int mfm_step(mfm_ctx *ctx, const mfm_particles *pp, double dt_max, double *dt_ho
     if (rc) return rc;
     rc = mfm_update(ctx, pp, dt_dev);
     if (rc) return rc;
-    // the step's one synchronisation: counters, max H and dt together
+    // the step's one synchronisation: counters and dt together
     int64_t c[NCOUNTERS];
     double sc[2];
     HIPCHK(ctx, hipMemcpyAsync(c, ctx->counters, sizeof(c), hipMemcpyDeviceToHost, ctx->stream),
@@ -568,24 +575,28 @@ int mfm_step(mfm_ctx *ctx, const mfm_particles *pp, double dt_max, double *dt_ho
     HIPCHK(ctx, hipMemcpyAsync(sc, ctx->scalars, sizeof(sc), hipMemcpyDeviceToHost, ctx->stream),
            "read dt");
     HIPCHK(ctx, hipStreamSynchronize(ctx->stream), "synchronise");
-    ctx->hmax_next = sc[0];
-    ctx->hmax_H = pp->H;
-    ctx->hmax_n = pp->n;
-    hmax = sc[0];
     if (c[C_STEP_SKIP]) {
-      if (c[C_PASS_LIST] > 0)
-        return fail(ctx, MFM_E_LIST, "candidate list capacity exceeded (raise max_list)");
-      if (c[C_CELL_OVERFLOW] > 0) ctx->margin_boost *= 1.1;
+      // lists longer than their planned blocks: the next attempt plans from
+      // the lengths this one recorded (the same order, the same lists)
+      if (c[C_PASS_LIST] > 0 && c[C_LIST_POOL])
+        return fail(ctx, MFM_E_LIST, "neighbour lists exceed the list pool (raise max_list)");
+      if (c[C_CELL_OVERFLOW] > 0) {
+        // new start values (and radii): the next search counts its lists
+        // first
+        grow_margin(ctx);
+        ctx->have_need = 0;
+      }
       continue;
     }
     ctx->margin_boost = 1.0;
+    ctx->overflow_streak = 0;
     *dt_host = sc[1];
     if (c[C_NONFINITE] > 0) return fail(ctx, MFM_E_NONFINITE, "non-finite step or state");
     if (c[C_PASS_NOCONV] > 0)
       return fail(ctx, MFM_E_H_NOCONV, "smoothing-length solve did not converge");
     return MFM_OK;
   }
-  return fail(ctx, MFM_E_CELLS, "smoothing lengths kept outgrowing the cell grid");
+  return fail(ctx, MFM_E_CELLS, "smoothing lengths kept outgrowing their search radii");
 }
 
 int mfm_diagnostics(mfm_ctx *ctx, const mfm_particles *pp, mfm_diag *out) {
@@ -664,7 +675,7 @@ const char *mfm_strerror(int status) {
     case MFM_E_WORKSPACE: return "workspace missing, misaligned or too small";
     case MFM_E_HIP: return "HIP runtime error";
     case MFM_E_H_NOCONV: return "smoothing-length solve did not converge";
-    case MFM_E_CELLS: return "smoothing lengths outgrew the cell grid";
+    case MFM_E_CELLS: return "smoothing lengths outgrew their search radii";
     case MFM_E_LIST: return "neighbour list capacity exceeded";
     case MFM_E_NONFINITE: return "non-finite time step or state";
     case MFM_E_STATE: return "call order violated";

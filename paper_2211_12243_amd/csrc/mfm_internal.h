@@ -34,7 +34,7 @@ enum {
   // the density pass in flight (cleared before each pass); its counts are
   // folded into the slots above only when the pass is accepted (a pass whose
   // H outgrew the cells is redone)
-  C_CELL_OVERFLOW,  // some H reached the cell side
+  C_CELL_OVERFLOW,  // some H reached its bracket (cell_margin H at the build, or half the box)
   C_PASS_NOCONV,
   C_PASS_BOOSTS,
   C_PASS_FAIL,
@@ -42,13 +42,15 @@ enum {
   C_STEP_SKIP,      // the pass is rejected: the kernels after it return at once
   C_DUMP_COUNT,     // face records appended since the dump was armed
   C_HARD_QUEUE,     // faces queued for the flux loop's FP64 pass in the current call
+  C_LIST_POOL,      // the planned list blocks exceed the list pool (set by each plan)
+  C_GRAD_QUEUE,     // mixed path: particles queued for the gradient loop's FP64 redo
   NCOUNTERS = 32
 };
 
 // Packed per-particle record the gradient loop gathers for each neighbour
 // (written by the density loop; one 128-byte line).
 enum { GIN_X = 0, GIN_Y, GIN_Z, GIN_H, GIN_V, GIN_RHO, GIN_VX, GIN_VY, GIN_VZ, GIN_P, GIN_C,
-       GIN_F32 = 12,  // from here: V, rho, vx, vy, vz, P, c rounded to FP32 (the mixed path's gather)
+       GIN_F32 = 12,  // from here: V, rho, P, c rounded to FP32 (the mixed path's gather)
        GIN_STRIDE = 16 };
 
 // Packed per-particle record the flux loop gathers for each face side
@@ -74,17 +76,43 @@ enum {
   F_STRIDE = 32
 };
 
-// Geometry of the cell grid, passed by value to kernels.
-struct CellGrid {
-  int nc[3];          // cells per axis (>= 3)
-  double inv[3];      // nc / box per axis
+// The neighbour search's bucket tree (sec. 2.2.3: the paper searches
+// neighbours per bucket of particles).  Level 0 has one node per bucket of
+// BUCKET consecutive particles of the Z-ordered array; a node of level l + 1
+// covers TREE_FANOUT consecutive nodes of level l; the top level has one
+// node.  A node holds the bounding box of its particles and R, cell_margin
+// times their largest H at the build (the largest candidate radius inside).
+constexpr int BUCKET = 64;
+constexpr int TREE_FANOUT = 8;
+constexpr int MAX_TREE_LEVELS = 12;
+constexpr int TNODE = 8;  // doubles per node: min x, y, z, max x, y, z, R, unused
+
+// The particle order: Morton keys of KEY_BITS bits per axis (SMALL_KEY_BITS
+// for sets of at most SMALL_SORT particles), sorted by a stable
+// least-significant-digit radix sort of RADIX_BITS-bit digits: 4 passes, or
+// 2 for the small sets (an even number, so that the result lands back in the
+// primary buffers).
+constexpr int KEY_BITS = 10;
+constexpr int SMALL_KEY_BITS = 5;
+constexpr int64_t SMALL_SORT = 1 << 16;
+constexpr int RADIX_BITS = 8;
+constexpr int RADIX = 1 << RADIX_BITS;
+static_assert((3 * KEY_BITS + RADIX_BITS - 1) / RADIX_BITS % 2 == 0 &&
+                  (3 * SMALL_KEY_BITS + RADIX_BITS - 1) / RADIX_BITS % 2 == 0,
+              "the sort must take an even number of passes");
+constexpr int SORT_BS = RADIX;   // threads per sort workgroup (one per digit)
+constexpr int SORT_ITEMS = 16;   // items per thread
+constexpr int SORT_TILE = SORT_BS * SORT_ITEMS;
+
+// Geometry of the box and the tree, passed by value to kernels.
+struct Tree {
   double box[3];      // periodic sides
   double half[3];     // box / 2
-  double side_min;    // smallest cell side: every pair closer than this is in the 27-cell stencil
+  double side_min;    // bound on any H: half the smallest side (minimum image)
   double hfac;        // cell_margin (times the rebuild boost): bound on H / H at the build
-  const int32_t *start;  // indexed by Morton code
-  const int32_t *count;  // indexed by Morton code
-  const int2 *range;     // (start, count) by Morton code, one load per cell
+  const double *node; // TNODE doubles per tree node, level by level
+  int nlev;           // tree levels (the top one has one node)
+  int lev_off[MAX_TREE_LEVELS], lev_cnt[MAX_TREE_LEVELS];
 };
 
 constexpr int MAX_EVENT_PAIRS = 1024;  // timed launches held between two harvests
@@ -96,24 +124,30 @@ struct mfm_ctx {
   char *ws;
   size_t ws_bytes;
   // workspace carve
-  uint32_t *code;      // n: Morton code of each particle's cell
-  int32_t *cell_count; // ncodes_max
-  int32_t *cell_start; // ncodes_max
-  int32_t *cursor;     // ncodes_max
-  int2 *crange;        // ncodes_max: (start, count) per cell
+  uint32_t *code;      // n: Morton key of each particle
+  int32_t *hist;       // RADIX per sort workgroup: digit counts, then first slots
+  double *tnode;       // the bucket tree, TNODE doubles per node
   int32_t *scan_tmp;   // block sums of the scans
   int32_t *order;      // n: input slot of each sorted slot
-  double *tmp;         // 16 n doubles: gather buffer of the permutation
+  double *tmp;         // 16 n doubles: gather buffer of the permutation (its front
+                       // doubles as the sort's second key and value buffers)
   double *pos4;        // 4 n: (x, y, z, H at the build) per particle
-  int32_t *cand;       // max_list * n candidates (r < cell side), entry k of i at [k * n + i];
+  int64_t *lseg;       // list_chunks(n) + 1: each chunk's first pool entry (list_at)
+  int64_t *lcap;       // list_chunks(n) + 1: the planned block sizes before their scan
+  int64_t *scan64;     // block sums of that scan
+  int32_t *ncand;      // n: each particle's candidate count in the last search (permuted with it)
+  int64_t pool;        // pool entries (list_len)
+  int have_need;       // ncand holds the last search's counts for need_n particles
+  int64_t need_n;
+  int32_t *cand;       // pool: candidates (r < cell_margin max(H_i, H_j) at the build);
                        // after the density loop: the candidates with r >= H_i
-  double *cand_r2;     // max_list * n: their squared distances (FP64, from the search)
-  float *rest_r2;      // max_list * n: squared distances of the r >= H_i list, rounded to FP32
+  double *cand_r2;     // pool: their squared distances (FP64, from the search)
+  float *rest_r2;      // pool: squared distances of the r >= H_i list, rounded to FP32
   int32_t *cand_cnt;   // n
-  int32_t *gl;         // max_list * n: gather set r < H_i of each particle (k-major), from the density loop
+  int32_t *gl;         // pool: gather set r < H_i of each particle, from the density loop
   int32_t *gl_cnt;     // n
   double *gin;         // GIN_STRIDE * n packed gradient-loop records
-  int32_t *fslot;      // max_list * n: faces each particle evaluates (k-major)
+  int32_t *fslot;      // pool: faces each particle evaluates
   int32_t *fcnt;       // n
   double *dq_ext;      // 5 n: flux contributions to particles outside the evaluating block
                        // and of the FP64 second pass, folded into dQ after the loop
@@ -121,25 +155,19 @@ struct mfm_ctx {
   int64_t hard_cap;    // its capacity
   double *rec;         // R_STRIDE * n packed flux records
   double *ekm;         // n: E_kin^max of the entropy switch (gradient loop)
+  int32_t *grad_q;     // n: particles queued for the mixed gradient loop's FP64 redo
   double *gwork;       // 3 n: sum_j dm_ij (x_j - x_i) (flux loop, MFV with gravity)
   // comoving integration (mfm_set_cosmology)
   double inv_a, hubble_n, hubble_np1;
   double *red;         // reduction partials
   int64_t *counters;   // NCOUNTERS
   double *scalars;     // small device scalars: [0] max H, [1] dt, [2..6] conserved sums
-  int64_t ncodes_max;
   size_t scan_tmp_len, red_len;
-  // current grid
-  CellGrid grid;
-  int64_t ncodes;
-  int bits;
+  // current tree geometry
+  Tree tree;
   double margin_boost;
+  int overflow_streak;  // density passes in a row rejected for an outgrown H
   int have_cells, have_density, have_grad;
-  // mfm_step: max H after its last density pass (read at its one
-  // synchronisation), for the next step's grid; checked on the device
-  double hmax_next;
-  const double *hmax_H;  // the H array it belongs to
-  int64_t hmax_n;
   int64_t n_cells_built;  // n of the particles the cells were built for
   // learned guess and face dump
   const void *mlp_state;  // network state (mfm_mlp_attach), null if none
@@ -202,20 +230,6 @@ __device__ __forceinline__ uint32_t morton3(int cx, int cy, int cz) {
   return spread_bits3((uint32_t)cx) | (spread_bits3((uint32_t)cy) << 1) |
          (spread_bits3((uint32_t)cz) << 2);
 }
-// Inverse of spread_bits3: every third bit of v, packed.
-__device__ __forceinline__ uint32_t compact_bits3(uint32_t v) {
-  v &= 0x09249249u;
-  v = (v | (v >> 2)) & 0x030C30C3u;
-  v = (v | (v >> 4)) & 0x0300F00Fu;
-  v = (v | (v >> 8)) & 0x030000FFu;
-  v = (v | (v >> 16)) & 0x000003FFu;
-  return v;
-}
-__device__ __forceinline__ int cell_coord(double x, double inv, int nc) {
-  int c = (int)(x * inv);
-  return c < 0 ? 0 : (c >= nc ? nc - 1 : c);
-}
-
 // 64-lane wave reductions.
 __device__ __forceinline__ int64_t wave_sum_i64(int64_t v) {
   for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
@@ -253,14 +267,26 @@ __device__ __forceinline__ void count_add(int64_t *ctr, int64_t v) {
 // Launchers (host side), one translation unit each.  All enqueue on ctx->stream
 // and return a hipError_t.
 // ---------------------------------------------------------------------------
-hipError_t launch_max_h(mfm_ctx *ctx, const mfm_particles *pp);
 // After a density pass: reject it (C_STEP_SKIP) if a candidate list
-// overflowed, an H outgrew the cells, or the max H at the cell build
-// (scalars[0] then) exceeded hmax_grid, the value the grid was sized for;
-// else fold the pass counts into the running counters.
-hipError_t launch_validate(mfm_ctx *ctx, double hmax_grid);
+// overflowed or an H outgrew its bound; else fold the pass counts into the
+// running counters.
+hipError_t launch_validate(mfm_ctx *ctx);
 hipError_t launch_build_cells(mfm_ctx *ctx, const mfm_particles *pp, int64_t *perm);
-hipError_t launch_candidates(mfm_ctx *ctx, const mfm_particles *pp);
+// Exclusive int64 scan (in place allowed); tmp: block sums of every level,
+// scan_len(n) entries.
+hipError_t scan_exclusive_i64(hipStream_t st, const int64_t *in, int64_t *out, int64_t n,
+                              int64_t *tmp);
+static inline size_t scan_len(int64_t n) {
+  size_t len = 64;
+  for (int64_t m = n; m > 1; m = (m + 1023) / 1024) len += (size_t)(m + 1023) / 1024;
+  return len;
+}
+// The neighbour search.  count_only: record each particle's candidate count
+// in ncand and write no list (the first search of a context).
+hipError_t launch_candidates(mfm_ctx *ctx, const mfm_particles *pp, bool count_only);
+// Plan the list blocks from ncand (plus a margin): lseg, and C_LIST_POOL when
+// they exceed the pool.
+hipError_t launch_plan_lists(mfm_ctx *ctx, int64_t n);
 hipError_t launch_density(mfm_ctx *ctx, const mfm_particles *pp);
 hipError_t launch_gradients(mfm_ctx *ctx, const mfm_particles *pp, double dt_max, double *dt_dev);
 // Times the whole flux loop as stage 4, its first-pass kernel as stage 6 and
@@ -291,18 +317,25 @@ __host__ __device__ __forceinline__ int xcd_block(int b, int nb) {
 
 static inline int blocks_for(int64_t n, int bs) { return (int)((n + bs - 1) / bs); }
 
-// Per-particle lists (candidates, faces) are stored in tiles of LIST_TILE
-// consecutive entries of one particle: entry k of particle i sits at
-// ((k / LIST_TILE) * n + i) * LIST_TILE + k % LIST_TILE.  LIST_TILE = 1 is the
-// k-major layout: the loops read entry k of 64 consecutive particles in
-// lockstep, one coalesced access (measured faster than 16-entry tiles, which
-// only help the appending writes).
-constexpr int LIST_TILE = 1;
-__host__ __device__ __forceinline__ int64_t list_at(int64_t i, int k, int64_t n) {
-  return (((int64_t)(k / LIST_TILE) * n + i) * LIST_TILE) + (k % LIST_TILE);
+// Per-particle lists (candidates, gather sets, faces) live in a pool shared
+// by chunks of LCH consecutive particles.  Chunk c owns the block
+// [lseg[c], lseg[c + 1]): LCH * K_c entries, entry k of particle i at
+// lseg[i / LCH] + k * LCH + i % LCH, so the loops read entry k of
+// consecutive particles in one coalesced access.  K_c, the chunk's capacity,
+// is planned from the longest candidate list the chunk had in the last
+// search (plus a margin), so the pool follows the lists' real lengths, not
+// the longest list of the set.
+constexpr int LCH = 16;
+__device__ __forceinline__ int64_t list_base(const int64_t *__restrict__ lseg, int64_t i) {
+  return lseg[i / LCH] + i % LCH;
 }
+__host__ __device__ __forceinline__ int64_t list_at(int64_t base, int k) {
+  return base + (int64_t)k * LCH;
+}
+static inline int64_t list_chunks(int64_t n) { return (n + LCH - 1) / LCH; }
+// entries of the pool: max_list per particle slot of the chunks
 static inline size_t list_len(int max_list, int64_t n) {
-  return (size_t)((max_list + LIST_TILE - 1) / LIST_TILE) * LIST_TILE * (size_t)n;
+  return (size_t)max_list * (size_t)(list_chunks(n) * LCH);
 }
 
 // Particles per workgroup of the flux loop: faces inside a block are computed

@@ -36,7 +36,7 @@ class mfm_params(ctypes.Structure):
         ("ngb_boost", ctypes.c_double), ("h_tol", ctypes.c_double), ("c_cfl", ctypes.c_double),
         ("psi1", ctypes.c_double), ("psi2", ctypes.c_double), ("riemann_tol", ctypes.c_double),
         ("alpha1", ctypes.c_double), ("box", ctypes.c_double * 3),
-        ("cell_margin", ctypes.c_double), ("max_cell_dim", ctypes.c_int32),
+        ("cell_margin", ctypes.c_double), ("reserved", ctypes.c_int32),
         ("pad0", ctypes.c_int32), ("alpha2", ctypes.c_double), ("alpha3", ctypes.c_double),
         ("entropy_switch", ctypes.c_int32), ("pad1", ctypes.c_int32),
         ("mixed_jump", ctypes.c_double),
@@ -170,7 +170,7 @@ def params_from_dict(cfg: dict, **over) -> mfm_params:
     """The library's parameter struct from the plain dict the tests share."""
     keys = ("scheme", "limiter", "max_boosts", "h_maxit", "riemann_maxit", "gamma", "n_ngb",
             "ncond_max", "ngb_boost", "h_tol", "c_cfl", "psi1", "psi2", "riemann_tol", "alpha1",
-            "box", "precision", "max_list", "cell_margin", "max_cell_dim", "guess",
+            "box", "precision", "max_list", "cell_margin", "guess",
             "mixed_jump", "alpha2", "alpha3", "entropy_switch")
     d = {k: cfg[k] for k in keys if k in cfg}
     d.update(over)

@@ -272,6 +272,36 @@ def random_gas(N: int = 2000, seed: int = 0, gamma: float = 5.0 / 3.0, n_ngb: fl
     return st
 
 
+def _h_from_cell_counts(counts, n_ngb, steps=(0, 1, 2, 3, 4, 6, 8, 12, 16, 24, 32)):
+    """Start values of H (in cells) from the particle counts of a periodic
+    grid: for each cell, the smallest cube of 2k + 1 cells around it that
+    holds the number of particles a sphere of N_NGB neighbours needs
+    (N_NGB * 6 / pi in the cube), with H scaled inside it as for uniform
+    density.  Cells between clumps and voids take the clump into account,
+    where the density of their own cell alone would not."""
+    n = counts.shape[0]
+    K = min(max(steps), (n - 1) // 2)
+    cs = np.pad(counts.astype(np.int64), K, mode="wrap")
+    for ax in range(3):
+        cs = cs.cumsum(axis=ax)
+    cs = np.pad(cs, ((1, 0), (1, 0), (1, 0)))
+    target = n_ngb * 6.0 / math.pi
+    H = np.full(counts.shape, np.nan)
+    C = None
+    for k in steps:
+        if k > K:
+            break
+        a0, a1 = slice(K - k, K - k + n), slice(K + k + 1, K + k + 1 + n)
+        C = (cs[a1, a1, a1] - cs[a0, a1, a1] - cs[a1, a0, a1] - cs[a1, a1, a0]
+             + cs[a0, a0, a1] + cs[a0, a1, a0] + cs[a1, a0, a0] - cs[a0, a0, a0])
+        pick = np.isnan(H) & (C >= target)
+        H[pick] = (k + 0.5) * (target / C[pick]) ** (1.0 / 3.0)
+        last = k
+    rest = np.isnan(H)
+    H[rest] = (last + 0.5) * (target / np.maximum(C[rest], 1)) ** (1.0 / 3.0)
+    return H
+
+
 def clustered(n: int = 256, seed: int = 4, gamma: float = 5.0 / 3.0, n_ngb: float = 32.0,
               sigma_ln: float = 1.5, vrms_over_cs: float = 10.0):
     """Log-normal clustered gas on an n^3 grid with N = n^3 particles in total."""
@@ -296,12 +326,29 @@ def clustered(n: int = 256, seed: int = 4, gamma: float = 5.0 / 3.0, n_ngb: floa
     ci = np.stack(np.unravel_index(cells, (n, n, n))).astype(np.float64)
     pos = (ci + rng.uniform(0.0, 1.0, size=ci.shape)) / n
     pos = np.mod(pos, 1.0)
-    # Zel'dovich-like displacement field psi(k) = i k delta(k) / k^2
+    # Zel'dovich-like displacement field psi(k) = i k delta(k) / k^2 on the
+    # grid (cell centres), interpolated trilinearly to the particles: a
+    # continuous velocity field, so neighbours in one cell do not share a
+    # velocity exactly
+    g = pos * n - 0.5
+    g0 = np.floor(g).astype(np.int64)
+    f = g - g0
     vel = []
     for K in (KX, KY, KZ):
         psik = 1j * K * dk / K2
         psik[0, 0, 0] = 0.0
-        vel.append(np.real(np.fft.ifftn(psik)).ravel()[cells])
+        field = np.real(np.fft.ifftn(psik))
+        v = np.zeros(N)
+        for cx in (0, 1):
+            wx = f[0] if cx else 1.0 - f[0]
+            ix = (g0[0] + cx) % n
+            for cy in (0, 1):
+                wy = f[1] if cy else 1.0 - f[1]
+                iy = (g0[1] + cy) % n
+                for cz in (0, 1):
+                    wz = f[2] if cz else 1.0 - f[2]
+                    v += wx * wy * wz * field[ix, iy, (g0[2] + cz) % n]
+        vel.append(v)
     vel = np.stack(vel)
     u0 = 1.0 / (gamma * (gamma - 1.0))  # sound speed 1 in code units
     vrms = np.sqrt((vel ** 2).sum(axis=0).mean())
@@ -309,8 +356,9 @@ def clustered(n: int = 256, seed: int = 4, gamma: float = 5.0 / 3.0, n_ngb: floa
     m = np.full(N, 1.0 / N)
     U = m * u0
     E = U + 0.5 * m * (vel ** 2).sum(axis=0)
-    rho_p = rho.ravel()[cells] * 1.0
-    H = (3.0 * n_ngb * m / (4.0 * math.pi * rho_p)) ** (1.0 / 3.0)
+    # start values of H from the particle counts around each cell (an
+    # initial condition carries its smoothing lengths)
+    H = _h_from_cell_counts(counts.reshape(n, n, n), n_ngb).ravel()[cells] / n
     return {"x": pos[0].copy(), "y": pos[1].copy(), "z": pos[2].copy(),
             "vx": vel[0].copy(), "vy": vel[1].copy(), "vz": vel[2].copy(),
             "m": m, "E": E, "U": U, "H": H}

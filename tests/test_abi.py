@@ -61,7 +61,7 @@ def test_default_params_are_the_papers(L):
 
 @pytest.mark.parametrize("field,value", [
     ("gamma", 1.0), ("n_ngb", 5.0), ("box", (1.0, 0.0, 1.0)), ("max_list", 5000),
-    ("max_cell_dim", 2), ("cell_margin", 0.5), ("scheme", 7), ("precision", 3), ("guess", 2),
+    ("reserved", 1), ("cell_margin", 0.5), ("scheme", 7), ("precision", 3), ("guess", 2),
     ("riemann_maxit", 0), ("h_maxit", 0), ("c_cfl", 0.0), ("alpha2", -1.0),
     ("entropy_switch", 2), ("mixed_jump", 0.5),
 ])

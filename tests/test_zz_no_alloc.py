@@ -22,7 +22,7 @@ STATE = ("x", "y", "z", "vx", "vy", "vz", "m", "E", "U")
 
 def _run(st, cfg, static):
     n = len(st["x"])
-    params = mfm.params_from_dict(cfg, max_cell_dim=32)
+    params = mfm.params_from_dict(cfg)
     ctx = mfm.Context(params, n, static=static)
     ps = mfm.ParticleSet(st)
     mfm.run_pipeline(ctx, ps, 1.0, update=False)
@@ -79,7 +79,7 @@ def test_static_context_limits():
     _need_gpu()
     L = mfm.lib()
     cap = L.mfm_static_workspace_bytes()
-    params = mfm.params_from_dict({"scheme": "mfm"}, max_cell_dim=32)
+    params = mfm.params_from_dict({"scheme": "mfm"})
     n_big = 200_000
     assert L.mfm_workspace_bytes(params, n_big) > cap
     with pytest.raises(mfm.MFMError, match="status -2"):
