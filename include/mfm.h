@@ -72,7 +72,7 @@ typedef struct mfm_params {
   int32_t h_maxit;       /* smoothing-length iteration cap (default 64) */
   int32_t riemann_maxit; /* Riemann Newton cap (default 100) */
   int32_t guess;         /* MFM_GUESS_PLAIN or MFM_GUESS_LEARNED */
-  int32_t max_list;      /* list pool, in entries per particle (default 128): the
+  int32_t max_list;      /* list pool, in entries per particle (default 160): the
                             lists of each chunk of 16 consecutive particles take
                             16 x (the chunk's longest candidate list + 1/8 + 4),
                             planned from the previous search, so a few long
@@ -190,7 +190,7 @@ int mfm_destroy(struct mfm_ctx *ctx);
  * nothing: no hipMalloc, no library allocator.  The caller still owns the
  * particle arrays.
  *   - Limit: mfm_workspace_bytes(p, n_max) must fit in the array (about
- *     15 000 particles at max_list 128); larger requests return
+ *     12 000 particles at the default max_list); larger requests return
  *     MFM_E_WORKSPACE.
  *   - One such context per GPU at a time (MFM_E_STATE while one exists;
  *     mfm_destroy releases it).  All its calls share the GPU's array, which

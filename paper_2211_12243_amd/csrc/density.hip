@@ -62,7 +62,7 @@ struct CandArgs {
 // 1.61; SLOTS 8 / LCAP 48, 1.17 + 1.62; LCAP 32, 1.39-1.42 + 1.63.  The LDS a
 // workgroup holds sets how many wavefronts a CU runs: fewer staged entries
 // per particle buy occupancy at the price of more direct stores.
-constexpr int SLOTS = 6;   // candidates per lane per round: 384 per wavefront
+constexpr int SLOTS = 4;   // candidates per lane per round: 256 per wavefront
 constexpr int TCH = LCH;   // particles per chunk: one list chunk
 static_assert(BUCKET % TCH == 0, "a bucket holds whole chunks");
 constexpr int LCAP = 48;   // list entries per particle staged in LDS (more are stored directly)
@@ -74,6 +74,15 @@ __device__ __forceinline__ double readlane_f64(double v, int l) {
   int2 r;
   r.x = __builtin_amdgcn_readlane(w.x, l);
   r.y = __builtin_amdgcn_readlane(w.y, l);
+  return *reinterpret_cast<const double *>(&r);
+}
+
+// A wave-uniform value moved to scalar registers (lane 0's copy).
+__device__ __forceinline__ double uniform_f64(double v) {
+  const int2 w = *reinterpret_cast<const int2 *>(&v);
+  int2 r;
+  r.x = __builtin_amdgcn_readfirstlane(w.x);
+  r.y = __builtin_amdgcn_readfirstlane(w.y);
   return *reinterpret_cast<const double *>(&r);
 }
 
@@ -118,14 +127,15 @@ __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) ca
       blo[2] = bhi[2] = tz;
     }
     // the chunk's box and radius
+    // (wave-uniform: held in scalar registers)
     double bc[3], bh[3];
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
       const double lo = wave_min_f64(blo[k]), hi = wave_max_f64(bhi[k]);
-      bc[k] = 0.5 * (lo + hi);
-      bh[k] = 0.5 * (hi - lo);
+      bc[k] = uniform_f64(0.5 * (lo + hi));
+      bh[k] = uniform_f64(0.5 * (hi - lo));
     }
-    const double Rc = wave_max_f64(th);
+    const double Rc = uniform_f64(wave_max_f64(th));
     // a node is opened when its box and the chunk's are closer than the
     // larger radius (raised by 1e-12 so that rounding in the box distance
     // cannot drop a pair at the edge)
@@ -176,22 +186,33 @@ __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) ca
     }
     // the accepted buckets in index order: the frontier's nodes, each
     // expanded to the buckets under it when the walk stopped early
+    // (64 at a time across the lanes; bmask holds the accepted ones of the
+    // last 64, from bbase)
     const int span = 3 * lev_stop;  // TREE_FANOUT = 2^3 nodes per level
     const int64_t nb0 = g.lev_cnt[0];
     int q = 0;
-    int64_t bk = 0, bend = 0;
-    auto next_bucket = [&]() -> int64_t {
+    int64_t bk = 0, bend = 0, bbase = 0;
+    uint64_t bmask = 0;
+    auto next_bucket = [&]() -> int {
+      if (span == 0) return q < nf ? s_f[cur][q++] : -1;  // accepted by the walk
       for (;;) {
+        if (bmask) {
+          const int t = __ffsll((unsigned long long)bmask) - 1;
+          bmask &= bmask - 1;
+          return (int)(bbase + t);
+        }
         if (bk >= bend) {
           if (q >= nf) return -1;
           const int64_t v = s_f[cur][q++];
-          if (span == 0) return v;  // accepted by the walk
           bk = v << span;
           bend = min((v + 1) << span, nb0);
           continue;
         }
-        const int64_t b = bk++;
-        if (opens(g.node + ((int64_t)g.lev_off[0] + b) * TNODE)) return b;
+        const int64_t b = bk + lane;
+        const bool ok = b < bend && opens(g.node + ((int64_t)g.lev_off[0] + b) * TNODE);
+        bmask = __ballot(ok);
+        bbase = bk;
+        bk += 64;
       }
     };
     // the accepted buckets' particles, filtered by their distance from the
@@ -201,12 +222,12 @@ __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) ca
       int nsel = 0;
       bool far = false;
       while (nsel <= 64 * (SLOTS - 1)) {
-        const int64_t bkt = next_bucket();
+        const int bkt = next_bucket();
         if (bkt < 0) {
           more = false;
           break;
         }
-        const int64_t j = bkt * BUCKET + lane;
+        const int j = bkt * BUCKET + lane;
         bool keep = false;
         if (j < n) {
           const double4 pj = a.pos[j];
@@ -228,7 +249,7 @@ __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) ca
           far = far || (keep && wrap);
         }
         const uint64_t m = __ballot(keep);
-        if (keep) s_cand[nsel + lanes_below(m)] = (int)j;
+        if (keep) s_cand[nsel + lanes_below(m)] = j;
         nsel += __popcll(m);
       }
       if (nsel == 0) break;  // wave-uniform: nothing left
@@ -499,12 +520,13 @@ __device__ __forceinline__ HSolve newton_h(const DensityArgs &a, double hcap, do
   r.h = h;
   r.h_store = h;
   if (h >= cover * (1.0 - 1e-12)) {
-    // the root lies beyond the cell side or grew by more than cell_margin
-    // since the build: this pass is redone on a grid (and candidate radii)
-    // sized from an estimate of the root (at fixed number density the
-    // neighbour number grows as H^3), written as the start value
+    // the root lies beyond half the box or grew by more than cell_margin
+    // since the build: this pass is redone with candidate radii from an
+    // estimate of the root (at fixed number density the neighbour number
+    // grows as H^3; 15% more for a density that falls outwards), written as
+    // the start value
     r.overflow = 1;
-    r.h_store = cover * cbrt(target / fmax((32.0 / 3.0) * s_last, 1.0)) * 1.05;
+    r.h_store = cover * cbrt(target / fmax((32.0 / 3.0) * s_last, 1.0)) * 1.15;
   }
   return r;
 }

@@ -207,7 +207,7 @@ void mfm_default_params(mfm_params *p) {
   p->h_maxit = 64;
   p->riemann_maxit = 100;
   p->guess = MFM_GUESS_PLAIN;
-  p->max_list = 128;
+  p->max_list = 160;
   p->gamma = 5.0 / 3.0;
   p->n_ngb = 32.0;
   p->ncond_max = 100.0;
@@ -377,10 +377,16 @@ int mfm_destroy(mfm_ctx *ctx) {
 namespace {
 
 // After a density pass some of whose H outgrew cell_margin times their value
-// at the build: those H now hold estimates of their roots (the next build's
-// radii follow them).  A second overflow in a row widens every radius too.
+// at the build: those H now hold estimates of their roots, and the next
+// build's radii follow them.  A second such pass in a row widens every
+// radius by a tenth as well; the widening outlives the step and decays by 2%
+// per accepted pass.
 void grow_margin(mfm_ctx *ctx) {
-  if (++ctx->overflow_streak >= 2) ctx->margin_boost *= 1.1;
+  if (++ctx->overflow_streak >= 2) ctx->margin_boost = fmin(ctx->margin_boost * 1.1, 2.0);
+}
+void relax_margin(mfm_ctx *ctx) {
+  ctx->overflow_streak = 0;
+  ctx->margin_boost = fmax(1.0, ctx->margin_boost * 0.98);
 }
 
 // Sort, permutation and tree build (no synchronisation).
@@ -459,8 +465,7 @@ int mfm_density(mfm_ctx *ctx, const mfm_particles *pp) {
     ctx->have_need = 0;  // new radii: the next search counts its lists first
     return fail(ctx, MFM_E_CELLS, "smoothing lengths outgrew their search radii; rebuild cells");
   }
-  ctx->margin_boost = 1.0;
-  ctx->overflow_streak = 0;
+  relax_margin(ctx);
   ctx->have_density = 1;
   ctx->have_grad = 0;
   if (c[C_PASS_NOCONV] > 0)
@@ -588,8 +593,7 @@ int mfm_step(mfm_ctx *ctx, const mfm_particles *pp, double dt_max, double *dt_ho
       }
       continue;
     }
-    ctx->margin_boost = 1.0;
-    ctx->overflow_streak = 0;
+    relax_margin(ctx);
     *dt_host = sc[1];
     if (c[C_NONFINITE] > 0) return fail(ctx, MFM_E_NONFINITE, "non-finite step or state");
     if (c[C_PASS_NOCONV] > 0)
