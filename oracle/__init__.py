@@ -172,8 +172,11 @@ def _bind(L):
     L.orc_update_src.argtypes = ([P, i64] + [_D] * 9 + [_D, ctypes.c_double, SP, _D, _D, _D, _D,
                                  C])
     L.orc_step_src.argtypes = [P, i64] + [_D] * 10 + [ctypes.c_double, SP, _D, C]
+    L.orc_rungs.argtypes = [P, i64, _D, _D, _D, _D, _D, ctypes.c_double, _I32]
+    L.orc_step_rungs.argtypes = ([P, i64] + [_D] * 10 + [ctypes.c_double, _I32, ctypes.c_int,
+                                                        _I64, C])
     for f in ("orc_fluxes_src", "orc_ekin_max", "orc_entropy_pressure", "orc_update_src",
-              "orc_step_src"):
+              "orc_step_src", "orc_rungs", "orc_step_rungs"):
         getattr(L, f).restype = ctypes.c_int
     for f in ("orc_neighbours", "orc_density", "orc_density_at", "orc_gradients", "orc_riemann",
               "orc_riemann_sample", "orc_face", "orc_fluxes", "orc_update", "orc_step"):
@@ -362,6 +365,41 @@ def step(cfg: dict, state: dict, dt_max: float):
     if rc:
         raise RuntimeError(f"orc_step failed: {rc}")
     return s, dt.value, cnt.as_dict()
+
+
+RUNG_MAX = 30
+
+
+def rungs(cfg: dict, x, y, z, H, dt_i, dt0: float):
+    """Rungs from the particles' own steps dt_i (sec. 2.3.10) with the
+    |r_i - r_j| <= 2 limiter over the flux pairs at H."""
+    p = make_params(cfg)
+    x, y, z, H, dt_i = (_f64(a) for a in (x, y, z, H, dt_i))
+    r = np.zeros(x.size, dtype=np.int32)
+    rc = lib().orc_rungs(ctypes.byref(p), x.size, _p(x), _p(y), _p(z), _p(H), _p(dt_i),
+                         float(dt0), r.ctypes.data_as(_I32))
+    if rc:
+        raise RuntimeError(f"orc_rungs failed: {rc}")
+    return r
+
+
+def step_rungs(cfg: dict, state: dict, dt0: float, rungs=None):
+    """One base step dt0 on individual steps, on a copy of ``state``; returns
+    (new_state, rungs, number of sub-steps, counters).  ``rungs`` given:
+    used as they are (no criterion, no limiter)."""
+    p = make_params(cfg)
+    s = {k: _f64(state[k]).copy() for k in STATE_KEYS}
+    n = s["x"].size
+    given = rungs is not None
+    r = np.array(rungs, dtype=np.int32) if given else np.zeros(n, dtype=np.int32)
+    nsub = ctypes.c_int64()
+    cnt = Counters()
+    rc = lib().orc_step_rungs(ctypes.byref(p), n, *[_p(s[k]) for k in STATE_KEYS], float(dt0),
+                              r.ctypes.data_as(_I32), int(given), ctypes.byref(nsub),
+                              ctypes.byref(cnt))
+    if rc:
+        raise RuntimeError(f"orc_step_rungs failed: {rc}")
+    return s, r, nsub.value, cnt.as_dict()
 
 
 def pipeline(cfg: dict, state: dict, dt_max: float):

@@ -431,9 +431,11 @@ static void density_limits(const orc_params *p, int *periodic, double *half) {
     for (int k = 0; k < 3; ++k) *half = fmin(*half, 0.5 * p->box[k]);
 }
 
-int orc_density(const orc_params *p, int64_t n, const double *x, const double *y,
-                const double *z, double *H, double *V, double *ncond, double *nngb,
-                orc_counters *cnt) {
+/* The density loop for the particles with act[i] != 0 (all when act is
+ * NULL); the others keep their H, V, ncond and nngb. */
+static int density_mask(const orc_params *p, int64_t n, const double *x, const double *y,
+                        const double *z, double *H, double *V, double *ncond, double *nngb,
+                        const uint8_t *act, orc_counters *cnt) {
   if (!p || n <= 0 || !x || !y || !z || !H || !V || !ncond || !nngb || !cnt) return -1;
   if (!(p->n_ngb > 32.0 / 3.0)) return -1; /* the self term alone would exceed N_NGB */
   int periodic;
@@ -446,7 +448,7 @@ int orc_density(const orc_params *p, int64_t n, const double *x, const double *y
   double rmax = 0.0;
   for (int64_t i = 0; i < n; ++i) {
     R[i] = fmin(2.0 * H[i], half);
-    if (R[i] > rmax) rmax = R[i];
+    if ((!act || act[i]) && R[i] > rmax) rmax = R[i];
   }
   orc_grid g;
   memset(&g, 0, sizeof(g));
@@ -454,6 +456,7 @@ int orc_density(const orc_params *p, int64_t n, const double *x, const double *y
   int64_t noconv = 0, boosts = 0, fails = 0, fallback = 0;
 #pragma omp parallel for schedule(dynamic, 64) reduction(+ : noconv, boosts, fails, fallback)
   for (int64_t i = 0; i < n; ++i) {
+    if (act && !act[i]) continue;
     dens_counts k = {0, 0, 0, 0};
     density_one(p, n, x, y, z, &g, have_grid, periodic, half, R[i], i, H[i], &H[i], &V[i],
                 &ncond[i], &nngb[i], &k);
@@ -469,6 +472,12 @@ int orc_density(const orc_params *p, int64_t n, const double *x, const double *y
   cnt->ncond_fail += fails;
   cnt->h_fallback += fallback;
   return 0;
+}
+
+int orc_density(const orc_params *p, int64_t n, const double *x, const double *y,
+                const double *z, double *H, double *V, double *ncond, double *nngb,
+                orc_counters *cnt) {
+  return density_mask(p, n, x, y, z, H, V, ncond, nngb, NULL, cnt);
 }
 
 /* The density loop for the nq particles listed in idx only (every particle
@@ -511,11 +520,14 @@ int orc_density_at(const orc_params *p, int64_t n, const double *x, const double
 /* ------------------------------------------------------------------------ */
 enum { Q_RHO = 0, Q_VX = 1, Q_VY = 2, Q_VZ = 3, Q_P = 4, NQ = 5 };
 
-int orc_gradients(const orc_params *p, int64_t n, const double *x, const double *y,
-                  const double *z, const double *H, const double *V, const double *m,
-                  const double *vx, const double *vy, const double *vz, const double *U,
-                  double *rho, double *P, double *c, double *B, double *grad, double *alpha,
-                  double *ncond, double *dt_i, orc_counters *cnt) {
+/* The gradient loop for the particles with act[i] != 0 (all when act is
+ * NULL); the primitives are set for every particle. */
+static int gradients_mask(const orc_params *p, int64_t n, const double *x, const double *y,
+                          const double *z, const double *H, const double *V, const double *m,
+                          const double *vx, const double *vy, const double *vz,
+                          const double *U, double *rho, double *P, double *c, double *B,
+                          double *grad, double *alpha, double *ncond, double *dt_i,
+                          const uint8_t *act, orc_counters *cnt) {
   if (!p || n <= 0) return -1;
   const double gam = p->gamma;
   /* Primitives: rho = m omega^-1, P = (gamma-1) U omega^-1 (sec. 2.3.7),
@@ -525,13 +537,14 @@ int orc_gradients(const orc_params *p, int64_t n, const double *x, const double 
     P[i] = (gam - 1.0) * U[i] / V[i];
     c[i] = sqrt(gam * P[i] / rho[i]);
   }
+  const double *qs[NQ] = {rho, vx, vy, vz, P};
   int64_t *start;
   int32_t *idx;
   if (build_lists(p, n, x, y, z, H, &start, &idx)) return -2;
-  const double *qs[NQ] = {rho, vx, vy, vz, P};
   int64_t pairs = 0, singular = 0;
 #pragma omp parallel for schedule(dynamic, 64) reduction(+ : pairs, singular)
   for (int64_t i = 0; i < n; ++i) {
+    if (act && !act[i]) continue;
     double e[6] = {0, 0, 0, 0, 0, 0};
     double s[NQ][3];
     double qmax[NQ], qmin[NQ];
@@ -620,6 +633,15 @@ int orc_gradients(const orc_params *p, int64_t n, const double *x, const double 
   cnt->grad_pairs += pairs;
   cnt->singular_e += singular;
   return 0;
+}
+
+int orc_gradients(const orc_params *p, int64_t n, const double *x, const double *y,
+                  const double *z, const double *H, const double *V, const double *m,
+                  const double *vx, const double *vy, const double *vz, const double *U,
+                  double *rho, double *P, double *c, double *B, double *grad, double *alpha,
+                  double *ncond, double *dt_i, orc_counters *cnt) {
+  return gradients_mask(p, n, x, y, z, H, V, m, vx, vy, vz, U, rho, P, c, B, grad, alpha, ncond,
+                        dt_i, NULL, cnt);
 }
 
 /* ------------------------------------------------------------------------ */
@@ -780,11 +802,13 @@ double orc_pair_limit(double qf, double qo, double qn, double psi1, double psi2)
   }
 }
 
-int orc_face(const orc_params *p, int64_t n, int64_t i, int64_t j, const double *x,
-             const double *y, const double *z, const double *H, const double *V,
-             const double *rho, const double *vx, const double *vy, const double *vz,
-             const double *P, const double *B, const double *grad, double dt, double *c,
-             orc_counters *cnt) {
+/* The face contribution A_ij F_ij of the pair (i, j), each side's primitives
+ * predicted over its own time ti, tj (half the step on a global step). */
+static int face_tau(const orc_params *p, int64_t n, int64_t i, int64_t j, const double *x,
+                    const double *y, const double *z, const double *H, const double *V,
+                    const double *rho, const double *vx, const double *vy, const double *vz,
+                    const double *P, const double *B, const double *grad, double ti, double tj,
+                    double *c, orc_counters *cnt) {
   const double gam = p->gamma;
   for (int k = 0; k < 5; ++k) c[k] = 0.0;
   double d[3];
@@ -824,14 +848,14 @@ int orc_face(const orc_params *p, int64_t n, int64_t i, int64_t j, const double 
   {
     double dvi = gi[Q_VX][0] + gi[Q_VY][1] + gi[Q_VZ][2];
     double dvj = gj[Q_VX][0] + gj[Q_VY][1] + gj[Q_VZ][2];
-    qpi[Q_RHO] = qi[Q_RHO] - 0.5 * dt * qi[Q_RHO] * dvi;
-    qpj[Q_RHO] = qj[Q_RHO] - 0.5 * dt * qj[Q_RHO] * dvj;
+    qpi[Q_RHO] = qi[Q_RHO] - ti * qi[Q_RHO] * dvi;
+    qpj[Q_RHO] = qj[Q_RHO] - tj * qj[Q_RHO] * dvj;
     for (int k = 0; k < 3; ++k) {
-      qpi[Q_VX + k] = qi[Q_VX + k] - 0.5 * dt * gi[Q_P][k] / qi[Q_RHO];
-      qpj[Q_VX + k] = qj[Q_VX + k] - 0.5 * dt * gj[Q_P][k] / qj[Q_RHO];
+      qpi[Q_VX + k] = qi[Q_VX + k] - ti * gi[Q_P][k] / qi[Q_RHO];
+      qpj[Q_VX + k] = qj[Q_VX + k] - tj * gj[Q_P][k] / qj[Q_RHO];
     }
-    qpi[Q_P] = qi[Q_P] - 0.5 * dt * gam * qi[Q_P] * dvi;
-    qpj[Q_P] = qj[Q_P] - 0.5 * dt * gam * qj[Q_P] * dvj;
+    qpi[Q_P] = qi[Q_P] - ti * gam * qi[Q_P] * dvi;
+    qpj[Q_P] = qj[Q_P] - tj * gam * qj[Q_P] * dvj;
   }
   /* Spatial extrapolation to the mid-point face (sec. 2.3.6), primitives. */
   double qL[NQ], qR[NQ];
@@ -909,6 +933,16 @@ int orc_face(const orc_params *p, int64_t n, int64_t i, int64_t j, const double 
   }
   for (int k = 0; k < 5; ++k) c[k] = Amag * F[k];
   return 0;
+}
+
+int orc_face(const orc_params *p, int64_t n, int64_t i, int64_t j, const double *x,
+             const double *y, const double *z, const double *H, const double *V,
+             const double *rho, const double *vx, const double *vy, const double *vz,
+             const double *P, const double *B, const double *grad, double dt, double *c,
+             orc_counters *cnt) {
+  /* a global step: both sides to the half step */
+  return face_tau(p, n, i, j, x, y, z, H, V, rho, vx, vy, vz, P, B, grad, 0.5 * dt, 0.5 * dt, c,
+                  cnt);
 }
 
 int orc_face_list(const orc_params *p, int64_t n, const double *x, const double *y,
@@ -1073,13 +1107,17 @@ static double hubble(double xt, double x0, double eta, double dt, double hn, dou
   return (xt - eta * dt * hn * x0) / (1.0 + eta * dt * hn1);
 }
 
-int orc_update_src(const orc_params *p, int64_t n, double *x, double *y, double *z, double *m,
-                   double *vx, double *vy, double *vz, double *E, double *U, const double *dQ,
-                   double dt, const orc_sources *src, const double *gwork,
-                   const double *ekin_max, const double *V, const double *H,
-                   orc_counters *cnt) {
-  if (!p || n <= 0) return -1;
-  double *pos[3] = {x, y, z};
+/* The close of the step for particle i over its step dt: the conserved
+ * update, the source terms, the pressure switch and the drift (x, v, E, U and
+ * m in place).  dQ holds its summed flux contributions at dQ[k n + i]. */
+typedef struct {
+  int64_t neg, guard;
+} close_counts;
+
+static void close_one(const orc_params *p, int64_t n, int64_t i, double *const pos[3], double *m,
+                      double *vx, double *vy, double *vz, double *E, double *U, const double *dQ,
+                      double dt, const orc_sources *src, const double *gwork,
+                      const double *ekin_max, const double *H, close_counts *cc) {
   const double gam = p->gamma;
   const double *acc = src ? src->accel : NULL;
   const double inv_a = src ? src->inv_a : 1.0;
@@ -1091,15 +1129,14 @@ int orc_update_src(const orc_params *p, int64_t n, double *x, double *y, double 
    * -3 H (gamma - 1) U and the entropy of a comoving adiabat likewise
    * (eta 3 (gamma - 1) / 2, which is 1 for gamma = 5/3) */
   const double eta_u = 1.5 * (gam - 1.0);
-  int64_t neg = 0, guard = 0;
-  for (int64_t i = 0; i < n; ++i) {
+  {
     double dm = dQ[i], dp[3] = {dQ[n + i], dQ[2 * n + i], dQ[3 * n + i]}, dE = dQ[4 * n + i];
     double v0[3] = {vx[i], vy[i], vz[i]};
     /* eq. internal_energy_integration with the start-of-step velocity (reading) */
     double v0sq = v0[0] * v0[0] + v0[1] * v0[1] + v0[2] * v0[2];
     double dU = dE - (v0[0] * dp[0] + v0[1] * dp[1] + v0[2] * dp[2]) + 0.5 * v0sq * dm;
     double m1 = m[i] + dm;
-    if (!(m1 > 0.0)) neg++; /* MFV mass depletion is counted, not clamped */
+    if (!(m1 > 0.0)) cc->neg++; /* MFV mass depletion is counted, not clamped */
     double p0[3] = {m[i] * v0[0], m[i] * v0[1], m[i] * v0[2]};
     double p1[3] = {p0[0] + dp[0], p0[1] + dp[1], p0[2] + dp[2]};
     double E1 = E[i] + dE;
@@ -1153,7 +1190,7 @@ int orc_update_src(const orc_params *p, int64_t n, double *x, double *y, double 
      * start of the step (counted), so the pressure stays positive. */
     if (!(U1 > 0.0)) {
       U1 = U[i];
-      guard++;
+      cc->guard++;
     }
     /* reading: drift with the mean of the old and new velocities (comoving:
      * dx/dt = v / a), periodic wrap */
@@ -1173,9 +1210,21 @@ int orc_update_src(const orc_params *p, int64_t n, double *x, double *y, double 
     E[i] = E1;
     U[i] = U1;
   }
+}
+
+int orc_update_src(const orc_params *p, int64_t n, double *x, double *y, double *z, double *m,
+                   double *vx, double *vy, double *vz, double *E, double *U, const double *dQ,
+                   double dt, const orc_sources *src, const double *gwork,
+                   const double *ekin_max, const double *V, const double *H,
+                   orc_counters *cnt) {
+  if (!p || n <= 0) return -1;
+  double *const pos[3] = {x, y, z};
+  close_counts cc = {0, 0};
+  for (int64_t i = 0; i < n; ++i)
+    close_one(p, n, i, pos, m, vx, vy, vz, E, U, dQ, dt, src, gwork, ekin_max, H, &cc);
   (void)V;
-  cnt->neg_mass += neg;
-  cnt->u_guard += guard;
+  cnt->neg_mass += cc.neg;
+  cnt->u_guard += cc.guard;
   return 0;
 }
 
@@ -1282,5 +1331,184 @@ int orc_step(const orc_params *p, int64_t n, double *x, double *y, double *z, do
   *dt_out = dt;
   free(V); free(nc0); free(nng); free(rho); free(P); free(c); free(B); free(grad);
   free(alpha); free(nc); free(dti); free(dQ); free(scale);
+  return rc;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Individual time steps (sec. 2.3.4, last paragraphs; sec. 2.3.10)          */
+/* ------------------------------------------------------------------------ */
+
+/* The rung of a particle whose own step is dti: the smallest r >= 0 with
+ * dti > 2^-r dt0 (sec. 2.3.10), by halving (exact in floating point);
+ * ORC_RUNG_MAX + 1 when no rung up to ORC_RUNG_MAX will do. */
+static int rung_of(double dti, double dt0) {
+  double s = dt0;
+  for (int r = 0; r <= ORC_RUNG_MAX; ++r) {
+    if (dti > s) return r;
+    s *= 0.5;
+  }
+  return ORC_RUNG_MAX + 1;
+}
+
+int orc_rungs(const orc_params *p, int64_t n, const double *x, const double *y,
+              const double *z, const double *H, const double *dt_i, double dt0, int32_t *rung) {
+  if (!p || n <= 0 || !dt_i || !rung || !(dt0 > 0.0)) return -1;
+  for (int64_t i = 0; i < n; ++i) {
+    rung[i] = rung_of(dt_i[i], dt0);
+    if (rung[i] > ORC_RUNG_MAX) return -3;
+  }
+  /* The rung limiter (sec. 2.3.10): interacting particles -- the pairs of
+   * the flux loop, r < max(H_i, H_j) -- differ by at most two rungs; the
+   * lower rung is raised, until no pair violates the bound. */
+  int64_t nf, *fa, *fb;
+  int rc = orc_face_list(p, n, x, y, z, H, &nf, &fa, &fb);
+  if (rc) return rc;
+  for (int changed = 1; changed;) {
+    changed = 0;
+    for (int64_t f = 0; f < nf; ++f) {
+      int32_t *ra = rung + fa[f], *rb = rung + fb[f];
+      if (*ra < *rb - 2) {
+        *ra = *rb - 2;
+        changed = 1;
+      }
+      if (*rb < *ra - 2) {
+        *rb = *ra - 2;
+        changed = 1;
+      }
+    }
+  }
+  free(fa);
+  free(fb);
+  return 0;
+}
+
+/* One base step dt0 on individual power-of-two steps.  reading (sec. 2.3.4,
+ * sec. 2.3.10), step by step:
+ *   - the rungs are set at the start of the base step, when every particle
+ *     is synchronised, from the CFL step (orc_rungs), and kept through it;
+ *   - the base step is cut into 2^r_max sub-steps of 2^-r_max dt0; a
+ *     particle is active at the sub-steps where its own step starts;
+ *   - at each sub-step the density and gradient loops run for the active
+ *     particles, at the positions of that time (an inactive particle at its
+ *     step-start position plus the elapsed time times its step-start
+ *     velocity); an inactive particle keeps its H, V, B and gradients, and
+ *     its state (m, v, E, U), from the start of its step;
+ *   - every face with an active end is evaluated (sec. 2.3.4, after
+ *     Springel 2010) with dt = min(dt_i, dt_j): each side's primitives are
+ *     predicted from its step start over the elapsed time plus dt / 2, and
+ *     dt A_ij F_ij goes to both particles;
+ *   - a particle whose step ends closes it (orc_update's close with its own
+ *     step and the contributions summed over it).
+ * With every rung equal this is the global step with dt = 2^-r dt0. */
+int orc_step_rungs(const orc_params *p, int64_t n, double *x, double *y, double *z, double *m,
+                   double *vx, double *vy, double *vz, double *E, double *U, double *H,
+                   double dt0, int32_t *rung, int rungs_given, int64_t *nsub_out,
+                   orc_counters *cnt) {
+  if (!p || n <= 0 || !rung || !nsub_out || !cnt || !(dt0 > 0.0)) return -1;
+  if (rungs_given)
+    for (int64_t i = 0; i < n; ++i)
+      if (rung[i] < 0 || rung[i] > ORC_RUNG_MAX) return -1;
+  size_t sz = (size_t)n * sizeof(double);
+  double *V = (double *)malloc(sz), *nc0 = (double *)malloc(sz), *nng = (double *)malloc(sz);
+  double *rho = (double *)malloc(sz), *P = (double *)malloc(sz), *c = (double *)malloc(sz);
+  double *B = (double *)malloc(6 * sz), *grad = (double *)malloc(15 * sz);
+  double *alpha = (double *)malloc(5 * sz), *nc = (double *)malloc(sz);
+  double *dti = (double *)malloc(sz), *dQ = (double *)calloc(5 * (size_t)n, sizeof(double));
+  double *xc = (double *)malloc(sz), *yc = (double *)malloc(sz), *zc = (double *)malloc(sz);
+  int64_t *s0 = (int64_t *)calloc((size_t)n, sizeof(int64_t));
+  uint8_t *act = (uint8_t *)malloc((size_t)n);
+  double *pos[3] = {x, y, z}, *cur[3] = {xc, yc, zc};
+  double *const state_pos[3] = {x, y, z};
+  int rc = orc_density(p, n, x, y, z, H, V, nc0, nng, cnt);
+  if (!rc)
+    rc = orc_gradients(p, n, x, y, z, H, V, m, vx, vy, vz, U, rho, P, c, B, grad, alpha, nc, dti,
+                       cnt);
+  if (!rc && !rungs_given) rc = orc_rungs(p, n, x, y, z, H, dti, dt0, rung);
+  int rmax = 0;
+  for (int64_t i = 0; !rc && i < n; ++i)
+    if (rung[i] > rmax) rmax = rung[i];
+  const int64_t nsub = (int64_t)1 << rmax;
+  const double delta = ldexp(dt0, -rmax);
+  close_counts cc = {0, 0};
+  for (int64_t k = 0; !rc && k < nsub; ++k) {
+    for (int64_t i = 0; i < n; ++i) act[i] = (k % ((int64_t)1 << (rmax - rung[i]))) == 0;
+    for (int q = 0; q < 3; ++q)
+      for (int64_t i = 0; i < n; ++i) {
+        const double *v = q == 0 ? vx : (q == 1 ? vy : vz);
+        double xn = pos[q][i];
+        if (!act[i]) {
+          xn += (double)(k - s0[i]) * delta * v[i];
+          const double L = p->box[q];
+          if (L > 0.0) {
+            if (xn < 0.0) xn += L;
+            if (xn >= L) xn -= L;
+          }
+        }
+        cur[q][i] = xn;
+      }
+    if (k > 0) {
+      rc = density_mask(p, n, xc, yc, zc, H, V, nc0, nng, act, cnt);
+      if (!rc)
+        rc = gradients_mask(p, n, xc, yc, zc, H, V, m, vx, vy, vz, U, rho, P, c, B, grad, alpha,
+                            nc, dti, act, cnt);
+      if (rc) break;
+    }
+    int64_t nf, *fa, *fb;
+    rc = orc_face_list(p, n, xc, yc, zc, H, &nf, &fa, &fb);
+    if (rc) break;
+    double *fc = (double *)malloc((size_t)(nf > 0 ? nf : 1) * 6 * sizeof(double));
+    int64_t iters = 0, vac = 0, npos = 0, mx = 0, used = 0;
+#pragma omp parallel for schedule(dynamic, 1024) reduction(+ : iters, vac, npos, mx, used)
+    for (int64_t f = 0; f < nf; ++f) {
+      const int64_t a = fa[f], b = fb[f];
+      fc[6 * f + 5] = 0.0;
+      if (!act[a] && !act[b]) continue;
+      const int rf = rung[a] > rung[b] ? rung[a] : rung[b];
+      const double dtf = ldexp(dt0, -rf); /* min(dt_a, dt_b) */
+      const double ta = (double)(k - s0[a]) * delta + 0.5 * dtf;
+      const double tb = (double)(k - s0[b]) * delta + 0.5 * dtf;
+      orc_counters local;
+      memset(&local, 0, sizeof(local));
+      face_tau(p, n, a, b, xc, yc, zc, H, V, rho, vx, vy, vz, P, B, grad, ta, tb, fc + 6 * f,
+               &local);
+      fc[6 * f + 5] = dtf;
+      used++;
+      iters += local.riemann_iters;
+      vac += local.vacuum;
+      npos += local.positivity;
+      mx += local.riemann_maxit;
+    }
+    /* each contribution to both ends, in face order */
+    for (int64_t f = 0; f < nf; ++f) {
+      const double dtf = fc[6 * f + 5];
+      if (dtf == 0.0) continue;
+      for (int q = 0; q < 5; ++q) {
+        const double v = dtf * fc[6 * f + q];
+        dQ[(int64_t)q * n + fa[f]] -= v;
+        dQ[(int64_t)q * n + fb[f]] += v;
+      }
+    }
+    free(fa);
+    free(fb);
+    free(fc);
+    cnt->faces += used;
+    cnt->riemann_iters += iters;
+    cnt->vacuum += vac;
+    cnt->positivity += npos;
+    cnt->riemann_maxit += mx;
+    /* the particles whose step ends now close it */
+    for (int64_t i = 0; i < n; ++i) {
+      if ((k + 1) % ((int64_t)1 << (rmax - rung[i])) != 0) continue;
+      close_one(p, n, i, state_pos, m, vx, vy, vz, E, U, dQ, ldexp(dt0, -rung[i]), NULL, NULL,
+                NULL, H, &cc);
+      for (int q = 0; q < 5; ++q) dQ[(int64_t)q * n + i] = 0.0;
+      s0[i] = k + 1;
+    }
+  }
+  cnt->neg_mass += cc.neg;
+  cnt->u_guard += cc.guard;
+  *nsub_out = rc ? 0 : nsub;
+  free(V); free(nc0); free(nng); free(rho); free(P); free(c); free(B); free(grad);
+  free(alpha); free(nc); free(dti); free(dQ); free(xc); free(yc); free(zc); free(s0); free(act);
   return rc;
 }

@@ -179,6 +179,26 @@ int orc_entropy_pressure(const orc_params *p, int64_t n, const double *m, const 
  * 2.3.7, 2.3.8, 2.3.9): hydro update, gravity source, Hubble terms, the
  * three-way pressure switch, drift (scaled by inv_a).  gwork and ekin_max
  * may be NULL; V and H are the step's volumes and support radii. */
+/* Individual time steps (sec. 2.3.4, sec. 2.3.10).  A rung r gives the step
+ * 2^-r dt0; ORC_RUNG_MAX bounds it. */
+#define ORC_RUNG_MAX 30
+
+/* The rung of each particle from its own step dt_i (the smallest r >= 0 with
+ * dt_i > 2^-r dt0), then the limiter |r_i - r_j| <= 2 over the pairs of the
+ * flux loop (the lower rung raised).  -3: a step below 2^-ORC_RUNG_MAX dt0. */
+int orc_rungs(const orc_params *p, int64_t n, const double *x, const double *y,
+              const double *z, const double *H, const double *dt_i, double dt0, int32_t *rung);
+
+/* One base step dt0 on individual steps (the reading is at the definition):
+ * the state is advanced in place like orc_step's; rung (n) receives the
+ * rungs used, or, with rungs_given, holds them (0..ORC_RUNG_MAX, no
+ * criterion or limiter applied: for tests of the sub-step scheme itself);
+ * nsub_out receives the number of sub-steps. */
+int orc_step_rungs(const orc_params *p, int64_t n, double *x, double *y, double *z, double *m,
+                   double *vx, double *vy, double *vz, double *E, double *U, double *H,
+                   double dt0, int32_t *rung, int rungs_given, int64_t *nsub_out,
+                   orc_counters *cnt);
+
 int orc_update_src(const orc_params *p, int64_t n, double *x, double *y, double *z, double *m,
                    double *vx, double *vy, double *vz, double *E, double *U, const double *dQ,
                    double dt, const orc_sources *src, const double *gwork,

@@ -11,6 +11,7 @@ import pytest
 
 import oracle
 import test_oracle_pins as pins
+import test_oracle_rungs as rungs
 import test_oracle_sources as sources
 
 
@@ -28,7 +29,7 @@ SWAP_PSI = [("qL[q] = orc_pair_limit(qL[q], qi[q], qj[q], p->psi1, p->psi2);",
              "qR[q] = orc_pair_limit(qR[q], qj[q], qi[q], p->psi2, p->psi1);")]
 SWAP_PSI_INSIDE = [("double d1 = psi1 * dq, d2 = psi2 * dq;",
                     "double d1 = psi2 * dq, d2 = psi1 * dq;")]
-NO_PREDICTOR = [("0.5 * dt * ", "0.0 * dt * ")]
+NO_PREDICTOR = [("0.5 * dt, 0.5 * dt, c,", "0.0 * dt, 0.0 * dt, c,")]
 START_FRAME = [("double vf[3] = {0.5 * (qpi[Q_VX] + qpj[Q_VX]), 0.5 * (qpi[Q_VY] + qpj[Q_VY]),",
                 "double vf[3] = {0.5 * (qi[Q_VX] + qj[Q_VX]), 0.5 * (qi[Q_VY] + qj[Q_VY]),"),
                ("0.5 * (qpi[Q_VZ] + qpj[Q_VZ])};", "0.5 * (qi[Q_VZ] + qj[Q_VZ])};")]
@@ -107,3 +108,36 @@ def test_source_at_the_kicked_state_is_caught(tmp_path):
     with oracle.use_library(_mutant(tmp_path, "kick", KICKED_SOURCE)):
         with pytest.raises(AssertionError):
             sources.test_free_fall_in_a_uniform_field()
+
+
+# individual time steps (sec. 2.3.4, sec. 2.3.10)
+FACE_DT_MAX = [("const int rf = rung[a] > rung[b] ? rung[a] : rung[b];",
+                "const int rf = rung[a] < rung[b] ? rung[a] : rung[b];")]
+NO_LIMITER = [("      if (*ra < *rb - 2) {", "      if (0) {"),
+              ("      if (*rb < *ra - 2) {", "      if (0) {")]
+RUNG_NOT_STRICT = [("    if (dti > s) return r;", "    if (dti >= s) return r;")]
+NO_DRIFT = [("xn += (double)(k - s0[i]) * delta * v[i];", "xn += 0.0;")]
+
+
+def test_face_step_of_the_larger_rung_is_caught(tmp_path):
+    with oracle.use_library(_mutant(tmp_path, "facedt", FACE_DT_MAX)):
+        with pytest.raises(AssertionError):
+            rungs.test_mixed_rungs_track_global_steps()
+
+
+def test_missing_rung_limiter_is_caught(tmp_path):
+    with oracle.use_library(_mutant(tmp_path, "nolimiter", NO_LIMITER)):
+        with pytest.raises(AssertionError):
+            rungs.test_rung_limiter_is_the_least_fixed_point()
+
+
+def test_non_strict_rung_criterion_is_caught(tmp_path):
+    with oracle.use_library(_mutant(tmp_path, "strict", RUNG_NOT_STRICT)):
+        with pytest.raises(AssertionError):
+            rungs.test_rung_is_the_smallest_power_of_two()
+
+
+def test_inactive_particles_left_behind_is_caught(tmp_path):
+    with oracle.use_library(_mutant(tmp_path, "nodrift", NO_DRIFT)):
+        with pytest.raises(AssertionError):
+            rungs.test_moving_lattice_on_random_rungs_moves_rigidly("mfm")
