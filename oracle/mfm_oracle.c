@@ -1338,6 +1338,13 @@ int orc_step(const orc_params *p, int64_t n, double *x, double *y, double *z, do
 /* Individual time steps (sec. 2.3.4, last paragraphs; sec. 2.3.10)          */
 /* ------------------------------------------------------------------------ */
 
+/* 2^-r dt0, by halving (exact in floating point). */
+static double rung_step(double dt0, int r) {
+  double s = dt0;
+  for (int k = 0; k < r; ++k) s *= 0.5;
+  return s;
+}
+
 /* The rung of a particle whose own step is dti: the smallest r >= 0 with
  * dti > 2^-r dt0 (sec. 2.3.10), by halving (exact in floating point);
  * ORC_RUNG_MAX + 1 when no rung up to ORC_RUNG_MAX will do. */
@@ -1428,7 +1435,7 @@ int orc_step_rungs(const orc_params *p, int64_t n, double *x, double *y, double 
   for (int64_t i = 0; !rc && i < n; ++i)
     if (rung[i] > rmax) rmax = rung[i];
   const int64_t nsub = (int64_t)1 << rmax;
-  const double delta = ldexp(dt0, -rmax);
+  const double delta = rung_step(dt0, rmax);
   close_counts cc = {0, 0};
   for (int64_t k = 0; !rc && k < nsub; ++k) {
     for (int64_t i = 0; i < n; ++i) act[i] = (k % ((int64_t)1 << (rmax - rung[i]))) == 0;
@@ -1464,7 +1471,7 @@ int orc_step_rungs(const orc_params *p, int64_t n, double *x, double *y, double 
       fc[6 * f + 5] = 0.0;
       if (!act[a] && !act[b]) continue;
       const int rf = rung[a] > rung[b] ? rung[a] : rung[b];
-      const double dtf = ldexp(dt0, -rf); /* min(dt_a, dt_b) */
+      const double dtf = rung_step(dt0, rf); /* min(dt_a, dt_b) */
       const double ta = (double)(k - s0[a]) * delta + 0.5 * dtf;
       const double tb = (double)(k - s0[b]) * delta + 0.5 * dtf;
       orc_counters local;
@@ -1499,7 +1506,7 @@ int orc_step_rungs(const orc_params *p, int64_t n, double *x, double *y, double 
     /* the particles whose step ends now close it */
     for (int64_t i = 0; i < n; ++i) {
       if ((k + 1) % ((int64_t)1 << (rmax - rung[i])) != 0) continue;
-      close_one(p, n, i, state_pos, m, vx, vy, vz, E, U, dQ, ldexp(dt0, -rung[i]), NULL, NULL,
+      close_one(p, n, i, state_pos, m, vx, vy, vz, E, U, dQ, rung_step(dt0, rung[i]), NULL, NULL,
                 NULL, H, &cc);
       for (int q = 0; q < 5; ++q) dQ[(int64_t)q * n + i] = 0.0;
       s0[i] = k + 1;
