@@ -275,6 +275,34 @@ int mfm_update(struct mfm_ctx *ctx, const mfm_particles *parts, const double *dt
  * the step taken.  Synchronises. */
 int mfm_step(struct mfm_ctx *ctx, const mfm_particles *parts, double dt_max, double *dt_host);
 
+/* Individual time steps (sec. 2.3.4, last paragraphs; sec. 2.3.10): one base
+ * step dt0 on a power-of-two hierarchy.
+ *   - Rungs: each particle's step is 2^-r dt0 with r the smallest integer
+ *     >= 0 such that its CFL step exceeds 2^-r dt0, raised until every pair
+ *     of the flux loop (r < max(H_i, H_j)) differs by at most two rungs; set
+ *     when the base step starts (every particle synchronised) and kept
+ *     through it.  With rungs_given, rung (device int32, n, in the input
+ *     order, permuted with the particles) holds them instead (0 ..
+ *     MFM_RUNG_MAX; no criterion, no limiter); else rung, when not NULL,
+ *     receives them (in the order of the particles after the call).
+ *   - The base step is cut into 2^max(r) sub-steps.  At each, the particles
+ *     whose step begins run the density and gradient loops, at the
+ *     positions of that time (a particle in mid-step: its step-start
+ *     position plus the elapsed time times its velocity, with its H, V, B,
+ *     gradients and state from its step start).  Every face with such an
+ *     end is solved with dt = min(dt_i, dt_j), each side predicted from its
+ *     step start over the elapsed time plus dt/2, and dt A_ij F_ij goes to
+ *     both particles; a particle whose step ends closes it (mfm_update's
+ *     close with its own step and the contributions summed over it).
+ *   - With every rung equal this is 2^r steps of mfm_step with 2^-r dt0.
+ * No source terms (mfm_set_cosmology at its defaults, no accel) and no
+ * entropy switch: MFM_E_ARG otherwise; a step that needs a rung deeper than
+ * MFM_RUNG_MAX: MFM_E_NONFINITE.  nsub_out (host, may be NULL) receives the
+ * number of sub-steps.  Synchronises once per sub-step. */
+#define MFM_RUNG_MAX 24
+int mfm_step_rungs(struct mfm_ctx *ctx, const mfm_particles *parts, double dt0, int32_t *rung,
+                   int rungs_given, int64_t *nsub_out);
+
 /* Counters accumulated since the last mfm_reset_counters, and the conserved
  * totals of the current state.  Synchronises. */
 int mfm_diagnostics(struct mfm_ctx *ctx, const mfm_particles *parts, mfm_diag *out);

@@ -107,8 +107,9 @@ _I32 = ctypes.POINTER(ctypes.c_int32)
 def lib():
     global _lib
     if _lib is None:
-        if not os.path.exists(_LIB):
-            build(force=False)
+        # (re)build when the library is missing or older than its source
+        if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+            build(force=True)
         _lib = _bind(ctypes.CDLL(_LIB))
     return _lib
 

@@ -229,6 +229,7 @@ struct Fields {
   double *x[4];
   int32_t *emode;
   int32_t *ncand;
+  int32_t *rung;  // rungs given by the caller of mfm_step_rungs (null: none)
 };
 
 __global__ void gather_k(int64_t n, Fields fs, const int32_t *__restrict__ order, double *tmp,
@@ -244,6 +245,7 @@ __global__ void gather_k(int64_t n, Fields fs, const int32_t *__restrict__ order
     if (fs.x[e]) tmp[(11 + e) * n + k] = fs.x[e][o];
   if (fs.emode) ((int32_t *)(tmp + 15 * n))[k] = fs.emode[o];
   ((int32_t *)(tmp + 15 * n))[n + k] = fs.ncand[o];
+  if (fs.rung) ((int32_t *)(tmp + 16 * n))[k] = fs.rung[o];
   if (perm) perm[k] = o;
 }
 
@@ -259,6 +261,7 @@ __global__ void writeback_k(int64_t n, Fields fs, const double *__restrict__ tmp
     if (fs.x[e]) fs.x[e][k] = tmp[(11 + e) * n + k];
   if (fs.emode) fs.emode[k] = ((const int32_t *)(tmp + 15 * n))[k];
   fs.ncand[k] = ((const int32_t *)(tmp + 15 * n))[n + k];
+  if (fs.rung) fs.rung[k] = ((const int32_t *)(tmp + 16 * n))[k];
   pos4[k] = make_double4(tmp[k], tmp[n + k], tmp[2 * n + k], tmp[9 * n + k]);
 }
 
@@ -306,10 +309,17 @@ hipError_t launch_build_cells(mfm_ctx *ctx, const mfm_particles *pp, int64_t *pe
   for (int e = 0; e < 3; ++e) fs.x[1 + e] = pp->accel ? pp->accel + (int64_t)e * n : nullptr;
   fs.emode = pp->emode;
   fs.ncand = ctx->ncand;
+  fs.rung = ctx->rung_perm;
   gather_k<<<blocks_for(n, BS), BS, 0, st>>>(n, fs, ctx->order, ctx->tmp, perm);
   writeback_k<<<blocks_for(n, BS), BS, 0, st>>>(n, fs, ctx->tmp,
                                                 reinterpret_cast<double4 *>(ctx->pos4));
   // the tree over the sorted particles
+  return launch_tree(ctx, n);
+}
+
+hipError_t launch_tree(mfm_ctx *ctx, int64_t n) {
+  hipStream_t st = ctx->stream;
+  const Tree &g = ctx->tree;
   leaf_box_k<<<g.lev_cnt[0], 64, 0, st>>>(n, reinterpret_cast<const double4 *>(ctx->pos4),
                                            g.hfac, ctx->tnode + (int64_t)g.lev_off[0] * TNODE);
   for (int l = 1; l < g.nlev; ++l)

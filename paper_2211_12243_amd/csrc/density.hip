@@ -34,6 +34,7 @@ struct CandArgs {
   const int64_t *lseg;  // list blocks of the chunks (list_at)
   int32_t *ncand;       // out: each particle's candidate count (the next plan's input)
   int count_only;       // record ncand only; write no list
+  const uint8_t *act;   // individual steps: 1 for the particles whose step begins (null: all)
   int32_t *cand;
   double *cand_r2;
   int32_t *cand_cnt;
@@ -108,6 +109,9 @@ __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) ca
   const bool no_room = a.count_only || a.counters[C_LIST_POOL] != 0;
   for (int t0 = 0; t0 < own_y; t0 += TCH) {
     const int T = min(TCH, own_y - t0);
+    // on individual steps, only chunks with a particle whose step begins
+    // need lists (wave-uniform)
+    if (a.act && !__ballot(lane < T && a.act[own_x + t0 + lane])) continue;
     const int64_t chunk = (own_x + t0) / LCH;
     const int64_t seg0 = no_room ? 0 : a.lseg[chunk];
     const int cap = no_room ? 0 : (int)((a.lseg[chunk + 1] - seg0) / LCH);
@@ -378,6 +382,7 @@ struct DensityArgs {
   float *rest_r2;
   int32_t *gl, *gl_cnt;
   const int64_t *lseg;    // list blocks of the chunks (list_at)
+  const uint8_t *act;     // individual steps: 1 for the particles whose step begins (null: all)
   double gamma, n_ngb, ncond_max, ngb_boost, h_tol;
   int h_maxit, max_boosts;
   int64_t *counters;
@@ -615,7 +620,8 @@ __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) de
   if (a.counters[C_PASS_LIST] != 0) return;
   const int64_t i0 = xcd_block(blockIdx.x, gridDim.x) * (int64_t)DT;
   const int64_t i = i0 + gt;
-  const bool valid = i < n;
+  // a particle in mid-step (individual steps) keeps its H and lists
+  const bool valid = i < n && (!a.act || a.act[i]);
   const int cnt = valid ? a.cand_cnt[i] : 0;
   const int64_t lb = valid ? list_base(a.lseg, i) : 0;
   int64_t noconv = 0, boosts = 0, fails = 0, overflow = 0;
@@ -689,7 +695,7 @@ __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) de
   // the staged lists, plane by plane: lane -> (plane kk + lane / DT, particle lane % DT)
   const int tl = lane % DT;
   const int64_t pl = i0 + tl;
-  const bool own = pl < n && s_gn[tl] >= 0;
+  const bool own = pl < n && (!a.act || a.act[pl]) && s_gn[tl] >= 0;
   const int glim = own ? s_gn[tl] : 0;
   const int rlim = own ? s_rn[tl] : 0;
   const int kmax = wave_max_i32(max(glim, rlim));
@@ -702,7 +708,7 @@ __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) de
       a.rest_r2[list_at(pb, k)] = s_f[k][tl];
     }
   }
-  if (lane < DT && pl < n) {
+  if (lane < DT && pl < n && (!a.act || a.act[pl])) {
     a.gl_cnt[pl] = own ? glim : -1;
     if (own) a.cand_cnt[pl] = rlim;
   }
@@ -720,7 +726,7 @@ __global__ void __launch_bounds__(BS) density_long_k(DensityArgs a, Tree g) {
   const int64_t n = a.n;
   if (a.counters[C_PASS_LIST] != 0) return;  // as in density_k
   int64_t noconv = 0, boosts = 0, fails = 0, overflow = 0;
-  if (i < n && a.gl_cnt[i] < 0) {
+  if (i < n && (!a.act || a.act[i]) && a.gl_cnt[i] < 0) {
     const int cnt = a.cand_cnt[i];
     const int64_t lb = list_base(a.lseg, i);
     auto at = [&](int k) { return list_at(lb, k); };
@@ -826,6 +832,7 @@ hipError_t launch_candidates(mfm_ctx *ctx, const mfm_particles *pp, bool count_o
   a.lseg = ctx->lseg;
   a.ncand = ctx->ncand;
   a.count_only = count_only ? 1 : 0;
+  a.act = ctx->rungs.rung ? ctx->rungs.act : nullptr;
   a.cand = ctx->cand;
   a.cand_r2 = ctx->cand_r2;
   a.cand_cnt = ctx->cand_cnt;
@@ -850,6 +857,7 @@ hipError_t launch_density(mfm_ctx *ctx, const mfm_particles *pp) {
   a.gl = ctx->gl;
   a.gl_cnt = ctx->gl_cnt;
   a.lseg = ctx->lseg;
+  a.act = ctx->rungs.rung ? ctx->rungs.act : nullptr;
   a.gamma = ctx->p.gamma;
   a.n_ngb = ctx->p.n_ngb;
   a.ncond_max = ctx->p.ncond_max;

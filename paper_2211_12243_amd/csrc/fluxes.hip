@@ -91,6 +91,10 @@ struct FluxArgs {
   double inv_a;
   // MFV with gravity: sum_j dm_ij (x_j - x_i) per particle (3 n; null: off)
   double *gwork;
+  // individual time steps (R.rung null: one global step): each face's step is
+  // min(dt_i, dt_j), each side predicted over its elapsed time plus half of
+  // it, positions from pos, and the flux sums are added to dQ
+  Rungs R;
 };
 
 // The work term of the exchanged mass (sec. 2.3.8): the mass dm that goes
@@ -437,7 +441,12 @@ struct FaceIn {
 
 __device__ __forceinline__ void load_side(const FluxArgs &a, int i, FaceIn<double> &s) {
   const double *r = a.rec + (int64_t)i * R_STRIDE;
-  s.x = r[R_X]; s.y = r[R_Y]; s.z = r[R_Z];
+  if (a.R.rung) {
+    const double4 p = a.pos[i];  // the position of this sub-step
+    s.x = p.x; s.y = p.y; s.z = p.z;
+  } else {
+    s.x = r[R_X]; s.y = r[R_Y]; s.z = r[R_Z];
+  }
   s.ih = r[R_IH]; s.V = r[R_V]; s.rho = r[R_RHO]; s.irho = r[R_IRHO];
   s.v[0] = r[R_VX]; s.v[1] = r[R_VY]; s.v[2] = r[R_VZ]; s.P = r[R_P];
 #pragma unroll
@@ -477,10 +486,23 @@ struct FaceState {
   int flags;
 };
 
+// On individual steps, a face's step is min(dt_L, dt_R), and each side is
+// predicted from its own step start: over its elapsed time plus half the
+// face's step.  On a global step dt and hL = hR = dt / 2 are left as given.
+template <typename T>
+__device__ __forceinline__ void face_step(const FluxArgs &a, int L, int R, double &dt, T &hL,
+                                          T &hR) {
+  if (!a.R.rung) return;
+  const int rf = max(a.R.rung[L], a.R.rung[R]);
+  dt = rung_step(a.R.dt0, rf);
+  hL = T(a.R.elapsed[L] + 0.5 * dt);
+  hR = T(a.R.elapsed[R] + 0.5 * dt);
+}
+
 // Face vector, half-step predictor, extrapolation, limiter, boost (sec. 2.3.3-2.3.6).
 template <typename T>
-__device__ void face_prepare(const FaceIn<T> &Ls, const FaceIn<T> &Rs, const FluxArgs &a, T hdt,
-                             FaceState<T> &fs) {
+__device__ void face_prepare(const FaceIn<T> &Ls, const FaceIn<T> &Rs, const FluxArgs &a, T hdtL,
+                             T hdtR, FaceState<T> &fs) {
   const Gas<T> &G = gas_of<T>(a);
   fs.skip = true;
   fs.flags = 0;
@@ -519,18 +541,18 @@ __device__ void face_prepare(const FaceIn<T> &Ls, const FaceIn<T> &Rs, const Flu
     // half-step Lagrangian predictor plus extrapolation to the mid-point face
     const T dvi = gi[3] + gi[7] + gi[11];
     const T dvj = gj[3] + gj[7] + gj[11];
-    qL[0] = qi[0] - hdt * qi[0] * dvi;
-    qR[0] = qj[0] - hdt * qj[0] * dvj;
+    qL[0] = qi[0] - hdtL * qi[0] * dvi;
+    qR[0] = qj[0] - hdtR * qj[0] * dvj;
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
-      qL[1 + k] = qi[1 + k] - hdt * gi[12 + k] * Ls.irho;
-      qR[1 + k] = qj[1 + k] - hdt * gj[12 + k] * Rs.irho;
+      qL[1 + k] = qi[1 + k] - hdtL * gi[12 + k] * Ls.irho;
+      qR[1 + k] = qj[1 + k] - hdtR * gj[12 + k] * Rs.irho;
       // the face moves with the mean of the two particles' velocities at the
       // half step, the time the fluxes stand for
       fs.vf[k] = T(0.5) * (qL[1 + k] + qR[1 + k]);
     }
-    qL[4] = qi[4] - hdt * G.gamma * qi[4] * dvi;
-    qR[4] = qj[4] - hdt * G.gamma * qj[4] * dvj;
+    qL[4] = qi[4] - hdtL * G.gamma * qi[4] * dvi;
+    qR[4] = qj[4] - hdtR * G.gamma * qj[4] * dvj;
 #pragma unroll
     for (int q = 0; q < 5; ++q) {
       qL[q] += T(0.5) * (gi[3 * q] * d[0] + gi[3 * q + 1] * d[1] + gi[3 * q + 2] * d[2]);
@@ -732,10 +754,13 @@ __global__ void __launch_bounds__(FTH) __attribute__((amdgpu_waves_per_eu(2))) f
     fs.flags = 0;
     bool defer = false;
     int Lslot = 0, Rslot = 0;
+    double dtf = dt;  // this face's step
     if (active) {
       i = b0 + p;
       Lslot = i < j ? i : j;
       Rslot = i < j ? j : i;
+      T hL = hdt, hR = hdt;
+      face_step(a, Lslot, Rslot, dtf, hL, hR);
       FaceIn<T> Ls, Rs;
       load_side(a, Lslot, Ls);
       load_side(a, Rslot, Rs);
@@ -747,7 +772,7 @@ __global__ void __launch_bounds__(FTH) __attribute__((amdgpu_waves_per_eu(2))) f
         defer = fmax(Ls.P, Rs.P) > J * fmin(Ls.P, Rs.P) ||
                 fmax(Ls.rho, Rs.rho) > J * fmin(Ls.rho, Rs.rho);
       }
-      face_prepare<T>(Ls, Rs, a, hdt, fs);
+      face_prepare<T>(Ls, Rs, a, hL, hR, fs);
       if (LEARNED || sizeof(T) == sizeof(float)) defer = defer || hand_over<T, LEARNED>(fs, a);
     }
     if (LEARNED || sizeof(T) == sizeof(float)) {
@@ -777,7 +802,9 @@ __global__ void __launch_bounds__(FTH) __attribute__((amdgpu_waves_per_eu(2))) f
       int it;
       double ps;
       face_solve<T, SCHEME, M>(fs, a, T(0), c, it, ps);
-      if (SCHEME == MFM_SCHEME_MFV && a.gwork) add_gwork(a, Lslot, Rslot, dt * c[0]);
+#pragma unroll
+      for (int q = 0; q < 5; ++q) c[q] *= dtf;
+      if (SCHEME == MFM_SCHEME_MFV && a.gwork) add_gwork(a, Lslot, Rslot, c[0]);
       const double sgn = (i < j) ? -1.0 : 1.0;  // the left (lower) side loses c
 #pragma unroll
       for (int q = 0; q < 5; ++q) c[q] *= sgn;
@@ -790,7 +817,7 @@ __global__ void __launch_bounds__(FTH) __attribute__((amdgpu_waves_per_eu(2))) f
         // the partner belongs to another block: its share goes to HBM
 #pragma unroll
         for (int q = (SCHEME == MFM_SCHEME_MFM ? 1 : 0); q < 5; ++q)
-          unsafeAtomicAdd(&a.dq_ext[(int64_t)q * n + j], -dt * c[q]);
+          unsafeAtomicAdd(&a.dq_ext[(int64_t)q * n + j], -c[q]);
       }
       {
         ++nfaces;
@@ -822,7 +849,11 @@ __global__ void __launch_bounds__(FTH) __attribute__((amdgpu_waves_per_eu(2))) f
   __syncthreads();
   for (int t = tid; t < nb; t += FTH) {
 #pragma unroll
-    for (int q = 0; q < 5; ++q) a.dQ[(int64_t)q * n + b0 + t] = dt * acc[q][t];
+    for (int q = 0; q < 5; ++q) {
+      double *d = a.dQ + (int64_t)q * n + b0 + t;
+      // individual steps: the sums of a particle's whole step accumulate
+      *d = a.R.rung ? *d + acc[q][t] : acc[q][t];
+    }
   }
   count_add(a.counters + C_FACES, nfaces);
   count_add(a.counters + C_RIEMANN_ITERS, iters_sum);
@@ -850,7 +881,12 @@ __device__ __forceinline__ void load_side64(const FluxArgs &a, int i, FaceIn<dou
     f[4 * k] = q.x; f[4 * k + 1] = q.y; f[4 * k + 2] = q.z; f[4 * k + 3] = q.w;
   }
   static_assert(F_B == 8, "B and the gradients start at the third float4 of the record");
-  s.x = a.x[i]; s.y = a.y[i]; s.z = a.z[i];
+  if (a.R.rung) {
+    const double4 p = a.pos[i];  // the position of this sub-step
+    s.x = p.x; s.y = p.y; s.z = p.z;
+  } else {
+    s.x = a.x[i]; s.y = a.y[i]; s.z = a.z[i];
+  }
   s.ih = 1.0 / a.H[i];
   s.V = a.V[i];
   s.rho = a.rho[i];
@@ -887,14 +923,17 @@ __global__ void __launch_bounds__(FTH) hard_faces_k(FluxArgs a) {
     fs.skip = true;
     fs.flags = 0;
     int L = 0, R = 0;
+    double dtf = dt;
     if (active) {
       const int2 q = a.hard_q[f];
       L = q.x;
       R = q.y;
+      double hL = hdt, hR = hdt;
+      face_step(a, L, R, dtf, hL, hR);
       FaceIn<double> Ls, Rs;
       load_side64<F32REC>(a, L, Ls);
       load_side64<F32REC>(a, R, Rs);
-      face_prepare<double>(Ls, Rs, a, hdt, fs);
+      face_prepare<double>(Ls, Rs, a, hL, hR, fs);
     }
     double p_learned = 0.0;
     if (LEARNED) {
@@ -931,10 +970,10 @@ __global__ void __launch_bounds__(FTH) hard_faces_k(FluxArgs a) {
       if (LEARNED && p_learned < 0.0) fs.flags |= F_FALLBACK;
 #pragma unroll
       for (int q = (SCHEME == MFM_SCHEME_MFM ? 1 : 0); q < 5; ++q) {
-        unsafeAtomicAdd(&a.dq_ext[(int64_t)q * n + L], -dt * c[q]);
-        unsafeAtomicAdd(&a.dq_ext[(int64_t)q * n + R], dt * c[q]);
+        unsafeAtomicAdd(&a.dq_ext[(int64_t)q * n + L], -dtf * c[q]);
+        unsafeAtomicAdd(&a.dq_ext[(int64_t)q * n + R], dtf * c[q]);
       }
-      if (SCHEME == MFM_SCHEME_MFV && a.gwork) add_gwork(a, L, R, dt * c[0]);
+      if (SCHEME == MFM_SCHEME_MFV && a.gwork) add_gwork(a, L, R, dtf * c[0]);
       ++nfaces;
       iters_sum += it;
       vac += (fs.flags & F_VACUUM) ? 1 : 0;
@@ -1078,6 +1117,7 @@ hipError_t launch_fluxes(mfm_ctx *ctx, const mfm_particles *pp, const double *dt
   a.vx = pp->vx; a.vy = pp->vy; a.vz = pp->vz; a.P = pp->P;
   a.inv_a = ctx->inv_a;
   a.gwork = (pp->accel && ctx->p.scheme == MFM_SCHEME_MFV) ? ctx->gwork : nullptr;
+  a.R = ctx->rungs;
   const bool learned = ctx->p.guess == MFM_GUESS_LEARNED;
   const bool mixed = ctx->p.precision == MFM_MIXED;
   if (learned) mlp_net_of(ctx->mlp_state, &a.net);

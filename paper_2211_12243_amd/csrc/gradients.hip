@@ -50,6 +50,7 @@ struct GradArgs {
   const double *m;  // masses, for E_kin^max
   double *ekm;      // E_kin^max = max_j m_i |v_j - v_i|^2 / 2 (null: not wanted)
   int32_t *grad_q;  // mixed path: particles whose E is redone in FP64 (grad_fix_k)
+  const uint8_t *act;  // individual steps: 1 for the particles whose step begins (null: all)
 };
 
 template <typename T>
@@ -138,7 +139,10 @@ __global__ void __launch_bounds__(BS) gradients_k(GradArgs a) {
   // every lane runs the loops below (the ring's plane bookkeeping is a
   // wavefront reduction); a lane past the end works on particle 0 and
   // writes nothing
-  const bool live = i < n;
+  // a particle in mid-step (individual steps) keeps its gradients and has no
+  // faces of its own: its faces are solved by the particles whose step begins
+  const bool live = i < n && (!a.act || a.act[i]);
+  if (i < n && !live) a.fcnt[i] = 0;
   const int64_t lb = list_base(a.lseg, live ? i : 0);
   {
     const double *gi = a.gin + (live ? i : 0) * GIN_STRIDE;
@@ -211,7 +215,7 @@ __global__ void __launch_bounds__(BS) gradients_k(GradArgs a) {
           nb.load(a.gin + (int64_t)jn * GIN_STRIDE);
           if (k + 2 < gc) jn2 = a.gl[list_at(lb, k + 2)];
         }
-        if (emit_face((int)i, j)) put_face(j);
+        if (emit_face((int)i, j) || (a.act && !a.act[j])) put_face(j);
         ++pairs;
         const double e0 = min_image(cur.x - xi, a.box[0], a.half[0]);
         const double e1 = min_image(cur.y - yi, a.box[1], a.half[1]);
@@ -281,7 +285,7 @@ __global__ void __launch_bounds__(BS) gradients_k(GradArgs a) {
           const double e2 = min_image(pj.z - zi, a.box[2], a.half[2]);
           in = e0 * e0 + e1 * e1 + e2 * e2 < hj2;
         }
-        if (in && emit_face((int)i, j)) put_face(j);
+        if (in && (emit_face((int)i, j) || (a.act && !a.act[j]))) put_face(j);
       }
       if (k % RSTEP == RSTEP - 1) store_done();
     }
@@ -600,6 +604,7 @@ hipError_t launch_gradients(mfm_ctx *ctx, const mfm_particles *pp, double dt_max
   a.m = pp->m;
   a.ekm = ctx->p.entropy_switch ? ctx->ekm : nullptr;
   a.grad_q = ctx->grad_q;
+  a.act = ctx->rungs.rung ? ctx->rungs.act : nullptr;
   if (ctx->p.precision == MFM_MIXED) {
     hipError_t e = hipMemsetAsync(ctx->counters + C_GRAD_QUEUE, 0, sizeof(int64_t), ctx->stream);
     if (e != hipSuccess) return e;

@@ -15,7 +15,8 @@ constexpr size_t ALIGN = 256;
 
 struct Layout {
   size_t code, hist, tnode, scan, lseg, lcap, scan64, ncand, order, tmp, pos4, cand, cand_r2, rest_r2,
-      cand_cnt, gl, gl_cnt, gin, fslot, fcnt, dq_ext, hard_q, rec, ekm, grad_q, gwork, red, counters,
+      cand_cnt, gl, gl_cnt, gin, fslot, fcnt, dq_ext, hard_q, rec, ekm, grad_q, rung, s0, act,
+      elapsed, gwork, red, counters,
       scalars;
   int64_t hard_cap;
   size_t total;
@@ -54,7 +55,7 @@ Layout make_layout(const mfm_params *p, int64_t n) {
   L.scan64 = take(8 * scan_len(nch + 1));
   L.ncand = take(4 * (size_t)n);
   L.order = take(4 * (size_t)n);
-  L.tmp = take(8 * 16 * (size_t)n);
+  L.tmp = take(8 * 17 * (size_t)n);
   L.pos4 = take(32 * (size_t)n);
   L.cand = take(4 * list_len(p->max_list, n));
   L.cand_r2 = take(8 * list_len(p->max_list, n));
@@ -72,6 +73,10 @@ Layout make_layout(const mfm_params *p, int64_t n) {
   L.rec = take(8 * (size_t)R_STRIDE * (size_t)n);
   L.ekm = take(8 * (size_t)n);
   L.grad_q = take(4 * (size_t)n);
+  L.rung = take(4 * (size_t)n);
+  L.s0 = take(4 * (size_t)n);
+  L.act = take((size_t)n);
+  L.elapsed = take(8 * (size_t)n);
   L.gwork = take(8 * 3 * (size_t)n);
   L.red = take(8 * 5 * 1024);
   L.counters = take(8 * NCOUNTERS);
@@ -274,6 +279,12 @@ int init_ctx(mfm_ctx *ctx, const mfm_params *p, int64_t n_max, void *workspace,
   ctx->rec = (double *)(ctx->ws + L.rec);
   ctx->ekm = (double *)(ctx->ws + L.ekm);
   ctx->grad_q = (int32_t *)(ctx->ws + L.grad_q);
+  ctx->rung_w = (int32_t *)(ctx->ws + L.rung);
+  ctx->s0_w = (int32_t *)(ctx->ws + L.s0);
+  ctx->act_w = (uint8_t *)(ctx->ws + L.act);
+  ctx->elapsed_w = (double *)(ctx->ws + L.elapsed);
+  memset(&ctx->rungs, 0, sizeof(ctx->rungs));
+  ctx->rung_perm = nullptr;
   ctx->gwork = (double *)(ctx->ws + L.gwork);
   ctx->inv_a = 1.0;
   ctx->hubble_n = ctx->hubble_np1 = 0.0;
@@ -601,6 +612,171 @@ int mfm_step(mfm_ctx *ctx, const mfm_particles *pp, double dt_max, double *dt_ho
     return MFM_OK;
   }
   return fail(ctx, MFM_E_CELLS, "smoothing lengths kept outgrowing their search radii");
+}
+
+}  // extern "C"
+
+namespace {
+
+// The device scalars the sub-step loop reads back: the counters and rmax.
+int read_step_counters(mfm_ctx *ctx, int64_t *c) {
+  HIPCHK(ctx, hipMemcpyAsync(c, ctx->counters, sizeof(int64_t) * NCOUNTERS,
+                             hipMemcpyDeviceToHost, ctx->stream),
+         "read counters");
+  HIPCHK(ctx, hipStreamSynchronize(ctx->stream), "synchronise");
+  return MFM_OK;
+}
+
+// After a rejected density pass: which retry, or the error.
+int on_skip(mfm_ctx *ctx, const int64_t *c) {
+  if (c[C_PASS_LIST] > 0 && c[C_LIST_POOL])
+    return fail(ctx, MFM_E_LIST, "neighbour lists exceed the list pool (raise max_list)");
+  if (c[C_CELL_OVERFLOW] > 0) {
+    grow_margin(ctx);
+    ctx->have_need = 0;
+  }
+  return MFM_OK;
+}
+
+// Leave the individual-step mode whatever happened.
+struct RungsOff {
+  mfm_ctx *ctx;
+  ~RungsOff() {
+    memset(&ctx->rungs, 0, sizeof(ctx->rungs));
+    ctx->rung_perm = nullptr;
+    ctx->have_cells = ctx->have_density = ctx->have_grad = 0;
+  }
+};
+
+}  // namespace
+
+extern "C" {
+
+int mfm_step_rungs(mfm_ctx *ctx, const mfm_particles *pp, double dt0, int32_t *rung_io,
+                   int rungs_given, int64_t *nsub_out) {
+  if (!ctx) return MFM_E_ARG;
+  if (nsub_out) *nsub_out = 0;
+  if (!check_parts(ctx, pp) || !(dt0 > 0.0) || !isfinite(dt0) || (rungs_given && !rung_io))
+    return fail(ctx, MFM_E_ARG, "invalid arguments");
+  if (pp->accel || ctx->inv_a != 1.0 || ctx->hubble_n != 0.0 || ctx->hubble_np1 != 0.0 ||
+      ctx->p.entropy_switch)
+    return fail(ctx, MFM_E_ARG, "individual steps take no source terms and no entropy switch");
+  if (ctx->p.guess == MFM_GUESS_LEARNED && !ctx->mlp_state)
+    return fail(ctx, MFM_E_STATE, "learned guess requested but no network attached");
+  RungsOff off{ctx};
+  memset(&ctx->rungs, 0, sizeof(ctx->rungs));
+  ctx->rung_perm = rungs_given ? rung_io : nullptr;
+  const int64_t n = pp->n;
+  double *dt_dev = ctx->scalars + 1;
+  int32_t *rmax_dev = reinterpret_cast<int32_t *>(ctx->scalars + 8);
+  int64_t c[NCOUNTERS];
+  // the base step starts with every particle synchronised: the order, the
+  // density and gradient loops of all of them (as mfm_step's first stages)
+  bool ok = false;
+  for (int attempt = 0; attempt < 6 && !ok; ++attempt) {
+    HIPCHK(ctx, hipMemsetAsync(ctx->counters + C_NONFINITE, 0, sizeof(int64_t), ctx->stream),
+           "clear step counters");
+    int rc = build_cells_async(ctx, pp, nullptr);
+    if (!rc) rc = density_async(ctx, pp);
+    if (rc) return rc;
+    int ev = stage_begin(ctx, 3);
+    HIPCHK(ctx, launch_gradients(ctx, pp, dt0, dt_dev), "gradients");
+    stage_end(ctx, ev);
+    rc = read_step_counters(ctx, c);
+    if (rc) return rc;
+    if (c[C_STEP_SKIP]) {
+      rc = on_skip(ctx, c);
+      if (rc) return rc;
+      continue;
+    }
+    ok = true;
+  }
+  if (!ok) return fail(ctx, MFM_E_CELLS, "smoothing lengths kept outgrowing their search radii");
+  relax_margin(ctx);
+  // rungs: from the CFL steps, with the limiter swept to its fixed point
+  // over the faces of the pass above (every particle active), or given
+  int32_t *rung = rungs_given ? rung_io : ctx->rung_w;
+  ctx->rungs.rung = rung;
+  HIPCHK(ctx, hipMemsetAsync(ctx->counters + C_RUNG_CHANGED, 0, 2 * sizeof(int64_t), ctx->stream),
+         "clear rung counters");
+  if (!rungs_given) {
+    HIPCHK(ctx, launch_rungs_from_dt(ctx, pp, dt0), "rungs");
+    for (int sweep = 0;; ++sweep) {
+      HIPCHK(ctx, hipMemsetAsync(ctx->counters + C_RUNG_CHANGED, 0, sizeof(int64_t), ctx->stream),
+             "clear the limiter flag");
+      HIPCHK(ctx, launch_rung_limiter(ctx, pp), "rung limiter");
+      int rc = read_step_counters(ctx, c);
+      if (rc) return rc;
+      if (c[C_RUNG_CHANGED] == 0) break;
+      if (sweep > 4 * MFM_RUNG_MAX) return fail(ctx, MFM_E_HIP, "rung limiter did not settle");
+    }
+    if (c[C_RUNG_DEEP] > 0)
+      return fail(ctx, MFM_E_NONFINITE, "a step needs a rung beyond MFM_RUNG_MAX");
+  } else {
+    HIPCHK(ctx, launch_rung_check(ctx, n), "check the rungs");
+    int rc = read_step_counters(ctx, c);
+    if (rc) return rc;
+    if (c[C_RUNG_DEEP] > 0) return fail(ctx, MFM_E_ARG, "a given rung is out of range");
+  }
+  HIPCHK(ctx, launch_rmax(ctx, n, rmax_dev), "deepest rung");
+  int32_t rmax = 0;
+  HIPCHK(ctx, hipMemcpyAsync(&rmax, rmax_dev, sizeof(rmax), hipMemcpyDeviceToHost, ctx->stream),
+         "read the deepest rung");
+  HIPCHK(ctx, hipStreamSynchronize(ctx->stream), "synchronise");
+  if (rmax < 0 || rmax > MFM_RUNG_MAX) return fail(ctx, MFM_E_ARG, "rung out of range");
+  const int64_t nsub = (int64_t)1 << rmax;
+  ctx->rungs.s0 = ctx->s0_w;
+  ctx->rungs.act = ctx->act_w;
+  ctx->rungs.elapsed = ctx->elapsed_w;
+  ctx->rungs.dt0 = dt0;
+  ctx->rungs.rmax = rmax;
+  HIPCHK(ctx, hipMemsetAsync(ctx->s0_w, 0, sizeof(int32_t) * n, ctx->stream), "clear step starts");
+  HIPCHK(ctx, hipMemsetAsync(pp->dQ, 0, sizeof(double) * 5 * n, ctx->stream), "clear flux sums");
+  for (int64_t k = 0; k < nsub; ++k) {
+    ctx->rungs.k = k;
+    ok = false;
+    for (int attempt = 0; attempt < 6 && !ok; ++attempt) {
+      HIPCHK(ctx, launch_substep_begin(ctx, pp), "sub-step start");
+      if (k > 0) {
+        // the particles whose step begins: tree at this sub-step's positions,
+        // search, density and gradient loops
+        int rc = setup_tree(ctx, n);
+        if (rc) return rc;
+        int ev = stage_begin(ctx, 0);
+        HIPCHK(ctx, launch_tree(ctx, n), "tree");
+        stage_end(ctx, ev);
+        rc = density_async(ctx, pp);
+        if (rc) return rc;
+        ev = stage_begin(ctx, 3);
+        HIPCHK(ctx, launch_gradients(ctx, pp, dt0, dt_dev), "gradients");
+        stage_end(ctx, ev);
+      }
+      HIPCHK(ctx, launch_fluxes(ctx, pp, dt_dev), "fluxes");
+      int ev = stage_begin(ctx, 5);
+      HIPCHK(ctx, launch_update(ctx, pp, dt_dev), "close");
+      stage_end(ctx, ev);
+      int rc = read_step_counters(ctx, c);
+      if (rc) return rc;
+      if (k > 0 && c[C_STEP_SKIP]) {
+        rc = on_skip(ctx, c);
+        if (rc) return rc;
+        continue;
+      }
+      ok = true;
+    }
+    if (!ok) return fail(ctx, MFM_E_CELLS, "smoothing lengths kept outgrowing their search radii");
+    if (k > 0) relax_margin(ctx);
+    if (c[C_NONFINITE] > 0) return fail(ctx, MFM_E_NONFINITE, "non-finite step or state");
+    if (c[C_PASS_NOCONV] > 0)
+      return fail(ctx, MFM_E_H_NOCONV, "smoothing-length solve did not converge");
+  }
+  if (!rungs_given && rung_io)
+    HIPCHK(ctx, hipMemcpyAsync(rung_io, ctx->rung_w, sizeof(int32_t) * n,
+                               hipMemcpyDeviceToDevice, ctx->stream),
+           "copy the rungs out");
+  HIPCHK(ctx, hipStreamSynchronize(ctx->stream), "synchronise");
+  if (nsub_out) *nsub_out = nsub;
+  return MFM_OK;
 }
 
 int mfm_diagnostics(mfm_ctx *ctx, const mfm_particles *pp, mfm_diag *out) {

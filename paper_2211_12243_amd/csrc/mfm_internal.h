@@ -44,6 +44,8 @@ enum {
   C_HARD_QUEUE,     // faces queued for the flux loop's FP64 pass in the current call
   C_LIST_POOL,      // the planned list blocks exceed the list pool (set by each plan)
   C_GRAD_QUEUE,     // mixed path: particles queued for the gradient loop's FP64 redo
+  C_RUNG_CHANGED,   // the rung limiter raised some rung in its last sweep
+  C_RUNG_DEEP,      // particles whose step needs a rung beyond MFM_RUNG_MAX
   NCOUNTERS = 32
 };
 
@@ -104,6 +106,24 @@ constexpr int SORT_BS = RADIX;   // threads per sort workgroup (one per digit)
 constexpr int SORT_ITEMS = 16;   // items per thread
 constexpr int SORT_TILE = SORT_BS * SORT_ITEMS;
 
+// Individual time steps (sec. 2.3.4, sec. 2.3.10), passed by value to the
+// kernels of a sub-step.  rung == null: one global step (every particle
+// active, the step from the dt argument).
+struct Rungs {
+  const int32_t *rung;     // each particle's rung: its step is 2^-rung dt0
+  int32_t *s0;             // the sub-step at which its current step began
+  const uint8_t *act;      // 1 where its step begins at this sub-step
+  const double *elapsed;   // (k - s0) times the sub-step: time since its step began
+  double dt0;              // the base step
+  int rmax;                // the deepest rung: 2^rmax sub-steps
+  int64_t k;               // this sub-step
+};
+// 2^-r dt, by halving (exact)
+__host__ __device__ __forceinline__ double rung_step(double dt, int r) {
+  for (int k = 0; k < r; ++k) dt *= 0.5;
+  return dt;
+}
+
 // Geometry of the box and the tree, passed by value to kernels.
 struct Tree {
   double box[3];      // periodic sides
@@ -129,7 +149,7 @@ struct mfm_ctx {
   double *tnode;       // the bucket tree, TNODE doubles per node
   int32_t *scan_tmp;   // block sums of the scans
   int32_t *order;      // n: input slot of each sorted slot
-  double *tmp;         // 16 n doubles: gather buffer of the permutation (its front
+  double *tmp;         // 17 n doubles: gather buffer of the permutation (its front
                        // doubles as the sort's second key and value buffers)
   double *pos4;        // 4 n: (x, y, z, H at the build) per particle
   int64_t *lseg;       // list_chunks(n) + 1: each chunk's first pool entry (list_at)
@@ -156,6 +176,13 @@ struct mfm_ctx {
   double *rec;         // R_STRIDE * n packed flux records
   double *ekm;         // n: E_kin^max of the entropy switch (gradient loop)
   int32_t *grad_q;     // n: particles queued for the mixed gradient loop's FP64 redo
+  // individual time steps (mfm_step_rungs)
+  int32_t *rung_w;     // n: rungs
+  int32_t *s0_w;       // n: sub-step at which each particle's step began
+  uint8_t *act_w;      // n: active flags of the current sub-step
+  double *elapsed_w;   // n: time since each particle's step began
+  Rungs rungs;         // rungs.rung == null outside mfm_step_rungs
+  int32_t *rung_perm;  // the caller's given rungs, permuted by the build (null: none)
   double *gwork;       // 3 n: sum_j dm_ij (x_j - x_i) (flux loop, MFV with gravity)
   // comoving integration (mfm_set_cosmology)
   double inv_a, hubble_n, hubble_np1;
@@ -293,6 +320,16 @@ hipError_t launch_gradients(mfm_ctx *ctx, const mfm_particles *pp, double dt_max
 // its FP64 second pass as stage 7.
 hipError_t launch_fluxes(mfm_ctx *ctx, const mfm_particles *pp, const double *dt_dev);
 hipError_t launch_update(mfm_ctx *ctx, const mfm_particles *pp, const double *dt_dev);
+// The bucket tree over the particles' current positions (pos4), in the
+// current order.
+hipError_t launch_tree(mfm_ctx *ctx, int64_t n);
+// Individual time steps: rungs from dt_i (or given), one limiter sweep over
+// the face lists, the active set and predicted positions of sub-step k.
+hipError_t launch_rungs_from_dt(mfm_ctx *ctx, const mfm_particles *pp, double dt0);
+hipError_t launch_rung_limiter(mfm_ctx *ctx, const mfm_particles *pp);
+hipError_t launch_rmax(mfm_ctx *ctx, int64_t n, int32_t *rmax_dev);
+hipError_t launch_rung_check(mfm_ctx *ctx, int64_t n);  // given rungs: out of range -> C_RUNG_DEEP
+hipError_t launch_substep_begin(mfm_ctx *ctx, const mfm_particles *pp);
 hipError_t launch_conserved(mfm_ctx *ctx, const mfm_particles *pp);
 
 // device pointers of a network state (mlp translation unit); net_out is an mlp::Net

@@ -23,6 +23,11 @@ struct UpdateArgs {
   int32_t *emode;       // out: 1 where the next density pass takes P from S
   double inv_a, hubble_n, hubble_np1, eta_u;
   int64_t *counters;
+  // individual time steps (R.rung null: every particle closes a global step):
+  // only the particles whose step ends at this sub-step close it, with their
+  // own step and the sums of its contributions, which are then cleared
+  Rungs R;
+  double *dQw;
 };
 
 // X^{n+1} = (X~ - eta dt H^n X^n) / (1 + eta dt H^{n+1}) (sec. 2.3.9)
@@ -35,9 +40,17 @@ __global__ void __launch_bounds__(BS) update_k(UpdateArgs a) {
   if (a.counters[C_STEP_SKIP]) return;  // the density pass was rejected
   const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   int64_t neg = 0, bad = 0, guard = 0;
-  if (i < a.n) {
+  bool close = i < a.n;
+  double dt = 0.0;
+  if (close && a.R.rung) {
+    const int r = a.R.rung[i];
+    close = (a.R.k + 1) % ((int64_t)1 << (a.R.rmax - r)) == 0;
+    dt = rung_step(a.R.dt0, r);
+  } else if (close) {
+    dt = a.dt[0];
+  }
+  if (close) {
     const int64_t n = a.n;
-    const double dt = a.dt[0];
     const double dm = a.dQ[i], dpx = a.dQ[n + i], dpy = a.dQ[2 * n + i],
                  dpz = a.dQ[3 * n + i], dE = a.dQ[4 * n + i];
     const double v0x = a.vx[i], v0y = a.vy[i], v0z = a.vz[i], m0 = a.m[i];
@@ -115,6 +128,11 @@ __global__ void __launch_bounds__(BS) update_k(UpdateArgs a) {
     a.vz[i] = v1z;
     a.E[i] = E1;
     a.U[i] = U1;
+    if (a.R.rung) {
+#pragma unroll
+      for (int q = 0; q < 5; ++q) a.dQw[q * n + i] = 0.0;
+      a.R.s0[i] = (int32_t)(a.R.k + 1);
+    }
   }
   count_add(a.counters + C_NEG_MASS, neg);
   count_add(a.counters + C_NONFINITE, bad);
@@ -185,6 +203,8 @@ hipError_t launch_update(mfm_ctx *ctx, const mfm_particles *pp, const double *dt
   a.hubble_np1 = ctx->hubble_np1;
   a.eta_u = 1.5 * (ctx->p.gamma - 1.0);
   a.counters = ctx->counters;
+  a.R = ctx->rungs;
+  a.dQw = pp->dQ;
   update_k<<<blocks_for(pp->n, BS), BS, 0, ctx->stream>>>(a);
   return hipGetLastError();
 }

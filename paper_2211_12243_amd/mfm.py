@@ -103,6 +103,8 @@ def lib():
         L.mfm_fluxes.argtypes = [C, PP, _PTR]
         L.mfm_update.argtypes = [C, PP, _PTR]
         L.mfm_step.argtypes = [C, PP, ctypes.c_double, ctypes.POINTER(ctypes.c_double)]
+        L.mfm_step_rungs.argtypes = [C, PP, ctypes.c_double, _PTR, ctypes.c_int,
+                                     ctypes.POINTER(ctypes.c_int64)]
         L.mfm_diagnostics.argtypes = [C, PP, ctypes.POINTER(mfm_diag)]
         L.mfm_reset_counters.argtypes = [C]
         L.mfm_enable_timing.argtypes = [C, ctypes.c_int]
@@ -142,7 +144,7 @@ def lib():
 EXPORTED = ("mfm_default_params", "mfm_workspace_bytes", "mfm_create", "mfm_destroy",
             "mfm_create_static", "mfm_static_workspace_bytes", "mfm_set_cosmology",
             "mfm_build_cells", "mfm_density", "mfm_gradients", "mfm_fluxes", "mfm_update",
-            "mfm_step", "mfm_diagnostics", "mfm_reset_counters", "mfm_enable_timing",
+            "mfm_step", "mfm_step_rungs", "mfm_diagnostics", "mfm_reset_counters", "mfm_enable_timing",
             "mfm_kernel_times", "mfm_strerror", "mfm_last_error", "mfm_mlp_state_bytes",
             "mfm_mlp_param_count", "mfm_mlp_init", "mfm_mlp_backward", "mfm_mlp_adam",
             "mfm_mlp_train_step",
@@ -200,6 +202,7 @@ class ParticleSet:
         optional (3, n) external acceleration."""
         n = int(len(state["x"]))
         self.n = n
+        self.device = device
         f64 = dict(dtype=torch.float64, device=device)
         self.t = {k: torch.as_tensor(state[k], **f64).contiguous().clone() for k in _STATE}
         for k in _DERIVED + ("dt_i",):
@@ -310,6 +313,30 @@ def mfm_step(ctx: Context, ps: ParticleSet, dt_max: float) -> float:
     dt = ctypes.c_double()
     _check(lib().mfm_step(ctx.h, ctypes.byref(ps.s), float(dt_max), ctypes.byref(dt)), ctx.h)
     return dt.value
+
+
+RUNG_MAX = 24
+
+
+def mfm_step_rungs(ctx: Context, ps: ParticleSet, dt0: float, rungs=None):
+    """One base step dt0 on individual time steps.  ``rungs`` (torch int32 on
+    the device, in the particles' current order) given: used as they are
+    (and permuted with the particles).  Returns (number of sub-steps, rungs
+    in the particles' order after the call)."""
+    import torch
+
+    given = rungs is not None
+    if given:
+        if rungs.dtype != torch.int32 or not rungs.is_cuda or rungs.numel() != ps.n:
+            raise MFMError("rungs must be a device int32 tensor of one entry per particle")
+        r = rungs.contiguous()
+    else:
+        r = torch.zeros(ps.n, dtype=torch.int32, device=ps.device)
+    nsub = ctypes.c_int64()
+    _check(lib().mfm_step_rungs(ctx.h, ctypes.byref(ps.s), float(dt0),
+                                ctypes.c_void_p(r.data_ptr()), int(given), ctypes.byref(nsub)),
+           ctx.h)
+    return nsub.value, r
 
 
 def mfm_diagnostics(ctx: Context, ps: ParticleSet | None = None) -> dict:

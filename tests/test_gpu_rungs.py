@@ -1,0 +1,164 @@
+"""GPU individual time steps (mfm_step_rungs) against the oracle's
+(oracle.step_rungs), sec. 2.3.4 and sec. 2.3.10.
+
+* Equal rungs: one base step is the same as 2^r global steps (mfm_step with
+  2^-r dt0), to 1e-13 (velocities against the sound speed).
+* Rungs from the CFL steps with the limiter (128^3 Sedov-like blast at 16^3,
+  MFM and MFV): the rungs equal the oracle's exactly, the state after the
+  base step within 1e-12 (FP64), the face count exact; mass, momentum and
+  energy conserved to roundoff.
+* Rungs given at random on a moving lattice: rigid motion, and the oracle's
+  face count (each face once per step of its smaller-step end).
+* Source terms are refused.
+"""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+pytestmark = pytest.mark.gpu
+
+import oracle  # noqa: E402
+from gpu_helpers import _need_gpu  # noqa: E402
+from paper_2211_12243_amd import mfm  # noqa: E402
+from paper_2211_12243_amd import workloads as W  # noqa: E402
+
+KEYS = ("x", "y", "z", "vx", "vy", "vz", "m", "E", "U", "H")
+
+
+def _by_id(ps, keys=KEYS):
+    ids = ps["id"].cpu().numpy()
+    out = {}
+    for k in keys:
+        t = ps[k].cpu().numpy()
+        a = np.empty_like(t)
+        a[ids] = t
+        out[k] = a
+    return out
+
+
+def _compare(got, ref, tol, box=1.0):
+    worst = 0.0
+    for k in KEYS:
+        d = np.abs(got[k] - ref[k])
+        if k in ("x", "y", "z"):
+            err = np.minimum(d, box - d).max()
+        else:
+            err = d.max() / max(np.abs(ref[k]).max(), 1e-300)
+        worst = max(worst, err)
+        assert err <= tol, (k, err)
+    return worst
+
+
+def _dt_min(cfg, st):
+    d, _ = oracle.density(cfg, st["x"], st["y"], st["z"], st["H"])
+    g, _ = oracle.gradients(cfg, st["x"], st["y"], st["z"], d["H"], d["V"], st["m"], st["vx"],
+                            st["vy"], st["vz"], st["U"])
+    return g["dt_i"].min()
+
+
+def test_equal_rungs_are_global_steps():
+    _need_gpu()
+    N = 16
+    st = W.soundwave(N, nyz=8, A=1e-3, gamma=5.0 / 3.0)
+    cfg = {"scheme": "mfv", "gamma": 5.0 / 3.0, "box": W.soundwave_box(N, 8)}
+    dt0 = 3.5 * _dt_min(cfg, st)
+    n = st["x"].size
+    a = mfm.Context(mfm.params_from_dict(cfg), n)
+    pa = mfm.ParticleSet(st)
+    print("[rungs] equal rungs", flush=True)
+    nsub, r = mfm.mfm_step_rungs(a, pa, dt0)
+    assert nsub == 4 and bool((r == 2).all())
+    b = mfm.Context(mfm.params_from_dict(cfg), n)
+    pb = mfm.ParticleSet(st)
+    for _ in range(4):
+        assert mfm.mfm_step(b, pb, dt0 / 4) == dt0 / 4
+    torch.cuda.synchronize()
+    box = W.soundwave_box(N, 8)
+    got, ref = _by_id(pa), _by_id(pb)
+    for k in KEYS:
+        d = np.abs(got[k] - ref[k])
+        if k in ("x", "y", "z"):
+            L = box["xyz".index(k)]
+            d = np.minimum(d, L - d)
+            assert d.max() <= 1e-13 * L, k
+        else:
+            # the velocities are of the wave's amplitude: against the sound speed
+            scale = max(np.abs(ref[k]).max(), 1.0 if k in ("vx", "vy", "vz") else 0.0)
+            assert d.max() <= 1e-13 * scale, k
+    a.close()
+    b.close()
+
+
+@pytest.mark.parametrize("scheme", ["mfm", "mfv"])
+def test_rungs_match_the_oracle(scheme):
+    _need_gpu()
+    st = W.sedov(n=16, seed=3)
+    cfg = {"scheme": scheme}
+    dt0 = 8.3 * _dt_min(cfg, st)
+    ref, r_ref, nsub_ref, cnt = oracle.step_rungs(cfg, st, dt0)
+    n = st["x"].size
+    ctx = mfm.Context(mfm.params_from_dict(cfg), n)
+    ps = mfm.ParticleSet(st)
+    d0 = mfm.mfm_diagnostics(ctx, ps)
+    mfm.mfm_reset_counters(ctx)
+    print(f"[rungs] sedov16 {scheme}: {nsub_ref} sub-steps", flush=True)
+    nsub, r = mfm.mfm_step_rungs(ctx, ps, dt0)
+    torch.cuda.synchronize()
+    diag = mfm.mfm_diagnostics(ctx, ps)
+    ids = ps["id"].cpu().numpy()
+    rung = np.empty(n, dtype=np.int32)
+    rung[ids] = r.cpu().numpy()
+    assert nsub == nsub_ref
+    assert np.array_equal(rung, r_ref)
+    assert len(np.unique(rung)) >= 4
+    worst = _compare(_by_id(ps), ref, 1e-12)
+    print(f"[rungs] worst {worst:.2e}, faces {diag['faces']} (oracle {cnt['faces']})", flush=True)
+    assert diag["faces"] == cnt["faces"]
+    pscale = float((st["m"] * (np.abs(ref["vx"]) + np.abs(ref["vy"]) + np.abs(ref["vz"]))).sum())
+    assert abs(diag["mass"] - d0["mass"]) <= 1e-14 * d0["mass"]
+    for k in ("px", "py", "pz"):
+        assert abs(diag[k] - d0[k]) <= 1e-13 * pscale, k
+    assert abs(diag["energy"] - d0["energy"]) <= 1e-13 * d0["energy"]
+    ctx.close()
+
+
+def test_given_rungs_on_a_moving_lattice():
+    _need_gpu()
+    v0 = (0.3, -0.1, 0.2)
+    st = W.uniform(n=8, jitter=0.0, v0=v0)
+    cfg = {"scheme": "mfm"}
+    d, _ = oracle.density(cfg, st["x"], st["y"], st["z"], st["H"])
+    st["H"] = d["H"]
+    r = np.random.default_rng(2).integers(0, 3, st["x"].size).astype(np.int32)
+    ref, _, nsub_ref, cnt = oracle.step_rungs(cfg, st, 0.05, rungs=r)
+    ctx = mfm.Context(mfm.params_from_dict(cfg), st["x"].size)
+    ps = mfm.ParticleSet(st)
+    mfm.mfm_reset_counters(ctx)
+    print("[rungs] moving lattice", flush=True)
+    nsub, _ = mfm.mfm_step_rungs(ctx, ps, 0.05, rungs=torch.as_tensor(r, device="cuda"))
+    torch.cuda.synchronize()
+    diag = mfm.mfm_diagnostics(ctx)
+    got = _by_id(ps)
+    assert nsub == nsub_ref == 4
+    for k, v in zip(("vx", "vy", "vz"), v0):
+        assert np.abs(got[k] - v).max() < 1e-13, k
+    _compare(got, ref, 1e-12)
+    assert diag["faces"] == cnt["faces"]
+    ctx.close()
+
+
+def test_sources_and_bad_rungs_are_refused():
+    _need_gpu()
+    st = W.sod(n=8, seed=1)
+    n = st["x"].size
+    ctx = mfm.Context(mfm.params_from_dict({"scheme": "mfm"}), n)
+    ps = mfm.ParticleSet(st)
+    mfm.mfm_set_cosmology(ctx, 0.5, 0.0, 0.0)
+    with pytest.raises(mfm.MFMError, match="status -1"):
+        mfm.mfm_step_rungs(ctx, ps, 1e-3)
+    mfm.mfm_set_cosmology(ctx, 1.0, 0.0, 0.0)
+    bad = torch.full((n,), mfm.RUNG_MAX + 1, dtype=torch.int32, device="cuda")
+    with pytest.raises(mfm.MFMError, match="status -1"):
+        mfm.mfm_step_rungs(ctx, ps, 1e-3, rungs=bad)
+    ctx.close()
