@@ -83,6 +83,8 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--clustered", type=int, default=256,
                     help="particles per axis of the clustered-gas leg (0: skip it)")
+    ap.add_argument("--rung-base", type=int, default=32,
+                    help="individual-step leg: base step in units of the global step (0: skip)")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="first copy a buffer of this many MiB on the device (a kernel of "
                          "known traffic, to calibrate hardware byte counters)")
@@ -395,6 +397,48 @@ def run_variant(args, st, variant, mlp_state, log_):
     return res
 
 
+def run_rungs(args, st, ms_global, log_):
+    """The same set on individual time steps (FP64): after the warm-up, one
+    base step of rung_base global steps' length (the global step of the last
+    warm-up step), against the global steps that cover the same time."""
+    import torch
+
+    from paper_2211_12243_amd import mfm
+
+    params = mfm.params_from_dict({"scheme": args.scheme}, precision="fp64")
+    ctx = mfm.Context(params, len(st["x"]))
+    ps = mfm.ParticleSet(st, ids=False)
+    dt = 0.0
+    for _ in range(args.warmup):
+        dt = mfm.mfm_step(ctx, ps, 1.0)
+    dt0 = args.rung_base * dt
+    mfm.mfm_reset_counters(ctx)
+    mfm.mfm_enable_timing(ctx, True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    nsub, r = mfm.mfm_step_rungs(ctx, ps, dt0)
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3
+    times = mfm.mfm_kernel_times(ctx)
+    diag = mfm.mfm_diagnostics(ctx, ps)
+    counts = torch.bincount(r.long()).cpu().tolist()
+    ctx.close()
+    res = {
+        "variant": "fp64",
+        "base_step": dt0,
+        "base_step_in_global_steps": args.rung_base,
+        "sub_steps": nsub,
+        "ms_per_base_step": ms,
+        "global_ms_same_time": ms_global * args.rung_base,
+        "speedup": ms_global * args.rung_base / ms,
+        "particles_per_rung": counts,
+        "faces": diag["faces"],
+        "stage_ms": {k: v[0] for k, v in times.items()},
+    }
+    log_(f"[bench] rungs: {res}")
+    return res
+
+
 def run_clustered(args, log_):
     """The clustered gas (log-normal density, sigma_ln = 1.5; smoothing lengths
     spread over a factor of about 30): mixed MFM, the first step from the
@@ -498,6 +542,8 @@ def main():
     if "mixed_learned" in variants:
         mlp_state, train_info = train_guess(args, log_)
     res = {v: run_variant(args, st, v, mlp_state, log_) for v in variants}
+    rungs = (run_rungs(args, st, res["fp64"]["ms_per_step"], log_)
+             if args.rung_base > 0 and "fp64" in res else None)
     clustered = run_clustered(args, log_) if args.clustered > 0 else None
     h = res[args.headline]
     out = {
@@ -523,6 +569,7 @@ def main():
                      for v, r in res.items()},
         "pairs_per_step": h["pairs_per_step"],
         "guess_training": train_info,
+        "individual_steps": rungs,
         "clustered": clustered,
     }
     if not args.no_cpu_baseline:

@@ -9,6 +9,9 @@
   energy conserved to roundoff.
 * Rungs given at random on a moving lattice: rigid motion, and the oracle's
   face count (each face once per step of its smaller-step end).
+* The 128^3 Sedov blast after five global steps, one base step of 32 of
+  them: the rung limiter and criterion hold on the oracle's pairs and CFL
+  steps of the base-step start, and M, P, E are conserved.
 * Source terms are refused.
 """
 import numpy as np
@@ -162,3 +165,59 @@ def test_sources_and_bad_rungs_are_refused():
     with pytest.raises(mfm.MFMError, match="status -1"):
         mfm.mfm_step_rungs(ctx, ps, 1e-3, rungs=bad)
     ctx.close()
+
+
+def test_full_size_base_step_properties():
+    """The 128^3 Sedov blast (the benchmark set) after five global steps, one
+    base step of 32 of them on individual steps: every flux pair of the
+    base-step start within two rungs, every rung the particle's own CFL rung
+    or raised by the limiter to two below a neighbour's, mass, momentum and
+    energy conserved to roundoff."""
+    _need_gpu()
+    st = W.sedov(n=128, seed=3)
+    n = st["x"].size
+    cfg = {"scheme": "mfm"}
+    ctx = mfm.Context(mfm.params_from_dict(cfg), n)
+    ps = mfm.ParticleSet(st)
+    dt = 0.0
+    for _ in range(5):
+        dt = mfm.mfm_step(ctx, ps, 1.0)
+    torch.cuda.synchronize()
+    start = _by_id(ps)
+    d0 = mfm.mfm_diagnostics(ctx, ps)
+    print("[rungs] 128^3: base step of 32 global steps", flush=True)
+    nsub, r = mfm.mfm_step_rungs(ctx, ps, 32 * dt)
+    torch.cuda.synchronize()
+    d1 = mfm.mfm_diagnostics(ctx, ps)
+    ids = ps["id"].cpu().numpy()
+    rung = np.empty(n, dtype=np.int32)
+    rung[ids] = r.cpu().numpy()
+    ctx.close()
+    print(f"[rungs] {nsub} sub-steps, rungs {np.bincount(rung)}", flush=True)
+    assert nsub == 2 ** rung.max() and rung.max() >= 3
+    # the pairs and CFL steps of the base-step start, from the oracle
+    dd, _ = oracle.density(cfg, start["x"], start["y"], start["z"], start["H"])
+    g, _ = oracle.gradients(cfg, start["x"], start["y"], start["z"], dd["H"], dd["V"],
+                            start["m"], start["vx"], start["vy"], start["vz"], start["U"])
+    fa, fb = oracle.fluxes_face_list(cfg, start["x"], start["y"], start["z"], dd["H"])
+    assert np.all(np.abs(rung[fa] - rung[fb]) <= 2)
+    dt0 = 32 * dt
+    own = np.zeros(n, dtype=np.int64)
+    s = np.full(n, dt0)
+    left = ~(g["dt_i"] > s)
+    while left.any():
+        own[left] += 1
+        s[left] *= 0.5
+        left = ~(g["dt_i"] > s)
+    nb_max = np.zeros(n, dtype=np.int64)
+    np.maximum.at(nb_max, fa, rung[fb])
+    np.maximum.at(nb_max, fb, rung[fa])
+    raised = rung != own
+    assert np.all(rung >= own)
+    assert np.all(rung[raised] == nb_max[raised] - 2)
+    pscale = float((start["m"] * (np.abs(start["vx"]) + np.abs(start["vy"]) +
+                                  np.abs(start["vz"]))).sum())
+    assert abs(d1["mass"] - d0["mass"]) <= 1e-14 * d0["mass"]
+    for k in ("px", "py", "pz"):
+        assert abs(d1[k] - d0[k]) <= 1e-13 * pscale, k
+    assert abs(d1["energy"] - d0["energy"]) <= 1e-13 * d0["energy"]
