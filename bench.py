@@ -48,7 +48,7 @@ sys.path.insert(0, ROOT)
 # flops per face of the flux loop, mean over a 20000-face sample of the first
 # step of the 128^3 Sedov set (Newton iterations included), and flops per
 # ordered pair of the gradient loop (limiter and time step included).
-FLOPS_PER_FACE = {"mfm": 458.29, "mfv": 545.29}
+FLOPS_PER_FACE = {"mfm": 450.29, "mfv": 537.29}
 FLOPS_PER_GRAD_PAIR = 151.0
 # Algorithmic HBM bytes per particle: the fields a loop must read and write
 # once (FP64 path):
@@ -79,7 +79,9 @@ def parse():
     ap.add_argument("--headline", default="fp64", choices=VARIANTS,
                     help="variant whose rate is the reported value")
     ap.add_argument("--scheme", default="mfm", choices=["mfm", "mfv"])
-    ap.add_argument("--train-steps", type=int, default=800)
+    ap.add_argument("--train-steps", type=int, default=6000)
+    ap.add_argument("--train-records", type=float, default=1e7,
+                    help="size of the guess network's record set (gated faces all kept)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--clustered", type=int, default=256,
                     help="particles per axis of the clustered-gas leg (0: skip it)")
@@ -255,67 +257,71 @@ def step1_fields(args, st, variant):
     return out
 
 
-def train_guess(args, log_):
-    """Train the guess network on faces the plain mixed solver dumps from
-    other sets than the timed one (Sedov 64^3 with another seed, after two
-    steps, and the 64^3 Kelvin-Helmholtz layers); returns (state, info)."""
-    import numpy as np
+def train_guess(args, c4, log_):
+    """The guess network's training set and training.  Face records dumped by
+    the plain solver from the shear layers (64^3, 10 steps per scheme), a
+    Sedov blast of the benchmark's recipe with another seed (20 steps after
+    two warm-up steps) and the clustered gas (one step): the faces that pass
+    the guess gate (all of them, or a uniform sample of half the set's share
+    where there are more) and a uniform sample of the others, about a third
+    of --train-records per set.  Split 90/10 (seeded); the network trains on
+    the gated records of the 90%.  Also: a network trained without the Sedov
+    records, scored on them (leave one set out).  Returns (state, info)."""
     import torch
 
-    from paper_2211_12243_amd import mfm
+    from paper_2211_12243_amd import learned, mfm
     from paper_2211_12243_amd import workloads as W
 
     t0 = time.perf_counter()
-    parts = []
-    for name, st, skip in (("sedov64", W.sedov(n=64, seed=17), 2), ("kh64", W.kh(n=64, seed=2), 0)):
-        params = mfm.params_from_dict({"scheme": args.scheme}, precision="mixed")
-        ctx = mfm.Context(params, len(st["x"]))
+    sets = [("kh64_mfv_fp64", lambda: W.kh(n=64, seed=2), "mfv", "fp64", 0, 10),
+            ("kh64_mfm_mixed", lambda: W.kh(n=64, seed=2), "mfm", "mixed", 0, 10),
+            (f"sedov{args.n}_mfm_mixed", lambda: W.sedov(n=args.n, seed=17), "mfm", "mixed",
+             2, 20),
+            ("clustered_mfm_mixed", lambda: c4, "mfm", "mixed", 0, 1)]
+    per_set = args.train_records / 3.0
+    rows, info_sets = {}, {}
+    for k, (name, make, scheme, precision, skip, steps) in enumerate(sets):
+        st = make()
+        n = len(st["x"])
+        share = per_set / (2 if name.startswith("kh64") else 1)
+        rate = min(1.0, 0.5 * share / (14.5 * n * steps))
+        ctx = mfm.Context(mfm.params_from_dict({"scheme": scheme}, precision=precision), n)
         ps = mfm.ParticleSet(st, ids=False)
         for _ in range(skip):
             mfm.mfm_step(ctx, ps, 1.0)
-        rec = torch.empty((4_000_000, mfm.DUMP_STRIDE), dtype=torch.float32, device="cuda")
-        mfm.mfm_face_dump(ctx, rec)
-        mfm.mfm_step(ctx, ps, 1.0)
-        cnt = mfm.mfm_face_dump_count(ctx)
-        mfm.mfm_face_dump(ctx, None)
-        sel = rec[:cnt][mfm.guess_gate(rec[:cnt])]
-        parts.append(sel)
-        log_(f"[bench] dumped {cnt} faces from {name}, {sel.shape[0]} pass the guess gate")
+        col = learned.Collector(ctx, 24 * n, rate, seed=100 + k,
+                                gated_budget=int(0.5 * share / steps))
+        for _ in range(steps):
+            col.step(ps)
+        rows[name] = col.rows()
+        info_sets[name] = {"particles": n, "steps": steps, "faces": col.faces,
+                           "gated": col.gated, "kept": int(rows[name].shape[0]),
+                           "truncated": col.truncated}
+        log_(f"[bench] guess records from {name}: {info_sets[name]}")
+        del col, ps
         ctx.close()
-    rows = torch.cat(parts)
-    r = rows[:, :7].double()
-    mean, std = r.mean(0).cpu().numpy(), r.std(0).cpu().numpy()
-    norm = np.zeros(16, dtype=np.float32)
-    norm[:6], norm[6:12] = mean[:6], np.maximum(std[:6], 1e-6)
-    norm[12], norm[13] = mean[6], max(std[6], 1e-6)
-    rng = np.random.default_rng(0)
-    p0 = np.zeros(mfm.mfm_mlp_param_count(), dtype=np.float32)
-    lay = mfm.mlp_param_layout()
-    for name, (off, shp) in lay.items():
-        if name.startswith("W") or name == "w4":
-            fan = 6 if name == "W1" else 64
-            w = rng.normal(0, np.sqrt((1.0 if name == "w4" else 2.0) / fan), shp)
-            if name == "W1":
-                w[6:] = 0.0
-            p0[off:off + w.size] = w.ravel()
-    stt = mfm.MLPState(p0, norm)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
-    g = torch.Generator(device="cuda").manual_seed(0)
-    n = rows.shape[0]
-    losses = []
-    for it in range(args.train_steps):
-        lr = 3e-3 if it < 0.7 * args.train_steps else 1e-3
-        idx = torch.randint(0, n, (16384,), device="cuda", generator=g)
-        want = it in (0, args.train_steps - 1)
-        loss = mfm.mfm_mlp_train_step(stt, rows[idx], lr, want_loss=want)
-        if want:
-            losses.append(loss)
+    parts = {name: learned.split(r, 0.9, seed=7) for name, r in rows.items()}
+    train_rows = torch.cat([p[0] for p in parts.values()])
+    test_rows = {name: p[1] for name, p in parts.items()}
+    stt, losses = learned.train(train_rows, args.train_steps, batch=16384, lr=3e-3, seed=0)
     torch.cuda.synchronize()
     t2 = time.perf_counter()
-    info = {"faces": int(n), "dump_s": t1 - t0, "train_s": t2 - t1, "steps": args.train_steps,
-            "batch": 16384, "loss_first": losses[0], "loss_last": losses[-1]}
+    held_out = {name: learned.rms_error(stt, r) for name, r in test_rows.items()}
+    sedov = sets[2][0]
+    loo_train = torch.cat([p[0] for name, p in parts.items() if name != sedov])
+    loo, _ = learned.train(loo_train, args.train_steps, batch=16384, lr=3e-3, seed=0)
+    info = {"records": int(sum(r.shape[0] for r in rows.values())),
+            "train_records": int(train_rows.shape[0]),
+            "train_gated": int(learned.usable(train_rows).sum()),
+            "sets": info_sets, "dump_s": t1 - t0, "train_s": t2 - t1,
+            "steps": args.train_steps, "batch": 16384,
+            "loss_first": losses[0], "loss_last": losses[-1],
+            "held_out_rms_ln_pstar": held_out,
+            "leave_out_sedov_rms_ln_pstar": learned.rms_error(loo, test_rows[sedov])}
     log_(f"[bench] trained guess network: {info}")
+    del rows, parts, train_rows, test_rows, loo_train
     return stt, info
 
 
@@ -346,6 +352,21 @@ def run_variant(args, st, variant, mlp_state, log_):
     times = mfm.mfm_kernel_times(ctx)
     diag = mfm.mfm_diagnostics(ctx, ps)
     diag["n"] = ps.n
+    newton = None
+    if precision == "mixed":
+        # one more step with every face dumped: Newton steps per face (mean,
+        # 99th percentile), over all faces and over those the guess gate picks
+        from paper_2211_12243_amd import learned
+
+        mfm.mfm_reset_counters(ctx)
+        col = learned.Collector(ctx, 24 * ps.n, None, seed=0)
+        col.step(ps)
+        newton = learned.iteration_stats(col.rows())
+        d1 = mfm.mfm_diagnostics(ctx)
+        newton["guess_fallbacks"] = d1["guess_fallback"]
+        newton["guess_fallback_rate"] = (d1["guess_fallback"] / newton["gated"]
+                                         if guess and newton["gated"] else 0.0)
+        del col
     ctx.close()
     K = args.steps
     t_grad = times["gradients"][0] / 1e3
@@ -385,6 +406,7 @@ def run_variant(args, st, variant, mlp_state, log_):
         "newton_iters_per_face": diag["riemann_iters"] / max(diag["faces"], 1),
         "fp64_pass_faces_frac": diag["hard_faces"] / max(diag["faces"], 1),
         "guess_fallback_frac": diag["guess_fallback"] / max(diag["faces"], 1),
+        "newton_after": newton,
         "roofline": {"bound": "alu", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
                      "frac": achieved / peak, "traffic": flux_traffic(variant),
                      "kernel": "fluxes_k", "mean_launch_ms": t_main * 1e3,
@@ -439,7 +461,47 @@ def run_rungs(args, st, ms_global, log_):
     return res
 
 
-def run_clustered(args, log_):
+def guess_pair(st, scheme, precision, mlp_state, log_, name):
+    """One step with the plain and one with the learned guess, both from the
+    state st: the flux loop's time (a step without the face dump, whose
+    per-face record counter would be timed with it), then, from st again,
+    Newton steps per face (mean and 99th percentile, all faces and gated
+    faces) and fallbacks of a step with every face dumped."""
+    import torch
+
+    from paper_2211_12243_amd import learned, mfm
+
+    out = {}
+    n = len(st["x"])
+    for guess in (0, 1):
+        params = mfm.params_from_dict({"scheme": scheme, "guess": guess}, precision=precision)
+        ctx = mfm.Context(params, n)
+        if guess:
+            mfm.mfm_mlp_attach(ctx, mlp_state)
+        ps = mfm.ParticleSet(st, ids=False)
+        mfm.mfm_enable_timing(ctx, True)
+        mfm.mfm_step(ctx, ps, 1.0)
+        torch.cuda.synchronize()
+        times = mfm.mfm_kernel_times(ctx)
+        mfm.mfm_enable_timing(ctx, False)
+        del ps
+        ps = mfm.ParticleSet(st, ids=False)
+        mfm.mfm_reset_counters(ctx)
+        col = learned.Collector(ctx, 24 * n, None, seed=0)
+        col.step(ps)
+        d = mfm.mfm_diagnostics(ctx)
+        r = learned.iteration_stats(col.rows())
+        r.update({"flux_ms": times["fluxes"][0], "flux_kernel_ms": times["flux_kernel"][0],
+                  "flux_hard_ms": times["flux_hard"][0], "hard_faces": d["hard_faces"],
+                  "guess_fallbacks": d["guess_fallback"]})
+        out["learned" if guess else "plain"] = r
+        del col, ps
+        ctx.close()
+    log_(f"[bench] {name} {precision} plain vs learned guess: {out}")
+    return out
+
+
+def run_clustered(args, st, log_, mlp_state=None):
     """The clustered gas (log-normal density, sigma_ln = 1.5; smoothing lengths
     spread over a factor of about 30): mixed MFM, the first step from the
     initial state (it counts the neighbour lists before planning them) and
@@ -447,16 +509,10 @@ def run_clustered(args, log_):
     import torch
 
     from paper_2211_12243_amd import mfm
-    from paper_2211_12243_amd import workloads as W
 
-    t = time.perf_counter()
-    st = W.clustered(n=args.clustered, seed=4)
     n = st["x"].size
-    log_(f"[bench] clustered n={args.clustered}^3 ({n} particles) made in "
-         f"{time.perf_counter() - t:.1f}s")
     ctx = mfm.Context(mfm.params_from_dict({"scheme": "mfm"}, precision="mixed"), n)
     ps = mfm.ParticleSet(st, ids=False)
-    del st
     mfm.mfm_enable_timing(ctx, True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -478,7 +534,12 @@ def run_clustered(args, log_):
     diag = mfm.mfm_diagnostics(ctx, ps)
     H = ps["H"]
     spread = float((H.max() / H.min()).item())
+    now = ps.host(["x", "y", "z", "vx", "vy", "vz", "m", "E", "U", "H"]) if mlp_state else None
+    del ps
     ctx.close()
+    pair = ({p: guess_pair(now, "mfm", p, mlp_state, log_, "clustered") for p in ("mixed", "fp64")}
+            if mlp_state else None)
+    del now
     t_pairs = (times["gradients"][0] + times["fluxes"][0]) / 1e3
     res = {
         "workload": f"clustered gas {args.clustered}^3 (log-normal, sigma_ln 1.5, vrms 10 c_s), "
@@ -495,6 +556,7 @@ def run_clustered(args, log_):
         "list_retries": diag["list_overflow"],
         "h_spread": spread,
         "vacuum_faces_per_step": diag["vacuum"] / K,
+        "guess": pair,
     }
     log_(f"[bench] clustered: {res}")
     return res
@@ -538,13 +600,21 @@ def main():
     st = W.sedov(n=args.n, seed=3)
     N = len(st["x"])
     log_(f"[bench] sedov n={args.n}^3 ({N} particles) made in {time.perf_counter() - t:.1f}s")
+    c4 = None
+    if args.clustered > 0 or "mixed_learned" in variants:
+        t = time.perf_counter()
+        nc = args.clustered if args.clustered > 0 else 64
+        c4 = W.clustered(n=nc, seed=4)
+        log_(f"[bench] clustered n={nc}^3 ({c4['x'].size} particles) made in "
+             f"{time.perf_counter() - t:.1f}s")
     mlp_state, train_info = (None, None)
     if "mixed_learned" in variants:
-        mlp_state, train_info = train_guess(args, log_)
+        mlp_state, train_info = train_guess(args, c4, log_)
     res = {v: run_variant(args, st, v, mlp_state, log_) for v in variants}
     rungs = (run_rungs(args, st, res["fp64"]["ms_per_step"], log_)
              if args.rung_base > 0 and "fp64" in res else None)
-    clustered = run_clustered(args, log_) if args.clustered > 0 else None
+    clustered = run_clustered(args, c4, log_, mlp_state) if args.clustered > 0 else None
+    del c4
     h = res[args.headline]
     out = {
         "metric": "pair interactions/s (grad+flux) & hydro-step ms, 2.1M Sedov, mixed vs FP64",
@@ -565,7 +635,8 @@ def main():
         "roofline": h["roofline"],
         "variants": {v: {k: r[k] for k in ("value", "ms_per_step", "stage_ms_per_step",
                                            "newton_iters_per_face", "fp64_pass_faces_frac",
-                                           "guess_fallback_frac", "kernels")}
+                                           "guess_fallback_frac", "newton_after",
+                                           "kernels")}
                      for v, r in res.items()},
         "pairs_per_step": h["pairs_per_step"],
         "guess_training": train_info,

@@ -325,10 +325,13 @@ const char *mfm_last_error(struct mfm_ctx *ctx);
  * Learned starting value of the exact Riemann iteration (sec. 2.3.3 uses the
  * exact solver; the guess only changes how many Newton steps it takes).
  *
- * The network maps six dimensionless features of a face's left and right
- * states in the face frame -- ln(rho_L/rho_R), ln(P_L/P_R),
- * slog((u_R-u_L)/c_avg), slog(u_L/c_L), slog(u_R/c_R), ln(c_L/c_R) with
- * slog(v) = sign(v) ln(1+|v|) -- to y = ln(p* / P_avg), P_avg = (P_L+P_R)/2.
+ * The network maps six features of a face's Riemann problem (left and right
+ * states in the face frame) -- ln(rho_L/rho_R), ln(P_L/P_R),
+ * slog((u_R-u_L)/c_avg) with slog(v) = sign(v) ln(1+|v|), ln(p0/P_avg) with
+ * P_avg = (P_L+P_R)/2, and 1/0 indicators of p0 being the two-rarefaction or
+ * the two-shock estimate -- to y = ln(p* / p0), the error of the plain
+ * starting value p0 (Toro's adaptive choice: the primitive-variable,
+ * two-rarefaction or two-shock estimate, floored at 1e-10 P_avg).
  * Architecture: 6 -> 64 -> 64 -> 64 -> 1, SiLU hidden activations, BF16
  * operands with FP32 accumulation on the matrix cores.  The FP32 parameter
  * vector (mfm_mlp_param_count floats) is, in order: W1 [16][64] (row k is
@@ -340,7 +343,7 @@ const char *mfm_last_error(struct mfm_ctx *ctx);
  * norm[14..15] are unused.
  *
  * In the flux loop (params.guess = MFM_GUESS_LEARNED), the Newton iteration
- * starts from the prediction P_avg e^y when that is finite and above the
+ * starts from the prediction p0 e^y when that is finite and above the
  * pressure floor; if its second residual exceeds its first, or it needs more
  * than 8 steps, the face is solved again from the plain guess and
  * guess_fallback counts it (riemann_iters counts the steps of both tries).
@@ -376,7 +379,7 @@ int mfm_mlp_adam(void *state_dev, float lr, int step, void *stream);
 int mfm_mlp_train_step(void *state_dev, const float *rows_dev, int64_t n, int64_t stride,
                        float lr, int step, float *loss_host, void *stream);
 
-/* y_dev[r] = predicted ln(p* / P_avg) for n rows laid out as in
+/* y_dev[r] = predicted ln(p* / p0) for n rows laid out as in
  * mfm_mlp_backward (the target column is not read). */
 int mfm_mlp_predict(const void *state_dev, const float *rows_dev, int64_t n, int64_t stride,
                     float *y_dev, void *stream);
@@ -393,8 +396,8 @@ int mfm_mlp_attach(struct mfm_ctx *ctx, const void *state_dev);
 
 /* Training data: while armed, every face the flux loop solves appends one
  * record of 8 floats to records_dev -- the six features, the target
- * ln(p* / P_avg) of the converged solution, and the number of Newton steps the
- * plain guess needed -- until capacity records are stored (further faces are
+ * ln(p* / p0) of the converged solution (p0: the plain starting value), and
+ * the number of Newton steps the face's solve took -- until capacity records are stored (further faces are
  * counted but not written).  Records are in no particular order.  Arming
  * (records_dev non-null) or disarming (null) resets the count.  Synchronises. */
 int mfm_face_dump(struct mfm_ctx *ctx, float *records_dev, int64_t capacity);

@@ -157,6 +157,8 @@ def _bind(L):
     L.orc_riemann.argtypes = [ctypes.c_double] * 8 + [ctypes.c_int, _D, _D,
                                                         ctypes.POINTER(ctypes.c_int)]
     L.orc_riemann_sample.argtypes = [ctypes.c_double] * 10 + [_D, _D, _D]
+    L.orc_riemann_guess.argtypes = [ctypes.c_double] * 7 + [ctypes.POINTER(ctypes.c_int)]
+    L.orc_riemann_guess.restype = ctypes.c_double
     L.orc_face_list_copy.argtypes = [P, i64, _D, _D, _D, _D, i64, _I64, _I64, _I64]
     L.orc_face_list_copy.restype = ctypes.c_int
     L.orc_pair_limit.restype = ctypes.c_double
@@ -273,6 +275,17 @@ def riemann(gamma, rhoL, uL, PL, rhoR, uR, PR, tol=1e-10, maxit=100):
                            float(uR), float(PR), float(tol), int(maxit), ctypes.byref(ps),
                            ctypes.byref(us), ctypes.byref(it))
     return st, ps.value, us.value, it.value
+
+
+def riemann_guess(gamma, rhoL, uL, PL, rhoR, uR, PR, with_branch=False):
+    """Starting value of the exact solver's Newton iteration (Toro's adaptive
+    choice, floored at 1e-10 of the mean pressure); with_branch: also the
+    estimate it came from (0 primitive-variable, 1 two-rarefaction, 2
+    two-shock)."""
+    b = ctypes.c_int()
+    p0 = lib().orc_riemann_guess(*(float(v) for v in (gamma, rhoL, uL, PL, rhoR, uR, PR)),
+                                 ctypes.byref(b))
+    return (p0, b.value) if with_branch else p0
 
 
 def riemann_sample(gamma, rhoL, uL, PL, rhoR, uR, PR, ps, us, xi):

@@ -665,6 +665,43 @@ static void pressure_fn(double gam, double p, double rhoK, double pK, double cK,
   }
 }
 
+/* reading: Toro's adaptive starting value of the Newton iteration
+ * (primitive-variable guess when the states are close, two-rarefaction or
+ * two-shock otherwise), floored at 1e-10 of the mean pressure */
+static double riemann_guess(double gam, double rhoL, double PL, double cL, double rhoR,
+                            double PR, double cR, double du, double floor_p, int *branch) {
+  double pmin = fmin(PL, PR), pmax = fmax(PL, PR);
+  double ppv = 0.5 * (PL + PR) - 0.125 * du * (rhoL + rhoR) * (cL + cR);
+  if (ppv < 0.0) ppv = 0.0;
+  double p0;
+  if (pmax / pmin <= 2.0 && pmin <= ppv && ppv <= pmax) {
+    p0 = ppv;
+    *branch = 0;
+  } else if (ppv < pmin) {
+    *branch = 1;
+    double zz = (gam - 1.0) / (2.0 * gam);
+    double num = cL + cR - 0.5 * (gam - 1.0) * du;
+    double den = cL / pow(PL, zz) + cR / pow(PR, zz);
+    p0 = pow(num / den, 1.0 / zz);
+  } else {
+    double gL = sqrt(2.0 / ((gam + 1.0) * rhoL) / ((gam - 1.0) / (gam + 1.0) * PL + ppv));
+    double gR = sqrt(2.0 / ((gam + 1.0) * rhoR) / ((gam - 1.0) / (gam + 1.0) * PR + ppv));
+    p0 = (gL * PL + gR * PR - du) / (gL + gR);
+    *branch = 2;
+  }
+  if (!(p0 > floor_p)) p0 = floor_p;
+  return p0;
+}
+
+double orc_riemann_guess(double gam, double rhoL, double uL, double PL, double rhoR, double uR,
+                         double PR, int *branch) {
+  double cL = sqrt(gam * PL / rhoL), cR = sqrt(gam * PR / rhoR);
+  int b;
+  double p0 = riemann_guess(gam, rhoL, PL, cL, rhoR, PR, cR, uR - uL, 1e-10 * 0.5 * (PL + PR), &b);
+  if (branch) *branch = b;
+  return p0;
+}
+
 int orc_riemann(double gam, double rhoL, double uL, double PL, double rhoR, double uR,
                 double PR, double tol, int maxit, double *pstar, double *ustar, int *iters) {
   double cL = sqrt(gam * PL / rhoL), cR = sqrt(gam * PR / rhoR);
@@ -676,27 +713,10 @@ int orc_riemann(double gam, double rhoL, double uL, double PL, double rhoR, doub
     *ustar = 0.5 * (uL + uR);
     return 1;
   }
-  /* reading: Toro's adaptive starting value (primitive-variable guess when
-   * the states are close, two-rarefaction or two-shock otherwise) */
-  double pmin = fmin(PL, PR), pmax = fmax(PL, PR);
-  double ppv = 0.5 * (PL + PR) - 0.125 * du * (rhoL + rhoR) * (cL + cR);
-  if (ppv < 0.0) ppv = 0.0;
-  double p0;
-  if (pmax / pmin <= 2.0 && pmin <= ppv && ppv <= pmax) {
-    p0 = ppv;
-  } else if (ppv < pmin) {
-    double zz = (gam - 1.0) / (2.0 * gam);
-    double num = cL + cR - 0.5 * (gam - 1.0) * du;
-    double den = cL / pow(PL, zz) + cR / pow(PR, zz);
-    p0 = pow(num / den, 1.0 / zz);
-  } else {
-    double gL = sqrt(2.0 / ((gam + 1.0) * rhoL) / ((gam - 1.0) / (gam + 1.0) * PL + ppv));
-    double gR = sqrt(2.0 / ((gam + 1.0) * rhoR) / ((gam - 1.0) / (gam + 1.0) * PR + ppv));
-    p0 = (gL * PL + gR * PR - du) / (gL + gR);
-  }
   double floor_p = 1e-10 * 0.5 * (PL + PR);
-  if (!(p0 > floor_p)) p0 = floor_p;
-  double p = p0, fL, dfL, fR, dfR;
+  int branch;
+  double p = riemann_guess(gam, rhoL, PL, cL, rhoR, PR, cR, du, floor_p, &branch), fL, dfL, fR,
+         dfR;
   int status = 2;
   for (int it = 1; it <= maxit; ++it) {
     pressure_fn(gam, p, rhoL, PL, cL, &fL, &dfL);

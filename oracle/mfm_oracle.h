@@ -115,6 +115,14 @@ int orc_gradients(const orc_params *p, int64_t n, const double *x, const double 
 int orc_riemann(double gamma, double rhoL, double uL, double PL, double rhoR, double uR,
                 double PR, double tol, int maxit, double *pstar, double *ustar, int *iters);
 
+/* The Newton iteration's starting value: Toro's adaptive choice (the
+ * primitive-variable estimate when the states are close, else the
+ * two-rarefaction or two-shock estimate), floored at 1e-10 (P_L + P_R) / 2.
+ * branch (optional): 0, 1 or 2 for the primitive-variable, two-rarefaction
+ * or two-shock estimate. */
+double orc_riemann_guess(double gamma, double rhoL, double uL, double PL, double rhoR, double uR,
+                         double PR, int *branch);
+
 /* Sample the exact solution at speed xi = x/t (Toro's sampling). */
 int orc_riemann_sample(double gamma, double rhoL, double uL, double PL, double rhoR, double uR,
                        double PR, double pstar, double ustar, double xi, double *rho, double *u,

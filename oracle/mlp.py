@@ -8,9 +8,12 @@ Newton iteration of the exact Riemann solver the paper uses for its fluxes
 (sec. 2.3.3, Toro's solver), which then converges to the same root whatever
 the start.  What is fixed here, in plain numpy and FP64:
 
-* the six dimensionless face features of the left and right states (face
-  frame, after reconstruction) and the target y = ln(p* / P_avg),
-  P_avg = (P_L + P_R) / 2, with p* from the oracle's exact solver;
+* the six face features of a Riemann problem (face frame, after
+  reconstruction): ln(rho_L/rho_R), ln(P_L/P_R), slog(du / c_avg) -- which
+  with gamma fix p* -- and the exact solver's starting value p0 (Toro's
+  adaptive choice, ``oracle.riemann_guess``) as ln(p0 / P_avg) with two
+  indicators of its estimate; the target y = ln(p* / p0), the error of p0,
+  with p* from the oracle's exact solver;
 * the perceptron 6 -> 64 -> 64 -> 64 -> 1 with SiLU hidden activations: a
   layer computes a_out[n] = silu(b[n] + sum_k a_in[k] W[k][n]); the output is
   b4 + sum_k a3[k] w4[k];
@@ -25,7 +28,8 @@ are padding), b1, W2 [64][64], b2, W3 [64][64], b3, w4 [64], b4.
 Pins (tests/test_oracle_mlp.py): the gradient against central finite
 differences; a hand-evaluated single-path network (one non-zero weight per
 layer) that catches transposed or shifted weights; the features' mirror
-symmetry and the target of Sod's problem from Toro's tables.
+symmetry (with the starting value's) and the target of Sod's problem from
+Toro's tables.
 """
 from __future__ import annotations
 
@@ -90,11 +94,16 @@ def slog(v):
     return np.sign(v) * np.log1p(np.abs(v))
 
 
-def features(rL, uL, pL, cL, rR, uR, pR, cR) -> np.ndarray:
-    """The six features of a face (arrays broadcast; last axis = feature)."""
-    return np.stack([np.log(rL / rR), np.log(pL / pR),
-                     slog((uR - uL) / (0.5 * (cL + cR))),
-                     slog(uL / cL), slog(uR / cR), np.log(cL / cR)], axis=-1)
+def features(rL, pL, rR, pR, du, cL, cR, p0, branch) -> np.ndarray:
+    """The six features of a face's Riemann problem (arrays broadcast; last
+    axis = feature): ln(rho_L/rho_R), ln(P_L/P_R), slog(du / c_avg), and the
+    plain starting value p0 as ln(p0 / P_avg) with two indicators of the
+    estimate it came from (two-rarefaction, two-shock)."""
+    b = np.asarray(branch)
+    return np.stack(np.broadcast_arrays(
+        np.log(rL / rR), np.log(pL / pR), slog(du / (0.5 * (cL + cR))),
+        np.log(p0 / (0.5 * (pL + pR))), (b == 1).astype(np.float64),
+        (b == 2).astype(np.float64)), axis=-1)
 
 
 def standardise(X, norm, round_bf16=False):

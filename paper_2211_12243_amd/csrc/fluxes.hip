@@ -30,16 +30,19 @@
 // steps on y^m = x (quadratic: 1e-7 -> 1e-14 -> roundoff); in FP32 it is the
 // hardware exp2/log2.  Other gammas call pow().
 //
-// Learned guess (LEARNED = true).  After the face states are reconstructed,
-// each wavefront evaluates the guess network (mlp_device.h) on its 64 faces
-// with BF16 MFMA and starts Newton from P_avg exp(y).  The exact iteration
-// always finishes the solve; a guess that is not finite and positive, whose
-// first Newton step increases |f|, or that needs more than GUESS_MAXIT
-// iterations is dropped for the plain guess (counted).
+// Learned guess.  The first pass hands every face that may pass the guess
+// network's gate to the FP64 second pass (hand_over).  There a wavefront of
+// 16 faces holding a gated one evaluates the network (mlp_device.h) on one
+// 16-row tile with BF16 MFMA, from a copy of the weights in LDS.  The network
+// predicts the error of the plain starting value p0, y = ln(p* / p0), and Newton
+// starts from p0 exp(y).  The exact iteration always finishes the solve; a
+// guess that is not finite and above the pressure floor, whose first Newton
+// step increases |f|, or that needs more than GUESS_MAXIT iterations is
+// dropped for the plain guess (counted).
 //
 // Face dump.  With a dump buffer armed, every face (once) appends an 8-float
-// record: the six guess features, ln(p* / P_avg) and the plain guess's Newton
-// iteration count -- the network's training data.
+// record: the six guess features, ln(p* / p0) and the Newton iteration count
+// of its solve -- the network's training data.
 #include "mfm_internal.h"
 #include "mlp_device.h"
 
@@ -78,10 +81,14 @@ struct FluxArgs {
   int64_t dump_cap;
   unsigned long long *dump_count;
   // the FP64 second pass: faces the first pass hands over
-  int2 *hard_q;             // (lower, higher) slot of each queued face
-  int64_t hard_cap;
-  unsigned long long *hard_count;
+  int2 *hard_q;             // (lower, higher) slot of each queued face, HARD_SEGS segments
+  int64_t hard_cap;         // of hard_cap / HARD_SEGS faces
+  unsigned long long *hard_len;  // segment lengths, HARD_SEG_STRIDE apart
   float jump;               // mixed path: pressure or density ratio that sends a face to FP64
+  // learned guess: the face-state pressure ratio and normal velocity jump
+  // (in units of c_L + c_R) beyond which the first pass hands a face over,
+  // a superset of the network's gate (0: off)
+  float gate_p, gate_du;
   // the caller's FP64 particle arrays, which the second pass reads in place of
   // the mixed path's FP32 record (near the edge of the support, W(r, H) moves
   // by 3 (1 - r/H)^-1 times the relative error of 1/H)
@@ -292,34 +299,51 @@ __device__ int riemann_newton(const Gas<T> &G, const Side<T> &L, const Side<T> &
 }
 
 // Toro's adaptive starting value: the primitive-variable pressure when the
-// states are close, else the two-rarefaction or two-shock value.
+// states are close, else the two-rarefaction or two-shock value (branch:
+// which of the three, mlp::GuessBranch).
 template <typename T, int M>
-__device__ T plain_guess(const Gas<T> &G, const Side<T> &L, const Side<T> &R) {
+__device__ T plain_guess(const Gas<T> &G, const Side<T> &L, const Side<T> &R, int &branch) {
   const T du = R.u - L.u;
   const T pmin = fmin(L.p, R.p), pmax = fmax(L.p, R.p);
   T ppv = T(0.5) * (L.p + R.p) - T(0.125) * du * (L.r + R.r) * (L.c + R.c);
   ppv = fmax(ppv, T(0));
+  branch = mlp::GUESS_PV;
   if (pmax <= T(2) * pmin && pmin <= ppv && ppv <= pmax) return ppv;
   if (ppv < pmin) {
+    branch = mlp::GUESS_TR;
     // two-rarefaction value: [(cL + cR - g7 du) / (cL pL^-g1 + cR pR^-g1)]^(1/g1)
     const T num = L.c + R.c - G.g7 * du;
     const T den = L.c * iroot_m<T, M>(L.p, G) + R.c * iroot_m<T, M>(R.p, G);
     const T t = num * frcp<T>(den);
     return M ? ipow<(M > 0 ? M : 1)>(t) : pow(t, T(1) / G.g1);
   }
+  branch = mlp::GUESS_TS;
   const T gL = L.sA * frsq<T>(L.B + ppv);
   const T gR = R.sA * frsq<T>(R.B + ppv);
   return (gL * L.p + gR * R.p - du) * frcp<T>(gL + gR);
 }
 
-// Exact Riemann solve: 0 converged, 1 vacuum, 2 iteration cap.  p_learned > 0
-// is tried first (guarded); *fallback is set when it was rejected.
+// The plain starting value above the solver's pressure floor.
+template <typename T, int M>
+__device__ T floored_guess(const Gas<T> &G, const Side<T> &L, const Side<T> &R, int &branch) {
+  const T pfloor = T(1e-10) * T(0.5) * (L.p + R.p);
+  const T p0 = plain_guess<T, M>(G, L, R, branch);
+  return p0 > pfloor ? p0 : pfloor;
+}
+
+// Exact Riemann solve: 0 converged, 1 vacuum, 2 iteration cap.  pguess and
+// branch: the plain starting value and its estimate.  learned: the network's
+// correction y to it, p0 exp(y), is tried first (guarded); fallback is set
+// when it was rejected.
 template <typename T, int M>
 __device__ int riemann_solve(const Gas<T> &G, const Side<T> &L, const Side<T> &R, T tol, int maxit,
-                             T p_learned, T &ps, T &us, int &iters, bool &fallback) {
+                             bool learned, float y, T &ps, T &us, int &iters, bool &fallback,
+                             T &pguess, int &branch) {
   const T du = R.u - L.u;
   iters = 0;
   fallback = false;
+  pguess = T(0);
+  branch = mlp::GUESS_PV;
   if (G.g4 * (L.c + R.c) <= du) {
     ps = T(0);
     us = T(0.5) * (L.u + R.u);
@@ -330,16 +354,17 @@ __device__ int riemann_solve(const Gas<T> &G, const Side<T> &L, const Side<T> &R
   // ~1e-4 tol.  FP32: stop once a step is below 1e-4, which leaves the root
   // at FP32 precision; the FP64 check that follows sets p* and u*.
   const T qtol = sizeof(T) == sizeof(double) ? T(1e-4) * tol : T(1e-8);
-  if (p_learned > T(0)) {
-    if (p_learned > pfloor && isfinite(p_learned)) {
-      const int st = riemann_newton<T, M>(G, L, R, p_learned, pfloor, tol, maxit, qtol,
-                                          GUESS_MAXIT, ps, us, iters);
+  const T p0 = floored_guess<T, M>(G, L, R, branch);
+  pguess = p0;
+  if (learned) {
+    const T pl = p0 * T(expf(y));
+    if (pl > pfloor && isfinite(pl)) {
+      const int st = riemann_newton<T, M>(G, L, R, pl, pfloor, tol, maxit, qtol, GUESS_MAXIT,
+                                          ps, us, iters);
       if (st != 3) return st;
     }
     fallback = true;
   }
-  T p0 = plain_guess<T, M>(G, L, R);
-  if (!(p0 > pfloor)) p0 = pfloor;
   return riemann_newton<T, M>(G, L, R, p0, pfloor, tol, maxit, qtol, 0, ps, us, iters);
 }
 
@@ -586,21 +611,28 @@ __device__ void face_prepare(const FaceIn<T> &Ls, const FaceIn<T> &Rs, const Flu
   fs.SR = make_side<T>(qR[0], uR, qR[4], G);
 }
 
-// Riemann solve and flux of a prepared face: c = |A_ij| F_ij (FP64).
+// Riemann solve and flux of a prepared face: c = |A_ij| F_ij (FP64).  learned,
+// y: the network's correction to the plain starting value; pguess_out,
+// branch: that plain value (0 for a vacuum or skipped face) and its estimate.
 template <typename T, int SCHEME, int M>
-__device__ void face_solve(FaceState<T> &fs, const FluxArgs &a, T p_learned, double c[5],
-                           int &iters, double &ps_out) {
+__device__ void face_solve(FaceState<T> &fs, const FluxArgs &a, bool learned, float y,
+                           double c[5], int &iters, double &ps_out, double &pguess_out,
+                           int &branch) {
   const Gas<T> &G = gas_of<T>(a);
 #pragma unroll
   for (int k = 0; k < 5; ++k) c[k] = 0.0;
   iters = 0;
   ps_out = 0.0;
+  pguess_out = 0.0;
+  branch = mlp::GUESS_PV;
   if (fs.skip) return;
   const Side<T> &SL = fs.SL, &SR = fs.SR;
-  T ps, us;
+  T ps, us, pg;
   const T tol = sizeof(T) == sizeof(float) ? T(a.rtol_f) : T(a.rtol);
   bool fallback;
-  int st = riemann_solve<T, M>(G, SL, SR, tol, a.rmaxit, p_learned, ps, us, iters, fallback);
+  int st = riemann_solve<T, M>(G, SL, SR, tol, a.rmaxit, learned, y, ps, us, iters, fallback,
+                               pg, branch);
+  pguess_out = (double)pg;
   if (fallback) fs.flags |= F_FALLBACK;
   if (st == 1) {
     fs.flags |= F_VACUUM;
@@ -652,10 +684,27 @@ __device__ void face_solve(FaceState<T> &fs, const FluxArgs &a, T p_learned, dou
   }
 }
 
+// A slot in a shared append buffer for each lane with want set: one atomic
+// per wavefront on the counter.  Every executing lane of the wavefront calls
+// it; lanes without want get an unused value.
+__device__ __forceinline__ unsigned long long wave_slot(unsigned long long *counter, bool want,
+                                                        int lane) {
+  const uint64_t m = __ballot(want);
+  if (!m) return 0ull;
+  const int leader = __ffsll((unsigned long long)m) - 1;
+  unsigned long long base = 0;
+  if (lane == leader) base = atomicAdd(counter, (unsigned long long)__popcll(m));
+  base = __shfl(base, leader, 64);
+  return base + __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32),
+                                          __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+}
+
 template <typename T>
-__device__ __forceinline__ void features_of(const FaceState<T> &fs, float x[mlp::NIN]) {
-  mlp::face_features((float)fs.SL.r, (float)fs.SL.u, (float)fs.SL.p, (float)fs.SL.c,
-                     (float)fs.SR.r, (float)fs.SR.u, (float)fs.SR.p, (float)fs.SR.c, x);
+__device__ __forceinline__ void features_of(const FaceState<T> &fs, double p0, int branch,
+                                            float x[mlp::NIN]) {
+  mlp::face_features((float)fs.SL.r, (float)fs.SL.p, (float)fs.SR.r, (float)fs.SR.p,
+                     (float)(fs.SR.u - fs.SL.u), (float)fs.SL.c, (float)fs.SR.c, (float)p0, branch,
+                     x);
 }
 
 // Faces the first pass hands to the FP64 second pass, judged (besides the
@@ -663,9 +712,12 @@ __device__ __forceinline__ void features_of(const FaceState<T> &fs, float x[mlp:
 // their pressures or densities differ by more than a.jump, or the face fell
 // back to first-order states -- where FP32 extrapolations cancel and the
 // Riemann problem is strongest.
-// Learned guess: a superset of the network's gate (pressure ratio above 1.9
-// or a normal velocity jump above 0.48 of the mean sound speed, against 2 and
-// 0.5 in the gate itself); the second pass applies the exact gate.
+// Learned guess: a superset of the network's gate (a.gate_p = 1.9 and
+// a.gate_du = 0.24, a pressure ratio above 1.9 or a normal velocity jump
+// above 0.48 of the mean sound speed, against 2 and 0.5 in the gate itself);
+// the second pass applies the exact gate.  In the mixed path these are
+// run-time values, so that the plain and the learned guess share one
+// instance of the first pass.
 template <typename T, bool LEARNED>
 __device__ __forceinline__ bool hand_over(const FaceState<T> &fs, const FluxArgs &a) {
   if (fs.skip) return false;
@@ -676,9 +728,11 @@ __device__ __forceinline__ bool hand_over(const FaceState<T> &fs, const FluxArgs
     h = fmax(pL, pR) > J * fmin(pL, pR) || fmax(fs.SL.r, fs.SR.r) > J * fmin(fs.SL.r, fs.SR.r) ||
         (fs.flags & F_POSITIVITY);
   }
-  if (LEARNED)
-    h = h || pL > T(1.9) * pR || pR > T(1.9) * pL ||
-        fabs(fs.SR.u - fs.SL.u) > T(0.24) * (fs.SL.c + fs.SR.c);
+  if (LEARNED || a.gate_p > 0.0f) {
+    const T gp = T(a.gate_p);
+    h = h || pL > gp * pR || pR > gp * pL ||
+        fabs(fs.SR.u - fs.SL.u) > T(a.gate_du) * (fs.SL.c + fs.SR.c);
+  }
   return h;
 }
 
@@ -776,20 +830,25 @@ __global__ void __launch_bounds__(FTH) __attribute__((amdgpu_waves_per_eu(2))) f
       if (LEARNED || sizeof(T) == sizeof(float)) defer = defer || hand_over<T, LEARNED>(fs, a);
     }
     if (LEARNED || sizeof(T) == sizeof(float)) {
-      // queue the wave's handed-over faces with one atomic per wave; a face
-      // that finds the queue full is solved here
+      // queue the wave's handed-over faces with one atomic per wave, in the
+      // segment of this workgroup; a face that finds the segment full is
+      // solved here
       const uint64_t dmask = __ballot(defer);
       if (dmask) {
+        const int seg = blockIdx.x % HARD_SEGS;
         const int leader = __ffsll((unsigned long long)dmask) - 1;
         unsigned long long base = 0;
-        if (lane == leader) base = atomicAdd(a.hard_count, (unsigned long long)__popcll(dmask));
+        if (lane == leader)
+          base = atomicAdd(a.hard_len + seg * HARD_SEG_STRIDE,
+                           (unsigned long long)__popcll(dmask));
         base = __shfl(base, leader, 64);
         if (defer) {
           const unsigned long long below = __builtin_amdgcn_mbcnt_hi(
               (uint32_t)(dmask >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)dmask, 0u));
           const unsigned long long slot = base + below;
-          if (slot < (unsigned long long)a.hard_cap) {
-            a.hard_q[slot] = make_int2(Lslot, Rslot);
+          const unsigned long long seg_cap = (unsigned long long)(a.hard_cap / HARD_SEGS);
+          if (slot < seg_cap) {
+            a.hard_q[seg * (int64_t)seg_cap + (int64_t)slot] = make_int2(Lslot, Rslot);
           } else {
             defer = false;
             ++overflow;
@@ -800,8 +859,9 @@ __global__ void __launch_bounds__(FTH) __attribute__((amdgpu_waves_per_eu(2))) f
     double c[5] = {0, 0, 0, 0, 0};
     if (active && !defer) {
       int it;
-      double ps;
-      face_solve<T, SCHEME, M>(fs, a, T(0), c, it, ps);
+      double ps, pg;
+      int br;
+      face_solve<T, SCHEME, M>(fs, a, false, 0.0f, c, it, ps, pg, br);
 #pragma unroll
       for (int q = 0; q < 5; ++q) c[q] *= dtf;
       if (SCHEME == MFM_SCHEME_MFV && a.gwork) add_gwork(a, Lslot, Rslot, c[0]);
@@ -826,15 +886,16 @@ __global__ void __launch_bounds__(FTH) __attribute__((amdgpu_waves_per_eu(2))) f
         pos += (fs.flags & F_POSITIVITY) ? 1 : 0;
         maxit += (fs.flags & F_MAXIT) ? 1 : 0;
         fb += (fs.flags & F_FALLBACK) ? 1 : 0;
-        if (a.dump && !fs.skip && !(fs.flags & F_VACUUM)) {
-          const unsigned long long slot = atomicAdd(a.dump_count, 1ull);
-          if (slot < (unsigned long long)a.dump_cap) {
+        if (a.dump) {
+          const bool rec = !fs.skip && !(fs.flags & F_VACUUM);
+          const unsigned long long slot = wave_slot(a.dump_count, rec, lane);
+          if (rec && slot < (unsigned long long)a.dump_cap) {
             float x[mlp::NIN];
-            features_of<T>(fs, x);
+            features_of<T>(fs, pg, br, x);
             float *r = a.dump + slot * 8;
 #pragma unroll
             for (int k = 0; k < mlp::NIN; ++k) r[k] = x[k];
-            r[6] = logf((float)(ps / (0.5 * ((double)fs.SL.p + (double)fs.SR.p))));
+            r[6] = logf((float)(ps / pg));
             r[7] = (float)it;
           }
         }
@@ -904,28 +965,65 @@ __device__ __forceinline__ void load_side64(const FluxArgs &a, int i, FaceIn<dou
 // pass its gate).  Both sides receive their share through FP64 atomics into
 // dq_ext, which is folded into dQ after this pass.  The queue length is read
 // on the device; the grid strides over it.
+//
+// With the learned guess the network's weights and vectors are first copied
+// to LDS.  A short queue (the usual case: well under 1% of the faces) leaves
+// the pass bound by the latency of a wavefront's work; a wavefront then
+// takes 16 faces (lanes 0..15), so that the network runs on a single 16-row
+// tile and four times as many wavefronts share the queue.  A long queue
+// (more than four rounds of the grid at 16 faces per wavefront) is taken 64
+// faces per wavefront, the network on its four tiles in turn.
 template <bool F32REC, int SCHEME, int M, bool LEARNED>
 __global__ void __launch_bounds__(FTH) hard_faces_k(FluxArgs a) {
   if (a.counters[C_STEP_SKIP]) return;  // the density pass was rejected
-  __shared__ uint16_t mlp_act[LEARNED ? (FTH / 64) * 16 * mlp::AST : 1];
+  constexpr int FTW = FTH / 64;  // wavefronts per workgroup
+  __shared__ uint16_t mlp_act[LEARNED ? FTW * 16 * mlp::AST : 1];
+  __shared__ __align__(16) uint16_t mlp_w[LEARNED ? mlp::NT : 1];
+  __shared__ float mlp_v[LEARNED ? mlp::NVEC : 1];
+  __shared__ int64_t seg_off[HARD_SEGS + 1];
   const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
-  const unsigned long long queued = *a.hard_count;
-  const int64_t nq = (int64_t)(queued < (unsigned long long)a.hard_cap ? queued
-                                                                        : (unsigned long long)a.hard_cap);
+  // the segments laid end to end: face g of the pass is entry g - seg_off[s]
+  // of the segment s with seg_off[s] <= g < seg_off[s + 1]
+  const int64_t seg_cap = a.hard_cap / HARD_SEGS;
+  if (tid < HARD_SEGS) {
+    const unsigned long long len = a.hard_len[tid * HARD_SEG_STRIDE];
+    seg_off[tid + 1] = (int64_t)(len < (unsigned long long)seg_cap ? len
+                                                                    : (unsigned long long)seg_cap);
+  }
+  __syncthreads();
+  if (tid == 0) {
+    seg_off[0] = 0;
+    for (int s = 0; s < HARD_SEGS; ++s) seg_off[s + 1] += seg_off[s];
+  }
+  __syncthreads();
+  const int64_t nq = seg_off[HARD_SEGS];
+  // faces per wave: 16 while that takes at most four rounds of the grid
+  const int fpw = (LEARNED && nq <= 4 * (int64_t)gridDim.x * FTW * 16) ? 16 : 64;
+  const int fpb = FTW * fpw;  // faces per workgroup and round
+  mlp::Vecs vecs{};
+  if (LEARNED) {
+    if ((int64_t)blockIdx.x * fpb >= nq) return;  // no face for this workgroup
+    vecs = mlp::stage_net(a.net, mlp_w, mlp_v, tid, FTH);
+    __syncthreads();
+  }
   const double dt = a.dt[0] * a.inv_a;  // the step times 1/a (comoving)
   const double hdt = 0.5 * dt;
   const int64_t n = a.n;
   int64_t nfaces = 0, iters_sum = 0, vac = 0, pos = 0, maxit = 0, fb = 0;
-  for (int64_t base = (int64_t)blockIdx.x * FTH; base < nq; base += (int64_t)gridDim.x * FTH) {
-    const int64_t f = base + tid;
-    const bool active = f < nq;
+  for (int64_t base = (int64_t)blockIdx.x * fpb; base < nq; base += (int64_t)gridDim.x * fpb) {
+    const int64_t g = base + wid * fpw + lane;
+    const bool active = lane < fpw && g < nq;
     FaceState<double> fs;
     fs.skip = true;
     fs.flags = 0;
     int L = 0, R = 0;
     double dtf = dt;
     if (active) {
-      const int2 q = a.hard_q[f];
+      int s = 0;  // the segment holding g: a binary search over the offsets
+#pragma unroll
+      for (int step = HARD_SEGS / 2; step > 0; step >>= 1)
+        if (seg_off[s + step] <= g) s += step;
+      const int2 q = a.hard_q[s * seg_cap + (g - seg_off[s])];
       L = q.x;
       R = q.y;
       double hL = hdt, hR = hdt;
@@ -935,39 +1033,38 @@ __global__ void __launch_bounds__(FTH) hard_faces_k(FluxArgs a) {
       load_side64<F32REC>(a, R, Rs);
       face_prepare<double>(Ls, Rs, a, hL, hR, fs);
     }
-    double p_learned = 0.0;
+    bool use_net = false;
+    float y = 0.f;
     if (LEARNED) {
-      // the wavefront evaluates the network on the 16-face tiles that hold a
-      // face passing its gate (wave-uniform branches)
+      // a wavefront holding a face that passes the gate evaluates the
+      // network on all its faces (wave-uniform branch)
       float x[mlp::NIN];
       bool gated = false;
       if (active && !fs.skip) {
-        features_of<double>(fs, x);
+        int br0;
+        const double p0 = floored_guess<double, M>(a.G, fs.SL, fs.SR, br0);
+        features_of<double>(fs, p0, br0, x);
         gated = mlp::needs_guess(x);
       }
-      const uint64_t gmask = __ballot(gated);
-      if (gmask) {
+      if (__ballot(gated)) {
         uint16_t *tile = mlp_act + wid * 16 * mlp::AST;
-        float y = 0.f;
-#pragma unroll 1
-        for (int mt = 0; mt < 4; ++mt) {
-          if (((gmask >> (16 * mt)) & 0xffffull) == 0) continue;
-          if ((lane >> 4) == mt) mlp::put_input(tile, lane & 15, gated ? x : nullptr, a.net.norm);
-          const float yt = mlp::forward_tile(tile, a.net, lane);
-          if ((lane >> 4) == mt) y = yt;
+        float yw;
+        if (fpw == 16) {
+          if (lane < 16) mlp::put_input(tile, lane, gated ? x : nullptr, vecs.norm);
+          yw = mlp::forward_rows(tile, mlp_w, vecs, lane);
+        } else {
+          yw = mlp::forward_wave(tile, gated ? x : nullptr, mlp_w, vecs, lane);
         }
-        if (gated) {
-          p_learned = 0.5 * (fs.SL.p + fs.SR.p) * (double)expf(y);
-          if (!(p_learned > 0.0)) p_learned = -1.0;  // rejected below
-        }
+        use_net = gated;
+        y = yw;
       }
     }
     if (active) {
       double c[5];
       int it;
-      double ps;
-      face_solve<double, SCHEME, M>(fs, a, p_learned != 0.0 ? p_learned : 0.0, c, it, ps);
-      if (LEARNED && p_learned < 0.0) fs.flags |= F_FALLBACK;
+      double ps, pg;
+      int br;
+      face_solve<double, SCHEME, M>(fs, a, use_net, y, c, it, ps, pg, br);
 #pragma unroll
       for (int q = (SCHEME == MFM_SCHEME_MFM ? 1 : 0); q < 5; ++q) {
         unsafeAtomicAdd(&a.dq_ext[(int64_t)q * n + L], -dtf * c[q]);
@@ -980,15 +1077,16 @@ __global__ void __launch_bounds__(FTH) hard_faces_k(FluxArgs a) {
       pos += (fs.flags & F_POSITIVITY) ? 1 : 0;
       maxit += (fs.flags & F_MAXIT) ? 1 : 0;
       fb += (fs.flags & F_FALLBACK) ? 1 : 0;
-      if (a.dump && !fs.skip && !(fs.flags & F_VACUUM)) {
-        const unsigned long long slot = atomicAdd(a.dump_count, 1ull);
-        if (slot < (unsigned long long)a.dump_cap) {
+      if (a.dump) {
+        const bool rec = !fs.skip && !(fs.flags & F_VACUUM);
+        const unsigned long long slot = wave_slot(a.dump_count, rec, lane);
+        if (rec && slot < (unsigned long long)a.dump_cap) {
           float x[mlp::NIN];
-          features_of<double>(fs, x);
+          features_of<double>(fs, pg, br, x);
           float *r = a.dump + slot * 8;
 #pragma unroll
           for (int k = 0; k < mlp::NIN; ++k) r[k] = x[k];
-          r[6] = logf((float)(ps / (0.5 * (fs.SL.p + fs.SR.p))));
+          r[6] = logf((float)(ps / pg));
           r[7] = (float)it;
         }
       }
@@ -1007,7 +1105,7 @@ __global__ void __launch_bounds__(FTH) hard_faces_k(FluxArgs a) {
 __global__ void zero_f64_k(double *v, int64_t m, unsigned long long *queue_len,
                            const int64_t *counters, double *w, int64_t mw) {
   if (counters[C_STEP_SKIP]) return;
-  if (blockIdx.x == 0 && threadIdx.x == 0) *queue_len = 0ull;
+  if (blockIdx.x == 0 && threadIdx.x < HARD_SEGS) queue_len[threadIdx.x * HARD_SEG_STRIDE] = 0ull;
   for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < m;
        k += (int64_t)gridDim.x * blockDim.x)
     v[k] = 0.0;
@@ -1111,7 +1209,7 @@ hipError_t launch_fluxes(mfm_ctx *ctx, const mfm_particles *pp, const double *dt
   a.dq_ext = ctx->dq_ext;
   a.hard_q = ctx->hard_q;
   a.hard_cap = ctx->hard_cap;
-  a.hard_count = reinterpret_cast<unsigned long long *>(ctx->counters + C_HARD_QUEUE);
+  a.hard_len = ctx->hard_len;
   a.jump = (float)ctx->p.mixed_jump;
   a.x = pp->x; a.y = pp->y; a.z = pp->z; a.H = pp->H; a.V = pp->V; a.rho = pp->rho;
   a.vx = pp->vx; a.vy = pp->vy; a.vz = pp->vz; a.P = pp->P;
@@ -1121,18 +1219,17 @@ hipError_t launch_fluxes(mfm_ctx *ctx, const mfm_particles *pp, const double *dt
   const bool learned = ctx->p.guess == MFM_GUESS_LEARNED;
   const bool mixed = ctx->p.precision == MFM_MIXED;
   if (learned) mlp_net_of(ctx->mlp_state, &a.net);
+  a.gate_p = learned ? 1.9f : 0.0f;
+  a.gate_du = learned ? 0.24f : 0.0f;
   const int nb = blocks_for(pp->n, FBS);
   const int64_t m5 = 5 * pp->n;
   const int fb = (int)std::min<int64_t>(blocks_for(m5, 256), 8192);
   const int ev_all = stage_begin(ctx, 4);
-  zero_f64_k<<<fb, 256, 0, ctx->stream>>>(ctx->dq_ext, m5, a.hard_count, ctx->counters, a.gwork,
+  zero_f64_k<<<fb, 256, 0, ctx->stream>>>(ctx->dq_ext, m5, a.hard_len, ctx->counters, a.gwork,
                                           3 * pp->n);
   const int ev_main = stage_begin(ctx, 6);
   if (mixed) {
-    if (learned)
-      launch_t<float, true>(a, ctx->p.scheme, m, nb, ctx->stream);
-    else
-      launch_t<float, false>(a, ctx->p.scheme, m, nb, ctx->stream);
+    launch_t<float, false>(a, ctx->p.scheme, m, nb, ctx->stream);  // learned: a.gate_*
   } else {
     if (learned)
       launch_t<double, true>(a, ctx->p.scheme, m, nb, ctx->stream);
@@ -1143,7 +1240,7 @@ hipError_t launch_fluxes(mfm_ctx *ctx, const mfm_particles *pp, const double *dt
   if (mixed || learned) {
     // the second pass strides over the queue with a grid of its own (its
     // length is known only on the device); an empty queue ends it at once
-    const int hb = 1024;
+    const int hb = 2048;
     const int ev_hard = stage_begin(ctx, 7);
     if (mixed) {
       if (learned) launch_hard<true, true>(a, ctx->p.scheme, m, hb, ctx->stream);

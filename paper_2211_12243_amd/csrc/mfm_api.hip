@@ -15,7 +15,8 @@ constexpr size_t ALIGN = 256;
 
 struct Layout {
   size_t code, hist, tnode, scan, lseg, lcap, scan64, ncand, order, tmp, pos4, cand, cand_r2, rest_r2,
-      cand_cnt, gl, gl_cnt, gin, fslot, fcnt, dq_ext, hard_q, rec, ekm, grad_q, rung, s0, act,
+      cand_cnt, gl, gl_cnt, gin, fslot, fcnt, dq_ext, hard_q, hard_len, rec, ekm, grad_q, rung,
+      s0, act,
       elapsed, gwork, red, counters,
       scalars;
   int64_t hard_cap;
@@ -67,9 +68,11 @@ Layout make_layout(const mfm_params *p, int64_t n) {
   L.fslot = take(4 * list_len(p->max_list, n));
   L.fcnt = take(4 * (size_t)n);
   L.dq_ext = take(8 * 5 * (size_t)n);
-  // the FP64 pass's queue holds as many faces as half the face lists
-  L.hard_cap = (int64_t)(list_len(p->max_list, n) / 2);
+  // the FP64 pass's queue holds as many faces as half the face lists, in
+  // HARD_SEGS equal segments
+  L.hard_cap = (int64_t)(list_len(p->max_list, n) / 2) / HARD_SEGS * HARD_SEGS;
   L.hard_q = take(8 * (size_t)L.hard_cap);
+  L.hard_len = take(8 * (size_t)HARD_SEGS * HARD_SEG_STRIDE);
   L.rec = take(8 * (size_t)R_STRIDE * (size_t)n);
   L.ekm = take(8 * (size_t)n);
   L.grad_q = take(4 * (size_t)n);
@@ -275,6 +278,7 @@ int init_ctx(mfm_ctx *ctx, const mfm_params *p, int64_t n_max, void *workspace,
   ctx->fcnt = (int32_t *)(ctx->ws + L.fcnt);
   ctx->dq_ext = (double *)(ctx->ws + L.dq_ext);
   ctx->hard_q = (int2 *)(ctx->ws + L.hard_q);
+  ctx->hard_len = (unsigned long long *)(ctx->ws + L.hard_len);
   ctx->hard_cap = L.hard_cap;
   ctx->rec = (double *)(ctx->ws + L.rec);
   ctx->ekm = (double *)(ctx->ws + L.ekm);

@@ -41,7 +41,6 @@ enum {
   C_PASS_LIST,      // particles whose candidate list overflowed
   C_STEP_SKIP,      // the pass is rejected: the kernels after it return at once
   C_DUMP_COUNT,     // face records appended since the dump was armed
-  C_HARD_QUEUE,     // faces queued for the flux loop's FP64 pass in the current call
   C_LIST_POOL,      // the planned list blocks exceed the list pool (set by each plan)
   C_GRAD_QUEUE,     // mixed path: particles queued for the gradient loop's FP64 redo
   C_RUNG_CHANGED,   // the rung limiter raised some rung in its last sweep
@@ -171,8 +170,10 @@ struct mfm_ctx {
   int32_t *fcnt;       // n
   double *dq_ext;      // 5 n: flux contributions to particles outside the evaluating block
                        // and of the FP64 second pass, folded into dQ after the loop
-  int2 *hard_q;        // faces (lower, higher slot) queued for the flux loop's FP64 pass
+  int2 *hard_q;        // faces (lower, higher slot) queued for the flux loop's FP64 pass:
+                       // HARD_SEGS segments of hard_cap / HARD_SEGS faces
   int64_t hard_cap;    // its capacity
+  unsigned long long *hard_len;  // the segments' lengths (HARD_SEG_STRIDE apart)
   double *rec;         // R_STRIDE * n packed flux records
   double *ekm;         // n: E_kin^max of the entropy switch (gradient loop)
   int32_t *grad_q;     // n: particles queued for the mixed gradient loop's FP64 redo
@@ -375,11 +376,20 @@ static inline size_t list_len(int max_list, int64_t n) {
   return (size_t)max_list * (size_t)(list_chunks(n) * LCH);
 }
 
-// Particles per workgroup of the flux loop: faces inside a block are computed
-// once, faces crossing its boundary by both blocks (see fluxes.hip).  On a
-// Morton-ordered lattice about 25% of the faces cross a 1024-particle block
-// boundary (38% for 256), so larger blocks evaluate fewer faces twice.
+// Particles per workgroup of the flux loop.  Every face is computed once, by
+// the block of the particle that lists it; a partner in another block receives
+// its share through FP64 global atomics (see fluxes.hip).  On a Morton-ordered
+// lattice about 25% of the faces cross a 1024-particle block boundary (38% for
+// 256), so larger blocks send fewer shares through HBM atomics.
 constexpr int FLUX_BLOCK = 1024;
+
+// The flux loop's FP64 second pass takes its faces from HARD_SEGS queues,
+// each with its own append counter (HARD_SEG_STRIDE 8-byte words apart, on
+// separate cache lines): where most faces are handed over (strong jumps
+// everywhere) a single counter serialises millions of same-address atomics.
+constexpr int HARD_SEGS = 32;
+constexpr int HARD_SEG_STRIDE = 32;
+static_assert((HARD_SEGS & (HARD_SEGS - 1)) == 0, "the second pass bisects the segments");
 
 // Exactly one of emit(i, j), emit(j, i) holds, and about half of any
 // particle's in-block faces are its own whatever its rank in the block.

@@ -2,10 +2,10 @@
 // mlp_device.h): forward and backward passes on BF16 MFMA with FP32
 // accumulation, Adam on an FP32 master copy, prediction.
 //
-// The network predicts y = ln(p* / P_avg) of a face's Riemann problem from
-// six dimensionless features of its left and right states; the flux loop uses
-// P_avg e^y as the starting value of the exact Newton iteration (which always
-// finishes the solve).  Training rows are the face records the flux loop dumps
+// The network predicts y = ln(p* / p0) of a face's Riemann problem, the error
+// of the plain starting value p0 (Toro's adaptive choice), from six
+// dimensionless features of its left and right states; the flux loop starts
+// the exact Newton iteration (which always finishes the solve) from p0 e^y.  Training rows are the face records the flux loop dumps
 // (mfm_face_dump): 8 floats per face, the raw features, the target and the
 // plain guess's iteration count.
 #include "mfm_internal.h"

@@ -140,52 +140,83 @@ __device__ inline void put_input(uint16_t *act, int row, const float *x, const f
   for (int k = NIN; k < K1; ++k) act[row * AST + k] = 0;
 }
 
-// Forward pass of one 16-row tile held in act (row stride AST), in place.
-// Every lane returns the unstandardised output of row lane % 16.
-__device__ inline float forward_tile(uint16_t *act, const Net &net, int lane) {
+// The FP32 vectors a forward pass reads besides the BF16 weight matrices:
+// the three hidden biases, the output weights and bias, the normalisation.
+struct Vecs {
+  const float *b1, *b2, *b3, *w4, *b4, *norm;
+};
+__device__ inline Vecs vecs_of(const Net &net) {
+  return Vecs{net.p + OFF_B1, net.p + OFF_B2, net.p + OFF_B3, net.p + OFF_W4, net.p + OFF_B4,
+              net.norm};
+}
+constexpr int NVEC = 4 * HID + 1 + NNORM;  // floats of an LDS copy of the vectors
+
+// Copies a network's BF16 weights (w, NT elements, 16-byte aligned) and FP32
+// vectors (v, NVEC floats) into LDS; every thread of the workgroup takes
+// part (tid of nth), and a workgroup barrier must follow before they are
+// read.  Returns the vectors' LDS addresses.
+__device__ inline Vecs stage_net(const Net &net, uint16_t *w, float *v, int tid, int nth) {
+  const uint4 *src = reinterpret_cast<const uint4 *>(net.wt);
+  uint4 *dst = reinterpret_cast<uint4 *>(w);
+  for (int k = tid; k < NT / 8; k += nth) dst[k] = src[k];
+  const Vecs g = vecs_of(net);
+  for (int k = tid; k < NVEC; k += nth) {
+    float x;
+    if (k < 4 * HID) {
+      const int q = k / HID, e = k % HID;
+      x = (q == 0 ? g.b1 : q == 1 ? g.b2 : q == 2 ? g.b3 : g.w4)[e];
+    } else if (k == 4 * HID) {
+      x = g.b4[0];
+    } else {
+      x = g.norm[k - 4 * HID - 1];
+    }
+    v[k] = x;
+  }
+  return Vecs{v, v + HID, v + 2 * HID, v + 3 * HID, v + 4 * HID, v + 4 * HID + 1};
+}
+
+// Forward pass of one 16-row tile held in act (row stride AST), in place,
+// with the weights wt and vectors v.  Every lane returns the unstandardised
+// output of row lane % 16.
+__device__ inline float forward_rows(uint16_t *act, const uint16_t *wt, const Vecs &v, int lane) {
   wave_lds_sync();
-  layer<1, K1>(act, AST, act, AST, net.wt + T_W1, net.p + OFF_B1, nullptr, 0, lane);
+  layer<1, K1>(act, AST, act, AST, wt + T_W1, v.b1, nullptr, 0, lane);
   wave_lds_sync();
-  layer<1, HID>(act, AST, act, AST, net.wt + T_W2, net.p + OFF_B2, nullptr, 0, lane);
+  layer<1, HID>(act, AST, act, AST, wt + T_W2, v.b2, nullptr, 0, lane);
   wave_lds_sync();
-  layer<1, HID>(act, AST, act, AST, net.wt + T_W3, net.p + OFF_B3, nullptr, 0, lane);
+  layer<1, HID>(act, AST, act, AST, wt + T_W3, v.b3, nullptr, 0, lane);
   wave_lds_sync();
   // output layer in FP32: lanes l, l+16, l+32, l+48 each sum 16 of the 64 terms
   const int r = lane & 15, k0 = (lane >> 4) * 16;
   float y = 0.f;
 #pragma unroll
-  for (int k = 0; k < 16; ++k) y += from_bf16(act[r * AST + k0 + k]) * net.p[OFF_W4 + k0 + k];
+  for (int k = 0; k < 16; ++k) y += from_bf16(act[r * AST + k0 + k]) * v.w4[k0 + k];
   y += __shfl_xor(y, 16, 64);
   y += __shfl_xor(y, 32, 64);
-  y += net.p[OFF_B4];
-  wave_lds_sync();
-  return net.norm[2 * NIN] + net.norm[2 * NIN + 1] * y;
+  y += v.b4[0];
+  wave_lds_sync();  // the tile is free for the wave's next rows
+  return v.norm[2 * NIN] + v.norm[2 * NIN + 1] * y;
 }
 
-// forward_tile as a real call: the flux loop evaluates the network rarely
-// (only tiles holding a gated face), so the network's registers are kept out
-// of the flux kernel's allocation and spilled around the call instead.
-__device__ __attribute__((noinline)) float forward_tile_call(uint16_t *act, const uint16_t *wt,
-                                                             const float *p, const float *norm,
-                                                             int lane) {
-  Net net;
-  net.wt = wt;
-  net.wr = nullptr;
-  net.p = p;
-  net.norm = norm;
-  return forward_tile(act, net, lane);
+// Forward pass of one 16-row tile with the network's own (global) weights.
+__device__ inline float forward_tile(uint16_t *act, const Net &net, int lane) {
+  return forward_rows(act, net.wt, vecs_of(net), lane);
 }
 
 // Forward pass for the 64 rows of a wave, one tile at a time through a
 // 16-row buffer; lane l supplies row l (x null: a zero row) and gets its output.
-__device__ inline float forward_wave(uint16_t *tile, const float *x, const Net &net, int lane) {
+__device__ inline float forward_wave(uint16_t *tile, const float *x, const uint16_t *wt,
+                                     const Vecs &v, int lane) {
   float y = 0.f;
   for (int mt = 0; mt < 4; ++mt) {
-    if ((lane >> 4) == mt) put_input(tile, lane & 15, x, net.norm);
-    const float yt = forward_tile(tile, net, lane);
+    if ((lane >> 4) == mt) put_input(tile, lane & 15, x, v.norm);
+    const float yt = forward_rows(tile, wt, v, lane);
     if ((lane >> 4) == mt) y = yt;
   }
   return y;
+}
+__device__ inline float forward_wave(uint16_t *tile, const float *x, const Net &net, int lane) {
+  return forward_wave(tile, x, net.wt, vecs_of(net), lane);
 }
 
 // Faces whose plain starting value is least accurate -- a pressure ratio
@@ -198,16 +229,23 @@ __device__ __host__ inline bool needs_guess(const float x[NIN]) {
   return fabsf(x[1]) > GATE_LOG_P || fabsf(x[2]) > GATE_DU;
 }
 
-// Learned-guess features of a face in its frame (left and right states).
-__device__ inline void face_features(float rL, float uL, float pL, float cL, float rR, float uR,
-                                     float pR, float cR, float x[NIN]) {
-  auto slog = [](float v) { return copysignf(log1pf(fabsf(v)), v); };
+// Which estimate the plain starting value p0 is (Toro's adaptive choice).
+enum GuessBranch { GUESS_PV = 0, GUESS_TR = 1, GUESS_TS = 2 };
+
+// Learned-guess features of a face's Riemann problem: the density and
+// pressure ratios, the normal velocity jump over the mean sound speed, and
+// the plain starting value p0 with the estimate it came from.  p* depends on
+// the states only through the first three (and gamma); p0 and its branch tell
+// the network where the error it predicts, ln(p*/p0), jumps.
+__device__ inline void face_features(float rL, float pL, float rR, float pR, float du, float cL,
+                                     float cR, float p0, int branch, float x[NIN]) {
+  const float v = du / (0.5f * (cL + cR));
   x[0] = logf(rL / rR);
   x[1] = logf(pL / pR);
-  x[2] = slog((uR - uL) / (0.5f * (cL + cR)));
-  x[3] = slog(uL / cL);
-  x[4] = slog(uR / cR);
-  x[5] = logf(cL / cR);
+  x[2] = copysignf(log1pf(fabsf(v)), v);
+  x[3] = logf(p0 / (0.5f * (pL + pR)));
+  x[4] = branch == GUESS_TR ? 1.0f : 0.0f;
+  x[5] = branch == GUESS_TS ? 1.0f : 0.0f;
 }
 
 }  // namespace mlp

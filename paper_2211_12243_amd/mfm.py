@@ -385,7 +385,7 @@ def run_pipeline(ctx: Context, ps: ParticleSet, dt_max: float, update: bool = Tr
 # --- learned Riemann guess ------------------------------------------------------------------
 
 MLP_NIN, MLP_K1, MLP_HID, MLP_NNORM = 6, 16, 64, 16
-DUMP_STRIDE = 8  # floats per face record: 6 features, ln(p*/P_avg), plain-guess iterations
+DUMP_STRIDE = 8  # floats per face record: 6 features, ln(p*/p0), Newton iterations
 
 
 GATE_LOG_P = 0.69314718  # ln 2: pressure ratio above 2

@@ -136,14 +136,17 @@ def _dump_faces(st, cfg, cap, precision="fp64", steps_before=0):
     return rec[:count], diag
 
 
-def _target_from_features(x, gamma):
-    """ln(p*/P_avg) of the states that a record's features describe (right
-    state rho = P = 1 at rest; the ratio depends only on the three groups)."""
+def _problem_of_features(x, gamma):
+    """The Riemann problem a record's first three features describe (right
+    state rho = P = 1 at rest; p* and the starting value p0 scale with the
+    pressure, so their ratios depend only on these groups): the solver's
+    status, ln(p*/p0), ln(p0/P_avg) and the estimate p0 came from."""
     rhoL, PL = math.exp(x[0]), math.exp(x[1])
     cL, cR = math.sqrt(gamma * PL / rhoL), math.sqrt(gamma)
     du = math.copysign(math.expm1(abs(x[2])), x[2]) * 0.5 * (cL + cR)
     s, ps, _, _ = oracle.riemann(gamma, rhoL, 0.0, PL, 1.0, du, 1.0)
-    return s, math.log(ps / (0.5 * (PL + 1.0)))
+    p0, b = oracle.riemann_guess(gamma, rhoL, 0.0, PL, 1.0, du, 1.0, with_branch=True)
+    return s, math.log(ps / p0), math.log(p0 / (0.5 * (PL + 1.0))), b
 
 
 @pytest.mark.parametrize("precision", ["fp64", "mixed"])
@@ -159,55 +162,71 @@ def test_face_dump_against_exact_solver(precision):
     # every face's iterations are counted once: the dump holds all of them
     assert int(r[:, 7].sum()) == diag["riemann_iters"]
     assert np.all(r[:, 7] >= 1)
-    # the sound-speed ratio is fixed by the density and pressure ratios
-    assert np.abs(r[:, 5] - 0.5 * (r[:, 1] - r[:, 0])).max() <= 2e-5
+    # the branch indicators: at most one is set
+    assert np.all(np.isin(r[:, 4], (0.0, 1.0)) & np.isin(r[:, 5], (0.0, 1.0)))
+    assert np.all(r[:, 4] + r[:, 5] <= 1.0)
     rng = np.random.default_rng(0)
-    worst = 0.0
+    worst, worst_p0, other_branch = 0.0, 0.0, 0
     for k in rng.choice(n, 1500, replace=False):
-        s, y = _target_from_features(r[k], 5.0 / 3.0)
+        s, y, lp0, b = _problem_of_features(r[k], 5.0 / 3.0)
         assert s == 0
+        if (b == 1) != (r[k, 4] == 1.0) or (b == 2) != (r[k, 5] == 1.0):
+            # the rebuilt states sit on a boundary between two estimates
+            # (features are rounded to FP32)
+            other_branch += 1
+            continue
         worst = max(worst, abs(y - r[k, 6]))
-    print(f"dumped target vs exact solver: max abs error {worst:.2e}", flush=True)
-    assert worst <= 1e-4
+        worst_p0 = max(worst_p0, abs(lp0 - r[k, 3]))
+    print(f"dumped target vs exact solver: max abs error {worst:.2e}; starting value "
+          f"{worst_p0:.2e}; {other_branch} of 1500 on another estimate", flush=True)
+    assert worst <= 1e-4 and worst_p0 <= 1e-4 and other_branch <= 3
 
 
-def _train(rows_dev, steps, lr, batch, seed=0):
-    r = rows_dev.cpu().numpy().astype(np.float64)
-    norm = omlp.norm_from(r[:, :6], r[:, 6]).astype(np.float32)
-    st = mfm.MLPState(omlp.init_params(seed).astype(np.float32), norm)
-    n = rows_dev.shape[0]
-    g = torch.Generator(device="cpu").manual_seed(seed)
-    losses = []
-    for it in range(steps):
-        idx = torch.randint(0, n, (batch,), generator=g).cuda()
-        want = it % 50 == 0 or it == steps - 1
-        l = mfm.mfm_mlp_train_step(st, rows_dev[idx].contiguous(), lr, want_loss=want)
-        if want:
-            losses.append(l)
+@pytest.fixture(scope="module")
+def trained_guess():
+    """The guess network trained as the library's training loop does it
+    (paper_2211_12243_amd.learned) on the gated faces dumped by plain runs of
+    four small sets other than the ones the tests below score it on: the
+    shock tube (MFV, 3 steps), a Sedov blast (MFM mixed, 5 steps after 5),
+    the shear layers (MFM, 3 steps) and the clustered gas (MFM mixed, 1 step)."""
+    from paper_2211_12243_amd import learned
+
+    _need_gpu()
+    parts = []
+    for k, (st, cfg, precision, skip, steps) in enumerate((
+            (W.sod(n=24, seed=21), {"scheme": "mfv"}, "fp64", 0, 3),
+            (W.sedov(n=32, seed=11), {"scheme": "mfm"}, "mixed", 5, 5),
+            (W.kh(n=32, seed=5), {"scheme": "mfm"}, "fp64", 0, 3),
+            (W.clustered(n=32, seed=6), {"scheme": "mfm"}, "mixed", 0, 1))):
+        ctx = mfm.Context(mfm.params_from_dict(cfg, precision=precision), len(st["x"]))
+        ps = mfm.ParticleSet(st, ids=False)
+        for _ in range(skip):
+            mfm.mfm_step(ctx, ps, 1.0)
+        col = learned.Collector(ctx, 24 * ps.n, 0.0, seed=k)
+        for _ in range(steps):
+            col.step(ps)
+        parts.append(col.rows())
+        ctx.close()
+    rows = torch.cat(parts)
+    print(f"[mlp] {rows.shape[0]} gated training faces", flush=True)
+    assert rows.shape[0] > 1000
+    st, losses = learned.train(rows, 6000, batch=8192, lr=3e-3, seed=0)
+    print(f"[mlp] loss {losses[0]:.3e} -> {losses[-1]:.3e}", flush=True)
     return st, losses
 
 
-def test_training_and_learned_guess_parity():
-    _need_gpu()
-    print("[mlp] train on faces of sod24 and sedov32 (after 5 steps)", flush=True)
-    parts = []
-    for st, cfg, k in ((W.sod(n=24, seed=21), {"scheme": "mfv"}, 0),
-                       (W.sedov(n=32, seed=11), {"scheme": "mfm"}, 5)):
-        rec, _ = _dump_faces(st, cfg, 4_000_000, steps_before=k)
-        parts.append(rec[mfm.guess_gate(rec)])
-    rec = torch.cat(parts)
-    print(f"{rec.shape[0]} training faces pass the gate", flush=True)
-    assert rec.shape[0] > 1000
-    st, losses = _train(rec, 400, 3e-3, 4096)
-    print("losses", [f"{v:.3e}" for v in losses], flush=True)
+def test_training_and_learned_guess_parity(trained_guess):
+    from paper_2211_12243_amd import learned
+
+    st, losses = trained_guess
     assert losses[-1] < 0.3 * losses[0]
-    # held-out set: prediction error of ln(p*/P_avg)
+    # held-out set: prediction error of ln(p*/p0)
     test_rows, _ = _dump_faces(W.sod(n=16, seed=12), {"scheme": "mfv"}, 2_000_000)
-    test_rows = test_rows[mfm.guess_gate(test_rows)]
-    y = mfm.mfm_mlp_predict(st, test_rows).cpu().numpy()
-    t = test_rows[:, 6].cpu().numpy()
-    print(f"held-out rms error of ln(p*/P_avg): {np.sqrt(np.mean((y - t) ** 2)):.3e}, "
-          f"target std {t.std():.3e}", flush=True)
+    t = test_rows[mfm.guess_gate(test_rows)][:, 6].cpu().numpy()
+    rms = learned.rms_error(st, test_rows)
+    print(f"held-out rms error of ln(p*/p0): {rms:.3e}, target std {t.std():.3e}",
+          flush=True)
+    assert rms < 0.5 * t.std()
 
     def attach(ctx):
         mfm.mfm_mlp_attach(ctx, st)
@@ -216,21 +235,64 @@ def test_training_and_learned_guess_parity():
              ("sedov24", W.sedov(n=24, seed=3), {"scheme": "mfm"}))
     for name, state, cfg in cases:
         for precision, tol in (("fp64", 1e-12), ("mixed", 1e-5)):
-            plain_rec, plain = _dump_faces(state, cfg, 2_000_000, precision)
-            hard = mfm.guess_gate(plain_rec)
-            nh = max(int(hard.sum()), 1)
-            it_hard_plain = float(plain_rec[hard][:, 7].sum())
+            _, plain = _dump_faces(state, cfg, 2_000_000, precision)
             print(f"[mlp] learned-guess parity {name} {precision}", flush=True)
             gpu, new, dt, diag, ref = run_both(dict(cfg, guess=1), state, precision=precision,
                                                setup=attach)
             check_fields(gpu, new, dt, diag, ref, tol, state, normwise=(precision == "mixed"))
-            saved = plain["riemann_iters"] - diag["riemann_iters"]
-            print(f"{name} {precision}: {int(hard.sum())} of {diag['faces']} faces gated; Newton "
-                  f"steps on them plain {it_hard_plain / nh:.3f}/face, learned "
-                  f"{(it_hard_plain - saved) / nh:.3f}/face; fallbacks "
-                  f"{diag['guess_fallback']}", flush=True)
+            print(f"{name} {precision}: Newton steps {plain['riemann_iters']} plain, "
+                  f"{diag['riemann_iters']} learned; fallbacks {diag['guess_fallback']}",
+                  flush=True)
             assert diag["faces"] == plain["faces"]
-            assert diag["guess_fallback"] < nh
+
+
+# Newton steps per gated face that the trained guess must save against
+# Toro's adaptive guess, on sets it was not trained on (observed on MI355X
+# over several trainings: 0.85-1.0 on the shock tube, 0.35-0.55 on the Sedov
+# blast; the plain guess takes about 3)
+GAIN_MARGIN = 0.25
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+@pytest.mark.parametrize("name,make,cfg,skip", [
+    ("sod16_mfv", lambda: W.sod(n=16, seed=12), {"scheme": "mfv"}, 5),
+    ("sedov24_mfm", lambda: W.sedov(n=24, seed=3), {"scheme": "mfm"}, 10),
+], ids=["sod16_mfv", "sedov24_mfm"])
+def test_learned_guess_saves_newton_steps(trained_guess, name, make, cfg, skip, precision):
+    """From the same state (after `skip` plain steps), one step with the plain
+    guess and one with the trained network, every face dumped: the faces the
+    gate hands to the network take at least GAIN_MARGIN fewer Newton steps on
+    average, and fewer than 5% of them fall back to the plain guess."""
+    from paper_2211_12243_amd import learned
+
+    st, _ = trained_guess
+    state = make()
+    ctx = mfm.Context(mfm.params_from_dict(cfg, precision=precision), len(state["x"]))
+    ps = mfm.ParticleSet(state, ids=False)
+    for _ in range(skip):
+        mfm.mfm_step(ctx, ps, 1.0)
+    start = ps.host(["x", "y", "z", "vx", "vy", "vz", "m", "E", "U", "H"])
+    ctx.close()
+    out = {}
+    for guess in (0, 1):
+        ctx = mfm.Context(mfm.params_from_dict(dict(cfg, guess=guess), precision=precision),
+                          len(state["x"]))
+        if guess:
+            mfm.mfm_mlp_attach(ctx, st)
+        ps = mfm.ParticleSet(start, ids=False)
+        col = learned.Collector(ctx, 24 * ps.n, None, seed=0)
+        col.step(ps)
+        out[guess] = learned.iteration_stats(col.rows())
+        out[guess]["fallbacks"] = mfm.mfm_diagnostics(ctx)["guess_fallback"]
+        ctx.close()
+    p, l = out[0], out[1]
+    print(f"[mlp] {name} {precision}: {p['gated']} of {p['faces']} faces gated; Newton steps "
+          f"per gated face plain {p['gated_mean']:.3f} (p99 {p['gated_p99']}), learned "
+          f"{l['gated_mean']:.3f} (p99 {l['gated_p99']}); all faces {p['all_mean']:.3f} -> "
+          f"{l['all_mean']:.3f}; fallbacks {l['fallbacks']}", flush=True)
+    assert p["gated"] > 100 and l["gated"] == p["gated"]
+    assert l["gated_mean"] <= p["gated_mean"] - GAIN_MARGIN
+    assert l["fallbacks"] < 0.05 * l["gated"]
 
 
 def test_garbage_weights_fall_back():

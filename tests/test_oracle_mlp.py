@@ -106,17 +106,32 @@ def test_adam_first_step_closed_form():
     assert np.allclose(p1 - p2, 1e-2 * g / (np.abs(g) + 1e-8), rtol=1e-12, atol=0)
 
 
+def _guess(g, rL, uL, pL, rR, uR, pR):
+    out = [oracle.riemann_guess(g, *s, with_branch=True) for s in zip(rL, uL, pL, rR, uR, pR)]
+    return np.array([o[0] for o in out]), np.array([o[1] for o in out])
+
+
 def test_feature_mirror_symmetry():
+    """The mirrored problem (left and right swapped, velocities reversed) has
+    the same p*, the same velocity jump and the same starting value and
+    branch: only the two ratios change sign.  Identical states at rest give
+    zero features (the primitive-variable estimate is their pressure)."""
     rng = np.random.default_rng(9)
     rL, rR, pL, pR = rng.uniform(0.1, 3, (4, 20))
     uL, uR = rng.normal(0, 2, (2, 20))
     g = 5.0 / 3.0
     cL, cR = np.sqrt(g * pL / rL), np.sqrt(g * pR / rR)
-    f = mlp.features(rL, uL, pL, cL, rR, uR, pR, cR)
-    m = mlp.features(rR, -uR, pR, cR, rL, -uL, pL, cL)
-    np.testing.assert_allclose(m, np.stack([-f[:, 0], -f[:, 1], f[:, 2], -f[:, 4], -f[:, 3],
-                                            -f[:, 5]], axis=1), rtol=1e-14, atol=1e-15)
-    same = mlp.features(rL, 0 * uL, pL, cL, rL, 0 * uL, pL, cL)
+    p0, b = _guess(g, rL, uL, pL, rR, uR, pR)
+    p0m, bm = _guess(g, rR, -uR, pR, rL, -uL, pL)
+    np.testing.assert_allclose(p0m, p0, rtol=1e-14)
+    assert np.array_equal(bm, b)
+    f = mlp.features(rL, pL, rR, pR, uR - uL, cL, cR, p0, b)
+    m = mlp.features(rR, pR, rL, pL, (-uL) - (-uR), cR, cL, p0m, bm)
+    np.testing.assert_allclose(m, np.stack([-f[:, 0], -f[:, 1], f[:, 2], f[:, 3], f[:, 4],
+                                            f[:, 5]], axis=1), rtol=1e-13, atol=1e-15)
+    assert set(np.unique(b)) >= {1, 2}  # both outer estimates occur in the sample
+    p0s, bs = _guess(g, rL, 0 * uL, pL, rL, 0 * uL, pL)
+    same = mlp.features(rL, pL, rL, pL, 0 * uL, cL, cL, p0s, bs)
     assert np.all(same == 0.0)
 
 

@@ -126,3 +126,50 @@ def test_strong_pressure_ratio_converges():
         assert st == 0 and it < 30
         st2, ps2, us2, _ = oracle.riemann(5 / 3, 1.0, 0.0, 1.0, 1.0, 0.0, ratio)
         assert ps == pytest.approx(ps2, rel=1e-12)
+
+
+@pytest.mark.parametrize("uL,uR,PL,PR", [(-1.0, 1.0, 1.0, 1.0), (-0.5, 1.2, 0.8, 1.5),
+                                          (0.0, 2.0, 2.0, 0.6)])
+def test_starting_value_is_exact_for_two_rarefactions(uL, uR, PL, PR):
+    """Toro's adaptive starting value takes the two-rarefaction estimate
+    when the primitive-variable one falls below both pressures; that
+    estimate is the exact p* when both waves are rarefactions."""
+    g = 1.4
+    st, ps, _, _ = oracle.riemann(g, 1.0, uL, PL, 0.7, uR, PR)
+    assert st == 0 and ps < min(PL, PR)
+    assert oracle.riemann_guess(g, 1.0, uL, PL, 0.7, uR, PR) == pytest.approx(ps, rel=1e-12)
+
+
+def test_starting_value_of_close_states():
+    """Identical states at rest: the primitive-variable estimate is the
+    common pressure.  A small pressure jump delta: its error is of second
+    order (the estimate linearises the wave curves about the mean state), so
+    halving delta divides it by about four."""
+    g = 5.0 / 3.0
+    assert oracle.riemann_guess(g, 1.2, 0.0, 0.9, 1.2, 0.0, 0.9) == 0.9
+    err = []
+    for d in (0.2, 0.1, 0.05):
+        st, ps, _, _ = oracle.riemann(g, 1.0, 0.0, 1.0 + d, 1.0, 0.0, 1.0)
+        assert st == 0
+        err.append(abs(oracle.riemann_guess(g, 1.0, 0.0, 1.0 + d, 1.0, 0.0, 1.0) - ps) / ps)
+    assert all(3.0 < a / b < 5.0 for a, b in zip(err, err[1:])), err
+
+
+def test_starting_value_of_strong_shocks_and_floor():
+    """Colliding flows (two shocks, p* above both pressures): the two-shock
+    estimate, evaluated at the primitive-variable pressure, lies between the
+    states' pressure and p*; within 10% of p* for a weak collision, while for
+    hypersonic ones it falls far short (0.37 p* at Mach 7, 0.03 p* at Mach
+    800) -- the faces where Newton needs the most steps.  Near vacuum the
+    value is kept above the pressure floor 1e-10 (P_L + P_R) / 2."""
+    g = 5.0 / 3.0
+    for U, rho, P in ((1.0, 1.0, 1.0), (5.0, 0.5, 0.2), (30.0, 1.0, 1e-3)):
+        st, ps, _, _ = oracle.riemann(g, rho, U, P, rho, -U, P)
+        p0 = oracle.riemann_guess(g, rho, U, P, rho, -U, P)
+        assert st == 0 and P < p0 < ps
+        if U == 1.0:
+            assert abs(p0 - ps) < 0.1 * ps
+    c = math.sqrt(g)
+    du = 2.0 / (g - 1.0) * 2 * c * (1 - 1e-9)  # just short of the vacuum condition
+    p0 = oracle.riemann_guess(g, 1.0, -0.5 * du, 1.0, 1.0, 0.5 * du, 1.0)
+    assert p0 >= 1e-10
