@@ -90,6 +90,10 @@ def parse():
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="first copy a buffer of this many MiB on the device (a kernel of "
                          "known traffic, to calibrate hardware byte counters)")
+    ap.add_argument("--no-small-configs", dest="small_configs", action="store_false",
+                    help="skip the 16^3 shock tube and 64^3 shear-layer timings")
+    ap.add_argument("--no-error-growth", dest="error_growth", action="store_false",
+                    help="skip the multi-step comparison with the oracle (CPU leg)")
     ap.add_argument("--quiet", action="store_true")
     return ap.parse_args()
 
@@ -501,6 +505,113 @@ def guess_pair(st, scheme, precision, mlp_state, log_, name):
     return out
 
 
+def run_small_configs(args, log_):
+    """The shock tube (16^3, MFV, FP64: one full step) and the shear layers
+    (64^3, MFV and MFM, FP64 and mixed: 10 steps after 2 warm-up steps):
+    ms per step and pair interactions/s per set."""
+    import torch
+
+    from paper_2211_12243_amd import mfm
+    from paper_2211_12243_amd import workloads as W
+
+    out = {}
+    for name, make, scheme, precision, steps in (
+            ("sod16_mfv_fp64", lambda: W.sod(n=16, seed=1), "mfv", "fp64", 1),
+            ("kh64_mfv_fp64", lambda: W.kh(n=64, seed=2), "mfv", "fp64", 10),
+            ("kh64_mfv_mixed", lambda: W.kh(n=64, seed=2), "mfv", "mixed", 10),
+            ("kh64_mfm_fp64", lambda: W.kh(n=64, seed=2), "mfm", "fp64", 10),
+            ("kh64_mfm_mixed", lambda: W.kh(n=64, seed=2), "mfm", "mixed", 10)):
+        st = make()
+        n = len(st["x"])
+        ctx = mfm.Context(mfm.params_from_dict({"scheme": scheme}, precision=precision), n)
+        ps = mfm.ParticleSet(st, ids=False)
+        if steps > 1:
+            for _ in range(2):
+                mfm.mfm_step(ctx, ps, 1.0)
+        mfm.mfm_reset_counters(ctx)
+        mfm.mfm_enable_timing(ctx, True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            mfm.mfm_step(ctx, ps, 1.0)
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) / steps * 1e3
+        times = mfm.mfm_kernel_times(ctx)
+        d = mfm.mfm_diagnostics(ctx, ps)
+        ctx.close()
+        t_pairs = (times["gradients"][0] + times["fluxes"][0]) / 1e3
+        out[name] = {"particles": n, "steps": steps, "ms_per_step": ms,
+                     "pair_interactions_per_s": (d["grad_pairs"] + d["faces"]) / t_pairs,
+                     "stage_ms_per_step": {k: v[0] / steps for k, v in times.items()}}
+        log_(f"[bench] {name}: {out[name]}")
+    return out
+
+
+def _state_error(gpu, ref):
+    """Per-field difference of two particle states: positions absolute
+    (periodic, unit box), velocities against the largest velocity component,
+    mass, energy and internal energy against their largest value."""
+    import numpy as np
+
+    vscale = max(float(np.abs(ref[k]).max()) for k in ("vx", "vy", "vz"))
+    out = {}
+    for k in ("x", "y", "z", "vx", "vy", "vz", "m", "E", "U"):
+        d = np.abs(gpu[k] - ref[k])
+        if k in ("x", "y", "z"):
+            out[k] = float(np.minimum(d, 1.0 - d).max())
+        elif k in ("vx", "vy", "vz"):
+            out[k] = float(d.max() / max(vscale, 1e-300))
+        else:
+            out[k] = float(d.max() / max(float(np.abs(ref[k]).max()), 1e-300))
+    return out
+
+
+def error_growth(name, st, scheme, precisions, steps, log_):
+    """The oracle and one GPU context per precision each step their own copy
+    of the set `steps` times (each with its own time step): the largest
+    field difference after every step, the per-field differences after the
+    last, the largest relative difference of the time steps."""
+    import numpy as np
+    import torch
+
+    import oracle
+    from paper_2211_12243_amd import mfm
+
+    cfg = {"scheme": scheme}
+    n = len(st["x"])
+    sides = {}
+    for prec in precisions:
+        ctx = mfm.Context(mfm.params_from_dict(cfg, precision=prec), n)
+        sides[prec] = (ctx, mfm.ParticleSet(st))
+    ref = {k: np.asarray(st[k], dtype=np.float64).copy() for k in oracle.STATE_KEYS}
+    res = {p: {"max_error_per_step": [], "dt_rel_diff_max": 0.0} for p in precisions}
+    t0 = time.perf_counter()
+    for s in range(steps):
+        ref, dt_ref, _ = oracle.step(cfg, ref, 1.0)
+        for prec, (ctx, ps) in sides.items():
+            dt = mfm.mfm_step(ctx, ps, 1.0)
+            torch.cuda.synchronize()
+            ids = ps["id"].cpu().numpy()
+            gpu = {}
+            for k in ("x", "y", "z", "vx", "vy", "vz", "m", "E", "U"):
+                a = np.empty(n)
+                a[ids] = ps[k].cpu().numpy()
+                gpu[k] = a
+            e = _state_error(gpu, ref)
+            r = res[prec]
+            r["max_error_per_step"].append(max(e.values()))
+            r["dt_rel_diff_max"] = max(r["dt_rel_diff_max"], abs(dt - dt_ref) / dt_ref)
+            r["last_step"] = e
+        log_(f"[bench] error growth {name}: step {s + 1} of {steps}, " + ", ".join(
+            f"{p} {res[p]['max_error_per_step'][-1]:.2e}" for p in precisions))
+    for ctx, _ in sides.values():
+        ctx.close()
+    out = {"particles": n, "scheme": scheme, "steps": steps,
+           "wall_s": time.perf_counter() - t0, **res}
+    log_(f"[bench] error growth {name}: {out}")
+    return out
+
+
 def run_clustered(args, st, log_, mlp_state=None):
     """The clustered gas (log-normal density, sigma_ln = 1.5; smoothing lengths
     spread over a factor of about 30): mixed MFM, the first step from the
@@ -615,6 +726,7 @@ def main():
              if args.rung_base > 0 and "fp64" in res else None)
     clustered = run_clustered(args, c4, log_, mlp_state) if args.clustered > 0 else None
     del c4
+    small = run_small_configs(args, log_) if args.small_configs else None
     h = res[args.headline]
     out = {
         "metric": "pair interactions/s (grad+flux) & hydro-step ms, 2.1M Sedov, mixed vs FP64",
@@ -642,11 +754,21 @@ def main():
         "guess_training": train_info,
         "individual_steps": rungs,
         "clustered": clustered,
+        "small_configs": small,
     }
     if not args.no_cpu_baseline:
         fields = {v: step1_fields(args, st, v) for v in ("fp64", "mixed") if v in variants}
         log_("[bench] timing the CPU oracle on one step of the same set")
         out["cpu_baseline"] = cpu_baseline(st, args.scheme, fields)
+        if args.error_growth:
+            from paper_2211_12243_amd import workloads as W
+
+            both = ("fp64", "mixed")
+            out["error_growth"] = {
+                "kh64_mfv": error_growth("kh64_mfv", W.kh(n=64, seed=2), "mfv", both, 10, log_),
+                "kh64_mfm": error_growth("kh64_mfm", W.kh(n=64, seed=2), "mfm", both, 10, log_),
+                f"sedov{args.n}_mfm": error_growth(f"sedov{args.n}_mfm", st, "mfm", both, 20,
+                                                   log_)}
     else:
         out["cpu_baseline"] = None
     print(json.dumps(out), flush=True)
