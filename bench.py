@@ -59,7 +59,11 @@ FLOPS_PER_GRAD_PAIR = 151.0
 #             dt_i, ncond written: 288 B
 #   fluxes    B, grad, primitives, position, V, 1/H read (32 doubles), dQ (5)
 #             written: 296 B
-BYTES_PER_PARTICLE = {"cells": 184, "density": 80, "gradients": 288, "fluxes": 296}
+#   search    position and H read (32 B), the candidate count and the list
+#             written (index + r^2, 12 B per candidate; 35 per particle on the
+#             128^3 Sedov set): 456 B
+BYTES_PER_PARTICLE = {"cells": 184, "density": 80, "gradients": 288, "fluxes": 296,
+                      "search": 456}
 PEAK_FP64_TFLOPS = 78.6
 PEAK_FP32_TFLOPS = 157.3
 PEAK_HBM_TBS = 8.0
@@ -392,7 +396,7 @@ def run_variant(args, st, variant, mlp_state, log_):
     kernels = {}
     for stage, unit_flops in (("gradients", FLOPS_PER_GRAD_PAIR * diag["grad_pairs"] / K),
                               ("fluxes", FLOPS_PER_FACE[args.scheme] * diag["faces"] / K),
-                              ("density", None), ("cells", None)):
+                              ("density", None), ("cells", None), ("search", None)):
         t = times[stage][0] / 1e3 / K
         hbm = BYTES_PER_PARTICLE[stage] * N / t / 1e12
         e = {"ms": t * 1e3, "hbm_TBs": hbm, "hbm_frac": hbm / PEAK_HBM_TBS}
@@ -401,7 +405,6 @@ def run_variant(args, st, variant, mlp_state, log_):
             e["valu_frac"] = e["TFLOPs"] / peak
         e["frac"] = max(e.get("valu_frac", 0.0), e["hbm_frac"])
         kernels[stage] = e
-    kernels["search"] = {"ms": times["search"][0] / K}
     res = {
         "value": pairs / (t_grad + t_flux),
         "ms_per_step": (t1 - t0) / K * 1e3,
