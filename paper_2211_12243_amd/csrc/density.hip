@@ -101,269 +101,274 @@ __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) ca
   const int lane = threadIdx.x;
   const int64_t n = a.n;
   int64_t overflow = 0;
-  const int bucket = xcd_block(blockIdx.x, gridDim.x);
-  const int own_x = bucket * BUCKET;
-  const int own_y = (int)min((int64_t)BUCKET, n - own_x);
   // a planned pool that does not fit leaves every chunk without room (and
   // the pass fails as a list overflow)
   const bool no_room = a.count_only || a.counters[C_LIST_POOL] != 0;
-  for (int t0 = 0; t0 < own_y; t0 += TCH) {
-    const int T = min(TCH, own_y - t0);
-    // on individual steps, only chunks with a particle whose step begins
-    // need lists (wave-uniform)
-    if (a.act && !__ballot(lane < T && a.act[own_x + t0 + lane])) continue;
-    const int64_t chunk = (own_x + t0) / LCH;
-    const int64_t seg0 = no_room ? 0 : a.lseg[chunk];
-    const int cap = no_room ? 0 : (int)((a.lseg[chunk + 1] - seg0) / LCH);
-    // lane t holds particle t of the chunk and the length of its list; the
-    // loop below broadcasts both
-    int tcnt = 0;
-    double tx = 0.0, ty = 0.0, tz = 0.0, tq = 0.0, th = 0.0;
-    const double4 p0 = a.pos[own_x + t0];
-    double blo[3] = {p0.x, p0.y, p0.z}, bhi[3] = {p0.x, p0.y, p0.z};
-    if (lane < T) {
-      const double4 pt = a.pos[own_x + t0 + lane];
-      tx = pt.x; ty = pt.y; tz = pt.z;
-      th = g.hfac * pt.w;
-      tq = th * th;  // squared radius of the particle's own H
-      blo[0] = bhi[0] = tx;
-      blo[1] = bhi[1] = ty;
-      blo[2] = bhi[2] = tz;
-    }
-    // the chunk's box and radius
-    // (wave-uniform: held in scalar registers)
-    double bc[3], bh[3];
-#pragma unroll
-    for (int k = 0; k < 3; ++k) {
-      const double lo = wave_min_f64(blo[k]), hi = wave_max_f64(bhi[k]);
-      bc[k] = uniform_f64(0.5 * (lo + hi));
-      bh[k] = uniform_f64(0.5 * (hi - lo));
-    }
-    const double Rc = uniform_f64(wave_max_f64(th));
-    // a node is opened when its box and the chunk's are closer than the
-    // larger radius (raised by 1e-12 so that rounding in the box distance
-    // cannot drop a pair at the edge)
-    auto opens = [&](const double *nd) {
-      double gap2 = 0.0;
-#pragma unroll
+  const int nbuckets = (int)((n + BUCKET - 1) / BUCKET);
+  // one bucket per workgroup on a full pass; on the sub-steps of individual
+  // time steps a capped grid strides over the buckets
+  for (int bucket = xcd_block(blockIdx.x, gridDim.x); bucket < nbuckets; bucket += gridDim.x) {
+    const int own_x = bucket * BUCKET;
+    const int own_y = (int)min((int64_t)BUCKET, n - own_x);
+    for (int t0 = 0; t0 < own_y; t0 += TCH) {
+      const int T = min(TCH, own_y - t0);
+      // on individual steps, only chunks with a particle whose step begins
+      // need lists (wave-uniform)
+      if (a.act && !__ballot(lane < T && a.act[own_x + t0 + lane])) continue;
+      const int64_t chunk = (own_x + t0) / LCH;
+      const int64_t seg0 = no_room ? 0 : a.lseg[chunk];
+      const int cap = no_room ? 0 : (int)((a.lseg[chunk + 1] - seg0) / LCH);
+      // lane t holds particle t of the chunk and the length of its list; the
+      // loop below broadcasts both
+      int tcnt = 0;
+      double tx = 0.0, ty = 0.0, tz = 0.0, tq = 0.0, th = 0.0;
+      const double4 p0 = a.pos[own_x + t0];
+      double blo[3] = {p0.x, p0.y, p0.z}, bhi[3] = {p0.x, p0.y, p0.z};
+      if (lane < T) {
+        const double4 pt = a.pos[own_x + t0 + lane];
+        tx = pt.x; ty = pt.y; tz = pt.z;
+        th = g.hfac * pt.w;
+        tq = th * th;  // squared radius of the particle's own H
+        blo[0] = bhi[0] = tx;
+        blo[1] = bhi[1] = ty;
+        blo[2] = bhi[2] = tz;
+      }
+      // the chunk's box and radius
+      // (wave-uniform: held in scalar registers)
+      double bc[3], bh[3];
+  #pragma unroll
       for (int k = 0; k < 3; ++k) {
-        double d = fabs(0.5 * (nd[k] + nd[3 + k]) - bc[k]);
-        d = fmin(d, g.box[k] - d);  // periodic images of the centres
-        const double gk = fmax(0.0, d - 0.5 * (nd[3 + k] - nd[k]) - bh[k]);
-        gap2 += gk * gk;
+        const double lo = wave_min_f64(blo[k]), hi = wave_max_f64(bhi[k]);
+        bc[k] = uniform_f64(0.5 * (lo + hi));
+        bh[k] = uniform_f64(0.5 * (hi - lo));
       }
-      const double R = fmax(Rc, nd[6]) * (1.0 + 1e-12);
-      return gap2 < R * R;
-    };
-    // breadth-first walk from the top node.  When a level would accept more
-    // nodes than the LDS holds (a chunk of wide particles), the walk stops
-    // above it and the buckets under the accepted nodes are tested one by
-    // one below.
-    int cur = 0, nf = 1, lev_stop = 0;
-    if (lane == 0) s_f[0][0] = 0;
-    __syncthreads();
-    for (int lev = g.nlev - 1; lev > 0; --lev) {
-      const int cl = lev - 1, cnt_c = g.lev_cnt[cl];
-      const double *nodes = g.node + (int64_t)g.lev_off[cl] * TNODE;
-      int nn = 0;
-      const int total = nf * TREE_FANOUT;
-      for (int u0 = 0; u0 < total; u0 += 64) {
-        const int u = u0 + lane;
-        bool open = false;
-        int child = 0;
-        if (u < total) {
-          child = s_f[cur][u / TREE_FANOUT] * TREE_FANOUT + u % TREE_FANOUT;
-          if (child < cnt_c) open = opens(nodes + (int64_t)child * TNODE);
+      const double Rc = uniform_f64(wave_max_f64(th));
+      // a node is opened when its box and the chunk's are closer than the
+      // larger radius (raised by 1e-12 so that rounding in the box distance
+      // cannot drop a pair at the edge)
+      auto opens = [&](const double *nd) {
+        double gap2 = 0.0;
+  #pragma unroll
+        for (int k = 0; k < 3; ++k) {
+          double d = fabs(0.5 * (nd[k] + nd[3 + k]) - bc[k]);
+          d = fmin(d, g.box[k] - d);  // periodic images of the centres
+          const double gk = fmax(0.0, d - 0.5 * (nd[3 + k] - nd[k]) - bh[k]);
+          gap2 += gk * gk;
         }
-        const uint64_t m = __ballot(open);
-        const int k = nn + lanes_below(m);
-        if (open && k < MAXF) s_f[cur ^ 1][k] = child;
-        nn += __popcll(m);
-      }
+        const double R = fmax(Rc, nd[6]) * (1.0 + 1e-12);
+        return gap2 < R * R;
+      };
+      // breadth-first walk from the top node.  When a level would accept more
+      // nodes than the LDS holds (a chunk of wide particles), the walk stops
+      // above it and the buckets under the accepted nodes are tested one by
+      // one below.
+      int cur = 0, nf = 1, lev_stop = 0;
+      if (lane == 0) s_f[0][0] = 0;
       __syncthreads();
-      if (nn > MAXF) {  // wave-uniform
-        lev_stop = lev;
-        break;
-      }
-      cur ^= 1;
-      nf = nn;
-    }
-    // the accepted buckets in index order: the frontier's nodes, each
-    // expanded to the buckets under it when the walk stopped early
-    // (64 at a time across the lanes; bmask holds the accepted ones of the
-    // last 64, from bbase)
-    const int span = 3 * lev_stop;  // TREE_FANOUT = 2^3 nodes per level
-    const int64_t nb0 = g.lev_cnt[0];
-    int q = 0;
-    int64_t bk = 0, bend = 0, bbase = 0;
-    uint64_t bmask = 0;
-    auto next_bucket = [&]() -> int {
-      if (span == 0) return q < nf ? s_f[cur][q++] : -1;  // accepted by the walk
-      for (;;) {
-        if (bmask) {
-          const int t = __ffsll((unsigned long long)bmask) - 1;
-          bmask &= bmask - 1;
-          return (int)(bbase + t);
+      for (int lev = g.nlev - 1; lev > 0; --lev) {
+        const int cl = lev - 1, cnt_c = g.lev_cnt[cl];
+        const double *nodes = g.node + (int64_t)g.lev_off[cl] * TNODE;
+        int nn = 0;
+        const int total = nf * TREE_FANOUT;
+        for (int u0 = 0; u0 < total; u0 += 64) {
+          const int u = u0 + lane;
+          bool open = false;
+          int child = 0;
+          if (u < total) {
+            child = s_f[cur][u / TREE_FANOUT] * TREE_FANOUT + u % TREE_FANOUT;
+            if (child < cnt_c) open = opens(nodes + (int64_t)child * TNODE);
+          }
+          const uint64_t m = __ballot(open);
+          const int k = nn + lanes_below(m);
+          if (open && k < MAXF) s_f[cur ^ 1][k] = child;
+          nn += __popcll(m);
         }
-        if (bk >= bend) {
-          if (q >= nf) return -1;
-          const int64_t v = s_f[cur][q++];
-          bk = v << span;
-          bend = min((v + 1) << span, nb0);
-          continue;
-        }
-        const int64_t b = bk + lane;
-        const bool ok = b < bend && opens(g.node + ((int64_t)g.lev_off[0] + b) * TNODE);
-        bmask = __ballot(ok);
-        bbase = bk;
-        bk += 64;
-      }
-    };
-    // the accepted buckets' particles, filtered by their distance from the
-    // chunk's box (every pair partner is within the larger radius of that
-    // box), compacted into s_cand a round at a time
-    for (bool more = true; more;) {
-      int nsel = 0;
-      bool far = false;
-      while (nsel <= 64 * (SLOTS - 1)) {
-        const int bkt = next_bucket();
-        if (bkt < 0) {
-          more = false;
+        __syncthreads();
+        if (nn > MAXF) {  // wave-uniform
+          lev_stop = lev;
           break;
         }
-        const int j = bkt * BUCKET + lane;
-        bool keep = false;
-        if (j < n) {
-          const double4 pj = a.pos[j];
-          const double pk[3] = {pj.x, pj.y, pj.z};
-          double gap2 = 0.0;
-          bool wrap = false;
-#pragma unroll
-          for (int k = 0; k < 3; ++k) {
-            double d = fabs(pk[k] - bc[k]);
-            // a candidate whose separation from some particle of the chunk
-            // may need the periodic image
-            wrap = wrap || d + bh[k] > g.half[k];
-            d = fmin(d, g.box[k] - d);
-            const double gk = fmax(0.0, d - bh[k]);
-            gap2 += gk * gk;
+        cur ^= 1;
+        nf = nn;
+      }
+      // the accepted buckets in index order: the frontier's nodes, each
+      // expanded to the buckets under it when the walk stopped early
+      // (64 at a time across the lanes; bmask holds the accepted ones of the
+      // last 64, from bbase)
+      const int span = 3 * lev_stop;  // TREE_FANOUT = 2^3 nodes per level
+      const int64_t nb0 = g.lev_cnt[0];
+      int q = 0;
+      int64_t bk = 0, bend = 0, bbase = 0;
+      uint64_t bmask = 0;
+      auto next_bucket = [&]() -> int {
+        if (span == 0) return q < nf ? s_f[cur][q++] : -1;  // accepted by the walk
+        for (;;) {
+          if (bmask) {
+            const int t = __ffsll((unsigned long long)bmask) - 1;
+            bmask &= bmask - 1;
+            return (int)(bbase + t);
           }
-          const double R = fmax(Rc, g.hfac * pj.w) * (1.0 + 1e-12);
-          keep = gap2 < R * R;
-          far = far || (keep && wrap);
+          if (bk >= bend) {
+            if (q >= nf) return -1;
+            const int64_t v = s_f[cur][q++];
+            bk = v << span;
+            bend = min((v + 1) << span, nb0);
+            continue;
+          }
+          const int64_t b = bk + lane;
+          const bool ok = b < bend && opens(g.node + ((int64_t)g.lev_off[0] + b) * TNODE);
+          bmask = __ballot(ok);
+          bbase = bk;
+          bk += 64;
         }
-        const uint64_t m = __ballot(keep);
-        if (keep) s_cand[nsel + lanes_below(m)] = j;
-        nsel += __popcll(m);
-      }
-      if (nsel == 0) break;  // wave-uniform: nothing left
-      __syncthreads();
-      // slots holding at least one candidate (the rest are neither loaded
-      // nor tested)
-      const int nsl = (nsel + 63) / 64;
-      double px[SLOTS], py[SLOTS], pz[SLOTS], pq[SLOTS];
-      int jj[SLOTS];
-#pragma unroll
-      for (int s = 0; s < SLOTS; ++s) {
-        if (s >= nsl) break;
-        const int c = s * 64 + lane;
-        // an empty lane: never the particle itself, and its distance
-        // overflows to +inf, which fails every test
-        jj[s] = -1;
-        px[s] = py[s] = pz[s] = 1e300;
-        pq[s] = 0.0;
-        if (c < nsel) {
-          const int j = s_cand[c];
-          const double4 pj = a.pos[j];
-          jj[s] = j;
-          px[s] = pj.x;
-          py[s] = pj.y;
-          pz[s] = pj.z;
-          pq[s] = (g.hfac * pj.w) * (g.hfac * pj.w);
+      };
+      // the accepted buckets' particles, filtered by their distance from the
+      // chunk's box (every pair partner is within the larger radius of that
+      // box), compacted into s_cand a round at a time
+      for (bool more = true; more;) {
+        int nsel = 0;
+        bool far = false;
+        while (nsel <= 64 * (SLOTS - 1)) {
+          const int bkt = next_bucket();
+          if (bkt < 0) {
+            more = false;
+            break;
+          }
+          const int j = bkt * BUCKET + lane;
+          bool keep = false;
+          if (j < n) {
+            const double4 pj = a.pos[j];
+            const double pk[3] = {pj.x, pj.y, pj.z};
+            double gap2 = 0.0;
+            bool wrap = false;
+  #pragma unroll
+            for (int k = 0; k < 3; ++k) {
+              double d = fabs(pk[k] - bc[k]);
+              // a candidate whose separation from some particle of the chunk
+              // may need the periodic image
+              wrap = wrap || d + bh[k] > g.half[k];
+              d = fmin(d, g.box[k] - d);
+              const double gk = fmax(0.0, d - bh[k]);
+              gap2 += gk * gk;
+            }
+            const double R = fmax(Rc, g.hfac * pj.w) * (1.0 + 1e-12);
+            keep = gap2 < R * R;
+            far = far || (keep && wrap);
+          }
+          const uint64_t m = __ballot(keep);
+          if (keep) s_cand[nsel + lanes_below(m)] = j;
+          nsel += __popcll(m);
         }
-      }
-      // the particles of the chunk against the candidates in registers; a
-      // round with a candidate that may sit across the periodic boundary
-      // takes the minimum image, any other the plain difference (the same
-      // value there)
-      auto test_chunk = [&](auto wrap) {
-      constexpr bool WRAP = decltype(wrap)::value;
-      for (int t = 0; t < T; ++t) {
-        const int ti = own_x + t0 + t;
-        const double ptx = readlane_f64(tx, t), pty = readlane_f64(ty, t),
-                     ptz = readlane_f64(tz, t), ptq = readlane_f64(tq, t);
-        int base = __builtin_amdgcn_readlane(tcnt, t);
-#pragma unroll
+        if (nsel == 0) break;  // wave-uniform: nothing left
+        __syncthreads();
+        // slots holding at least one candidate (the rest are neither loaded
+        // nor tested)
+        const int nsl = (nsel + 63) / 64;
+        double px[SLOTS], py[SLOTS], pz[SLOTS], pq[SLOTS];
+        int jj[SLOTS];
+  #pragma unroll
         for (int s = 0; s < SLOTS; ++s) {
           if (s >= nsl) break;
-          double ex = px[s] - ptx, ey = py[s] - pty, ez = pz[s] - ptz;
-          if (WRAP) {
-            ex = min_image(ex, g.box[0], g.half[0]);
-            ey = min_image(ey, g.box[1], g.half[1]);
-            ez = min_image(ez, g.box[2], g.half[2]);
+          const int c = s * 64 + lane;
+          // an empty lane: never the particle itself, and its distance
+          // overflows to +inf, which fails every test
+          jj[s] = -1;
+          px[s] = py[s] = pz[s] = 1e300;
+          pq[s] = 0.0;
+          if (c < nsel) {
+            const int j = s_cand[c];
+            const double4 pj = a.pos[j];
+            jj[s] = j;
+            px[s] = pj.x;
+            py[s] = pj.y;
+            pz[s] = pj.z;
+            pq[s] = (g.hfac * pj.w) * (g.hfac * pj.w);
           }
-          const double r2 = ex * ex + ey * ey + ez * ez;
-          // r2 < max(ptq, pq) as two compares, the particle's own radius by
-          // the integer order of the bit patterns (the same order for the
-          // non-negative values here, +inf included) so that the compiler
-          // keeps them apart, and one lane mask per compare: no branch and
-          // no per-slot canonicalisation of the operands
-          const bool na = r2 < pq[s];
-          const bool nt = __double_as_longlong(r2) < __double_as_longlong(ptq);
-          const bool other = jj[s] != ti;
-          const bool hit = (na | nt) & other;
-          const uint64_t m = (__builtin_amdgcn_ballot_w64(na) | __builtin_amdgcn_ballot_w64(nt)) &
-                             __builtin_amdgcn_ballot_w64(other);
-          const int k = base + lanes_below(m);
-          const int nb = base + __popcll(m);
-          if (nb <= LCAP) {  // wave-uniform: every hit of the slot is staged
-            if (hit) {
-              s_idx[t][k] = jj[s];
-              s_r2[t][k] = r2;
-            }
-          } else if (hit) {
-            if (k < LCAP) {
-              s_idx[t][k] = jj[s];
-              s_r2[t][k] = r2;
-            } else if (k < cap) {
-              const int64_t at = list_at(seg0 + t, k);
-              a.cand[at] = jj[s];
-              a.cand_r2[at] = r2;
-            }
-          }
-          base = nb;
         }
-        tcnt = lane == t ? base : tcnt;
+        // the particles of the chunk against the candidates in registers; a
+        // round with a candidate that may sit across the periodic boundary
+        // takes the minimum image, any other the plain difference (the same
+        // value there)
+        auto test_chunk = [&](auto wrap) {
+        constexpr bool WRAP = decltype(wrap)::value;
+        for (int t = 0; t < T; ++t) {
+          const int ti = own_x + t0 + t;
+          const double ptx = readlane_f64(tx, t), pty = readlane_f64(ty, t),
+                       ptz = readlane_f64(tz, t), ptq = readlane_f64(tq, t);
+          int base = __builtin_amdgcn_readlane(tcnt, t);
+  #pragma unroll
+          for (int s = 0; s < SLOTS; ++s) {
+            if (s >= nsl) break;
+            double ex = px[s] - ptx, ey = py[s] - pty, ez = pz[s] - ptz;
+            if (WRAP) {
+              ex = min_image(ex, g.box[0], g.half[0]);
+              ey = min_image(ey, g.box[1], g.half[1]);
+              ez = min_image(ez, g.box[2], g.half[2]);
+            }
+            const double r2 = ex * ex + ey * ey + ez * ez;
+            // r2 < max(ptq, pq) as two compares, the particle's own radius by
+            // the integer order of the bit patterns (the same order for the
+            // non-negative values here, +inf included) so that the compiler
+            // keeps them apart, and one lane mask per compare: no branch and
+            // no per-slot canonicalisation of the operands
+            const bool na = r2 < pq[s];
+            const bool nt = __double_as_longlong(r2) < __double_as_longlong(ptq);
+            const bool other = jj[s] != ti;
+            const bool hit = (na | nt) & other;
+            const uint64_t m = (__builtin_amdgcn_ballot_w64(na) | __builtin_amdgcn_ballot_w64(nt)) &
+                               __builtin_amdgcn_ballot_w64(other);
+            const int k = base + lanes_below(m);
+            const int nb = base + __popcll(m);
+            if (nb <= LCAP) {  // wave-uniform: every hit of the slot is staged
+              if (hit) {
+                s_idx[t][k] = jj[s];
+                s_r2[t][k] = r2;
+              }
+            } else if (hit) {
+              if (k < LCAP) {
+                s_idx[t][k] = jj[s];
+                s_r2[t][k] = r2;
+              } else if (k < cap) {
+                const int64_t at = list_at(seg0 + t, k);
+                a.cand[at] = jj[s];
+                a.cand_r2[at] = r2;
+              }
+            }
+            base = nb;
+          }
+          tcnt = lane == t ? base : tcnt;
+        }
+        };
+        if (__ballot(far))
+          test_chunk(std::true_type{});
+        else
+          test_chunk(std::false_type{});
+        __syncthreads();
       }
-      };
-      if (__ballot(far))
-        test_chunk(std::true_type{});
-      else
-        test_chunk(std::false_type{});
+      if (lane < TCH) s_cnt[lane] = tcnt;
+      __syncthreads();
+      // the chunk's staged lists, plane by plane:
+      // lane -> (plane kk + lane / TCH, particle lane % TCH)
+      int mine = lane < T ? min(s_cnt[lane], min(LCAP, cap)) : 0;
+      const int kmax = wave_max_i32(mine);
+      const int tl = lane % TCH;
+      const int lim = tl < T ? min(s_cnt[tl], min(LCAP, cap)) : 0;
+      for (int kk = 0; kk < kmax; kk += 64 / TCH) {
+        const int k = kk + lane / TCH;
+        if (k < lim) {
+          const int64_t at = list_at(seg0 + tl, k);
+          a.cand[at] = s_idx[tl][k];
+          a.cand_r2[at] = s_r2[tl][k];
+        }
+      }
+      if (lane < T) a.ncand[own_x + t0 + lane] = s_cnt[lane];
+      if (lane < T && !a.count_only) {
+        const int c = s_cnt[lane];
+        a.cand_cnt[own_x + t0 + lane] = min(c, cap);
+        overflow += c > cap ? 1 : 0;
+      }
       __syncthreads();
     }
-    if (lane < TCH) s_cnt[lane] = tcnt;
-    __syncthreads();
-    // the chunk's staged lists, plane by plane: lane -> (plane kk + lane / TCH, particle lane % TCH)
-    int mine = lane < T ? min(s_cnt[lane], min(LCAP, cap)) : 0;
-    const int kmax = wave_max_i32(mine);
-    const int tl = lane % TCH;
-    const int lim = tl < T ? min(s_cnt[tl], min(LCAP, cap)) : 0;
-    for (int kk = 0; kk < kmax; kk += 64 / TCH) {
-      const int k = kk + lane / TCH;
-      if (k < lim) {
-        const int64_t at = list_at(seg0 + tl, k);
-        a.cand[at] = s_idx[tl][k];
-        a.cand_r2[at] = s_r2[tl][k];
-      }
-    }
-    if (lane < T) a.ncand[own_x + t0 + lane] = s_cnt[lane];
-    if (lane < T && !a.count_only) {
-      const int c = s_cnt[lane];
-      a.cand_cnt[own_x + t0 + lane] = min(c, cap);
-      overflow += c > cap ? 1 : 0;
-    }
-    __syncthreads();
   }
   count_add(a.counters + C_PASS_LIST, overflow);
 }
@@ -383,6 +388,7 @@ struct DensityArgs {
   int32_t *gl, *gl_cnt;
   const int64_t *lseg;    // list blocks of the chunks (list_at)
   const uint8_t *act;     // individual steps: 1 for the particles whose step begins (null: all)
+  int32_t *long_q;        // particles whose list density_k cannot hold (C_LONG_QUEUE of them)
   double gamma, n_ngb, ncond_max, ngb_boost, h_tol;
   int h_maxit, max_boosts;
   int64_t *counters;
@@ -397,7 +403,7 @@ struct DensityArgs {
 // (194 VGPRs, 2 waves) 2.30 ms, 4 particles per wavefront with 16 lanes
 // each 2.5-2.7 ms; with about 40 (the pair radius), DM = 12 1.25 ms, DM = 10
 // 1.20, DM = 8 at 3 waves 1.18, DM = 8 held to 128 VGPRs for 4 waves 1.15.
-// Longer lists go to density_long_k.
+// Longer lists go to density_wave_k.
 constexpr int DT = 8;
 constexpr int DG = 64 / DT;
 constexpr int DM = 8;
@@ -605,26 +611,33 @@ __device__ __forceinline__ void finish_particle(const DensityArgs &a, int64_t i,
 // split at r = H_i, in candidate order: the gather set goes to gl, the rest
 // (index and FP32 r^2) back into cand / rest_r2.  Both are staged in LDS and
 // leave as k-major planes of DT consecutive particles.  A list longer than
-// DCAP is left whole, marked gl_cnt = -1, for density_long_k.
-__global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) density_k(DensityArgs a, Tree g) {
-  __shared__ int32_t s_i[DCAP][DT];  // gather set from the front, rest indices from the back
-  __shared__ float s_f[DCAP][DT];    // rest r^2
-  __shared__ int s_gn[DT], s_rn[DT];
+// DCAP is left whole, marked gl_cnt = -1 and queued for density_wave_k.
+struct DensityStage {
+  int32_t (*s_i)[DT];  // gather set from the front, rest indices from the back
+  float (*s_f)[DT];    // rest r^2
+  int *s_gn, *s_rn;
+};
+struct PassCounts {
+  int64_t noconv = 0, boosts = 0, fails = 0, overflow = 0;
+};
+
+__device__ __forceinline__ void density_group(const DensityArgs &a, const Tree &g, int64_t grp,
+                                              const DensityStage &st, PassCounts &pc) {
   const int lane = threadIdx.x;
   const int gt = lane / DG, sub = lane % DG;
   const uint64_t below = (1ull << lane) - 1ull;
   const uint64_t gmask = ((1ull << DG) - 1ull) << (gt * DG);
   const int64_t n = a.n;
-  // a search whose lists overflowed leaves the pass to be redone: nothing
-  // here may change the state
-  if (a.counters[C_PASS_LIST] != 0) return;
-  const int64_t i0 = xcd_block(blockIdx.x, gridDim.x) * (int64_t)DT;
+  auto s_i = st.s_i;
+  auto s_f = st.s_f;
+  int *s_gn = st.s_gn, *s_rn = st.s_rn;
+  const int64_t i0 = grp * DT;
   const int64_t i = i0 + gt;
   // a particle in mid-step (individual steps) keeps its H and lists
   const bool valid = i < n && (!a.act || a.act[i]);
+  if (a.act && !__ballot(valid)) return;  // wave-uniform: nothing to do
   const int cnt = valid ? a.cand_cnt[i] : 0;
   const int64_t lb = valid ? list_base(a.lseg, i) : 0;
-  int64_t noconv = 0, boosts = 0, fails = 0, overflow = 0;
   if (valid && cnt <= DCAP) {
     // the distances r (not r^2): the square root is taken once here, not at
     // every Newton pass, and membership is r < h as in the kernel's support
@@ -682,14 +695,17 @@ __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) de
       s_gn[gt] = gn;
       s_rn[gt] = rn;
       finish_particle(a, i, r);
-      noconv = r.noconv;
-      boosts = r.boosts;
-      fails = r.fails;
-      overflow = r.overflow;
+      pc.noconv += r.noconv;
+      pc.boosts += r.boosts;
+      pc.fails += r.fails;
+      pc.overflow += r.overflow;
     }
   } else if (valid && sub == 0) {
-    s_gn[gt] = -1;  // left whole in cand for density_long_k
+    s_gn[gt] = -1;  // left whole in cand for density_wave_k
     s_rn[gt] = -1;
+    const unsigned long long slot =
+        atomicAdd(reinterpret_cast<unsigned long long *>(a.counters + C_LONG_QUEUE), 1ull);
+    a.long_q[slot] = (int32_t)i;
   }
   __syncthreads();
   // the staged lists, plane by plane: lane -> (plane kk + lane / DT, particle lane % DT)
@@ -712,60 +728,122 @@ __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) de
     a.gl_cnt[pl] = own ? glim : -1;
     if (own) a.cand_cnt[pl] = rlim;
   }
-  count_add(a.counters + C_PASS_NOCONV, noconv);
-  count_add(a.counters + C_PASS_BOOSTS, boosts);
-  count_add(a.counters + C_PASS_FAIL, fails);
-  count_add(a.counters + C_CELL_OVERFLOW, overflow);
+  __syncthreads();  // the staging arrays may be reused by another group
 }
 
-// The lists density_k could not hold (gl_cnt = -1): one lane per particle,
-// the list streamed from HBM on every pass, then split in place (an entry
-// moves only to a slot at or before its own).
-__global__ void __launch_bounds__(BS) density_long_k(DensityArgs a, Tree g) {
-  const int64_t i = xcd_block(blockIdx.x, gridDim.x) * (int64_t)blockDim.x + threadIdx.x;
-  const int64_t n = a.n;
+// One group of DT particles per workgroup (a full pass).
+__global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) density_k(DensityArgs a, Tree g) {
+  __shared__ int32_t s_i[DCAP][DT];
+  __shared__ float s_f[DCAP][DT];
+  __shared__ int s_gn[DT], s_rn[DT];
+  // a search whose lists overflowed leaves the pass to be redone: nothing
+  // here may change the state
+  if (a.counters[C_PASS_LIST] != 0) return;
+  PassCounts pc;
+  density_group(a, g, xcd_block(blockIdx.x, gridDim.x), DensityStage{s_i, s_f, s_gn, s_rn}, pc);
+  count_add(a.counters + C_PASS_NOCONV, pc.noconv);
+  count_add(a.counters + C_PASS_BOOSTS, pc.boosts);
+  count_add(a.counters + C_PASS_FAIL, pc.fails);
+  count_add(a.counters + C_CELL_OVERFLOW, pc.overflow);
+}
+
+// The sub-steps of individual time steps, where few particles are active: a
+// capped grid whose workgroups stride over the groups, skipping a group
+// without an active particle.
+__global__ void __launch_bounds__(64) density_sub_k(DensityArgs a, Tree g) {
+  __shared__ int32_t s_i[DCAP][DT];
+  __shared__ float s_f[DCAP][DT];
+  __shared__ int s_gn[DT], s_rn[DT];
+  if (a.counters[C_PASS_LIST] != 0) return;
+  PassCounts pc;
+  const int64_t ngroups = (a.n + DT - 1) / DT;
+  for (int64_t grp = blockIdx.x; grp < ngroups; grp += gridDim.x) {
+    // a wave-uniform test: the group holds a particle whose step begins
+    const int64_t i = grp * DT + threadIdx.x / DG;
+    if (!__ballot(i < a.n && a.act[i])) continue;
+    density_group(a, g, grp, DensityStage{s_i, s_f, s_gn, s_rn}, pc);
+  }
+  count_add(a.counters + C_PASS_NOCONV, pc.noconv);
+  count_add(a.counters + C_PASS_BOOSTS, pc.boosts);
+  count_add(a.counters + C_PASS_FAIL, pc.fails);
+  count_add(a.counters + C_CELL_OVERFLOW, pc.overflow);
+}
+
+// Sum over the 64 lanes of a wavefront as a butterfly (every lane gets the
+// same bits: each pairwise sum is formed from the same two operands).
+__device__ __forceinline__ double wave_sum_f64(double v) {
+#pragma unroll
+  for (int off = 1; off < 64; off <<= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+
+// The lists density_k could not hold (queued, gl_cnt = -1): one wavefront
+// per particle, its lanes taking the list entries k = lane, lane + 64, ...
+// from HBM on every pass (sums by wavefront butterflies), then the split in
+// candidate order, 64 entries at a time (an entry moves only to a slot at or
+// before its own, after the whole chunk has been read).  The grid strides
+// over the queue, whose length is read on the device.
+__global__ void __launch_bounds__(BS) density_wave_k(DensityArgs a, Tree g) {
   if (a.counters[C_PASS_LIST] != 0) return;  // as in density_k
+  const int lane = threadIdx.x & 63;
+  const int64_t wave = (int64_t)blockIdx.x * (BS / 64) + (threadIdx.x >> 6);
+  const int64_t nwaves = (int64_t)gridDim.x * (BS / 64);
+  const int64_t nq = a.counters[C_LONG_QUEUE];
+  const uint64_t below = (1ull << lane) - 1ull;
   int64_t noconv = 0, boosts = 0, fails = 0, overflow = 0;
-  if (i < n && (!a.act || a.act[i]) && a.gl_cnt[i] < 0) {
+  for (int64_t q = wave; q < nq; q += nwaves) {
+    const int64_t i = a.long_q[q];
     const int cnt = a.cand_cnt[i];
     const int64_t lb = list_base(a.lseg, i);
-    auto at = [&](int k) { return list_at(lb, k); };
     const double4 pi = a.pos[i];
     auto sums = [&](double h, double ih, double &s, double &ds) {
       s = 0.0;
       ds = 0.0;
-      for (int k = 0; k < cnt; ++k) {
-        const double r = sqrt(a.cand_r2[at(k)]);
+      for (int k = lane; k < cnt; k += 64) {
+        const double r = sqrt(a.cand_r2[list_at(lb, k)]);
         if (r < h) add_pair(s, ds, r, ih);
       }
+      s = wave_sum_f64(s);
+      ds = wave_sum_f64(ds);
     };
     auto esums = [&](double h, double ih, double &ws, double e[6]) {
       ws = 0.0;
-      for (int q = 0; q < 6; ++q) e[q] = 0.0;
-      for (int k = 0; k < cnt; ++k) {
-        const double r = sqrt(a.cand_r2[at(k)]);
-        if (r < h) add_e(ws, e, r, ih, a.pos[a.cand[at(k)]], pi, g);
+      for (int m = 0; m < 6; ++m) e[m] = 0.0;
+      for (int k = lane; k < cnt; k += 64) {
+        const double r = sqrt(a.cand_r2[list_at(lb, k)]);
+        if (r < h) add_e(ws, e, r, ih, a.pos[a.cand[list_at(lb, k)]], pi, g);
       }
+      ws = wave_sum_f64(ws);
+      for (int m = 0; m < 6; ++m) e[m] = wave_sum_f64(e[m]);
     };
     const HSolve r = newton_h(a, hcap_of(g, pi), a.H[i], sums, esums);
     int gn = 0, rn = 0;
-    for (int k = 0; k < cnt; ++k) {
-      const double r2 = a.cand_r2[at(k)];
-      const int j = a.cand[at(k)];
-      if (sqrt(r2) < r.h) {
-        a.gl[at(gn++)] = j;
-      } else {
-        a.cand[at(rn)] = j;
-        a.rest_r2[at(rn++)] = (float)r2;
+    for (int base = 0; base < cnt; base += 64) {
+      const int k = base + lane;
+      const bool in = k < cnt;
+      const double r2 = in ? a.cand_r2[list_at(lb, k)] : 0.0;
+      const int j = in ? a.cand[list_at(lb, k)] : 0;
+      const bool near = in && sqrt(r2) < r.h;
+      const bool far = in && !near;
+      const uint64_t mn = __ballot(near), mf = __ballot(far);
+      if (near) a.gl[list_at(lb, gn + __popcll(mn & below))] = j;
+      if (far) {
+        const int p = rn + __popcll(mf & below);
+        a.cand[list_at(lb, p)] = j;
+        a.rest_r2[list_at(lb, p)] = (float)r2;
       }
+      gn += __popcll(mn);
+      rn += __popcll(mf);
     }
-    a.gl_cnt[i] = gn;
-    a.cand_cnt[i] = rn;
-    finish_particle(a, i, r);
-    noconv = r.noconv;
-    boosts = r.boosts;
-    fails = r.fails;
-    overflow = r.overflow;
+    if (lane == 0) {
+      a.gl_cnt[i] = gn;
+      a.cand_cnt[i] = rn;
+      finish_particle(a, i, r);
+      noconv += r.noconv;
+      boosts += r.boosts;
+      fails += r.fails;
+      overflow += r.overflow;
+    }
   }
   count_add(a.counters + C_PASS_NOCONV, noconv);
   count_add(a.counters + C_PASS_BOOSTS, boosts);
@@ -806,7 +884,10 @@ __global__ void plan_k(int64_t n, int64_t nch, const int32_t *__restrict__ ncand
 
 __global__ void pool_check_k(const int64_t *__restrict__ lseg, int64_t nch, int64_t pool,
                              int64_t *counters) {
-  if (threadIdx.x == 0) counters[C_LIST_POOL] = lseg[nch] > pool ? 1 : 0;
+  if (threadIdx.x == 0) {
+    counters[C_LIST_POOL] = lseg[nch] > pool ? 1 : 0;
+    counters[C_LONG_QUEUE] = 0;  // the density loop that follows fills the queue
+  }
 }
 
 }  // namespace
@@ -837,7 +918,9 @@ hipError_t launch_candidates(mfm_ctx *ctx, const mfm_particles *pp, bool count_o
   a.cand_r2 = ctx->cand_r2;
   a.cand_cnt = ctx->cand_cnt;
   a.counters = ctx->counters;
-  cand_tree_k<<<(unsigned)ctx->tree.lev_cnt[0], 64, 0, ctx->stream>>>(a, ctx->tree);
+  const int64_t buckets = ctx->tree.lev_cnt[0];
+  const int64_t grid = a.act ? std::min<int64_t>(buckets, 4096) : buckets;
+  cand_tree_k<<<(unsigned)grid, 64, 0, ctx->stream>>>(a, ctx->tree);
   return hipGetLastError();
 }
 
@@ -866,7 +949,12 @@ hipError_t launch_density(mfm_ctx *ctx, const mfm_particles *pp) {
   a.h_maxit = ctx->p.h_maxit;
   a.max_boosts = ctx->p.max_boosts;
   a.counters = ctx->counters;
-  density_k<<<(unsigned)((pp->n + DT - 1) / DT), 64, 0, ctx->stream>>>(a, ctx->tree);
-  density_long_k<<<blocks_for(pp->n, BS), BS, 0, ctx->stream>>>(a, ctx->tree);
+  a.long_q = ctx->grad_q;  // the gradient loop's queue, unused until that loop
+  const int64_t groups = (pp->n + DT - 1) / DT;
+  if (a.act)
+    density_sub_k<<<(unsigned)std::min<int64_t>(groups, 8192), 64, 0, ctx->stream>>>(a, ctx->tree);
+  else
+    density_k<<<(unsigned)groups, 64, 0, ctx->stream>>>(a, ctx->tree);
+  density_wave_k<<<2048, BS, 0, ctx->stream>>>(a, ctx->tree);
   return hipGetLastError();
 }

@@ -776,6 +776,9 @@ __global__ void __launch_bounds__(FTH) __attribute__((amdgpu_waves_per_eu(2))) f
   if (tid == FTH - 1) pref[FBS] = run;
   __syncthreads();
   const int T_faces = pref[FBS];
+  // a sub-step of individual time steps adds the block's sums to dQ: a block
+  // without a face to solve has nothing to add
+  if (a.R.rung && T_faces == 0) return;
   const double dt = a.dt[0] * a.inv_a;  // the step times 1/a (comoving)
   const T hdt = T(0.5 * dt);
   int64_t nfaces = 0, iters_sum = 0, vac = 0, pos = 0, maxit = 0, fb = 0, overflow = 0;

@@ -45,6 +45,7 @@ enum {
   C_GRAD_QUEUE,     // mixed path: particles queued for the gradient loop's FP64 redo
   C_RUNG_CHANGED,   // the rung limiter raised some rung in its last sweep
   C_RUNG_DEEP,      // particles whose step needs a rung beyond MFM_RUNG_MAX
+  C_LONG_QUEUE,     // density loop: particles queued for the wavefront-per-particle pass
   NCOUNTERS = 32
 };
 
