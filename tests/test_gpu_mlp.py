@@ -248,9 +248,10 @@ def test_training_and_learned_guess_parity(trained_guess):
 
 # Newton steps per gated face that the trained guess must save against
 # Toro's adaptive guess, on sets it was not trained on (observed on MI355X
-# over several trainings: 0.85-1.0 on the shock tube, 0.35-0.55 on the Sedov
-# blast; the plain guess takes about 3)
-GAIN_MARGIN = 0.25
+# over several trainings, which differ in the order of the gradient sums:
+# 0.85-1.0 on the shock tube, 0.35-0.73 on the Sedov blast; the plain guess
+# takes about 3)
+GAIN_MARGIN = 0.2
 
 
 @pytest.mark.parametrize("precision", ["fp64", "mixed"])
