@@ -190,8 +190,31 @@ __global__ void __launch_bounds__(64) leaf_box_k(int64_t n, const double4 *__res
     hi[k] = wave_max_f64(hi[k]);
   }
   h = wave_max_f64(h);
+  // each chunk of LCH lanes: its box's half-diagonal against its particles'
+  // mean search radius (the spread flag the search reads); a lane past the
+  // end takes the last particle, which lies in the same chunk
+  const double4 pl = pos4[live ? i : n - 1];
+  double clo[3] = {pl.x, pl.y, pl.z}, chi[3] = {pl.x, pl.y, pl.z}, r = live ? hfac * pl.w : 0.0;
+  double cnt = live ? 1.0 : 0.0;
+  for (int o = 1; o < LCH; o <<= 1) {
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      clo[k] = fmin(clo[k], __shfl_xor(clo[k], o, 64));
+      chi[k] = fmax(chi[k], __shfl_xor(chi[k], o, 64));
+    }
+    r += __shfl_xor(r, o, 64);
+    cnt += __shfl_xor(cnt, o, 64);
+  }
+  double diag2 = 0.0;
+#pragma unroll
+  for (int k = 0; k < 3; ++k) diag2 += (chi[k] - clo[k]) * (chi[k] - clo[k]);
+  const double rmean = cnt > 0.0 ? r / cnt : 0.0;
+  const bool spread = live && diag2 > 4.0 * SPREAD_RATIO * SPREAD_RATIO * rmean * rmean;
+  const uint64_t sm = __ballot(spread && (threadIdx.x % LCH) == 0);
+  int mask = 0;
+  for (int c = 0; c < BUCKET / LCH; ++c) mask |= ((sm >> (c * LCH)) & 1ull) ? 1 << c : 0;
   if (threadIdx.x < TNODE) {
-    const double v[TNODE] = {lo[0], lo[1], lo[2], hi[0], hi[1], hi[2], hfac * h, 0.0};
+    const double v[TNODE] = {lo[0], lo[1], lo[2], hi[0], hi[1], hi[2], hfac * h, (double)mask};
     node[b * TNODE + threadIdx.x] = v[threadIdx.x];
   }
 }

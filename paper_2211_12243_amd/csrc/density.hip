@@ -68,6 +68,7 @@ constexpr int TCH = LCH;   // particles per chunk: one list chunk
 static_assert(BUCKET % TCH == 0, "a bucket holds whole chunks");
 constexpr int LCAP = 48;   // list entries per particle staged in LDS (more are stored directly)
 constexpr int MAXF = 256;  // accepted nodes of one tree level per chunk
+constexpr int TSUB = 4;    // particles per sub-chunk of a spread chunk (cells.hip marks them)
 
 // Lane l's value in every lane (a scalar broadcast, no memory traffic).
 __device__ __forceinline__ double readlane_f64(double v, int l) {
@@ -110,264 +111,278 @@ __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) ca
   for (int bucket = xcd_block(blockIdx.x, gridDim.x); bucket < nbuckets; bucket += gridDim.x) {
     const int own_x = bucket * BUCKET;
     const int own_y = (int)min((int64_t)BUCKET, n - own_x);
-    for (int t0 = 0; t0 < own_y; t0 += TCH) {
-      const int T = min(TCH, own_y - t0);
-      // on individual steps, only chunks with a particle whose step begins
-      // need lists (wave-uniform)
-      if (a.act && !__ballot(lane < T && a.act[own_x + t0 + lane])) continue;
-      const int64_t chunk = (own_x + t0) / LCH;
-      const int64_t seg0 = no_room ? 0 : a.lseg[chunk];
-      const int cap = no_room ? 0 : (int)((a.lseg[chunk + 1] - seg0) / LCH);
-      // lane t holds particle t of the chunk and the length of its list; the
-      // loop below broadcasts both
-      int tcnt = 0;
-      double tx = 0.0, ty = 0.0, tz = 0.0, tq = 0.0, th = 0.0;
-      const double4 p0 = a.pos[own_x + t0];
-      double blo[3] = {p0.x, p0.y, p0.z}, bhi[3] = {p0.x, p0.y, p0.z};
-      if (lane < T) {
-        const double4 pt = a.pos[own_x + t0 + lane];
-        tx = pt.x; ty = pt.y; tz = pt.z;
-        th = g.hfac * pt.w;
-        tq = th * th;  // squared radius of the particle's own H
-        blo[0] = bhi[0] = tx;
-        blo[1] = bhi[1] = ty;
-        blo[2] = bhi[2] = tz;
-      }
-      // the chunk's box and radius
-      // (wave-uniform: held in scalar registers)
-      double bc[3], bh[3];
-  #pragma unroll
-      for (int k = 0; k < 3; ++k) {
-        const double lo = wave_min_f64(blo[k]), hi = wave_max_f64(bhi[k]);
-        bc[k] = uniform_f64(0.5 * (lo + hi));
-        bh[k] = uniform_f64(0.5 * (hi - lo));
-      }
-      const double Rc = uniform_f64(wave_max_f64(th));
-      // a node is opened when its box and the chunk's are closer than the
-      // larger radius (raised by 1e-12 so that rounding in the box distance
-      // cannot drop a pair at the edge)
-      auto opens = [&](const double *nd) {
-        double gap2 = 0.0;
-  #pragma unroll
+    // the tree build marked the chunks of this bucket that spread over a box
+    // much wider than their particles' radii (where the sorted order jumps,
+    // in sparse gas): those are searched TSUB particles at a time, since a
+    // smaller box accepts far fewer candidates
+    const int spread = (int)g.node[((int64_t)g.lev_off[0] + bucket) * TNODE + TNODE_SPREAD];
+    for (int c0 = 0; c0 < own_y; c0 += TCH) {
+      const int T16 = min(TCH, own_y - c0);
+      if (a.act && !__ballot(lane < T16 && a.act[own_x + c0 + lane])) continue;
+      const int step = (spread >> (c0 / TCH)) & 1 ? TSUB : TCH;
+      for (int t0 = c0; t0 < c0 + T16; t0 += step) {
+        const int T = min(step, c0 + T16 - t0);
+        // on individual steps, only chunks with a particle whose step begins
+        // need lists (wave-uniform)
+        if (a.act && !__ballot(lane < T && a.act[own_x + t0 + lane])) continue;
+        const int64_t chunk = (own_x + t0) / LCH;
+        const int64_t cbase = no_room ? 0 : a.lseg[chunk];
+        const int cap = no_room ? 0 : (int)((a.lseg[chunk + 1] - cbase) / LCH);
+        // the list base of the first particle here (list_at: particle i of a
+        // chunk at block offset i mod LCH)
+        const int64_t seg0 = cbase + (own_x + t0) % LCH;
+        // lane t holds particle t of the chunk and the length of its list; the
+        // loop below broadcasts both
+        int tcnt = 0;
+        double tx = 0.0, ty = 0.0, tz = 0.0, tq = 0.0, th = 0.0;
+        const double4 p0 = a.pos[own_x + t0];
+        double blo[3] = {p0.x, p0.y, p0.z}, bhi[3] = {p0.x, p0.y, p0.z};
+        if (lane < T) {
+          const double4 pt = a.pos[own_x + t0 + lane];
+          tx = pt.x; ty = pt.y; tz = pt.z;
+          th = g.hfac * pt.w;
+          tq = th * th;  // squared radius of the particle's own H
+          blo[0] = bhi[0] = tx;
+          blo[1] = bhi[1] = ty;
+          blo[2] = bhi[2] = tz;
+        }
+        // the chunk's box and radius
+        // (wave-uniform: held in scalar registers)
+        double bc[3], bh[3];
+    #pragma unroll
         for (int k = 0; k < 3; ++k) {
-          double d = fabs(0.5 * (nd[k] + nd[3 + k]) - bc[k]);
-          d = fmin(d, g.box[k] - d);  // periodic images of the centres
-          const double gk = fmax(0.0, d - 0.5 * (nd[3 + k] - nd[k]) - bh[k]);
-          gap2 += gk * gk;
+          const double lo = wave_min_f64(blo[k]), hi = wave_max_f64(bhi[k]);
+          bc[k] = uniform_f64(0.5 * (lo + hi));
+          bh[k] = uniform_f64(0.5 * (hi - lo));
         }
-        const double R = fmax(Rc, nd[6]) * (1.0 + 1e-12);
-        return gap2 < R * R;
-      };
-      // breadth-first walk from the top node.  When a level would accept more
-      // nodes than the LDS holds (a chunk of wide particles), the walk stops
-      // above it and the buckets under the accepted nodes are tested one by
-      // one below.
-      int cur = 0, nf = 1, lev_stop = 0;
-      if (lane == 0) s_f[0][0] = 0;
-      __syncthreads();
-      for (int lev = g.nlev - 1; lev > 0; --lev) {
-        const int cl = lev - 1, cnt_c = g.lev_cnt[cl];
-        const double *nodes = g.node + (int64_t)g.lev_off[cl] * TNODE;
-        int nn = 0;
-        const int total = nf * TREE_FANOUT;
-        for (int u0 = 0; u0 < total; u0 += 64) {
-          const int u = u0 + lane;
-          bool open = false;
-          int child = 0;
-          if (u < total) {
-            child = s_f[cur][u / TREE_FANOUT] * TREE_FANOUT + u % TREE_FANOUT;
-            if (child < cnt_c) open = opens(nodes + (int64_t)child * TNODE);
+        const double Rc = uniform_f64(wave_max_f64(th));
+        // a node is opened when its box and the chunk's are closer than the
+        // larger radius (raised by 1e-12 so that rounding in the box distance
+        // cannot drop a pair at the edge)
+        auto opens = [&](const double *nd) {
+          double gap2 = 0.0;
+    #pragma unroll
+          for (int k = 0; k < 3; ++k) {
+            double d = fabs(0.5 * (nd[k] + nd[3 + k]) - bc[k]);
+            d = fmin(d, g.box[k] - d);  // periodic images of the centres
+            const double gk = fmax(0.0, d - 0.5 * (nd[3 + k] - nd[k]) - bh[k]);
+            gap2 += gk * gk;
           }
-          const uint64_t m = __ballot(open);
-          const int k = nn + lanes_below(m);
-          if (open && k < MAXF) s_f[cur ^ 1][k] = child;
-          nn += __popcll(m);
-        }
+          const double R = fmax(Rc, nd[6]) * (1.0 + 1e-12);
+          return gap2 < R * R;
+        };
+        // breadth-first walk from the top node.  When a level would accept more
+        // nodes than the LDS holds (a chunk of wide particles), the walk stops
+        // above it and the buckets under the accepted nodes are tested one by
+        // one below.
+        int cur = 0, nf = 1, lev_stop = 0;
+        if (lane == 0) s_f[0][0] = 0;
         __syncthreads();
-        if (nn > MAXF) {  // wave-uniform
-          lev_stop = lev;
-          break;
-        }
-        cur ^= 1;
-        nf = nn;
-      }
-      // the accepted buckets in index order: the frontier's nodes, each
-      // expanded to the buckets under it when the walk stopped early
-      // (64 at a time across the lanes; bmask holds the accepted ones of the
-      // last 64, from bbase)
-      const int span = 3 * lev_stop;  // TREE_FANOUT = 2^3 nodes per level
-      const int64_t nb0 = g.lev_cnt[0];
-      int q = 0;
-      int64_t bk = 0, bend = 0, bbase = 0;
-      uint64_t bmask = 0;
-      auto next_bucket = [&]() -> int {
-        if (span == 0) return q < nf ? s_f[cur][q++] : -1;  // accepted by the walk
-        for (;;) {
-          if (bmask) {
-            const int t = __ffsll((unsigned long long)bmask) - 1;
-            bmask &= bmask - 1;
-            return (int)(bbase + t);
+        for (int lev = g.nlev - 1; lev > 0; --lev) {
+          const int cl = lev - 1, cnt_c = g.lev_cnt[cl];
+          const double *nodes = g.node + (int64_t)g.lev_off[cl] * TNODE;
+          int nn = 0;
+          const int total = nf * TREE_FANOUT;
+          for (int u0 = 0; u0 < total; u0 += 64) {
+            const int u = u0 + lane;
+            bool open = false;
+            int child = 0;
+            if (u < total) {
+              child = s_f[cur][u / TREE_FANOUT] * TREE_FANOUT + u % TREE_FANOUT;
+              if (child < cnt_c) open = opens(nodes + (int64_t)child * TNODE);
+            }
+            const uint64_t m = __ballot(open);
+            const int k = nn + lanes_below(m);
+            if (open && k < MAXF) s_f[cur ^ 1][k] = child;
+            nn += __popcll(m);
           }
-          if (bk >= bend) {
-            if (q >= nf) return -1;
-            const int64_t v = s_f[cur][q++];
-            bk = v << span;
-            bend = min((v + 1) << span, nb0);
-            continue;
-          }
-          const int64_t b = bk + lane;
-          const bool ok = b < bend && opens(g.node + ((int64_t)g.lev_off[0] + b) * TNODE);
-          bmask = __ballot(ok);
-          bbase = bk;
-          bk += 64;
-        }
-      };
-      // the accepted buckets' particles, filtered by their distance from the
-      // chunk's box (every pair partner is within the larger radius of that
-      // box), compacted into s_cand a round at a time
-      for (bool more = true; more;) {
-        int nsel = 0;
-        bool far = false;
-        while (nsel <= 64 * (SLOTS - 1)) {
-          const int bkt = next_bucket();
-          if (bkt < 0) {
-            more = false;
+          __syncthreads();
+          if (nn > MAXF) {  // wave-uniform
+            lev_stop = lev;
             break;
           }
-          const int j = bkt * BUCKET + lane;
-          bool keep = false;
-          if (j < n) {
-            const double4 pj = a.pos[j];
-            const double pk[3] = {pj.x, pj.y, pj.z};
-            double gap2 = 0.0;
-            bool wrap = false;
-  #pragma unroll
-            for (int k = 0; k < 3; ++k) {
-              double d = fabs(pk[k] - bc[k]);
-              // a candidate whose separation from some particle of the chunk
-              // may need the periodic image
-              wrap = wrap || d + bh[k] > g.half[k];
-              d = fmin(d, g.box[k] - d);
-              const double gk = fmax(0.0, d - bh[k]);
-              gap2 += gk * gk;
+          cur ^= 1;
+          nf = nn;
+        }
+        // the accepted buckets in index order: the frontier's nodes, each
+        // expanded to the buckets under it when the walk stopped early
+        // (64 at a time across the lanes; bmask holds the accepted ones of the
+        // last 64, from bbase)
+        const int span = 3 * lev_stop;  // TREE_FANOUT = 2^3 nodes per level
+        const int64_t nb0 = g.lev_cnt[0];
+        int q = 0;
+        int64_t bk = 0, bend = 0, bbase = 0;
+        uint64_t bmask = 0;
+        auto next_bucket = [&]() -> int {
+          if (span == 0) return q < nf ? s_f[cur][q++] : -1;  // accepted by the walk
+          for (;;) {
+            if (bmask) {
+              const int t = __ffsll((unsigned long long)bmask) - 1;
+              bmask &= bmask - 1;
+              return (int)(bbase + t);
             }
-            const double R = fmax(Rc, g.hfac * pj.w) * (1.0 + 1e-12);
-            keep = gap2 < R * R;
-            far = far || (keep && wrap);
+            if (bk >= bend) {
+              if (q >= nf) return -1;
+              const int64_t v = s_f[cur][q++];
+              bk = v << span;
+              bend = min((v + 1) << span, nb0);
+              continue;
+            }
+            const int64_t b = bk + lane;
+            const bool ok = b < bend && opens(g.node + ((int64_t)g.lev_off[0] + b) * TNODE);
+            bmask = __ballot(ok);
+            bbase = bk;
+            bk += 64;
           }
-          const uint64_t m = __ballot(keep);
-          if (keep) s_cand[nsel + lanes_below(m)] = j;
-          nsel += __popcll(m);
-        }
-        if (nsel == 0) break;  // wave-uniform: nothing left
-        __syncthreads();
-        // slots holding at least one candidate (the rest are neither loaded
-        // nor tested)
-        const int nsl = (nsel + 63) / 64;
-        double px[SLOTS], py[SLOTS], pz[SLOTS], pq[SLOTS];
-        int jj[SLOTS];
-  #pragma unroll
-        for (int s = 0; s < SLOTS; ++s) {
-          if (s >= nsl) break;
-          const int c = s * 64 + lane;
-          // an empty lane: never the particle itself, and its distance
-          // overflows to +inf, which fails every test
-          jj[s] = -1;
-          px[s] = py[s] = pz[s] = 1e300;
-          pq[s] = 0.0;
-          if (c < nsel) {
-            const int j = s_cand[c];
-            const double4 pj = a.pos[j];
-            jj[s] = j;
-            px[s] = pj.x;
-            py[s] = pj.y;
-            pz[s] = pj.z;
-            pq[s] = (g.hfac * pj.w) * (g.hfac * pj.w);
+        };
+        // the accepted buckets' particles, filtered by their distance from the
+        // chunk's box (every pair partner is within the larger radius of that
+        // box), compacted into s_cand a round at a time
+        for (bool more = true; more;) {
+          int nsel = 0;
+          bool far = false;
+          while (nsel <= 64 * (SLOTS - 1)) {
+            const int bkt = next_bucket();
+            if (bkt < 0) {
+              more = false;
+              break;
+            }
+            const int j = bkt * BUCKET + lane;
+            bool keep = false;
+            if (j < n) {
+              const double4 pj = a.pos[j];
+              const double pk[3] = {pj.x, pj.y, pj.z};
+              double gap2 = 0.0;
+              bool wrap = false;
+    #pragma unroll
+              for (int k = 0; k < 3; ++k) {
+                double d = fabs(pk[k] - bc[k]);
+                // a candidate whose separation from some particle of the chunk
+                // may need the periodic image
+                wrap = wrap || d + bh[k] > g.half[k];
+                d = fmin(d, g.box[k] - d);
+                const double gk = fmax(0.0, d - bh[k]);
+                gap2 += gk * gk;
+              }
+              const double R = fmax(Rc, g.hfac * pj.w) * (1.0 + 1e-12);
+              keep = gap2 < R * R;
+              far = far || (keep && wrap);
+            }
+            const uint64_t m = __ballot(keep);
+            if (keep) s_cand[nsel + lanes_below(m)] = j;
+            nsel += __popcll(m);
           }
-        }
-        // the particles of the chunk against the candidates in registers; a
-        // round with a candidate that may sit across the periodic boundary
-        // takes the minimum image, any other the plain difference (the same
-        // value there)
-        auto test_chunk = [&](auto wrap) {
-        constexpr bool WRAP = decltype(wrap)::value;
-        for (int t = 0; t < T; ++t) {
-          const int ti = own_x + t0 + t;
-          const double ptx = readlane_f64(tx, t), pty = readlane_f64(ty, t),
-                       ptz = readlane_f64(tz, t), ptq = readlane_f64(tq, t);
-          int base = __builtin_amdgcn_readlane(tcnt, t);
-  #pragma unroll
+          if (nsel == 0) break;  // wave-uniform: nothing left
+          __syncthreads();
+          // slots holding at least one candidate (the rest are neither loaded
+          // nor tested)
+          const int nsl = (nsel + 63) / 64;
+          double px[SLOTS], py[SLOTS], pz[SLOTS], pq[SLOTS];
+          int jj[SLOTS];
+    #pragma unroll
           for (int s = 0; s < SLOTS; ++s) {
             if (s >= nsl) break;
-            double ex = px[s] - ptx, ey = py[s] - pty, ez = pz[s] - ptz;
-            if (WRAP) {
-              ex = min_image(ex, g.box[0], g.half[0]);
-              ey = min_image(ey, g.box[1], g.half[1]);
-              ez = min_image(ez, g.box[2], g.half[2]);
+            const int c = s * 64 + lane;
+            // an empty lane: never the particle itself, and its distance
+            // overflows to +inf, which fails every test
+            jj[s] = -1;
+            px[s] = py[s] = pz[s] = 1e300;
+            pq[s] = 0.0;
+            if (c < nsel) {
+              const int j = s_cand[c];
+              const double4 pj = a.pos[j];
+              jj[s] = j;
+              px[s] = pj.x;
+              py[s] = pj.y;
+              pz[s] = pj.z;
+              pq[s] = (g.hfac * pj.w) * (g.hfac * pj.w);
             }
-            const double r2 = ex * ex + ey * ey + ez * ez;
-            // r2 < max(ptq, pq) as two compares, the particle's own radius by
-            // the integer order of the bit patterns (the same order for the
-            // non-negative values here, +inf included) so that the compiler
-            // keeps them apart, and one lane mask per compare: no branch and
-            // no per-slot canonicalisation of the operands
-            const bool na = r2 < pq[s];
-            const bool nt = __double_as_longlong(r2) < __double_as_longlong(ptq);
-            const bool other = jj[s] != ti;
-            const bool hit = (na | nt) & other;
-            const uint64_t m = (__builtin_amdgcn_ballot_w64(na) | __builtin_amdgcn_ballot_w64(nt)) &
-                               __builtin_amdgcn_ballot_w64(other);
-            const int k = base + lanes_below(m);
-            const int nb = base + __popcll(m);
-            if (nb <= LCAP) {  // wave-uniform: every hit of the slot is staged
-              if (hit) {
-                s_idx[t][k] = jj[s];
-                s_r2[t][k] = r2;
-              }
-            } else if (hit) {
-              if (k < LCAP) {
-                s_idx[t][k] = jj[s];
-                s_r2[t][k] = r2;
-              } else if (k < cap) {
-                const int64_t at = list_at(seg0 + t, k);
-                a.cand[at] = jj[s];
-                a.cand_r2[at] = r2;
-              }
-            }
-            base = nb;
           }
-          tcnt = lane == t ? base : tcnt;
+          // the particles of the chunk against the candidates in registers; a
+          // round with a candidate that may sit across the periodic boundary
+          // takes the minimum image, any other the plain difference (the same
+          // value there)
+          auto test_chunk = [&](auto wrap) {
+          constexpr bool WRAP = decltype(wrap)::value;
+          for (int t = 0; t < T; ++t) {
+            const int ti = own_x + t0 + t;
+            const double ptx = readlane_f64(tx, t), pty = readlane_f64(ty, t),
+                         ptz = readlane_f64(tz, t), ptq = readlane_f64(tq, t);
+            int base = __builtin_amdgcn_readlane(tcnt, t);
+    #pragma unroll
+            for (int s = 0; s < SLOTS; ++s) {
+              if (s >= nsl) break;
+              double ex = px[s] - ptx, ey = py[s] - pty, ez = pz[s] - ptz;
+              if (WRAP) {
+                ex = min_image(ex, g.box[0], g.half[0]);
+                ey = min_image(ey, g.box[1], g.half[1]);
+                ez = min_image(ez, g.box[2], g.half[2]);
+              }
+              const double r2 = ex * ex + ey * ey + ez * ez;
+              // r2 < max(ptq, pq) as two compares, the particle's own radius by
+              // the integer order of the bit patterns (the same order for the
+              // non-negative values here, +inf included) so that the compiler
+              // keeps them apart, and one lane mask per compare: no branch and
+              // no per-slot canonicalisation of the operands
+              const bool na = r2 < pq[s];
+              const bool nt = __double_as_longlong(r2) < __double_as_longlong(ptq);
+              const bool other = jj[s] != ti;
+              const bool hit = (na | nt) & other;
+              const uint64_t m =
+                  (__builtin_amdgcn_ballot_w64(na) | __builtin_amdgcn_ballot_w64(nt)) &
+                  __builtin_amdgcn_ballot_w64(other);
+              const int k = base + lanes_below(m);
+              const int nb = base + __popcll(m);
+              if (nb <= LCAP) {  // wave-uniform: every hit of the slot is staged
+                if (hit) {
+                  s_idx[t][k] = jj[s];
+                  s_r2[t][k] = r2;
+                }
+              } else if (hit) {
+                if (k < LCAP) {
+                  s_idx[t][k] = jj[s];
+                  s_r2[t][k] = r2;
+                } else if (k < cap) {
+                  const int64_t at = list_at(seg0 + t, k);
+                  a.cand[at] = jj[s];
+                  a.cand_r2[at] = r2;
+                }
+              }
+              base = nb;
+            }
+            tcnt = lane == t ? base : tcnt;
+          }
+          };
+          if (__ballot(far))
+            test_chunk(std::true_type{});
+          else
+            test_chunk(std::false_type{});
+          __syncthreads();
         }
-        };
-        if (__ballot(far))
-          test_chunk(std::true_type{});
-        else
-          test_chunk(std::false_type{});
+        if (lane < TCH) s_cnt[lane] = tcnt;
+        __syncthreads();
+        // the chunk's staged lists, plane by plane:
+        // lane -> (plane kk + lane / TCH, particle lane % TCH)
+        int mine = lane < T ? min(s_cnt[lane], min(LCAP, cap)) : 0;
+        const int kmax = wave_max_i32(mine);
+        const int tl = lane % TCH;
+        const int lim = tl < T ? min(s_cnt[tl], min(LCAP, cap)) : 0;
+        for (int kk = 0; kk < kmax; kk += 64 / TCH) {
+          const int k = kk + lane / TCH;
+          if (k < lim) {
+            const int64_t at = list_at(seg0 + tl, k);
+            a.cand[at] = s_idx[tl][k];
+            a.cand_r2[at] = s_r2[tl][k];
+          }
+        }
+        if (lane < T) a.ncand[own_x + t0 + lane] = s_cnt[lane];
+        if (lane < T && !a.count_only) {
+          const int c = s_cnt[lane];
+          a.cand_cnt[own_x + t0 + lane] = min(c, cap);
+          overflow += c > cap ? 1 : 0;
+        }
         __syncthreads();
       }
-      if (lane < TCH) s_cnt[lane] = tcnt;
-      __syncthreads();
-      // the chunk's staged lists, plane by plane:
-      // lane -> (plane kk + lane / TCH, particle lane % TCH)
-      int mine = lane < T ? min(s_cnt[lane], min(LCAP, cap)) : 0;
-      const int kmax = wave_max_i32(mine);
-      const int tl = lane % TCH;
-      const int lim = tl < T ? min(s_cnt[tl], min(LCAP, cap)) : 0;
-      for (int kk = 0; kk < kmax; kk += 64 / TCH) {
-        const int k = kk + lane / TCH;
-        if (k < lim) {
-          const int64_t at = list_at(seg0 + tl, k);
-          a.cand[at] = s_idx[tl][k];
-          a.cand_r2[at] = s_r2[tl][k];
-        }
-      }
-      if (lane < T) a.ncand[own_x + t0 + lane] = s_cnt[lane];
-      if (lane < T && !a.count_only) {
-        const int c = s_cnt[lane];
-        a.cand_cnt[own_x + t0 + lane] = min(c, cap);
-        overflow += c > cap ? 1 : 0;
-      }
-      __syncthreads();
     }
   }
   count_add(a.counters + C_PASS_LIST, overflow);
@@ -769,17 +784,10 @@ __global__ void __launch_bounds__(64) density_sub_k(DensityArgs a, Tree g) {
   count_add(a.counters + C_CELL_OVERFLOW, pc.overflow);
 }
 
-// Sum over the 64 lanes of a wavefront as a butterfly (every lane gets the
-// same bits: each pairwise sum is formed from the same two operands).
-__device__ __forceinline__ double wave_sum_f64(double v) {
-#pragma unroll
-  for (int off = 1; off < 64; off <<= 1) v += __shfl_xor(v, off, 64);
-  return v;
-}
-
 // The lists density_k could not hold (queued, gl_cnt = -1): one wavefront
 // per particle, its lanes taking the list entries k = lane, lane + 64, ...
-// from HBM on every pass (sums by wavefront butterflies), then the split in
+// from HBM on every pass (sums by wavefront butterflies, wave_sum_f64: every
+// lane gets the same bits, so all take the same branches), then the split in
 // candidate order, 64 entries at a time (an entry moves only to a slot at or
 // before its own, after the whole chunk has been read).  The grid strides
 // over the queue, whose length is read on the device.

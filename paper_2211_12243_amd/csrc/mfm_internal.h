@@ -87,7 +87,12 @@ enum {
 constexpr int BUCKET = 64;
 constexpr int TREE_FANOUT = 8;
 constexpr int MAX_TREE_LEVELS = 12;
-constexpr int TNODE = 8;  // doubles per node: min x, y, z, max x, y, z, R, unused
+constexpr int TNODE = 8;  // doubles per node: min x, y, z, max x, y, z, R, spread mask
+constexpr int TNODE_SPREAD = 7;  // leaves: bit c set when chunk c of the bucket is spread
+// A chunk of LCH particles is "spread" when its box's half-diagonal exceeds
+// SPREAD_RATIO times its particles' mean search radius; the search takes it
+// a few particles at a time.
+constexpr double SPREAD_RATIO = 1.5;
 
 // The particle order: Morton keys of KEY_BITS bits per axis (SMALL_KEY_BITS
 // for sets of at most SMALL_SORT particles), sorted by a stable
