@@ -92,7 +92,7 @@ constexpr int TNODE_SPREAD = 7;  // leaves: bit c set when chunk c of the bucket
 // A chunk of LCH particles is "spread" when its box's half-diagonal exceeds
 // SPREAD_RATIO times its particles' mean search radius; the search takes it
 // a few particles at a time.
-constexpr double SPREAD_RATIO = 1.5;
+constexpr double SPREAD_RATIO = 3.0;
 
 // The particle order: Morton keys of KEY_BITS bits per axis (SMALL_KEY_BITS
 // for sets of at most SMALL_SORT particles), sorted by a stable
