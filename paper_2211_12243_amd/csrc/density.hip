@@ -39,10 +39,12 @@ struct CandArgs {
   double *cand_r2;
   int32_t *cand_cnt;
   int64_t *counters;
+  int csplit;           // workgroups per bucket (1, or BUCKET / TCH on a small set)
 };
 
 // The neighbour search: one wavefront per bucket of BUCKET consecutive
-// particles, taken in chunks of TCH.  For a chunk, the wavefront walks the
+// particles, taken in chunks of TCH (on a set of few buckets, one wavefront
+// per chunk, so that the chip fills).  For a chunk, the wavefront walks the
 // bucket tree breadth first: a node is opened when its box comes closer to
 // the chunk's box than the larger of the two candidate radii (each
 // cell_margin times the largest H at the build inside), which every pair
@@ -69,6 +71,7 @@ static_assert(BUCKET % TCH == 0, "a bucket holds whole chunks");
 constexpr int LCAP = 48;   // list entries per particle staged in LDS (more are stored directly)
 constexpr int MAXF = 256;  // accepted nodes of one tree level per chunk
 constexpr int TSUB = 4;    // particles per sub-chunk of a spread chunk (cells.hip marks them)
+constexpr int SEARCH_WG_TARGET = 4096;  // buckets below which each chunk has its own workgroup
 
 // Lane l's value in every lane (a scalar broadcast, no memory traffic).
 __device__ __forceinline__ double readlane_f64(double v, int l) {
@@ -106,9 +109,12 @@ __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) ca
   // the pass fails as a list overflow)
   const bool no_room = a.count_only || a.counters[C_LIST_POOL] != 0;
   const int nbuckets = (int)((n + BUCKET - 1) / BUCKET);
-  // one bucket per workgroup on a full pass; on the sub-steps of individual
-  // time steps a capped grid strides over the buckets
-  for (int bucket = xcd_block(blockIdx.x, gridDim.x); bucket < nbuckets; bucket += gridDim.x) {
+  // one bucket per workgroup on a full pass (one chunk per workgroup on a
+  // set of few buckets, csplit > 1); on the sub-steps of individual time
+  // steps a capped grid strides over the buckets
+  const int nwork = nbuckets * a.csplit;
+  for (int w = xcd_block(blockIdx.x, gridDim.x); w < nwork; w += gridDim.x) {
+    const int bucket = w / a.csplit;
     const int own_x = bucket * BUCKET;
     const int own_y = (int)min((int64_t)BUCKET, n - own_x);
     // the tree build marked the chunks of this bucket that spread over a box
@@ -116,7 +122,7 @@ __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) ca
     // in sparse gas): those are searched TSUB particles at a time, since a
     // smaller box accepts far fewer candidates
     const int spread = (int)g.node[((int64_t)g.lev_off[0] + bucket) * TNODE + TNODE_SPREAD];
-    for (int c0 = 0; c0 < own_y; c0 += TCH) {
+    for (int c0 = (w % a.csplit) * TCH; c0 < own_y; c0 += a.csplit * TCH) {
       const int T16 = min(TCH, own_y - c0);
       if (a.act && !__ballot(lane < T16 && a.act[own_x + c0 + lane])) continue;
       const int step = (spread >> (c0 / TCH)) & 1 ? TSUB : TCH;
@@ -927,7 +933,9 @@ hipError_t launch_candidates(mfm_ctx *ctx, const mfm_particles *pp, bool count_o
   a.cand_cnt = ctx->cand_cnt;
   a.counters = ctx->counters;
   const int64_t buckets = ctx->tree.lev_cnt[0];
-  const int64_t grid = a.act ? std::min<int64_t>(buckets, 4096) : buckets;
+  // under SEARCH_WG_TARGET buckets each chunk gets a workgroup of its own
+  a.csplit = (!a.act && buckets < SEARCH_WG_TARGET) ? BUCKET / TCH : 1;
+  const int64_t grid = a.act ? std::min<int64_t>(buckets, 4096) : buckets * a.csplit;
   cand_tree_k<<<(unsigned)grid, 64, 0, ctx->stream>>>(a, ctx->tree);
   return hipGetLastError();
 }

@@ -15,7 +15,10 @@
 // native FP64 global atomic add into dq_ext, which is folded into dQ after
 // the loop.  Evaluating a block-crossing face on both sides instead (no
 // global atomics) costs 25% more face evaluations at 1024 particles per
-// block.
+// block.  A set of few blocks (a few thousand particles) would leave most of
+// the chip idle and each workgroup with a long serial face loop: there each
+// block's faces are cut into contiguous slices, one workgroup per slice;
+// slice 0 writes the block's sums and the others add theirs into dq_ext.
 //
 // Precision.  T = double is the FP64 path.  T = float is the mixed path: the
 // separation is formed in FP64 from FP64 positions and rounded; the face
@@ -53,6 +56,8 @@ constexpr int FTH = 256;         // threads per workgroup
 constexpr int PPT = FBS / FTH;   // particles per thread in the block prefix sum
 static_assert(FBS % FTH == 0, "flux block must be a multiple of the workgroup size");
 constexpr int GUESS_MAXIT = 8;
+constexpr int FLUX_WG_TARGET = 1024;  // workgroups below which blocks are split
+constexpr int FLUX_MAX_SPLIT = 32;
 
 template <typename T>
 struct Gas {
@@ -89,6 +94,9 @@ struct FluxArgs {
   // (in units of c_L + c_R) beyond which the first pass hands a face over,
   // a superset of the network's gate (0: off)
   float gate_p, gate_du;
+  // workgroups per block of FBS particles (a small set: several share a
+  // block, each solving a contiguous slice of its faces)
+  int split;
   // the caller's FP64 particle arrays, which the second pass reads in place of
   // the mixed path's FP32 record (near the edge of the support, W(r, H) moves
   // by 3 (1 - r/H)^-1 times the relative error of 1/H)
@@ -744,7 +752,10 @@ __global__ void __launch_bounds__(FTH) __attribute__((amdgpu_waves_per_eu(2))) f
   __shared__ double acc[5][FBS];
   const int64_t n = a.n;
   const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
-  const int b0 = xcd_block(blockIdx.x, gridDim.x) * FBS;
+  // a.split workgroups share a block, each taking one slice of its faces
+  const int w = xcd_block(blockIdx.x, gridDim.x);
+  const int slice = w % a.split;
+  const int b0 = (w / a.split) * FBS;
   const int nb = (int)min((int64_t)FBS, n - b0);
   // block exclusive prefix sum of the per-particle face counts: each thread
   // sums PPT consecutive particles, then a wave scan and the wave offsets
@@ -779,6 +790,9 @@ __global__ void __launch_bounds__(FTH) __attribute__((amdgpu_waves_per_eu(2))) f
   // a sub-step of individual time steps adds the block's sums to dQ: a block
   // without a face to solve has nothing to add
   if (a.R.rung && T_faces == 0) return;
+  const int f_lo = (int)((int64_t)T_faces * slice / a.split);
+  const int f_hi = (int)((int64_t)T_faces * (slice + 1) / a.split);
+  if (slice > 0 && f_lo == f_hi) return;  // an empty slice adds nothing
   const double dt = a.dt[0] * a.inv_a;  // the step times 1/a (comoving)
   const T hdt = T(0.5 * dt);
   int64_t nfaces = 0, iters_sum = 0, vac = 0, pos = 0, maxit = 0, fb = 0, overflow = 0;
@@ -795,17 +809,17 @@ __global__ void __launch_bounds__(FTH) __attribute__((amdgpu_waves_per_eu(2))) f
     jf = a.fslot[list_at(list_base(a.lseg, b0 + lo), f - pref[lo])];
   };
   int p_next = FBS, j_next = 0;
-  if (tid < T_faces) locate(tid, p_next, j_next);
-  for (int base = 0; base < T_faces; base += FTH) {
+  if (f_lo + tid < f_hi) locate(f_lo + tid, p_next, j_next);
+  for (int base = f_lo; base < f_hi; base += FTH) {
     const int f = base + tid;
-    const bool active = f < T_faces;
+    const bool active = f < f_hi;
     int p = FBS;  // sentinel key for idle lanes (they sit at the wave's end)
     int i = 0, j = 0;
     if (active) {
       p = p_next;
       j = j_next;
     }
-    if (f + FTH < T_faces) locate(f + FTH, p_next, j_next);
+    if (f + FTH < f_hi) locate(f + FTH, p_next, j_next);
     FaceState<T> fs;
     fs.skip = true;
     fs.flags = 0;
@@ -914,9 +928,14 @@ __global__ void __launch_bounds__(FTH) __attribute__((amdgpu_waves_per_eu(2))) f
   for (int t = tid; t < nb; t += FTH) {
 #pragma unroll
     for (int q = 0; q < 5; ++q) {
-      double *d = a.dQ + (int64_t)q * n + b0 + t;
-      // individual steps: the sums of a particle's whole step accumulate
-      *d = a.R.rung ? *d + acc[q][t] : acc[q][t];
+      if (slice == 0) {
+        double *d = a.dQ + (int64_t)q * n + b0 + t;
+        // individual steps: the sums of a particle's whole step accumulate
+        *d = a.R.rung ? *d + acc[q][t] : acc[q][t];
+      } else if (acc[q][t] != 0.0) {
+        // the other slices of the block add theirs through dq_ext
+        unsafeAtomicAdd(&a.dq_ext[(int64_t)q * n + b0 + t], acc[q][t]);
+      }
     }
   }
   count_add(a.counters + C_FACES, nfaces);
@@ -1224,7 +1243,12 @@ hipError_t launch_fluxes(mfm_ctx *ctx, const mfm_particles *pp, const double *dt
   if (learned) mlp_net_of(ctx->mlp_state, &a.net);
   a.gate_p = learned ? 1.9f : 0.0f;
   a.gate_du = learned ? 0.24f : 0.0f;
-  const int nb = blocks_for(pp->n, FBS);
+  // a set of few blocks (under FLUX_WG_TARGET) splits each block's faces
+  // over several workgroups so that the chip fills; a sub-step of individual
+  // steps keeps one workgroup per block (most of them have no face to solve)
+  const int nblk = blocks_for(pp->n, FBS);
+  a.split = ctx->rungs.rung ? 1 : std::max(1, std::min(FLUX_MAX_SPLIT, FLUX_WG_TARGET / nblk));
+  const int nb = nblk * a.split;
   const int64_t m5 = 5 * pp->n;
   const int fb = (int)std::min<int64_t>(blocks_for(m5, 256), 8192);
   const int ev_all = stage_begin(ctx, 4);

@@ -112,8 +112,9 @@ def test_list_overflow_in_a_step_leaves_the_state():
 
 
 def test_soundwave_step_time():
-    """8192 particles (the sound wave at N = 128): a step is bound by launches
-    and host round trips, not by the kernels."""
+    """8192 particles (the sound wave at N = 128): few flux blocks and search
+    buckets must still fill the chip (sliced flux blocks, a wavefront per
+    search chunk); 0.30 ms per step measured, 0.67 ms without them."""
     _need_gpu()
     st = W.soundwave(128, nyz=8, A=1e-3, gamma=1.4)
     cfg = {"scheme": "mfm", "gamma": 1.4, "limiter": 0, "box": W.soundwave_box(128, 8)}
@@ -130,4 +131,4 @@ def test_soundwave_step_time():
     ms = (time.perf_counter() - t0) / k * 1e3
     print(f"[step] sound wave N=128: {ms:.3f} ms per step", flush=True)
     ctx.close()
-    assert ms < 0.64
+    assert ms < 0.45
