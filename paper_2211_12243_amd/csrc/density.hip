@@ -39,7 +39,7 @@ struct CandArgs {
   double *cand_r2;
   int32_t *cand_cnt;
   int64_t *counters;
-  int csplit;           // workgroups per bucket (1, or BUCKET / TCH on a small set)
+  int csplit;           // workgroups per bucket (1, or BUCKET / TCH: small set, sub-step)
 };
 
 // The neighbour search: one wavefront per bucket of BUCKET consecutive
@@ -111,7 +111,7 @@ __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) ca
   const int nbuckets = (int)((n + BUCKET - 1) / BUCKET);
   // one bucket per workgroup on a full pass (one chunk per workgroup on a
   // set of few buckets, csplit > 1); on the sub-steps of individual time
-  // steps a capped grid strides over the buckets
+  // steps a capped grid strides over the chunks
   const int nwork = nbuckets * a.csplit;
   for (int w = xcd_block(blockIdx.x, gridDim.x); w < nwork; w += gridDim.x) {
     const int bucket = w / a.csplit;
@@ -933,9 +933,11 @@ hipError_t launch_candidates(mfm_ctx *ctx, const mfm_particles *pp, bool count_o
   a.cand_cnt = ctx->cand_cnt;
   a.counters = ctx->counters;
   const int64_t buckets = ctx->tree.lev_cnt[0];
-  // under SEARCH_WG_TARGET buckets each chunk gets a workgroup of its own
-  a.csplit = (!a.act && buckets < SEARCH_WG_TARGET) ? BUCKET / TCH : 1;
-  const int64_t grid = a.act ? std::min<int64_t>(buckets, 4096) : buckets * a.csplit;
+  // under SEARCH_WG_TARGET buckets, and on the sub-steps of individual
+  // steps (few chunks, scattered, need lists), each chunk gets a workgroup
+  // of its own; on a sub-step a capped grid strides over the chunks
+  a.csplit = (a.act || buckets < SEARCH_WG_TARGET) ? BUCKET / TCH : 1;
+  const int64_t grid = a.act ? std::min<int64_t>(buckets * a.csplit, 8192) : buckets * a.csplit;
   cand_tree_k<<<(unsigned)grid, 64, 0, ctx->stream>>>(a, ctx->tree);
   return hipGetLastError();
 }

@@ -928,12 +928,12 @@ __global__ void __launch_bounds__(FTH) __attribute__((amdgpu_waves_per_eu(2))) f
   for (int t = tid; t < nb; t += FTH) {
 #pragma unroll
     for (int q = 0; q < 5; ++q) {
-      if (slice == 0) {
-        double *d = a.dQ + (int64_t)q * n + b0 + t;
-        // individual steps: the sums of a particle's whole step accumulate
-        *d = a.R.rung ? *d + acc[q][t] : acc[q][t];
+      if (slice == 0 && !a.R.rung) {
+        a.dQ[(int64_t)q * n + b0 + t] = acc[q][t];
       } else if (acc[q][t] != 0.0) {
-        // the other slices of the block add theirs through dq_ext
+        // the other slices of the block add theirs through dq_ext; on a
+        // sub-step of individual steps dq_ext is dQ itself, where the sums
+        // of a particle's whole step accumulate
         unsafeAtomicAdd(&a.dq_ext[(int64_t)q * n + b0 + t], acc[q][t]);
       }
     }
@@ -1123,7 +1123,8 @@ __global__ void __launch_bounds__(FTH) hard_faces_k(FluxArgs a) {
 }
 
 // dq_ext (and the second pass's queue length) is cleared before the flux
-// loop and folded into dQ after it.
+// loop and folded into dQ after it (on a sub-step of individual steps only
+// the queue length: the shares go straight into dQ).
 __global__ void zero_f64_k(double *v, int64_t m, unsigned long long *queue_len,
                            const int64_t *counters, double *w, int64_t mw) {
   if (counters[C_STEP_SKIP]) return;
@@ -1228,7 +1229,9 @@ hipError_t launch_fluxes(mfm_ctx *ctx, const mfm_particles *pp, const double *dt
   a.dump = ctx->dump;
   a.dump_cap = ctx->dump_cap;
   a.dump_count = ctx->dump_count;
-  a.dq_ext = ctx->dq_ext;
+  // individual steps: every share goes straight into dQ, which holds the
+  // sums of the whole base step (nothing to clear or fold per sub-step)
+  a.dq_ext = ctx->rungs.rung ? pp->dQ : ctx->dq_ext;
   a.hard_q = ctx->hard_q;
   a.hard_cap = ctx->hard_cap;
   a.hard_len = ctx->hard_len;
@@ -1252,8 +1255,9 @@ hipError_t launch_fluxes(mfm_ctx *ctx, const mfm_particles *pp, const double *dt
   const int64_t m5 = 5 * pp->n;
   const int fb = (int)std::min<int64_t>(blocks_for(m5, 256), 8192);
   const int ev_all = stage_begin(ctx, 4);
-  zero_f64_k<<<fb, 256, 0, ctx->stream>>>(ctx->dq_ext, m5, a.hard_len, ctx->counters, a.gwork,
-                                          3 * pp->n);
+  zero_f64_k<<<ctx->rungs.rung ? 1 : fb, 256, 0, ctx->stream>>>(ctx->rungs.rung ? nullptr : ctx->dq_ext,
+                                          ctx->rungs.rung ? 0 : m5, a.hard_len, ctx->counters,
+                                          a.gwork, 3 * pp->n);
   const int ev_main = stage_begin(ctx, 6);
   if (mixed) {
     launch_t<float, false>(a, ctx->p.scheme, m, nb, ctx->stream);  // learned: a.gate_*
@@ -1277,7 +1281,8 @@ hipError_t launch_fluxes(mfm_ctx *ctx, const mfm_particles *pp, const double *dt
     }
     stage_end(ctx, ev_hard);
   }
-  fold_f64_k<<<fb, 256, 0, ctx->stream>>>(pp->dQ, ctx->dq_ext, m5, ctx->counters);
+  if (!ctx->rungs.rung)
+    fold_f64_k<<<fb, 256, 0, ctx->stream>>>(pp->dQ, ctx->dq_ext, m5, ctx->counters);
   stage_end(ctx, ev_all);
   return hipGetLastError();
 }

@@ -143,6 +143,8 @@ __global__ void __launch_bounds__(BS) gradients_k(GradArgs a) {
   // faces of its own: its faces are solved by the particles whose step begins
   const bool live = i < n && (!a.act || a.act[i]);
   if (i < n && !live) a.fcnt[i] = 0;
+  // on a sub-step most wavefronts hold no such particle: they are done
+  if (a.act && !__ballot(live)) return;
   const int64_t lb = list_base(a.lseg, live ? i : 0);
   {
     const double *gi = a.gin + (live ? i : 0) * GIN_STRIDE;
