@@ -96,6 +96,7 @@ __global__ void substep_begin_k(int64_t n, Rungs R, const double *__restrict__ x
   act[i] = on ? 1 : 0;
   elapsed[i] = e;
   double p[3] = {x[i], y[i], z[i]};
+  const double h = H[i];
   if (!on) {
     const double v[3] = {vx[i], vy[i], vz[i]}, L[3] = {bx, by, bz};
 #pragma unroll
@@ -105,12 +106,13 @@ __global__ void substep_begin_k(int64_t n, Rungs R, const double *__restrict__ x
       if (q >= L[k]) q -= L[k];
       p[k] = q;
     }
-    double *g = gin + i * GIN_STRIDE;
-    g[GIN_X] = p[0];
-    g[GIN_Y] = p[1];
-    g[GIN_Z] = p[2];
+    // the record's first 32 bytes whole (position and the unchanged H): one
+    // full aligned store instead of three partial ones
+    static_assert(GIN_X == 0 && GIN_Y == 1 && GIN_Z == 2 && GIN_H == 3,
+                  "the record opens with the position and H");
+    *reinterpret_cast<double4 *>(gin + i * GIN_STRIDE) = make_double4(p[0], p[1], p[2], h);
   }
-  pos4[i] = make_double4(p[0], p[1], p[2], H[i]);
+  pos4[i] = make_double4(p[0], p[1], p[2], h);
 }
 
 }  // namespace
