@@ -36,7 +36,9 @@ struct GradArgs {
   int64_t n;
   const double *gin;
   const double *H;      // converged support radii (SoA: 16 particles per cache line)
-  const double4 *pos;   // (x, y, z, 0) per particle
+  // (x, y, z, H) per particle: this pass's positions (on a sub-step of
+  // individual steps, every particle's at that time)
+  const double4 *pos;
   const int32_t *cand, *cand_cnt;  // candidates with r >= H_i
   const float *rest_r2;             // their r^2, rounded to FP32
   const int32_t *gl, *gl_cnt;
@@ -129,7 +131,21 @@ template <> struct NbRec<double> {
   }
 };
 
-template <typename T>
+// A neighbour's record.  On a sub-step of individual steps (RUNG) its
+// position comes from pos, where the sub-step start has put every particle
+// at that time (gin keeps the position of the particle's last density pass).
+template <bool RUNG, typename T>
+__device__ __forceinline__ void load_nb(NbRec<T> &nb, const GradArgs &a, int64_t j) {
+  nb.load(a.gin + j * GIN_STRIDE);
+  if (RUNG) {
+    const double4 p = a.pos[j];
+    nb.x = p.x;
+    nb.y = p.y;
+    nb.z = p.z;
+  }
+}
+
+template <typename T, bool RUNG>
 __global__ void __launch_bounds__(BS) gradients_k(GradArgs a) {
   if (a.counters[C_STEP_SKIP]) return;  // the density pass was rejected
   __shared__ int32_t s_ring[BS / 64][RING][64];
@@ -206,7 +222,7 @@ __global__ void __launch_bounds__(BS) gradients_k(GradArgs a) {
     int jn = gc > 0 ? a.gl[list_at(lb, 0)] : 0;
     int jn2 = gc > 1 ? a.gl[list_at(lb, 1)] : 0;
     NbRec<T> nb;
-    if (gc > 0) nb.load(a.gin + (int64_t)jn * GIN_STRIDE);
+    if (gc > 0) load_nb<RUNG>(nb, a, jn);
     for (int k = 0; k < gmax; ++k) {
       if (k % RSTEP == 0) make_room();
       if (k < gc) {
@@ -214,7 +230,7 @@ __global__ void __launch_bounds__(BS) gradients_k(GradArgs a) {
         const NbRec<T> cur = nb;
         if (k + 1 < gc) {
           jn = jn2;
-          nb.load(a.gin + (int64_t)jn * GIN_STRIDE);
+          load_nb<RUNG>(nb, a, jn);
           if (k + 2 < gc) jn2 = a.gl[list_at(lb, k + 2)];
         }
         if (emit_face((int)i, j) || (a.act && !a.act[j])) put_face(j);
@@ -453,15 +469,26 @@ __global__ void __launch_bounds__(64) grad_fix_k(GradArgs a) {
       s[q][0] = s[q][1] = s[q][2] = 0.0;
       qmax[q] = qmin[q] = q64[q];
     }
-    auto sep = [&](const double *gj, double d[3]) {
-      d[0] = min_image(gj[GIN_X] - xi, a.box[0], a.half[0]);
-      d[1] = min_image(gj[GIN_Y] - yi, a.box[1], a.half[1]);
-      d[2] = min_image(gj[GIN_Z] - zi, a.box[2], a.half[2]);
+    // a neighbour's separation: its position from pos on a sub-step of
+    // individual steps (see load_nb), else from its record
+    auto sep = [&](int64_t j, double d[3]) {
+      double p[3];
+      if (a.act) {
+        const double4 q = a.pos[j];
+        p[0] = q.x; p[1] = q.y; p[2] = q.z;
+      } else {
+        const double *gj = a.gin + j * GIN_STRIDE;
+        p[0] = gj[GIN_X]; p[1] = gj[GIN_Y]; p[2] = gj[GIN_Z];
+      }
+      d[0] = min_image(p[0] - xi, a.box[0], a.half[0]);
+      d[1] = min_image(p[1] - yi, a.box[1], a.half[1]);
+      d[2] = min_image(p[2] - zi, a.box[2], a.half[2]);
     };
     for (int k = lane; k < gc; k += 64) {
-      const double *gj = a.gin + (int64_t)a.gl[list_at(lb, k)] * GIN_STRIDE;
+      const int64_t j = a.gl[list_at(lb, k)];
+      const double *gj = a.gin + j * GIN_STRIDE;
       double d[3];
-      sep(gj, d);
+      sep(j, d);
       const double r2 = d[0] * d[0] + d[1] * d[1] + d[2] * d[2];
       if (r2 == 0.0) continue;
       const double wv = gj[GIN_V] * wnorm * spline_wt<double>(sqrt(r2) * ih);
@@ -501,7 +528,7 @@ __global__ void __launch_bounds__(64) grad_fix_k(GradArgs a) {
       double dmax[5] = {0, 0, 0, 0, 0}, dmin[5] = {0, 0, 0, 0, 0};
       for (int k = lane; k < gc; k += 64) {
         double d[3];
-        sep(a.gin + (int64_t)a.gl[list_at(lb, k)] * GIN_STRIDE, d);
+        sep(a.gl[list_at(lb, k)], d);
 #pragma unroll
         for (int q = 0; q < 5; ++q) {
           const double ex = 0.5 * (g[q][0] * d[0] + g[q][1] * d[1] + g[q][2] * d[2]);
@@ -610,11 +637,17 @@ hipError_t launch_gradients(mfm_ctx *ctx, const mfm_particles *pp, double dt_max
   if (ctx->p.precision == MFM_MIXED) {
     hipError_t e = hipMemsetAsync(ctx->counters + C_GRAD_QUEUE, 0, sizeof(int64_t), ctx->stream);
     if (e != hipSuccess) return e;
-    gradients_k<float><<<blocks_for(pp->n, BS), BS, 0, ctx->stream>>>(a);
+    if (a.act)
+      gradients_k<float, true><<<blocks_for(pp->n, BS), BS, 0, ctx->stream>>>(a);
+    else
+      gradients_k<float, false><<<blocks_for(pp->n, BS), BS, 0, ctx->stream>>>(a);
     // one wavefront per queued particle, the queue's length read on the device
     grad_fix_k<<<1024, 64, 0, ctx->stream>>>(a);
   } else {
-    gradients_k<double><<<blocks_for(pp->n, BS), BS, 0, ctx->stream>>>(a);
+    if (a.act)
+      gradients_k<double, true><<<blocks_for(pp->n, BS), BS, 0, ctx->stream>>>(a);
+    else
+      gradients_k<double, false><<<blocks_for(pp->n, BS), BS, 0, ctx->stream>>>(a);
   }
   min_partial_k<<<RED_BLOCKS, BS, 0, ctx->stream>>>(pp->dt_i, pp->n, ctx->red, ctx->counters);
   dt_final_k<<<1, BS, 0, ctx->stream>>>(ctx->red, RED_BLOCKS, dt_max, dt_dev, ctx->counters);

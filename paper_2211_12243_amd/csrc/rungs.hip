@@ -77,16 +77,17 @@ __global__ void rmax_k(int64_t n, const int32_t *__restrict__ rung, int32_t *out
 }
 
 // Sub-step k: which particles begin a step, the time since each particle's
-// step began, and the positions of that time (a particle in mid-step at its
-// step-start position plus the elapsed time times its velocity; its H is the
-// one of its last density pass).  The gradient loop's records of the
-// particles in mid-step get those positions too.
+// step began, and the positions of that time in pos4 (a particle in mid-step
+// at its step-start position plus the elapsed time times its velocity; its H
+// is the one of its last density pass).  The search, the density and
+// gradient loops and the flux loop take every position from pos4 on a
+// sub-step.
 __global__ void substep_begin_k(int64_t n, Rungs R, const double *__restrict__ x,
                                 const double *__restrict__ y, const double *__restrict__ z,
                                 const double *__restrict__ vx, const double *__restrict__ vy,
                                 const double *__restrict__ vz, const double *__restrict__ H,
                                 double bx, double by, double bz, uint8_t *act, double *elapsed,
-                                double4 *pos4, double *gin) {
+                                double4 *pos4) {
   const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (i >= n) return;
   const int r = R.rung[i];
@@ -106,11 +107,6 @@ __global__ void substep_begin_k(int64_t n, Rungs R, const double *__restrict__ x
       if (q >= L[k]) q -= L[k];
       p[k] = q;
     }
-    // the record's first 32 bytes whole (position and the unchanged H): one
-    // full aligned store instead of three partial ones
-    static_assert(GIN_X == 0 && GIN_Y == 1 && GIN_Z == 2 && GIN_H == 3,
-                  "the record opens with the position and H");
-    *reinterpret_cast<double4 *>(gin + i * GIN_STRIDE) = make_double4(p[0], p[1], p[2], h);
   }
   pos4[i] = make_double4(p[0], p[1], p[2], h);
 }
@@ -146,6 +142,6 @@ hipError_t launch_substep_begin(mfm_ctx *ctx, const mfm_particles *pp) {
   substep_begin_k<<<blocks_for(pp->n, BS), BS, 0, ctx->stream>>>(
       pp->n, ctx->rungs, pp->x, pp->y, pp->z, pp->vx, pp->vy, pp->vz, pp->H, ctx->p.box[0],
       ctx->p.box[1], ctx->p.box[2], ctx->act_w, ctx->elapsed_w,
-      reinterpret_cast<double4 *>(ctx->pos4), ctx->gin);
+      reinterpret_cast<double4 *>(ctx->pos4));
   return hipGetLastError();
 }

@@ -7,6 +7,8 @@
   MFM and MFV): the rungs equal the oracle's exactly, the state after the
   base step within 1e-12 (FP64), the face count exact; mass, momentum and
   energy conserved to roundoff.
+* The mixed path on the oracle's rungs: within 1e-5 of the oracle, and
+  conservative to roundoff.
 * Rungs given at random on a moving lattice: rigid motion, and the oracle's
   face count (each face once per step of its smaller-step end).
 * The 128^3 Sedov blast after five global steps, one base step of 32 of
@@ -117,6 +119,40 @@ def test_rungs_match_the_oracle(scheme):
     assert len(np.unique(rung)) >= 4
     worst = _compare(_by_id(ps), ref, 1e-12)
     print(f"[rungs] worst {worst:.2e}, faces {diag['faces']} (oracle {cnt['faces']})", flush=True)
+    assert diag["faces"] == cnt["faces"]
+    pscale = float((st["m"] * (np.abs(ref["vx"]) + np.abs(ref["vy"]) + np.abs(ref["vz"]))).sum())
+    assert abs(diag["mass"] - d0["mass"]) <= 1e-14 * d0["mass"]
+    for k in ("px", "py", "pz"):
+        assert abs(diag[k] - d0[k]) <= 1e-13 * pscale, k
+    assert abs(diag["energy"] - d0["energy"]) <= 1e-13 * d0["energy"]
+    ctx.close()
+
+
+def test_mixed_rungs_match_the_oracle():
+    """The mixed path on rungs: the oracle's rungs given, the state after the
+    base step within the mixed path's bound of the oracle's FP64 one (its
+    gradient redo and flux passes take the mid-step neighbours' positions of
+    each sub-step), and M, P, E conserved to roundoff (every face's share is
+    accumulated in FP64, once per side with opposite signs)."""
+    _need_gpu()
+    st = W.sedov(n=16, seed=3)
+    cfg = {"scheme": "mfm"}
+    dt0 = 8.3 * _dt_min(cfg, st)
+    ref, r_ref, nsub_ref, cnt = oracle.step_rungs(cfg, st, dt0)
+    n = st["x"].size
+    ctx = mfm.Context(mfm.params_from_dict(cfg, precision="mixed"), n)
+    ps = mfm.ParticleSet(st)
+    d0 = mfm.mfm_diagnostics(ctx, ps)
+    mfm.mfm_reset_counters(ctx)
+    print(f"[rungs] sedov16 mfm mixed: {nsub_ref} sub-steps", flush=True)
+    given = torch.from_numpy(np.ascontiguousarray(r_ref, dtype=np.int32)).cuda()
+    nsub, r = mfm.mfm_step_rungs(ctx, ps, dt0, given)
+    torch.cuda.synchronize()
+    diag = mfm.mfm_diagnostics(ctx, ps)
+    assert nsub == nsub_ref
+    worst = _compare(_by_id(ps), ref, 1e-5)
+    print(f"[rungs] mixed worst {worst:.2e}, faces {diag['faces']} (oracle {cnt['faces']})",
+          flush=True)
     assert diag["faces"] == cnt["faces"]
     pscale = float((st["m"] * (np.abs(ref["vx"]) + np.abs(ref["vy"]) + np.abs(ref["vz"]))).sum())
     assert abs(diag["mass"] - d0["mass"]) <= 1e-14 * d0["mass"]
