@@ -12,6 +12,7 @@
 // that tree per chunk of a bucket, so a particle's candidates follow its own
 // H and its neighbours', not the largest H of the set.
 #include "mfm_internal.h"
+#include "lanes.h"
 
 namespace {
 
@@ -186,25 +187,24 @@ __global__ void __launch_bounds__(64) leaf_box_k(int64_t n, const double4 *__res
   double lo[3] = {p.x, p.y, p.z}, hi[3] = {p.x, p.y, p.z}, h = live ? p.w : 0.0;
 #pragma unroll
   for (int k = 0; k < 3; ++k) {
-    lo[k] = wave_min_f64(lo[k]);
-    hi[k] = wave_max_f64(hi[k]);
+    lo[k] = lanes::wave_min_f64(lo[k]);
+    hi[k] = lanes::wave_max_f64(hi[k]);
   }
-  h = wave_max_f64(h);
+  h = lanes::wave_max_f64(h);
   // each chunk of LCH lanes: its box's half-diagonal against its particles'
   // mean search radius (the spread flag the search reads); a lane past the
   // end takes the last particle, which lies in the same chunk
   const double4 pl = pos4[live ? i : n - 1];
   double clo[3] = {pl.x, pl.y, pl.z}, chi[3] = {pl.x, pl.y, pl.z}, r = live ? hfac * pl.w : 0.0;
   double cnt = live ? 1.0 : 0.0;
-  for (int o = 1; o < LCH; o <<= 1) {
+  static_assert(LCH == 16, "a chunk is one 16-lane DPP row");
 #pragma unroll
-    for (int k = 0; k < 3; ++k) {
-      clo[k] = fmin(clo[k], __shfl_xor(clo[k], o, 64));
-      chi[k] = fmax(chi[k], __shfl_xor(chi[k], o, 64));
-    }
-    r += __shfl_xor(r, o, 64);
-    cnt += __shfl_xor(cnt, o, 64);
+  for (int k = 0; k < 3; ++k) {
+    clo[k] = lanes::row_min_f64(clo[k]);
+    chi[k] = lanes::row_max_f64(chi[k]);
   }
+  r = lanes::row_sum_f64(r);
+  cnt = lanes::row_sum_f64(cnt);
   double diag2 = 0.0;
 #pragma unroll
   for (int k = 0; k < 3; ++k) diag2 += (chi[k] - clo[k]) * (chi[k] - clo[k]);

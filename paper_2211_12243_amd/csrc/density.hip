@@ -22,6 +22,7 @@
 //   cand / rest_r2    the other candidates, r >= H_i, with r^2 in FP32, where
 //                     the gradient loop finds the faces with H_i <= r < H_j.
 #include "mfm_internal.h"
+#include "lanes.h"
 
 namespace {
 
@@ -157,11 +158,11 @@ __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) ca
         double bc[3], bh[3];
     #pragma unroll
         for (int k = 0; k < 3; ++k) {
-          const double lo = wave_min_f64(blo[k]), hi = wave_max_f64(bhi[k]);
+          const double lo = lanes::wave_min_f64(blo[k]), hi = lanes::wave_max_f64(bhi[k]);
           bc[k] = uniform_f64(0.5 * (lo + hi));
           bh[k] = uniform_f64(0.5 * (hi - lo));
         }
-        const double Rc = uniform_f64(wave_max_f64(th));
+        const double Rc = uniform_f64(lanes::wave_max_f64(th));
         // a node is opened when its box and the chunk's are closer than the
         // larger radius (raised by 1e-12 so that rounding in the box distance
         // cannot drop a pair at the edge)
@@ -370,7 +371,7 @@ __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) ca
         // the chunk's staged lists, plane by plane:
         // lane -> (plane kk + lane / TCH, particle lane % TCH)
         int mine = lane < T ? min(s_cnt[lane], min(LCAP, cap)) : 0;
-        const int kmax = wave_max_i32(mine);
+        const int kmax = lanes::wave_max_i32(mine);
         const int tl = lane % TCH;
         const int lim = tl < T ? min(s_cnt[tl], min(LCAP, cap)) : 0;
         for (int kk = 0; kk < kmax; kk += 64 / TCH) {
@@ -624,6 +625,10 @@ __device__ __forceinline__ void finish_particle(const DensityArgs &a, int64_t i,
   gr[2] = make_double4(vz, P, cs, 0.0);
   float4 *gf = reinterpret_cast<float4 *>(a.gin + i * GIN_STRIDE + GIN_F32);
   gf[0] = make_float4((float)V, (float)rho, (float)P, (float)cs);
+  // the record's last 16 bytes are unused: written too, so that no 32-byte
+  // sector of it is left partly written
+  static_assert(GIN_F32 + 4 == GIN_STRIDE, "the FP32 copies end 16 bytes before the record");
+  gf[1] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
 }
 
 // One wavefront per DT consecutive particles.  A particle's candidate list is
