@@ -74,15 +74,6 @@ constexpr int MAXF = 256;  // accepted nodes of one tree level per chunk
 constexpr int TSUB = 4;    // particles per sub-chunk of a spread chunk (cells.hip marks them)
 constexpr int SEARCH_WG_TARGET = 4096;  // buckets below which each chunk has its own workgroup
 
-// Lane l's value in every lane (a scalar broadcast, no memory traffic).
-__device__ __forceinline__ double readlane_f64(double v, int l) {
-  const int2 w = *reinterpret_cast<const int2 *>(&v);
-  int2 r;
-  r.x = __builtin_amdgcn_readlane(w.x, l);
-  r.y = __builtin_amdgcn_readlane(w.y, l);
-  return *reinterpret_cast<const double *>(&r);
-}
-
 // A wave-uniform value moved to scalar registers (lane 0's copy).
 __device__ __forceinline__ double uniform_f64(double v) {
   const int2 w = *reinterpret_cast<const int2 *>(&v);
@@ -313,8 +304,8 @@ __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) ca
           constexpr bool WRAP = decltype(wrap)::value;
           for (int t = 0; t < T; ++t) {
             const int ti = own_x + t0 + t;
-            const double ptx = readlane_f64(tx, t), pty = readlane_f64(ty, t),
-                         ptz = readlane_f64(tz, t), ptq = readlane_f64(tq, t);
+            const double ptx = lanes::read_f64(tx, t), pty = lanes::read_f64(ty, t),
+                         ptz = lanes::read_f64(tz, t), ptq = lanes::read_f64(tq, t);
             int base = __builtin_amdgcn_readlane(tcnt, t);
     #pragma unroll
             for (int s = 0; s < SLOTS; ++s) {
@@ -432,16 +423,6 @@ constexpr int DM = 8;
 constexpr int DCAP = DG * DM;
 static_assert(LCH % DT == 0, "a wavefront's particles share one list chunk");
 
-// A double moved across lanes by a DPP control (both halves).
-template <int CTRL>
-__device__ __forceinline__ double dpp_f64(double v) {
-  const int2 w = *reinterpret_cast<const int2 *>(&v);
-  int2 r;
-  r.x = __builtin_amdgcn_mov_dpp(w.x, CTRL, 0xf, 0xf, false);
-  r.y = __builtin_amdgcn_mov_dpp(w.y, CTRL, 0xf, 0xf, false);
-  return *reinterpret_cast<const double *>(&r);
-}
-
 // Sum over the G lanes of an aligned group, as a butterfly: lane pairs
 // 1 apart, then 2 apart, then the other quad.  Every lane gets the same bits,
 // since each pairwise sum is formed from the same two operands.  For G = 8
@@ -452,9 +433,9 @@ template <int G>
 __device__ __forceinline__ double group_sum(double v) {
   static_assert(G == 1 || G == 8, "group sums are built for 1 or 8 lanes");
   if constexpr (G == 8) {
-    v += dpp_f64<0xB1>(v);   // quad_perm [1, 0, 3, 2]: partner lane ^ 1
-    v += dpp_f64<0x4E>(v);   // quad_perm [2, 3, 0, 1]: partner lane ^ 2
-    v += dpp_f64<0x141>(v);  // row_half_mirror: lane 7 - l of its 8
+    v += lanes::dpp_f64<lanes::QUAD_XOR1>(v);        // partner lane ^ 1
+    v += lanes::dpp_f64<lanes::QUAD_XOR2>(v);        // partner lane ^ 2
+    v += lanes::dpp_f64<lanes::ROW_HALF_MIRROR>(v);  // lane 7 - l of its 8
   }
   return v;
 }
@@ -740,7 +721,7 @@ __device__ __forceinline__ void density_group(const DensityArgs &a, const Tree &
   const bool own = pl < n && (!a.act || a.act[pl]) && s_gn[tl] >= 0;
   const int glim = own ? s_gn[tl] : 0;
   const int rlim = own ? s_rn[tl] : 0;
-  const int kmax = wave_max_i32(max(glim, rlim));
+  const int kmax = lanes::wave_max_i32(max(glim, rlim));
   const int64_t pb = pl < n ? list_base(a.lseg, pl) : 0;
   for (int kk = 0; kk < kmax; kk += 64 / DT) {
     const int k = kk + lane / DT;

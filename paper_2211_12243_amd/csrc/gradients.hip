@@ -17,6 +17,7 @@
 // in FP64 (and the gradients formed with that inverse), as are the outputs
 // kept in FP64 arrays.
 #include "mfm_internal.h"
+#include "lanes.h"
 
 namespace {
 
@@ -201,12 +202,12 @@ __global__ void __launch_bounds__(BS) gradients_k(GradArgs a) {
     // before RSTEP list entries (at most one face each per lane): keep every
     // slot they may take inside the ring
     auto make_room = [&]() {
-      const int hi = wave_max_i32(nf);
+      const int hi = lanes::wave_max_i32(nf);
       while (hi + RSTEP > flushed + RING) store_plane(flushed++);
     };
     // after it: store the planes every lane has passed
     auto store_done = [&]() {
-      const int lo = wave_min_i32(live ? nf : 0x7fffffff);
+      const int lo = lanes::wave_min_i32(live ? nf : 0x7fffffff);
       while (flushed < lo) store_plane(flushed++);
     };
     // faces of the flux loop: r < max(H_i, H_j); one evaluation per face
@@ -214,7 +215,7 @@ __global__ void __launch_bounds__(BS) gradients_k(GradArgs a) {
     // (1) the gather set r < H_i (the density loop's compact list, in
     // candidate order): every member is also a face
     const int gc = live ? a.gl_cnt[i] : 0;
-    const int gmax = wave_max_i32(gc);
+    const int gmax = lanes::wave_max_i32(gc);
     // the first loop runs two entries ahead for the list index and one ahead
     // for the neighbour's record, so that a gather is in flight while the
     // previous entry is summed; the others load their next entry one
@@ -281,7 +282,7 @@ __global__ void __launch_bounds__(BS) gradients_k(GradArgs a) {
     // clearly inside or outside H_j is decided from it, one within a band of
     // 2^-22 around H_j^2 from the exact FP64 r^2 of the positions.
     const int cnt = live ? a.cand_cnt[i] : 0;
-    const int cmax = wave_max_i32(cnt);
+    const int cmax = lanes::wave_max_i32(cnt);
     int cj = cnt > 0 ? a.cand[list_at(lb, 0)] : 0;
     float cr = cnt > 0 ? a.rest_r2[list_at(lb, 0)] : 0.0f;
     for (int k = 0; k < cmax; ++k) {
@@ -307,7 +308,7 @@ __global__ void __launch_bounds__(BS) gradients_k(GradArgs a) {
       }
       if (k % RSTEP == RSTEP - 1) store_done();
     }
-    for (const int top = wave_max_i32(nf); flushed < top;) store_plane(flushed++);
+    for (const int top = lanes::wave_max_i32(nf); flushed < top;) store_plane(flushed++);
     T b[6];
     T det = sym_inv<T>(e, b);
     T nc = sym_frob<T>(b) * sym_frob<T>(e) / T(3);

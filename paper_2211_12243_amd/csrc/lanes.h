@@ -73,5 +73,13 @@ __device__ __forceinline__ int wave_max_i32(int v) {
   return max(max(__builtin_amdgcn_readlane(v, 0), __builtin_amdgcn_readlane(v, 16)),
              max(__builtin_amdgcn_readlane(v, 32), __builtin_amdgcn_readlane(v, 48)));
 }
+__device__ __forceinline__ int wave_min_i32(int v) {
+  v = min(v, dpp_i32<QUAD_XOR1>(v));
+  v = min(v, dpp_i32<QUAD_XOR2>(v));
+  v = min(v, dpp_i32<ROW_HALF_MIRROR>(v));
+  v = min(v, dpp_i32<ROW_MIRROR>(v));
+  return min(min(__builtin_amdgcn_readlane(v, 0), __builtin_amdgcn_readlane(v, 16)),
+             min(__builtin_amdgcn_readlane(v, 32), __builtin_amdgcn_readlane(v, 48)));
+}
 
 }  // namespace lanes
