@@ -298,7 +298,11 @@ int mfm_step(struct mfm_ctx *ctx, const mfm_particles *parts, double dt_max, dou
  * No source terms (mfm_set_cosmology at its defaults, no accel) and no
  * entropy switch: MFM_E_ARG otherwise; a step that needs a rung deeper than
  * MFM_RUNG_MAX: MFM_E_NONFINITE.  nsub_out (host, may be NULL) receives the
- * number of sub-steps.  Synchronises once per sub-step. */
+ * number of sub-steps.  Synchronises once per sub-step.  The first call on a
+ * context from mfm_create allocates a small pinned host buffer and an event
+ * (freed by mfm_destroy) for the per-sub-step read of the pass counters; a
+ * context from mfm_create_static allocates nothing and reads them with a
+ * synchronising copy. */
 #define MFM_RUNG_MAX 24
 int mfm_step_rungs(struct mfm_ctx *ctx, const mfm_particles *parts, double dt0, int32_t *rung,
                    int rungs_given, int64_t *nsub_out);

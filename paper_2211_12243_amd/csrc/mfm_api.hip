@@ -377,6 +377,11 @@ int mfm_destroy(mfm_ctx *ctx) {
   hipStreamSynchronize(ctx->stream);
   if (ctx->ev_created)
     for (int q = 0; q < 2 * MAX_EVENT_PAIRS; ++q) hipEventDestroy(ctx->ev_pool[q]);
+  if (ctx->host_ctr) {
+    hipEventDestroy(ctx->ev_ctr);
+    hipHostFree(ctx->host_ctr);
+    ctx->host_ctr = nullptr;
+  }
   if (ctx->static_dev) {
     std::lock_guard<std::mutex> lock(static_mu);
     static_busy[ctx->static_dev - 1] = 0;
@@ -631,6 +636,32 @@ int read_step_counters(mfm_ctx *ctx, int64_t *c) {
   return MFM_OK;
 }
 
+// The counters at the end of sub-step k of individual steps.  With the
+// pinned copy, the start of sub-step k + 1 (when there is one) is enqueued
+// before the host waits, so that the GPU runs it while the host takes the
+// counters and enqueues the rest of that sub-step; *next_begun says so.  A
+// rejected sub-step k is started again from its own start, which overwrites
+// what that early start wrote.
+int read_substep_counters(mfm_ctx *ctx, const mfm_particles *pp, int64_t *c, int64_t k,
+                          int64_t nsub, bool *next_begun) {
+  *next_begun = false;
+  if (!ctx->host_ctr) return read_step_counters(ctx, c);
+  HIPCHK(ctx, hipMemcpyAsync(ctx->host_ctr, ctx->counters, sizeof(int64_t) * NCOUNTERS,
+                             hipMemcpyDeviceToHost, ctx->stream),
+         "read counters");
+  HIPCHK(ctx, hipEventRecord(ctx->ev_ctr, ctx->stream), "record the counters' event");
+  if (k + 1 < nsub) {
+    ctx->rungs.k = k + 1;
+    const hipError_t e = launch_substep_begin(ctx, pp);
+    ctx->rungs.k = k;
+    HIPCHK(ctx, e, "next sub-step start");
+    *next_begun = true;
+  }
+  HIPCHK(ctx, hipEventSynchronize(ctx->ev_ctr), "synchronise");
+  memcpy(c, ctx->host_ctr, sizeof(int64_t) * NCOUNTERS);
+  return MFM_OK;
+}
+
 // After a rejected density pass: which retry, or the error.
 int on_skip(mfm_ctx *ctx, const int64_t *c) {
   if (c[C_PASS_LIST] > 0 && c[C_LIST_POOL])
@@ -736,11 +767,22 @@ int mfm_step_rungs(mfm_ctx *ctx, const mfm_particles *pp, double dt0, int32_t *r
   ctx->rungs.rmax = rmax;
   HIPCHK(ctx, hipMemsetAsync(ctx->s0_w, 0, sizeof(int32_t) * n, ctx->stream), "clear step starts");
   HIPCHK(ctx, hipMemsetAsync(pp->dQ, 0, sizeof(double) * 5 * n, ctx->stream), "clear flux sums");
+  if (!ctx->host_ctr && !ctx->static_dev) {
+    // the pinned counter copy of the sub-step loop (kept until mfm_destroy)
+    if (hipHostMalloc((void **)&ctx->host_ctr, sizeof(int64_t) * NCOUNTERS) != hipSuccess) {
+      ctx->host_ctr = nullptr;
+    } else if (hipEventCreateWithFlags(&ctx->ev_ctr, hipEventDisableTiming) != hipSuccess) {
+      hipHostFree(ctx->host_ctr);
+      ctx->host_ctr = nullptr;
+    }
+  }
+  bool begun = false;  // this sub-step's start was enqueued by the one before
   for (int64_t k = 0; k < nsub; ++k) {
     ctx->rungs.k = k;
     ok = false;
     for (int attempt = 0; attempt < 6 && !ok; ++attempt) {
-      HIPCHK(ctx, launch_substep_begin(ctx, pp), "sub-step start");
+      if (!begun) HIPCHK(ctx, launch_substep_begin(ctx, pp), "sub-step start");
+      begun = false;
       if (k > 0) {
         // the particles whose step begins: tree at this sub-step's positions,
         // search, density and gradient loops
@@ -759,9 +801,10 @@ int mfm_step_rungs(mfm_ctx *ctx, const mfm_particles *pp, double dt0, int32_t *r
       int ev = stage_begin(ctx, 5);
       HIPCHK(ctx, launch_update(ctx, pp, dt_dev), "close");
       stage_end(ctx, ev);
-      int rc = read_step_counters(ctx, c);
+      int rc = read_substep_counters(ctx, pp, c, k, nsub, &begun);
       if (rc) return rc;
       if (k > 0 && c[C_STEP_SKIP]) {
+        begun = false;  // sub-step k starts again from its own start
         rc = on_skip(ctx, c);
         if (rc) return rc;
         continue;

@@ -217,6 +217,11 @@ struct mfm_ctx {
   double stage_ms[MFM_NSTAGES];
   int64_t stage_count[MFM_NSTAGES];
   int static_dev;  // 1 + the GPU whose static scratch this context uses (0: caller's workspace)
+  // individual steps: pinned host copy of the counters and the event after
+  // which it holds a sub-step's values (made on first use; none on a static
+  // context, which reads the counters with a plain synchronising copy)
+  int64_t *host_ctr;
+  hipEvent_t ev_ctr;
   char err[512];
 };
 
