@@ -754,26 +754,23 @@ __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) de
   count_add(a.counters + C_CELL_OVERFLOW, pc.overflow);
 }
 
-// The sub-steps of individual time steps, where few particles are active: a
-// capped grid whose workgroups stride over the groups, skipping a group
-// without an active particle.
-__global__ void __launch_bounds__(64) density_sub_k(DensityArgs a, Tree g) {
-  __shared__ int32_t s_i[DCAP][DT];
-  __shared__ float s_f[DCAP][DT];
-  __shared__ int s_gn[DT], s_rn[DT];
-  if (a.counters[C_PASS_LIST] != 0) return;
-  PassCounts pc;
-  const int64_t ngroups = (a.n + DT - 1) / DT;
-  for (int64_t grp = blockIdx.x; grp < ngroups; grp += gridDim.x) {
-    // a wave-uniform test: the group holds a particle whose step begins
-    const int64_t i = grp * DT + threadIdx.x / DG;
-    if (!__ballot(i < a.n && a.act[i])) continue;
-    density_group(a, g, grp, DensityStage{s_i, s_f, s_gn, s_rn}, pc);
-  }
-  count_add(a.counters + C_PASS_NOCONV, pc.noconv);
-  count_add(a.counters + C_PASS_BOOSTS, pc.boosts);
-  count_add(a.counters + C_PASS_FAIL, pc.fails);
-  count_add(a.counters + C_CELL_OVERFLOW, pc.overflow);
+// The sub-steps of individual time steps, where few particles are active:
+// every particle whose step begins is queued for density_wave_k, whose 64
+// lanes per particle shorten the serial chain of loads and Newton passes
+// that the few busy wavefronts of an 8-lane group would run.
+__global__ void __launch_bounds__(BS) queue_active_k(DensityArgs a) {
+  if (a.counters[C_PASS_LIST] != 0) return;  // as in density_k
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  const bool on = i < a.n && a.act[i];
+  const uint64_t m = __ballot(on);
+  if (!m) return;  // wave-uniform
+  const int leader = __ffsll((unsigned long long)m) - 1;
+  unsigned long long base = 0;
+  if ((int)(threadIdx.x & 63) == leader)
+    base = atomicAdd(reinterpret_cast<unsigned long long *>(a.counters + C_LONG_QUEUE),
+                     (unsigned long long)__popcll(m));
+  base = __shfl(base, leader, 64);
+  if (on) a.long_q[base + lanes_below(m)] = (int32_t)i;
 }
 
 // The lists density_k could not hold (queued, gl_cnt = -1): one wavefront
@@ -956,7 +953,7 @@ hipError_t launch_density(mfm_ctx *ctx, const mfm_particles *pp) {
   a.long_q = ctx->grad_q;  // the gradient loop's queue, unused until that loop
   const int64_t groups = (pp->n + DT - 1) / DT;
   if (a.act)
-    density_sub_k<<<(unsigned)std::min<int64_t>(groups, 8192), 64, 0, ctx->stream>>>(a, ctx->tree);
+    queue_active_k<<<blocks_for(pp->n, BS), BS, 0, ctx->stream>>>(a);
   else
     density_k<<<(unsigned)groups, 64, 0, ctx->stream>>>(a, ctx->tree);
   density_wave_k<<<2048, BS, 0, ctx->stream>>>(a, ctx->tree);
