@@ -223,18 +223,24 @@ __global__ void __launch_bounds__(BS) gradients_k(GradArgs a) {
     int jn = gc > 0 ? a.gl[list_at(lb, 0)] : 0;
     int jn2 = gc > 1 ? a.gl[list_at(lb, 1)] : 0;
     NbRec<T> nb;
-    if (gc > 0) load_nb<RUNG>(nb, a, jn);
+    bool nact = true;  // on a sub-step: the next neighbour's active flag, with its record
+    if (gc > 0) {
+      load_nb<RUNG>(nb, a, jn);
+      if (RUNG) nact = a.act[jn] != 0;
+    }
     for (int k = 0; k < gmax; ++k) {
       if (k % RSTEP == 0) make_room();
       if (k < gc) {
         const int j = jn;
         const NbRec<T> cur = nb;
+        const bool jact = nact;
         if (k + 1 < gc) {
           jn = jn2;
           load_nb<RUNG>(nb, a, jn);
+          if (RUNG) nact = a.act[jn] != 0;
           if (k + 2 < gc) jn2 = a.gl[list_at(lb, k + 2)];
         }
-        if (emit_face((int)i, j) || (a.act && !a.act[j])) put_face(j);
+        if (emit_face((int)i, j) || (RUNG && !jact)) put_face(j);
         ++pairs;
         const double e0 = min_image(cur.x - xi, a.box[0], a.half[0]);
         const double e1 = min_image(cur.y - yi, a.box[1], a.half[1]);
@@ -283,18 +289,32 @@ __global__ void __launch_bounds__(BS) gradients_k(GradArgs a) {
     // 2^-22 around H_j^2 from the exact FP64 r^2 of the positions.
     const int cnt = live ? a.cand_cnt[i] : 0;
     const int cmax = lanes::wave_max_i32(cnt);
+    // the list entry two ahead, the neighbour's H (and on a sub-step its
+    // active flag) one ahead, so that no load is waited for in the
+    // iteration that issues it
     int cj = cnt > 0 ? a.cand[list_at(lb, 0)] : 0;
     float cr = cnt > 0 ? a.rest_r2[list_at(lb, 0)] : 0.0f;
+    int cj2 = cnt > 1 ? a.cand[list_at(lb, 1)] : 0;
+    float cr2 = cnt > 1 ? a.rest_r2[list_at(lb, 1)] : 0.0f;
+    double ch = cnt > 0 ? a.H[cj] : 0.0;
+    bool cact = RUNG && cnt > 0 ? a.act[cj] != 0 : true;
     for (int k = 0; k < cmax; ++k) {
       if (k % RSTEP == 0) make_room();
       if (k < cnt) {
         const int j = cj;
         const double r2f = (double)cr;
+        const double hj = ch;
+        const bool jact = cact;
         if (k + 1 < cnt) {
-          cj = a.cand[list_at(lb, k + 1)];
-          cr = a.rest_r2[list_at(lb, k + 1)];
+          cj = cj2;
+          cr = cr2;
+          ch = a.H[cj];
+          if (RUNG) cact = a.act[cj] != 0;
+          if (k + 2 < cnt) {
+            cj2 = a.cand[list_at(lb, k + 2)];
+            cr2 = a.rest_r2[list_at(lb, k + 2)];
+          }
         }
-        const double hj = a.H[j];
         const double hj2 = hj * hj;
         bool in = r2f < hj2 * (1.0 - 0x1p-22) && r2f > 1e-30;
         if (!in && !(r2f > hj2 * (1.0 + 0x1p-22) && r2f > 1e-30)) {
@@ -304,7 +324,7 @@ __global__ void __launch_bounds__(BS) gradients_k(GradArgs a) {
           const double e2 = min_image(pj.z - zi, a.box[2], a.half[2]);
           in = e0 * e0 + e1 * e1 + e2 * e2 < hj2;
         }
-        if (in && (emit_face((int)i, j) || (a.act && !a.act[j]))) put_face(j);
+        if (in && (emit_face((int)i, j) || (RUNG && !jact))) put_face(j);
       }
       if (k % RSTEP == RSTEP - 1) store_done();
     }
