@@ -272,7 +272,16 @@ int mfm_set_cosmology(struct mfm_ctx *ctx, double inv_a, double hubble_n, double
 int mfm_update(struct mfm_ctx *ctx, const mfm_particles *parts, const double *dt_dev);
 
 /* One full step: cells, density, gradients, fluxes, update.  dt_host receives
- * the step taken.  Synchronises. */
+ * the step taken.  Synchronises.  The cells stage sorts as mfm_build_cells
+ * does, except while the order of the last sort still groups the particles
+ * well: a step on the same arrays (same x pointer and count) after a step
+ * whose cells, search and density stages took no longer than those of the
+ * step of that sort (timed with events; at most 16 steps after it) builds
+ * the tree over the particles in their present order instead.  Which pairs
+ * interact does not depend on the order; mfm_build_cells and
+ * mfm_step_rungs always sort, and so does every step on a context from
+ * mfm_create_static.  A context from mfm_create makes two events for this
+ * on its first step (freed by mfm_destroy). */
 int mfm_step(struct mfm_ctx *ctx, const mfm_particles *parts, double dt_max, double *dt_host);
 
 /* Individual time steps (sec. 2.3.4, last paragraphs; sec. 2.3.10): one base

@@ -340,6 +340,24 @@ hipError_t launch_build_cells(mfm_ctx *ctx, const mfm_particles *pp, int64_t *pe
   return launch_tree(ctx, n);
 }
 
+namespace {
+
+// pos4 = (x, y, z, H) of the particles in their present order
+__global__ void pos4_k(int64_t n, const double *__restrict__ x, const double *__restrict__ y,
+                       const double *__restrict__ z, const double *__restrict__ H,
+                       double4 *pos4) {
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i < n) pos4[i] = make_double4(x[i], y[i], z[i], H[i]);
+}
+
+}  // namespace
+
+hipError_t launch_refresh_cells(mfm_ctx *ctx, const mfm_particles *pp) {
+  pos4_k<<<blocks_for(pp->n, BS), BS, 0, ctx->stream>>>(
+      pp->n, pp->x, pp->y, pp->z, pp->H, reinterpret_cast<double4 *>(ctx->pos4));
+  return launch_tree(ctx, pp->n);
+}
+
 hipError_t launch_tree(mfm_ctx *ctx, int64_t n) {
   hipStream_t st = ctx->stream;
   const Tree &g = ctx->tree;

@@ -377,6 +377,11 @@ int mfm_destroy(mfm_ctx *ctx) {
   hipStreamSynchronize(ctx->stream);
   if (ctx->ev_created)
     for (int q = 0; q < 2 * MAX_EVENT_PAIRS; ++q) hipEventDestroy(ctx->ev_pool[q]);
+  if (ctx->ev_ord_made) {
+    hipEventDestroy(ctx->ev_ord[0]);
+    hipEventDestroy(ctx->ev_ord[1]);
+    ctx->ev_ord_made = 0;
+  }
   if (ctx->host_ctr) {
     hipEventDestroy(ctx->ev_ctr);
     hipHostFree(ctx->host_ctr);
@@ -423,6 +428,21 @@ int build_cells_async(mfm_ctx *ctx, const mfm_particles *pp, int64_t *perm) {
   return MFM_OK;
 }
 
+// The tree over the particles in their present order, without the sort
+// (mfm_step's reuse of the last order).
+int refresh_cells_async(mfm_ctx *ctx, const mfm_particles *pp) {
+  int rc = setup_tree(ctx, pp->n);
+  if (rc) return rc;
+  const int ev = stage_begin(ctx, 0);
+  HIPCHK(ctx, launch_refresh_cells(ctx, pp), "tree");
+  stage_end(ctx, ev);
+  ctx->have_cells = 1;
+  ctx->have_density = 0;
+  ctx->have_grad = 0;
+  ctx->n_cells_built = pp->n;
+  return MFM_OK;
+}
+
 // Neighbour search, density pass and its validation (no synchronisation).
 int density_async(mfm_ctx *ctx, const mfm_particles *pp) {
   static_assert(C_STEP_SKIP - C_CELL_OVERFLOW == 5, "per-pass counters are contiguous");
@@ -452,6 +472,7 @@ extern "C" {
 int mfm_build_cells(mfm_ctx *ctx, const mfm_particles *pp, int64_t *perm) {
   if (!ctx) return MFM_E_ARG;
   if (!check_parts(ctx, pp)) return fail(ctx, MFM_E_ARG, "invalid particle set");
+  ctx->keep_order = 0;
   return build_cells_async(ctx, pp, perm);
 }
 
@@ -577,14 +598,41 @@ int mfm_step(mfm_ctx *ctx, const mfm_particles *pp, double dt_max, double *dt_ho
   // is rejected on the device; the kernels after it return at once (the
   // state is not updated), and the step is repeated with larger radii or
   // blocks.
+  //
+  // The particle order: the sort (and the permutation of every array) is
+  // skipped while the last step left keep_order set for these arrays: the
+  // tree is then built over the particles in the order the last sort gave
+  // them.  Events time the cells, search and density stages of every step;
+  // a step that keeps the order saves the sort but its search and density
+  // loops slow down as the particles drift out of their grouping, so the
+  // next step sorts again once that time reaches the one of the step of the
+  // last sort, after KEEP_MAX_STEPS steps, or on a repeated attempt.  A
+  // sorting step whose search first counted its lists (a first step, grown
+  // radii) is no reference: the step after it sorts again.  A context on
+  // the static scratch makes no events and always sorts.  The order changes only the grouping of the search,
+  // never which pairs interact.
   double *dt_dev = ctx->scalars + 1;
   for (int attempt = 0; attempt < 6; ++attempt) {
     HIPCHK(ctx, hipMemsetAsync(ctx->counters + C_NONFINITE, 0, sizeof(int64_t), ctx->stream),
            "clear step counters");
-    int rc = build_cells_async(ctx, pp, nullptr);
+    const bool kept = attempt == 0 && ctx->keep_order && ctx->order_x == pp->x &&
+                      ctx->order_n == pp->n && ctx->have_need && ctx->need_n == pp->n;
+    ctx->keep_order = 0;
+    if (!ctx->ev_ord_made && !ctx->static_dev) {
+      if (hipEventCreate(&ctx->ev_ord[0]) == hipSuccess) {
+        if (hipEventCreate(&ctx->ev_ord[1]) == hipSuccess)
+          ctx->ev_ord_made = 1;
+        else
+          hipEventDestroy(ctx->ev_ord[0]);
+      }
+    }
+    const bool counted = !ctx->have_need || ctx->need_n != pp->n;  // a counting search
+    if (ctx->ev_ord_made) HIPCHK(ctx, hipEventRecord(ctx->ev_ord[0], ctx->stream), "event");
+    int rc = kept ? refresh_cells_async(ctx, pp) : build_cells_async(ctx, pp, nullptr);
     if (rc) return rc;
     rc = density_async(ctx, pp);
     if (rc) return rc;
+    if (ctx->ev_ord_made) HIPCHK(ctx, hipEventRecord(ctx->ev_ord[1], ctx->stream), "event");
     ctx->have_density = 1;
     rc = mfm_gradients(ctx, pp, dt_max, dt_dev);
     if (rc) return rc;
@@ -603,7 +651,8 @@ int mfm_step(mfm_ctx *ctx, const mfm_particles *pp, double dt_max, double *dt_ho
     if (c[C_STEP_SKIP]) {
       // lists longer than their planned blocks: the next attempt plans from
       // the lengths this one recorded (the same order, the same lists)
-      if (c[C_PASS_LIST] > 0 && c[C_LIST_POOL])
+      // (on a kept order the next attempt sorts first, which may fit the pool)
+      if (c[C_PASS_LIST] > 0 && c[C_LIST_POOL] && !kept)
         return fail(ctx, MFM_E_LIST, "neighbour lists exceed the list pool (raise max_list)");
       if (c[C_CELL_OVERFLOW] > 0) {
         // new start values (and radii): the next search counts its lists
@@ -615,6 +664,20 @@ int mfm_step(mfm_ctx *ctx, const mfm_particles *pp, double dt_max, double *dt_ho
     }
     relax_margin(ctx);
     *dt_host = sc[1];
+    // the order for the next step
+    float ms = 0.0f;
+    if (ctx->ev_ord_made &&
+        hipEventElapsedTime(&ms, ctx->ev_ord[0], ctx->ev_ord[1]) == hipSuccess) {
+      if (!kept) {
+        ctx->ms_sorted = ms;
+        ctx->steps_kept = 0;
+      } else {
+        ++ctx->steps_kept;
+      }
+      ctx->keep_order = !counted && ms <= ctx->ms_sorted && ctx->steps_kept + 1 < KEEP_MAX_STEPS;
+    }
+    ctx->order_x = pp->x;
+    ctx->order_n = pp->n;
     if (c[C_NONFINITE] > 0) return fail(ctx, MFM_E_NONFINITE, "non-finite step or state");
     if (c[C_PASS_NOCONV] > 0)
       return fail(ctx, MFM_E_H_NOCONV, "smoothing-length solve did not converge");
@@ -699,6 +762,7 @@ int mfm_step_rungs(mfm_ctx *ctx, const mfm_particles *pp, double dt0, int32_t *r
   if (ctx->p.guess == MFM_GUESS_LEARNED && !ctx->mlp_state)
     return fail(ctx, MFM_E_STATE, "learned guess requested but no network attached");
   RungsOff off{ctx};
+  ctx->keep_order = 0;  // the base step sorts; the next mfm_step sorts again
   memset(&ctx->rungs, 0, sizeof(ctx->rungs));
   ctx->rung_perm = rungs_given ? rung_io : nullptr;
   const int64_t n = pp->n;

@@ -222,6 +222,17 @@ struct mfm_ctx {
   // context, which reads the counters with a plain synchronising copy)
   int64_t *host_ctr;
   hipEvent_t ev_ctr;
+  // mfm_step's reuse of the particle order: keep_order says the next step
+  // may skip the sort (set at the end of a step, for the arrays order_x of
+  // order_n particles); ev_ord time the cells, search and density stages
+  // of a step (made on first use; none on a static context, which always
+  // sorts), ms_sorted is that time in the step of the last sort, steps_kept
+  // the steps since
+  int keep_order, steps_kept, ev_ord_made;
+  hipEvent_t ev_ord[2];
+  float ms_sorted;
+  const double *order_x;
+  int64_t order_n;
   char err[512];
 };
 
@@ -335,6 +346,8 @@ hipError_t launch_update(mfm_ctx *ctx, const mfm_particles *pp, const double *dt
 // The bucket tree over the particles' current positions (pos4), in the
 // current order.
 hipError_t launch_tree(mfm_ctx *ctx, int64_t n);
+// pos4 from the particle arrays in their present order, then the tree (no sort)
+hipError_t launch_refresh_cells(mfm_ctx *ctx, const mfm_particles *pp);
 // Individual time steps: rungs from dt_i (or given), one limiter sweep over
 // the face lists, the active set and predicted positions of sub-step k.
 hipError_t launch_rungs_from_dt(mfm_ctx *ctx, const mfm_particles *pp, double dt0);
@@ -359,6 +372,9 @@ void stage_end(mfm_ctx *ctx, int slot);
 // particles and its L2 keeps serving the same neighbours.  A bijection on
 // [0, nb): XCD x takes nb / 8 workgroups, plus one if x < nb % 8.
 constexpr int NUM_XCD = 8;
+
+// mfm_step keeps the particle order for at most KEEP_MAX_STEPS steps
+constexpr int KEEP_MAX_STEPS = 16;
 __host__ __device__ __forceinline__ int xcd_block(int b, int nb) {
   const int q = nb / NUM_XCD, r = nb % NUM_XCD, x = b % NUM_XCD;
   return x * q + (x < r ? x : r) + b / NUM_XCD;
