@@ -41,6 +41,9 @@ struct CandArgs {
   int32_t *cand_cnt;
   int64_t *counters;
   int csplit;           // workgroups per bucket (1, or BUCKET / TCH: small set, sub-step)
+  // a sub-step's list pass: the chunks holding an active particle
+  // (C_CHUNK_QUEUE of them; csplit = BUCKET / TCH); null: every chunk
+  const int32_t *chunk_q;
 };
 
 // The neighbour search: one wavefront per bucket of BUCKET consecutive
@@ -104,8 +107,12 @@ __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4))) ca
   // one bucket per workgroup on a full pass (one chunk per workgroup on a
   // set of few buckets, csplit > 1); on the sub-steps of individual time
   // steps a capped grid strides over the chunks
-  const int nwork = nbuckets * a.csplit;
-  for (int w = xcd_block(blockIdx.x, gridDim.x); w < nwork; w += gridDim.x) {
+  // work item w: chunk w % csplit of bucket w / csplit (with csplit =
+  // BUCKET / TCH, w is the chunk's index); a queue lists the items to take
+  const int64_t nwork = a.chunk_q ? a.counters[C_CHUNK_QUEUE] : (int64_t)nbuckets * a.csplit;
+  for (int64_t q = a.chunk_q ? (int64_t)blockIdx.x : (int64_t)xcd_block(blockIdx.x, gridDim.x);
+       q < nwork; q += gridDim.x) {
+    const int w = a.chunk_q ? a.chunk_q[q] : (int)q;
     const int bucket = w / a.csplit;
     const int own_x = bucket * BUCKET;
     const int own_y = (int)min((int64_t)BUCKET, n - own_x);
@@ -867,6 +874,28 @@ __global__ void validate_k(int64_t *c) {
 // through the sort), an eighth more and 4 (positions and H drift between
 // searches), times LCH.  The entry past the last chunk is 0, so that the
 // scan ends with the total.
+// A sub-step's list pass: the chunks (LCH consecutive particles, one
+// 16-lane row of a wavefront) holding a particle whose step begins are
+// queued, one atomic per wavefront.
+__global__ void __launch_bounds__(BS) queue_chunks_k(int64_t n, const uint8_t *__restrict__ act,
+                                                     int32_t *chunk_q, int64_t *counters) {
+  static_assert(LCH == 16 && BUCKET % 64 == 0, "four chunks to a wavefront");
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  const int lane = threadIdx.x & 63;
+  const uint64_t m = __ballot(i < n && act[i]);
+  // lane 16 r stands for row r: is any of its 16 particles active
+  const bool head = lane % LCH == 0 && ((m >> lane) & 0xFFFFull) != 0;
+  const uint64_t hm = __ballot(head);
+  if (!hm) return;  // wave-uniform
+  const int leader = __ffsll((unsigned long long)hm) - 1;
+  unsigned long long base = 0;
+  if (lane == leader)
+    base = atomicAdd(reinterpret_cast<unsigned long long *>(counters + C_CHUNK_QUEUE),
+                     (unsigned long long)__popcll(hm));
+  base = __shfl(base, leader, 64);
+  if (head) chunk_q[base + lanes_below(hm)] = (int32_t)(i / LCH);
+}
+
 __global__ void plan_k(int64_t n, int64_t nch, const int32_t *__restrict__ ncand, int64_t *cap) {
   const int64_t c = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (c > nch) return;
@@ -884,6 +913,7 @@ __global__ void pool_check_k(const int64_t *__restrict__ lseg, int64_t nch, int6
   if (threadIdx.x == 0) {
     counters[C_LIST_POOL] = lseg[nch] > pool ? 1 : 0;
     counters[C_LONG_QUEUE] = 0;  // the density loop that follows fills the queue
+    counters[C_CHUNK_QUEUE] = 0;  // and a sub-step's list pass its chunk queue
   }
 }
 
@@ -920,6 +950,15 @@ hipError_t launch_candidates(mfm_ctx *ctx, const mfm_particles *pp, bool count_o
   // steps (few chunks, scattered, need lists), each chunk gets a workgroup
   // of its own; on a sub-step a capped grid strides over the chunks
   a.csplit = (a.act || buckets < SEARCH_WG_TARGET) ? BUCKET / TCH : 1;
+  // a sub-step's list pass takes the chunks with an active particle from a
+  // queue (in the gradient loop's queue buffer, unused until that loop; the
+  // counting pass, rare on a sub-step, strides over every chunk)
+  a.chunk_q = nullptr;
+  if (a.act && !count_only) {
+    queue_chunks_k<<<blocks_for(pp->n, BS), BS, 0, ctx->stream>>>(pp->n, a.act, ctx->grad_q,
+                                                                   ctx->counters);
+    a.chunk_q = ctx->grad_q;
+  }
   const int64_t grid = a.act ? std::min<int64_t>(buckets * a.csplit, 8192) : buckets * a.csplit;
   cand_tree_k<<<(unsigned)grid, 64, 0, ctx->stream>>>(a, ctx->tree);
   return hipGetLastError();

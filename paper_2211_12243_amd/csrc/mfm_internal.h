@@ -46,8 +46,10 @@ enum {
   C_RUNG_CHANGED,   // the rung limiter raised some rung in its last sweep
   C_RUNG_DEEP,      // particles whose step needs a rung beyond MFM_RUNG_MAX
   C_LONG_QUEUE,     // density loop: particles queued for the wavefront-per-particle pass
+  C_CHUNK_QUEUE,    // sub-steps: 16-particle chunks with an active particle, queued for the search
   NCOUNTERS = 32
 };
+static_assert(C_CHUNK_QUEUE < NCOUNTERS, "every counter has its slot");
 
 // Packed per-particle record the gradient loop gathers for each neighbour
 // (written by the density loop; one 128-byte line).
