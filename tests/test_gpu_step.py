@@ -9,7 +9,8 @@ then repeats it.  These tests drive each path against the oracle's step:
 * a particle set replaced in place (same arrays) by one with larger H, so the
   max H the previous step left is stale;
 * a candidate list capacity too small: an error, with the state untouched;
-* the time per step on the 8192-particle sound wave.
+* the time per step on the 8192-particle sound wave;
+* steps that keep the last particle order against steps that sort.
 """
 import time
 
@@ -132,3 +133,46 @@ def test_soundwave_step_time():
     print(f"[step] sound wave N=128: {ms:.3f} ms per step", flush=True)
     ctx.close()
     assert ms < 0.45
+
+
+def test_kept_order_steps_match_sorted_steps():
+    """mfm_step may skip the Morton sort and build the tree over the order of
+    its last sort (while its timed cells, search and density stages stay
+    below those of that sorting step).  Such steps must give what steps that
+    sort every time give (mfm_build_cells before each step clears the
+    reuse), particle by particle: the order changes only the grouping of
+    the search and the rounding order of the sums."""
+    _need_gpu()
+    st = W.kh(n=32, seed=2)
+    cfg = {"scheme": "mfm"}
+    n = st["x"].size
+    a = mfm.Context(mfm.params_from_dict(cfg), n)
+    pa = mfm.ParticleSet(st)
+    b = mfm.Context(mfm.params_from_dict(cfg), n)
+    pb = mfm.ParticleSet(st)
+    cells_a, cells_b = [], []
+    for k in range(8):
+        mfm.mfm_enable_timing(a, True)
+        da = mfm.mfm_step(a, pa, 1.0)
+        cells_a.append(mfm.mfm_kernel_times(a)["cells"][0])
+        mfm.mfm_build_cells(b, pb)
+        mfm.mfm_enable_timing(b, True)
+        db = mfm.mfm_step(b, pb, 1.0)
+        cells_b.append(mfm.mfm_kernel_times(b)["cells"][0])
+        assert abs(da - db) <= 1e-12 * db, k
+    torch.cuda.synchronize()
+    print("[step] cells ms, reusing:", " ".join(f"{t:.3f}" for t in cells_a), flush=True)
+    print("[step] cells ms, sorting:", " ".join(f"{t:.3f}" for t in cells_b), flush=True)
+    got, ref = _by_id(pa), _by_id(pb)
+    for k in KEYS:
+        d = np.abs(got[k] - ref[k])
+        if k in ("x", "y", "z"):
+            d = np.minimum(d, 1.0 - d)
+            assert d.max() <= 1e-13, k
+        else:
+            # velocities against the flow's speed scale, the rest against
+            # their own magnitude
+            scale = max(np.abs(ref[k]).max(), 1.0 if k in ("vx", "vy", "vz") else 0.0)
+            assert d.max() <= 1e-11 * scale, k
+    a.close()
+    b.close()
